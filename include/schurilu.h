@@ -1,0 +1,177 @@
+/*
+ * schurilu.h -- C ABI of libschurilu: block-Jacobi and two-level (additive
+ * Schur-complement) ILU preconditioners with flexible GMRES, as hand-written
+ * HIP kernels for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Xu, Li, Osei-Kuffuor, "A Two-level GPU-Accelerated Incomplete LU
+ * Preconditioner for General Sparse Linear Systems", arXiv 2303.08881.
+ *
+ * Conventions for every call
+ *  - Matrices are CSR with int64 row pointers, int32 column indices sorted
+ *    strictly ascending inside each row, FP64 values, and a stored diagonal.
+ *  - Pointers named d_* are device pointers (HIP device memory, e.g. the
+ *    data_ptr() of a torch CUDA/HIP tensor); pointers named h_* are host.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *  - Return value: 0 on success, ILU_NOT_CONVERGED (> 0) from fgmres_solve
+ *    when the iteration limit was reached, a negative ILU_ERR_* code on error.
+ *    ilu_last_error() then returns a message (thread-local, valid until the
+ *    next call from the same thread).
+ *  - Nothing here falls back to a CPU path: without a usable gfx950 device
+ *    every call that computes returns ILU_ERR_HIP.
+ */
+#ifndef SCHURILU_H
+#define SCHURILU_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define ILU_OK 0
+#define ILU_NOT_CONVERGED 1
+#define ILU_ERR_INVALID_ARG (-1)
+#define ILU_ERR_CSR (-2)        /* unsorted / duplicate / out-of-range column, missing diagonal */
+#define ILU_ERR_ZERO_PIVOT (-3) /* zero or non-finite pivot; row (original numbering) in the message */
+#define ILU_ERR_OOM (-4)
+#define ILU_ERR_HIP (-5)
+#define ILU_ERR_BREAKDOWN (-6)  /* NaN/Inf inside the Krylov iteration */
+#define ILU_ERR_CAPACITY (-7)   /* an ILUT working row outgrew the kernel's on-chip buffer */
+#define ILU_ERR_TIMEOUT (-8)    /* a bounded dependency wait expired (internal error) */
+
+/* ---- option values ---- */
+#define ILU_METHOD_BJ 0    /* block Jacobi: Section 2.1, Alg. 4                    */
+#define ILU_METHOD_SCHUR 1 /* additive two-level: Alg. 1, Section 3.2, Alg. 5      */
+#define ILU_FACT_ILU0 0    /* ILU(0) on the pattern of the block                    */
+#define ILU_FACT_MILU0 1   /* modified ILU(0): dropped fill added to the diagonal,
+                              Section 2.3 eq. (16)                                  */
+#define ILU_FACT_ILUT 2    /* threshold ILU with a per-part fill limit              */
+#define ILU_PIVOT_ERROR 0
+#define ILU_PIVOT_PERTURB 1
+
+typedef struct {
+  int64_t n;               /* rows = columns */
+  int64_t nnz;             /* row_ptr[n] */
+  const int64_t *d_row_ptr; /* n+1, device */
+  const int32_t *d_col;    /* nnz, device */
+  const double *d_val;     /* nnz, device */
+} ilu_csr_t;
+
+/*
+ * Options.  Defaults (ilu_default_options): BJ, ILU(0) everywhere, 3 inner
+ * GMRES steps (the paper's default, Section 4.1), no drop, pivot errors.
+ *  interior_fact  factor of each subdomain block A_i (BJ), or of the interior
+ *                 rows plus the partial elimination of the interface rows
+ *                 (SCHUR, eq. (17));
+ *  interface_fact SCHUR only: factor of each local Schur complement S~_i,
+ *                 whose triangular factors precondition the reduced system
+ *                 (eq. (18)-(19));
+ *  droptol, lfil  ILUT: an entry w_j of row i is dropped when
+ *                 |w_j| < droptol * ||a_i||_2; at most lfil entries are kept
+ *                 in the L part and in the U part of each row (the Schur part
+ *                 of a partially eliminated row counts as its U part); the
+ *                 diagonal is always kept.  lfil < 0 means no limit (only for
+ *                 n <= 8192).
+ *  inner_iters    SCHUR: GMRES steps on the reduced system per apply;
+ *                 0 applies the local Schur factors once (block Jacobi on S).
+ *  inner_rtol     SCHUR: stop the inner GMRES once its residual estimate is
+ *                 <= inner_rtol times the norm of its right-hand side.
+ *  pivot_mode     ILU_PIVOT_ERROR: a zero pivot fails setup with
+ *                 ILU_ERR_ZERO_PIVOT.  ILU_PIVOT_PERTURB: a pivot with
+ *                 |u_ii| < pivot_tol * max_j |a_ij| is replaced by
+ *                 +-pivot_tol * max_j |a_ij| (sign of u_ii, + for 0).
+ */
+typedef struct {
+  int32_t method;
+  int32_t interior_fact;
+  int32_t interface_fact;
+  double droptol;
+  int32_t lfil;
+  int32_t inner_iters;
+  double inner_rtol;
+  int32_t pivot_mode;
+  double pivot_tol;
+} ilu_options_t;
+
+typedef struct {
+  int32_t iterations;   /* outer Arnoldi steps summed over restart cycles */
+  int32_t converged;    /* 1 if ||b - A x|| <= rtol ||b|| at exit           */
+  double final_relres;  /* true relative residual at exit                   */
+  double setup_ms;      /* time of the ilu_setup that built P (device events) */
+  double solve_ms;      /* time of this fgmres_solve                         */
+} ilu_result_t;
+
+typedef struct ilu_precond ilu_precond_t;
+
+/* Fill *opt with the defaults listed above. */
+void ilu_default_options(ilu_options_t *opt);
+
+/*
+ * ilu_setup -- build the preconditioner P of A (Alg. 4 setup for BJ, Alg. 5
+ * setup for SCHUR), entirely on the device.
+ *  A        device CSR (validated on the device: ILU_ERR_CSR on bad input).
+ *  d_part   device int32[n], subdomain of each row (0 <= part < nparts), or
+ *           NULL for a single subdomain.  Rows coupled to another subdomain
+ *           in either direction become interface rows (Section 2.2.1); each
+ *           subdomain is ordered interior-first in its original row order.
+ *  nparts   >= 1.
+ *  opt      options (host struct), NULL for the defaults.
+ *  stream   stream for all setup work; the call returns after the stream has
+ *           finished it (errors are then known).
+ *  P        out: handle owning all device memory of the preconditioner.
+ *           A and d_part may be freed once ilu_setup returns.
+ */
+int ilu_setup(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts, const ilu_options_t *opt,
+              void *stream, ilu_precond_t **P);
+
+/*
+ * ilu_apply -- z = M^{-1} r (device vectors of length n, original numbering),
+ * asynchronous on `stream`.  BJ: gather, L solve, U solve, scatter (Alg. 4).
+ * SCHUR: f' = L_B^-1 f, g' = g - W f', inner GMRES on the reduced system,
+ * u = U_B^-1 (f' - Z y), scatter (Section 3.2).  r and z must not alias.
+ * Not re-entrant per handle (the workspace lives in P).
+ */
+int ilu_apply(ilu_precond_t *P, const double *d_r, double *d_z, void *stream);
+
+/*
+ * fgmres_solve -- right-preconditioned flexible GMRES(restart) for A x = b
+ * (Section 4.1).  d_x holds x0 on entry and the iterate on exit.  Stops when
+ * the Givens residual estimate reaches rtol*||b|| and the true residual
+ * confirms it, or after maxit Arnoldi steps.  Synchronises `stream`.
+ * res may be NULL.  h_hist, if not NULL, receives maxit+1 doubles: the
+ * relative residual estimate after each step (entry 0 = initial).
+ */
+int fgmres_solve(const ilu_csr_t *A, ilu_precond_t *P, const double *d_b, double *d_x, double rtol,
+                 int32_t restart, int32_t maxit, void *stream, ilu_result_t *res, double *h_hist);
+
+/* y = A x (device, FP64, each row summed in column order with fma). */
+int csr_spmv(const ilu_csr_t *A, const double *d_x, double *d_y, void *stream);
+
+/* Release every device allocation of P.  NULL is accepted. */
+void ilu_destroy(ilu_precond_t *P);
+
+/* Message for the last error of the calling thread. */
+const char *ilu_last_error(void);
+
+/*
+ * ilu_export -- copy an internal array to host memory for inspection.
+ * If h_buf is NULL only *len (element count) is set.  Otherwise *len must be
+ * >= the element count on entry.  Codes (element types in brackets):
+ *   0 perm [int32 n] new->old, 1 iperm [int32 n], 2 interface flag [uint8 n],
+ *   3 offsets [int64 2*nparts+2]: interior starts, then interface starts,
+ *   CSR blocks at base+0 row_ptr [int64], +1 col [int32], +2 val [double]:
+ *   10 L_B, 13 U_B (interior cols), 17 Z (interface cols, permuted numbering),
+ *   20 W (interface rows, interior cols), 23 L_S, 26 U_S (interface numbering),
+ *   30 C_off (interface rows, other subdomains' interface columns);
+ *   16 diag of U_B [double n_B], 29 diag of U_S [double n_S];
+ *   40..43 level of each row of L_B, U_B, L_S, U_S [int32].
+ */
+int ilu_export(ilu_precond_t *P, int32_t what, void *h_buf, int64_t *len);
+
+/* Sizes: n, n_B (interior rows), n_S (interface rows), nparts. */
+int ilu_info(ilu_precond_t *P, int64_t *n, int64_t *nB, int64_t *nS, int32_t *nparts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

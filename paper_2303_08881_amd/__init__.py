@@ -1,0 +1,27 @@
+"""Python binding of libschurilu (argument marshalling only).
+
+Every numerical step runs in the gfx950 HIP kernels behind the C ABI declared
+in include/schurilu.h; PyTorch supplies device memory and the current stream.
+Importing this package does not load the library; the first call does, and it
+raises if the library is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+from .binding import (  # noqa: F401
+    BJ,
+    SCHUR,
+    ILU0,
+    MILU0,
+    ILUT,
+    PIVOT_ERROR,
+    PIVOT_PERTURB,
+    SchurILUError,
+    DeviceCSR,
+    Precond,
+    setup,
+    fgmres,
+    spmv,
+    lib,
+    LIB_PATH,
+    EXPORT,
+)

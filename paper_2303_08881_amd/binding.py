@@ -1,0 +1,208 @@
+"""ctypes binding of the C ABI in include/schurilu.h.
+
+Names follow the C entry points: ``setup`` -> ilu_setup, ``Precond.apply`` ->
+ilu_apply, ``fgmres`` -> fgmres_solve, ``spmv`` -> csr_spmv,
+``Precond.export`` -> ilu_export.  Tensors must live on the current HIP
+device; the current torch stream is passed to every call.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libschurilu.so")
+
+BJ, SCHUR = 0, 1
+ILU0, MILU0, ILUT = 0, 1, 2
+PIVOT_ERROR, PIVOT_PERTURB = 0, 1
+OK, NOT_CONVERGED = 0, 1
+
+EXPORT = dict(perm=(0, np.int32), iperm=(1, np.int32), iface=(2, np.uint8), offsets=(3, np.int64),
+              DB=(16, np.float64), DS=(29, np.float64), lev_LB=(40, np.int32), lev_UB=(41, np.int32),
+              lev_LS=(42, np.int32), lev_US=(43, np.int32))
+_CSR_CODES = dict(LB=10, UB=13, Z=17, W=20, LS=23, US=26, Coff=30)
+_FIELD_T = (np.int64, np.int32, np.float64)
+
+
+class SchurILUError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class _CSR(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("d_row_ptr", C.c_void_p), ("d_col", C.c_void_p),
+                ("d_val", C.c_void_p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("method", C.c_int32), ("interior_fact", C.c_int32), ("interface_fact", C.c_int32),
+                ("droptol", C.c_double), ("lfil", C.c_int32), ("inner_iters", C.c_int32),
+                ("inner_rtol", C.c_double), ("pivot_mode", C.c_int32), ("pivot_tol", C.c_double)]
+
+
+class _Res(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("final_relres", C.c_double),
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libschurilu.so (built in-tree by build.py); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SchurILUError(-5, f"{LIB_PATH} not found: build it with paper_2303_08881_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.ilu_default_options.argtypes = [vp]
+        L.ilu_default_options.restype = None
+        L.ilu_setup.argtypes = [vp, vp, i32, vp, vp, C.POINTER(vp)]
+        L.ilu_apply.argtypes = [vp, vp, vp, vp]
+        L.fgmres_solve.argtypes = [vp, vp, vp, vp, d, i32, i32, vp, vp, vp]
+        L.csr_spmv.argtypes = [vp, vp, vp, vp]
+        L.ilu_destroy.argtypes = [vp]
+        L.ilu_destroy.restype = None
+        L.ilu_last_error.argtypes = []
+        L.ilu_last_error.restype = C.c_char_p
+        L.ilu_export.argtypes = [vp, i32, vp, C.POINTER(i64)]
+        L.ilu_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, allow_not_converged: bool = False) -> int:
+    if rc < 0 or (rc > 0 and not allow_not_converged):
+        raise SchurILUError(rc, lib().ilu_last_error().decode())
+    return rc
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr() if t is not None else 0)
+
+
+class DeviceCSR:
+    """CSR matrix resident in device memory (torch tensors)."""
+
+    def __init__(self, n, row_ptr, col, val):
+        self.n = int(n)
+        self.row_ptr, self.col, self.val = row_ptr, col, val
+        self.nnz = int(col.numel())
+        self._c = _CSR(self.n, self.nnz, row_ptr.data_ptr(), col.data_ptr(), val.data_ptr())
+
+    @staticmethod
+    def from_host(A, device="cuda"):
+        torch = _torch()
+        rp = torch.as_tensor(np.asarray(A.row_ptr, dtype=np.int64)).to(device)
+        ci = torch.as_tensor(np.asarray(A.col, dtype=np.int32)).to(device)
+        v = torch.as_tensor(np.asarray(A.val, dtype=np.float64)).to(device)
+        return DeviceCSR(A.n, rp, ci, v)
+
+    @property
+    def ref(self):
+        return C.byref(self._c)
+
+
+def _options(method=BJ, interior_fact=ILU0, interface_fact=ILU0, droptol=0.0, lfil=-1, inner_iters=3,
+             inner_rtol=0.0, pivot_mode=PIVOT_ERROR, pivot_tol=0.0):
+    return _Opts(method, interior_fact, interface_fact, droptol, lfil, inner_iters, inner_rtol, pivot_mode,
+                 pivot_tol)
+
+
+class Precond:
+    """Handle returned by ilu_setup; owns the device memory of the preconditioner."""
+
+    def __init__(self, handle, n):
+        self._h = handle
+        self.n = n
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ilu_destroy(self._h)
+        self._h = None
+
+    def apply(self, r, z=None):
+        torch = _torch()
+        if z is None:
+            z = torch.empty_like(r)
+        _check(lib().ilu_apply(self._h, _ptr(r), _ptr(z), _stream()))
+        return z
+
+    def info(self):
+        n, nB, nS, npart = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib().ilu_info(self._h, C.byref(n), C.byref(nB), C.byref(nS), C.byref(npart)))
+        return dict(n=n.value, nB=nB.value, nS=nS.value, nparts=npart.value)
+
+    def _export(self, code, dtype):
+        ln = C.c_int64(0)
+        _check(lib().ilu_export(self._h, code, None, C.byref(ln)))
+        out = np.zeros(ln.value, dtype=dtype)
+        _check(lib().ilu_export(self._h, code, out.ctypes.data_as(C.c_void_p), C.byref(ln)))
+        return out
+
+    def export(self, name):
+        """Copy an internal array to host: perm, iperm, iface, offsets, DB, DS, lev_*."""
+        code, dt = EXPORT[name]
+        return self._export(code, dt)
+
+    def csr(self, name):
+        """(row_ptr, col, val) of LB, UB, Z, W, LS, US or Coff."""
+        base = _CSR_CODES[name]
+        return tuple(self._export(base + k, _FIELD_T[k]) for k in range(3))
+
+
+def setup(A: DeviceCSR, part=None, nparts=1, **opts) -> Precond:
+    """ilu_setup: build the preconditioner of A on the device."""
+    h = C.c_void_p()
+    o = _options(**opts)
+    torch = _torch()
+    if part is not None and not (isinstance(part, torch.Tensor) and part.is_cuda):
+        part = torch.as_tensor(np.asarray(part, dtype=np.int32)).to(A.val.device)
+    pp = C.c_void_p(part.data_ptr()) if part is not None else C.c_void_p(0)
+    _check(lib().ilu_setup(A.ref, pp, int(nparts), C.byref(o), _stream(), C.byref(h)))
+    return Precond(h, A.n)
+
+
+def fgmres(A: DeviceCSR, P: Precond, b, x0=None, rtol=1e-8, restart=30, maxit=1000, history=False):
+    """fgmres_solve: right-preconditioned FGMRES(restart); returns a dict."""
+    torch = _torch()
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    res = _Res()
+    hist = np.full(maxit + 1, np.nan) if history else None
+    hp = hist.ctypes.data_as(C.c_void_p) if history else None
+    rc = lib().fgmres_solve(A.ref, P._h, _ptr(b), _ptr(x), float(rtol), int(restart), int(maxit), _stream(),
+                            C.byref(res), hp)
+    _check(rc, allow_not_converged=True)
+    out = dict(x=x, iterations=res.iterations, converged=bool(res.converged), relres=res.final_relres,
+               setup_ms=res.setup_ms, solve_ms=res.solve_ms, rc=rc)
+    if history:
+        out["history"] = hist[: res.iterations + 1]
+    return out
+
+
+def spmv(A: DeviceCSR, x, y=None):
+    """csr_spmv: y = A x."""
+    torch = _torch()
+    if y is None:
+        y = torch.empty_like(x)
+    _check(lib().csr_spmv(A.ref, _ptr(x), _ptr(y), _stream()))
+    return y

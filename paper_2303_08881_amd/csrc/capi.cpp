@@ -1,0 +1,937 @@
+// capi.cpp -- runtime and C ABI of libschurilu (see include/schurilu.h).
+//
+// The host side only sequences kernels, owns device memory and reads back a
+// handful of scalars (sizes during setup, the residual estimate once per
+// outer Krylov step).  Every arithmetic step of setup and solve runs in the
+// gfx950 kernels of factor.hip, levels.hip, trsv.hip, krylov.hip, setup.hip
+// and prims.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+using namespace silu;
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int silu_hip_fail(hipError_t e, int line) {
+  return fail(ILU_ERR_HIP, "HIP error '%s' (capi.cpp:%d)", hipGetErrorString(e), line);
+}
+
+namespace silu {
+int check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ILU_ERR_HIP, "launch of %s failed: %s", what, hipGetErrorString(e));
+  return 0;
+}
+}  // namespace silu
+
+#define HIPCK(x)                                        \
+  do {                                                  \
+    hipError_t _e = (x);                                \
+    if (_e != hipSuccess) return silu_hip_fail(_e, __LINE__); \
+  } while (0)
+#define RC(x)                   \
+  do {                          \
+    int _r = (x);               \
+    if (_r) return _r;          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory owner
+// ---------------------------------------------------------------------------
+struct Mem {
+  std::vector<void *> ptrs;
+  ~Mem() { release(); }
+  void release() {
+    for (void *p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+  template <typename T>
+  int alloc(T **out, int64_t count) {
+    *out = nullptr;
+    size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ILU_ERR_OOM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    ptrs.push_back(p);
+    *out = (T *)p;
+    return 0;
+  }
+};
+
+struct Csr {
+  int64_t n = 0, nnz = 0;
+  int64_t *rp = nullptr;
+  int32_t *ci = nullptr;
+  double *v = nullptr;
+};
+
+struct Schedule {
+  int64_t nrows = 0, nlev = 0, nchunks = 0;
+  int32_t *rows = nullptr, *chunk_start = nullptr, *chunk_level = nullptr, *level_of = nullptr;
+  int64_t *level_ptr = nullptr;
+  unsigned long long *level_done = nullptr, *ticket = nullptr;
+  unsigned long long epoch = 0, ticket_base = 0;
+  int64_t grid = 0;
+};
+
+struct GmresWork {
+  int64_t n = 0;
+  int m = 0;
+  double *V = nullptr, *Zb = nullptr, *r = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
+         *c = nullptr, *pa = nullptr, *pb = nullptr, *scal = nullptr;  // scal: [0] bnorm [1] beta [2] hn [3] est
+  int *flags = nullptr;                                                // [0] stop [1] nsteps
+  Mem mem;
+};
+
+struct ilu_precond {
+  int device = 0;
+  int64_t n = 0, nB = 0, nS = 0;
+  int32_t nparts = 1;
+  ilu_options_t opt;
+  int num_cu = 256;
+  Mem mem;
+  int32_t *perm = nullptr, *iperm = nullptr;
+  uint8_t *iface = nullptr;
+  std::vector<int64_t> offsets;  // 2*nparts+2
+  Csr L1, U1, LS, US, Coff;
+  double *DB = nullptr, *DS = nullptr;
+  Schedule sL1, sU1, sLS, sUS;
+  double *xp = nullptr;
+  // reduced-system GMRES
+  double *iV = nullptr, *it1 = nullptr, *it2 = nullptr, *iH = nullptr, *ics = nullptr, *isn = nullptr,
+         *ig = nullptr, *ic = nullptr, *ipa = nullptr, *ipb = nullptr, *iscal = nullptr;
+  int *iflags = nullptr;
+  Status *status = nullptr;
+  double *host_pinned = nullptr;  // 8 doubles for read-backs
+  double setup_ms = 0.0;
+  GmresWork *gw = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+static int read_i64(const int64_t *d, int64_t *h, hipStream_t s) {
+  HIPCK(hipMemcpyAsync(h, d, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  return 0;
+}
+
+static int check_status(ilu_precond *P, hipStream_t s, const char *phase, const int32_t *row_map, int64_t row_off) {
+  Status h;
+  HIPCK(hipMemcpyAsync(&h, P->status, sizeof(Status), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  if (h.code == 0) return 0;
+  int64_t row = h.row;
+  if (row_map && row >= 0) {
+    int32_t orig = -1;
+    if (hipMemcpy(&orig, row_map + row_off + row, sizeof(int32_t), hipMemcpyDeviceToHost) == hipSuccess) row = orig;
+  }
+  switch (h.code) {
+    case ILU_ERR_ZERO_PIVOT:
+      return fail(ILU_ERR_ZERO_PIVOT, "%s: zero or non-finite pivot at row %lld (original numbering)", phase,
+                  (long long)row);
+    case ILU_ERR_CAPACITY:
+      return fail(ILU_ERR_CAPACITY, "%s: working row %lld exceeds the on-chip capacity", phase, (long long)row);
+    case ILU_ERR_TIMEOUT:
+      return fail(ILU_ERR_TIMEOUT, "%s: dependency wait expired at row %lld", phase, (long long)row);
+    default:
+      return fail(h.code, "%s: device error %d at row %lld", phase, h.code, (long long)row);
+  }
+}
+
+static int bits_for(uint64_t maxkey) {
+  int b = 1;
+  while (b < 32 && (maxkey >> b)) b++;
+  return b;
+}
+
+// scan of a device count array into a freshly allocated row pointer; returns total
+static int make_rp(Mem &mem, const int64_t *cnt, int64_t n, int64_t **rp, int64_t *total, void *tmp, size_t tmpb,
+                   hipStream_t s) {
+  RC(mem.alloc(rp, n + 1));
+  RC(scan_i64(cnt, *rp, n, tmp, tmpb, s));
+  return read_i64(*rp + n, total, s);
+}
+
+// compact per-row slots to CSR keeping columns in [lo, hi), shifted by -shift
+static int slots_to_csr(Mem &mem, int64_t nrows, const int64_t *cap_rp, const int32_t *len, const int32_t *sc,
+                        const double *sv, int64_t lo, int64_t hi, int64_t shift, Csr *out, int64_t *cnt_tmp,
+                        void *tmp, size_t tmpb, hipStream_t s) {
+  out->n = nrows;
+  RC(launch_count_rows(nrows, cap_rp, len, sc, lo, hi, cnt_tmp, s));
+  RC(make_rp(mem, cnt_tmp, nrows, &out->rp, &out->nnz, tmp, tmpb, s));
+  RC(mem.alloc(&out->ci, out->nnz));
+  RC(mem.alloc(&out->v, out->nnz));
+  return launch_compact_rows(nrows, cap_rp, len, sc, sv, out->rp, out->ci, out->v, lo, hi, shift, s);
+}
+
+struct Slots {
+  int64_t *Lcap = nullptr, *Ucap = nullptr, *Rcap = nullptr, *Lrp = nullptr, *Urp = nullptr, *Rrp = nullptr;
+  int32_t *Lc = nullptr, *Uc = nullptr, *Rc = nullptr, *Llen = nullptr, *Ulen = nullptr, *Rlen = nullptr;
+  double *Lv = nullptr, *Uv = nullptr, *Rv = nullptr, *D = nullptr;
+};
+
+// Factor M (rows < nfull full, the rest partial) with the schedule of the
+// given segments.  Scratch goes to `tmp`.
+static int run_factor(ilu_precond *P, Mem &tmp, const Csr &M, int64_t nfull, int32_t method,
+                      const std::vector<int64_t> &a_start, const std::vector<int64_t> &a_len,
+                      const std::vector<int64_t> &b_start, const std::vector<int64_t> &b_len, Slots &S,
+                      const int32_t *row_map, int64_t row_off, void *stmp, size_t stmpb, hipStream_t s,
+                      const char *phase) {
+  const int64_t n = M.n;
+  if (method == ILU_FACT_ILUT && P->opt.lfil < 0 && n > 4096)
+    return fail(ILU_ERR_INVALID_ARG, "ILUT with unlimited fill (lfil < 0) is limited to n <= 4096");
+  // capacities
+  RC(tmp.alloc(&S.Lcap, n));
+  RC(tmp.alloc(&S.Ucap, nfull));
+  RC(tmp.alloc(&S.Rcap, n - nfull));
+  RC(launch_fact_caps(M.rp, M.ci, n, nfull, method, P->opt.lfil, S.Lcap, S.Ucap, S.Rcap, s));
+  int64_t tl, tu, tr;
+  RC(make_rp(tmp, S.Lcap, n, &S.Lrp, &tl, stmp, stmpb, s));
+  RC(make_rp(tmp, S.Ucap, nfull, &S.Urp, &tu, stmp, stmpb, s));
+  RC(make_rp(tmp, S.Rcap, n - nfull, &S.Rrp, &tr, stmp, stmpb, s));
+  RC(tmp.alloc(&S.Lc, tl));
+  RC(tmp.alloc(&S.Lv, tl));
+  RC(tmp.alloc(&S.Uc, tu));
+  RC(tmp.alloc(&S.Uv, tu));
+  RC(tmp.alloc(&S.Rc, tr));
+  RC(tmp.alloc(&S.Rv, tr));
+  RC(tmp.alloc(&S.Llen, n));
+  RC(tmp.alloc(&S.Ulen, nfull));
+  RC(tmp.alloc(&S.Rlen, n - nfull));
+  RC(tmp.alloc(&S.D, nfull));
+  RC(fill_i32(S.Ulen, 0, nfull, s));
+  // schedule: FACT_CHUNK-row chunks of each segment, interleaved
+  const int32_t nseg = (int32_t)a_start.size();
+  std::vector<int64_t> hv(4 * nseg);
+  for (int k = 0; k < nseg; k++) {
+    hv[k] = a_start[k];
+    hv[nseg + k] = a_len[k];
+    hv[2 * nseg + k] = b_start[k];
+    hv[3 * nseg + k] = b_len[k];
+  }
+  int64_t *seg;
+  RC(tmp.alloc(&seg, 4 * nseg));
+  HIPCK(hipMemcpyAsync(seg, hv.data(), sizeof(int64_t) * 4 * nseg, hipMemcpyHostToDevice, s));
+  int64_t *nchunks_seg, *cstart;
+  RC(tmp.alloc(&nchunks_seg, nseg));
+  RC(launch_chunk_counts(nseg, seg, seg + nseg, seg + 2 * nseg, seg + 3 * nseg, nchunks_seg, s));
+  int64_t nchunks;
+  RC(make_rp(tmp, nchunks_seg, nseg, &cstart, &nchunks, stmp, stmpb, s));
+  if (nchunks > 0) {
+    uint32_t *key, *key2;
+    int32_t *val, *val2;
+    RC(tmp.alloc(&key, nchunks));
+    RC(tmp.alloc(&key2, nchunks));
+    RC(tmp.alloc(&val, nchunks));
+    RC(tmp.alloc(&val2, nchunks));
+    RC(launch_chunk_keys(nchunks, nseg, cstart, key, val, s));
+    void *rtmp;
+    size_t rtb = radix_tmp_bytes(nchunks);
+    RC(tmp.alloc((char **)&rtmp, (int64_t)rtb));
+    int64_t maxq = 0;
+    for (int k = 0; k < nseg; k++) maxq = std::max<int64_t>(maxq, (a_len[k] + b_len[k] + 15) / 16);
+    RC(radix_sort(key, val, key2, val2, nchunks, bits_for((uint64_t)maxq), rtmp, rtb, s));
+    int64_t *clen, *cptr, total;
+    RC(tmp.alloc(&clen, nchunks));
+    RC(launch_chunk_len(nchunks, nseg, cstart, val2, seg + nseg, seg + 3 * nseg, clen, s));
+    RC(make_rp(tmp, clen, nchunks, &cptr, &total, stmp, stmpb, s));
+    int32_t *order;
+    RC(tmp.alloc(&order, total));
+    RC(launch_chunk_rows(nchunks, nseg, cstart, val2, seg, seg + nseg, seg + 2 * nseg, cptr, order, s));
+    int *done;
+    unsigned int *ticket;
+    RC(tmp.alloc(&done, n));
+    RC(tmp.alloc(&ticket, 1));
+    HIPCK(hipMemsetAsync(done, 0, sizeof(int) * std::max<int64_t>(n, 1), s));
+    HIPCK(hipMemsetAsync(ticket, 0, sizeof(unsigned int), s));
+    FactLaunch f;
+    f.rp = M.rp;
+    f.ci = M.ci;
+    f.v = M.v;
+    f.n = n;
+    f.nfull = nfull;
+    f.method = method;
+    f.droptol = P->opt.droptol;
+    f.lfil = P->opt.lfil;
+    f.pivot_mode = P->opt.pivot_mode;
+    f.pivot_tol = P->opt.pivot_tol;
+    f.nchunks = nchunks;
+    f.chunk_ptr = cptr;
+    f.order = order;
+    f.ticket = ticket;
+    f.Lrp = S.Lrp;
+    f.Lc = S.Lc;
+    f.Lv = S.Lv;
+    f.Llen = S.Llen;
+    f.Urp = S.Urp;
+    f.Uc = S.Uc;
+    f.Uv = S.Uv;
+    f.Ulen = S.Ulen;
+    f.Rrp = S.Rrp;
+    f.Rc = S.Rc;
+    f.Rv = S.Rv;
+    f.Rlen = S.Rlen;
+    f.D = S.D;
+    f.done = done;
+    f.epoch = 1;
+    f.status = P->status;
+    f.max_waves = (int64_t)P->num_cu * 16;
+    RC(launch_factor_rows(f, s));
+    RC(check_status(P, s, phase, row_map, row_off));
+  }
+  return 0;
+}
+
+// level schedule of a triangular factor
+static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, int64_t lo, int64_t hi, Schedule &S,
+                          void *stmp, size_t stmpb, hipStream_t s, const char *phase) {
+  const int64_t n = T.n;
+  S.nrows = n;
+  if (n == 0) return 0;
+  Mem &mem = P->mem;
+  RC(mem.alloc(&S.level_of, n));
+  int *done;
+  unsigned int *ticket;
+  RC(tmp.alloc(&done, n));
+  RC(tmp.alloc(&ticket, 1));
+  HIPCK(hipMemsetAsync(done, 0, sizeof(int) * n, s));
+  HIPCK(hipMemsetAsync(ticket, 0, sizeof(unsigned int), s));
+  RC(launch_levels(T.rp, T.ci, n, lower, lo, hi, S.level_of, done, 1, ticket, P->status, (int64_t)P->num_cu * 32, s));
+  RC(check_status(P, s, phase, nullptr, 0));
+  int32_t *dmax;
+  RC(tmp.alloc(&dmax, 1));
+  RC(max_i32(S.level_of, n, dmax, s));
+  int32_t hmax = 0;
+  HIPCK(hipMemcpyAsync(&hmax, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  S.nlev = (int64_t)hmax + 1;
+  uint32_t *key, *key2;
+  int32_t *val;
+  RC(tmp.alloc(&key, n));
+  RC(tmp.alloc(&key2, n));
+  RC(tmp.alloc(&val, n));
+  RC(mem.alloc(&S.rows, n));
+  RC(launch_levels_to_keys(S.level_of, n, key, val, s));
+  void *rtmp;
+  const size_t rtb = radix_tmp_bytes(n);
+  RC(tmp.alloc((char **)&rtmp, (int64_t)rtb));
+  RC(radix_sort(key, val, key2, S.rows, n, bits_for((uint64_t)hmax), rtmp, rtb, s));
+  int64_t *cnt;
+  RC(tmp.alloc(&cnt, S.nlev));
+  RC(histogram_keys(key2, n, S.nlev, cnt, s));
+  int64_t tot;
+  RC(make_rp(mem, cnt, S.nlev, &S.level_ptr, &tot, stmp, stmpb, s));
+  int64_t *ccnt, *cbase;
+  RC(tmp.alloc(&ccnt, S.nlev));
+  RC(launch_level_chunk_counts(S.level_ptr, S.nlev, ccnt, s));
+  RC(make_rp(tmp, ccnt, S.nlev, &cbase, &S.nchunks, stmp, stmpb, s));
+  RC(mem.alloc(&S.chunk_start, S.nchunks + 1));
+  RC(mem.alloc(&S.chunk_level, S.nchunks));
+  RC(launch_level_chunks(S.level_ptr, S.nlev, cbase, S.chunk_start, S.chunk_level, s));
+  RC(mem.alloc(&S.level_done, S.nlev));
+  RC(mem.alloc(&S.ticket, 1));
+  HIPCK(hipMemsetAsync(S.level_done, 0, sizeof(unsigned long long) * S.nlev, s));
+  HIPCK(hipMemsetAsync(S.ticket, 0, sizeof(unsigned long long), s));
+  S.epoch = 0;
+  S.ticket_base = 0;
+  S.grid = std::min<int64_t>(S.nchunks, (int64_t)P->num_cu * 16);
+  return 0;
+}
+
+static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, int64_t split, const double *b,
+                const int32_t *bmap, double *x, double *scat, const int32_t *smap, hipStream_t s) {
+  if (S.nrows == 0) return 0;
+  S.epoch++;
+  TrsvLaunch t;
+  t.nrows = S.nrows;
+  t.rows = S.rows;
+  t.chunk_start = S.chunk_start;
+  t.chunk_level = S.chunk_level;
+  t.nchunks = S.nchunks;
+  t.level_ptr = S.level_ptr;
+  t.level_done = S.level_done;
+  t.epoch = S.epoch;
+  t.ticket = S.ticket;
+  t.ticket_base = S.ticket_base;
+  t.rp = T.rp;
+  t.ci = T.ci;
+  t.v = T.v;
+  t.diag = diag;
+  t.split_col = split;
+  t.b = b;
+  t.b_map = bmap;
+  t.x = x;
+  t.scatter_out = scat;
+  t.scatter_map = smap;
+  t.status = P->status;
+  t.max_waves = S.grid;
+  S.ticket_base += (unsigned long long)(S.nchunks + S.grid);
+  return launch_trsv(t, s);
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void ilu_default_options(ilu_options_t *o) {
+  if (!o) return;
+  o->method = ILU_METHOD_BJ;
+  o->interior_fact = ILU_FACT_ILU0;
+  o->interface_fact = ILU_FACT_ILU0;
+  o->droptol = 0.0;
+  o->lfil = -1;
+  o->inner_iters = 3;
+  o->inner_rtol = 0.0;
+  o->pivot_mode = ILU_PIVOT_ERROR;
+  o->pivot_tol = 0.0;
+}
+
+const char *ilu_last_error(void) { return g_err.c_str(); }
+
+static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts, const ilu_options_t *opt,
+                      hipStream_t s, ilu_precond *P) {
+  const int64_t n = A->n;
+  HIPCK(hipGetDevice(&P->device));
+  {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && cu > 0)
+      P->num_cu = cu;
+  }
+  Mem &mem = P->mem;
+  Mem tmp;
+  RC(mem.alloc(&P->status, 1));
+  HIPCK(hipMemsetAsync(P->status, 0, sizeof(Status), s));
+  HIPCK(hipHostMalloc((void **)&P->host_pinned, 8 * sizeof(double), hipHostMallocDefault));
+
+  const size_t stmpb = scan_tmp_bytes(std::max<int64_t>(n + 1, 256 * ((n + 2047) / 2048) + 1) + 64);
+  void *stmp;
+  RC(tmp.alloc((char **)&stmp, (int64_t)stmpb));
+
+  // 1. validation
+  int32_t *err;
+  RC(tmp.alloc(&err, 2));
+  RC(fill_i32(err, 0x7fffffff, 2, s));
+  RC(launch_validate(A->d_row_ptr, A->d_col, n, A->nnz, d_part, nparts, err, s));
+  int32_t herr[2];
+  HIPCK(hipMemcpyAsync(herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  if (herr[0] != 0x7fffffff)
+    return fail(ILU_ERR_CSR, "invalid CSR at row %d (row pointers, unsorted/duplicate/out-of-range columns, or "
+                "missing diagonal)", herr[0]);
+  if (herr[1] != 0x7fffffff) return fail(ILU_ERR_INVALID_ARG, "partition value out of range at row %d", herr[1]);
+
+  // 2. interface classification, 3. permutation
+  RC(mem.alloc(&P->iface, n));
+  HIPCK(hipMemsetAsync(P->iface, 0, std::max<int64_t>(n, 1), s));
+  RC(launch_classify(A->d_row_ptr, A->d_col, n, d_part, P->iface, s));
+  RC(mem.alloc(&P->perm, n));
+  RC(mem.alloc(&P->iperm, n));
+  {
+    uint32_t *key, *key2;
+    int32_t *val;
+    RC(tmp.alloc(&key, n));
+    RC(tmp.alloc(&key2, n));
+    RC(tmp.alloc(&val, n));
+    RC(launch_perm_keys(n, d_part, nparts, P->iface, key, val, s));
+    void *rtmp;
+    const size_t rtb = radix_tmp_bytes(n);
+    RC(tmp.alloc((char **)&rtmp, (int64_t)rtb));
+    RC(radix_sort(key, val, key2, P->perm, n, bits_for((uint64_t)(2 * nparts)), rtmp, rtb, s));
+    RC(launch_inverse_perm(n, P->perm, P->iperm, s));
+    int64_t *cnt, *starts, tot;
+    RC(tmp.alloc(&cnt, 2 * nparts));
+    RC(histogram_keys(key2, n, 2 * nparts, cnt, s));
+    RC(make_rp(tmp, cnt, 2 * nparts, &starts, &tot, stmp, stmpb, s));
+    std::vector<int64_t> h(2 * nparts + 1);
+    HIPCK(hipMemcpyAsync(h.data(), starts, sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    P->offsets.assign(2 * nparts + 2, 0);
+    for (int k = 0; k <= nparts; k++) P->offsets[k] = h[k];
+    for (int k = 0; k <= nparts; k++) P->offsets[nparts + 1 + k] = h[nparts + k];
+  }
+  P->nB = P->offsets[nparts];
+  P->nS = n - P->nB;
+  const int64_t nB = P->nB, nS = P->nS;
+
+  // 4. permuted subdomain blocks and the cross-subdomain coupling
+  Csr Ah;
+  Ah.n = n;
+  P->Coff.n = nS;
+  {
+    int64_t *ca, *cc;
+    RC(tmp.alloc(&ca, n));
+    RC(tmp.alloc(&cc, nS));
+    RC(launch_extract_counts(A->d_row_ptr, A->d_col, n, nB, d_part, P->perm, ca, cc, s));
+    RC(make_rp(tmp, ca, n, &Ah.rp, &Ah.nnz, stmp, stmpb, s));
+    RC(make_rp(mem, cc, nS, &P->Coff.rp, &P->Coff.nnz, stmp, stmpb, s));
+    RC(tmp.alloc(&Ah.ci, Ah.nnz));
+    RC(tmp.alloc(&Ah.v, Ah.nnz));
+    RC(mem.alloc(&P->Coff.ci, P->Coff.nnz));
+    RC(mem.alloc(&P->Coff.v, P->Coff.nnz));
+    RC(launch_extract_fill(A->d_row_ptr, A->d_col, A->d_val, n, nB, d_part, P->perm, P->iperm, Ah.rp, Ah.ci, Ah.v,
+                           P->Coff.rp, P->Coff.ci, P->Coff.v, s));
+  }
+
+  // 5. factorization of the subdomain blocks
+  const bool schur = opt->method == ILU_METHOD_SCHUR;
+  std::vector<int64_t> as(nparts), al(nparts), bs(nparts), bl(nparts);
+  for (int k = 0; k < nparts; k++) {
+    as[k] = P->offsets[k];
+    al[k] = P->offsets[k + 1] - P->offsets[k];
+    bs[k] = P->offsets[nparts + 1 + k];
+    bl[k] = P->offsets[nparts + 2 + k] - P->offsets[nparts + 1 + k];
+  }
+  Slots F;
+  RC(run_factor(P, tmp, Ah, schur ? nB : n, opt->interior_fact, as, al, bs, bl, F, P->perm, 0, stmp, stmpb, s,
+                "factorization"));
+  int64_t *cnt_tmp;
+  RC(tmp.alloc(&cnt_tmp, n + 1));
+  // L1 = [L_B; W]: all rows, interior columns
+  RC(slots_to_csr(mem, n, F.Lrp, F.Llen, F.Lc, F.Lv, 0, nB, 0, &P->L1, cnt_tmp, stmp, stmpb, s));
+  // U1 = [U_B | Z]: interior rows, every column
+  RC(slots_to_csr(mem, nB, F.Urp, F.Ulen, F.Uc, F.Uv, 0, n, 0, &P->U1, cnt_tmp, stmp, stmpb, s));
+  RC(mem.alloc(&P->DB, nB));
+  if (nB) HIPCK(hipMemcpyAsync(P->DB, F.D, sizeof(double) * nB, hipMemcpyDeviceToDevice, s));
+  RC(mem.alloc(&P->DS, nS));
+  if (!schur) {
+    RC(slots_to_csr(mem, nS, F.Lrp + nB, F.Llen + nB, F.Lc, F.Lv, nB, n, nB, &P->LS, cnt_tmp, stmp, stmpb, s));
+    RC(slots_to_csr(mem, nS, F.Urp + nB, F.Ulen + nB, F.Uc, F.Uv, nB, n, nB, &P->US, cnt_tmp, stmp, stmpb, s));
+    if (nS) HIPCK(hipMemcpyAsync(P->DS, F.D + nB, sizeof(double) * nS, hipMemcpyDeviceToDevice, s));
+  } else if (nS > 0) {
+    Csr St;
+    RC(slots_to_csr(tmp, nS, F.Rrp, F.Rlen, F.Rc, F.Rv, nB, n, nB, &St, cnt_tmp, stmp, stmpb, s));
+    std::vector<int64_t> sa(nparts), sl(nparts), sb(nparts, 0), sbl(nparts, 0);
+    for (int k = 0; k < nparts; k++) {
+      sa[k] = bs[k] - nB;
+      sl[k] = bl[k];
+    }
+    Slots G;
+    RC(run_factor(P, tmp, St, nS, opt->interface_fact, sa, sl, sb, sbl, G, P->perm, nB, stmp, stmpb, s,
+                  "interface factorization"));
+    RC(slots_to_csr(mem, nS, G.Lrp, G.Llen, G.Lc, G.Lv, 0, nS, 0, &P->LS, cnt_tmp, stmp, stmpb, s));
+    RC(slots_to_csr(mem, nS, G.Urp, G.Ulen, G.Uc, G.Uv, 0, nS, 0, &P->US, cnt_tmp, stmp, stmpb, s));
+    HIPCK(hipMemcpyAsync(P->DS, G.D, sizeof(double) * nS, hipMemcpyDeviceToDevice, s));
+  } else {
+    P->LS.n = P->US.n = 0;
+  }
+
+  // 6. level schedules of the four triangular solves
+  RC(build_schedule(P, tmp, P->L1, true, 0, n, P->sL1, stmp, stmpb, s, "levels L"));
+  RC(build_schedule(P, tmp, P->U1, false, 0, nB, P->sU1, stmp, stmpb, s, "levels U"));
+  RC(build_schedule(P, tmp, P->LS, true, 0, nS, P->sLS, stmp, stmpb, s, "levels L_S"));
+  RC(build_schedule(P, tmp, P->US, false, 0, nS, P->sUS, stmp, stmpb, s, "levels U_S"));
+
+  // 7. workspaces
+  RC(mem.alloc(&P->xp, n));
+  if (schur && nS > 0) {
+    const int k = std::max(opt->inner_iters, 0);
+    RC(mem.alloc(&P->iV, (int64_t)(k + 1) * nS));
+    RC(mem.alloc(&P->it1, nS));
+    RC(mem.alloc(&P->it2, nS));
+    RC(mem.alloc(&P->iH, (int64_t)(k + 1) * (k + 1)));
+    RC(mem.alloc(&P->ics, k + 1));
+    RC(mem.alloc(&P->isn, k + 1));
+    RC(mem.alloc(&P->ig, k + 2));
+    RC(mem.alloc(&P->ic, k + 1));
+    RC(mem.alloc(&P->ipa, RED_BLOCKS));
+    RC(mem.alloc(&P->ipb, RED_BLOCKS));
+    RC(mem.alloc(&P->iscal, 8));
+    RC(mem.alloc(&P->iflags, 4));
+  }
+  HIPCK(hipStreamSynchronize(s));
+  return 0;
+}
+
+int ilu_setup(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts, const ilu_options_t *opt_in, void *stream,
+              ilu_precond_t **out) {
+  if (!out) return fail(ILU_ERR_INVALID_ARG, "P must not be NULL");
+  *out = nullptr;
+  if (!A || A->n < 0 || A->nnz < 0) return fail(ILU_ERR_INVALID_ARG, "invalid matrix descriptor");
+  if (A->n > 0 && (!A->d_row_ptr || !A->d_col || !A->d_val)) return fail(ILU_ERR_INVALID_ARG, "NULL matrix array");
+  if (A->n >= 0x7fffffff || A->nnz >= ((int64_t)1 << 40)) return fail(ILU_ERR_INVALID_ARG, "matrix too large");
+  if (nparts < 1 || (!d_part && nparts != 1)) return fail(ILU_ERR_INVALID_ARG, "nparts must be >= 1 (1 without part)");
+  ilu_options_t opt;
+  ilu_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  if (opt.method != ILU_METHOD_BJ && opt.method != ILU_METHOD_SCHUR)
+    return fail(ILU_ERR_INVALID_ARG, "unknown method %d", opt.method);
+  for (int f : {opt.interior_fact, opt.interface_fact})
+    if (f != ILU_FACT_ILU0 && f != ILU_FACT_MILU0 && f != ILU_FACT_ILUT)
+      return fail(ILU_ERR_INVALID_ARG, "unknown factorization %d", f);
+  if (opt.inner_iters < 0 || opt.inner_iters > 1000) return fail(ILU_ERR_INVALID_ARG, "inner_iters out of range");
+  if (!(opt.droptol >= 0.0) || !(opt.inner_rtol >= 0.0) || !(opt.pivot_tol >= 0.0))
+    return fail(ILU_ERR_INVALID_ARG, "negative tolerance");
+  hipStream_t s = (hipStream_t)stream;
+  ilu_precond *P = new ilu_precond();
+  P->n = A->n;
+  P->nparts = nparts;
+  P->opt = opt;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    delete P;
+    return fail(ILU_ERR_HIP, "hipEventCreate failed");
+  }
+  (void)hipEventRecord(e0, s);
+  int rc = setup_impl(A, d_part, nparts, &opt, s, P);
+  (void)hipEventRecord(e1, s);
+  if (rc == 0) {
+    float ms = 0.f;
+    (void)hipEventSynchronize(e1);
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    P->setup_ms = ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    (void)hipStreamSynchronize(s);
+    ilu_destroy(P);
+    return rc;
+  }
+  *out = P;
+  return 0;
+}
+
+void ilu_destroy(ilu_precond_t *P) {
+  if (!P) return;
+  if (P->host_pinned) (void)hipHostFree(P->host_pinned);
+  P->host_pinned = nullptr;
+  delete P->gw;
+  delete P;
+}
+
+// y = the reduced-system GMRES approximation for rhs g' (both in interface numbering)
+static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t s) {
+  const int64_t nS = P->nS;
+  const int k = P->opt.inner_iters;
+  double *V = P->iV;
+  RC(trsv(P, P->sLS, P->LS, nullptr, 0, gp, nullptr, V, nullptr, nullptr, s));
+  RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, V, nullptr, V, nullptr, nullptr, s));
+  if (k == 0) return launch_copy(V, y, nS, s);
+  double *beta = P->iscal, *hn = P->iscal + 1, *est = P->iscal + 2;
+  int *stop = P->iflags, *nsteps = P->iflags + 1;
+  const int ldh = k + 1;
+  RC(launch_dot_partial(V, V, nS, P->ipa, s));
+  RC(launch_reduce_final(P->ipa, beta, s));
+  RC(launch_init_krylov(P->ig, beta, stop, nsteps, s));
+  RC(launch_scale_copy(V, nullptr, beta, V, nS, nullptr, s));
+  for (int j = 0; j < k; j++) {
+    double *vj = V + (int64_t)j * nS, *w = V + (int64_t)(j + 1) * nS;
+    RC(launch_spmv(P->Coff.rp, P->Coff.ci, P->Coff.v, nS, vj, P->it1, s));
+    RC(trsv(P, P->sLS, P->LS, nullptr, 0, P->it1, nullptr, P->it2, nullptr, nullptr, s));
+    RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, P->it2, nullptr, P->it2, nullptr, nullptr, s));
+    RC(launch_vec_sum(w, vj, P->it2, nS, s));
+    double *pc = P->ipa, *pn = P->ipb;
+    RC(launch_dot_partial(w, V, nS, pc, s));
+    for (int i = 0; i <= j; i++) {
+      const double *vnext = i < j ? V + (int64_t)(i + 1) * nS : nullptr;
+      RC(launch_mgs_step(w, V + (int64_t)i * nS, pc, P->iH + i + (int64_t)ldh * j, vnext, nS, pn, stop, s));
+      std::swap(pc, pn);
+    }
+    RC(launch_givens(P->iH, ldh, P->ics, P->isn, P->ig, j, pc, stop, nsteps, est, hn, beta, P->opt.inner_rtol, s));
+    RC(launch_scale_copy(w, nullptr, hn, w, nS, stop, s));
+  }
+  RC(launch_backsolve(P->iH, ldh, P->ig, nsteps, P->ic, s));
+  return launch_combine(y, V, nS, P->ic, nsteps, nS, false, s);
+}
+
+static int apply_impl(ilu_precond *P, const double *r, double *z, hipStream_t s) {
+  const int64_t n = P->n, nB = P->nB, nS = P->nS;
+  if (n == 0) return 0;
+  double *xp = P->xp;
+  // f' = L_B^-1 r[perm_B] and g' = r[perm_S] - W f' in one level-scheduled pass
+  RC(trsv(P, P->sL1, P->L1, nullptr, 0, r, P->perm, xp, nullptr, nullptr, s));
+  if (nS > 0) {
+    double *gp = xp + nB;
+    if (P->opt.method == ILU_METHOD_SCHUR) {
+      RC(inner_gmres(P, gp, gp, s));
+    } else {
+      RC(trsv(P, P->sLS, P->LS, nullptr, 0, gp, nullptr, gp, nullptr, nullptr, s));
+      RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, gp, nullptr, gp, nullptr, nullptr, s));
+    }
+    RC(launch_scatter(gp, P->perm + nB, nS, z, s));
+  }
+  // u = U_B^-1 (f' - Z y), scattered to z
+  RC(trsv(P, P->sU1, P->U1, P->DB, nB, xp, nullptr, xp, z, P->perm, s));
+  return 0;
+}
+
+int ilu_apply(ilu_precond_t *P, const double *d_r, double *d_z, void *stream) {
+  if (!P || (P->n > 0 && (!d_r || !d_z))) return fail(ILU_ERR_INVALID_ARG, "NULL argument");
+  if (d_r == d_z && P->n > 0) return fail(ILU_ERR_INVALID_ARG, "r and z must not alias");
+  HIPCK(hipSetDevice(P->device));
+  return apply_impl(P, d_r, d_z, (hipStream_t)stream);
+}
+
+int csr_spmv(const ilu_csr_t *A, const double *d_x, double *d_y, void *stream) {
+  if (!A || A->n < 0 || (A->n > 0 && (!d_x || !d_y || !A->d_row_ptr || !A->d_col || !A->d_val)))
+    return fail(ILU_ERR_INVALID_ARG, "invalid arguments");
+  return launch_spmv(A->d_row_ptr, A->d_col, A->d_val, A->n, d_x, d_y, (hipStream_t)stream);
+}
+
+static int read_scalars(ilu_precond *P, const double *d, int cnt, hipStream_t s) {
+  HIPCK(hipMemcpyAsync(P->host_pinned, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  return 0;
+}
+
+static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, double *x, double rtol, int m, int maxit,
+                       hipStream_t s, ilu_result_t *res, double *hist) {
+  const int64_t n = A->n;
+  if (!P->gw || P->gw->n != n || P->gw->m != m) {
+    delete P->gw;
+    P->gw = new GmresWork();
+    GmresWork &w = *P->gw;
+    w.n = n;
+    w.m = m;
+    RC(w.mem.alloc(&w.V, (int64_t)(m + 1) * n));
+    RC(w.mem.alloc(&w.Zb, (int64_t)m * n));
+    RC(w.mem.alloc(&w.r, n));
+    RC(w.mem.alloc(&w.H, (int64_t)(m + 1) * (m + 1)));
+    RC(w.mem.alloc(&w.cs, m + 1));
+    RC(w.mem.alloc(&w.sn, m + 1));
+    RC(w.mem.alloc(&w.g, m + 2));
+    RC(w.mem.alloc(&w.c, m + 1));
+    RC(w.mem.alloc(&w.pa, RED_BLOCKS));
+    RC(w.mem.alloc(&w.pb, RED_BLOCKS));
+    RC(w.mem.alloc(&w.scal, 8));
+    RC(w.mem.alloc(&w.flags, 4));
+  }
+  GmresWork &w = *P->gw;
+  double *bnorm = w.scal, *beta = w.scal + 1, *hn = w.scal + 2, *est = w.scal + 3;
+  int *stop = w.flags, *nsteps = w.flags + 1;
+  const int ldh = m + 1;
+  const int64_t *rp = A->d_row_ptr;
+  const int32_t *ci = A->d_col;
+  const double *av = A->d_val;
+  int its = 0, converged = 0;
+  double relres = 0.0;
+
+  RC(launch_dot_partial(b, b, n, w.pa, s));
+  RC(launch_reduce_final(w.pa, bnorm, s));
+  RC(read_scalars(P, bnorm, 1, s));
+  const double hb = P->host_pinned[0];
+  if (!std::isfinite(hb)) return fail(ILU_ERR_BREAKDOWN, "non-finite ||b||");
+  if (hb == 0.0) {
+    RC(fill_f64(x, 0.0, n, s));
+    HIPCK(hipStreamSynchronize(s));
+    if (hist) hist[0] = 0.0;
+    converged = 1;
+  } else {
+    RC(launch_residual(rp, ci, av, n, b, x, w.r, s));
+    RC(launch_dot_partial(w.r, w.r, n, w.pa, s));
+    RC(launch_reduce_final(w.pa, beta, s));
+    RC(read_scalars(P, beta, 1, s));
+    double hbeta = P->host_pinned[0];
+    relres = hbeta / hb;
+    if (hist) hist[0] = relres;
+    if (!std::isfinite(hbeta)) return fail(ILU_ERR_BREAKDOWN, "non-finite initial residual");
+    if (hbeta <= rtol * hb) converged = 1;
+    while (!converged && its < maxit) {
+      RC(launch_scale_copy(w.r, nullptr, beta, w.V, n, nullptr, s));
+      RC(launch_init_krylov(w.g, beta, stop, nsteps, s));
+      for (int j = 0; j < m; j++) {
+        double *vj = w.V + (int64_t)j * n, *wv = w.V + (int64_t)(j + 1) * n, *zj = w.Zb + (int64_t)j * n;
+        RC(apply_impl(P, vj, zj, s));
+        RC(launch_spmv(rp, ci, av, n, zj, wv, s));
+        double *pc = w.pa, *pn = w.pb;
+        RC(launch_dot_partial(wv, w.V, n, pc, s));
+        for (int i = 0; i <= j; i++) {
+          const double *vnext = i < j ? w.V + (int64_t)(i + 1) * n : nullptr;
+          RC(launch_mgs_step(wv, w.V + (int64_t)i * n, pc, w.H + i + (int64_t)ldh * j, vnext, n, pn, stop, s));
+          std::swap(pc, pn);
+        }
+        RC(launch_givens(w.H, ldh, w.cs, w.sn, w.g, j, pc, stop, nsteps, est, hn, bnorm, rtol, s));
+        RC(launch_scale_copy(wv, nullptr, hn, wv, n, stop, s));
+        its++;
+        HIPCK(hipMemcpyAsync(P->host_pinned, est, sizeof(double), hipMemcpyDeviceToHost, s));
+        int hstop = 0;
+        HIPCK(hipMemcpyAsync(&hstop, stop, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        const double e = P->host_pinned[0];
+        if (hist) hist[its] = e / hb;
+        if (hstop == 3) return fail(ILU_ERR_BREAKDOWN, "non-finite value in the Arnoldi process at step %d", its);
+        if (hstop || its >= maxit) break;
+      }
+      RC(launch_backsolve(w.H, ldh, w.g, nsteps, w.c, s));
+      RC(launch_combine(x, w.Zb, n, w.c, nsteps, n, true, s));
+      RC(launch_residual(rp, ci, av, n, b, x, w.r, s));
+      RC(launch_dot_partial(w.r, w.r, n, w.pa, s));
+      RC(launch_reduce_final(w.pa, beta, s));
+      RC(read_scalars(P, beta, 1, s));
+      hbeta = P->host_pinned[0];
+      relres = hbeta / hb;
+      if (!std::isfinite(hbeta)) return fail(ILU_ERR_BREAKDOWN, "non-finite residual");
+      if (hbeta <= rtol * hb) converged = 1;
+    }
+  }
+  RC(check_status(P, s, "solve", nullptr, 0));
+  if (res) {
+    res->iterations = its;
+    res->converged = converged;
+    res->final_relres = relres;
+  }
+  return converged ? ILU_OK : ILU_NOT_CONVERGED;
+}
+
+int fgmres_solve(const ilu_csr_t *A, ilu_precond_t *P, const double *d_b, double *d_x, double rtol, int32_t restart,
+                 int32_t maxit, void *stream, ilu_result_t *res, double *h_hist) {
+  if (!A || !P || A->n != P->n) return fail(ILU_ERR_INVALID_ARG, "matrix and preconditioner sizes differ");
+  if (A->n > 0 && (!d_b || !d_x)) return fail(ILU_ERR_INVALID_ARG, "NULL vector");
+  if (restart < 1 || restart > 1000 || maxit < 0 || !(rtol >= 0.0))
+    return fail(ILU_ERR_INVALID_ARG, "restart/maxit/rtol out of range");
+  HIPCK(hipSetDevice(P->device));
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  (void)hipEventRecord(e0, s);
+  int rc = fgmres_impl(A, P, d_b, d_x, rtol, restart, maxit, s, res, h_hist);
+  (void)hipEventRecord(e1, s);
+  float ms = 0.f;
+  (void)hipEventSynchronize(e1);
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (res) {
+    res->setup_ms = P->setup_ms;
+    res->solve_ms = ms;
+  }
+  return rc;
+}
+
+int ilu_info(ilu_precond_t *P, int64_t *n, int64_t *nB, int64_t *nS, int32_t *nparts) {
+  if (!P) return fail(ILU_ERR_INVALID_ARG, "NULL handle");
+  if (n) *n = P->n;
+  if (nB) *nB = P->nB;
+  if (nS) *nS = P->nS;
+  if (nparts) *nparts = P->nparts;
+  return 0;
+}
+
+static int export_csr(const Csr &c, int field, void *h, int64_t *len) {
+  const int64_t cnt = field == 0 ? (c.rp ? c.n + 1 : 0) : c.nnz;
+  if (!h) {
+    *len = cnt;
+    return 0;
+  }
+  if (*len < cnt) return fail(ILU_ERR_INVALID_ARG, "export buffer too small");
+  *len = cnt;
+  if (cnt == 0) return 0;
+  const void *src = field == 0 ? (const void *)c.rp : field == 1 ? (const void *)c.ci : (const void *)c.v;
+  const size_t es = field == 0 ? 8 : field == 1 ? 4 : 8;
+  HIPCK(hipMemcpy(h, src, es * cnt, hipMemcpyDeviceToHost));
+  return 0;
+}
+
+static int export_raw(const void *d, int64_t cnt, size_t es, void *h, int64_t *len) {
+  if (!h) {
+    *len = cnt;
+    return 0;
+  }
+  if (*len < cnt) return fail(ILU_ERR_INVALID_ARG, "export buffer too small");
+  *len = cnt;
+  if (cnt > 0) HIPCK(hipMemcpy(h, d, es * cnt, hipMemcpyDeviceToHost));
+  return 0;
+}
+
+// L_B / W / U_B / Z are views of L1 / U1 restricted by rows / columns: exported
+// through a host-side split of the copied arrays.
+static int export_split(const Csr &c, int64_t r0, int64_t r1, int64_t c0, int64_t c1, int64_t shift, int field,
+                        void *h, int64_t *len) {
+  std::vector<int64_t> rp(c.n + 1, 0);
+  std::vector<int32_t> ci(c.nnz);
+  std::vector<double> v(c.nnz);
+  if (c.n > 0) HIPCK(hipMemcpy(rp.data(), c.rp, 8 * (c.n + 1), hipMemcpyDeviceToHost));
+  if (c.nnz > 0) {
+    HIPCK(hipMemcpy(ci.data(), c.ci, 4 * c.nnz, hipMemcpyDeviceToHost));
+    HIPCK(hipMemcpy(v.data(), c.v, 8 * c.nnz, hipMemcpyDeviceToHost));
+  }
+  std::vector<int64_t> orp(1, 0);
+  std::vector<int32_t> oci;
+  std::vector<double> ov;
+  for (int64_t r = r0; r < r1; r++) {
+    for (int64_t p = rp[r]; p < rp[r + 1]; p++)
+      if (ci[p] >= c0 && ci[p] < c1) {
+        oci.push_back((int32_t)(ci[p] - shift));
+        ov.push_back(v[p]);
+      }
+    orp.push_back((int64_t)oci.size());
+  }
+  const int64_t cnt = field == 0 ? (int64_t)orp.size() : (int64_t)oci.size();
+  if (!h) {
+    *len = cnt;
+    return 0;
+  }
+  if (*len < cnt) return fail(ILU_ERR_INVALID_ARG, "export buffer too small");
+  *len = cnt;
+  if (field == 0) memcpy(h, orp.data(), 8 * cnt);
+  if (field == 1) memcpy(h, oci.data(), 4 * cnt);
+  if (field == 2) memcpy(h, ov.data(), 8 * cnt);
+  return 0;
+}
+
+int ilu_export(ilu_precond_t *P, int32_t what, void *h, int64_t *len) {
+  if (!P || !len) return fail(ILU_ERR_INVALID_ARG, "NULL argument");
+  const int64_t n = P->n, nB = P->nB, nS = P->nS;
+  switch (what) {
+    case 0: return export_raw(P->perm, n, 4, h, len);
+    case 1: return export_raw(P->iperm, n, 4, h, len);
+    case 2: return export_raw(P->iface, n, 1, h, len);
+    case 3: {
+      const int64_t cnt = (int64_t)P->offsets.size();
+      if (!h) {
+        *len = cnt;
+        return 0;
+      }
+      if (*len < cnt) return fail(ILU_ERR_INVALID_ARG, "export buffer too small");
+      *len = cnt;
+      memcpy(h, P->offsets.data(), 8 * cnt);
+      return 0;
+    }
+    case 16: return export_raw(P->DB, nB, 8, h, len);
+    case 29: return export_raw(P->DS, nS, 8, h, len);
+    case 40: return export_raw(P->sL1.level_of, nB, 4, h, len);
+    case 41: return export_raw(P->sU1.level_of, nB, 4, h, len);
+    case 42: return export_raw(P->sLS.level_of, nS, 4, h, len);
+    case 43: return export_raw(P->sUS.level_of, nS, 4, h, len);
+    default: break;
+  }
+  if (what >= 10 && what <= 12) return export_split(P->L1, 0, nB, 0, nB, 0, what - 10, h, len);
+  if (what >= 13 && what <= 15) return export_split(P->U1, 0, nB, 0, nB, 0, what - 13, h, len);
+  if (what >= 17 && what <= 19) return export_split(P->U1, 0, nB, nB, n, 0, what - 17, h, len);
+  if (what >= 20 && what <= 22) return export_split(P->L1, nB, n, 0, nB, 0, what - 20, h, len);
+  if (what >= 23 && what <= 25) return export_csr(P->LS, what - 23, h, len);
+  if (what >= 26 && what <= 28) return export_csr(P->US, what - 26, h, len);
+  if (what >= 30 && what <= 32) return export_csr(P->Coff, what - 30, h, len);
+  return fail(ILU_ERR_INVALID_ARG, "unknown export code %d", what);
+}
+
+}  // extern "C"

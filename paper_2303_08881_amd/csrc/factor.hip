@@ -1,0 +1,575 @@
+// factor.hip -- row-wise incomplete LU on the device: ILU(0), MILU(0), ILUT,
+// full rows and partial (Schur-complement) rows.
+//
+// What is computed (per row r, columns ascending):
+//   * w = row r of M;  tau_r = droptol * ||row r of M||_2 (ILUT only);
+//   * for each pivot column k < lim (lim = r for full rows, nfull for the
+//     partial rows of eq. (17)) in ascending order:
+//       w_k = w_k / u_kk; ILUT: if |w_k| < tau_r drop it and skip;
+//       w_j = fma(-w_k, u_kj, w_j) for u_kj in the U part of row k;
+//       a u_kj outside the current row is new fill (ILUT), dropped and summed
+//       into the diagonal (MILU, Section 2.3 eq. (16)), or dropped (ILU(0));
+//   * ILUT: off-diagonal entries of the U / Schur part below tau_r are
+//     dropped; each part keeps its lfil largest magnitudes (ties: smaller
+//     column first); the diagonal is always kept.
+//
+// GPU organisation (no level analysis is needed, so fill may appear anywhere):
+//   * one wavefront per row, rows handed out by an atomic ticket in a
+//     topological order: subdomains are independent, and inside a subdomain
+//     every dependency of a row precedes it in the local (interior-first)
+//     order.  A ticket covers CHUNK consecutive local rows of one subdomain,
+//     processed one after the other by the same wave, and tickets interleave
+//     the subdomains round-robin;
+//   * a row waits on the per-row completion flag of each pivot k
+//     (agent-scope release/acquire); every wait is bounded;
+//   * the working row is kept sorted by column in LDS; the pivot walk is a
+//     scan of its prefix; fill is merged in place (one wave: read all, then
+//     write all);
+//   * results go to fixed-capacity per-row slots (ELL-like, capacities from a
+//     scan) and are compacted into CSR afterwards.
+#include "common.hpp"
+
+namespace silu {
+
+constexpr int FACT_CAP = 512;  // working-row capacity (entries) per wave
+constexpr int FACT_CHUNK = 16; // consecutive rows per ticket
+
+struct FactArgs {
+  const int64_t *rp;
+  const int32_t *ci;
+  const double *v;
+  int64_t n, nfull;
+  int32_t method;
+  double droptol;
+  int32_t lfil;
+  int32_t pivot_mode;
+  double pivot_tol;
+  // schedule
+  int64_t nchunks;
+  const int64_t *chunk_ptr;  // [nchunks+1] into order[]
+  const int32_t *order;      // rows in ticket order
+  unsigned int *ticket;
+  // outputs
+  const int64_t *Lrp;
+  int32_t *Lc;
+  double *Lv;
+  int32_t *Llen;
+  const int64_t *Urp;
+  int32_t *Uc;
+  double *Uv;
+  int32_t *Ulen;
+  const int64_t *Rrp;
+  int32_t *Rc;
+  double *Rv;
+  int32_t *Rlen;
+  double *D;
+  int *done;
+  int epoch;
+  Status *st;
+};
+
+__device__ inline int lower_bound_lds(const int32_t *a, int lo, int hi, int32_t key) {
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Keep-set of a part [b, e) of the working row: predicate p(e) and, for ILUT,
+// the lfil largest magnitudes.  Writes kept entries in column order to
+// (oc, ov) and returns their count.  extra_diag >= 0 marks an index that is
+// always kept and does not count toward lfil.
+__device__ int emit_part(const int32_t *wc, const double *wv, const uint8_t *wd, int b, int e, bool ilut,
+                         double tau, int lfil, int always, int32_t *oc, double *ov, bool tau_drop) {
+  const int lane = lane_id();
+  // candidates: not dropped, and (tau_drop -> |w| >= tau); `always` is separate
+  int ncand = 0;
+  for (int base = b; base < e; base += WAVE) {
+    int x = base + lane;
+    bool c = x < e && x != always && !wd[x] && !(ilut && tau_drop && fabs(wv[x]) < tau);
+    ncand += popc64(ballot(c));
+  }
+  const bool limit = ilut && lfil >= 0 && ncand > lfil;
+  int out = 0;
+  for (int base = b; base < e; base += WAVE) {
+    int x = base + lane;
+    bool keep = false;
+    if (x < e) {
+      if (x == always) {
+        keep = true;
+      } else {
+        keep = !wd[x] && !(ilut && tau_drop && fabs(wv[x]) < tau);
+        if (keep && limit) {
+          const double m = fabs(wv[x]);
+          const int32_t cx = wc[x];
+          int rank = 0;
+          for (int y = b; y < e; y++) {
+            if (y == always || wd[y]) continue;
+            const double my = fabs(wv[y]);
+            if (tau_drop && my < tau) continue;
+            if (my > m || (my == m && wc[y] < cx)) rank++;
+          }
+          keep = rank < lfil;
+        }
+      }
+    }
+    unsigned long long mk = ballot(keep);
+    if (keep) {
+      int at = out + mbcnt(mk);
+      oc[at] = wc[x];
+      ov[at] = wv[x];
+    }
+    out += popc64(mk);
+  }
+  return out;
+}
+
+__global__ void __launch_bounds__(WAVE) k_factor_rows(FactArgs a) {
+  __shared__ int32_t wc[FACT_CAP];
+  __shared__ double wv[FACT_CAP];
+  __shared__ uint8_t wd[FACT_CAP];
+  __shared__ int32_t fins[WAVE];
+  __shared__ int32_t fcol[WAVE];
+  __shared__ double fval[WAVE];
+  const int lane = lane_id();
+  const bool ilut = a.method == ILU_FACT_ILUT;
+  const bool milu = a.method == ILU_FACT_MILU0;
+
+  for (;;) {
+    const unsigned int t = wave_ticket(a.ticket);
+    if (t >= (unsigned long long)a.nchunks) return;
+    if (ld_relaxed(&a.st->abort)) return;
+    const int64_t cb = a.chunk_ptr[t], ce = a.chunk_ptr[t + 1];
+    for (int64_t oi = cb; oi < ce; oi++) {
+      const int64_t r = a.order[oi];
+      const int64_t lim = r < a.nfull ? r : a.nfull;
+      const int64_t rb = a.rp[r];
+      int len = (int)(a.rp[r + 1] - rb);
+      if (len > FACT_CAP) {
+        if (lane == 0) raise_error(a.st, ILU_ERR_CAPACITY, r);
+        return;
+      }
+      for (int x = lane; x < len; x += WAVE) {
+        wc[x] = a.ci[rb + x];
+        wv[x] = a.v[rb + x];
+        wd[x] = 0;
+      }
+      __syncthreads();
+      double tau = 0.0, rowinf = 0.0;
+      if (ilut) {
+        double s = 0.0;
+        if (lane == 0)
+          for (int x = 0; x < len; x++) s = fma(wv[x], wv[x], s);
+        tau = uniform_f64(a.droptol * sqrt(__shfl(s, 0, WAVE)));
+      }
+      if (a.pivot_mode == ILU_PIVOT_PERTURB) {
+        double m = 0.0;
+        for (int x = lane; x < len; x += WAVE) m = fmax(m, fabs(wv[x]));
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, WAVE));
+        rowinf = uniform_f64(m);
+      }
+      double drop = 0.0;  // MILU: dropped fill of this row, summed in (k, j) order (lane 0)
+      bool failed = false;
+
+      for (int pos = 0;; pos++) {
+        // every value that decides the control flow below is made wave-uniform
+        const int32_t k = uniform_i32(pos < len ? wc[pos] : 0x7fffffff);
+        if (k >= lim) break;
+        bool ok = true;
+        if (lane == 0) ok = wait_flag_eq(&a.done[k], a.epoch, a.st, r);
+        if (!uniform_i32((int)ok)) {
+          failed = true;
+          break;
+        }
+        fence_acquire();
+        const double wk = uniform_f64(wv[pos] / a.D[k]);
+        if (ilut && fabs(wk) < tau) {
+          __syncthreads();
+          if (lane == 0) {
+            wv[pos] = 0.0;
+            wd[pos] = 1;
+          }
+          __syncthreads();
+          continue;
+        }
+        __syncthreads();
+        if (lane == 0) wv[pos] = wk;
+        __syncthreads();
+        const int64_t ub = a.Urp[k];
+        const int ul = a.Ulen[k];
+        for (int base = 0; base < ul; base += WAVE) {
+          const int j = base + lane;
+          const bool have = j < ul;
+          const int32_t c = have ? a.Uc[ub + j] : 0x7fffffff;
+          const double u = have ? a.Uv[ub + j] : 0.0;
+          const int idx = have ? lower_bound_lds(wc, pos + 1, len, c) : len;
+          const bool found = have && idx < len && wc[idx] == c;
+          if (found) wv[idx] = fma(-wk, u, wv[idx]);
+          const bool fill = have && !found;
+          const unsigned long long fm = ballot(fill);
+          if (fm == 0ull) {
+            __syncthreads();
+            continue;
+          }
+          if (ilut) {
+            const int nf = popc64(fm);
+            if (len + nf > FACT_CAP) {
+              if (lane == 0) raise_error(a.st, ILU_ERR_CAPACITY, r);
+              return;
+            }
+            if (fill) {
+              const int rk = mbcnt(fm);
+              fins[rk] = idx;
+              fcol[rk] = c;
+              fval[rk] = fma(-wk, u, 0.0);
+            }
+            __syncthreads();
+            // read every working entry after the pivot, then write it shifted
+            int32_t rc_[FACT_CAP / WAVE];
+            double rv_[FACT_CAP / WAVE];
+            int np_[FACT_CAP / WAVE];
+#pragma unroll
+            for (int q = 0; q < FACT_CAP / WAVE; q++) {
+              const int x = pos + 1 + q * WAVE + lane;
+              np_[q] = -1;
+              if (x < len) {
+                rc_[q] = wc[x];
+                rv_[q] = wv[x];
+                // number of fills inserted at or before x
+                int lo = 0, hi = nf;
+                while (lo < hi) {
+                  int mid = (lo + hi) >> 1;
+                  if (fins[mid] <= x)
+                    lo = mid + 1;
+                  else
+                    hi = mid;
+                }
+                np_[q] = x + lo;
+              }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < FACT_CAP / WAVE; q++) {
+              if (np_[q] >= 0) {
+                wc[np_[q]] = rc_[q];
+                wv[np_[q]] = rv_[q];
+                wd[np_[q]] = 0;
+              }
+            }
+            if (lane < nf) {
+              const int at = fins[lane] + lane;
+              wc[at] = fcol[lane];
+              wv[at] = fval[lane];
+              wd[at] = 0;
+            }
+            len += nf;
+            __syncthreads();
+          } else if (milu) {
+            // sum the dropped products in column order, exactly as written
+            unsigned long long m = fm;
+            while (m) {
+              const int b = __ffsll((long long)m) - 1;
+              m &= m - 1;
+              const double ubv = __shfl(u, b, WAVE);
+              if (lane == 0) drop = fma(-wk, ubv, drop);
+            }
+            __syncthreads();
+          } else {
+            __syncthreads();
+          }
+        }
+      }
+      if (failed) return;
+      __syncthreads();
+
+      if (r < a.nfull) {  // full row: L | d | U
+        const int pd = uniform_i32(lower_bound_lds(wc, 0, len, (int32_t)r));
+        double d = wv[pd];
+        if (milu) d = d + __shfl(drop, 0, WAVE);
+        d = uniform_f64(d);
+        if (a.pivot_mode == ILU_PIVOT_PERTURB) {
+          const double thr = a.pivot_tol * rowinf;
+          if (fabs(d) < thr) d = (d < 0.0) ? -thr : thr;
+        }
+        if (d == 0.0 || !isfinite(d)) {
+          if (lane == 0) raise_error(a.st, ILU_ERR_ZERO_PIVOT, r);
+          return;
+        }
+        if (lane == 0) a.D[r] = d;
+        const int nl = emit_part(wc, wv, wd, 0, pd, ilut, tau, a.lfil, -1, a.Lc + a.Lrp[r], a.Lv + a.Lrp[r], false);
+        const int nu =
+            emit_part(wc, wv, wd, pd + 1, len, ilut, tau, a.lfil, -1, a.Uc + a.Urp[r], a.Uv + a.Urp[r], true);
+        if (lane == 0) {
+          a.Llen[r] = nl;
+          a.Ulen[r] = nu;
+        }
+      } else {  // partial row: L (interior columns) | Schur remainder R
+        const int pl = uniform_i32(lower_bound_lds(wc, 0, len, (int32_t)a.nfull));
+        const int pd = uniform_i32(lower_bound_lds(wc, pl, len, (int32_t)r));
+        if (milu) {
+          __syncthreads();
+          if (lane == 0) wv[pd] = wv[pd] + drop;
+          __syncthreads();
+        }
+        const int nl = emit_part(wc, wv, wd, 0, pl, ilut, tau, a.lfil, -1, a.Lc + a.Lrp[r], a.Lv + a.Lrp[r], false);
+        const int64_t ro = a.Rrp[r - a.nfull];
+        const int nr = emit_part(wc, wv, wd, pl, len, ilut, tau, a.lfil, pd, a.Rc + ro, a.Rv + ro, true);
+        if (lane == 0) {
+          a.Llen[r] = nl;
+          a.Rlen[r - a.nfull] = nr;
+        }
+      }
+      __syncthreads();
+      if (lane == 0) st_release(&a.done[r], a.epoch);
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// capacities of the per-row output slots
+// ---------------------------------------------------------------------------
+__global__ void k_fact_caps(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nfull, int32_t method,
+                            int32_t lfil, int64_t *Lcap, int64_t *Ucap, int64_t *Rcap) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int64_t lim = r < nfull ? r : nfull;
+  int64_t cl = 0, cu = 0, cr = 0;
+  if (method == ILU_FACT_ILUT) {
+    cl = lfil >= 0 ? (lfil < lim ? lfil : lim) : lim;
+    if (r < nfull) {
+      const int64_t hi = n - r - 1;
+      cu = lfil >= 0 ? (lfil < hi ? lfil : hi) : hi;
+    } else {
+      const int64_t hi = n - nfull - 1;
+      cr = (lfil >= 0 ? (lfil < hi ? lfil : hi) : hi) + 1;
+    }
+  } else {
+    for (int64_t p = rp[r]; p < rp[r + 1]; p++) {
+      const int64_t c = ci[p];
+      if (c < lim)
+        cl++;
+      else if (r < nfull && c > r)
+        cu++;
+      else if (r >= nfull)
+        cr++;
+    }
+  }
+  Lcap[r] = cl;
+  if (r < nfull)
+    Ucap[r] = cu;
+  else
+    Rcap[r - nfull] = cr;
+}
+
+// compaction of per-row slots into CSR (one thread per row)
+__global__ void k_compact_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len, const int32_t *sc,
+                               const double *sv, const int64_t *out_rp, int32_t *oc, double *ov, int64_t col_lo,
+                               int64_t col_hi, int64_t shift) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int64_t b = cap_rp[r];
+  int64_t o = out_rp[r];
+  for (int64_t p = b; p < b + len[r]; p++) {
+    const int64_t c = sc[p];
+    if (c >= col_lo && c < col_hi) {
+      oc[o] = (int32_t)(c - shift);
+      ov[o] = sv[p];
+      o++;
+    }
+  }
+}
+
+__global__ void k_count_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len, const int32_t *sc,
+                             int64_t col_lo, int64_t col_hi, int64_t *cnt) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int64_t b = cap_rp[r];
+  int64_t k = 0;
+  for (int64_t p = b; p < b + len[r]; p++) {
+    const int64_t c = sc[p];
+    k += (c >= col_lo && c < col_hi);
+  }
+  cnt[r] = k;
+}
+
+// ---------------------------------------------------------------------------
+// schedule: chunks of FACT_CHUNK consecutive local rows, subdomains interleaved
+// ---------------------------------------------------------------------------
+// Segment s covers local rows [0, size_s): the first a_len[s] of them are rows
+// a_start[s] + l, the rest b_start[s] + (l - a_len[s]).
+__global__ void k_chunk_counts(int32_t nseg, const int64_t *a_start, const int64_t *a_len, const int64_t *b_start,
+                               const int64_t *b_len, int64_t *nchunks_seg) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  const int64_t size = a_len[s] + b_len[s];
+  nchunks_seg[s] = (size + FACT_CHUNK - 1) / FACT_CHUNK;
+  (void)a_start;
+  (void)b_start;
+}
+
+// chunk id c (segment-major) -> key = local chunk index, value = c
+__global__ void k_chunk_keys(int64_t nchunks, int32_t nseg, const int64_t *cstart, uint32_t *key, int32_t *val) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= nchunks) return;
+  int lo = 0, hi = nseg;  // largest s with cstart[s] <= c
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (cstart[mid] <= c)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  key[c] = (uint32_t)(c - cstart[lo]);
+  val[c] = (int32_t)c;
+}
+
+// ticket t -> its chunk length
+__global__ void k_chunk_len(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
+                            const int64_t *a_len, const int64_t *b_len, int64_t *len) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nchunks) return;
+  const int64_t c = sorted_chunk[t];
+  int lo = 0, hi = nseg;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (cstart[mid] <= c)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int64_t q = c - cstart[lo];
+  const int64_t size = a_len[lo] + b_len[lo];
+  const int64_t first = q * FACT_CHUNK;
+  const int64_t m = size - first < FACT_CHUNK ? size - first : FACT_CHUNK;
+  len[t] = m;
+}
+
+__global__ void k_chunk_rows(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
+                             const int64_t *a_start, const int64_t *a_len, const int64_t *b_start,
+                             const int64_t *chunk_ptr, int32_t *order) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nchunks) return;
+  const int64_t c = sorted_chunk[t];
+  int lo = 0, hi = nseg;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (cstart[mid] <= c)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int64_t q = c - cstart[lo];
+  const int64_t o = chunk_ptr[t];
+  const int64_t m = chunk_ptr[t + 1] - o;
+  for (int64_t k = 0; k < m; k++) {
+    const int64_t l = q * FACT_CHUNK + k;
+    order[o + k] = (int32_t)(l < a_len[lo] ? a_start[lo] + l : b_start[lo] + (l - a_len[lo]));
+  }
+}
+
+}  // namespace silu
+
+// ---------------------------------------------------------------------------
+// host launchers (called from the runtime)
+// ---------------------------------------------------------------------------
+#include "launch.hpp"
+
+namespace silu {
+
+int launch_fact_caps(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nfull, int32_t method, int32_t lfil,
+                     int64_t *Lcap, int64_t *Ucap, int64_t *Rcap, hipStream_t s) {
+  if (n == 0) return 0;
+  k_fact_caps<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, n, nfull, method, lfil, Lcap, Ucap, Rcap);
+  return check_launch("fact_caps");
+}
+
+int launch_factor_rows(const FactLaunch &f, hipStream_t s) {
+  FactArgs a;
+  a.rp = f.rp;
+  a.ci = f.ci;
+  a.v = f.v;
+  a.n = f.n;
+  a.nfull = f.nfull;
+  a.method = f.method;
+  a.droptol = f.droptol;
+  a.lfil = f.lfil;
+  a.pivot_mode = f.pivot_mode;
+  a.pivot_tol = f.pivot_tol;
+  a.nchunks = f.nchunks;
+  a.chunk_ptr = f.chunk_ptr;
+  a.order = f.order;
+  a.ticket = f.ticket;
+  a.Lrp = f.Lrp;
+  a.Lc = f.Lc;
+  a.Lv = f.Lv;
+  a.Llen = f.Llen;
+  a.Urp = f.Urp;
+  a.Uc = f.Uc;
+  a.Uv = f.Uv;
+  a.Ulen = f.Ulen;
+  a.Rrp = f.Rrp;
+  a.Rc = f.Rc;
+  a.Rv = f.Rv;
+  a.Rlen = f.Rlen;
+  a.D = f.D;
+  a.done = f.done;
+  a.epoch = f.epoch;
+  a.st = (Status *)f.status;
+  if (f.nchunks == 0) return 0;
+  int64_t grid = f.nchunks < f.max_waves ? f.nchunks : f.max_waves;
+  k_factor_rows<<<(unsigned)grid, WAVE, 0, s>>>(a);
+  return check_launch("factor_rows");
+}
+
+int launch_compact_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len, const int32_t *sc,
+                        const double *sv, const int64_t *out_rp, int32_t *oc, double *ov, int64_t col_lo,
+                        int64_t col_hi, int64_t shift, hipStream_t s) {
+  if (nrows == 0) return 0;
+  k_compact_rows<<<(unsigned)((nrows + 255) / 256), 256, 0, s>>>(nrows, cap_rp, len, sc, sv, out_rp, oc, ov, col_lo,
+                                                                  col_hi, shift);
+  return check_launch("compact_rows");
+}
+
+int launch_count_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len, const int32_t *sc, int64_t col_lo,
+                      int64_t col_hi, int64_t *cnt, hipStream_t s) {
+  if (nrows == 0) return 0;
+  k_count_rows<<<(unsigned)((nrows + 255) / 256), 256, 0, s>>>(nrows, cap_rp, len, sc, col_lo, col_hi, cnt);
+  return check_launch("count_rows");
+}
+
+int launch_chunk_counts(int32_t nseg, const int64_t *a_start, const int64_t *a_len, const int64_t *b_start,
+                        const int64_t *b_len, int64_t *nchunks_seg, hipStream_t s) {
+  k_chunk_counts<<<(nseg + 255) / 256, 256, 0, s>>>(nseg, a_start, a_len, b_start, b_len, nchunks_seg);
+  return check_launch("chunk_counts");
+}
+
+int launch_chunk_keys(int64_t nchunks, int32_t nseg, const int64_t *cstart, uint32_t *key, int32_t *val,
+                      hipStream_t s) {
+  if (nchunks == 0) return 0;
+  k_chunk_keys<<<(unsigned)((nchunks + 255) / 256), 256, 0, s>>>(nchunks, nseg, cstart, key, val);
+  return check_launch("chunk_keys");
+}
+
+int launch_chunk_len(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
+                     const int64_t *a_len, const int64_t *b_len, int64_t *len, hipStream_t s) {
+  if (nchunks == 0) return 0;
+  k_chunk_len<<<(unsigned)((nchunks + 255) / 256), 256, 0, s>>>(nchunks, nseg, cstart, sorted_chunk, a_len, b_len,
+                                                                 len);
+  return check_launch("chunk_len");
+}
+
+int launch_chunk_rows(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
+                      const int64_t *a_start, const int64_t *a_len, const int64_t *b_start,
+                      const int64_t *chunk_ptr, int32_t *order, hipStream_t s) {
+  if (nchunks == 0) return 0;
+  k_chunk_rows<<<(unsigned)((nchunks + 255) / 256), 256, 0, s>>>(nchunks, nseg, cstart, sorted_chunk, a_start,
+                                                                  a_len, b_start, chunk_ptr, order);
+  return check_launch("chunk_rows");
+}
+
+}  // namespace silu

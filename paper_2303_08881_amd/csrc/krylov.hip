@@ -1,0 +1,269 @@
+// krylov.hip -- CSR SpMV / residual and the vector kernels of the (flexible)
+// GMRES iterations of Section 4.1 and of the reduced-system solve of
+// Section 3.2 (eq. (18)-(19)).
+//
+// * SpMV and residual: one row per lane, entries summed in column order with
+//   fma (the sequential definition, so results are reproducible bit for bit).
+// * Reductions are deterministic: a fixed grid of RED_BLOCKS blocks writes
+//   one partial per block, and every consumer re-reduces the partials in the
+//   same fixed order, so all blocks agree on the value without atomics.
+// * Modified Gram-Schmidt runs as j+1 fused passes: pass i subtracts
+//   h_{i-1} v_{i-1} from w and forms the partial dot with v_i.
+// * The Hessenberg column update, Givens rotation and residual estimate run
+//   in one single-thread kernel; a device stop word lets the reduced-system
+//   GMRES run its fixed number of steps with no host synchronisation.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace silu {
+
+constexpr int RED_THREADS = 256;
+
+__global__ void k_spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x,
+                       double *y) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int64_t p = rp[i]; p < rp[i + 1]; p++) s = fma(v[p], x[ci[p]], s);
+  y[i] = s;
+}
+
+__global__ void k_residual(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
+                           const double *x, double *r) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = b[i];
+  for (int64_t p = rp[i]; p < rp[i + 1]; p++) s = fma(-v[p], x[ci[p]], s);
+  r[i] = s;
+}
+
+int launch_spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x, double *y,
+                hipStream_t s) {
+  if (n == 0) return 0;
+  k_spmv<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, v, n, x, y);
+  return check_launch("spmv");
+}
+
+int launch_residual(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
+                    const double *x, double *r, hipStream_t s) {
+  if (n == 0) return 0;
+  k_residual<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, v, n, b, x, r);
+  return check_launch("residual");
+}
+
+// ---- deterministic reductions -------------------------------------------
+__device__ double block_sum(double v) {
+  __shared__ double ws[RED_THREADS / WAVE];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  if (lane_id() == 0) ws[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < RED_THREADS / WAVE; w++) t += ws[w];
+  __syncthreads();
+  return t;  // valid in thread 0
+}
+
+// every caller gets the same value: lane l sums partials l, l+64, ... in
+// order, then a fixed butterfly
+__device__ double reduce_partials(const double *p) {
+  const int lane = lane_id();
+  double s = 0.0;
+  for (int k = lane; k < RED_BLOCKS; k += WAVE) s += p[k];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, WAVE);
+  return s;
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_dot_partial(const double *x, const double *y, int64_t n,
+                                                            double *partials) {
+  double s = 0.0;
+  const int64_t stride = (int64_t)RED_BLOCKS * RED_THREADS;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += stride) s = fma(x[i], y[i], s);
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+int launch_dot_partial(const double *x, const double *y, int64_t n, double *partials, hipStream_t s) {
+  k_dot_partial<<<RED_BLOCKS, RED_THREADS, 0, s>>>(x, y, n, partials);
+  return check_launch("dot_partial");
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_mgs_step(double *w, const double *v_prev, const double *pp,
+                                                         double *h_out, const double *v_next, int64_t n,
+                                                         double *pn) {
+  __shared__ double sh;
+  if (threadIdx.x < WAVE) {
+    double h = reduce_partials(pp);
+    if (threadIdx.x == 0) {
+      sh = h;
+      if (blockIdx.x == 0) *h_out = h;
+    }
+  }
+  __syncthreads();
+  const double h = sh;
+  double s = 0.0;
+  const int64_t stride = (int64_t)RED_BLOCKS * RED_THREADS;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += stride) {
+    const double wi = fma(-h, v_prev[i], w[i]);
+    w[i] = wi;
+    s = fma(wi, v_next ? v_next[i] : wi, s);
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) pn[blockIdx.x] = s;
+}
+
+int launch_mgs_step(double *w, const double *v_prev, const double *partials_prev, double *h_out,
+                    const double *v_next, int64_t n, double *partials_next, const int *stop, hipStream_t s) {
+  (void)stop;
+  k_mgs_step<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, v_prev, partials_prev, h_out, v_next, n, partials_next);
+  return check_launch("mgs_step");
+}
+
+__global__ void k_reduce_final(const double *partials, double *out, bool take_sqrt) {
+  double s = reduce_partials(partials);
+  if (threadIdx.x == 0) *out = take_sqrt ? sqrt(s) : s;
+}
+
+int launch_reduce_final(const double *partials, double *out, hipStream_t s) {
+  k_reduce_final<<<1, WAVE, 0, s>>>(partials, out, true);
+  return check_launch("reduce_final");
+}
+
+// y = x / (*den)  (skipped when *den == 0)
+__global__ void k_scale_div(const double *x, const double *den, double *y, int64_t n) {
+  const double d = *den;
+  if (d == 0.0) return;
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i] / d;
+}
+
+int launch_scale_copy(const double *x, const double *alpha_num, const double *alpha_den, double *y, int64_t n,
+                      const int *stop, hipStream_t s) {
+  (void)alpha_num;
+  (void)stop;
+  if (n == 0) return 0;
+  k_scale_div<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, alpha_den, y, n);
+  return check_launch("scale_div");
+}
+
+__global__ void k_vec_sum(double *y, const double *a, const double *b, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a[i] + b[i];
+}
+int launch_vec_sum(double *y, const double *a, const double *b, int64_t n, hipStream_t s) {
+  if (n == 0) return 0;
+  k_vec_sum<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(y, a, b, n);
+  return check_launch("vec_sum");
+}
+
+__global__ void k_copy(const double *x, double *y, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+int launch_copy(const double *x, double *y, int64_t n, hipStream_t s) {
+  if (n == 0) return 0;
+  k_copy<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, n);
+  return check_launch("copy");
+}
+
+__global__ void k_scatter(const double *x, const int32_t *map, int64_t n, double *z) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) z[map[i]] = x[i];
+}
+int launch_scatter(const double *x, const int32_t *map, int64_t n, double *z, hipStream_t s) {
+  if (n == 0) return 0;
+  k_scatter<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, map, n, z);
+  return check_launch("scatter");
+}
+
+// ---- Arnoldi bookkeeping (one thread) -------------------------------------
+// stop codes: 1 = exact breakdown (h_{j+1,j} = 0), 2 = estimate below tolerance,
+// 3 = non-finite value.
+__global__ void k_givens(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm,
+                         int *stop, int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol) {
+  const double hn2 = reduce_partials(pnorm);
+  if (threadIdx.x != 0) return;
+  if (*stop) return;
+  const double hn = sqrt(hn2);
+  *hn_out = hn;
+  double *col = H + (int64_t)ldh * j;
+  col[j + 1] = hn;
+  for (int i = 0; i < j; i++) {
+    const double a = col[i], b = col[i + 1];
+    col[i] = fma(cs[i], a, sn[i] * b);
+    col[i + 1] = fma(-sn[i], a, cs[i] * b);
+  }
+  const double a = col[j], b = col[j + 1];
+  const double r = sqrt(fma(a, a, b * b));
+  cs[j] = a / r;
+  sn[j] = b / r;
+  col[j] = r;
+  col[j + 1] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  *nsteps = j + 1;
+  const double e = fabs(g[j + 1]);
+  *est = e;
+  if (!isfinite(hn) || !isfinite(e))
+    *stop = 3;
+  else if (hn == 0.0)
+    *stop = 1;
+  else if (e <= rtol * (*tol_ref))
+    *stop = 2;
+}
+
+int launch_givens(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm, int *stop,
+                  int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol, hipStream_t s) {
+  k_givens<<<1, WAVE, 0, s>>>(H, ldh, cs, sn, g, j, pnorm, stop, nsteps, est, hn_out, tol_ref, rtol);
+  return check_launch("givens");
+}
+
+// R c = g by back substitution (sizes from *nsteps)
+__global__ void k_backsolve(const double *H, int ldh, const double *g, const int *nsteps, double *c) {
+  if (threadIdx.x != 0) return;
+  const int m = *nsteps;
+  for (int i = m - 1; i >= 0; i--) {
+    double s = g[i];
+    for (int l = i + 1; l < m; l++) s = fma(-H[i + (int64_t)ldh * l], c[l], s);
+    c[i] = s / H[i + (int64_t)ldh * i];
+  }
+}
+
+int launch_backsolve(const double *H, int ldh, const double *g, const int *nsteps, double *c, hipStream_t s) {
+  k_backsolve<<<1, WAVE, 0, s>>>(H, ldh, g, nsteps, c);
+  return check_launch("backsolve");
+}
+
+// y (+)= sum_i c_i V_i, i < *nsteps, accumulated in i order per element
+__global__ void k_combine(double *y, const double *V, int64_t ldv, const double *c, const int *nsteps, int64_t n,
+                          bool accumulate) {
+  int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= n) return;
+  const int m = *nsteps;
+  double s = accumulate ? y[l] : 0.0;
+  for (int i = 0; i < m; i++) s = fma(c[i], V[(int64_t)i * ldv + l], s);
+  y[l] = s;
+}
+
+int launch_combine(double *y, const double *V, int64_t ldv, const double *c, const int *nsteps, int64_t n,
+                   bool accumulate, hipStream_t s) {
+  if (n == 0) return 0;
+  k_combine<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(y, V, ldv, c, nsteps, n, accumulate);
+  return check_launch("combine");
+}
+
+// g[0] = beta; stop = (beta == 0); nsteps = 0
+__global__ void k_init_krylov(double *g, const double *beta, int *stop, int *nsteps) {
+  if (threadIdx.x != 0) return;
+  const double b = *beta;
+  g[0] = b;
+  *nsteps = 0;
+  *stop = (b == 0.0) ? 1 : (!isfinite(b) ? 3 : 0);
+}
+
+int launch_init_krylov(double *g, const double *beta, int *stop, int *nsteps, hipStream_t s) {
+  k_init_krylov<<<1, WAVE, 0, s>>>(g, beta, stop, nsteps);
+  return check_launch("init_krylov");
+}
+
+}  // namespace silu

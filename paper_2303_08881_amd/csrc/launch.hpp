@@ -1,0 +1,155 @@
+// launch.hpp -- host-side launchers of the gfx950 kernels (internal interface
+// between the kernel translation units and the runtime in capi.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace silu {
+
+int check_launch(const char *what);  // records a HIP launch error, returns ILU_ERR_HIP or 0
+
+// ---- prims.hip ----
+// out[0..n] = exclusive scan of in[0..n-1], out[n] = total (out may not alias in)
+int scan_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp, size_t tmp_bytes, hipStream_t s);
+size_t scan_tmp_bytes(int64_t n);
+// stable LSD radix sort of (key, val) by key (keys < 2^key_bits); results in key_out/val_out
+int radix_sort(const uint32_t *key_in, const int32_t *val_in, uint32_t *key_out, int32_t *val_out, int64_t n,
+               int key_bits, void *tmp, size_t tmp_bytes, hipStream_t s);
+size_t radix_tmp_bytes(int64_t n);
+int histogram_keys(const uint32_t *key, int64_t n, int64_t nbins, int64_t *counts, hipStream_t s);
+int fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+int fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
+int fill_f64(double *p, double v, int64_t n, hipStream_t s);
+int iota_i32(int32_t *p, int64_t n, hipStream_t s);
+int max_i32(const int32_t *p, int64_t n, int32_t *d_out, hipStream_t s);
+
+// ---- setup.hip ----
+int launch_validate(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nnz, const int32_t *part, int32_t nparts,
+                    void *status, hipStream_t s);
+int launch_classify(const int64_t *rp, const int32_t *ci, int64_t n, const int32_t *part, uint8_t *iface,
+                    hipStream_t s);
+int launch_perm_keys(int64_t n, const int32_t *part, int32_t nparts, const uint8_t *iface, uint32_t *key,
+                     int32_t *val, hipStream_t s);
+int launch_inverse_perm(int64_t n, const int32_t *perm, int32_t *iperm, hipStream_t s);
+int launch_extract_counts(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nB, const int32_t *part,
+                          const int32_t *perm, int64_t *cnt_intra, int64_t *cnt_cross, hipStream_t s);
+int launch_extract_fill(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, int64_t nB,
+                        const int32_t *part, const int32_t *perm, const int32_t *iperm, const int64_t *rp_intra,
+                        int32_t *ci_intra, double *v_intra, const int64_t *rp_cross, int32_t *ci_cross,
+                        double *v_cross, hipStream_t s);
+
+// ---- factor.hip ----
+struct FactLaunch {
+  const int64_t *rp;
+  const int32_t *ci;
+  const double *v;
+  int64_t n, nfull;
+  int32_t method;
+  double droptol;
+  int32_t lfil;
+  int32_t pivot_mode;
+  double pivot_tol;
+  int64_t nchunks;
+  const int64_t *chunk_ptr;
+  const int32_t *order;
+  unsigned int *ticket;
+  const int64_t *Lrp;
+  int32_t *Lc;
+  double *Lv;
+  int32_t *Llen;
+  const int64_t *Urp;
+  int32_t *Uc;
+  double *Uv;
+  int32_t *Ulen;
+  const int64_t *Rrp;
+  int32_t *Rc;
+  double *Rv;
+  int32_t *Rlen;
+  double *D;
+  int *done;
+  int epoch;
+  void *status;
+  int64_t max_waves;
+};
+int launch_fact_caps(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nfull, int32_t method, int32_t lfil,
+                     int64_t *Lcap, int64_t *Ucap, int64_t *Rcap, hipStream_t s);
+int launch_factor_rows(const FactLaunch &f, hipStream_t s);
+int launch_compact_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len, const int32_t *sc,
+                        const double *sv, const int64_t *out_rp, int32_t *oc, double *ov, int64_t col_lo,
+                        int64_t col_hi, int64_t shift, hipStream_t s);
+int launch_count_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len, const int32_t *sc, int64_t col_lo,
+                      int64_t col_hi, int64_t *cnt, hipStream_t s);
+int launch_chunk_counts(int32_t nseg, const int64_t *a_start, const int64_t *a_len, const int64_t *b_start,
+                        const int64_t *b_len, int64_t *nchunks_seg, hipStream_t s);
+int launch_chunk_keys(int64_t nchunks, int32_t nseg, const int64_t *cstart, uint32_t *key, int32_t *val,
+                      hipStream_t s);
+int launch_chunk_len(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
+                     const int64_t *a_len, const int64_t *b_len, int64_t *len, hipStream_t s);
+int launch_chunk_rows(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
+                      const int64_t *a_start, const int64_t *a_len, const int64_t *b_start,
+                      const int64_t *chunk_ptr, int32_t *order, hipStream_t s);
+
+// ---- levels.hip ----
+// level of each row of a triangular CSR: lower -> dependencies are columns in
+// [lo, r); upper -> (r, hi).  Sync-free, natural order, bounded waits.
+int launch_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool lower, int64_t lo, int64_t hi,
+                  int32_t *level, int *done, int epoch, unsigned int *ticket, void *status, int64_t max_waves,
+                  hipStream_t s);
+// chunk table of a level-ordered row list: level_ptr[nlev+1] -> chunks of <= 64 rows
+int launch_level_chunk_counts(const int64_t *level_ptr, int64_t nlev, int64_t *cnt, hipStream_t s);
+int launch_level_chunks(const int64_t *level_ptr, int64_t nlev, const int64_t *chunk_base, int32_t *chunk_start,
+                        int32_t *chunk_level, hipStream_t s);
+int launch_levels_to_keys(const int32_t *level, int64_t n, uint32_t *key, int32_t *val, hipStream_t s);
+
+// ---- trsv.hip ----
+struct TrsvLaunch {
+  int64_t nrows;           // rows in this solve
+  const int32_t *rows;     // level-ordered row ids (nrows)
+  const int32_t *chunk_start;  // [nchunks+1]
+  const int32_t *chunk_level;  // [nchunks]
+  int64_t nchunks;
+  const int64_t *level_ptr;  // [nlev+1]
+  unsigned long long *level_done;  // [nlev] cumulative counters
+  unsigned long long epoch;
+  unsigned long long *ticket;
+  unsigned long long ticket_base;
+  const int64_t *rp;
+  const int32_t *ci;
+  const double *v;
+  const double *diag;      // NULL -> unit diagonal
+  int64_t split_col;       // upper solves: columns >= split_col are processed first (Z part)
+  const double *b;         // right-hand side base
+  const int32_t *b_map;    // rhs index = b_map ? b_map[row] : row
+  double *x;               // solution, indexed by row; columns index x too
+  double *scatter_out;     // optional: scatter_out[scatter_map[row]] = x
+  const int32_t *scatter_map;
+  void *status;
+  int64_t max_waves;
+};
+int launch_trsv(const TrsvLaunch &t, hipStream_t s);
+
+// ---- krylov.hip ----
+int launch_spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x, double *y,
+                hipStream_t s);
+int launch_residual(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
+                    const double *x, double *r, hipStream_t s);
+constexpr int RED_BLOCKS = 512;  // fixed grid of the deterministic reductions
+int launch_dot_partial(const double *x, const double *y, int64_t n, double *partials, hipStream_t s);
+// w -= h v_prev with h = sum(partials_prev) (also stored to *h_out), then the
+// partial dot of the new w with v_next (with w itself when v_next is NULL)
+int launch_mgs_step(double *w, const double *v_prev, const double *partials_prev, double *h_out,
+                    const double *v_next, int64_t n, double *partials_next, const int *stop, hipStream_t s);
+int launch_reduce_final(const double *partials, double *out, hipStream_t s);  // *out = sqrt(sum)
+int launch_scale_copy(const double *x, const double *alpha_num, const double *alpha_den, double *y, int64_t n,
+                      const int *stop, hipStream_t s);  // y = x / (*den), skipped if *den == 0
+int launch_vec_sum(double *y, const double *a, const double *b, int64_t n, hipStream_t s);  // y = a + b
+int launch_copy(const double *x, double *y, int64_t n, hipStream_t s);
+int launch_scatter(const double *x, const int32_t *map, int64_t n, double *z, hipStream_t s);
+int launch_givens(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm, int *stop,
+                  int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol, hipStream_t s);
+int launch_backsolve(const double *H, int ldh, const double *g, const int *nsteps, double *c, hipStream_t s);
+int launch_combine(double *y, const double *V, int64_t ldv, const double *c, const int *nsteps, int64_t n,
+                   bool accumulate, hipStream_t s);
+int launch_init_krylov(double *g, const double *beta, int *stop, int *nsteps, hipStream_t s);
+
+}  // namespace silu

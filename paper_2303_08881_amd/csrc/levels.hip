@@ -1,0 +1,154 @@
+// levels.hip -- level sets of sparse triangular factors (Section 3.1: the
+// analysis phase that lets the rows of one level be processed together).
+//
+// level(r) = 0 when row r has no dependency, else 1 + max level(dependency);
+// for a lower factor the dependencies of r are its columns in [lo, r), for an
+// upper factor its columns in (r, hi).
+//
+// Sync-free evaluation: a wave takes 64 consecutive rows (in dependency
+// order: ascending for lower, descending for upper) by atomic ticket.  A row
+// first waits, with bounded polls, for the completion flags of dependencies
+// outside its chunk, then the chunk resolves its internal chain in rounds
+// (each round finishes every row whose in-chunk dependencies are done).
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace silu {
+
+__global__ void __launch_bounds__(WAVE) k_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool lower,
+                                                  int64_t lo, int64_t hi, int32_t *level, int *done, int epoch,
+                                                  unsigned int *ticket, Status *st) {
+  __shared__ int32_t lev_s[WAVE];
+  __shared__ int32_t ok_s[WAVE];
+  const int lane = lane_id();
+  const int64_t nchunks = (n + WAVE - 1) / WAVE;
+  for (;;) {
+    const int64_t t = wave_ticket(ticket);
+    if (t >= nchunks) return;
+    const int64_t q = t * WAVE + lane;  // position in dependency order
+    const bool valid = q < n;
+    const int64_t r = lower ? q : n - 1 - q;
+    const int64_t cb = t * WAVE;        // chunk covers positions [cb, cb+64)
+    int32_t m = 0;                       // max over resolved dependencies of level+1
+    bool ok = true;
+    if (valid) {
+      for (int64_t p = rp[r]; p < rp[r + 1]; p++) {
+        const int64_t c = ci[p];
+        const bool dep = lower ? (c >= lo && c < r) : (c > r && c < hi);
+        if (!dep) continue;
+        const int64_t qc = lower ? c : n - 1 - c;
+        if (qc >= cb) continue;  // inside this chunk: resolved below
+        if (!wait_flag_eq(&done[c], epoch, st, r)) {
+          ok = false;
+          break;
+        }
+      }
+    }
+    if (ballot(!ok)) return;
+    fence_acquire();
+    if (valid) {
+      for (int64_t p = rp[r]; p < rp[r + 1]; p++) {
+        const int64_t c = ci[p];
+        const bool dep = lower ? (c >= lo && c < r) : (c > r && c < hi);
+        if (!dep) continue;
+        const int64_t qc = lower ? c : n - 1 - c;
+        if (qc >= cb) continue;
+        m = max(m, level[c] + 1);
+      }
+    }
+    ok_s[lane] = valid ? 0 : 1;
+    lev_s[lane] = m;
+    __syncthreads();
+    // in-chunk chain: dependencies sit at smaller positions, i.e. lower lanes
+    for (int round = 0; round < WAVE; round++) {
+      bool ready = true;
+      int32_t mm = m;
+      if (valid && !ok_s[lane]) {
+        for (int64_t p = rp[r]; p < rp[r + 1]; p++) {
+          const int64_t c = ci[p];
+          const bool dep = lower ? (c >= lo && c < r) : (c > r && c < hi);
+          if (!dep) continue;
+          const int64_t qc = lower ? c : n - 1 - c;
+          if (qc < cb) continue;
+          const int l2 = (int)(qc - cb);
+          if (!ok_s[l2]) {
+            ready = false;
+            break;
+          }
+          mm = max(mm, lev_s[l2] + 1);
+        }
+      }
+      __syncthreads();
+      if (valid && !ok_s[lane] && ready) {
+        lev_s[lane] = mm;
+        ok_s[lane] = 1;
+      }
+      __syncthreads();
+      if (!ballot(ok_s[lane] == 0)) break;
+    }
+    if (valid) {
+      level[r] = lev_s[lane];
+      st_release(&done[r], epoch);
+    }
+    __syncthreads();
+  }
+}
+
+int launch_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool lower, int64_t lo, int64_t hi,
+                  int32_t *level, int *done, int epoch, unsigned int *ticket, void *status, int64_t max_waves,
+                  hipStream_t s) {
+  if (n == 0) return 0;
+  const int64_t nchunks = (n + WAVE - 1) / WAVE;
+  const int64_t grid = nchunks < max_waves ? nchunks : max_waves;
+  k_levels<<<(unsigned)grid, WAVE, 0, s>>>(rp, ci, n, lower, lo, hi, level, done, epoch, ticket, (Status *)status);
+  return check_launch("levels");
+}
+
+__global__ void k_levels_to_keys(const int32_t *level, int64_t n, uint32_t *key, int32_t *val) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = (uint32_t)level[i];
+  val[i] = (int32_t)i;
+}
+
+int launch_levels_to_keys(const int32_t *level, int64_t n, uint32_t *key, int32_t *val, hipStream_t s) {
+  if (n == 0) return 0;
+  k_levels_to_keys<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(level, n, key, val);
+  return check_launch("levels_to_keys");
+}
+
+// number of <=64-row chunks in each level
+__global__ void k_level_chunk_counts(const int64_t *level_ptr, int64_t nlev, int64_t *cnt) {
+  int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= nlev) return;
+  cnt[l] = (level_ptr[l + 1] - level_ptr[l] + WAVE - 1) / WAVE;
+}
+
+int launch_level_chunk_counts(const int64_t *level_ptr, int64_t nlev, int64_t *cnt, hipStream_t s) {
+  if (nlev == 0) return 0;
+  k_level_chunk_counts<<<(unsigned)((nlev + 255) / 256), 256, 0, s>>>(level_ptr, nlev, cnt);
+  return check_launch("level_chunk_counts");
+}
+
+__global__ void k_level_chunks(const int64_t *level_ptr, int64_t nlev, const int64_t *chunk_base,
+                               int32_t *chunk_start, int32_t *chunk_level) {
+  int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (l >= nlev) return;
+  const int64_t b = level_ptr[l], e = level_ptr[l + 1];
+  int64_t c = chunk_base[l];
+  for (int64_t x = b; x < e; x += WAVE, c++) {
+    chunk_start[c] = (int32_t)x;
+    chunk_level[c] = (int32_t)l;
+  }
+  if (l == nlev - 1) chunk_start[chunk_base[nlev]] = (int32_t)e;
+}
+
+int launch_level_chunks(const int64_t *level_ptr, int64_t nlev, const int64_t *chunk_base, int32_t *chunk_start,
+                        int32_t *chunk_level, hipStream_t s) {
+  if (nlev == 0) return 0;
+  k_level_chunks<<<(unsigned)((nlev + 255) / 256), 256, 0, s>>>(level_ptr, nlev, chunk_base, chunk_start,
+                                                                 chunk_level);
+  return check_launch("level_chunks");
+}
+
+}  // namespace silu
