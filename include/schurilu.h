@@ -48,6 +48,9 @@ extern "C" {
 #define ILU_FACT_ILUT 2    /* threshold ILU with a per-part fill limit              */
 #define ILU_PIVOT_ERROR 0
 #define ILU_PIVOT_PERTURB 1
+#define ILU_TRSV_AUTO 0    /* pick per triangular factor (see trsv_mode)       */
+#define ILU_TRSV_LEVELS 1  /* level-scheduled across workgroups, sync-free     */
+#define ILU_TRSV_BLOCK 2   /* one workgroup per subdomain, barrier per level   */
 
 typedef struct {
   int64_t n;               /* rows = columns */
@@ -80,6 +83,11 @@ typedef struct {
  *                 ILU_ERR_ZERO_PIVOT.  ILU_PIVOT_PERTURB: a pivot with
  *                 |u_ii| < pivot_tol * max_j |a_ij| is replaced by
  *                 +-pivot_tol * max_j |a_ij| (sign of u_ii, + for 0).
+ *  trsv_mode      execution of the triangular solves (results are identical
+ *                 bit for bit): ILU_TRSV_BLOCK solves each subdomain in one
+ *                 workgroup (chosen by AUTO when a subdomain has at most 2^20
+ *                 rows and at most 16384 levels); ILU_TRSV_LEVELS spreads every
+ *                 level over the whole GPU with sync-free level counters.
  */
 typedef struct {
   int32_t method;
@@ -91,6 +99,7 @@ typedef struct {
   double inner_rtol;
   int32_t pivot_mode;
   double pivot_tol;
+  int32_t trsv_mode;
 } ilu_options_t;
 
 typedef struct {
@@ -167,6 +176,26 @@ const char *ilu_last_error(void);
  *   40..43 level of each row of L_B, U_B, L_S, U_S [int32].
  */
 int ilu_export(ilu_precond_t *P, int32_t what, void *h_buf, int64_t *len);
+
+/*
+ * Kernel timing (a profiling aid for benchmarks; process-global, not
+ * thread-safe).  While on, each launch of the solve-phase kernels below is
+ * bracketed by HIP events on the stream it is launched on; durations are
+ * resolved at the next host synchronisation.  ilu_kernel_stats returns, for
+ * one kernel class, the summed duration, the number of launches and the
+ * summed algorithmic bytes (each stored entry, row pointer, right-hand side
+ * and solution element counted once per launch).  reset != 0 clears it.
+ */
+#define ILU_K_TRSV_LB 0  /* forward solve with L_B, rows of W included (one extra level) */
+#define ILU_K_TRSV_UB 1  /* backward solve with U_B, Z columns included           */
+#define ILU_K_TRSV_LS 2  /* forward solve with the local Schur factors L_S        */
+#define ILU_K_TRSV_US 3  /* backward solve with U_S                               */
+#define ILU_K_SPMV 4     /* y = A x in the outer Krylov loop                      */
+#define ILU_K_SPMV_COFF 5 /* C_off y in the reduced-system operator              */
+#define ILU_K_MGS 6      /* one fused modified Gram-Schmidt pass                  */
+#define ILU_K_COUNT 7
+void ilu_kernel_timing(int32_t on);
+int ilu_kernel_stats(int32_t kind, double *total_ms, int64_t *launches, double *bytes, int32_t reset);
 
 /* Sizes: n, n_B (interior rows), n_S (interface rows), nparts. */
 int ilu_info(ilu_precond_t *P, int64_t *n, int64_t *nB, int64_t *nS, int32_t *nparts);

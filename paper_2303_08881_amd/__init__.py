@@ -15,6 +15,9 @@ from .binding import (  # noqa: F401
     ILUT,
     PIVOT_ERROR,
     PIVOT_PERTURB,
+    TRSV_AUTO,
+    TRSV_LEVELS,
+    TRSV_BLOCK,
     SchurILUError,
     DeviceCSR,
     Precond,

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libschurilu.so")
 BJ, SCHUR = 0, 1
 ILU0, MILU0, ILUT = 0, 1, 2
 PIVOT_ERROR, PIVOT_PERTURB = 0, 1
+TRSV_AUTO, TRSV_LEVELS, TRSV_BLOCK = 0, 1, 2
 OK, NOT_CONVERGED = 0, 1
 
 EXPORT = dict(perm=(0, np.int32), iperm=(1, np.int32), iface=(2, np.uint8), offsets=(3, np.int64),
@@ -41,7 +42,8 @@ class _CSR(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("interior_fact", C.c_int32), ("interface_fact", C.c_int32),
                 ("droptol", C.c_double), ("lfil", C.c_int32), ("inner_iters", C.c_int32),
-                ("inner_rtol", C.c_double), ("pivot_mode", C.c_int32), ("pivot_tol", C.c_double)]
+                ("inner_rtol", C.c_double), ("pivot_mode", C.c_int32), ("pivot_tol", C.c_double),
+                ("trsv_mode", C.c_int32)]
 
 
 class _Res(C.Structure):
@@ -72,6 +74,9 @@ def lib():
         L.ilu_last_error.restype = C.c_char_p
         L.ilu_export.argtypes = [vp, i32, vp, C.POINTER(i64)]
         L.ilu_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]
+        L.ilu_kernel_timing.argtypes = [i32]
+        L.ilu_kernel_timing.restype = None
+        L.ilu_kernel_stats.argtypes = [i32, C.POINTER(d), C.POINTER(i64), C.POINTER(d), i32]
         _lib = L
     return _lib
 
@@ -120,9 +125,9 @@ class DeviceCSR:
 
 
 def _options(method=BJ, interior_fact=ILU0, interface_fact=ILU0, droptol=0.0, lfil=-1, inner_iters=3,
-             inner_rtol=0.0, pivot_mode=PIVOT_ERROR, pivot_tol=0.0):
+             inner_rtol=0.0, pivot_mode=PIVOT_ERROR, pivot_tol=0.0, trsv_mode=TRSV_AUTO):
     return _Opts(method, interior_fact, interface_fact, droptol, lfil, inner_iters, inner_rtol, pivot_mode,
-                 pivot_tol)
+                 pivot_tol, trsv_mode)
 
 
 class Precond:

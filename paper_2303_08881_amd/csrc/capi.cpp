@@ -84,6 +84,62 @@ struct Mem {
   }
 };
 
+// ---------------------------------------------------------------------------
+// kernel timing: HIP events around each launch of the solve-phase kernels,
+// resolved at host synchronisation points (profiling aid; process-global)
+// ---------------------------------------------------------------------------
+struct KStat {
+  double ms = 0.0, bytes = 0.0;
+  int64_t launches = 0;
+};
+struct PendingTiming {
+  hipEvent_t a, b;
+  int kind;
+  double bytes;
+};
+static bool g_timing = false;
+static KStat g_kstat[ILU_K_COUNT];
+static std::vector<PendingTiming> g_pending;
+static std::vector<hipEvent_t> g_event_pool;
+
+static hipEvent_t pool_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+static void timing_collect() {
+  for (auto &p : g_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      g_kstat[p.kind].ms += ms;
+      g_kstat[p.kind].bytes += p.bytes;
+      g_kstat[p.kind].launches++;
+    }
+    g_event_pool.push_back(p.a);
+    g_event_pool.push_back(p.b);
+  }
+  g_pending.clear();
+}
+
+template <typename F>
+static int timed(int kind, double bytes, hipStream_t s, F &&launch) {
+  if (!g_timing) return launch();
+  hipEvent_t a = pool_event(), b = pool_event();
+  if (!a || !b) return launch();
+  (void)hipEventRecord(a, s);
+  int rc = launch();
+  (void)hipEventRecord(b, s);
+  g_pending.push_back({a, b, kind, bytes});
+  if (g_pending.size() > 4096) timing_collect();
+  return rc;
+}
+
 struct Csr {
   int64_t n = 0, nnz = 0;
   int64_t *rp = nullptr;
@@ -98,6 +154,16 @@ struct Schedule {
   unsigned long long *level_done = nullptr, *ticket = nullptr;
   unsigned long long epoch = 0, ticket_base = 0;
   int64_t grid = 0;
+  // block-local variant: one workgroup per subdomain
+  bool use_block = false;
+  int64_t nblk = 0;
+  int32_t *blk_rows = nullptr, *blk_lev_ptr = nullptr;
+  // level-ordered copy of the factor for the block-local solve
+  int32_t *lo_meta = nullptr, *lo_nent = nullptr, *lo_ci = nullptr;
+  double *lo_v = nullptr, *lo_diag = nullptr, *lo_x = nullptr;
+  int32_t lo_maxent = 0;
+  const int32_t *rhs_map = nullptr;  // gather map baked into lo_meta
+  const int32_t *sct_map = nullptr;  // scatter map baked into lo_meta
 };
 
 struct GmresWork {
@@ -119,7 +185,7 @@ struct ilu_precond {
   int32_t *perm = nullptr, *iperm = nullptr;
   uint8_t *iface = nullptr;
   std::vector<int64_t> offsets;  // 2*nparts+2
-  Csr L1, U1, LS, US, Coff;
+  Csr L1, U1, LS, US, Coff, Zb;
   double *DB = nullptr, *DS = nullptr;
   Schedule sL1, sU1, sLS, sUS;
   double *xp = nullptr;
@@ -129,6 +195,7 @@ struct ilu_precond {
   int *iflags = nullptr;
   Status *status = nullptr;
   double *host_pinned = nullptr;  // 8 doubles for read-backs
+  int64_t *blk_starts = nullptr;  // device: interior starts, interface starts, interface starts (local)
   double setup_ms = 0.0;
   GmresWork *gw = nullptr;
 };
@@ -311,7 +378,9 @@ static int run_factor(ilu_precond *P, Mem &tmp, const Csr &M, int64_t nfull, int
 
 // level schedule of a triangular factor
 static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, int64_t lo, int64_t hi, Schedule &S,
-                          void *stmp, size_t stmpb, hipStream_t s, const char *phase) {
+                          const int64_t *bs1, const int64_t *bs2, int64_t split, const double *diag, int64_t ext_col,
+                          const int32_t *rhs_map, const int32_t *sct_map, void *stmp, size_t stmpb, hipStream_t s,
+                          const char *phase) {
   const int64_t n = T.n;
   S.nrows = n;
   if (n == 0) return 0;
@@ -362,14 +431,78 @@ static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, in
   S.epoch = 0;
   S.ticket_base = 0;
   S.grid = std::min<int64_t>(S.nchunks, (int64_t)P->num_cu * 16);
+
+  // block-local schedule: rows sorted by (subdomain, level)
+  S.nblk = P->nparts;
+  const uint64_t nkeys = (uint64_t)S.nblk * (uint64_t)S.nlev;
+  const int mode = P->opt.trsv_mode;
+  const bool feasible = S.nlev <= 16384 && nkeys < (1ull << 31);
+  const bool want = mode == ILU_TRSV_BLOCK || (mode == ILU_TRSV_AUTO && n / S.nblk <= (int64_t)1 << 20);
+  if (mode == ILU_TRSV_BLOCK && !feasible)
+    return fail(ILU_ERR_INVALID_ARG, "%s: block-local solve needs <= 16384 levels (has %lld)", phase,
+                (long long)S.nlev);
+  if (feasible && want) {
+    int32_t *blk;
+    RC(tmp.alloc(&blk, n));
+    RC(launch_row_blocks(n, (int32_t)S.nblk, bs1, bs2, split, blk, s));
+    RC(launch_block_level_keys(S.level_of, blk, n, S.nlev, key, val, s));
+    RC(mem.alloc(&S.blk_rows, n));
+    RC(radix_sort(key, val, key2, S.blk_rows, n, bits_for(nkeys - 1), rtmp, rtb, s));
+    int64_t *bcnt, *bptr, btot;
+    RC(tmp.alloc(&bcnt, (int64_t)nkeys));
+    RC(histogram_keys(key2, n, (int64_t)nkeys, bcnt, s));
+    const size_t stb2 = scan_tmp_bytes((int64_t)nkeys) + 64;
+    void *stmp2;
+    RC(tmp.alloc((char **)&stmp2, (int64_t)stb2));
+    RC(make_rp(tmp, bcnt, (int64_t)nkeys, &bptr, &btot, stmp2, stb2, s));
+    RC(mem.alloc(&S.blk_lev_ptr, (int64_t)nkeys + 1));
+    RC(launch_i64_to_i32(bptr, S.blk_lev_ptr, (int64_t)nkeys + 1, s));
+    // level-ordered copy of the factor
+    int32_t *pos, *dmax;
+    int64_t *lcnt, *lrp, lnnz;
+    RC(tmp.alloc(&pos, n));
+    RC(tmp.alloc(&lcnt, n));
+    RC(tmp.alloc(&dmax, 1));
+    RC(fill_i32(dmax, 0, 1, s));
+    RC(mem.alloc(&S.lo_nent, n));
+    RC(launch_level_order_copy(S.blk_rows, T.rp, T.ci, T.v, diag, n, ext_col, pos, lcnt, S.lo_nent, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, nullptr, nullptr, dmax, 0, s));
+    RC(make_rp(tmp, lcnt, n, &lrp, &lnnz, stmp, stmpb, s));
+    if (lnnz >= ((int64_t)1 << 31)) return fail(ILU_ERR_INVALID_ARG, "%s: factor too large for the block solve", phase);
+    RC(mem.alloc(&S.lo_ci, lnnz + 32));  // vector loads of a short last row read past its end
+    RC(mem.alloc(&S.lo_v, lnnz + 32));
+    RC(mem.alloc(&S.lo_meta, 4 * n));
+    RC(mem.alloc(&S.lo_x, n + 256));
+    if (diag) RC(mem.alloc(&S.lo_diag, n));
+    S.rhs_map = rhs_map;
+    S.sct_map = sct_map;
+    RC(launch_level_order_copy(S.blk_rows, T.rp, T.ci, T.v, diag, n, ext_col, pos, lcnt, S.lo_nent, lrp, S.lo_ci,
+                               S.lo_v, S.lo_diag, rhs_map, sct_map, S.lo_meta, dmax, 1, s));
+    HIPCK(hipMemcpyAsync(&S.lo_maxent, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    S.use_block = true;
+  }
   return 0;
 }
 
+// Algorithmic bytes of one triangular solve: every stored entry (column and
+// value), the row pointers and the level-ordered row list once, the right-hand
+// side read and the solution written once (plus the gather map, the diagonal
+// and the scatter when present).
+static double trsv_bytes(const Schedule &S, const Csr &T, bool diag, bool bmap, bool scat) {
+  const double n = (double)S.nrows;
+  double b = 12.0 * (double)T.nnz + 8.0 * (n + 1) + 4.0 * n + 8.0 * n + 8.0 * n;
+  if (diag) b += 8.0 * n;
+  if (bmap) b += 4.0 * n;
+  if (scat) b += 12.0 * n;
+  return b;
+}
+
 static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, int64_t split, const double *b,
-                const int32_t *bmap, double *x, double *scat, const int32_t *smap, hipStream_t s) {
+                const int32_t *bmap, double *x, double *scat, const int32_t *smap, hipStream_t s, int role) {
   if (S.nrows == 0) return 0;
-  S.epoch++;
   TrsvLaunch t;
+  if (!S.use_block) S.epoch++;
   t.nrows = S.nrows;
   t.rows = S.rows;
   t.chunk_start = S.chunk_start;
@@ -392,8 +525,31 @@ static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, i
   t.scatter_map = smap;
   t.status = P->status;
   t.max_waves = S.grid;
-  S.ticket_base += (unsigned long long)(S.nchunks + S.grid);
-  return launch_trsv(t, s);
+  t.role = role;
+  if (!S.use_block) S.ticket_base += (unsigned long long)(S.nchunks + S.grid);
+  const double bytes = trsv_bytes(S, T, diag != nullptr, bmap != nullptr, scat != nullptr);
+  if (S.use_block) {
+    if (bmap != S.rhs_map || (scat && smap != S.sct_map))
+      return fail(ILU_ERR_INVALID_ARG, "internal: gather/scatter map differs from the schedule's");
+
+    t.nblk = S.nblk;
+    t.nlev_blk = S.nlev;
+    t.blk_rows = S.blk_rows;
+    t.blk_lev_ptr = S.blk_lev_ptr;
+    t.lo_meta = S.lo_meta;
+    t.lo_nent = S.lo_nent;
+    t.lo_ci = S.lo_ci;
+    t.lo_v = S.lo_v;
+    t.lo_diag = S.lo_diag;
+    t.lo_x = S.lo_x;
+    t.lo_maxent = S.lo_maxent;
+    return timed(ILU_K_TRSV_LB + role, bytes, s, [&] { return launch_trsv_lds(t, s); });
+  }
+  return timed(ILU_K_TRSV_LB + role, bytes, s, [&] { return launch_trsv(t, s); });
+}
+
+static double spmv_bytes(int64_t n, int64_t nnz, bool resid) {
+  return 12.0 * (double)nnz + 8.0 * (double)(n + 1) + 16.0 * (double)n + (resid ? 8.0 * (double)n : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -412,6 +568,7 @@ void ilu_default_options(ilu_options_t *o) {
   o->inner_rtol = 0.0;
   o->pivot_mode = ILU_PIVOT_ERROR;
   o->pivot_tol = 0.0;
+  o->trsv_mode = ILU_TRSV_AUTO;
 }
 
 const char *ilu_last_error(void) { return g_err.c_str(); }
@@ -516,8 +673,9 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
   RC(tmp.alloc(&cnt_tmp, n + 1));
   // L1 = [L_B; W]: all rows, interior columns
   RC(slots_to_csr(mem, n, F.Lrp, F.Llen, F.Lc, F.Lv, 0, nB, 0, &P->L1, cnt_tmp, stmp, stmpb, s));
-  // U1 = [U_B | Z]: interior rows, every column
+  // U1 = [U_B | Z]: interior rows, every column; Zb = the Z block alone
   RC(slots_to_csr(mem, nB, F.Urp, F.Ulen, F.Uc, F.Uv, 0, n, 0, &P->U1, cnt_tmp, stmp, stmpb, s));
+  RC(slots_to_csr(mem, nB, F.Urp, F.Ulen, F.Uc, F.Uv, nB, n, 0, &P->Zb, cnt_tmp, stmp, stmpb, s));
   RC(mem.alloc(&P->DB, nB));
   if (nB) HIPCK(hipMemcpyAsync(P->DB, F.D, sizeof(double) * nB, hipMemcpyDeviceToDevice, s));
   RC(mem.alloc(&P->DS, nS));
@@ -544,10 +702,26 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
   }
 
   // 6. level schedules of the four triangular solves
-  RC(build_schedule(P, tmp, P->L1, true, 0, n, P->sL1, stmp, stmpb, s, "levels L"));
-  RC(build_schedule(P, tmp, P->U1, false, 0, nB, P->sU1, stmp, stmpb, s, "levels U"));
-  RC(build_schedule(P, tmp, P->LS, true, 0, nS, P->sLS, stmp, stmpb, s, "levels L_S"));
-  RC(build_schedule(P, tmp, P->US, false, 0, nS, P->sUS, stmp, stmpb, s, "levels U_S"));
+  {
+    std::vector<int64_t> hb(3 * (nparts + 1));
+    for (int k = 0; k <= nparts; k++) {
+      hb[k] = P->offsets[k];
+      hb[nparts + 1 + k] = P->offsets[nparts + 1 + k];
+      hb[2 * (nparts + 1) + k] = P->offsets[nparts + 1 + k] - nB;
+    }
+    RC(mem.alloc(&P->blk_starts, (int64_t)hb.size()));
+    HIPCK(hipMemcpyAsync(P->blk_starts, hb.data(), sizeof(int64_t) * hb.size(), hipMemcpyHostToDevice, s));
+  }
+  const int64_t *bs_int = P->blk_starts, *bs_ifc = P->blk_starts + (nparts + 1),
+                *bs_loc = P->blk_starts + 2 * (nparts + 1);
+  RC(build_schedule(P, tmp, P->L1, true, 0, n, P->sL1, bs_int, bs_ifc, nB, nullptr, INT64_MAX, P->perm, nullptr, stmp,
+                    stmpb, s, "levels L"));
+  RC(build_schedule(P, tmp, P->U1, false, 0, nB, P->sU1, bs_int, nullptr, 0, P->DB, nB, nullptr, P->perm, stmp, stmpb,
+                    s, "levels U"));
+  RC(build_schedule(P, tmp, P->LS, true, 0, nS, P->sLS, bs_loc, nullptr, 0, nullptr, INT64_MAX, nullptr, nullptr, stmp,
+                    stmpb, s, "levels L_S"));
+  RC(build_schedule(P, tmp, P->US, false, 0, nS, P->sUS, bs_loc, nullptr, 0, P->DS, INT64_MAX, nullptr, nullptr, stmp,
+                    stmpb, s, "levels U_S"));
 
   // 7. workspaces
   RC(mem.alloc(&P->xp, n));
@@ -589,6 +763,8 @@ int ilu_setup(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts, const i
   if (opt.inner_iters < 0 || opt.inner_iters > 1000) return fail(ILU_ERR_INVALID_ARG, "inner_iters out of range");
   if (!(opt.droptol >= 0.0) || !(opt.inner_rtol >= 0.0) || !(opt.pivot_tol >= 0.0))
     return fail(ILU_ERR_INVALID_ARG, "negative tolerance");
+  if (opt.trsv_mode < ILU_TRSV_AUTO || opt.trsv_mode > ILU_TRSV_BLOCK)
+    return fail(ILU_ERR_INVALID_ARG, "unknown trsv_mode %d", opt.trsv_mode);
   hipStream_t s = (hipStream_t)stream;
   ilu_precond *P = new ilu_precond();
   P->n = A->n;
@@ -632,8 +808,8 @@ static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t 
   const int64_t nS = P->nS;
   const int k = P->opt.inner_iters;
   double *V = P->iV;
-  RC(trsv(P, P->sLS, P->LS, nullptr, 0, gp, nullptr, V, nullptr, nullptr, s));
-  RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, V, nullptr, V, nullptr, nullptr, s));
+  RC(trsv(P, P->sLS, P->LS, nullptr, 0, gp, nullptr, V, nullptr, nullptr, s, 2));
+  RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, V, nullptr, V, nullptr, nullptr, s, 3));
   if (k == 0) return launch_copy(V, y, nS, s);
   double *beta = P->iscal, *hn = P->iscal + 1, *est = P->iscal + 2;
   int *stop = P->iflags, *nsteps = P->iflags + 1;
@@ -644,9 +820,10 @@ static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t 
   RC(launch_scale_copy(V, nullptr, beta, V, nS, nullptr, s));
   for (int j = 0; j < k; j++) {
     double *vj = V + (int64_t)j * nS, *w = V + (int64_t)(j + 1) * nS;
-    RC(launch_spmv(P->Coff.rp, P->Coff.ci, P->Coff.v, nS, vj, P->it1, s));
-    RC(trsv(P, P->sLS, P->LS, nullptr, 0, P->it1, nullptr, P->it2, nullptr, nullptr, s));
-    RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, P->it2, nullptr, P->it2, nullptr, nullptr, s));
+    RC(timed(ILU_K_SPMV_COFF, spmv_bytes(nS, P->Coff.nnz, false), s,
+             [&] { return launch_spmv(P->Coff.rp, P->Coff.ci, P->Coff.v, nS, vj, P->it1, s); }));
+    RC(trsv(P, P->sLS, P->LS, nullptr, 0, P->it1, nullptr, P->it2, nullptr, nullptr, s, 2));
+    RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, P->it2, nullptr, P->it2, nullptr, nullptr, s, 3));
     RC(launch_vec_sum(w, vj, P->it2, nS, s));
     double *pc = P->ipa, *pn = P->ipb;
     RC(launch_dot_partial(w, V, nS, pc, s));
@@ -667,19 +844,22 @@ static int apply_impl(ilu_precond *P, const double *r, double *z, hipStream_t s)
   if (n == 0) return 0;
   double *xp = P->xp;
   // f' = L_B^-1 r[perm_B] and g' = r[perm_S] - W f' in one level-scheduled pass
-  RC(trsv(P, P->sL1, P->L1, nullptr, 0, r, P->perm, xp, nullptr, nullptr, s));
+  RC(trsv(P, P->sL1, P->L1, nullptr, 0, r, P->perm, xp, nullptr, nullptr, s, 0));
   if (nS > 0) {
     double *gp = xp + nB;
     if (P->opt.method == ILU_METHOD_SCHUR) {
       RC(inner_gmres(P, gp, gp, s));
     } else {
-      RC(trsv(P, P->sLS, P->LS, nullptr, 0, gp, nullptr, gp, nullptr, nullptr, s));
-      RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, gp, nullptr, gp, nullptr, nullptr, s));
+      RC(trsv(P, P->sLS, P->LS, nullptr, 0, gp, nullptr, gp, nullptr, nullptr, s, 2));
+      RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, gp, nullptr, gp, nullptr, nullptr, s, 3));
     }
     RC(launch_scatter(gp, P->perm + nB, nS, z, s));
   }
-  // u = U_B^-1 (f' - Z y), scattered to z
-  RC(trsv(P, P->sU1, P->U1, P->DB, nB, xp, nullptr, xp, z, P->perm, s));
+  // u = U_B^-1 (f' - Z y), scattered to z; the block-local solve takes the
+  // Z correction as its own pass first (same order of operations)
+  if (P->sU1.use_block && P->Zb.nnz > 0)
+    RC(launch_ext_correct(P->Zb.rp, P->Zb.ci, P->Zb.v, nB, nB, xp + nB, xp, s));
+  RC(trsv(P, P->sU1, P->U1, P->DB, nB, xp, nullptr, xp, z, P->perm, s, 1));
   return 0;
 }
 
@@ -760,12 +940,14 @@ static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, doub
       for (int j = 0; j < m; j++) {
         double *vj = w.V + (int64_t)j * n, *wv = w.V + (int64_t)(j + 1) * n, *zj = w.Zb + (int64_t)j * n;
         RC(apply_impl(P, vj, zj, s));
-        RC(launch_spmv(rp, ci, av, n, zj, wv, s));
+        RC(timed(ILU_K_SPMV, spmv_bytes(n, A->nnz, false), s, [&] { return launch_spmv(rp, ci, av, n, zj, wv, s); }));
         double *pc = w.pa, *pn = w.pb;
         RC(launch_dot_partial(wv, w.V, n, pc, s));
         for (int i = 0; i <= j; i++) {
           const double *vnext = i < j ? w.V + (int64_t)(i + 1) * n : nullptr;
-          RC(launch_mgs_step(wv, w.V + (int64_t)i * n, pc, w.H + i + (int64_t)ldh * j, vnext, n, pn, stop, s));
+          RC(timed(ILU_K_MGS, 32.0 * (double)n, s, [&] {
+            return launch_mgs_step(wv, w.V + (int64_t)i * n, pc, w.H + i + (int64_t)ldh * j, vnext, n, pn, stop, s);
+          }));
           std::swap(pc, pn);
         }
         RC(launch_givens(w.H, ldh, w.cs, w.sn, w.g, j, pc, stop, nsteps, est, hn, bnorm, rtol, s));
@@ -776,6 +958,7 @@ static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, doub
         HIPCK(hipMemcpyAsync(&hstop, stop, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCK(hipStreamSynchronize(s));
         const double e = P->host_pinned[0];
+        if (g_timing) timing_collect();
         if (hist) hist[its] = e / hb;
         if (hstop == 3) return fail(ILU_ERR_BREAKDOWN, "non-finite value in the Arnoldi process at step %d", its);
         if (hstop || its >= maxit) break;
@@ -825,6 +1008,21 @@ int fgmres_solve(const ilu_csr_t *A, ilu_precond_t *P, const double *d_b, double
     res->solve_ms = ms;
   }
   return rc;
+}
+
+void ilu_kernel_timing(int32_t on) {
+  if (!on) timing_collect();
+  g_timing = on != 0;
+}
+
+int ilu_kernel_stats(int32_t kind, double *total_ms, int64_t *launches, double *bytes, int32_t reset) {
+  if (kind < 0 || kind >= ILU_K_COUNT) return fail(ILU_ERR_INVALID_ARG, "unknown kernel class %d", kind);
+  timing_collect();
+  if (total_ms) *total_ms = g_kstat[kind].ms;
+  if (launches) *launches = g_kstat[kind].launches;
+  if (bytes) *bytes = g_kstat[kind].bytes;
+  if (reset) g_kstat[kind] = KStat();
+  return 0;
 }
 
 int ilu_info(ilu_precond_t *P, int64_t *n, int64_t *nB, int64_t *nS, int32_t *nparts) {

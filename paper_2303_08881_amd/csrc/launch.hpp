@@ -125,8 +125,37 @@ struct TrsvLaunch {
   const int32_t *scatter_map;
   void *status;
   int64_t max_waves;
+  int role;  // 0 L_B|W, 1 U_B|Z, 2 L_S, 3 U_S
+  // block-local schedule (launch_trsv_block)
+  int64_t nblk;
+  int64_t nlev_blk;
+  const int32_t *blk_rows;     // rows sorted by (block, level)
+  const int32_t *blk_lev_ptr;  // [nblk * nlev_blk + 1]
+  // level-ordered copy of the factor (launch_trsv_lds)
+  const int32_t *lo_meta;  // int4 per position
+  const int32_t *lo_nent;
+  const int32_t *lo_ci;
+  const double *lo_v;
+  const double *lo_diag;
+  double *lo_x;            // nrows + 256 slots
+  int32_t lo_maxent;
 };
 int launch_trsv(const TrsvLaunch &t, hipStream_t s);
+int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s);
+// x[i] -= sum_j E_ij y[col_j - col_off] (rows of E in column order)
+int launch_ext_correct(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, int64_t col_off,
+                       const double *y, double *x, hipStream_t s);
+// stage 0: pos[rows[q]] = q, padded entry counts, max entries; stage 1: fill the copy
+int launch_level_order_copy(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v,
+                            const double *diag, int64_t n, int64_t split, int32_t *pos, int64_t *cnt, int32_t *nent,
+                            const int64_t *orp, int32_t *oci, double *ov, double *odiag, const int32_t *rhs_map,
+                            const int32_t *sct_map, int32_t *meta, int32_t *maxent, int stage, hipStream_t s);
+// block id of each row from ascending block starts (s1 below split, s2 from split on; s2 may be NULL)
+int launch_row_blocks(int64_t nrows, int32_t nblk, const int64_t *s1, const int64_t *s2, int64_t split, int32_t *blk,
+                      hipStream_t s);
+int launch_block_level_keys(const int32_t *level, const int32_t *blk, int64_t n, int64_t nlev, uint32_t *key,
+                            int32_t *val, hipStream_t s);
+int launch_i64_to_i32(const int64_t *in, int32_t *out, int64_t n, hipStream_t s);
 
 // ---- krylov.hip ----
 int launch_spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x, double *y,

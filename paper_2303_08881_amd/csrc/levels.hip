@@ -117,6 +117,62 @@ int launch_levels_to_keys(const int32_t *level, int64_t n, uint32_t *key, int32_
   return check_launch("levels_to_keys");
 }
 
+// block (subdomain) of each row: rows below `split` use the ascending block
+// starts s1[0..nblk], the others s2[0..nblk] (NULL: s1 for every row); the
+// block is the last one whose start is <= r (empty blocks are skipped).
+__device__ inline int32_t last_start_le(const int64_t *s, int32_t nblk, int64_t r) {
+  int32_t lo = 0, hi = nblk + 1;  // first index with s[idx] > r, in [0, nblk+1]
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (s[mid] <= r)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  const int32_t b = lo - 1;
+  return b < 0 ? 0 : (b >= nblk ? nblk - 1 : b);
+}
+
+__global__ void k_row_blocks(int64_t nrows, int32_t nblk, const int64_t *s1, const int64_t *s2, int64_t split,
+                             int32_t *blk) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  blk[r] = last_start_le((s2 && r >= split) ? s2 : s1, nblk, r);
+}
+
+int launch_row_blocks(int64_t nrows, int32_t nblk, const int64_t *s1, const int64_t *s2, int64_t split, int32_t *blk,
+                      hipStream_t s) {
+  if (nrows == 0) return 0;
+  k_row_blocks<<<(unsigned)((nrows + 255) / 256), 256, 0, s>>>(nrows, nblk, s1, s2, split, blk);
+  return check_launch("row_blocks");
+}
+
+__global__ void k_block_level_keys(const int32_t *level, const int32_t *blk, int64_t n, int64_t nlev, uint32_t *key,
+                                   int32_t *val) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = (uint32_t)((int64_t)blk[i] * nlev + level[i]);
+  val[i] = (int32_t)i;
+}
+
+int launch_block_level_keys(const int32_t *level, const int32_t *blk, int64_t n, int64_t nlev, uint32_t *key,
+                            int32_t *val, hipStream_t s) {
+  if (n == 0) return 0;
+  k_block_level_keys<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(level, blk, n, nlev, key, val);
+  return check_launch("block_level_keys");
+}
+
+__global__ void k_i64_to_i32(const int64_t *in, int32_t *out, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (int32_t)in[i];
+}
+
+int launch_i64_to_i32(const int64_t *in, int32_t *out, int64_t n, hipStream_t s) {
+  if (n == 0) return 0;
+  k_i64_to_i32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(in, out, n);
+  return check_launch("i64_to_i32");
+}
+
 // number of <=64-row chunks in each level
 __global__ void k_level_chunk_counts(const int64_t *level_ptr, int64_t nlev, int64_t *cnt) {
   int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;

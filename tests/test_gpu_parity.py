@@ -72,18 +72,20 @@ def _ids():
 def built():
     cache = {}
 
-    def get(idx):
-        if idx not in cache:
+    def get(idx, mode=None):
+        key = (idx, mode)
+        if key not in cache:
             name, o = CONFIGS[idx]
             A, b, part, p = _case(name)
-            print(f"[parity] case {name} opts {o} n={A.n}", flush=True)
-            P_o = oracle.Precond(A, part, p, **o)
             m = silu()
+            mode_ = m.TRSV_BLOCK if mode == "block" else m.TRSV_LEVELS if mode == "levels" else m.TRSV_AUTO
+            print(f"[parity] case {name} opts {o} trsv {mode} n={A.n}", flush=True)
+            P_o = oracle.Precond(A, part, p, **o)
             Ad = m.DeviceCSR.from_host(A)
-            P_g = m.setup(Ad, part, p, **o)
+            P_g = m.setup(Ad, part, p, trsv_mode=mode_, **o)
             torch.cuda.synchronize()
-            cache[idx] = (A, b, part, p, o, P_o, Ad, P_g)
-        return cache[idx]
+            cache[key] = (A, b, part, p, o, P_o, Ad, P_g)
+        return cache[key]
 
     return get
 
@@ -113,9 +115,10 @@ def test_factors_match(built, idx):
         np.testing.assert_allclose(P_g.export(name), P_o.export(name), rtol=1e-12, err_msg=name)
 
 
+@pytest.mark.parametrize("mode", ["block", "levels"])
 @pytest.mark.parametrize("idx", range(len(CONFIGS)), ids=_ids())
-def test_apply_matches(built, idx):
-    A, b, part, p, o, P_o, Ad, P_g = built(idx)
+def test_apply_matches(built, idx, mode):
+    A, b, part, p, o, P_o, Ad, P_g = built(idx, mode)
     r = synth.uniform_rhs(A.n, 100 + idx)
     zo = P_o.apply(r)
     zg = P_g.apply(torch.as_tensor(r).cuda()).cpu().numpy()
@@ -123,9 +126,10 @@ def test_apply_matches(built, idx):
     np.testing.assert_allclose(zg, zo, rtol=tol, atol=tol * np.abs(zo).max())
 
 
+@pytest.mark.parametrize("mode", ["block", "levels"])
 @pytest.mark.parametrize("idx", range(len(CONFIGS)), ids=_ids())
-def test_fgmres_matches(built, idx):
-    A, b, part, p, o, P_o, Ad, P_g = built(idx)
+def test_fgmres_matches(built, idx, mode):
+    A, b, part, p, o, P_o, Ad, P_g = built(idx, mode)
     restart = 30 if A.n < 5000 else 50
     ro = oracle.fgmres(A, P_o, b, rtol=1e-8, restart=restart, maxit=600)
     rg = silu().fgmres(Ad, P_g, torch.as_tensor(b).cuda(), rtol=1e-8, restart=restart, maxit=600)
