@@ -264,6 +264,58 @@ struct Slots {
   double *Lv = nullptr, *Uv = nullptr, *Rv = nullptr, *D = nullptr;
 };
 
+// Tickets of csize consecutive local rows of one segment, segments
+// interleaved round-robin (local chunk index major), optionally walking each
+// segment from its end.  Returns the chunk pointers and the row order.
+static int build_chunks(Mem &tmp, const std::vector<int64_t> &a_start, const std::vector<int64_t> &a_len,
+                        const std::vector<int64_t> &b_start, const std::vector<int64_t> &b_len, int64_t csize,
+                        bool reverse, int64_t *nchunks_out, int64_t **cptr_out, int32_t **order_out, void *stmp,
+                        size_t stmpb, hipStream_t s) {
+  const int32_t nseg = (int32_t)a_start.size();
+  std::vector<int64_t> hv(4 * nseg);
+  int64_t maxq = 0;
+  for (int k = 0; k < nseg; k++) {
+    hv[k] = a_start[k];
+    hv[nseg + k] = a_len[k];
+    hv[2 * nseg + k] = b_start[k];
+    hv[3 * nseg + k] = b_len[k];
+    maxq = std::max<int64_t>(maxq, (a_len[k] + b_len[k] + csize - 1) / csize);
+  }
+  int64_t *seg;
+  RC(tmp.alloc(&seg, 4 * nseg));
+  HIPCK(hipMemcpyAsync(seg, hv.data(), sizeof(int64_t) * 4 * nseg, hipMemcpyHostToDevice, s));
+  int64_t *nchunks_seg, *cstart, nchunks;
+  RC(tmp.alloc(&nchunks_seg, nseg));
+  RC(launch_chunk_counts(nseg, seg + nseg, seg + 3 * nseg, csize, nchunks_seg, s));
+  RC(make_rp(tmp, nchunks_seg, nseg, &cstart, &nchunks, stmp, stmpb, s));
+  *nchunks_out = nchunks;
+  *cptr_out = nullptr;
+  *order_out = nullptr;
+  if (nchunks == 0) return 0;
+  uint32_t *key, *key2;
+  int32_t *val, *val2;
+  RC(tmp.alloc(&key, nchunks));
+  RC(tmp.alloc(&key2, nchunks));
+  RC(tmp.alloc(&val, nchunks));
+  RC(tmp.alloc(&val2, nchunks));
+  RC(launch_chunk_keys(nchunks, nseg, cstart, key, val, s));
+  void *rtmp;
+  const size_t rtb = radix_tmp_bytes(nchunks);
+  RC(tmp.alloc((char **)&rtmp, (int64_t)rtb));
+  RC(radix_sort(key, val, key2, val2, nchunks, bits_for((uint64_t)maxq), rtmp, rtb, s));
+  int64_t *clen, *cptr, total;
+  RC(tmp.alloc(&clen, nchunks));
+  RC(launch_chunk_len(nchunks, nseg, cstart, val2, seg + nseg, seg + 3 * nseg, csize, clen, s));
+  RC(make_rp(tmp, clen, nchunks, &cptr, &total, stmp, stmpb, s));
+  int32_t *order;
+  RC(tmp.alloc(&order, total));
+  RC(launch_chunk_rows(nchunks, nseg, cstart, val2, seg, seg + nseg, seg + 2 * nseg, seg + 3 * nseg, cptr, csize,
+                       reverse, order, s));
+  *cptr_out = cptr;
+  *order_out = order;
+  return 0;
+}
+
 // Factor M (rows < nfull full, the rest partial) with the schedule of the
 // given segments.  Scratch goes to `tmp`.
 static int run_factor(ilu_precond *P, Mem &tmp, const Csr &M, int64_t nfull, int32_t method,
@@ -294,44 +346,11 @@ static int run_factor(ilu_precond *P, Mem &tmp, const Csr &M, int64_t nfull, int
   RC(tmp.alloc(&S.Rlen, n - nfull));
   RC(tmp.alloc(&S.D, nfull));
   RC(fill_i32(S.Ulen, 0, nfull, s));
-  // schedule: FACT_CHUNK-row chunks of each segment, interleaved
-  const int32_t nseg = (int32_t)a_start.size();
-  std::vector<int64_t> hv(4 * nseg);
-  for (int k = 0; k < nseg; k++) {
-    hv[k] = a_start[k];
-    hv[nseg + k] = a_len[k];
-    hv[2 * nseg + k] = b_start[k];
-    hv[3 * nseg + k] = b_len[k];
-  }
-  int64_t *seg;
-  RC(tmp.alloc(&seg, 4 * nseg));
-  HIPCK(hipMemcpyAsync(seg, hv.data(), sizeof(int64_t) * 4 * nseg, hipMemcpyHostToDevice, s));
-  int64_t *nchunks_seg, *cstart;
-  RC(tmp.alloc(&nchunks_seg, nseg));
-  RC(launch_chunk_counts(nseg, seg, seg + nseg, seg + 2 * nseg, seg + 3 * nseg, nchunks_seg, s));
-  int64_t nchunks;
-  RC(make_rp(tmp, nchunks_seg, nseg, &cstart, &nchunks, stmp, stmpb, s));
+  int64_t nchunks = 0, *cptr = nullptr;
+  int32_t *order = nullptr;
+  RC(build_chunks(tmp, a_start, a_len, b_start, b_len, FACT_CHUNK_ROWS, false, &nchunks, &cptr, &order, stmp, stmpb,
+                  s));
   if (nchunks > 0) {
-    uint32_t *key, *key2;
-    int32_t *val, *val2;
-    RC(tmp.alloc(&key, nchunks));
-    RC(tmp.alloc(&key2, nchunks));
-    RC(tmp.alloc(&val, nchunks));
-    RC(tmp.alloc(&val2, nchunks));
-    RC(launch_chunk_keys(nchunks, nseg, cstart, key, val, s));
-    void *rtmp;
-    size_t rtb = radix_tmp_bytes(nchunks);
-    RC(tmp.alloc((char **)&rtmp, (int64_t)rtb));
-    int64_t maxq = 0;
-    for (int k = 0; k < nseg; k++) maxq = std::max<int64_t>(maxq, (a_len[k] + b_len[k] + 15) / 16);
-    RC(radix_sort(key, val, key2, val2, nchunks, bits_for((uint64_t)maxq), rtmp, rtb, s));
-    int64_t *clen, *cptr, total;
-    RC(tmp.alloc(&clen, nchunks));
-    RC(launch_chunk_len(nchunks, nseg, cstart, val2, seg + nseg, seg + 3 * nseg, clen, s));
-    RC(make_rp(tmp, clen, nchunks, &cptr, &total, stmp, stmpb, s));
-    int32_t *order;
-    RC(tmp.alloc(&order, total));
-    RC(launch_chunk_rows(nchunks, nseg, cstart, val2, seg, seg + nseg, seg + 2 * nseg, cptr, order, s));
     int *done;
     unsigned int *ticket;
     RC(tmp.alloc(&done, n));
@@ -377,8 +396,13 @@ static int run_factor(ilu_precond *P, Mem &tmp, const Csr &M, int64_t nfull, int
 }
 
 // level schedule of a triangular factor
+struct Segs {
+  std::vector<int64_t> a_start, a_len, b_start, b_len;
+};
+
 static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, int64_t lo, int64_t hi, Schedule &S,
-                          const int64_t *bs1, const int64_t *bs2, int64_t split, const double *diag, int64_t ext_col,
+                          const Segs &seg, const int64_t *bs1, const int64_t *bs2, int64_t split, const double *diag,
+                          int64_t ext_col,
                           const int32_t *rhs_map, const int32_t *sct_map, void *stmp, size_t stmpb, hipStream_t s,
                           const char *phase) {
   const int64_t n = T.n;
@@ -392,8 +416,15 @@ static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, in
   RC(tmp.alloc(&ticket, 1));
   HIPCK(hipMemsetAsync(done, 0, sizeof(int) * n, s));
   HIPCK(hipMemsetAsync(ticket, 0, sizeof(unsigned int), s));
-  RC(launch_levels(T.rp, T.ci, n, lower, lo, hi, S.level_of, done, 1, ticket, P->status, (int64_t)P->num_cu * 32, s));
-  RC(check_status(P, s, phase, nullptr, 0));
+  {
+    int64_t nch, *cptr;
+    int32_t *order;
+    RC(build_chunks(tmp, seg.a_start, seg.a_len, seg.b_start, seg.b_len, LEVEL_CHUNK_ROWS, !lower, &nch, &cptr, &order,
+                    stmp, stmpb, s));
+    RC(launch_levels_seq(T.rp, T.ci, lower, lo, hi, nch, cptr, order, S.level_of, done, 1, ticket, P->status,
+                         (int64_t)P->num_cu * 32, s));
+    RC(check_status(P, s, phase, nullptr, 0));
+  }
   int32_t *dmax;
   RC(tmp.alloc(&dmax, 1));
   RC(max_i32(S.level_of, n, dmax, s));
@@ -714,14 +745,21 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
   }
   const int64_t *bs_int = P->blk_starts, *bs_ifc = P->blk_starts + (nparts + 1),
                 *bs_loc = P->blk_starts + 2 * (nparts + 1);
-  RC(build_schedule(P, tmp, P->L1, true, 0, n, P->sL1, bs_int, bs_ifc, nB, nullptr, INT64_MAX, P->perm, nullptr, stmp,
-                    stmpb, s, "levels L"));
-  RC(build_schedule(P, tmp, P->U1, false, 0, nB, P->sU1, bs_int, nullptr, 0, P->DB, nB, nullptr, P->perm, stmp, stmpb,
-                    s, "levels U"));
-  RC(build_schedule(P, tmp, P->LS, true, 0, nS, P->sLS, bs_loc, nullptr, 0, nullptr, INT64_MAX, nullptr, nullptr, stmp,
-                    stmpb, s, "levels L_S"));
-  RC(build_schedule(P, tmp, P->US, false, 0, nS, P->sUS, bs_loc, nullptr, 0, P->DS, INT64_MAX, nullptr, nullptr, stmp,
-                    stmpb, s, "levels U_S"));
+  Segs seg_l1{as, al, bs, bl}, seg_u1{as, al, as, std::vector<int64_t>(nparts, 0)}, seg_s;
+  for (int k = 0; k < nparts; k++) {
+    seg_s.a_start.push_back(bs[k] - nB);
+    seg_s.a_len.push_back(bl[k]);
+    seg_s.b_start.push_back(0);
+    seg_s.b_len.push_back(0);
+  }
+  RC(build_schedule(P, tmp, P->L1, true, 0, n, P->sL1, seg_l1, bs_int, bs_ifc, nB, nullptr, INT64_MAX, P->perm, nullptr,
+                    stmp, stmpb, s, "levels L"));
+  RC(build_schedule(P, tmp, P->U1, false, 0, nB, P->sU1, seg_u1, bs_int, nullptr, 0, P->DB, nB, nullptr, P->perm, stmp,
+                    stmpb, s, "levels U"));
+  RC(build_schedule(P, tmp, P->LS, true, 0, nS, P->sLS, seg_s, bs_loc, nullptr, 0, nullptr, INT64_MAX, nullptr, nullptr,
+                    stmp, stmpb, s, "levels L_S"));
+  RC(build_schedule(P, tmp, P->US, false, 0, nS, P->sUS, seg_s, bs_loc, nullptr, 0, P->DS, INT64_MAX, nullptr, nullptr,
+                    stmp, stmpb, s, "levels U_S"));
 
   // 7. workspaces
   RC(mem.alloc(&P->xp, n));

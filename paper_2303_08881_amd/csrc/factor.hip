@@ -32,7 +32,6 @@
 namespace silu {
 
 constexpr int FACT_CAP = 512;  // working-row capacity (entries) per wave
-constexpr int FACT_CHUNK = 16; // consecutive rows per ticket
 
 struct FactArgs {
   const int64_t *rp;
@@ -398,18 +397,16 @@ __global__ void k_count_rows(int64_t nrows, const int64_t *cap_rp, const int32_t
 }
 
 // ---------------------------------------------------------------------------
-// schedule: chunks of FACT_CHUNK consecutive local rows, subdomains interleaved
+// schedule: chunks of consecutive local rows, subdomains interleaved
 // ---------------------------------------------------------------------------
 // Segment s covers local rows [0, size_s): the first a_len[s] of them are rows
 // a_start[s] + l, the rest b_start[s] + (l - a_len[s]).
-__global__ void k_chunk_counts(int32_t nseg, const int64_t *a_start, const int64_t *a_len, const int64_t *b_start,
-                               const int64_t *b_len, int64_t *nchunks_seg) {
+__global__ void k_chunk_counts(int32_t nseg, const int64_t *a_len, const int64_t *b_len, int64_t csize,
+                               int64_t *nchunks_seg) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nseg) return;
   const int64_t size = a_len[s] + b_len[s];
-  nchunks_seg[s] = (size + FACT_CHUNK - 1) / FACT_CHUNK;
-  (void)a_start;
-  (void)b_start;
+  nchunks_seg[s] = (size + csize - 1) / csize;
 }
 
 // chunk id c (segment-major) -> key = local chunk index, value = c
@@ -430,7 +427,7 @@ __global__ void k_chunk_keys(int64_t nchunks, int32_t nseg, const int64_t *cstar
 
 // ticket t -> its chunk length
 __global__ void k_chunk_len(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
-                            const int64_t *a_len, const int64_t *b_len, int64_t *len) {
+                            const int64_t *a_len, const int64_t *b_len, int64_t csize, int64_t *len) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= nchunks) return;
   const int64_t c = sorted_chunk[t];
@@ -444,14 +441,16 @@ __global__ void k_chunk_len(int64_t nchunks, int32_t nseg, const int64_t *cstart
   }
   const int64_t q = c - cstart[lo];
   const int64_t size = a_len[lo] + b_len[lo];
-  const int64_t first = q * FACT_CHUNK;
-  const int64_t m = size - first < FACT_CHUNK ? size - first : FACT_CHUNK;
+  const int64_t first = q * csize;
+  const int64_t m = size - first < csize ? size - first : csize;
   len[t] = m;
 }
 
+// rows of each chunk; reverse = the local order runs from the end of the segment
 __global__ void k_chunk_rows(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
                              const int64_t *a_start, const int64_t *a_len, const int64_t *b_start,
-                             const int64_t *chunk_ptr, int32_t *order) {
+                             const int64_t *b_len, const int64_t *chunk_ptr, int64_t csize, bool reverse,
+                             int32_t *order) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= nchunks) return;
   const int64_t c = sorted_chunk[t];
@@ -466,8 +465,10 @@ __global__ void k_chunk_rows(int64_t nchunks, int32_t nseg, const int64_t *cstar
   const int64_t q = c - cstart[lo];
   const int64_t o = chunk_ptr[t];
   const int64_t m = chunk_ptr[t + 1] - o;
+  const int64_t size = a_len[lo] + b_len[lo];
   for (int64_t k = 0; k < m; k++) {
-    const int64_t l = q * FACT_CHUNK + k;
+    int64_t l = q * csize + k;
+    if (reverse) l = size - 1 - l;
     order[o + k] = (int32_t)(l < a_len[lo] ? a_start[lo] + l : b_start[lo] + (l - a_len[lo]));
   }
 }
@@ -542,9 +543,9 @@ int launch_count_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len, 
   return check_launch("count_rows");
 }
 
-int launch_chunk_counts(int32_t nseg, const int64_t *a_start, const int64_t *a_len, const int64_t *b_start,
-                        const int64_t *b_len, int64_t *nchunks_seg, hipStream_t s) {
-  k_chunk_counts<<<(nseg + 255) / 256, 256, 0, s>>>(nseg, a_start, a_len, b_start, b_len, nchunks_seg);
+int launch_chunk_counts(int32_t nseg, const int64_t *a_len, const int64_t *b_len, int64_t csize, int64_t *nchunks_seg,
+                        hipStream_t s) {
+  k_chunk_counts<<<(nseg + 255) / 256, 256, 0, s>>>(nseg, a_len, b_len, csize, nchunks_seg);
   return check_launch("chunk_counts");
 }
 
@@ -556,19 +557,20 @@ int launch_chunk_keys(int64_t nchunks, int32_t nseg, const int64_t *cstart, uint
 }
 
 int launch_chunk_len(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
-                     const int64_t *a_len, const int64_t *b_len, int64_t *len, hipStream_t s) {
+                     const int64_t *a_len, const int64_t *b_len, int64_t csize, int64_t *len, hipStream_t s) {
   if (nchunks == 0) return 0;
   k_chunk_len<<<(unsigned)((nchunks + 255) / 256), 256, 0, s>>>(nchunks, nseg, cstart, sorted_chunk, a_len, b_len,
-                                                                 len);
+                                                                 csize, len);
   return check_launch("chunk_len");
 }
 
 int launch_chunk_rows(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
-                      const int64_t *a_start, const int64_t *a_len, const int64_t *b_start,
-                      const int64_t *chunk_ptr, int32_t *order, hipStream_t s) {
+                      const int64_t *a_start, const int64_t *a_len, const int64_t *b_start, const int64_t *b_len,
+                      const int64_t *chunk_ptr, int64_t csize, bool reverse, int32_t *order, hipStream_t s) {
   if (nchunks == 0) return 0;
   k_chunk_rows<<<(unsigned)((nchunks + 255) / 256), 256, 0, s>>>(nchunks, nseg, cstart, sorted_chunk, a_start,
-                                                                  a_len, b_start, chunk_ptr, order);
+                                                                  a_len, b_start, b_len, chunk_ptr, csize, reverse,
+                                                                  order);
   return check_launch("chunk_rows");
 }
 

@@ -79,15 +79,19 @@ int launch_compact_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len
                         int64_t col_hi, int64_t shift, hipStream_t s);
 int launch_count_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len, const int32_t *sc, int64_t col_lo,
                       int64_t col_hi, int64_t *cnt, hipStream_t s);
-int launch_chunk_counts(int32_t nseg, const int64_t *a_start, const int64_t *a_len, const int64_t *b_start,
-                        const int64_t *b_len, int64_t *nchunks_seg, hipStream_t s);
+// tickets of `csize` consecutive local rows per segment, segments interleaved
+// (local row l of segment s: l < a_len ? a_start + l : b_start + l - a_len;
+// reverse walks each segment from its end)
+int launch_chunk_counts(int32_t nseg, const int64_t *a_len, const int64_t *b_len, int64_t csize, int64_t *nchunks_seg,
+                        hipStream_t s);
 int launch_chunk_keys(int64_t nchunks, int32_t nseg, const int64_t *cstart, uint32_t *key, int32_t *val,
                       hipStream_t s);
 int launch_chunk_len(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
-                     const int64_t *a_len, const int64_t *b_len, int64_t *len, hipStream_t s);
+                     const int64_t *a_len, const int64_t *b_len, int64_t csize, int64_t *len, hipStream_t s);
 int launch_chunk_rows(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
-                      const int64_t *a_start, const int64_t *a_len, const int64_t *b_start,
-                      const int64_t *chunk_ptr, int32_t *order, hipStream_t s);
+                      const int64_t *a_start, const int64_t *a_len, const int64_t *b_start, const int64_t *b_len,
+                      const int64_t *chunk_ptr, int64_t csize, bool reverse, int32_t *order, hipStream_t s);
+constexpr int FACT_CHUNK_ROWS = 16;
 
 // ---- levels.hip ----
 // level of each row of a triangular CSR: lower -> dependencies are columns in
@@ -95,6 +99,10 @@ int launch_chunk_rows(int64_t nchunks, int32_t nseg, const int64_t *cstart, cons
 int launch_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool lower, int64_t lo, int64_t hi,
                   int32_t *level, int *done, int epoch, unsigned int *ticket, void *status, int64_t max_waves,
                   hipStream_t s);
+constexpr int LEVEL_CHUNK_ROWS = 32;
+int launch_levels_seq(const int64_t *rp, const int32_t *ci, bool lower, int64_t lo, int64_t hi, int64_t nchunks,
+                      const int64_t *chunk_ptr, const int32_t *order, int32_t *level, int *done, int epoch,
+                      unsigned int *ticket, void *status, int64_t max_waves, hipStream_t s);
 // chunk table of a level-ordered row list: level_ptr[nlev+1] -> chunks of <= 64 rows
 int launch_level_chunk_counts(const int64_t *level_ptr, int64_t nlev, int64_t *cnt, hipStream_t s);
 int launch_level_chunks(const int64_t *level_ptr, int64_t nlev, const int64_t *chunk_base, int32_t *chunk_start,

@@ -94,6 +94,75 @@ __global__ void __launch_bounds__(WAVE) k_levels(const int64_t *rp, const int32_
   }
 }
 
+// Chunked variant: tickets hand out short runs of consecutive rows of one
+// subdomain in dependency order (ascending for lower factors, descending for
+// upper ones; subdomains interleaved).  A wave processes its rows one after
+// the other; for each row all lanes gather the levels of its dependencies --
+// from LDS when the dependency is an earlier row of the same chunk, else
+// after a bounded wait on its completion flag -- and a wave max gives the
+// level.  Any topological order is deadlock-free: every dependency outside
+// the chunk belongs to an earlier ticket.
+__global__ void __launch_bounds__(WAVE) k_levels_seq(const int64_t *rp, const int32_t *ci, bool lower, int64_t lo,
+                                                     int64_t hi, int64_t nchunks, const int64_t *chunk_ptr,
+                                                     const int32_t *order, int32_t *level, int *done, int epoch,
+                                                     unsigned int *ticket, Status *st) {
+  __shared__ int32_t crow[LEVEL_CHUNK_ROWS];
+  __shared__ int32_t clev[LEVEL_CHUNK_ROWS];
+  const int lane = lane_id();
+  for (;;) {
+    const unsigned int t = wave_ticket(ticket);
+    if (t >= (unsigned long long)nchunks) return;
+    const int64_t cb = chunk_ptr[t], ce = chunk_ptr[t + 1];
+    for (int64_t oi = cb; oi < ce; oi++) {
+      const int32_t j = (int32_t)(oi - cb);
+      const int64_t r = order[oi];
+      int32_t m = 0;
+      bool ok = true;
+      for (int64_t base = rp[r]; base < rp[r + 1]; base += WAVE) {
+        const int64_t p = base + lane;
+        if (p < rp[r + 1]) {
+          const int64_t c = ci[p];
+          const bool dep = lower ? (c >= lo && c < r) : (c > r && c < hi);
+          if (dep) {
+            int32_t lv = -1;
+            for (int32_t k = 0; k < j; k++)
+              if (crow[k] == (int32_t)c) lv = clev[k];
+            if (lv < 0) {
+              if (!wait_flag_eq(&done[c], epoch, st, r)) {
+                ok = false;
+              } else {
+                fence_acquire();
+                lv = level[c];
+              }
+            }
+            m = max(m, lv + 1);
+          }
+        }
+      }
+      if (ballot(!ok)) return;
+      m = uniform_i32(wave_max_int(m));
+      if (lane == 0) {
+        level[r] = m;
+        crow[j] = (int32_t)r;
+        clev[j] = m;
+      }
+      __syncthreads();
+      if (lane == 0) st_release(&done[r], epoch);
+    }
+    __syncthreads();
+  }
+}
+
+int launch_levels_seq(const int64_t *rp, const int32_t *ci, bool lower, int64_t lo, int64_t hi, int64_t nchunks,
+                      const int64_t *chunk_ptr, const int32_t *order, int32_t *level, int *done, int epoch,
+                      unsigned int *ticket, void *status, int64_t max_waves, hipStream_t s) {
+  if (nchunks == 0) return 0;
+  const int64_t grid = nchunks < max_waves ? nchunks : max_waves;
+  k_levels_seq<<<(unsigned)grid, WAVE, 0, s>>>(rp, ci, lower, lo, hi, nchunks, chunk_ptr, order, level, done, epoch,
+                                               ticket, (Status *)status);
+  return check_launch("levels_seq");
+}
+
 int launch_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool lower, int64_t lo, int64_t hi,
                   int32_t *level, int *done, int epoch, unsigned int *ticket, void *status, int64_t max_waves,
                   hipStream_t s) {

@@ -210,15 +210,34 @@ int radix_sort(const uint32_t *key_in, const int32_t *val_in, uint32_t *key_out,
 }
 
 // ---------------------------------------------------------------- misc
-__global__ void k_histogram(const uint32_t *key, int64_t n, int64_t nbins, int64_t *counts) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n && key[i] < (uint64_t)nbins) atomicAdd((unsigned long long *)&counts[key[i]], 1ull);
+// exact integer counts; bins below HIST_LDS are counted in LDS per block
+// first (few bins receive most keys, e.g. subdomain ids), the rest directly
+constexpr int HIST_LDS = 4096;
+
+__global__ void __launch_bounds__(256) k_histogram(const uint32_t *key, int64_t n, int64_t nbins, int64_t *counts) {
+  __shared__ int h[HIST_LDS];
+  const int nl = nbins < HIST_LDS ? (int)nbins : HIST_LDS;
+  for (int b = threadIdx.x; b < nl; b += 256) h[b] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += stride) {
+    const uint32_t k = key[i];
+    if (k < (uint32_t)nl)
+      atomicAdd(&h[k], 1);
+    else if (k < (uint64_t)nbins)
+      atomicAdd((unsigned long long *)&counts[k], 1ull);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nl; b += 256)
+    if (h[b]) atomicAdd((unsigned long long *)&counts[b], (unsigned long long)h[b]);
 }
 
 int histogram_keys(const uint32_t *key, int64_t n, int64_t nbins, int64_t *counts, hipStream_t s) {
   if (int rc = fill_i64(counts, 0, nbins, s)) return rc;
   if (n == 0) return 0;
-  k_histogram<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(key, n, nbins, counts);
+  int64_t blocks = (n + 256 * 16 - 1) / (256 * 16);
+  if (blocks > 2048) blocks = 2048;
+  k_histogram<<<(unsigned)blocks, 256, 0, s>>>(key, n, nbins, counts);
   return check_launch("histogram");
 }
 
