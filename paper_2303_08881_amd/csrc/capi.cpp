@@ -158,12 +158,14 @@ struct Schedule {
   bool use_block = false;
   int64_t nblk = 0;
   int32_t *blk_rows = nullptr, *blk_lev_ptr = nullptr;
-  // level-ordered copy of the factor for the block-local solve
-  int32_t *lo_meta = nullptr, *lo_nent = nullptr, *lo_ci = nullptr;
-  double *lo_v = nullptr, *lo_diag = nullptr, *lo_x = nullptr;
-  int32_t lo_maxent = 0;
-  const int32_t *rhs_map = nullptr;  // gather map baked into lo_meta
-  const int32_t *sct_map = nullptr;  // scatter map baked into lo_meta
+  // fixed-stride storage of the factor for the block-local solve
+  int32_t *lds_c = nullptr, *lds_rec = nullptr, *lds_ri = nullptr;
+  double *lds_v = nullptr;
+  int32_t lds_g = 1, lds_bt = 64;
+  int64_t ext_col = 0;               // dependency columns of the block-local solve are < ext_col
+  int64_t nloc = 0;                  // rows in the block-local solve; rows nloc.. follow in one pass
+  const int32_t *rhs_map = nullptr;  // gather map baked into lds_ri
+  const int32_t *sct_map = nullptr;  // scatter map baked into lds_rec
 };
 
 struct GmresWork {
@@ -473,43 +475,55 @@ static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, in
     return fail(ILU_ERR_INVALID_ARG, "%s: block-local solve needs <= 16384 levels (has %lld)", phase,
                 (long long)S.nlev);
   if (feasible && want) {
+    // Rows from split on in a factor with two block-start tables (the rows of
+    // W in [L_B; W]) depend only on rows below split: they are left out of
+    // the block-local solve and computed by one parallel pass after it.
+    const int64_t nloc = bs2 ? split : n;
+    S.nloc = nloc;
     int32_t *blk;
-    RC(tmp.alloc(&blk, n));
-    RC(launch_row_blocks(n, (int32_t)S.nblk, bs1, bs2, split, blk, s));
-    RC(launch_block_level_keys(S.level_of, blk, n, S.nlev, key, val, s));
-    RC(mem.alloc(&S.blk_rows, n));
-    RC(radix_sort(key, val, key2, S.blk_rows, n, bits_for(nkeys - 1), rtmp, rtb, s));
+    RC(tmp.alloc(&blk, nloc));
+    RC(launch_row_blocks(nloc, (int32_t)S.nblk, bs1, nullptr, split, blk, s));
+    RC(launch_block_level_keys(S.level_of, blk, nloc, S.nlev, key, val, s));
+    RC(mem.alloc(&S.blk_rows, nloc));
+    RC(radix_sort(key, val, key2, S.blk_rows, nloc, bits_for(nkeys - 1), rtmp, rtb, s));
     int64_t *bcnt, *bptr, btot;
     RC(tmp.alloc(&bcnt, (int64_t)nkeys));
-    RC(histogram_keys(key2, n, (int64_t)nkeys, bcnt, s));
+    RC(histogram_keys(key2, nloc, (int64_t)nkeys, bcnt, s));
     const size_t stb2 = scan_tmp_bytes((int64_t)nkeys) + 64;
     void *stmp2;
     RC(tmp.alloc((char **)&stmp2, (int64_t)stb2));
     RC(make_rp(tmp, bcnt, (int64_t)nkeys, &bptr, &btot, stmp2, stb2, s));
     RC(mem.alloc(&S.blk_lev_ptr, (int64_t)nkeys + 1));
     RC(launch_i64_to_i32(bptr, S.blk_lev_ptr, (int64_t)nkeys + 1, s));
-    // level-ordered copy of the factor
-    int32_t *pos, *dmax;
-    int64_t *lcnt, *lrp, lnnz;
-    RC(tmp.alloc(&pos, n));
-    RC(tmp.alloc(&lcnt, n));
-    RC(tmp.alloc(&dmax, 1));
-    RC(fill_i32(dmax, 0, 1, s));
-    RC(mem.alloc(&S.lo_nent, n));
-    RC(launch_level_order_copy(S.blk_rows, T.rp, T.ci, T.v, diag, n, ext_col, pos, lcnt, S.lo_nent, nullptr, nullptr,
-                               nullptr, nullptr, nullptr, nullptr, nullptr, dmax, 0, s));
-    RC(make_rp(tmp, lcnt, n, &lrp, &lnnz, stmp, stmpb, s));
-    if (lnnz >= ((int64_t)1 << 31)) return fail(ILU_ERR_INVALID_ARG, "%s: factor too large for the block solve", phase);
-    RC(mem.alloc(&S.lo_ci, lnnz + 32));  // vector loads of a short last row read past its end
-    RC(mem.alloc(&S.lo_v, lnnz + 32));
-    RC(mem.alloc(&S.lo_meta, 4 * n));
-    RC(mem.alloc(&S.lo_x, n + 256));
-    if (diag) RC(mem.alloc(&S.lo_diag, n));
+    // fixed-stride storage: G lanes of four entries per row, G the smallest
+    // power of two (<= 8) that covers the longest row; threads per workgroup
+    // cover the widest level (rows beyond take the slow path)
+    int32_t *pos, *dm;
+    RC(tmp.alloc(&pos, nloc));
+    RC(tmp.alloc(&dm, 2));
+    RC(fill_i32(dm, 0, 2, s));
+    RC(launch_lds_prepare(S.blk_rows, T.rp, T.ci, nloc, ext_col, S.blk_lev_ptr, (int64_t)nkeys, pos, dm, dm + 1,
+                          s));
+    int32_t hm[2] = {0, 0};
+    HIPCK(hipMemcpyAsync(hm, dm, sizeof(hm), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    int G = 1;
+    while (G < 8 && 4 * G < hm[0]) G *= 2;
+    if ((nloc + 1) * (int64_t)G * 4 >= ((int64_t)1 << 30))
+      return fail(ILU_ERR_INVALID_ARG, "%s: factor too large for the block solve", phase);
+    int64_t bt = ((int64_t)std::max(hm[1], 1) * G + 63) / 64 * 64;
+    S.lds_g = G;
+    S.lds_bt = (int32_t)std::min<int64_t>(bt, 512);
+    const int64_t ne = (nloc + 1) * G * 4;
+    RC(mem.alloc(&S.lds_c, ne));
+    RC(mem.alloc(&S.lds_v, ne));
+    RC(mem.alloc(&S.lds_rec, 4 * (nloc + 1)));
+    RC(mem.alloc(&S.lds_ri, nloc + 1));
     S.rhs_map = rhs_map;
     S.sct_map = sct_map;
-    RC(launch_level_order_copy(S.blk_rows, T.rp, T.ci, T.v, diag, n, ext_col, pos, lcnt, S.lo_nent, lrp, S.lo_ci,
-                               S.lo_v, S.lo_diag, rhs_map, sct_map, S.lo_meta, dmax, 1, s));
-    HIPCK(hipMemcpyAsync(&S.lo_maxent, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    S.ext_col = ext_col;
+    RC(launch_lds_fill(S.blk_rows, T.rp, T.ci, T.v, diag, nloc, ext_col, pos, S.blk_lev_ptr, (int64_t)nkeys, G, rhs_map,
+                       sct_map, S.lds_c, S.lds_v, S.lds_rec, S.lds_ri, s));
     HIPCK(hipStreamSynchronize(s));
     S.use_block = true;
   }
@@ -567,14 +581,19 @@ static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, i
     t.nlev_blk = S.nlev;
     t.blk_rows = S.blk_rows;
     t.blk_lev_ptr = S.blk_lev_ptr;
-    t.lo_meta = S.lo_meta;
-    t.lo_nent = S.lo_nent;
-    t.lo_ci = S.lo_ci;
-    t.lo_v = S.lo_v;
-    t.lo_diag = S.lo_diag;
-    t.lo_x = S.lo_x;
-    t.lo_maxent = S.lo_maxent;
-    return timed(ILU_K_TRSV_LB + role, bytes, s, [&] { return launch_trsv_lds(t, s); });
+    t.lds_c = S.lds_c;
+    t.lds_v = S.lds_v;
+    t.lds_rec = S.lds_rec;
+    t.lds_ri = S.lds_ri;
+    t.lds_g = S.lds_g;
+    t.lds_bt = S.lds_bt;
+    t.split_col = S.ext_col;
+    t.nrows = S.nloc;
+    return timed(ILU_K_TRSV_LB + role, bytes, s, [&] {
+      RC(launch_trsv_lds(t, s));
+      if (S.nloc < S.nrows) RC(launch_rows_lower(T.rp, T.ci, T.v, S.nloc, S.nrows, b, bmap, x, s));
+      return 0;
+    });
   }
   return timed(ILU_K_TRSV_LB + role, bytes, s, [&] { return launch_trsv(t, s); });
 }

@@ -139,25 +139,32 @@ struct TrsvLaunch {
   int64_t nlev_blk;
   const int32_t *blk_rows;     // rows sorted by (block, level)
   const int32_t *blk_lev_ptr;  // [nblk * nlev_blk + 1]
-  // level-ordered copy of the factor (launch_trsv_lds)
-  const int32_t *lo_meta;  // int4 per position
-  const int32_t *lo_nent;
-  const int32_t *lo_ci;
-  const double *lo_v;
-  const double *lo_diag;
-  double *lo_x;            // nrows + 256 slots
-  int32_t lo_maxent;
+  // block-local storage (launch_trsv_lds): fixed-stride dependency entries
+  const int32_t *lds_c;    // [(nrows + 1) * 4G] window slots
+  const double *lds_v;     // [(nrows + 1) * 4G]
+  const int32_t *lds_rec;  // int4 per position (+ dummy)
+  const int32_t *lds_ri;   // rhs index per position (+ dummy)
+  int32_t lds_g;           // lanes per row: 1, 2, 4 or 8
+  int32_t lds_bt;          // threads per workgroup (multiple of 64, <= 512)
 };
 int launch_trsv(const TrsvLaunch &t, hipStream_t s);
 int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s);
+// rows row0..n-1 of a unit lower factor whose dependencies are all solved:
+// x_r = b[bmap ? bmap[r] : r] - sum_j l_rj x_j in column order
+int launch_rows_lower(const int64_t *rp, const int32_t *ci, const double *v, int64_t row0, int64_t n, const double *b,
+                      const int32_t *bmap, double *x, hipStream_t s);
 // x[i] -= sum_j E_ij y[col_j - col_off] (rows of E in column order)
 int launch_ext_correct(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, int64_t col_off,
                        const double *y, double *x, hipStream_t s);
-// stage 0: pos[rows[q]] = q, padded entry counts, max entries; stage 1: fill the copy
-int launch_level_order_copy(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v,
-                            const double *diag, int64_t n, int64_t split, int32_t *pos, int64_t *cnt, int32_t *nent,
-                            const int64_t *orp, int32_t *oci, double *ov, double *odiag, const int32_t *rhs_map,
-                            const int32_t *sct_map, int32_t *meta, int32_t *maxent, int stage, hipStream_t s);
+// block-local storage: pos[rows[q]] = q, the longest dependency row and the
+// widest level (maxent, maxw must be zeroed), then the fixed-stride fill
+int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci, int64_t n, int64_t split,
+                       const int32_t *lev_ptr, int64_t nseg, int32_t *pos, int32_t *maxent, int32_t *maxw,
+                       hipStream_t s);
+int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
+                    int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G,
+                    const int32_t *rhs_map, const int32_t *sct_map, int32_t *oc, double *ov, int32_t *rec,
+                    int32_t *ri, hipStream_t s);
 // block id of each row from ascending block starts (s1 below split, s2 from split on; s2 may be NULL)
 int launch_row_blocks(int64_t nrows, int32_t nblk, const int64_t *s1, const int64_t *s2, int64_t split, int32_t *blk,
                       hipStream_t s);

@@ -20,7 +20,7 @@
 
 namespace silu {
 // (k_trsv: cross-workgroup level-scheduled variant; k_trsv_lds: one
-// workgroup per subdomain on a level-ordered copy of the factor)
+// workgroup per subdomain, software-pipelined, further below)
 
 struct TrsvArgs {
   const int32_t *rows;
@@ -100,308 +100,407 @@ __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Block-local variant: the subdomains are independent, so each block of rows
+// Block-local solve.  The subdomains are independent, so each block of rows
 // (one subdomain) is solved by one workgroup that walks the block's levels
-// with a workgroup barrier between consecutive non-empty levels.  Rows are
-// listed block-major, level-minor; lev_ptr[b * nlev + l] .. [.. + 1] delimits
-// the rows of level l in block b.  No cross-workgroup communication at all.
-// ---------------------------------------------------------------------------
-constexpr int BT = 256;          // threads per block-local solve
-constexpr int BT_LDS_LEVELS = 16384;
-
-// ---------------------------------------------------------------------------
-// Block-local solve on a level-ordered copy of the factor.  Inside block b the
-// rows are stored in solve order (level by level) and every dependency column
-// is renumbered to its position in that order, so one level's rows and
-// entries are contiguous in memory (coalesced streaming).
+// with a workgroup barrier between consecutive non-empty levels; there is no
+// communication between workgroups.  Rows are listed block-major,
+// level-minor; lev_ptr[b * nlev + l] .. [.. + 1] delimits the positions of
+// level l in block b.
 //
-// Software pipeline: each thread owns at most one row of each level.  The
-// metadata of its row (one 16-byte record, entry count, diagonal) is loaded
-// six levels ahead, the right-hand side and the first PK entries (16-byte
-// vector loads; rows are padded to a multiple of 4 entries) four levels
-// ahead, into register sets that rotate by unrolling the level loop four
-// times (copying a set would wait for its loads).  Every pipeline load is
-// unconditional with a valid address, so the number of memory operations
-// between a load and its use is fixed and the in-order vmcnt waits that the
-// compiler inserts before level l do not wait for later levels' loads (the
-// counter tracks at most 63 operations per wave, which sets the depth).
-// Rows with more than PK entries, with a dependency older than the LDS window,
-// or past the first BT rows of a level, are recomputed on a slow path.  The solution of
-// the last XWIN positions is kept in an LDS ring: a dependency at position
-// c >= q1 - XWIN (q1 = end of the current level) is read from LDS, older ones
-// from the level-ordered global copy x_lo.  Columns outside the solve (the Z
-// block of the U_B solve) are not part of the copy: that correction runs
-// first as its own pass (k_ext_correct), as in the sequential definition.
+// Storage (built at setup, "position" = index in that order):
+//   ent_c/ent_v  the dependency entries of each position at a fixed stride of
+//                4G (G = 1, 2, 4 or 8): column order, each column replaced by
+//                the slot of its position in the LDS solution window,
+//                padded with the window's zero slot and 0.0;
+//   rec          {row (or ~row for a slow row), scatter index, diagonal};
+//   rhs_idx      index of the row's right-hand side in b.
+// A row is handled by G consecutive lanes, lane g summing entries 4g..4g+3
+// with fma (lane 0 starting from the right-hand side); the G partial sums
+// are combined pairwise across lanes (fixed order, so results are
+// reproducible run to run; the sum order differs from the sequential one by
+// rounding only) and the diagonal divides once.
+//
+// Latency is the whole cost of this solve (a level holds tens of rows), so
+// every load is issued eight levels before its use: each thread keeps eight
+// register sets that rotate by unrolling the level loop eight times, and the
+// right-hand-side index is loaded eight levels before the right-hand side it
+// locates.  All pipeline addresses come from the level pointers in LDS --
+// none depends on a load of the same pipeline stage -- and every pipeline
+// load is unconditional (idle lanes read a dummy position), so the number of
+// memory operations between a load and its use is fixed: the compiler's
+// in-order waits before level l then cover only level l's own loads.  Six
+// loads per level keep 48 in flight, under the 63 that the counter tracks.
+//
+// The solution of the last XWIN positions lives in an LDS ring.  Rows with
+// more than 4G entries, with a dependency older than the ring, or beyond
+// blockDim/G rows in their level are "slow": they are summed sequentially in
+// column order from the natural-order factor and solution (written by this
+// workgroup before an earlier barrier).  Columns outside the solve (the Z
+// block of the U_B solve) run first as their own pass (k_ext_correct).  A
+// scatter role writes its solution only to the scattered output (the
+// natural-order copy is not needed afterwards); its slow rows read
+// dependencies from there.
 // ---------------------------------------------------------------------------
-constexpr int XWIN = 8192;
+constexpr int XWIN = 8192;            // solution window (positions), power of two
+constexpr int BT_MAX = 512;           // threads per block-local solve
+constexpr int BT_LDS_LEVELS = 16384;  // level pointers kept in LDS
+constexpr int LOOK = 8;               // pipeline depth in levels
 
 struct LdsTrsvArgs {
-  const int4 *meta;        // position -> {row, rhs index, scatter index, first entry}
-  const int32_t *nent;     // position -> entry count (entries padded per row to a multiple of 4)
-  const int32_t *lev_ptr;  // [nblk * nlev + 1] positions
+  const int4 *ent_c;       // [(npos + 1) * G] four window slots
+  const double2 *ent_v;    // [(npos + 1) * G * 2]
+  const int4 *rec;         // [npos + 1]
+  const int32_t *rhs_idx;  // [npos + 1]
+  const int32_t *lev_ptr;  // [nblk * nlev + 1]
   int32_t nlev;
-  int32_t npos;            // positions (rows) of the whole schedule, >= 1
-  const int32_t *ci;       // dependency positions, 16-byte aligned rows
+  int32_t npos;            // positions; index npos is the dummy read by idle lanes
+  int32_t bt;              // blockDim.x, passed as an argument: reading blockDim
+                           // is a load from the dispatch packet with a full wait
+  const int64_t *rp;       // natural-order factor (slow rows)
+  const int32_t *ci;
   const double *v;
-  const double *diag;      // by position (diagonal roles only)
+  int64_t split;           // dependency columns are < split
   const double *b;
-  double *x_lo;            // solution by position; BT more slots receive idle lanes' stores
-  double *x;               // solution by row
-  double *scatter_out;     // scatter roles only
+  double *x;               // solution, natural order (not written by scatter roles)
+  double *scatter_out;     // scatter roles: the solution of row r goes to scatter_out[smap[r]] only
+  const int32_t *smap;
 };
 
-// Software pipeline over levels (see the notes above k_trsv_lds).
-template <int PK>
-struct Row {
-  int32_t r, si, n;
-  double d, rhs;
-  int32_t c[PK];
-  double w[PK];
-};
-struct Meta {
-  int4 m;  // r, ri, si, e0
-  int32_t n;
-  double d;
+struct PSet {
+  int4 c;
+  double2 w0, w1;
+  int4 rec;
+  double rhs;
 };
 
-template <bool DIAG>
-__device__ __forceinline__ void load_meta(const LdsTrsvArgs &a, const int32_t *lp, int32_t l, Meta &M) {
-  const int32_t q = lp[l] + (int32_t)threadIdx.x;
-  const bool ok = q < lp[l + 1];
-  const int32_t qc = ok ? q : a.npos - 1;
-  M.m = a.meta[qc];
-  const int32_t n = a.nent[qc];
-  M.n = ok ? n : 0;
-  if (DIAG) M.d = a.diag[qc];
+__device__ __forceinline__ double rec_diag(const int4 &r) { return __hiloint2double(r.w, r.z); }
+
+// DPP lane exchanges inside groups of 2, 4, 8 lanes (quad permutations, and
+// the mirror of 8 lanes, which pairs each lane with one of the other quad)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
-
-template <int PK, bool DIAG, bool SCAT>
-__device__ __forceinline__ void load_row(const LdsTrsvArgs &a, const Meta &M, Row<PK> &R) {
-  R.r = M.m.x;
-  R.si = M.m.z;
-  R.n = M.n;
-  R.d = DIAG ? M.d : 1.0;
-  R.rhs = a.b[M.m.y];
-  const int4 *c4 = reinterpret_cast<const int4 *>(a.ci + M.m.w);
-  const double2 *v2 = reinterpret_cast<const double2 *>(a.v + M.m.w);
-#pragma unroll
-  for (int k = 0; k < PK / 4; k++) {
-    const int4 c = c4[k];
-    R.c[4 * k] = c.x;
-    R.c[4 * k + 1] = c.y;
-    R.c[4 * k + 2] = c.z;
-    R.c[4 * k + 3] = c.w;
-  }
-#pragma unroll
-  for (int k = 0; k < PK / 2; k++) {
-    const double2 w = v2[k];
-    R.w[2 * k] = w.x;
-    R.w[2 * k + 1] = w.y;
-  }
-}
-
-template <bool DIAG>
-__device__ __forceinline__ double slow_row(const LdsTrsvArgs &a, const double *win, int32_t q, int32_t wlo) {
-  const int4 m = a.meta[q];
-  double s = a.b[m.y];
-  const int32_t n = a.nent[q];
-  for (int32_t k = 0; k < n; k++) {
-    const int32_t c = a.ci[m.w + k];
-    const double xv = c >= wlo ? win[c & (XWIN - 1)] : a.x_lo[c];
-    s = fma(-a.v[m.w + k], xv, s);
-  }
-  if (DIAG) s = s / a.diag[q];
+template <int G>
+__device__ __forceinline__ double group_sum(double s) {
+  if (G >= 2) s = s + dpp_f64<0xB1>(s);   // quad_perm [1,0,3,2]
+  if (G >= 4) s = s + dpp_f64<0x4E>(s);   // quad_perm [2,3,0,1]
+  if (G >= 8) s = s + dpp_f64<0x141>(s);  // row_half_mirror
   return s;
 }
 
-template <int PK, bool DIAG, bool SCAT>
-__device__ __forceinline__ void level_step(const LdsTrsvArgs &a, double *win, const int32_t *lp, int32_t l,
-                                           Row<PK> &R, Meta &M) {
-  const int32_t q0 = lp[l], q1 = lp[l + 1];
-  if (q0 != q1) {  // uniform
-    const int32_t wlo = q1 - XWIN;
-    const int32_t q = q0 + (int32_t)threadIdx.x;
-    const bool mine = q < q1;
-    double xv[PK];
-    bool slow = R.n > PK;
-#pragma unroll
-    for (int k = 0; k < PK; k++) {
-      xv[k] = win[R.c[k] & (XWIN - 1)];
-      slow |= (k < R.n) && R.c[k] < wlo;
-    }
-    double s = R.rhs;
-#pragma unroll
-    for (int k = 0; k < PK; k++) {
-      const double t = fma(-R.w[k], xv[k], s);
-      s = (k < R.n) ? t : s;
-    }
-    if (DIAG) s = s / R.d;
-    if (mine && slow) s = slow_row<DIAG>(a, win, q, wlo);
-    if (mine) win[q & (XWIN - 1)] = s;
-    a.x_lo[mine ? q : a.npos + (int32_t)threadIdx.x] = s;
-    if (mine) {
-      a.x[R.r] = s;
-      if (SCAT) a.scatter_out[R.si] = s;
-    }
-    for (int32_t qq = q0 + BT + (int32_t)threadIdx.x; qq < q1; qq += BT) {  // rows past the first BT
-      const double s2 = slow_row<DIAG>(a, win, qq, wlo);
-      const int4 m = a.meta[qq];
-      win[qq & (XWIN - 1)] = s2;
-      a.x_lo[qq] = s2;
-      a.x[m.x] = s2;
-      if (SCAT) a.scatter_out[m.z] = s2;
-    }
-    __syncthreads();
+template <bool DIAG, bool SCAT>
+__device__ __forceinline__ double slow_row(const LdsTrsvArgs &a, int32_t r, int32_t ri, double d) {
+  double s = a.b[ri];
+  for (int64_t p = a.rp[r]; p < a.rp[r + 1]; p++) {
+    const int32_t c = a.ci[p];
+    if (c < a.split) s = fma(-a.v[p], SCAT ? a.scatter_out[a.smap[c]] : a.x[c], s);
   }
-  load_row<PK, DIAG, SCAT>(a, M, R);  // level l + 4
-  load_meta<DIAG>(a, lp, l + 6, M);
+  if (DIAG) s = s / d;
+  // Drain this path's loads here: otherwise the compiler cannot tell, where
+  // the slow and fast paths join, that the temporaries of the slow path are
+  // no longer in flight, and it would wait for every outstanding load (the
+  // fast path's prefetches included) on every level.
+  __builtin_amdgcn_s_waitcnt(0);
+  return s;
 }
 
-template <int PK, bool DIAG, bool SCAT>
-__global__ void __launch_bounds__(BT) k_trsv_lds(LdsTrsvArgs a) {
-  __shared__ double win[XWIN];
-  __shared__ int32_t lp[BT_LDS_LEVELS + 8];
+// Load the pipeline set of the row handled by this lane in a level whose
+// positions are [lo, hi) (idle lanes read the dummy position).
+template <int G>
+__device__ __forceinline__ void refill(const LdsTrsvArgs &a, int32_t lo, int32_t hi, int32_t j, int32_t g, int32_t ri,
+                                       PSet &E) {
+  const int32_t q = lo + j;
+  const int32_t qc = q < hi ? q : a.npos;
+  const int32_t e = qc * G + g;
+  E.c = a.ent_c[e];
+  E.w0 = a.ent_v[2 * e];
+  E.w1 = a.ent_v[2 * e + 1];
+  E.rec = a.rec[qc];
+  E.rhs = a.b[ri];
+}
+__device__ __forceinline__ int32_t load_ri(const LdsTrsvArgs &a, int32_t lo, int32_t hi, int32_t j) {
+  const int32_t q = lo + j;
+  return a.rhs_idx[q < hi ? q : a.npos];
+}
+
+template <int G, bool DIAG, bool SCAT>
+__device__ __forceinline__ void pstep(const LdsTrsvArgs &a, double *win, const int32_t *lp, int32_t l, int32_t j,
+                                      int32_t g, PSet &E, int32_t &RI) {
+  // every LDS read of the step first, so that a single wait covers them: the
+  // bounds of levels l, l + LOOK, l + 2 LOOK and the four window values
+  const int32_t q0 = lp[l], q1 = lp[l + 1];
+  const int32_t f0 = lp[l + LOOK], f1 = lp[l + LOOK + 1];
+  const int32_t i0 = lp[l + 2 * LOOK], i1 = lp[l + 2 * LOOK + 1];
+  const double x0 = win[E.c.x], x1 = win[E.c.y], x2 = win[E.c.z], x3 = win[E.c.w];
+  const int32_t q = q0 + j;
+  const bool mine = q < q1;
+  double s = g == 0 ? E.rhs : 0.0;
+  s = fma(-E.w0.x, x0, s);
+  s = fma(-E.w0.y, x1, s);
+  s = fma(-E.w1.x, x2, s);
+  s = fma(-E.w1.y, x3, s);
+  s = group_sum<G>(s);
+  const bool slow = E.rec.x < 0;
+  const int32_t r = slow ? ~E.rec.x : E.rec.x;
+  if (DIAG) s = s / rec_diag(E.rec);
+  if (mine && slow) s = slow_row<DIAG, SCAT>(a, r, a.rhs_idx[q], rec_diag(E.rec));
+  if (mine && g == 0) {
+    win[q & (XWIN - 1)] = s;
+    if (SCAT)
+      a.scatter_out[E.rec.y] = s;
+    else
+      a.x[r] = s;
+  }
+  // rows beyond bt/G in this level: one thread each, slow path
+  const int32_t cap = a.bt / G;
+  for (int32_t qq = q0 + cap + (int32_t)threadIdx.x; qq < q1; qq += a.bt) {
+    const int4 rc = a.rec[qq];
+    const int32_t rr = rc.x < 0 ? ~rc.x : rc.x;
+    const double s2 = slow_row<DIAG, SCAT>(a, rr, a.rhs_idx[qq], rec_diag(rc));
+    win[qq & (XWIN - 1)] = s2;
+    if (SCAT)
+      a.scatter_out[rc.y] = s2;
+    else
+      a.x[rr] = s2;
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  __syncthreads();  // also for an empty level: the step stays branch-free
+  refill<G>(a, f0, f1, j, g, RI, E);  // RI holds the rhs index of level l + LOOK
+  // keep the next index load after the last use of RI, so both live in the
+  // same register (otherwise the loop carries a copy that waits for the load)
+  __builtin_amdgcn_sched_barrier(0);
+  RI = load_ri(a, i0, i1, j);
+}
+
+template <int G, bool DIAG, bool SCAT>
+__global__ void __launch_bounds__(BT_MAX) k_trsv_lds(LdsTrsvArgs a) {
+  __shared__ double win[XWIN + 1];  // slot XWIN stays 0.0: the target of padding entries
+  __shared__ int32_t lp[BT_LDS_LEVELS + 2 * LOOK + 10];
   const int64_t base = (int64_t)blockIdx.x * a.nlev;
   const int32_t tid = (int32_t)threadIdx.x;
   const int32_t nlev = a.nlev;
-  for (int l = tid; l <= nlev; l += BT) lp[l] = a.lev_ptr[base + l];
+  for (int32_t l = tid; l <= nlev; l += a.bt) lp[l] = a.lev_ptr[base + l];
+  for (int32_t k = tid; k <= XWIN; k += a.bt) win[k] = 0.0;
   __syncthreads();
-  if (tid < 7) lp[nlev + 1 + tid] = lp[nlev];  // empty levels past the end
+  if (tid < 2 * LOOK + 9) lp[nlev + 1 + tid] = lp[nlev];  // empty levels past the end
   __syncthreads();
-  Row<PK> R0, R1, R2, R3;
-  Meta M0, M1;
-  load_meta<DIAG>(a, lp, 0, M0);
-  load_row<PK, DIAG, SCAT>(a, M0, R0);
-  load_meta<DIAG>(a, lp, 1, M1);
-  load_row<PK, DIAG, SCAT>(a, M1, R1);
-  load_meta<DIAG>(a, lp, 2, M0);
-  load_row<PK, DIAG, SCAT>(a, M0, R2);
-  load_meta<DIAG>(a, lp, 3, M1);
-  load_row<PK, DIAG, SCAT>(a, M1, R3);
-  load_meta<DIAG>(a, lp, 4, M0);
-  load_meta<DIAG>(a, lp, 5, M1);
+  // the loop runs a multiple of eight levels (the extra ones are empty), so
+  // it has a single exit and the compiler keeps the eight steps in order
+  const int32_t j = tid / G, g = tid % G;
+  PSet E0, E1, E2, E3, E4, E5, E6, E7;
+  int32_t R0, R1, R2, R3, R4, R5, R6, R7;
+  // Prologue in the loop's own load order (E0 R0 E1 R1 ... E7 R7, pinned by
+  // scheduling barriers): the compiler merges the state at loop entry with
+  // the state at the back edge, and any load that looked more recent at entry
+  // would be waited for on every iteration.
+  {
+    const int32_t t0 = load_ri(a, lp[0], lp[1], j), t1 = load_ri(a, lp[1], lp[2], j), t2 = load_ri(a, lp[2], lp[3], j),
+                  t3 = load_ri(a, lp[3], lp[4], j), t4 = load_ri(a, lp[4], lp[5], j), t5 = load_ri(a, lp[5], lp[6], j),
+                  t6 = load_ri(a, lp[6], lp[7], j), t7 = load_ri(a, lp[7], lp[8], j);
+    refill<G>(a, lp[0], lp[1], j, g, t0, E0);
+    __builtin_amdgcn_sched_barrier(0);
+    R0 = load_ri(a, lp[8], lp[9], j);
+    __builtin_amdgcn_sched_barrier(0);
+    refill<G>(a, lp[1], lp[2], j, g, t1, E1);
+    __builtin_amdgcn_sched_barrier(0);
+    R1 = load_ri(a, lp[9], lp[10], j);
+    __builtin_amdgcn_sched_barrier(0);
+    refill<G>(a, lp[2], lp[3], j, g, t2, E2);
+    __builtin_amdgcn_sched_barrier(0);
+    R2 = load_ri(a, lp[10], lp[11], j);
+    __builtin_amdgcn_sched_barrier(0);
+    refill<G>(a, lp[3], lp[4], j, g, t3, E3);
+    __builtin_amdgcn_sched_barrier(0);
+    R3 = load_ri(a, lp[11], lp[12], j);
+    __builtin_amdgcn_sched_barrier(0);
+    refill<G>(a, lp[4], lp[5], j, g, t4, E4);
+    __builtin_amdgcn_sched_barrier(0);
+    R4 = load_ri(a, lp[12], lp[13], j);
+    __builtin_amdgcn_sched_barrier(0);
+    refill<G>(a, lp[5], lp[6], j, g, t5, E5);
+    __builtin_amdgcn_sched_barrier(0);
+    R5 = load_ri(a, lp[13], lp[14], j);
+    __builtin_amdgcn_sched_barrier(0);
+    refill<G>(a, lp[6], lp[7], j, g, t6, E6);
+    __builtin_amdgcn_sched_barrier(0);
+    R6 = load_ri(a, lp[14], lp[15], j);
+    __builtin_amdgcn_sched_barrier(0);
+    refill<G>(a, lp[7], lp[8], j, g, t7, E7);
+    __builtin_amdgcn_sched_barrier(0);
+    R7 = load_ri(a, lp[15], lp[16], j);
+    __builtin_amdgcn_sched_barrier(0);
+  }
   // eight levels per iteration: the compiler tracks outstanding loads exactly
-  // inside straight-line code but drains them at a loop back-edge
+  // inside straight-line code, and the register sets keep their names
   for (int32_t l = 0; l < nlev; l += 8) {
-    level_step<PK, DIAG, SCAT>(a, win, lp, l, R0, M0);
-    if (l + 1 >= nlev) break;
-    level_step<PK, DIAG, SCAT>(a, win, lp, l + 1, R1, M1);
-    if (l + 2 >= nlev) break;
-    level_step<PK, DIAG, SCAT>(a, win, lp, l + 2, R2, M0);
-    if (l + 3 >= nlev) break;
-    level_step<PK, DIAG, SCAT>(a, win, lp, l + 3, R3, M1);
-    if (l + 4 >= nlev) break;
-    level_step<PK, DIAG, SCAT>(a, win, lp, l + 4, R0, M0);
-    if (l + 5 >= nlev) break;
-    level_step<PK, DIAG, SCAT>(a, win, lp, l + 5, R1, M1);
-    if (l + 6 >= nlev) break;
-    level_step<PK, DIAG, SCAT>(a, win, lp, l + 6, R2, M0);
-    if (l + 7 >= nlev) break;
-    level_step<PK, DIAG, SCAT>(a, win, lp, l + 7, R3, M1);
+    pstep<G, DIAG, SCAT>(a, win, lp, l, j, g, E0, R0);
+    pstep<G, DIAG, SCAT>(a, win, lp, l + 1, j, g, E1, R1);
+    pstep<G, DIAG, SCAT>(a, win, lp, l + 2, j, g, E2, R2);
+    pstep<G, DIAG, SCAT>(a, win, lp, l + 3, j, g, E3, R3);
+    pstep<G, DIAG, SCAT>(a, win, lp, l + 4, j, g, E4, R4);
+    pstep<G, DIAG, SCAT>(a, win, lp, l + 5, j, g, E5, R5);
+    pstep<G, DIAG, SCAT>(a, win, lp, l + 6, j, g, E6, R6);
+    pstep<G, DIAG, SCAT>(a, win, lp, l + 7, j, g, E7, R7);
+  }
+}
+
+template <bool DIAG, bool SCAT>
+static void launch_g(int G, unsigned grid, unsigned bt, const LdsTrsvArgs &a, hipStream_t s) {
+  switch (G) {
+    case 1: k_trsv_lds<1, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
+    case 2: k_trsv_lds<2, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
+    case 4: k_trsv_lds<4, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
+    default: k_trsv_lds<8, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
   }
 }
 
 int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s) {
   if (t.nblk == 0 || t.nrows == 0) return 0;
-  if (t.nlev_blk > BT_LDS_LEVELS) return ILU_ERR_INVALID_ARG;
+  if (t.nlev_blk > BT_LDS_LEVELS || t.lds_bt < 64 || t.lds_bt > BT_MAX || t.lds_bt % 64 != 0 ||
+      (t.lds_g != 1 && t.lds_g != 2 && t.lds_g != 4 && t.lds_g != 8))
+    return ILU_ERR_INVALID_ARG;
   LdsTrsvArgs a;
-  a.meta = reinterpret_cast<const int4 *>(t.lo_meta);
-  a.nent = t.lo_nent;
+  a.ent_c = reinterpret_cast<const int4 *>(t.lds_c);
+  a.ent_v = reinterpret_cast<const double2 *>(t.lds_v);
+  a.rec = reinterpret_cast<const int4 *>(t.lds_rec);
+  a.rhs_idx = t.lds_ri;
   a.lev_ptr = t.blk_lev_ptr;
   a.nlev = (int32_t)t.nlev_blk;
   a.npos = (int32_t)t.nrows;
-  a.ci = t.lo_ci;
-  a.v = t.lo_v;
-  a.diag = t.lo_diag;
+  a.rp = t.rp;
+  a.ci = t.ci;
+  a.v = t.v;
+  a.split = t.split_col;
   a.b = t.b;
-  a.x_lo = t.lo_x;
   a.x = t.x;
   a.scatter_out = t.scatter_out;
-  const unsigned g = (unsigned)t.nblk;
-  // row lengths decide the register copy: 4 entries for short rows, 20 otherwise
-  const bool wide = t.lo_maxent > 4;
+  a.smap = t.scatter_map;
+  a.bt = t.lds_bt;
+  const unsigned g = (unsigned)t.nblk, bt = (unsigned)t.lds_bt;
   switch (t.role) {
     case 0:
-      if (wide) k_trsv_lds<20, false, false><<<g, BT, 0, s>>>(a);
-      else k_trsv_lds<4, false, false><<<g, BT, 0, s>>>(a);
-      break;
-    case 1:
-      if (wide) k_trsv_lds<20, true, true><<<g, BT, 0, s>>>(a);
-      else k_trsv_lds<4, true, true><<<g, BT, 0, s>>>(a);
-      break;
-    case 2:
-      if (wide) k_trsv_lds<20, false, false><<<g, BT, 0, s>>>(a);
-      else k_trsv_lds<4, false, false><<<g, BT, 0, s>>>(a);
-      break;
-    default:
-      if (wide) k_trsv_lds<20, true, false><<<g, BT, 0, s>>>(a);
-      else k_trsv_lds<4, true, false><<<g, BT, 0, s>>>(a);
-      break;
+    case 2: launch_g<false, false>(t.lds_g, g, bt, a, s); break;
+    case 1: launch_g<true, true>(t.lds_g, g, bt, a, s); break;
+    default: launch_g<true, false>(t.lds_g, g, bt, a, s); break;
   }
   return check_launch("trsv_lds");
 }
 
-// ---- construction of the level-ordered copy ----
+// ---- construction of the block-local storage ----
 __global__ void k_pos_of_row(const int32_t *rows, int64_t n, int32_t *pos) {
   int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q < n) pos[rows[q]] = (int32_t)q;
 }
 
-// dependency entries (columns < split) of the row at position q, padded to a
-// multiple of 4 so every row starts 16-byte aligned
-__global__ void k_lo_counts(const int32_t *rows, const int64_t *rp, const int32_t *ci, int64_t n, int64_t split,
-                            int64_t *cnt, int32_t *nent) {
+// dependency entries (columns < split) of the row at each position; maximum
+__global__ void k_lds_counts(const int32_t *rows, const int64_t *rp, const int32_t *ci, int64_t n, int64_t split,
+                             int32_t *maxent) {
   int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q >= n) return;
-  int64_t k = 0;
+  int32_t k = 0;
   for (int64_t p = rp[rows[q]]; p < rp[rows[q] + 1]; p++) k += ci[p] < split;
-  nent[q] = (int32_t)k;
-  cnt[q] = (k + 3) & ~(int64_t)3;
+  atomicMax(maxent, k);
 }
 
-// entries of the row at position q in column order, renumbered to positions;
-// columns >= split are left out; padding entries are zero
-__global__ void k_lo_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v,
-                          const double *diag, int64_t n, int64_t split, const int32_t *pos, const int64_t *orp,
-                          int32_t *oci, double *ov, double *odiag, const int32_t *rhs_map, const int32_t *sct_map,
-                          int4 *meta) {
+// widest level of any block
+__global__ void k_max_width(const int32_t *lev_ptr, int64_t nseg, int32_t *out) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < nseg) atomicMax(out, lev_ptr[k + 1] - lev_ptr[k]);
+}
+
+// Fill one position q (q == n: the dummy position).  lev_ptr is searched for
+// the end of q's level, which bounds what the LDS window still holds.
+__global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v,
+                           const double *diag, int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr,
+                           int64_t nseg, int G, const int32_t *rhs_map, const int32_t *sct_map, int32_t *oc,
+                           double *ov, int4 *rec, int32_t *ri) {
   int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (q >= n) return;
+  if (q > n) return;
+  const int64_t o = q * G * 4, cap = (int64_t)G * 4;
+  int64_t k = 0;
+  if (q == n) {
+    for (; k < cap; k++) {
+      oc[o + k] = XWIN;
+      ov[o + k] = 0.0;
+    }
+    rec[q] = make_int4(0, 0, __double2loint(1.0), __double2hiint(1.0));
+    ri[q] = 0;
+    return;
+  }
   const int32_t r = rows[q];
-  int64_t o = orp[q];
+  int32_t mind = 0x7fffffff;
   for (int64_t p = rp[r]; p < rp[r + 1]; p++)
     if (ci[p] < split) {
-      oci[o] = pos[ci[p]];
-      ov[o++] = v[p];
+      const int32_t pc = pos[ci[p]];
+      mind = min(mind, pc);
+      if (k < cap) {
+        oc[o + k] = pc & (XWIN - 1);
+        ov[o + k] = v[p];
+      }
+      k++;
     }
-  for (; o < orp[q + 1]; o++) {
-    oci[o] = 0;
-    ov[o] = 0.0;
+  const bool too_long = k > cap;
+  for (; k < cap; k++) {
+    oc[o + k] = XWIN;
+    ov[o + k] = 0.0;
   }
-  if (diag) odiag[q] = diag[r];
-  meta[q] = make_int4(r, rhs_map ? rhs_map[r] : r, sct_map ? sct_map[r] : 0, (int32_t)orp[q]);
+  // end of q's level: the first segment boundary above q
+  int64_t lo = 0, hi = nseg;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (lev_ptr[mid + 1] <= q)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  const int32_t lend = lev_ptr[lo + 1];
+  const bool slow = too_long || (int64_t)mind < (int64_t)lend - XWIN;
+  const double d = diag ? diag[r] : 1.0;
+  rec[q] = make_int4(slow ? ~r : r, sct_map ? sct_map[r] : 0, __double2loint(d), __double2hiint(d));
+  ri[q] = rhs_map ? rhs_map[r] : r;
 }
 
-__global__ void k_max_i32_simple(const int32_t *p, int64_t n, int32_t *out) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) atomicMax(out, p[i]);
-}
-
-int launch_level_order_copy(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v,
-                            const double *diag, int64_t n, int64_t split, int32_t *pos, int64_t *cnt, int32_t *nent,
-                            const int64_t *orp, int32_t *oci, double *ov, double *odiag, const int32_t *rhs_map,
-                            const int32_t *sct_map, int32_t *meta, int32_t *maxent, int stage, hipStream_t s) {
+int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci, int64_t n, int64_t split,
+                       const int32_t *lev_ptr, int64_t nseg, int32_t *pos, int32_t *maxent, int32_t *maxw,
+                       hipStream_t s) {
   if (n == 0) return 0;
   const unsigned g = (unsigned)((n + 255) / 256);
-  if (stage == 0) {
-    k_pos_of_row<<<g, 256, 0, s>>>(rows, n, pos);
-    k_lo_counts<<<g, 256, 0, s>>>(rows, rp, ci, n, split, cnt, nent);
-    k_max_i32_simple<<<g, 256, 0, s>>>(nent, n, maxent);
-  } else {
-    k_lo_fill<<<g, 256, 0, s>>>(rows, rp, ci, v, diag, n, split, pos, orp, oci, ov, odiag, rhs_map, sct_map,
-                                reinterpret_cast<int4 *>(meta));
-  }
-  return check_launch("level_order_copy");
+  k_pos_of_row<<<g, 256, 0, s>>>(rows, n, pos);
+  k_lds_counts<<<g, 256, 0, s>>>(rows, rp, ci, n, split, maxent);
+  k_max_width<<<(unsigned)((nseg + 255) / 256), 256, 0, s>>>(lev_ptr, nseg, maxw);
+  return check_launch("lds_prepare");
+}
+
+int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
+                    int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G,
+                    const int32_t *rhs_map, const int32_t *sct_map, int32_t *oc, double *ov, int32_t *rec,
+                    int32_t *ri, hipStream_t s) {
+  k_lds_fill<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(rows, rp, ci, v, diag, n, split, pos, lev_ptr, nseg, G,
+                                                              rhs_map, sct_map, oc, ov, reinterpret_cast<int4 *>(rec),
+                                                              ri);
+  return check_launch("lds_fill");
+}
+
+// Rows whose dependencies are all solved, one thread each, summed in column
+// order from the right-hand side: the rows of W after the block-local L_B
+// solve (g' = g - W f', Section 3.2).
+__global__ void k_rows_lower(const int64_t *rp, const int32_t *ci, const double *v, int64_t row0, int64_t n,
+                             const double *b, const int32_t *bmap, double *x) {
+  const int64_t r = row0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double s = b[bmap ? bmap[r] : r];
+  for (int64_t p = rp[r]; p < rp[r + 1]; p++) s = fma(-v[p], x[ci[p]], s);
+  x[r] = s;
+}
+
+int launch_rows_lower(const int64_t *rp, const int32_t *ci, const double *v, int64_t row0, int64_t n, const double *b,
+                      const int32_t *bmap, double *x, hipStream_t s) {
+  if (n <= row0) return 0;
+  k_rows_lower<<<(unsigned)((n - row0 + 255) / 256), 256, 0, s>>>(rp, ci, v, row0, n, b, bmap, x);
+  return check_launch("rows_lower");
 }
 
 // x[i] -= sum_j E_ij y_j over the rows of E (columns in y's numbering),
