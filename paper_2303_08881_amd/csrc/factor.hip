@@ -43,11 +43,15 @@ struct FactArgs {
   int32_t lfil;
   int32_t pivot_mode;
   double pivot_tol;
-  // schedule
+  // schedule: chunks of consecutive rows, grouped in streams (contiguous
+  // ranges of one segment's chunks, in row order); workgroup w serves stream
+  // w mod nstreams through that stream's ticket counter
   int64_t nchunks;
-  const int64_t *chunk_ptr;  // [nchunks+1] into order[]
-  const int32_t *order;      // rows in ticket order
-  unsigned int *ticket;
+  const int64_t *chunk_ptr;     // [nchunks+1] into order[]
+  const int32_t *order;         // rows, chunk after chunk
+  int64_t nstreams;
+  const int64_t *stream_chunk;  // [nstreams+1] first chunk of each stream
+  unsigned int *ticket;         // [nstreams]
   // outputs
   const int64_t *Lrp;
   int32_t *Lc;
@@ -138,10 +142,13 @@ __global__ void __launch_bounds__(WAVE) k_factor_rows(FactArgs a) {
   const bool ilut = a.method == ILU_FACT_ILUT;
   const bool milu = a.method == ILU_FACT_MILU0;
 
+  const int64_t sid = (int64_t)blockIdx.x % a.nstreams;
+  const int64_t c0 = a.stream_chunk[sid], nc = a.stream_chunk[sid + 1] - c0;
   for (;;) {
-    const unsigned int t = wave_ticket(a.ticket);
-    if (t >= (unsigned long long)a.nchunks) return;
+    const unsigned int tl = wave_ticket(a.ticket + sid);
+    if ((int64_t)tl >= nc) return;
     if (ld_relaxed(&a.st->abort)) return;
+    const int64_t t = c0 + (int64_t)tl;
     const int64_t cb = a.chunk_ptr[t], ce = a.chunk_ptr[t + 1];
     for (int64_t oi = cb; oi < ce; oi++) {
       const int64_t r = a.order[oi];
@@ -174,17 +181,35 @@ __global__ void __launch_bounds__(WAVE) k_factor_rows(FactArgs a) {
       double drop = 0.0;  // MILU: dropped fill of this row, summed in (k, j) order (lane 0)
       bool failed = false;
 
+      bool first = true;
       for (int pos = 0;; pos++) {
         // every value that decides the control flow below is made wave-uniform
         const int32_t k = uniform_i32(pos < len ? wc[pos] : 0x7fffffff);
         if (k >= lim) break;
-        bool ok = true;
-        if (lane == 0) ok = wait_flag_eq(&a.done[k], a.epoch, a.st, r);
-        if (!uniform_i32((int)ok)) {
-          failed = true;
-          break;
+        // Dependencies are waited for in rounds: the lanes wait together for
+        // every pivot still ahead in the working row, then one acquire makes
+        // all their rows visible.  A fill that becomes a pivot later (marked
+        // by bit 1 of wd) starts the next round when it is reached.
+        if (first || uniform_i32((int)(wd[pos] & 2))) {
+          first = false;
+          bool ok = true;
+          for (int x = pos + lane; x < len; x += WAVE) {
+            const int32_t kx = wc[x];
+            if (kx >= lim) break;
+            if (!wait_flag_eq(&a.done[kx], a.epoch, a.st, r)) {
+              ok = false;
+              break;
+            }
+          }
+          if (ballot(!ok) != 0ull) {
+            failed = true;
+            break;
+          }
+          fence_acquire();
+          __syncthreads();
+          for (int x = pos + lane; x < len; x += WAVE) wd[x] &= (uint8_t)~2u;
+          __syncthreads();
         }
-        fence_acquire();
         const double wk = uniform_f64(wv[pos] / a.D[k]);
         if (ilut && fabs(wk) < tau) {
           __syncthreads();
@@ -230,6 +255,7 @@ __global__ void __launch_bounds__(WAVE) k_factor_rows(FactArgs a) {
             // read every working entry after the pivot, then write it shifted
             int32_t rc_[FACT_CAP / WAVE];
             double rv_[FACT_CAP / WAVE];
+            uint8_t rd_[FACT_CAP / WAVE];
             int np_[FACT_CAP / WAVE];
 #pragma unroll
             for (int q = 0; q < FACT_CAP / WAVE; q++) {
@@ -238,6 +264,7 @@ __global__ void __launch_bounds__(WAVE) k_factor_rows(FactArgs a) {
               if (x < len) {
                 rc_[q] = wc[x];
                 rv_[q] = wv[x];
+                rd_[q] = wd[x];
                 // number of fills inserted at or before x
                 int lo = 0, hi = nf;
                 while (lo < hi) {
@@ -256,14 +283,14 @@ __global__ void __launch_bounds__(WAVE) k_factor_rows(FactArgs a) {
               if (np_[q] >= 0) {
                 wc[np_[q]] = rc_[q];
                 wv[np_[q]] = rv_[q];
-                wd[np_[q]] = 0;
+                wd[np_[q]] = rd_[q];
               }
             }
             if (lane < nf) {
               const int at = fins[lane] + lane;
               wc[at] = fcol[lane];
               wv[at] = fval[lane];
-              wd[at] = 0;
+              wd[at] = fcol[lane] < lim ? 2 : 0;  // a new pivot: not covered by the last round
             }
             len += nf;
             __syncthreads();
@@ -504,6 +531,8 @@ int launch_factor_rows(const FactLaunch &f, hipStream_t s) {
   a.nchunks = f.nchunks;
   a.chunk_ptr = f.chunk_ptr;
   a.order = f.order;
+  a.nstreams = f.nstreams;
+  a.stream_chunk = f.stream_chunk;
   a.ticket = f.ticket;
   a.Lrp = f.Lrp;
   a.Lc = f.Lc;
@@ -522,9 +551,53 @@ int launch_factor_rows(const FactLaunch &f, hipStream_t s) {
   a.epoch = f.epoch;
   a.st = (Status *)f.status;
   if (f.nchunks == 0) return 0;
-  int64_t grid = f.nchunks < f.max_waves ? f.nchunks : f.max_waves;
-  k_factor_rows<<<(unsigned)grid, WAVE, 0, s>>>(a);
+  // Every stream needs a workgroup that runs (a stream's rows may wait on an
+  // earlier stream of the same segment, never on a later one): the grid is
+  // launched cooperatively, which guarantees that all its workgroups are
+  // resident at once, and has at least one workgroup per stream.
+  if (f.grid < f.nstreams || f.nstreams < 1) return ILU_ERR_INVALID_ARG;
+  void *args[] = {&a};
+  const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_factor_rows),
+                                                  dim3((unsigned)f.grid), dim3(WAVE), args, 0, s);
+  if (e != hipSuccess) return ILU_ERR_HIP;
   return check_launch("factor_rows");
+}
+
+// Workgroups of k_factor_rows that fit on the device at once.
+int factor_resident_waves(int num_cu) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_factor_rows, WAVE, 0) != hipSuccess) return 0;
+  return per_cu * num_cu;
+}
+
+// Histogram of log2 of each row's distance to its second-nearest lower
+// neighbour (i - max{j < i - 1 : a_ij != 0}): the dominant distance is the
+// length of the runs of consecutive rows that depend on one another ("lines"
+// of a grid), the natural size of a chunk.
+__global__ void k_gap_hist(const int64_t *rp, const int32_t *ci, int64_t n, unsigned long long *hist) {
+  __shared__ unsigned long long h[32];
+  if (threadIdx.x < 32) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) {
+    int64_t best = -1;
+    for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+      const int64_t j = ci[p];
+      if (j < i - 1 && j > best) best = j;
+    }
+    if (best >= 0) {
+      const unsigned long long g = (unsigned long long)(i - best);
+      atomicAdd(&h[63 - __clzll((long long)g)], 1ull);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+int launch_gap_hist(const int64_t *rp, const int32_t *ci, int64_t n, unsigned long long *hist, hipStream_t s) {
+  if (n == 0) return 0;
+  k_gap_hist<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, n, hist);
+  return check_launch("gap_hist");
 }
 
 int launch_compact_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len, const int32_t *sc,
