@@ -318,102 +318,93 @@ static int build_chunks(Mem &tmp, const std::vector<int64_t> &a_start, const std
   return 0;
 }
 
-// Schedule of the factorization: each segment (interior rows, then its
-// interface rows) is cut into chunks of `csize` consecutive rows, and its
-// chunk sequence into `sps` contiguous streams, where sps gives each stream
-// about `per_stream` of the segment's share of the `grid` workgroups.  A
-// stream's chunks are taken in row order by the workgroups serving it, so the
-// workgroups of one segment work at several places of its row order at once
-// (a factorization front crosses many of them), while no row ever waits for
-// a row of a later stream.  Returns the chunks (cptr, order) and the streams
-// (first chunk of each, device) in stream order.
+// Schedule of the factorization, built on the host as a table of chunks
+// (runs of consecutive rows) grouped in streams.  Part A of each segment (its
+// rows factored in full) is cut into chunks of `ca` rows -- a line: rows along
+// a line depend on one another, so a workgroup that owns one serialises
+// nothing that could overlap -- and its chunk sequence into streams of `pa`
+// rows -- a plane.  Every plane then advances at once, each a few lines behind
+// the one it depends on; streams of one segment only wait on earlier streams.
+// Part B (interface rows of a partial factorization, which depend on part A
+// only and not on one another) becomes one stream per segment of `cb`-row
+// chunks that starts without workgroups: workgroups join it, and any other
+// stream with chunks left, once their own stream has handed out all its
+// chunks.  The part-A streams come first (ninit of them) and get the grid.
 static int build_streams(Mem &tmp, const std::vector<int64_t> &a_start, const std::vector<int64_t> &a_len,
-                         const std::vector<int64_t> &b_start, const std::vector<int64_t> &b_len, int64_t csize,
-                         int64_t grid, int64_t per_stream, int64_t *nchunks_out, int64_t **cptr_out,
-                         int32_t **order_out, int64_t *nstreams_out, int64_t **stream_chunk_out, void *stmp,
-                         size_t stmpb, hipStream_t s) {
+                         const std::vector<int64_t> &b_start, const std::vector<int64_t> &b_len, int64_t ca,
+                         int64_t pa, int64_t cb, int64_t grid, int64_t *nchunks_out, int32_t **chunks_out,
+                         int64_t *nstreams_out, int64_t *ninit_out, int64_t **stream_chunk_out, hipStream_t s) {
   const int32_t nseg = (int32_t)a_start.size();
-  std::vector<int64_t> nck(nseg), cst(nseg + 1, 0);
-  int64_t nonempty = 0;
-  for (int k = 0; k < nseg; k++) {
-    nck[k] = (a_len[k] + b_len[k] + csize - 1) / csize;
-    cst[k + 1] = cst[k] + nck[k];
-    nonempty += nck[k] > 0;
-  }
-  const int64_t nchunks = cst[nseg];
-  *nchunks_out = nchunks;
-  *cptr_out = nullptr;
-  *order_out = nullptr;
+  *nchunks_out = 0;
+  *chunks_out = nullptr;
   *nstreams_out = 0;
+  *ninit_out = 0;
   *stream_chunk_out = nullptr;
-  if (nchunks == 0) return 0;
-  if (nonempty > grid) return fail(ILU_ERR_INVALID_ARG, "more subdomains (%lld) than resident workgroups (%lld)",
-                                   (long long)nonempty, (long long)grid);
-  const int64_t share = std::max<int64_t>(1, grid / nonempty);
-  const int64_t want = std::max<int64_t>(1, share / std::max<int64_t>(per_stream, 1));
-  std::vector<int32_t> sorted;
+  // plane length in whole chunks; planes merge until every part-A stream can
+  // have a workgroup of its own
+  int64_t per = std::max<int64_t>(1, pa / ca);
+  for (;;) {
+    int64_t na = 0;
+    for (int k = 0; k < nseg; k++) na += (a_len[k] + ca * per - 1) / (ca * per);
+    if (na <= grid) break;
+    per *= 2;
+  }
+  std::vector<int32_t> ch;  // {first row, rows} pairs
   std::vector<int64_t> sc;
-  sorted.reserve((size_t)nchunks);
-  for (int k = 0; k < nseg; k++) {
-    if (!nck[k]) continue;
-    const int64_t sps = std::min<int64_t>(want, nck[k]);
-    for (int64_t j = 0; j < sps; j++) {
-      sc.push_back((int64_t)sorted.size());
-      for (int64_t c = j * nck[k] / sps; c < (j + 1) * nck[k] / sps; c++) sorted.push_back((int32_t)(cst[k] + c));
+  auto add_stream = [&](int64_t r0, int64_t len, int64_t csize) {
+    sc.push_back((int64_t)ch.size() / 2);
+    for (int64_t o = 0; o < len; o += csize) {
+      ch.push_back((int32_t)(r0 + o));
+      ch.push_back((int32_t)std::min<int64_t>(csize, len - o));
     }
-  }
-  sc.push_back((int64_t)sorted.size());
-  const int64_t ns = (int64_t)sc.size() - 1;
-  std::vector<int64_t> hv(5 * nseg + 1);
-  for (int k = 0; k < nseg; k++) {
-    hv[k] = a_start[k];
-    hv[nseg + k] = a_len[k];
-    hv[2 * nseg + k] = b_start[k];
-    hv[3 * nseg + k] = b_len[k];
-  }
-  for (int k = 0; k <= nseg; k++) hv[4 * nseg + k] = cst[k];
-  int64_t *seg, *stream_chunk;
-  int32_t *dsorted;
-  RC(tmp.alloc(&seg, 5 * nseg + 1));
-  RC(tmp.alloc(&stream_chunk, ns + 1));
-  RC(tmp.alloc(&dsorted, nchunks));
-  HIPCK(hipMemcpyAsync(seg, hv.data(), sizeof(int64_t) * hv.size(), hipMemcpyHostToDevice, s));
-  HIPCK(hipMemcpyAsync(stream_chunk, sc.data(), sizeof(int64_t) * sc.size(), hipMemcpyHostToDevice, s));
-  HIPCK(hipMemcpyAsync(dsorted, sorted.data(), sizeof(int32_t) * sorted.size(), hipMemcpyHostToDevice, s));
-  int64_t *clen, *cptr, total;
-  RC(tmp.alloc(&clen, nchunks));
-  RC(launch_chunk_len(nchunks, nseg, seg + 4 * nseg, dsorted, seg + nseg, seg + 3 * nseg, csize, clen, s));
-  RC(make_rp(tmp, clen, nchunks, &cptr, &total, stmp, stmpb, s));
-  int32_t *order;
-  RC(tmp.alloc(&order, total));
-  RC(launch_chunk_rows(nchunks, nseg, seg + 4 * nseg, dsorted, seg, seg + nseg, seg + 2 * nseg, seg + 3 * nseg, cptr,
-                       csize, false, order, s));
-  // the host vectors above must outlive the copies
-  HIPCK(hipStreamSynchronize(s));
-  *cptr_out = cptr;
-  *order_out = order;
+  };
+  for (int k = 0; k < nseg; k++)
+    for (int64_t o = 0; o < a_len[k]; o += ca * per) add_stream(a_start[k] + o, std::min(ca * per, a_len[k] - o), ca);
+  int64_t ninit = (int64_t)sc.size();
+  for (int k = 0; k < nseg; k++)
+    if (b_len[k] > 0) add_stream(b_start[k], b_len[k], cb);
+  const int64_t ns = (int64_t)sc.size();
+  if (ns == 0) return 0;
+  if (ninit == 0) ninit = std::min<int64_t>(ns, grid);  // no part A: part-B streams start the work
+  if (ninit > grid) return fail(ILU_ERR_INVALID_ARG, "factorization: %lld streams for %lld workgroups",
+                                (long long)ninit, (long long)grid);
+  sc.push_back((int64_t)ch.size() / 2);
+  const int64_t nch = (int64_t)ch.size() / 2;
+  int32_t *dch;
+  int64_t *dsc;
+  RC(tmp.alloc(&dch, 2 * nch));
+  RC(tmp.alloc(&dsc, ns + 1));
+  HIPCK(hipMemcpyAsync(dch, ch.data(), sizeof(int32_t) * ch.size(), hipMemcpyHostToDevice, s));
+  HIPCK(hipMemcpyAsync(dsc, sc.data(), sizeof(int64_t) * sc.size(), hipMemcpyHostToDevice, s));
+  HIPCK(hipStreamSynchronize(s));  // the host vectors go out of scope
+  *nchunks_out = nch;
+  *chunks_out = dch;
   *nstreams_out = ns;
-  *stream_chunk_out = stream_chunk;
+  *ninit_out = ninit;
+  *stream_chunk_out = dsc;
   return 0;
 }
 
-// Chunk size of the factorization: the dominant distance from a row to its
-// second-nearest lower neighbour (a grid line in natural order), clamped to
-// [16, 256] -- consecutive rows of a line depend on one another anyway, so a
-// workgroup that owns a whole line serialises nothing that could overlap.
-static int factor_chunk_rows(Mem &tmp, const Csr &M, hipStream_t s, int64_t *csize) {
+// Line and plane lengths of the rows [0, nrows) of M (the rows factored in
+// full): the dominant distances to a row's second-nearest and farthest lower
+// neighbours, lines clamped to [16, 256].
+static int factor_geometry(Mem &tmp, const Csr &M, int64_t nrows, hipStream_t s, int64_t *line, int64_t *plane) {
   unsigned long long *dh;
-  RC(tmp.alloc(&dh, 32));
-  HIPCK(hipMemsetAsync(dh, 0, 32 * sizeof(unsigned long long), s));
-  RC(launch_gap_hist(M.rp, M.ci, M.n, dh, s));
-  unsigned long long h[32];
+  RC(tmp.alloc(&dh, 64));
+  HIPCK(hipMemsetAsync(dh, 0, 64 * sizeof(unsigned long long), s));
+  RC(launch_gap_hist(M.rp, M.ci, nrows, dh, s));
+  unsigned long long h[64];
   HIPCK(hipMemcpyAsync(h, dh, sizeof(h), hipMemcpyDeviceToHost, s));
   HIPCK(hipStreamSynchronize(s));
-  int best = -1;
-  for (int b = 0; b < 32; b++)
-    if (h[b] && (best < 0 || h[b] > h[best])) best = b;
-  const int64_t g = best < 0 ? 16 : ((int64_t)1 << best);
-  *csize = std::min<int64_t>(256, std::max<int64_t>(16, g));
+  auto mode = [&](const unsigned long long *v) {
+    int best = -1;
+    for (int b = 0; b < 32; b++)
+      if (v[b] && (best < 0 || v[b] > v[best])) best = b;
+    return best;
+  };
+  const int bl = mode(h), bp = mode(h + 32);
+  *line = std::min<int64_t>(256, std::max<int64_t>(16, bl < 0 ? 16 : ((int64_t)1 << bl)));
+  *plane = std::max<int64_t>(*line, bp < 0 ? *line : ((int64_t)1 << bp));
   return 0;
 }
 
@@ -447,13 +438,13 @@ static int run_factor(ilu_precond *P, Mem &tmp, const Csr &M, int64_t nfull, int
   RC(tmp.alloc(&S.Rlen, n - nfull));
   RC(tmp.alloc(&S.D, nfull));
   RC(fill_i32(S.Ulen, 0, nfull, s));
-  int64_t nchunks = 0, *cptr = nullptr, nstreams = 0, *stream_chunk = nullptr, csize = 16;
-  int32_t *order = nullptr;
+  int64_t nchunks = 0, nstreams = 0, ninit = 0, *stream_chunk = nullptr, line = 16, plane = 16;
+  int32_t *chunks = nullptr;
   const int64_t grid = std::min<int64_t>(factor_resident_waves(P->num_cu), (int64_t)P->num_cu * 16);
   if (grid < 1) return fail(ILU_ERR_HIP, "%s: no resident workgroups for the factorization", phase);
-  RC(factor_chunk_rows(tmp, M, s, &csize));
-  RC(build_streams(tmp, a_start, a_len, b_start, b_len, csize, grid, FACT_WAVES_PER_STREAM, &nchunks, &cptr, &order,
-                   &nstreams, &stream_chunk, stmp, stmpb, s));
+  RC(factor_geometry(tmp, M, nfull, s, &line, &plane));
+  RC(build_streams(tmp, a_start, a_len, b_start, b_len, line, plane, FACT_PART_B_CHUNK, grid, &nchunks, &chunks,
+                   &nstreams, &ninit, &stream_chunk, s));
   if (nchunks > 0) {
     int *done;
     unsigned int *ticket;
@@ -473,9 +464,9 @@ static int run_factor(ilu_precond *P, Mem &tmp, const Csr &M, int64_t nfull, int
     f.pivot_mode = P->opt.pivot_mode;
     f.pivot_tol = P->opt.pivot_tol;
     f.nchunks = nchunks;
-    f.chunk_ptr = cptr;
-    f.order = order;
+    f.chunks = chunks;
     f.nstreams = nstreams;
+    f.ninit = ninit;
     f.stream_chunk = stream_chunk;
     f.ticket = ticket;
     f.Lrp = S.Lrp;

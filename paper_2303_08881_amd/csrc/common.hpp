@@ -46,6 +46,12 @@ __device__ inline unsigned long long ld_relaxed_u64(const unsigned long long *p)
 __device__ inline void st_release(int *p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Device-scope (write-through) store: leaves no dirty line in this XCD's L2,
+// which keeps the L2 write-back of the next device-scope release short.
+template <typename T>
+__device__ inline void st_dev(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ inline void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 __device__ inline void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 

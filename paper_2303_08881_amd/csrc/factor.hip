@@ -43,13 +43,13 @@ struct FactArgs {
   int32_t lfil;
   int32_t pivot_mode;
   double pivot_tol;
-  // schedule: chunks of consecutive rows, grouped in streams (contiguous
-  // ranges of one segment's chunks, in row order); workgroup w serves stream
-  // w mod nstreams through that stream's ticket counter
+  // schedule: chunks of consecutive rows {first row, count}, grouped in
+  // streams (contiguous runs of chunks in row order, each with a ticket
+  // counter); workgroup w starts on stream w mod ninit and, once that stream
+  // has handed out all its chunks, joins the next stream that has chunks left
   int64_t nchunks;
-  const int64_t *chunk_ptr;     // [nchunks+1] into order[]
-  const int32_t *order;         // rows, chunk after chunk
-  int64_t nstreams;
+  const int2 *chunks;
+  int64_t nstreams, ninit;
   const int64_t *stream_chunk;  // [nstreams+1] first chunk of each stream
   unsigned int *ticket;         // [nstreams]
   // outputs
@@ -123,8 +123,8 @@ __device__ int emit_part(const int32_t *wc, const double *wv, const uint8_t *wd,
     unsigned long long mk = ballot(keep);
     if (keep) {
       int at = out + mbcnt(mk);
-      oc[at] = wc[x];
-      ov[at] = wv[x];
+      st_dev(oc + at, wc[x]);
+      st_dev(ov + at, wv[x]);
     }
     out += popc64(mk);
   }
@@ -142,16 +142,24 @@ __global__ void __launch_bounds__(WAVE) k_factor_rows(FactArgs a) {
   const bool ilut = a.method == ILU_FACT_ILUT;
   const bool milu = a.method == ILU_FACT_MILU0;
 
-  const int64_t sid = (int64_t)blockIdx.x % a.nstreams;
-  const int64_t c0 = a.stream_chunk[sid], nc = a.stream_chunk[sid + 1] - c0;
+  int64_t sid = (int64_t)blockIdx.x % a.ninit;
   for (;;) {
-    const unsigned int tl = wave_ticket(a.ticket + sid);
-    if ((int64_t)tl >= nc) return;
+    // A stream is left only once it has handed out all its chunks, so every
+    // stream keeps a workgroup until then; a stream that no row depends on
+    // (interface rows of a partial factorization) may start without one.
+    int64_t t = -1;
+    for (int64_t tries = 0; tries < a.nstreams && t < 0; tries++) {
+      const int64_t c0 = a.stream_chunk[sid], nc = a.stream_chunk[sid + 1] - c0;
+      if ((int64_t)uniform_i32(ld_relaxed(reinterpret_cast<const int *>(a.ticket + sid))) < nc) {
+        const unsigned int tl = wave_ticket(a.ticket + sid);
+        if ((int64_t)tl < nc) t = c0 + (int64_t)tl;
+      }
+      if (t < 0) sid = sid + 1 < a.nstreams ? sid + 1 : 0;
+    }
+    if (t < 0) return;
     if (ld_relaxed(&a.st->abort)) return;
-    const int64_t t = c0 + (int64_t)tl;
-    const int64_t cb = a.chunk_ptr[t], ce = a.chunk_ptr[t + 1];
-    for (int64_t oi = cb; oi < ce; oi++) {
-      const int64_t r = a.order[oi];
+    const int2 ch = a.chunks[t];
+    for (int64_t r = ch.x; r < (int64_t)ch.x + ch.y; r++) {
       const int64_t lim = r < a.nfull ? r : a.nfull;
       const int64_t rb = a.rp[r];
       int len = (int)(a.rp[r + 1] - rb);
@@ -325,13 +333,13 @@ __global__ void __launch_bounds__(WAVE) k_factor_rows(FactArgs a) {
           if (lane == 0) raise_error(a.st, ILU_ERR_ZERO_PIVOT, r);
           return;
         }
-        if (lane == 0) a.D[r] = d;
+        if (lane == 0) st_dev(a.D + r, d);
         const int nl = emit_part(wc, wv, wd, 0, pd, ilut, tau, a.lfil, -1, a.Lc + a.Lrp[r], a.Lv + a.Lrp[r], false);
         const int nu =
             emit_part(wc, wv, wd, pd + 1, len, ilut, tau, a.lfil, -1, a.Uc + a.Urp[r], a.Uv + a.Urp[r], true);
         if (lane == 0) {
-          a.Llen[r] = nl;
-          a.Ulen[r] = nu;
+          st_dev(a.Llen + r, nl);
+          st_dev(a.Ulen + r, nu);
         }
       } else {  // partial row: L (interior columns) | Schur remainder R
         const int pl = uniform_i32(lower_bound_lds(wc, 0, len, (int32_t)a.nfull));
@@ -345,8 +353,8 @@ __global__ void __launch_bounds__(WAVE) k_factor_rows(FactArgs a) {
         const int64_t ro = a.Rrp[r - a.nfull];
         const int nr = emit_part(wc, wv, wd, pl, len, ilut, tau, a.lfil, pd, a.Rc + ro, a.Rv + ro, true);
         if (lane == 0) {
-          a.Llen[r] = nl;
-          a.Rlen[r - a.nfull] = nr;
+          st_dev(a.Llen + r, nl);
+          st_dev(a.Rlen + (r - a.nfull), nr);
         }
       }
       __syncthreads();
@@ -529,9 +537,9 @@ int launch_factor_rows(const FactLaunch &f, hipStream_t s) {
   a.pivot_mode = f.pivot_mode;
   a.pivot_tol = f.pivot_tol;
   a.nchunks = f.nchunks;
-  a.chunk_ptr = f.chunk_ptr;
-  a.order = f.order;
+  a.chunks = reinterpret_cast<const int2 *>(f.chunks);
   a.nstreams = f.nstreams;
+  a.ninit = f.ninit;
   a.stream_chunk = f.stream_chunk;
   a.ticket = f.ticket;
   a.Lrp = f.Lrp;
@@ -555,7 +563,7 @@ int launch_factor_rows(const FactLaunch &f, hipStream_t s) {
   // earlier stream of the same segment, never on a later one): the grid is
   // launched cooperatively, which guarantees that all its workgroups are
   // resident at once, and has at least one workgroup per stream.
-  if (f.grid < f.nstreams || f.nstreams < 1) return ILU_ERR_INVALID_ARG;
+  if (f.grid < f.ninit || f.ninit < 1 || f.ninit > f.nstreams) return ILU_ERR_INVALID_ARG;
   void *args[] = {&a};
   const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_factor_rows),
                                                   dim3((unsigned)f.grid), dim3(WAVE), args, 0, s);
@@ -570,28 +578,32 @@ int factor_resident_waves(int num_cu) {
   return per_cu * num_cu;
 }
 
-// Histogram of log2 of each row's distance to its second-nearest lower
-// neighbour (i - max{j < i - 1 : a_ij != 0}): the dominant distance is the
-// length of the runs of consecutive rows that depend on one another ("lines"
-// of a grid), the natural size of a chunk.
+// Histograms of log2 of each row's distance to its second-nearest lower
+// neighbour (i - max{j < i - 1 : a_ij != 0}) and to its farthest one
+// (i - min{j < i - 1}).  In a natural ordering of a grid the dominant values
+// are the length of a line and of a plane: consecutive rows along a line
+// depend on one another, and a plane depends on the plane before it.
 __global__ void k_gap_hist(const int64_t *rp, const int32_t *ci, int64_t n, unsigned long long *hist) {
-  __shared__ unsigned long long h[32];
-  if (threadIdx.x < 32) h[threadIdx.x] = 0;
+  __shared__ unsigned long long h[64];
+  if (threadIdx.x < 64) h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) {
-    int64_t best = -1;
+    int64_t best = -1, far = i;
     for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
       const int64_t j = ci[p];
-      if (j < i - 1 && j > best) best = j;
+      if (j < i - 1) {
+        if (j > best) best = j;
+        if (j < far) far = j;
+      }
     }
     if (best >= 0) {
-      const unsigned long long g = (unsigned long long)(i - best);
-      atomicAdd(&h[63 - __clzll((long long)g)], 1ull);
+      atomicAdd(&h[63 - __clzll((long long)(i - best))], 1ull);
+      atomicAdd(&h[32 + 63 - __clzll((long long)(i - far))], 1ull);
     }
   }
   __syncthreads();
-  if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+  if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
 int launch_gap_hist(const int64_t *rp, const int32_t *ci, int64_t n, unsigned long long *hist, hipStream_t s) {

@@ -50,9 +50,8 @@ struct FactLaunch {
   int32_t pivot_mode;
   double pivot_tol;
   int64_t nchunks;
-  const int64_t *chunk_ptr;
-  const int32_t *order;
-  int64_t nstreams;
+  const int32_t *chunks;        // int2 {first row, rows} per chunk, stream after stream
+  int64_t nstreams, ninit;      // streams; the first ninit get the workgroups at the start
   const int64_t *stream_chunk;  // [nstreams+1]
   unsigned int *ticket;         // [nstreams], zeroed
   const int64_t *Lrp;
@@ -71,10 +70,10 @@ struct FactLaunch {
   int *done;
   int epoch;
   void *status;
-  int64_t grid;  // workgroups, all resident (factor_resident_waves), >= nstreams
+  int64_t grid;  // workgroups, all resident (factor_resident_waves), >= ninit
 };
 int factor_resident_waves(int num_cu);
-// histogram (32 buckets, zeroed) of log2 of each row's second-nearest lower-neighbour distance
+// histograms (2 x 32 buckets, zeroed) of log2 of each row's second-nearest and farthest lower-neighbour distance
 int launch_gap_hist(const int64_t *rp, const int32_t *ci, int64_t n, unsigned long long *hist, hipStream_t s);
 int launch_fact_caps(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nfull, int32_t method, int32_t lfil,
                      int64_t *Lcap, int64_t *Ucap, int64_t *Rcap, hipStream_t s);
@@ -96,7 +95,7 @@ int launch_chunk_len(int64_t nchunks, int32_t nseg, const int64_t *cstart, const
 int launch_chunk_rows(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
                       const int64_t *a_start, const int64_t *a_len, const int64_t *b_start, const int64_t *b_len,
                       const int64_t *chunk_ptr, int64_t csize, bool reverse, int32_t *order, hipStream_t s);
-constexpr int FACT_WAVES_PER_STREAM = 24;  // workgroups per factorization stream
+constexpr int FACT_PART_B_CHUNK = 4;  // rows per chunk of a partial factorization's interface rows
 
 // ---- levels.hip ----
 // level of each row of a triangular CSR: lower -> dependencies are columns in
