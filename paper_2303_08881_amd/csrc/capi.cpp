@@ -266,58 +266,6 @@ struct Slots {
   double *Lv = nullptr, *Uv = nullptr, *Rv = nullptr, *D = nullptr;
 };
 
-// Tickets of csize consecutive local rows of one segment, segments
-// interleaved round-robin (local chunk index major), optionally walking each
-// segment from its end.  Returns the chunk pointers and the row order.
-static int build_chunks(Mem &tmp, const std::vector<int64_t> &a_start, const std::vector<int64_t> &a_len,
-                        const std::vector<int64_t> &b_start, const std::vector<int64_t> &b_len, int64_t csize,
-                        bool reverse, int64_t *nchunks_out, int64_t **cptr_out, int32_t **order_out, void *stmp,
-                        size_t stmpb, hipStream_t s) {
-  const int32_t nseg = (int32_t)a_start.size();
-  std::vector<int64_t> hv(4 * nseg);
-  int64_t maxq = 0;
-  for (int k = 0; k < nseg; k++) {
-    hv[k] = a_start[k];
-    hv[nseg + k] = a_len[k];
-    hv[2 * nseg + k] = b_start[k];
-    hv[3 * nseg + k] = b_len[k];
-    maxq = std::max<int64_t>(maxq, (a_len[k] + b_len[k] + csize - 1) / csize);
-  }
-  int64_t *seg;
-  RC(tmp.alloc(&seg, 4 * nseg));
-  HIPCK(hipMemcpyAsync(seg, hv.data(), sizeof(int64_t) * 4 * nseg, hipMemcpyHostToDevice, s));
-  int64_t *nchunks_seg, *cstart, nchunks;
-  RC(tmp.alloc(&nchunks_seg, nseg));
-  RC(launch_chunk_counts(nseg, seg + nseg, seg + 3 * nseg, csize, nchunks_seg, s));
-  RC(make_rp(tmp, nchunks_seg, nseg, &cstart, &nchunks, stmp, stmpb, s));
-  *nchunks_out = nchunks;
-  *cptr_out = nullptr;
-  *order_out = nullptr;
-  if (nchunks == 0) return 0;
-  uint32_t *key, *key2;
-  int32_t *val, *val2;
-  RC(tmp.alloc(&key, nchunks));
-  RC(tmp.alloc(&key2, nchunks));
-  RC(tmp.alloc(&val, nchunks));
-  RC(tmp.alloc(&val2, nchunks));
-  RC(launch_chunk_keys(nchunks, nseg, cstart, key, val, s));
-  void *rtmp;
-  const size_t rtb = radix_tmp_bytes(nchunks);
-  RC(tmp.alloc((char **)&rtmp, (int64_t)rtb));
-  RC(radix_sort(key, val, key2, val2, nchunks, bits_for((uint64_t)maxq), rtmp, rtb, s));
-  int64_t *clen, *cptr, total;
-  RC(tmp.alloc(&clen, nchunks));
-  RC(launch_chunk_len(nchunks, nseg, cstart, val2, seg + nseg, seg + 3 * nseg, csize, clen, s));
-  RC(make_rp(tmp, clen, nchunks, &cptr, &total, stmp, stmpb, s));
-  int32_t *order;
-  RC(tmp.alloc(&order, total));
-  RC(launch_chunk_rows(nchunks, nseg, cstart, val2, seg, seg + nseg, seg + 2 * nseg, seg + 3 * nseg, cptr, csize,
-                       reverse, order, s));
-  *cptr_out = cptr;
-  *order_out = order;
-  return 0;
-}
-
 // Schedule of the factorization, built on the host as a table of chunks
 // (runs of consecutive rows) grouped in streams.  Part A of each segment (its
 // rows factored in full) is cut into chunks of `ca` rows -- a line: rows along
@@ -332,8 +280,9 @@ static int build_chunks(Mem &tmp, const std::vector<int64_t> &a_start, const std
 // chunks.  The part-A streams come first (ninit of them) and get the grid.
 static int build_streams(Mem &tmp, const std::vector<int64_t> &a_start, const std::vector<int64_t> &a_len,
                          const std::vector<int64_t> &b_start, const std::vector<int64_t> &b_len, int64_t ca,
-                         int64_t pa, int64_t cb, int64_t grid, int64_t *nchunks_out, int32_t **chunks_out,
-                         int64_t *nstreams_out, int64_t *ninit_out, int64_t **stream_chunk_out, hipStream_t s) {
+                         int64_t pa, int64_t cb, bool reverse, int64_t grid, int64_t *nchunks_out,
+                         int32_t **chunks_out, int64_t *nstreams_out, int64_t *ninit_out, int64_t **stream_chunk_out,
+                         hipStream_t s) {
   const int32_t nseg = (int32_t)a_start.size();
   *nchunks_out = 0;
   *chunks_out = nullptr;
@@ -351,18 +300,21 @@ static int build_streams(Mem &tmp, const std::vector<int64_t> &a_start, const st
   }
   std::vector<int32_t> ch;  // {first row, rows} pairs
   std::vector<int64_t> sc;
+  // a chunk is {first row, rows}; in reverse its rows run downwards from the
+  // first, and the chunks and streams of a segment start at its last row
   auto add_stream = [&](int64_t r0, int64_t len, int64_t csize) {
     sc.push_back((int64_t)ch.size() / 2);
     for (int64_t o = 0; o < len; o += csize) {
-      ch.push_back((int32_t)(r0 + o));
+      ch.push_back((int32_t)(reverse ? r0 - o : r0 + o));
       ch.push_back((int32_t)std::min<int64_t>(csize, len - o));
     }
   };
   for (int k = 0; k < nseg; k++)
-    for (int64_t o = 0; o < a_len[k]; o += ca * per) add_stream(a_start[k] + o, std::min(ca * per, a_len[k] - o), ca);
+    for (int64_t o = 0; o < a_len[k]; o += ca * per)
+      add_stream(reverse ? a_start[k] + a_len[k] - 1 - o : a_start[k] + o, std::min(ca * per, a_len[k] - o), ca);
   int64_t ninit = (int64_t)sc.size();
   for (int k = 0; k < nseg; k++)
-    if (b_len[k] > 0) add_stream(b_start[k], b_len[k], cb);
+    if (b_len[k] > 0) add_stream(reverse ? b_start[k] + b_len[k] - 1 : b_start[k], b_len[k], cb);
   const int64_t ns = (int64_t)sc.size();
   if (ns == 0) return 0;
   if (ninit == 0) ninit = std::min<int64_t>(ns, grid);  // no part A: part-B streams start the work
@@ -385,14 +337,15 @@ static int build_streams(Mem &tmp, const std::vector<int64_t> &a_start, const st
   return 0;
 }
 
-// Line and plane lengths of the rows [0, nrows) of M (the rows factored in
-// full): the dominant distances to a row's second-nearest and farthest lower
-// neighbours, lines clamped to [16, 256].
-static int factor_geometry(Mem &tmp, const Csr &M, int64_t nrows, hipStream_t s, int64_t *line, int64_t *plane) {
+// Line and plane lengths of the rows [0, nrows) of M: the dominant distances
+// to a row's second-nearest and farthest lower (upper) neighbours, lines
+// clamped to [16, 256].
+static int row_geometry(Mem &tmp, const Csr &M, int64_t nrows, bool upper, hipStream_t s, int64_t *line,
+                        int64_t *plane) {
   unsigned long long *dh;
   RC(tmp.alloc(&dh, 64));
   HIPCK(hipMemsetAsync(dh, 0, 64 * sizeof(unsigned long long), s));
-  RC(launch_gap_hist(M.rp, M.ci, nrows, dh, s));
+  RC(launch_gap_hist(M.rp, M.ci, nrows, upper, dh, s));
   unsigned long long h[64];
   HIPCK(hipMemcpyAsync(h, dh, sizeof(h), hipMemcpyDeviceToHost, s));
   HIPCK(hipStreamSynchronize(s));
@@ -442,9 +395,9 @@ static int run_factor(ilu_precond *P, Mem &tmp, const Csr &M, int64_t nfull, int
   int32_t *chunks = nullptr;
   const int64_t grid = std::min<int64_t>(factor_resident_waves(P->num_cu), (int64_t)P->num_cu * 16);
   if (grid < 1) return fail(ILU_ERR_HIP, "%s: no resident workgroups for the factorization", phase);
-  RC(factor_geometry(tmp, M, nfull, s, &line, &plane));
-  RC(build_streams(tmp, a_start, a_len, b_start, b_len, line, plane, FACT_PART_B_CHUNK, grid, &nchunks, &chunks,
-                   &nstreams, &ninit, &stream_chunk, s));
+  RC(row_geometry(tmp, M, nfull, false, s, &line, &plane));
+  RC(build_streams(tmp, a_start, a_len, b_start, b_len, line, plane, FACT_PART_B_CHUNK, false, grid, &nchunks,
+                   &chunks, &nstreams, &ninit, &stream_chunk, s));
   if (nchunks > 0) {
     int *done;
     unsigned int *ticket;
@@ -507,19 +460,24 @@ static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, in
   if (n == 0) return 0;
   Mem &mem = P->mem;
   RC(mem.alloc(&S.level_of, n));
-  int *done;
-  unsigned int *ticket;
-  RC(tmp.alloc(&done, n));
-  RC(tmp.alloc(&ticket, 1));
-  HIPCK(hipMemsetAsync(done, 0, sizeof(int) * n, s));
-  HIPCK(hipMemsetAsync(ticket, 0, sizeof(unsigned int), s));
   {
-    int64_t nch, *cptr;
-    int32_t *order;
-    RC(build_chunks(tmp, seg.a_start, seg.a_len, seg.b_start, seg.b_len, LEVEL_CHUNK_ROWS, !lower, &nch, &cptr, &order,
-                    stmp, stmpb, s));
-    RC(launch_levels_seq(T.rp, T.ci, lower, lo, hi, nch, cptr, order, S.level_of, done, 1, ticket, P->status,
-                         (int64_t)P->num_cu * 32, s));
+    // level sweep on the factorization's kind of schedule (lines and planes
+    // of this factor's own pattern, from the bottom for L, the top for U)
+    int64_t line = 16, plane = 16, nch = 0, ns = 0, ninit = 0, *sc = nullptr;
+    int32_t *chunks = nullptr;
+    const int64_t grid = std::min<int64_t>(levels_resident_waves(P->num_cu), (int64_t)P->num_cu * 32);
+    if (grid < 1) return fail(ILU_ERR_HIP, "%s: no resident workgroups for the level sweep", phase);
+    RC(row_geometry(tmp, T, n, !lower, s, &line, &plane));
+    RC(build_streams(tmp, seg.a_start, seg.a_len, seg.b_start, seg.b_len, line, plane, 4, !lower, grid, &nch, &chunks,
+                     &ns, &ninit, &sc, s));
+    int *done;
+    unsigned int *ticket;
+    RC(tmp.alloc(&done, n));
+    RC(tmp.alloc(&ticket, std::max<int64_t>(ns, 1)));
+    HIPCK(hipMemsetAsync(done, 0, sizeof(int) * n, s));
+    HIPCK(hipMemsetAsync(ticket, 0, sizeof(unsigned int) * std::max<int64_t>(ns, 1), s));
+    RC(launch_levels_stream(T.rp, T.ci, lower, lo, hi, chunks, ns, ninit, sc, ticket, S.level_of, done, P->status,
+                            grid, s));
     RC(check_status(P, s, phase, nullptr, 0));
   }
   int32_t *dmax;

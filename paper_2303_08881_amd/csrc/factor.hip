@@ -431,83 +431,6 @@ __global__ void k_count_rows(int64_t nrows, const int64_t *cap_rp, const int32_t
   cnt[r] = k;
 }
 
-// ---------------------------------------------------------------------------
-// schedule: chunks of consecutive local rows, subdomains interleaved
-// ---------------------------------------------------------------------------
-// Segment s covers local rows [0, size_s): the first a_len[s] of them are rows
-// a_start[s] + l, the rest b_start[s] + (l - a_len[s]).
-__global__ void k_chunk_counts(int32_t nseg, const int64_t *a_len, const int64_t *b_len, int64_t csize,
-                               int64_t *nchunks_seg) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nseg) return;
-  const int64_t size = a_len[s] + b_len[s];
-  nchunks_seg[s] = (size + csize - 1) / csize;
-}
-
-// chunk id c (segment-major) -> key = local chunk index, value = c
-__global__ void k_chunk_keys(int64_t nchunks, int32_t nseg, const int64_t *cstart, uint32_t *key, int32_t *val) {
-  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= nchunks) return;
-  int lo = 0, hi = nseg;  // largest s with cstart[s] <= c
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (cstart[mid] <= c)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  key[c] = (uint32_t)(c - cstart[lo]);
-  val[c] = (int32_t)c;
-}
-
-// ticket t -> its chunk length
-__global__ void k_chunk_len(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
-                            const int64_t *a_len, const int64_t *b_len, int64_t csize, int64_t *len) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= nchunks) return;
-  const int64_t c = sorted_chunk[t];
-  int lo = 0, hi = nseg;
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (cstart[mid] <= c)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  const int64_t q = c - cstart[lo];
-  const int64_t size = a_len[lo] + b_len[lo];
-  const int64_t first = q * csize;
-  const int64_t m = size - first < csize ? size - first : csize;
-  len[t] = m;
-}
-
-// rows of each chunk; reverse = the local order runs from the end of the segment
-__global__ void k_chunk_rows(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
-                             const int64_t *a_start, const int64_t *a_len, const int64_t *b_start,
-                             const int64_t *b_len, const int64_t *chunk_ptr, int64_t csize, bool reverse,
-                             int32_t *order) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= nchunks) return;
-  const int64_t c = sorted_chunk[t];
-  int lo = 0, hi = nseg;
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (cstart[mid] <= c)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  const int64_t q = c - cstart[lo];
-  const int64_t o = chunk_ptr[t];
-  const int64_t m = chunk_ptr[t + 1] - o;
-  const int64_t size = a_len[lo] + b_len[lo];
-  for (int64_t k = 0; k < m; k++) {
-    int64_t l = q * csize + k;
-    if (reverse) l = size - 1 - l;
-    order[o + k] = (int32_t)(l < a_len[lo] ? a_start[lo] + l : b_start[lo] + (l - a_len[lo]));
-  }
-}
-
 }  // namespace silu
 
 // ---------------------------------------------------------------------------
@@ -580,35 +503,38 @@ int factor_resident_waves(int num_cu) {
 
 // Histograms of log2 of each row's distance to its second-nearest lower
 // neighbour (i - max{j < i - 1 : a_ij != 0}) and to its farthest one
-// (i - min{j < i - 1}).  In a natural ordering of a grid the dominant values
-// are the length of a line and of a plane: consecutive rows along a line
-// depend on one another, and a plane depends on the plane before it.
-__global__ void k_gap_hist(const int64_t *rp, const int32_t *ci, int64_t n, unsigned long long *hist) {
+// (i - min{j < i - 1}); with `upper`, of the mirrored distances to upper
+// neighbours (min{j > i + 1} - i and max{j > i + 1} - i).  In a natural
+// ordering of a grid the dominant values are the length of a line and of a
+// plane: consecutive rows along a line depend on one another, and a plane
+// depends on the plane before it.
+__global__ void k_gap_hist(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, unsigned long long *hist) {
   __shared__ unsigned long long h[64];
   if (threadIdx.x < 64) h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) {
-    int64_t best = -1, far = i;
+    int64_t near = -1, far = -1;
     for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
-      const int64_t j = ci[p];
-      if (j < i - 1) {
-        if (j > best) best = j;
-        if (j < far) far = j;
+      const int64_t d = upper ? (int64_t)ci[p] - i : i - (int64_t)ci[p];
+      if (d > 1) {
+        if (near < 0 || d < near) near = d;
+        if (d > far) far = d;
       }
     }
-    if (best >= 0) {
-      atomicAdd(&h[63 - __clzll((long long)(i - best))], 1ull);
-      atomicAdd(&h[32 + 63 - __clzll((long long)(i - far))], 1ull);
+    if (near > 0) {
+      atomicAdd(&h[63 - __clzll((long long)near)], 1ull);
+      atomicAdd(&h[32 + 63 - __clzll((long long)far)], 1ull);
     }
   }
   __syncthreads();
   if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
-int launch_gap_hist(const int64_t *rp, const int32_t *ci, int64_t n, unsigned long long *hist, hipStream_t s) {
+int launch_gap_hist(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, unsigned long long *hist,
+                    hipStream_t s) {
   if (n == 0) return 0;
-  k_gap_hist<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, n, hist);
+  k_gap_hist<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, n, upper, hist);
   return check_launch("gap_hist");
 }
 
@@ -626,37 +552,6 @@ int launch_count_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len, 
   if (nrows == 0) return 0;
   k_count_rows<<<(unsigned)((nrows + 255) / 256), 256, 0, s>>>(nrows, cap_rp, len, sc, col_lo, col_hi, cnt);
   return check_launch("count_rows");
-}
-
-int launch_chunk_counts(int32_t nseg, const int64_t *a_len, const int64_t *b_len, int64_t csize, int64_t *nchunks_seg,
-                        hipStream_t s) {
-  k_chunk_counts<<<(nseg + 255) / 256, 256, 0, s>>>(nseg, a_len, b_len, csize, nchunks_seg);
-  return check_launch("chunk_counts");
-}
-
-int launch_chunk_keys(int64_t nchunks, int32_t nseg, const int64_t *cstart, uint32_t *key, int32_t *val,
-                      hipStream_t s) {
-  if (nchunks == 0) return 0;
-  k_chunk_keys<<<(unsigned)((nchunks + 255) / 256), 256, 0, s>>>(nchunks, nseg, cstart, key, val);
-  return check_launch("chunk_keys");
-}
-
-int launch_chunk_len(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
-                     const int64_t *a_len, const int64_t *b_len, int64_t csize, int64_t *len, hipStream_t s) {
-  if (nchunks == 0) return 0;
-  k_chunk_len<<<(unsigned)((nchunks + 255) / 256), 256, 0, s>>>(nchunks, nseg, cstart, sorted_chunk, a_len, b_len,
-                                                                 csize, len);
-  return check_launch("chunk_len");
-}
-
-int launch_chunk_rows(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
-                      const int64_t *a_start, const int64_t *a_len, const int64_t *b_start, const int64_t *b_len,
-                      const int64_t *chunk_ptr, int64_t csize, bool reverse, int32_t *order, hipStream_t s) {
-  if (nchunks == 0) return 0;
-  k_chunk_rows<<<(unsigned)((nchunks + 255) / 256), 256, 0, s>>>(nchunks, nseg, cstart, sorted_chunk, a_start,
-                                                                  a_len, b_start, b_len, chunk_ptr, csize, reverse,
-                                                                  order);
-  return check_launch("chunk_rows");
 }
 
 }  // namespace silu

@@ -73,8 +73,10 @@ struct FactLaunch {
   int64_t grid;  // workgroups, all resident (factor_resident_waves), >= ninit
 };
 int factor_resident_waves(int num_cu);
-// histograms (2 x 32 buckets, zeroed) of log2 of each row's second-nearest and farthest lower-neighbour distance
-int launch_gap_hist(const int64_t *rp, const int32_t *ci, int64_t n, unsigned long long *hist, hipStream_t s);
+// histograms (2 x 32 buckets, zeroed) of log2 of each row's second-nearest and farthest lower (upper)
+// neighbour distance
+int launch_gap_hist(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, unsigned long long *hist,
+                    hipStream_t s);
 int launch_fact_caps(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nfull, int32_t method, int32_t lfil,
                      int64_t *Lcap, int64_t *Ucap, int64_t *Rcap, hipStream_t s);
 int launch_factor_rows(const FactLaunch &f, hipStream_t s);
@@ -83,30 +85,15 @@ int launch_compact_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len
                         int64_t col_hi, int64_t shift, hipStream_t s);
 int launch_count_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len, const int32_t *sc, int64_t col_lo,
                       int64_t col_hi, int64_t *cnt, hipStream_t s);
-// tickets of `csize` consecutive local rows per segment, segments interleaved
-// (local row l of segment s: l < a_len ? a_start + l : b_start + l - a_len;
-// reverse walks each segment from its end)
-int launch_chunk_counts(int32_t nseg, const int64_t *a_len, const int64_t *b_len, int64_t csize, int64_t *nchunks_seg,
-                        hipStream_t s);
-int launch_chunk_keys(int64_t nchunks, int32_t nseg, const int64_t *cstart, uint32_t *key, int32_t *val,
-                      hipStream_t s);
-int launch_chunk_len(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
-                     const int64_t *a_len, const int64_t *b_len, int64_t csize, int64_t *len, hipStream_t s);
-int launch_chunk_rows(int64_t nchunks, int32_t nseg, const int64_t *cstart, const int32_t *sorted_chunk,
-                      const int64_t *a_start, const int64_t *a_len, const int64_t *b_start, const int64_t *b_len,
-                      const int64_t *chunk_ptr, int64_t csize, bool reverse, int32_t *order, hipStream_t s);
 constexpr int FACT_PART_B_CHUNK = 4;  // rows per chunk of a partial factorization's interface rows
 
-// ---- levels.hip ----
-// level of each row of a triangular CSR: lower -> dependencies are columns in
-// [lo, r); upper -> (r, hi).  Sync-free, natural order, bounded waits.
-int launch_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool lower, int64_t lo, int64_t hi,
-                  int32_t *level, int *done, int epoch, unsigned int *ticket, void *status, int64_t max_waves,
-                  hipStream_t s);
-constexpr int LEVEL_CHUNK_ROWS = 32;
-int launch_levels_seq(const int64_t *rp, const int32_t *ci, bool lower, int64_t lo, int64_t hi, int64_t nchunks,
-                      const int64_t *chunk_ptr, const int32_t *order, int32_t *level, int *done, int epoch,
-                      unsigned int *ticket, void *status, int64_t max_waves, hipStream_t s);
+constexpr int LEVEL_CHUNK_MAX = 256;  // rows per chunk of the level sweep
+// Level sweep over a stream schedule (build_streams); done[] zeroed, grid
+// workgroups all resident (levels_resident_waves) and >= ninit.
+int levels_resident_waves(int num_cu);
+int launch_levels_stream(const int64_t *rp, const int32_t *ci, bool lower, int64_t lo, int64_t hi,
+                         const int32_t *chunks, int64_t nstreams, int64_t ninit, const int64_t *stream_chunk,
+                         unsigned int *ticket, int32_t *level, int *done, void *status, int64_t grid, hipStream_t s);
 // chunk table of a level-ordered row list: level_ptr[nlev+1] -> chunks of <= 64 rows
 int launch_level_chunk_counts(const int64_t *level_ptr, int64_t nlev, int64_t *cnt, hipStream_t s);
 int launch_level_chunks(const int64_t *level_ptr, int64_t nlev, const int64_t *chunk_base, int32_t *chunk_start,

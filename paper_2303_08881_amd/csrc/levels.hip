@@ -5,135 +5,73 @@
 // for a lower factor the dependencies of r are its columns in [lo, r), for an
 // upper factor its columns in (r, hi).
 //
-// Sync-free evaluation: a wave takes 64 consecutive rows (in dependency
-// order: ascending for lower, descending for upper) by atomic ticket.  A row
-// first waits, with bounded polls, for the completion flags of dependencies
-// outside its chunk, then the chunk resolves its internal chain in rounds
-// (each round finishes every row whose in-chunk dependencies are done).
+// Also here: the keys that sort rows by level (and by block, then level) and
+// the chunk table of the cross-workgroup triangular solve.
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace silu {
 
-__global__ void __launch_bounds__(WAVE) k_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool lower,
-                                                  int64_t lo, int64_t hi, int32_t *level, int *done, int epoch,
-                                                  unsigned int *ticket, Status *st) {
-  __shared__ int32_t lev_s[WAVE];
-  __shared__ int32_t ok_s[WAVE];
-  const int lane = lane_id();
-  const int64_t nchunks = (n + WAVE - 1) / WAVE;
-  for (;;) {
-    const int64_t t = wave_ticket(ticket);
-    if (t >= nchunks) return;
-    const int64_t q = t * WAVE + lane;  // position in dependency order
-    const bool valid = q < n;
-    const int64_t r = lower ? q : n - 1 - q;
-    const int64_t cb = t * WAVE;        // chunk covers positions [cb, cb+64)
-    int32_t m = 0;                       // max over resolved dependencies of level+1
-    bool ok = true;
-    if (valid) {
-      for (int64_t p = rp[r]; p < rp[r + 1]; p++) {
-        const int64_t c = ci[p];
-        const bool dep = lower ? (c >= lo && c < r) : (c > r && c < hi);
-        if (!dep) continue;
-        const int64_t qc = lower ? c : n - 1 - c;
-        if (qc >= cb) continue;  // inside this chunk: resolved below
-        if (!wait_flag_eq(&done[c], epoch, st, r)) {
-          ok = false;
-          break;
-        }
-      }
+// Level of every row of a triangular factor by a dependency-ordered sweep:
+// level(r) = 1 + max level of the rows r depends on (0 without any).  The
+// rows come in chunks of consecutive rows (a line, from the top down for an
+// upper factor) grouped in streams, exactly like the factorization's schedule.
+// A workgroup sums one row at a time: dependencies inside its chunk come from
+// LDS, the others from the completion flag of their row, which holds
+// level + 1 (0 = not yet known) -- the value is its own payload, so no fence
+// is needed on either side.  Waits are bounded.
+__device__ inline int wait_nonzero(const int *flag, Status *st, int64_t row) {
+  long it = 0;
+  int v;
+  while ((v = ld_relaxed(flag)) == 0) {
+    if (++it > SPIN_LIMIT) {
+      raise_error(st, ILU_ERR_TIMEOUT, row);
+      return -1;
     }
-    if (ballot(!ok)) return;
-    fence_acquire();
-    if (valid) {
-      for (int64_t p = rp[r]; p < rp[r + 1]; p++) {
-        const int64_t c = ci[p];
-        const bool dep = lower ? (c >= lo && c < r) : (c > r && c < hi);
-        if (!dep) continue;
-        const int64_t qc = lower ? c : n - 1 - c;
-        if (qc >= cb) continue;
-        m = max(m, level[c] + 1);
-      }
-    }
-    ok_s[lane] = valid ? 0 : 1;
-    lev_s[lane] = m;
-    __syncthreads();
-    // in-chunk chain: dependencies sit at smaller positions, i.e. lower lanes
-    for (int round = 0; round < WAVE; round++) {
-      bool ready = true;
-      int32_t mm = m;
-      if (valid && !ok_s[lane]) {
-        for (int64_t p = rp[r]; p < rp[r + 1]; p++) {
-          const int64_t c = ci[p];
-          const bool dep = lower ? (c >= lo && c < r) : (c > r && c < hi);
-          if (!dep) continue;
-          const int64_t qc = lower ? c : n - 1 - c;
-          if (qc < cb) continue;
-          const int l2 = (int)(qc - cb);
-          if (!ok_s[l2]) {
-            ready = false;
-            break;
-          }
-          mm = max(mm, lev_s[l2] + 1);
-        }
-      }
-      __syncthreads();
-      if (valid && !ok_s[lane] && ready) {
-        lev_s[lane] = mm;
-        ok_s[lane] = 1;
-      }
-      __syncthreads();
-      if (!ballot(ok_s[lane] == 0)) break;
-    }
-    if (valid) {
-      level[r] = lev_s[lane];
-      st_release(&done[r], epoch);
-    }
-    __syncthreads();
+    if ((it & 255) == 0 && ld_relaxed(&st->abort)) return -1;
+    __builtin_amdgcn_s_sleep(1);
   }
+  return v;
 }
 
-// Chunked variant: tickets hand out short runs of consecutive rows of one
-// subdomain in dependency order (ascending for lower factors, descending for
-// upper ones; subdomains interleaved).  A wave processes its rows one after
-// the other; for each row all lanes gather the levels of its dependencies --
-// from LDS when the dependency is an earlier row of the same chunk, else
-// after a bounded wait on its completion flag -- and a wave max gives the
-// level.  Any topological order is deadlock-free: every dependency outside
-// the chunk belongs to an earlier ticket.
-__global__ void __launch_bounds__(WAVE) k_levels_seq(const int64_t *rp, const int32_t *ci, bool lower, int64_t lo,
-                                                     int64_t hi, int64_t nchunks, const int64_t *chunk_ptr,
-                                                     const int32_t *order, int32_t *level, int *done, int epoch,
-                                                     unsigned int *ticket, Status *st) {
-  __shared__ int32_t crow[LEVEL_CHUNK_ROWS];
-  __shared__ int32_t clev[LEVEL_CHUNK_ROWS];
+__global__ void __launch_bounds__(WAVE) k_levels_stream(const int64_t *rp, const int32_t *ci, bool lower, int64_t lo,
+                                                        int64_t hi, const int2 *chunks, int64_t nstreams,
+                                                        int64_t ninit, const int64_t *stream_chunk,
+                                                        unsigned int *ticket, int32_t *level, int *done, Status *st) {
+  __shared__ int32_t clev[LEVEL_CHUNK_MAX];
   const int lane = lane_id();
+  int64_t sid = (int64_t)blockIdx.x % ninit;
   for (;;) {
-    const unsigned int t = wave_ticket(ticket);
-    if (t >= (unsigned long long)nchunks) return;
-    const int64_t cb = chunk_ptr[t], ce = chunk_ptr[t + 1];
-    for (int64_t oi = cb; oi < ce; oi++) {
-      const int32_t j = (int32_t)(oi - cb);
-      const int64_t r = order[oi];
+    int64_t t = -1;
+    for (int64_t tries = 0; tries < nstreams && t < 0; tries++) {
+      const int64_t c0 = stream_chunk[sid], nc = stream_chunk[sid + 1] - c0;
+      if ((int64_t)uniform_i32(ld_relaxed(reinterpret_cast<const int *>(ticket + sid))) < nc) {
+        const unsigned int tl = wave_ticket(ticket + sid);
+        if ((int64_t)tl < nc) t = c0 + (int64_t)tl;
+      }
+      if (t < 0) sid = sid + 1 < nstreams ? sid + 1 : 0;
+    }
+    if (t < 0) return;
+    if (ld_relaxed(&st->abort)) return;
+    const int2 ch = chunks[t];
+    const int64_t first = ch.x;
+    for (int32_t i = 0; i < ch.y; i++) {
+      const int64_t r = lower ? first + i : first - i;
       int32_t m = 0;
       bool ok = true;
       for (int64_t base = rp[r]; base < rp[r + 1]; base += WAVE) {
         const int64_t p = base + lane;
         if (p < rp[r + 1]) {
           const int64_t c = ci[p];
-          const bool dep = lower ? (c >= lo && c < r) : (c > r && c < hi);
-          if (dep) {
-            int32_t lv = -1;
-            for (int32_t k = 0; k < j; k++)
-              if (crow[k] == (int32_t)c) lv = clev[k];
-            if (lv < 0) {
-              if (!wait_flag_eq(&done[c], epoch, st, r)) {
-                ok = false;
-              } else {
-                fence_acquire();
-                lv = level[c];
-              }
+          if (lower ? (c >= lo && c < r) : (c > r && c < hi)) {
+            const int64_t off = lower ? c - first : first - c;  // position in this chunk
+            int32_t lv;
+            if (off >= 0 && off < i) {
+              lv = clev[off];
+            } else {
+              const int v = wait_nonzero(&done[c], st, r);
+              ok = ok && v > 0;
+              lv = v - 1;
             }
             m = max(m, lv + 1);
           }
@@ -143,34 +81,35 @@ __global__ void __launch_bounds__(WAVE) k_levels_seq(const int64_t *rp, const in
       m = uniform_i32(wave_max_int(m));
       if (lane == 0) {
         level[r] = m;
-        crow[j] = (int32_t)r;
-        clev[j] = m;
+        clev[i] = m;
+        st_dev(&done[r], m + 1);
       }
       __syncthreads();
-      if (lane == 0) st_release(&done[r], epoch);
     }
-    __syncthreads();
   }
 }
 
-int launch_levels_seq(const int64_t *rp, const int32_t *ci, bool lower, int64_t lo, int64_t hi, int64_t nchunks,
-                      const int64_t *chunk_ptr, const int32_t *order, int32_t *level, int *done, int epoch,
-                      unsigned int *ticket, void *status, int64_t max_waves, hipStream_t s) {
-  if (nchunks == 0) return 0;
-  const int64_t grid = nchunks < max_waves ? nchunks : max_waves;
-  k_levels_seq<<<(unsigned)grid, WAVE, 0, s>>>(rp, ci, lower, lo, hi, nchunks, chunk_ptr, order, level, done, epoch,
-                                               ticket, (Status *)status);
-  return check_launch("levels_seq");
+int levels_resident_waves(int num_cu) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_levels_stream, WAVE, 0) != hipSuccess) return 0;
+  return per_cu * num_cu;
 }
 
-int launch_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool lower, int64_t lo, int64_t hi,
-                  int32_t *level, int *done, int epoch, unsigned int *ticket, void *status, int64_t max_waves,
-                  hipStream_t s) {
-  if (n == 0) return 0;
-  const int64_t nchunks = (n + WAVE - 1) / WAVE;
-  const int64_t grid = nchunks < max_waves ? nchunks : max_waves;
-  k_levels<<<(unsigned)grid, WAVE, 0, s>>>(rp, ci, n, lower, lo, hi, level, done, epoch, ticket, (Status *)status);
-  return check_launch("levels");
+int launch_levels_stream(const int64_t *rp, const int32_t *ci, bool lower, int64_t lo, int64_t hi,
+                         const int32_t *chunks, int64_t nstreams, int64_t ninit, const int64_t *stream_chunk,
+                         unsigned int *ticket, int32_t *level, int *done, void *status, int64_t grid, hipStream_t s) {
+  if (nstreams == 0) return 0;
+  if (grid < ninit || ninit < 1 || ninit > nstreams) return ILU_ERR_INVALID_ARG;
+  const int2 *ch = reinterpret_cast<const int2 *>(chunks);
+  Status *st = (Status *)status;
+  void *args[] = {(void *)&rp, (void *)&ci, (void *)&lower, (void *)&lo, (void *)&hi, (void *)&ch,
+                  (void *)&nstreams, (void *)&ninit, (void *)&stream_chunk, (void *)&ticket, (void *)&level,
+                  (void *)&done, (void *)&st};
+  // all workgroups resident at once, as in the factorization
+  const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_levels_stream),
+                                                  dim3((unsigned)grid), dim3(WAVE), args, 0, s);
+  if (e != hipSuccess) return ILU_ERR_HIP;
+  return check_launch("levels_stream");
 }
 
 __global__ void k_levels_to_keys(const int32_t *level, int64_t n, uint32_t *key, int32_t *val) {
