@@ -30,6 +30,15 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 KERNELS = ["trsv_LB_W", "trsv_UB_Z", "trsv_LS", "trsv_US", "spmv_A", "spmv_Coff", "mgs"]
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+CSRC = os.path.join(ROOT, "paper_2303_08881_amd", "csrc")
+# source file of each kernel class (traffic figures are void once it changes)
+KERNEL_SOURCE = {"trsv_LB_W": "trsv.hip", "trsv_UB_Z": "trsv.hip", "trsv_LS": "trsv.hip", "trsv_US": "trsv.hip",
+                 "spmv_A": "krylov.hip", "spmv_Coff": "krylov.hip", "mgs": "krylov.hip"}
+# block-local solve instance of each class: k_trsv_lds<G, E, DIAG, SCAT> (schedule index, DIAG, SCAT)
+TRSV_ROLE = {"trsv_LB_W": (0, "false", "false"), "trsv_UB_Z": (1, "true", "true"), "trsv_LS": (2, "false", "false"),
+             "trsv_US": (3, "true", "false")}
+COPY_BYTES = 256 << 20  # the calibration copy: 256 MiB read, 256 MiB written
 WORKLOADS = {
     # name: (generator key, options, rtol, restart)
     "aniso3d_128_slab16": ("aniso3d_128_slab16",
@@ -44,6 +53,71 @@ DESCRIPTION = {
                           "b = U(-1,1) seed 2",
     "aniso2d_64": "2D 5-point -(u_xx + 0.01 u_yy), 64^2, one block, ILU(0), FGMRES(30) to rtol 1e-8, b = A 1",
 }
+
+
+def source_hash(name: str) -> str:
+    import hashlib
+
+    with open(os.path.join(CSRC, name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def kernel_instance(cls: str, sched) -> str | None:
+    """Kernel (demangled name prefix) that runs a kernel class in this workload."""
+    if cls in TRSV_ROLE:
+        k, diag, scat = TRSV_ROLE[cls]
+        if sched is None or not sched[4 * k]:
+            return None
+        return f"void silu::k_trsv_lds<{sched[4 * k + 1]}, {sched[4 * k + 2]}, {diag}, {scat}>"
+    return {"spmv_A": "silu::k_spmv(", "spmv_Coff": "silu::k_spmv(", "mgs": "silu::k_mgs_step("}.get(cls)
+
+
+def measured_traffic(cls: str, sched):
+    """HBM bytes per launch of a kernel class from profiles/traffic.json (counter runs of this workload), or None
+    when there is none or the kernel's source changed since the counters were taken."""
+    inst = kernel_instance(cls, sched)
+    if inst is None or not os.path.exists(TRAFFIC_JSON):
+        return None
+    with open(TRAFFIC_JSON) as f:
+        tj = json.load(f)
+    for name, rec in tj.get("kernels", {}).items():
+        if name.startswith(inst) and rec.get("source_sha") == source_hash(KERNEL_SOURCE[cls]):
+            return rec["bytes_per_launch"]
+    return None
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str, workload: str) -> None:
+    """Write profiles/traffic.json from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of
+    `bench.py --copy-calibration`: each counter is scaled by what it reads for the 256 MiB device copy."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        acc = defaultdict(list)
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") == counter:
+                    acc[row["Kernel_Name"]].append(float(row["Counter_Value"]) * 1024.0)
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    copy = [k for k in fetch if "copyBuffer" in k and fetch[k] > COPY_BYTES / 2]
+    if not copy:
+        raise SystemExit("no calibration copy kernel in the counter runs (run bench.py with --copy-calibration)")
+    cf, cw = COPY_BYTES / fetch[copy[0]], COPY_BYTES / write[copy[0]]
+    out = {"workload": workload, "calibration": {"kernel": copy[0], "bytes": COPY_BYTES, "fetch_factor": cf,
+                                                  "write_factor": cw},
+           "kernels": {}}
+    for name in fetch:
+        src = "trsv.hip" if "k_trsv" in name else "krylov.hip" if ("k_spmv" in name or "k_mgs" in name) else None
+        if src is None:
+            continue
+        fb, wb = fetch[name] * cf, write.get(name, 0.0) * cw
+        out["kernels"][name] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
+                                "source_sha": source_hash(src)}
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    print(json.dumps(out["calibration"]))
 
 
 def cpu_baseline(A, b, part, nparts, opts, rtol, restart, gpu_iters, sample_iters):
@@ -77,7 +151,14 @@ def main():
     ap.add_argument("--workload", default="aniso3d_128_slab16", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=5)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 256 MiB device copy before the steps (scale for counter runs)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc counter files and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the subdomains of this solver live on one "
               "device at their real per-GPU shape and no multi-GPU path is built.", file=sys.stderr)
@@ -103,6 +184,12 @@ def main():
         P.close()
         return out
 
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -136,8 +223,12 @@ def main():
     roof = None
     if dom:
         d = kstats[dom]
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(d["gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(d["gbs"] / HBM_PEAK_GBS, 5), "traffic": None,
+        P = silu.setup(Ad, pd, nparts, **opts)
+        sched = [int(v) for v in P.export("schedule")]
+        P.close()
+        roof = {"kernel": dom, "instance": kernel_instance(dom, sched), "bound": "hbm",
+                "achieved": round(d["gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(d["gbs"] / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom, sched),
                 "avg_launch_us": round(d["avg_us"], 3), "bytes_per_launch": d["bytes_per_launch"],
                 "launches": d["launches"]}
 

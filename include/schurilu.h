@@ -173,7 +173,10 @@ const char *ilu_last_error(void);
  *   20 W (interface rows, interior cols), 23 L_S, 26 U_S (interface numbering),
  *   30 C_off (interface rows, other subdomains' interface columns);
  *   16 diag of U_B [double n_B], 29 diag of U_S [double n_S];
- *   40..43 level of each row of L_B, U_B, L_S, U_S [int32].
+ *   40..43 level of each row of L_B, U_B, L_S, U_S [int32];
+ *   44 schedule of the L_B, U_B, L_S, U_S solves [int32 16]: for each, 1 if
+ *      solved block-locally (one workgroup per subdomain), lanes per row,
+ *      entries per lane, threads per workgroup.
  */
 int ilu_export(ilu_precond_t *P, int32_t what, void *h_buf, int64_t *len);
 

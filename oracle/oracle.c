@@ -16,8 +16,30 @@
  *                                 Schur factors, solved by a few GMRES steps
  *   Section 4.1                   right-preconditioned flexible GMRES(m)
  *
- * Readings where the paper is silent are listed in the design doc of the
- * repository (ILUT norm and per-part fill limit, tie-breaks, stopping rules).
+ * Where the paper is silent this file reads it as follows:
+ *  - a row is an interface row when it is coupled to another subdomain in
+ *    either direction (the pattern is symmetrised), so E and F are block
+ *    diagonal;
+ *  - each subdomain keeps its rows in their original order, interior rows
+ *    first; globally all interiors (subdomain-major), then all interfaces;
+ *  - ILUT: tau_i = droptol * ||a_i||_2 (norm of the original row, summed in
+ *    column order); an L entry below tau_i is dropped when it is reached as
+ *    a pivot, other entries after the elimination; at most lfil entries are
+ *    kept in the L part and, separately, in the U part (the Schur part of a
+ *    partially eliminated row counts as its U part), ranked by |v|
+ *    descending, then column ascending; the diagonal is always kept;
+ *  - the interface factor of the two-level method is taken of the Schur
+ *    rows left by the partial factorization, and preconditions the reduced
+ *    system as in eq. (18)-(19);
+ *  - the inner GMRES starts from zero and takes a fixed number of steps
+ *    (stopping early only on breakdown or an optional relative tolerance);
+ *    zero steps means one application of the interface factors;
+ *  - pivots: a zero or non-finite pivot is an error unless perturbation is
+ *    asked for, which replaces |u_ii| < tol * max_j |a_ij| by
+ *    +-tol * max_j |a_ij| (sign of u_ii, + for 0);
+ *  - FGMRES: modified Gram-Schmidt, Givens rotations with
+ *    r = sqrt(fma(a, a, b*b)), convergence on |g_{j+1}| <= rtol ||b||
+ *    confirmed by the true residual, iterations counted over restarts.
  */
 #include "oracle.h"
 

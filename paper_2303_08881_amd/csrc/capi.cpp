@@ -161,7 +161,7 @@ struct Schedule {
   // fixed-stride storage of the factor for the block-local solve
   int32_t *lds_c = nullptr, *lds_rec = nullptr, *lds_ri = nullptr;
   double *lds_v = nullptr;
-  int32_t lds_g = 1, lds_bt = 64;
+  int32_t lds_g = 1, lds_e = 4, lds_bt = 64;
   int64_t ext_col = 0;               // dependency columns of the block-local solve are < ext_col
   int64_t nloc = 0;                  // rows in the block-local solve; rows nloc.. follow in one pass
   const int32_t *rhs_map = nullptr;  // gather map baked into lds_ri
@@ -560,14 +560,17 @@ static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, in
     int32_t hm[2] = {0, 0};
     HIPCK(hipMemcpyAsync(hm, dm, sizeof(hm), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
-    int G = 1;
-    while (G < 8 && 4 * G < hm[0]) G *= 2;
-    if ((nloc + 1) * (int64_t)G * 4 >= ((int64_t)1 << 30))
+    // entries per lane E and lanes per row G: one lane of 4 for short rows,
+    // else lanes of 8, as few as cover the longest row (at most 8 lanes)
+    int G = 1, E = hm[0] <= 4 ? 4 : 8;
+    while (E == 8 && G < 8 && 8 * G < hm[0]) G *= 2;
+    if ((nloc + 1) * (int64_t)G * E >= ((int64_t)1 << 30))
       return fail(ILU_ERR_INVALID_ARG, "%s: factor too large for the block solve", phase);
     int64_t bt = ((int64_t)std::max(hm[1], 1) * G + 63) / 64 * 64;
     S.lds_g = G;
+    S.lds_e = E;
     S.lds_bt = (int32_t)std::min<int64_t>(bt, 512);
-    const int64_t ne = (nloc + 1) * G * 4;
+    const int64_t ne = (nloc + 1) * G * E;
     RC(mem.alloc(&S.lds_c, ne));
     RC(mem.alloc(&S.lds_v, ne));
     RC(mem.alloc(&S.lds_rec, 4 * (nloc + 1)));
@@ -575,7 +578,7 @@ static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, in
     S.rhs_map = rhs_map;
     S.sct_map = sct_map;
     S.ext_col = ext_col;
-    RC(launch_lds_fill(S.blk_rows, T.rp, T.ci, T.v, diag, nloc, ext_col, pos, S.blk_lev_ptr, (int64_t)nkeys, G, rhs_map,
+    RC(launch_lds_fill(S.blk_rows, T.rp, T.ci, T.v, diag, nloc, ext_col, pos, S.blk_lev_ptr, (int64_t)nkeys, G * E, rhs_map,
                        sct_map, S.lds_c, S.lds_v, S.lds_rec, S.lds_ri, s));
     HIPCK(hipStreamSynchronize(s));
     S.use_block = true;
@@ -639,6 +642,7 @@ static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, i
     t.lds_rec = S.lds_rec;
     t.lds_ri = S.lds_ri;
     t.lds_g = S.lds_g;
+    t.lds_e = S.lds_e;
     t.lds_bt = S.lds_bt;
     t.split_col = S.ext_col;
     t.nrows = S.nloc;
@@ -1230,6 +1234,24 @@ int ilu_export(ilu_precond_t *P, int32_t what, void *h, int64_t *len) {
     case 41: return export_raw(P->sU1.level_of, nB, 4, h, len);
     case 42: return export_raw(P->sLS.level_of, nS, 4, h, len);
     case 43: return export_raw(P->sUS.level_of, nS, 4, h, len);
+    case 44: {  // schedule of the four solves: {block-local, lanes per row, entries per lane, threads} each
+      const Schedule *sch[4] = {&P->sL1, &P->sU1, &P->sLS, &P->sUS};
+      int32_t v[16];
+      for (int k = 0; k < 4; k++) {
+        v[4 * k] = sch[k]->use_block ? 1 : 0;
+        v[4 * k + 1] = sch[k]->lds_g;
+        v[4 * k + 2] = sch[k]->lds_e;
+        v[4 * k + 3] = sch[k]->lds_bt;
+      }
+      if (!h) {
+        *len = 16;
+        return 0;
+      }
+      if (*len < 16) return fail(ILU_ERR_INVALID_ARG, "export buffer too small");
+      *len = 16;
+      memcpy(h, v, sizeof(v));
+      return 0;
+    }
     default: break;
   }
   if (what >= 10 && what <= 12) return export_split(P->L1, 0, nB, 0, nB, 0, what - 10, h, len);

@@ -131,11 +131,12 @@ struct TrsvLaunch {
   const int32_t *blk_rows;     // rows sorted by (block, level)
   const int32_t *blk_lev_ptr;  // [nblk * nlev_blk + 1]
   // block-local storage (launch_trsv_lds): fixed-stride dependency entries
-  const int32_t *lds_c;    // [(nrows + 1) * 4G] window slots
-  const double *lds_v;     // [(nrows + 1) * 4G]
+  const int32_t *lds_c;    // [(nrows + 1) * G * E] window slots
+  const double *lds_v;     // [(nrows + 1) * G * E]
   const int32_t *lds_rec;  // int4 per position (+ dummy)
   const int32_t *lds_ri;   // rhs index per position (+ dummy)
-  int32_t lds_g;           // lanes per row: 1, 2, 4 or 8
+  int32_t lds_g;           // lanes per row: 1 (E = 4), or 1, 2, 4, 8 (E = 8)
+  int32_t lds_e;           // entries per lane: 4 or 8
   int32_t lds_bt;          // threads per workgroup (multiple of 64, <= 512)
 };
 int launch_trsv(const TrsvLaunch &t, hipStream_t s);
@@ -153,7 +154,7 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
                        const int32_t *lev_ptr, int64_t nseg, int32_t *pos, int32_t *maxent, int32_t *maxw,
                        hipStream_t s);
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
-                    int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G,
+                    int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int width,
                     const int32_t *rhs_map, const int32_t *sct_map, int32_t *oc, double *ov, int32_t *rec,
                     int32_t *ri, hipStream_t s);
 // block id of each row from ascending block starts (s1 below split, s2 from split on; s2 may be NULL)

@@ -109,30 +109,32 @@ __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
 //
 // Storage (built at setup, "position" = index in that order):
 //   ent_c/ent_v  the dependency entries of each position at a fixed stride of
-//                4G (G = 1, 2, 4 or 8): column order, each column replaced by
-//                the slot of its position in the LDS solution window,
-//                padded with the window's zero slot and 0.0;
+//                G*E (G lanes per row of E = 4 or 8 entries each): column
+//                order, each column replaced by the slot of its position in
+//                the LDS solution window, padded with the window's zero slot
+//                and 0.0;
 //   rec          {row (or ~row for a slow row), scatter index, diagonal};
 //   rhs_idx      index of the row's right-hand side in b.
-// A row is handled by G consecutive lanes, lane g summing entries 4g..4g+3
-// with fma (lane 0 starting from the right-hand side); the G partial sums
-// are combined pairwise across lanes (fixed order, so results are
-// reproducible run to run; the sum order differs from the sequential one by
-// rounding only) and the diagonal divides once.
+// A row is handled by G consecutive lanes, lane g summing entries
+// gE..gE+E-1 with fma (lane 0 starting from the right-hand side); the G
+// partial sums are combined pairwise across lanes (fixed order, so results
+// are reproducible run to run; the sum order differs from the sequential one
+// by rounding only) and the diagonal divides once.
 //
 // Latency is the whole cost of this solve (a level holds tens of rows), so
-// every load is issued eight levels before its use: each thread keeps eight
-// register sets that rotate by unrolling the level loop eight times, and the
-// right-hand-side index is loaded eight levels before the right-hand side it
-// locates.  All pipeline addresses come from the level pointers in LDS --
-// none depends on a load of the same pipeline stage -- and every pipeline
-// load is unconditional (idle lanes read a dummy position), so the number of
-// memory operations between a load and its use is fixed: the compiler's
-// in-order waits before level l then cover only level l's own loads.  Six
-// loads per level keep 48 in flight, under the 63 that the counter tracks.
+// every load is issued LOOK levels before its use (LOOK = 8 for E = 4, 6 for
+// E = 8): each thread keeps LOOK register sets that rotate by unrolling the
+// level loop LOOK times, and the right-hand-side index is loaded LOOK levels
+// before the right-hand side it locates.  All pipeline addresses come from
+// the level pointers in LDS -- none depends on a load of the same pipeline
+// stage -- and every pipeline load is unconditional (idle lanes read a dummy
+// position), so the number of memory operations between a load and its use
+// is fixed: the compiler's in-order waits before level l then cover only
+// level l's own loads.  3 + 3E/4 loads per level keep LOOK times that many
+// in flight, under the 63 that the counter tracks.
 //
 // The solution of the last XWIN positions lives in an LDS ring.  Rows with
-// more than 4G entries, with a dependency older than the ring, or beyond
+// more than G*E entries, with a dependency older than the ring, or beyond
 // blockDim/G rows in their level are "slow": they are summed sequentially in
 // column order from the natural-order factor and solution (written by this
 // workgroup before an earlier barrier).  Columns outside the solve (the Z
@@ -144,11 +146,16 @@ __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
 constexpr int XWIN = 8192;            // solution window (positions), power of two
 constexpr int BT_MAX = 512;           // threads per block-local solve
 constexpr int BT_LDS_LEVELS = 16384;  // level pointers kept in LDS
-constexpr int LOOK = 8;               // pipeline depth in levels
+constexpr int LOOK_MAX = 8;
+
+template <int E>
+constexpr int look_of() {
+  return E == 8 ? 6 : 8;
+}
 
 struct LdsTrsvArgs {
-  const int4 *ent_c;       // [(npos + 1) * G] four window slots
-  const double2 *ent_v;    // [(npos + 1) * G * 2]
+  const int4 *ent_c;       // [(npos + 1) * G * E / 4] window slots
+  const double2 *ent_v;    // [(npos + 1) * G * E / 2]
   const int4 *rec;         // [npos + 1]
   const int32_t *rhs_idx;  // [npos + 1]
   const int32_t *lev_ptr;  // [nblk * nlev + 1]
@@ -166,9 +173,10 @@ struct LdsTrsvArgs {
   const int32_t *smap;
 };
 
+template <int E>
 struct PSet {
-  int4 c;
-  double2 w0, w1;
+  int4 c[E / 4];
+  double2 w[E / 2];
   int4 rec;
   double rhs;
 };
@@ -209,48 +217,58 @@ __device__ __forceinline__ double slow_row(const LdsTrsvArgs &a, int32_t r, int3
 
 // Load the pipeline set of the row handled by this lane in a level whose
 // positions are [lo, hi) (idle lanes read the dummy position).
-template <int G>
+template <int G, int E>
 __device__ __forceinline__ void refill(const LdsTrsvArgs &a, int32_t lo, int32_t hi, int32_t j, int32_t g, int32_t ri,
-                                       PSet &E) {
+                                       PSet<E> &S) {
   const int32_t q = lo + j;
   const int32_t qc = q < hi ? q : a.npos;
   const int32_t e = qc * G + g;
-  E.c = a.ent_c[e];
-  E.w0 = a.ent_v[2 * e];
-  E.w1 = a.ent_v[2 * e + 1];
-  E.rec = a.rec[qc];
-  E.rhs = a.b[ri];
+#pragma unroll
+  for (int i = 0; i < E / 4; i++) S.c[i] = a.ent_c[e * (E / 4) + i];
+#pragma unroll
+  for (int i = 0; i < E / 2; i++) S.w[i] = a.ent_v[e * (E / 2) + i];
+  S.rec = a.rec[qc];
+  S.rhs = a.b[ri];
 }
 __device__ __forceinline__ int32_t load_ri(const LdsTrsvArgs &a, int32_t lo, int32_t hi, int32_t j) {
   const int32_t q = lo + j;
   return a.rhs_idx[q < hi ? q : a.npos];
 }
 
-template <int G, bool DIAG, bool SCAT>
+template <int G, int E, bool DIAG, bool SCAT>
 __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, double *win, const int32_t *lp, int32_t l, int32_t j,
-                                      int32_t g, PSet &E, int32_t &RI) {
+                                      int32_t g, PSet<E> &S, int32_t &RI) {
+  constexpr int LOOK = look_of<E>();
   // every LDS read of the step first, so that a single wait covers them: the
-  // bounds of levels l, l + LOOK, l + 2 LOOK and the four window values
+  // bounds of levels l, l + LOOK, l + 2 LOOK and the window values
   const int32_t q0 = lp[l], q1 = lp[l + 1];
   const int32_t f0 = lp[l + LOOK], f1 = lp[l + LOOK + 1];
   const int32_t i0 = lp[l + 2 * LOOK], i1 = lp[l + 2 * LOOK + 1];
-  const double x0 = win[E.c.x], x1 = win[E.c.y], x2 = win[E.c.z], x3 = win[E.c.w];
+  double xv[E];
+#pragma unroll
+  for (int i = 0; i < E / 4; i++) {
+    xv[4 * i] = win[S.c[i].x];
+    xv[4 * i + 1] = win[S.c[i].y];
+    xv[4 * i + 2] = win[S.c[i].z];
+    xv[4 * i + 3] = win[S.c[i].w];
+  }
   const int32_t q = q0 + j;
   const bool mine = q < q1;
-  double s = g == 0 ? E.rhs : 0.0;
-  s = fma(-E.w0.x, x0, s);
-  s = fma(-E.w0.y, x1, s);
-  s = fma(-E.w1.x, x2, s);
-  s = fma(-E.w1.y, x3, s);
+  double s = g == 0 ? S.rhs : 0.0;
+#pragma unroll
+  for (int i = 0; i < E / 2; i++) {
+    s = fma(-S.w[i].x, xv[2 * i], s);
+    s = fma(-S.w[i].y, xv[2 * i + 1], s);
+  }
   s = group_sum<G>(s);
-  const bool slow = E.rec.x < 0;
-  const int32_t r = slow ? ~E.rec.x : E.rec.x;
-  if (DIAG) s = s / rec_diag(E.rec);
-  if (mine && slow) s = slow_row<DIAG, SCAT>(a, r, a.rhs_idx[q], rec_diag(E.rec));
+  const bool slow = S.rec.x < 0;
+  const int32_t r = slow ? ~S.rec.x : S.rec.x;
+  if (DIAG) s = s / rec_diag(S.rec);
+  if (mine && slow) s = slow_row<DIAG, SCAT>(a, r, a.rhs_idx[q], rec_diag(S.rec));
   if (mine && g == 0) {
     win[q & (XWIN - 1)] = s;
     if (SCAT)
-      a.scatter_out[E.rec.y] = s;
+      a.scatter_out[S.rec.y] = s;
     else
       a.x[r] = s;
   }
@@ -268,99 +286,73 @@ __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, double *win, const i
     __builtin_amdgcn_s_waitcnt(0);
   }
   __syncthreads();  // also for an empty level: the step stays branch-free
-  refill<G>(a, f0, f1, j, g, RI, E);  // RI holds the rhs index of level l + LOOK
+  refill<G, E>(a, f0, f1, j, g, RI, S);  // RI holds the rhs index of level l + LOOK
   // keep the next index load after the last use of RI, so both live in the
   // same register (otherwise the loop carries a copy that waits for the load)
   __builtin_amdgcn_sched_barrier(0);
   RI = load_ri(a, i0, i1, j);
 }
 
-template <int G, bool DIAG, bool SCAT>
+template <int G, int E, bool DIAG, bool SCAT>
 __global__ void __launch_bounds__(BT_MAX) k_trsv_lds(LdsTrsvArgs a) {
+  constexpr int LOOK = look_of<E>();
   __shared__ double win[XWIN + 1];  // slot XWIN stays 0.0: the target of padding entries
-  __shared__ int32_t lp[BT_LDS_LEVELS + 2 * LOOK + 10];
+  __shared__ int32_t lp[BT_LDS_LEVELS + 3 * LOOK_MAX + 2];
   const int64_t base = (int64_t)blockIdx.x * a.nlev;
   const int32_t tid = (int32_t)threadIdx.x;
   const int32_t nlev = a.nlev;
   for (int32_t l = tid; l <= nlev; l += a.bt) lp[l] = a.lev_ptr[base + l];
   for (int32_t k = tid; k <= XWIN; k += a.bt) win[k] = 0.0;
   __syncthreads();
-  if (tid < 2 * LOOK + 9) lp[nlev + 1 + tid] = lp[nlev];  // empty levels past the end
+  if (tid < 3 * LOOK + 1) lp[nlev + 1 + tid] = lp[nlev];  // empty levels past the end
   __syncthreads();
-  // the loop runs a multiple of eight levels (the extra ones are empty), so
-  // it has a single exit and the compiler keeps the eight steps in order
   const int32_t j = tid / G, g = tid % G;
-  PSet E0, E1, E2, E3, E4, E5, E6, E7;
-  int32_t R0, R1, R2, R3, R4, R5, R6, R7;
-  // Prologue in the loop's own load order (E0 R0 E1 R1 ... E7 R7, pinned by
+  PSet<E> S[LOOK];
+  int32_t R[LOOK];
+  // Prologue in the loop's own load order (S0 R0 S1 R1 ..., pinned by
   // scheduling barriers): the compiler merges the state at loop entry with
   // the state at the back edge, and any load that looked more recent at entry
   // would be waited for on every iteration.
   {
-    const int32_t t0 = load_ri(a, lp[0], lp[1], j), t1 = load_ri(a, lp[1], lp[2], j), t2 = load_ri(a, lp[2], lp[3], j),
-                  t3 = load_ri(a, lp[3], lp[4], j), t4 = load_ri(a, lp[4], lp[5], j), t5 = load_ri(a, lp[5], lp[6], j),
-                  t6 = load_ri(a, lp[6], lp[7], j), t7 = load_ri(a, lp[7], lp[8], j);
-    refill<G>(a, lp[0], lp[1], j, g, t0, E0);
-    __builtin_amdgcn_sched_barrier(0);
-    R0 = load_ri(a, lp[8], lp[9], j);
-    __builtin_amdgcn_sched_barrier(0);
-    refill<G>(a, lp[1], lp[2], j, g, t1, E1);
-    __builtin_amdgcn_sched_barrier(0);
-    R1 = load_ri(a, lp[9], lp[10], j);
-    __builtin_amdgcn_sched_barrier(0);
-    refill<G>(a, lp[2], lp[3], j, g, t2, E2);
-    __builtin_amdgcn_sched_barrier(0);
-    R2 = load_ri(a, lp[10], lp[11], j);
-    __builtin_amdgcn_sched_barrier(0);
-    refill<G>(a, lp[3], lp[4], j, g, t3, E3);
-    __builtin_amdgcn_sched_barrier(0);
-    R3 = load_ri(a, lp[11], lp[12], j);
-    __builtin_amdgcn_sched_barrier(0);
-    refill<G>(a, lp[4], lp[5], j, g, t4, E4);
-    __builtin_amdgcn_sched_barrier(0);
-    R4 = load_ri(a, lp[12], lp[13], j);
-    __builtin_amdgcn_sched_barrier(0);
-    refill<G>(a, lp[5], lp[6], j, g, t5, E5);
-    __builtin_amdgcn_sched_barrier(0);
-    R5 = load_ri(a, lp[13], lp[14], j);
-    __builtin_amdgcn_sched_barrier(0);
-    refill<G>(a, lp[6], lp[7], j, g, t6, E6);
-    __builtin_amdgcn_sched_barrier(0);
-    R6 = load_ri(a, lp[14], lp[15], j);
-    __builtin_amdgcn_sched_barrier(0);
-    refill<G>(a, lp[7], lp[8], j, g, t7, E7);
-    __builtin_amdgcn_sched_barrier(0);
-    R7 = load_ri(a, lp[15], lp[16], j);
-    __builtin_amdgcn_sched_barrier(0);
+    int32_t t[LOOK];
+#pragma unroll
+    for (int k = 0; k < LOOK; k++) t[k] = load_ri(a, lp[k], lp[k + 1], j);
+#pragma unroll
+    for (int k = 0; k < LOOK; k++) {
+      refill<G, E>(a, lp[k], lp[k + 1], j, g, t[k], S[k]);
+      __builtin_amdgcn_sched_barrier(0);
+      R[k] = load_ri(a, lp[k + LOOK], lp[k + LOOK + 1], j);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
-  // eight levels per iteration: the compiler tracks outstanding loads exactly
-  // inside straight-line code, and the register sets keep their names
-  for (int32_t l = 0; l < nlev; l += 8) {
-    pstep<G, DIAG, SCAT>(a, win, lp, l, j, g, E0, R0);
-    pstep<G, DIAG, SCAT>(a, win, lp, l + 1, j, g, E1, R1);
-    pstep<G, DIAG, SCAT>(a, win, lp, l + 2, j, g, E2, R2);
-    pstep<G, DIAG, SCAT>(a, win, lp, l + 3, j, g, E3, R3);
-    pstep<G, DIAG, SCAT>(a, win, lp, l + 4, j, g, E4, R4);
-    pstep<G, DIAG, SCAT>(a, win, lp, l + 5, j, g, E5, R5);
-    pstep<G, DIAG, SCAT>(a, win, lp, l + 6, j, g, E6, R6);
-    pstep<G, DIAG, SCAT>(a, win, lp, l + 7, j, g, E7, R7);
+  // LOOK levels per iteration, a whole number of iterations (the extra levels
+  // are empty): the loop has a single exit, the compiler keeps the steps in
+  // order and the register sets keep their names
+  for (int32_t l = 0; l < nlev; l += LOOK) {
+#pragma unroll
+    for (int k = 0; k < LOOK; k++) pstep<G, E, DIAG, SCAT>(a, win, lp, l + k, j, g, S[k], R[k]);
   }
 }
 
 template <bool DIAG, bool SCAT>
-static void launch_g(int G, unsigned grid, unsigned bt, const LdsTrsvArgs &a, hipStream_t s) {
+static void launch_ge(int G, int E, unsigned grid, unsigned bt, const LdsTrsvArgs &a, hipStream_t s) {
+  if (E == 4) {
+    k_trsv_lds<1, 4, DIAG, SCAT><<<grid, bt, 0, s>>>(a);
+    return;
+  }
   switch (G) {
-    case 1: k_trsv_lds<1, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
-    case 2: k_trsv_lds<2, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
-    case 4: k_trsv_lds<4, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
-    default: k_trsv_lds<8, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
+    case 1: k_trsv_lds<1, 8, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
+    case 2: k_trsv_lds<2, 8, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
+    case 4: k_trsv_lds<4, 8, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
+    default: k_trsv_lds<8, 8, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
   }
 }
 
 int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s) {
   if (t.nblk == 0 || t.nrows == 0) return 0;
-  if (t.nlev_blk > BT_LDS_LEVELS || t.lds_bt < 64 || t.lds_bt > BT_MAX || t.lds_bt % 64 != 0 ||
-      (t.lds_g != 1 && t.lds_g != 2 && t.lds_g != 4 && t.lds_g != 8))
+  const bool ge_ok = (t.lds_e == 4 && t.lds_g == 1) ||
+                     (t.lds_e == 8 && (t.lds_g == 1 || t.lds_g == 2 || t.lds_g == 4 || t.lds_g == 8));
+  if (t.nlev_blk > BT_LDS_LEVELS || t.lds_bt < 64 || t.lds_bt > BT_MAX || t.lds_bt % 64 != 0 || !ge_ok)
     return ILU_ERR_INVALID_ARG;
   LdsTrsvArgs a;
   a.ent_c = reinterpret_cast<const int4 *>(t.lds_c);
@@ -382,9 +374,9 @@ int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s) {
   const unsigned g = (unsigned)t.nblk, bt = (unsigned)t.lds_bt;
   switch (t.role) {
     case 0:
-    case 2: launch_g<false, false>(t.lds_g, g, bt, a, s); break;
-    case 1: launch_g<true, true>(t.lds_g, g, bt, a, s); break;
-    default: launch_g<true, false>(t.lds_g, g, bt, a, s); break;
+    case 2: launch_ge<false, false>(t.lds_g, t.lds_e, g, bt, a, s); break;
+    case 1: launch_ge<true, true>(t.lds_g, t.lds_e, g, bt, a, s); break;
+    default: launch_ge<true, false>(t.lds_g, t.lds_e, g, bt, a, s); break;
   }
   return check_launch("trsv_lds");
 }
@@ -415,11 +407,11 @@ __global__ void k_max_width(const int32_t *lev_ptr, int64_t nseg, int32_t *out) 
 // the end of q's level, which bounds what the LDS window still holds.
 __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v,
                            const double *diag, int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr,
-                           int64_t nseg, int G, const int32_t *rhs_map, const int32_t *sct_map, int32_t *oc,
+                           int64_t nseg, int width, const int32_t *rhs_map, const int32_t *sct_map, int32_t *oc,
                            double *ov, int4 *rec, int32_t *ri) {
   int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q > n) return;
-  const int64_t o = q * G * 4, cap = (int64_t)G * 4;
+  const int64_t o = q * width, cap = width;
   int64_t k = 0;
   if (q == n) {
     for (; k < cap; k++) {
@@ -475,10 +467,10 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
 }
 
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
-                    int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G,
+                    int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int width,
                     const int32_t *rhs_map, const int32_t *sct_map, int32_t *oc, double *ov, int32_t *rec,
                     int32_t *ri, hipStream_t s) {
-  k_lds_fill<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(rows, rp, ci, v, diag, n, split, pos, lev_ptr, nseg, G,
+  k_lds_fill<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(rows, rp, ci, v, diag, n, split, pos, lev_ptr, nseg, width,
                                                               rhs_map, sct_map, oc, ov, reinterpret_cast<int4 *>(rec),
                                                               ri);
   return check_launch("lds_fill");
