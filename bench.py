@@ -93,19 +93,23 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str) -> None:
     from collections import defaultdict
 
     def per_kernel(path, counter):
-        acc = defaultdict(list)
+        """Mean counter bytes per dispatch of each kernel, and the largest device-copy dispatch."""
+        acc, copy = defaultdict(list), 0.0
         with open(path) as f:
             for row in csv.DictReader(f):
                 if row.get("Counter_Name") == counter:
-                    acc[row["Kernel_Name"]].append(float(row["Counter_Value"]) * 1024.0)
-        return {k: sum(v) / len(v) for k, v in acc.items()}
+                    b = float(row["Counter_Value"]) * 1024.0
+                    acc[row["Kernel_Name"]].append(b)
+                    if "copyBuffer" in row["Kernel_Name"]:
+                        copy = max(copy, b)
+        return {k: sum(v) / len(v) for k, v in acc.items()}, copy
 
-    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
-    copy = [k for k in fetch if "copyBuffer" in k and fetch[k] > COPY_BYTES / 2]
-    if not copy:
-        raise SystemExit("no calibration copy kernel in the counter runs (run bench.py with --copy-calibration)")
-    cf, cw = COPY_BYTES / fetch[copy[0]], COPY_BYTES / write[copy[0]]
-    out = {"workload": workload, "calibration": {"kernel": copy[0], "bytes": COPY_BYTES, "fetch_factor": cf,
+    (fetch, cfb), (write, cwb) = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    if cfb < COPY_BYTES / 4 or cwb < COPY_BYTES / 4:
+        raise SystemExit("no calibration copy in the counter runs (run bench.py with --copy-calibration)")
+    cf, cw = COPY_BYTES / cfb, COPY_BYTES / cwb
+    out = {"workload": workload, "calibration": {"copy_bytes": COPY_BYTES, "fetch_counter_bytes": cfb,
+                                                  "write_counter_bytes": cwb, "fetch_factor": cf,
                                                   "write_factor": cw},
            "kernels": {}}
     for name in fetch:
