@@ -560,9 +560,9 @@ static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, in
     int32_t hm[2] = {0, 0};
     HIPCK(hipMemcpyAsync(hm, dm, sizeof(hm), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
-    // entries per lane E and lanes per row G: one lane of 4 for short rows,
-    // else lanes of 8, as few as cover the longest row (at most 8 lanes)
-    int G = 1, E = hm[0] <= 4 ? 4 : 8;
+    // entries per lane E and lanes per row G: one lane of 2 or 4 for short
+    // rows, else lanes of 8, as few as cover the longest row (at most 8)
+    int G = 1, E = hm[0] <= 2 ? 2 : hm[0] <= 4 ? 4 : 8;
     while (E == 8 && G < 8 && 8 * G < hm[0]) G *= 2;
     if ((nloc + 1) * (int64_t)G * E >= ((int64_t)1 << 30))
       return fail(ILU_ERR_INVALID_ARG, "%s: factor too large for the block solve", phase);

@@ -135,8 +135,8 @@ struct TrsvLaunch {
   const double *lds_v;     // [(nrows + 1) * G * E]
   const int32_t *lds_rec;  // int4 per position (+ dummy)
   const int32_t *lds_ri;   // rhs index per position (+ dummy)
-  int32_t lds_g;           // lanes per row: 1 (E = 4), or 1, 2, 4, 8 (E = 8)
-  int32_t lds_e;           // entries per lane: 4 or 8
+  int32_t lds_g;           // lanes per row: 1 (E = 2, 4), or 1, 2, 4, 8 (E = 8)
+  int32_t lds_e;           // entries per lane: 2, 4 or 8
   int32_t lds_bt;          // threads per workgroup (multiple of 64, <= 512)
 };
 int launch_trsv(const TrsvLaunch &t, hipStream_t s);

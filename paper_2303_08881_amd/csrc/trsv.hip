@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
 //
 // Storage (built at setup, "position" = index in that order):
 //   ent_c/ent_v  the dependency entries of each position at a fixed stride of
-//                G*E (G lanes per row of E = 4 or 8 entries each): column
+//                G*E (G lanes per row of E = 2, 4 or 8 entries each): column
 //                order, each column replaced by the slot of its position in
 //                the LDS solution window, padded with the window's zero slot
 //                and 0.0;
@@ -122,16 +122,16 @@ __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
 // by rounding only) and the diagonal divides once.
 //
 // Latency is the whole cost of this solve (a level holds tens of rows), so
-// every load is issued LOOK levels before its use (LOOK = 8 for E = 4, 6 for
-// E = 8): each thread keeps LOOK register sets that rotate by unrolling the
+// every load is issued LOOK levels before its use (LOOK = 10, 8, 6 for
+// E = 2, 4, 8): each thread keeps LOOK register sets that rotate by unrolling the
 // level loop LOOK times, and the right-hand-side index is loaded LOOK levels
 // before the right-hand side it locates.  All pipeline addresses come from
 // the level pointers in LDS -- none depends on a load of the same pipeline
 // stage -- and every pipeline load is unconditional (idle lanes read a dummy
 // position), so the number of memory operations between a load and its use
 // is fixed: the compiler's in-order waits before level l then cover only
-// level l's own loads.  3 + 3E/4 loads per level keep LOOK times that many
-// in flight, under the 63 that the counter tracks.
+// level l's own loads.  LOOK times the loads and the store of a level stay
+// under the 63 memory operations that the counter tracks.
 //
 // The solution of the last XWIN positions lives in an LDS ring.  Rows with
 // more than G*E entries, with a dependency older than the ring, or beyond
@@ -146,11 +146,14 @@ __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
 constexpr int XWIN = 8192;            // solution window (positions), power of two
 constexpr int BT_MAX = 512;           // threads per block-local solve
 constexpr int BT_LDS_LEVELS = 16384;  // level pointers kept in LDS
-constexpr int LOOK_MAX = 8;
+constexpr int LOOK_MAX = 10;
 
+// loads per level: E/4 (columns; one for E = 2) + E/2 (values; one for E = 2)
+// + record + right-hand side + its index, and one store: LOOK times that
+// stays within the 63 operations the counter tracks
 template <int E>
 constexpr int look_of() {
-  return E == 8 ? 6 : 8;
+  return E == 8 ? 6 : E == 4 ? 8 : 10;
 }
 
 struct LdsTrsvArgs {
@@ -173,9 +176,24 @@ struct LdsTrsvArgs {
   const int32_t *smap;
 };
 
+// window slots of a lane's entries: int2 for E = 2, E/4 int4 otherwise
+template <int E>
+struct Cols {
+  int4 v[E / 4];
+  __device__ __forceinline__ int32_t get(int k) const {
+    const int4 &q = v[k / 4];
+    return (k & 3) == 0 ? q.x : (k & 3) == 1 ? q.y : (k & 3) == 2 ? q.z : q.w;
+  }
+};
+template <>
+struct Cols<2> {
+  int2 v;
+  __device__ __forceinline__ int32_t get(int k) const { return k == 0 ? v.x : v.y; }
+};
+
 template <int E>
 struct PSet {
-  int4 c[E / 4];
+  Cols<E> c;
   double2 w[E / 2];
   int4 rec;
   double rhs;
@@ -223,8 +241,12 @@ __device__ __forceinline__ void refill(const LdsTrsvArgs &a, int32_t lo, int32_t
   const int32_t q = lo + j;
   const int32_t qc = q < hi ? q : a.npos;
   const int32_t e = qc * G + g;
+  if constexpr (E == 2) {
+    S.c.v = reinterpret_cast<const int2 *>(a.ent_c)[e];
+  } else {
 #pragma unroll
-  for (int i = 0; i < E / 4; i++) S.c[i] = a.ent_c[e * (E / 4) + i];
+    for (int i = 0; i < E / 4; i++) S.c.v[i] = a.ent_c[e * (E / 4) + i];
+  }
 #pragma unroll
   for (int i = 0; i < E / 2; i++) S.w[i] = a.ent_v[e * (E / 2) + i];
   S.rec = a.rec[qc];
@@ -246,12 +268,7 @@ __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, double *win, const i
   const int32_t i0 = lp[l + 2 * LOOK], i1 = lp[l + 2 * LOOK + 1];
   double xv[E];
 #pragma unroll
-  for (int i = 0; i < E / 4; i++) {
-    xv[4 * i] = win[S.c[i].x];
-    xv[4 * i + 1] = win[S.c[i].y];
-    xv[4 * i + 2] = win[S.c[i].z];
-    xv[4 * i + 3] = win[S.c[i].w];
-  }
+  for (int k = 0; k < E; k++) xv[k] = win[S.c.get(k)];
   const int32_t q = q0 + j;
   const bool mine = q < q1;
   double s = g == 0 ? S.rhs : 0.0;
@@ -336,6 +353,10 @@ __global__ void __launch_bounds__(BT_MAX) k_trsv_lds(LdsTrsvArgs a) {
 
 template <bool DIAG, bool SCAT>
 static void launch_ge(int G, int E, unsigned grid, unsigned bt, const LdsTrsvArgs &a, hipStream_t s) {
+  if (E == 2) {
+    k_trsv_lds<1, 2, DIAG, SCAT><<<grid, bt, 0, s>>>(a);
+    return;
+  }
   if (E == 4) {
     k_trsv_lds<1, 4, DIAG, SCAT><<<grid, bt, 0, s>>>(a);
     return;
@@ -350,7 +371,7 @@ static void launch_ge(int G, int E, unsigned grid, unsigned bt, const LdsTrsvArg
 
 int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s) {
   if (t.nblk == 0 || t.nrows == 0) return 0;
-  const bool ge_ok = (t.lds_e == 4 && t.lds_g == 1) ||
+  const bool ge_ok = ((t.lds_e == 2 || t.lds_e == 4) && t.lds_g == 1) ||
                      (t.lds_e == 8 && (t.lds_g == 1 || t.lds_g == 2 || t.lds_g == 4 || t.lds_g == 8));
   if (t.nlev_blk > BT_LDS_LEVELS || t.lds_bt < 64 || t.lds_bt > BT_MAX || t.lds_bt % 64 != 0 || !ge_ok)
     return ILU_ERR_INVALID_ARG;

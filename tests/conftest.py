@@ -10,7 +10,7 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
-    config.addinivalue_line("markers", "slow: larger CPU case")
+    config.addinivalue_line("markers", "slow: full-size case (tens of seconds)")
 
 
 @pytest.fixture(scope="session", autouse=True)

@@ -192,3 +192,74 @@ def test_edge_partitions(kind):
         r = synth.uniform_rhs(A.n, 4)
         np.testing.assert_allclose(Pg.apply(torch.as_tensor(r).cuda()).cpu().numpy(), Po.apply(r), rtol=1e-10,
                                    atol=1e-14)
+
+
+# ---- the 128^3 slab workload at full size, as the benchmark runs it ----
+SLAB_OPTS = dict(method=oracle.SCHUR, interior_fact=oracle.ILUT, interface_fact=oracle.MILU0, droptol=1e-3, lfil=20,
+                 inner_iters=10)
+
+
+@pytest.fixture(scope="module")
+def slab_full():
+    A, b, part, p = synth.workload("aniso3d_128_slab16")
+    print(f"[parity] full slab workload n={A.n} nnz={A.nnz}", flush=True)
+    P_o = oracle.Precond(A, part, p, **SLAB_OPTS)
+    m = silu()
+    Ad = m.DeviceCSR.from_host(A)
+    P_g = m.setup(Ad, torch.as_tensor(part).cuda(), p, **SLAB_OPTS)
+    torch.cuda.synchronize()
+    return A, b, part, p, P_o, Ad, P_g
+
+
+@pytest.mark.slow
+def test_full_slab_setup_matches(slab_full):
+    """Every integer output bit-exact and every factor within 1e-12 at n = 2,097,152, 16 subdomains."""
+    A, b, part, p, P_o, Ad, P_g = slab_full
+    for name in ("perm", "iperm", "iface", "offsets", "lev_LB", "lev_UB", "lev_LS", "lev_US"):
+        np.testing.assert_array_equal(P_g.export(name), P_o.export(name), err_msg=name)
+    for name in ("LB", "UB", "Z", "W", "LS", "US", "Coff"):
+        rg, cg, vg = P_g.csr(name)
+        ro, co, vo = P_o.csr(name)
+        np.testing.assert_array_equal(rg, ro, err_msg=f"{name} row_ptr")
+        np.testing.assert_array_equal(cg, co, err_msg=f"{name} col")
+        np.testing.assert_allclose(vg, vo, rtol=1e-12, atol=1e-12 * np.abs(vo).max(initial=1.0), err_msg=name)
+    for name in ("DB", "DS"):
+        np.testing.assert_allclose(P_g.export(name), P_o.export(name), rtol=1e-12, err_msg=name)
+    sched = P_g.export("schedule")
+    assert all(sched[4 * k] == 1 for k in range(4)), sched  # the benchmark's block-local solves
+
+
+@pytest.mark.slow
+def test_full_slab_apply_and_fgmres(slab_full):
+    A, b, part, p, P_o, Ad, P_g = slab_full
+    r = synth.uniform_rhs(A.n, 11)
+    zo = P_o.apply(r)
+    zg = P_g.apply(torch.as_tensor(r).cuda()).cpu().numpy()
+    np.testing.assert_allclose(zg, zo, rtol=1e-10, atol=1e-10 * np.abs(zo).max())
+    ro = oracle.fgmres(A, P_o, b, rtol=1e-8, restart=50, maxit=600)
+    rg = silu().fgmres(Ad, P_g, torch.as_tensor(b).cuda(), rtol=1e-8, restart=50, maxit=600)
+    assert ro["converged"] and rg["converged"]
+    assert abs(rg["iterations"] - ro["iterations"]) <= 1, (rg["iterations"], ro["iterations"])
+    xg = rg["x"].cpu().numpy()
+    assert np.linalg.norm(oracle.residual(A, b, xg)) / np.linalg.norm(b) <= 1e-8
+
+
+def test_runs_are_deterministic():
+    """Two setups of the same system give bitwise identical factors; two applies identical vectors."""
+    m = silu()
+    A = synth.aniso7(12, Nz=16)
+    part = synth.slab_partition(12, 4, Nz=16)
+    opts = dict(method=oracle.SCHUR, interior_fact=oracle.ILUT, interface_fact=oracle.MILU0, inner_iters=5,
+                **ILUT_OPTS)
+    Ad = m.DeviceCSR.from_host(A)
+    P1 = m.setup(Ad, part, 4, **opts)
+    P2 = m.setup(Ad, part, 4, **opts)
+    for name in ("LB", "UB", "Z", "W", "LS", "US"):
+        for a1, a2 in zip(P1.csr(name), P2.csr(name)):
+            assert np.array_equal(a1, a2), name
+    r = torch.as_tensor(synth.uniform_rhs(A.n, 3)).cuda()
+    z1 = P1.apply(r).cpu().numpy()
+    z2 = P1.apply(r).cpu().numpy()
+    z3 = P2.apply(r).cpu().numpy()
+    assert np.array_equal(z1.view(np.uint64), z2.view(np.uint64))
+    assert np.array_equal(z1.view(np.uint64), z3.view(np.uint64))
