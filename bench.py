@@ -154,7 +154,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="aniso3d_128_slab16", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=5)
+    ap.add_argument("--cpu-sample-iters", type=int, default=40)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device copy before the steps (scale for counter runs)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),

@@ -162,6 +162,9 @@ struct Schedule {
   int32_t *lds_c = nullptr, *lds_rec = nullptr, *lds_ri = nullptr;
   double *lds_v = nullptr;
   int32_t lds_g = 1, lds_e = 4, lds_bt = 64;
+  int32_t lds_helpers = 0;
+  unsigned long long *lds_prog = nullptr, lds_epoch = 0;
+  double *lds_sink = nullptr;
   int64_t ext_col = 0;               // dependency columns of the block-local solve are < ext_col
   int64_t nloc = 0;                  // rows in the block-local solve; rows nloc.. follow in one pass
   const int32_t *rhs_map = nullptr;  // gather map baked into lds_ri
@@ -569,6 +572,14 @@ static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, in
     int64_t bt = ((int64_t)std::max(hm[1], 1) * G + 63) / 64 * 64;
     S.lds_g = G;
     S.lds_e = E;
+    // one L2 prefetch helper per subdomain
+    S.lds_helpers = TRSV_HELPERS;
+    if (S.lds_helpers > 0) {
+      const int64_t hb = (S.nblk + 7) / 8 * 8;
+      RC(mem.alloc(&S.lds_prog, S.nblk));
+      RC(mem.alloc(&S.lds_sink, hb * (S.lds_helpers + 1)));
+      HIPCK(hipMemsetAsync(S.lds_prog, 0, sizeof(unsigned long long) * S.nblk, s));
+    }
     S.lds_bt = (int32_t)std::min<int64_t>(bt, 512);
     const int64_t ne = (nloc + 1) * G * E;
     RC(mem.alloc(&S.lds_c, ne));
@@ -644,6 +655,10 @@ static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, i
     t.lds_g = S.lds_g;
     t.lds_e = S.lds_e;
     t.lds_bt = S.lds_bt;
+    t.lds_helpers = S.lds_helpers;
+    t.lds_prog = S.lds_prog;
+    t.lds_epoch = ++S.lds_epoch;
+    t.lds_sink = S.lds_sink;
     t.split_col = S.ext_col;
     t.nrows = S.nloc;
     return timed(ILU_K_TRSV_LB + role, bytes, s, [&] {

@@ -32,6 +32,9 @@
 namespace silu {
 
 constexpr int FACT_CAP = 512;  // working-row capacity (entries) per wave
+constexpr int FACT_UCACHE = 768;  // LDS entries caching the U rows of a round's pivots (>= FACT_CAP, so a
+                                  // round's first pivot always fits)
+constexpr int FACT_UROW = 16;     // entries of a cached U row fetched by unrolled loads (the rest in a loop)
 
 struct FactArgs {
   const int64_t *rp;
@@ -131,13 +134,19 @@ __device__ int emit_part(const int32_t *wc, const double *wv, const uint8_t *wd,
   return out;
 }
 
-__global__ void __launch_bounds__(WAVE) k_factor_rows(FactArgs a) {
+__global__ void __launch_bounds__(WAVE, 2) k_factor_rows(FactArgs a) {
   __shared__ int32_t wc[FACT_CAP];
   __shared__ double wv[FACT_CAP];
   __shared__ uint8_t wd[FACT_CAP];
   __shared__ int32_t fins[WAVE];
   __shared__ int32_t fcol[WAVE];
   __shared__ double fval[WAVE];
+  // U rows of the pivots of the current round, and which slot holds whose
+  __shared__ uint8_t ws[FACT_CAP];  // slot of each working entry's cached pivot row
+  __shared__ double tD[WAVE];
+  __shared__ int32_t toff[WAVE], tlen[WAVE];
+  __shared__ int32_t cc[FACT_UCACHE];
+  __shared__ double cv[FACT_UCACHE];
   const int lane = lane_id();
   const bool ilut = a.method == ILU_FACT_ILUT;
   const bool milu = a.method == ILU_FACT_MILU0;
@@ -198,6 +207,13 @@ __global__ void __launch_bounds__(WAVE) k_factor_rows(FactArgs a) {
         // every pivot still ahead in the working row, then one acquire makes
         // all their rows visible.  A fill that becomes a pivot later (marked
         // by bit 1 of wd) starts the next round when it is reached.
+        //
+        // The round also fetches, all in parallel, the diagonal and the U row
+        // of the first WAVE pivots from pos on into an LDS cache (as many as
+        // fit), and tags their working entries with the slot; a pivot left
+        // out is marked like a new fill and starts the next round.  Every
+        // round re-caches all pivots from its position on, so no slot of an
+        // earlier round is read after being overwritten.
         if (first || uniform_i32((int)(wd[pos] & 2))) {
           first = false;
           bool ok = true;
@@ -214,11 +230,66 @@ __global__ void __launch_bounds__(WAVE) k_factor_rows(FactArgs a) {
             break;
           }
           fence_acquire();
+          const int x = pos + lane;
+          const int32_t kx = x < len ? wc[x] : 0x7fffffff;
+          const bool piv = kx < lim;  // the pivots ahead are a prefix of [pos, len)
+          double dk = 0.0;
+          int64_t ub = 0;
+          int ul = 0;
+          if (piv) {
+            dk = a.D[kx];
+            ub = a.Urp[kx];
+            ul = a.Ulen[kx];
+          }
+          // exclusive prefix sum of the row lengths over the lanes
+          int off = ul;
+          for (int o = 1; o < WAVE; o <<= 1) {
+            const int v = __shfl_up(off, o, WAVE);
+            if (lane >= o) off += v;
+          }
+          off -= ul;
+          const bool cached = piv && off + ul <= FACT_UCACHE;
+          // every load of the copy first, then the LDS stores
+          int32_t uc_[FACT_UROW];
+          double uv_[FACT_UROW];
+#pragma unroll
+          for (int q = 0; q < FACT_UROW; q++) {
+            if (cached && q < ul) {
+              uc_[q] = a.Uc[ub + q];
+              uv_[q] = a.Uv[ub + q];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < FACT_UROW; q++) {
+            if (cached && q < ul) {
+              cc[off + q] = uc_[q];
+              cv[off + q] = uv_[q];
+            }
+          }
+          for (int q = FACT_UROW; cached && q < ul; q++) {
+            cc[off + q] = a.Uc[ub + q];
+            cv[off + q] = a.Uv[ub + q];
+          }
+          if (cached) {
+            tD[lane] = dk;
+            toff[lane] = off;
+            tlen[lane] = ul;
+          }
           __syncthreads();
-          for (int x = pos + lane; x < len; x += WAVE) wd[x] &= (uint8_t)~2u;
+          if (x < len) {
+            if (cached) {
+              ws[x] = (uint8_t)lane;
+              wd[x] &= (uint8_t)~2u;
+            } else if (piv) {
+              wd[x] |= 2;
+            }
+          }
+          for (int y = pos + WAVE + lane; y < len; y += WAVE)
+            if (wc[y] < lim) wd[y] |= 2;
           __syncthreads();
         }
-        const double wk = uniform_f64(wv[pos] / a.D[k]);
+        const int slot = uniform_i32((int)ws[pos]);
+        const double wk = uniform_f64(wv[pos] / tD[slot]);
         if (ilut && fabs(wk) < tau) {
           __syncthreads();
           if (lane == 0) {
@@ -231,13 +302,13 @@ __global__ void __launch_bounds__(WAVE) k_factor_rows(FactArgs a) {
         __syncthreads();
         if (lane == 0) wv[pos] = wk;
         __syncthreads();
-        const int64_t ub = a.Urp[k];
-        const int ul = a.Ulen[k];
+        const int ub = uniform_i32(toff[slot]);
+        const int ul = uniform_i32(tlen[slot]);
         for (int base = 0; base < ul; base += WAVE) {
           const int j = base + lane;
           const bool have = j < ul;
-          const int32_t c = have ? a.Uc[ub + j] : 0x7fffffff;
-          const double u = have ? a.Uv[ub + j] : 0.0;
+          const int32_t c = have ? cc[ub + j] : 0x7fffffff;
+          const double u = have ? cv[ub + j] : 0.0;
           const int idx = have ? lower_bound_lds(wc, pos + 1, len, c) : len;
           const bool found = have && idx < len && wc[idx] == c;
           if (found) wv[idx] = fma(-wk, u, wv[idx]);
@@ -260,39 +331,48 @@ __global__ void __launch_bounds__(WAVE) k_factor_rows(FactArgs a) {
               fval[rk] = fma(-wk, u, 0.0);
             }
             __syncthreads();
-            // read every working entry after the pivot, then write it shifted
-            int32_t rc_[FACT_CAP / WAVE];
-            double rv_[FACT_CAP / WAVE];
-            uint8_t rd_[FACT_CAP / WAVE];
-            int np_[FACT_CAP / WAVE];
+            // Shift every working entry after the pivot to make room: the
+            // upper half of the slots first, each half read completely before
+            // it is written (destinations only move up and never cross).
+            constexpr int NS = FACT_CAP / WAVE, HS = NS / 2;
+#pragma unroll 1
+            for (int h = 1; h >= 0; h--) {
+              int32_t rc_[HS];
+              double rv_[HS];
+              uint8_t rd_[HS], rs_[HS];
+              int np_[HS];
 #pragma unroll
-            for (int q = 0; q < FACT_CAP / WAVE; q++) {
-              const int x = pos + 1 + q * WAVE + lane;
-              np_[q] = -1;
-              if (x < len) {
-                rc_[q] = wc[x];
-                rv_[q] = wv[x];
-                rd_[q] = wd[x];
-                // number of fills inserted at or before x
-                int lo = 0, hi = nf;
-                while (lo < hi) {
-                  int mid = (lo + hi) >> 1;
-                  if (fins[mid] <= x)
-                    lo = mid + 1;
-                  else
-                    hi = mid;
+              for (int qq = 0; qq < HS; qq++) {
+                const int x = pos + 1 + (h * HS + qq) * WAVE + lane;
+                np_[qq] = -1;
+                if (x < len) {
+                  rc_[qq] = wc[x];
+                  rv_[qq] = wv[x];
+                  rd_[qq] = wd[x];
+                  rs_[qq] = ws[x];
+                  // number of fills inserted at or before x
+                  int lo = 0, hi = nf;
+                  while (lo < hi) {
+                    int mid = (lo + hi) >> 1;
+                    if (fins[mid] <= x)
+                      lo = mid + 1;
+                    else
+                      hi = mid;
+                  }
+                  np_[qq] = x + lo;
                 }
-                np_[q] = x + lo;
               }
-            }
-            __syncthreads();
+              __syncthreads();
 #pragma unroll
-            for (int q = 0; q < FACT_CAP / WAVE; q++) {
-              if (np_[q] >= 0) {
-                wc[np_[q]] = rc_[q];
-                wv[np_[q]] = rv_[q];
-                wd[np_[q]] = rd_[q];
+              for (int qq = 0; qq < HS; qq++) {
+                if (np_[qq] >= 0) {
+                  wc[np_[qq]] = rc_[qq];
+                  wv[np_[qq]] = rv_[qq];
+                  wd[np_[qq]] = rd_[qq];
+                  ws[np_[qq]] = rs_[qq];
+                }
               }
+              __syncthreads();
             }
             if (lane < nf) {
               const int at = fins[lane] + lane;

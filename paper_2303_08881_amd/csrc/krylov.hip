@@ -74,20 +74,43 @@ __device__ double reduce_partials(const double *p) {
   return s;
 }
 
+// Vector passes take 16-byte loads (two elements) when every operand allows
+// it (VEC: n even, pointers 16-byte aligned); each thread still accumulates
+// its elements in a fixed order, so the partials are the same on every run.
+static bool vec2_ok(int64_t n, const void *a, const void *b, const void *c) {
+  auto al = [](const void *p) { return p == nullptr || ((uintptr_t)p & 15) == 0; };
+  return (n & 1) == 0 && al(a) && al(b) && al(c);
+}
+
+template <bool VEC>
 __global__ void __launch_bounds__(RED_THREADS) k_dot_partial(const double *x, const double *y, int64_t n,
                                                             double *partials) {
   double s = 0.0;
   const int64_t stride = (int64_t)RED_BLOCKS * RED_THREADS;
-  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += stride) s = fma(x[i], y[i], s);
+  const int64_t i0 = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x;
+  if (VEC) {
+    const double2 *x2 = reinterpret_cast<const double2 *>(x), *y2 = reinterpret_cast<const double2 *>(y);
+    for (int64_t i = i0; i < n / 2; i += stride) {
+      const double2 a = x2[i], b = y2[i];
+      s = fma(a.x, b.x, s);
+      s = fma(a.y, b.y, s);
+    }
+  } else {
+    for (int64_t i = i0; i < n; i += stride) s = fma(x[i], y[i], s);
+  }
   s = block_sum(s);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
 int launch_dot_partial(const double *x, const double *y, int64_t n, double *partials, hipStream_t s) {
-  k_dot_partial<<<RED_BLOCKS, RED_THREADS, 0, s>>>(x, y, n, partials);
+  if (vec2_ok(n, x, y, nullptr))
+    k_dot_partial<true><<<RED_BLOCKS, RED_THREADS, 0, s>>>(x, y, n, partials);
+  else
+    k_dot_partial<false><<<RED_BLOCKS, RED_THREADS, 0, s>>>(x, y, n, partials);
   return check_launch("dot_partial");
 }
 
+template <bool VEC, bool NEXT>
 __global__ void __launch_bounds__(RED_THREADS) k_mgs_step(double *w, const double *v_prev, const double *pp,
                                                          double *h_out, const double *v_next, int64_t n,
                                                          double *pn) {
@@ -103,10 +126,26 @@ __global__ void __launch_bounds__(RED_THREADS) k_mgs_step(double *w, const doubl
   const double h = sh;
   double s = 0.0;
   const int64_t stride = (int64_t)RED_BLOCKS * RED_THREADS;
-  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += stride) {
-    const double wi = fma(-h, v_prev[i], w[i]);
-    w[i] = wi;
-    s = fma(wi, v_next ? v_next[i] : wi, s);
+  const int64_t i0 = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x;
+  if (VEC) {
+    double2 *w2 = reinterpret_cast<double2 *>(w);
+    const double2 *p2 = reinterpret_cast<const double2 *>(v_prev), *n2 = reinterpret_cast<const double2 *>(v_next);
+    for (int64_t i = i0; i < n / 2; i += stride) {
+      double2 wi = w2[i];
+      const double2 vp = p2[i];
+      wi.x = fma(-h, vp.x, wi.x);
+      wi.y = fma(-h, vp.y, wi.y);
+      w2[i] = wi;
+      const double2 vn = NEXT ? n2[i] : wi;
+      s = fma(wi.x, vn.x, s);
+      s = fma(wi.y, vn.y, s);
+    }
+  } else {
+    for (int64_t i = i0; i < n; i += stride) {
+      const double wi = fma(-h, v_prev[i], w[i]);
+      w[i] = wi;
+      s = fma(wi, NEXT ? v_next[i] : wi, s);
+    }
   }
   s = block_sum(s);
   if (threadIdx.x == 0) pn[blockIdx.x] = s;
@@ -115,7 +154,19 @@ __global__ void __launch_bounds__(RED_THREADS) k_mgs_step(double *w, const doubl
 int launch_mgs_step(double *w, const double *v_prev, const double *partials_prev, double *h_out,
                     const double *v_next, int64_t n, double *partials_next, const int *stop, hipStream_t s) {
   (void)stop;
-  k_mgs_step<<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, v_prev, partials_prev, h_out, v_next, n, partials_next);
+  const bool vec = vec2_ok(n, w, v_prev, v_next);
+  if (vec && v_next)
+    k_mgs_step<true, true><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, v_prev, partials_prev, h_out, v_next, n,
+                                                              partials_next);
+  else if (vec)
+    k_mgs_step<true, false><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, v_prev, partials_prev, h_out, v_next, n,
+                                                               partials_next);
+  else if (v_next)
+    k_mgs_step<false, true><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, v_prev, partials_prev, h_out, v_next, n,
+                                                               partials_next);
+  else
+    k_mgs_step<false, false><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, v_prev, partials_prev, h_out, v_next, n,
+                                                                partials_next);
   return check_launch("mgs_step");
 }
 

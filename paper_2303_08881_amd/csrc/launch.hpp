@@ -138,7 +138,12 @@ struct TrsvLaunch {
   int32_t lds_g;           // lanes per row: 1 (E = 2, 4), or 1, 2, 4, 8 (E = 8)
   int32_t lds_e;           // entries per lane: 2, 4 or 8
   int32_t lds_bt;          // threads per workgroup (multiple of 64, <= 512)
+  int32_t lds_helpers;     // L2 prefetch workgroups per subdomain (0: none)
+  unsigned long long *lds_prog;  // [nblk] solver progress words
+  unsigned long long lds_epoch;  // distinct per launch
+  double *lds_sink;        // [grid] (never written with finite data)
 };
+constexpr int TRSV_HELPERS = 1;  // L2 prefetch workgroups per subdomain of a block-local solve
 int launch_trsv(const TrsvLaunch &t, hipStream_t s);
 int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s);
 // rows row0..n-1 of a unit lower factor whose dependencies are all solved:

@@ -174,6 +174,13 @@ struct LdsTrsvArgs {
   double *x;               // solution, natural order (not written by scatter roles)
   double *scatter_out;     // scatter roles: the solution of row r goes to scatter_out[smap[r]] only
   const int32_t *smap;
+  // L2 prefetch helpers (see k_trsv_lds): solvers are workgroups [0, nblk),
+  // helpers start at hbase (a multiple of 8, so a helper shares its
+  // solver's XCD and L2) with a stride of hbase per helper rank
+  int32_t nblk, hbase;
+  unsigned long long *prog;  // [nblk] (epoch << 32) | level the solver has reached
+  unsigned long long epoch;
+  double *sink;              // [nblk * helpers] keeps the prefetch loads alive
 };
 
 // window slots of a lane's entries: int2 for E = 2, E/4 int4 otherwise
@@ -310,11 +317,91 @@ __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, double *win, const i
   RI = load_ri(a, i0, i1, j);
 }
 
+// L2 prefetch helper: a workgroup on the solver's XCD that streams the
+// storage of the levels just ahead of the solver (entries, records,
+// right-hand-side indices and right-hand sides) through the shared L2, so
+// that the solver's own pipelined loads hit there.  It reads the solver's
+// published level, stays at most HELP_AHEAD levels ahead, issues HELP_BATCH
+// independent loads per thread before using any, and folds them into a sink
+// value so the loads are not removed.  It only reads; every wait is bounded,
+// and the solver never waits for it.
+constexpr int HELP_AHEAD = 32;
+constexpr int HELP_LEVELS = 4;  // levels per helper step
+constexpr int HELP_BATCH = 8;
+
+template <int G, int E>
+__device__ void help_prefetch(const LdsTrsvArgs &a, int32_t b) {
+  const int32_t tid = (int32_t)threadIdx.x;
+  const int32_t *lpg = a.lev_ptr + (int64_t)b * a.nlev;
+  const int4 *c4 = reinterpret_cast<const int4 *>(a.ent_c);
+  unsigned acc = 0;
+  double dacc = 0.0;
+  int32_t pf = 0;
+  long idle = 0;
+  while (pf < a.nlev) {
+    const unsigned long long pr = __hip_atomic_load(a.prog + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t lvl = (pr >> 32) == a.epoch ? (int32_t)(pr & 0xffffffffu) : -1;
+    const int32_t target = min(lvl + HELP_AHEAD, a.nlev);
+    if (pf >= target) {
+      if (++idle > (1L << 20)) break;
+      __builtin_amdgcn_s_sleep(2);
+      continue;
+    }
+    idle = 0;
+    const int32_t pe = min(target, pf + HELP_LEVELS);
+    const int32_t q0 = lpg[pf], q1 = lpg[pe];
+    // entries (as int4 and double2 words), records, right-hand-side indices
+    const int64_t nc4 = (int64_t)(q1 - q0) * G * E / 4, nv2 = (int64_t)(q1 - q0) * G * E / 2;
+    const int64_t c0 = (int64_t)q0 * G * E / 4, v0 = (int64_t)q0 * G * E / 2;
+    for (int64_t i = tid; i < nv2; i += (int64_t)a.bt * HELP_BATCH) {
+      double2 w[HELP_BATCH];
+      int4 c[HELP_BATCH];
+#pragma unroll
+      for (int k = 0; k < HELP_BATCH; k++) {
+        const int64_t ii = i + (int64_t)k * a.bt;
+        w[k] = ii < nv2 ? a.ent_v[v0 + ii] : make_double2(0.0, 0.0);
+        c[k] = ii < nc4 ? c4[c0 + ii] : make_int4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < HELP_BATCH; k++) {
+        dacc += w[k].x;
+        acc ^= (unsigned)c[k].x;
+      }
+    }
+    for (int32_t q = q0 + tid; q < q1; q += a.bt * HELP_BATCH) {
+      int4 rc[HELP_BATCH];
+      int32_t ri[HELP_BATCH];
+#pragma unroll
+      for (int k = 0; k < HELP_BATCH; k++) {
+        const int32_t qq = q + k * a.bt;
+        rc[k] = qq < q1 ? a.rec[qq] : make_int4(0, 0, 0, 0);
+        ri[k] = qq < q1 ? a.rhs_idx[qq] : -1;
+      }
+      double bv[HELP_BATCH];
+#pragma unroll
+      for (int k = 0; k < HELP_BATCH; k++) bv[k] = ri[k] >= 0 ? a.b[ri[k]] : 0.0;
+#pragma unroll
+      for (int k = 0; k < HELP_BATCH; k++) {
+        acc ^= (unsigned)rc[k].x;
+        dacc += bv[k];
+      }
+    }
+    pf = pe;
+  }
+  // never true for finite data; keeps the loads
+  if (acc == 0x9e3779b9u && dacc == -1.0) a.sink[blockIdx.x] = dacc;
+}
+
 template <int G, int E, bool DIAG, bool SCAT>
 __global__ void __launch_bounds__(BT_MAX) k_trsv_lds(LdsTrsvArgs a) {
   constexpr int LOOK = look_of<E>();
   __shared__ double win[XWIN + 1];  // slot XWIN stays 0.0: the target of padding entries
   __shared__ int32_t lp[BT_LDS_LEVELS + 3 * LOOK_MAX + 2];
+  if ((int32_t)blockIdx.x >= a.nblk) {
+    const int32_t i = (int32_t)blockIdx.x - a.hbase;
+    if (i >= 0 && i % a.hbase < a.nblk) help_prefetch<G, E>(a, i % a.hbase);
+    return;
+  }
   const int64_t base = (int64_t)blockIdx.x * a.nlev;
   const int32_t tid = (int32_t)threadIdx.x;
   const int32_t nlev = a.nlev;
@@ -346,6 +433,9 @@ __global__ void __launch_bounds__(BT_MAX) k_trsv_lds(LdsTrsvArgs a) {
   // are empty): the loop has a single exit, the compiler keeps the steps in
   // order and the register sets keep their names
   for (int32_t l = 0; l < nlev; l += LOOK) {
+    if (a.prog && tid == 0)  // the level reached, for the prefetch helpers
+      __hip_atomic_store(a.prog + blockIdx.x, (a.epoch << 32) | (unsigned long long)l, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
     for (int k = 0; k < LOOK; k++) pstep<G, E, DIAG, SCAT>(a, win, lp, l + k, j, g, S[k], R[k]);
   }
@@ -392,7 +482,14 @@ int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s) {
   a.scatter_out = t.scatter_out;
   a.smap = t.scatter_map;
   a.bt = t.lds_bt;
-  const unsigned g = (unsigned)t.nblk, bt = (unsigned)t.lds_bt;
+  a.nblk = (int32_t)t.nblk;
+  a.hbase = (int32_t)((t.nblk + 7) / 8 * 8);
+  a.prog = t.lds_helpers > 0 ? t.lds_prog : nullptr;
+  a.epoch = t.lds_epoch;
+  a.sink = t.lds_sink;
+  const unsigned g = (unsigned)(t.nblk + (t.lds_helpers > 0 ? (int64_t)a.hbase * t.lds_helpers + (a.hbase - t.nblk)
+                                                               : 0)),
+                 bt = (unsigned)t.lds_bt;
   switch (t.role) {
     case 0:
     case 2: launch_ge<false, false>(t.lds_g, t.lds_e, g, bt, a, s); break;
