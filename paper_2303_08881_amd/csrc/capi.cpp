@@ -953,16 +953,15 @@ static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t 
              [&] { return launch_spmv(P->Coff.rp, P->Coff.ci, P->Coff.v, nS, vj, P->it1, s); }));
     RC(trsv(P, P->sLS, P->LS, nullptr, 0, P->it1, nullptr, P->it2, nullptr, nullptr, s, 2));
     RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, P->it2, nullptr, P->it2, nullptr, nullptr, s, 3));
-    RC(launch_vec_sum(w, vj, P->it2, nS, s));
     double *pc = P->ipa, *pn = P->ipb;
-    RC(launch_dot_partial(w, V, nS, pc, s));
+    RC(launch_sum_dot(w, vj, P->it2, V, nS, pc, s));  // w = v_j + D^-1 C_off v_j, <w, v_0>
     for (int i = 0; i <= j; i++) {
       const double *vnext = i < j ? V + (int64_t)(i + 1) * nS : nullptr;
       RC(launch_mgs_step(w, V + (int64_t)i * nS, pc, P->iH + i + (int64_t)ldh * j, vnext, nS, pn, stop, s));
       std::swap(pc, pn);
     }
-    RC(launch_givens(P->iH, ldh, P->ics, P->isn, P->ig, j, pc, stop, nsteps, est, hn, beta, P->opt.inner_rtol, s));
-    RC(launch_scale_copy(w, nullptr, hn, w, nS, stop, s));
+    RC(launch_givens_scale(P->iH, ldh, P->ics, P->isn, P->ig, j, pc, stop, nsteps, est, hn, beta,
+                           P->opt.inner_rtol, w, nS, s));
   }
   RC(launch_backsolve(P->iH, ldh, P->ig, nsteps, P->ic, s));
   return launch_combine(y, V, nS, P->ic, nsteps, nS, false, s);
@@ -1079,8 +1078,7 @@ static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, doub
           }));
           std::swap(pc, pn);
         }
-        RC(launch_givens(w.H, ldh, w.cs, w.sn, w.g, j, pc, stop, nsteps, est, hn, bnorm, rtol, s));
-        RC(launch_scale_copy(wv, nullptr, hn, wv, n, stop, s));
+        RC(launch_givens_scale(w.H, ldh, w.cs, w.sn, w.g, j, pc, stop, nsteps, est, hn, bnorm, rtol, wv, n, s));
         its++;
         HIPCK(hipMemcpyAsync(P->host_pinned, est, sizeof(double), hipMemcpyDeviceToHost, s));
         int hstop = 0;

@@ -10,8 +10,9 @@
 // * Modified Gram-Schmidt runs as j+1 fused passes: pass i subtracts
 //   h_{i-1} v_{i-1} from w and forms the partial dot with v_i.
 // * The Hessenberg column update, Givens rotation and residual estimate run
-//   in one single-thread kernel; a device stop word lets the reduced-system
-//   GMRES run its fixed number of steps with no host synchronisation.
+//   in the first thread of the normalisation kernel; a device stop word lets
+//   the reduced-system GMRES run its fixed number of steps with no host
+//   synchronisation.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -110,6 +111,48 @@ int launch_dot_partial(const double *x, const double *y, int64_t n, double *part
   return check_launch("dot_partial");
 }
 
+// w = a + b and the partials of <w, v> in one pass, each thread summing its
+// elements in the order k_dot_partial uses
+template <bool VEC>
+__global__ void __launch_bounds__(RED_THREADS) k_sum_dot(double *w, const double *a, const double *b,
+                                                        const double *v, int64_t n, double *partials) {
+  double s = 0.0;
+  const int64_t stride = (int64_t)RED_BLOCKS * RED_THREADS;
+  const int64_t i0 = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x;
+  if (VEC) {
+    const double2 *a2 = reinterpret_cast<const double2 *>(a), *b2 = reinterpret_cast<const double2 *>(b),
+                  *v2 = reinterpret_cast<const double2 *>(v);
+    double2 *w2 = reinterpret_cast<double2 *>(w);
+    for (int64_t i = i0; i < n / 2; i += stride) {
+      const double2 x = a2[i], y = b2[i], u = v2[i];
+      double2 t;
+      t.x = x.x + y.x;
+      t.y = x.y + y.y;
+      w2[i] = t;
+      s = fma(t.x, u.x, s);
+      s = fma(t.y, u.y, s);
+    }
+  } else {
+    for (int64_t i = i0; i < n; i += stride) {
+      const double t = a[i] + b[i];
+      w[i] = t;
+      s = fma(t, v[i], s);
+    }
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+int launch_sum_dot(double *w, const double *a, const double *b, const double *v, int64_t n, double *partials,
+                   hipStream_t s) {
+  const bool vec = vec2_ok(n, w, a, b) && vec2_ok(n, v, nullptr, nullptr);
+  if (vec)
+    k_sum_dot<true><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, a, b, v, n, partials);
+  else
+    k_sum_dot<false><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, a, b, v, n, partials);
+  return check_launch("sum_dot");
+}
+
 template <bool VEC, bool NEXT>
 __global__ void __launch_bounds__(RED_THREADS) k_mgs_step(double *w, const double *v_prev, const double *pp,
                                                          double *h_out, const double *v_next, int64_t n,
@@ -197,16 +240,6 @@ int launch_scale_copy(const double *x, const double *alpha_num, const double *al
   return check_launch("scale_div");
 }
 
-__global__ void k_vec_sum(double *y, const double *a, const double *b, int64_t n) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) y[i] = a[i] + b[i];
-}
-int launch_vec_sum(double *y, const double *a, const double *b, int64_t n, hipStream_t s) {
-  if (n == 0) return 0;
-  k_vec_sum<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(y, a, b, n);
-  return check_launch("vec_sum");
-}
-
 __global__ void k_copy(const double *x, double *y, int64_t n) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) y[i] = x[i];
@@ -227,46 +260,81 @@ int launch_scatter(const double *x, const int32_t *map, int64_t n, double *z, hi
   return check_launch("scatter");
 }
 
-// ---- Arnoldi bookkeeping (one thread) -------------------------------------
+// ---- Arnoldi bookkeeping -------------------------------------------------
 // stop codes: 1 = exact breakdown (h_{j+1,j} = 0), 2 = estimate below tolerance,
 // 3 = non-finite value.
-__global__ void k_givens(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm,
-                         int *stop, int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol) {
-  const double hn2 = reduce_partials(pnorm);
-  if (threadIdx.x != 0) return;
-  if (*stop) return;
-  const double hn = sqrt(hn2);
-  *hn_out = hn;
-  double *col = H + (int64_t)ldh * j;
-  col[j + 1] = hn;
-  for (int i = 0; i < j; i++) {
-    const double a = col[i], b = col[i + 1];
-    col[i] = fma(cs[i], a, sn[i] * b);
-    col[i + 1] = fma(-sn[i], a, cs[i] * b);
+// The Givens step of column j and the normalisation w = w / h_{j+1,j} in one
+// launch: every block
+// reduces the norm partials itself (the same value in each), block 0 updates
+// the Hessenberg column, and all blocks scale their slice (skipped when the
+// norm is zero, as in k_scale_div).  The rotation uses r = sqrt(fma(a, a, b*b)).  Only the Givens part looks at the stop
+// word: a stopped process leaves H and g alone, and whatever w then holds is
+// never used.
+template <bool VEC>
+__global__ void __launch_bounds__(RED_THREADS) k_givens_scale(double *H, int ldh, double *cs, double *sn, double *g,
+                                                             int j, const double *pnorm, int *stop, int *nsteps,
+                                                             double *est, double *hn_out, const double *tol_ref,
+                                                             double rtol, double *w, int64_t n) {
+  __shared__ double sh;
+  if (threadIdx.x < WAVE) {
+    const double hn2 = reduce_partials(pnorm);
+    if (threadIdx.x == 0) sh = sqrt(hn2);
   }
-  const double a = col[j], b = col[j + 1];
-  const double r = sqrt(fma(a, a, b * b));
-  cs[j] = a / r;
-  sn[j] = b / r;
-  col[j] = r;
-  col[j + 1] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  *nsteps = j + 1;
-  const double e = fabs(g[j + 1]);
-  *est = e;
-  if (!isfinite(hn) || !isfinite(e))
-    *stop = 3;
-  else if (hn == 0.0)
-    *stop = 1;
-  else if (e <= rtol * (*tol_ref))
-    *stop = 2;
+  __syncthreads();
+  const double hn = sh;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !*stop) {
+    *hn_out = hn;
+    double *col = H + (int64_t)ldh * j;
+    col[j + 1] = hn;
+    for (int i = 0; i < j; i++) {
+      const double a = col[i], b = col[i + 1];
+      col[i] = fma(cs[i], a, sn[i] * b);
+      col[i + 1] = fma(-sn[i], a, cs[i] * b);
+    }
+    const double a = col[j], b = col[j + 1];
+    const double r = sqrt(fma(a, a, b * b));
+    cs[j] = a / r;
+    sn[j] = b / r;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    *nsteps = j + 1;
+    const double e = fabs(g[j + 1]);
+    *est = e;
+    if (!isfinite(hn) || !isfinite(e))
+      *stop = 3;
+    else if (hn == 0.0)
+      *stop = 1;
+    else if (e <= rtol * (*tol_ref))
+      *stop = 2;
+  }
+  if (hn == 0.0) return;
+  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
+  const int64_t i0 = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x;
+  if (VEC) {
+    double2 *w2 = reinterpret_cast<double2 *>(w);
+    for (int64_t i = i0; i < n / 2; i += stride) {
+      double2 t = w2[i];
+      t.x = t.x / hn;
+      t.y = t.y / hn;
+      w2[i] = t;
+    }
+  } else {
+    for (int64_t i = i0; i < n; i += stride) w[i] = w[i] / hn;
+  }
 }
 
-int launch_givens(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm, int *stop,
-                  int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol, hipStream_t s) {
-  k_givens<<<1, WAVE, 0, s>>>(H, ldh, cs, sn, g, j, pnorm, stop, nsteps, est, hn_out, tol_ref, rtol);
-  return check_launch("givens");
+int launch_givens_scale(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm, int *stop,
+                        int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol, double *w,
+                        int64_t n, hipStream_t s) {
+  if (vec2_ok(n, w, nullptr, nullptr))
+    k_givens_scale<true><<<RED_BLOCKS, RED_THREADS, 0, s>>>(H, ldh, cs, sn, g, j, pnorm, stop, nsteps, est, hn_out,
+                                                           tol_ref, rtol, w, n);
+  else
+    k_givens_scale<false><<<RED_BLOCKS, RED_THREADS, 0, s>>>(H, ldh, cs, sn, g, j, pnorm, stop, nsteps, est, hn_out,
+                                                            tol_ref, rtol, w, n);
+  return check_launch("givens_scale");
 }
 
 // R c = g by back substitution (sizes from *nsteps)

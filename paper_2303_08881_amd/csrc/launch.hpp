@@ -183,11 +183,16 @@ int launch_mgs_step(double *w, const double *v_prev, const double *partials_prev
 int launch_reduce_final(const double *partials, double *out, hipStream_t s);  // *out = sqrt(sum)
 int launch_scale_copy(const double *x, const double *alpha_num, const double *alpha_den, double *y, int64_t n,
                       const int *stop, hipStream_t s);  // y = x / (*den), skipped if *den == 0
-int launch_vec_sum(double *y, const double *a, const double *b, int64_t n, hipStream_t s);  // y = a + b
 int launch_copy(const double *x, double *y, int64_t n, hipStream_t s);
 int launch_scatter(const double *x, const int32_t *map, int64_t n, double *z, hipStream_t s);
-int launch_givens(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm, int *stop,
-                  int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol, hipStream_t s);
+// Givens step of Hessenberg column j (norm h_{j+1,j} = sqrt of the summed
+// partials; skipped when *stop is set) and w = w / h_{j+1,j} (skipped when it is 0)
+int launch_givens_scale(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm, int *stop,
+                        int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol, double *w,
+                        int64_t n, hipStream_t s);
+// w = a + b and the partials of <w, v>
+int launch_sum_dot(double *w, const double *a, const double *b, const double *v, int64_t n, double *partials,
+                   hipStream_t s);
 int launch_backsolve(const double *H, int ldh, const double *g, const int *nsteps, double *c, hipStream_t s);
 int launch_combine(double *y, const double *V, int64_t ldv, const double *c, const int *nsteps, int64_t n,
                    bool accumulate, hipStream_t s);
