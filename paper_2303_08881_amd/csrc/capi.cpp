@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -155,20 +156,18 @@ struct Schedule {
   unsigned long long epoch = 0, ticket_base = 0;
   int64_t grid = 0;
   // block-local variant: one workgroup per subdomain
+  bool block_ok = false;  // levels and blocks fit the block-local solve
   bool use_block = false;
   int64_t nblk = 0;
   int32_t *blk_rows = nullptr, *blk_lev_ptr = nullptr;
+  int32_t *pos = nullptr;            // row -> position (inverse of blk_rows)
+  const int32_t *out_map = nullptr;  // row -> index of its solution in the output vector
   // fixed-stride storage of the factor for the block-local solve
-  int32_t *lds_c = nullptr, *lds_rec = nullptr, *lds_ri = nullptr;
+  int32_t *lds_c = nullptr, *lds_rec = nullptr;
   double *lds_v = nullptr;
   int32_t lds_g = 1, lds_e = 4, lds_bt = 64;
-  int32_t lds_helpers = 0;
-  unsigned long long *lds_prog = nullptr, lds_epoch = 0;
-  double *lds_sink = nullptr;
-  int64_t ext_col = 0;               // dependency columns of the block-local solve are < ext_col
-  int64_t nloc = 0;                  // rows in the block-local solve; rows nloc.. follow in one pass
-  const int32_t *rhs_map = nullptr;  // gather map baked into lds_ri
-  const int32_t *sct_map = nullptr;  // scatter map baked into lds_rec
+  int64_t ext_col = 0;  // dependency columns of the block-local solve are < ext_col
+  int64_t nloc = 0;     // rows in the block-local solve (the rows of W follow in their own pass)
 };
 
 struct GmresWork {
@@ -194,6 +193,15 @@ struct ilu_precond {
   double *DB = nullptr, *DS = nullptr;
   Schedule sL1, sU1, sLS, sUS;
   double *xp = nullptr;
+  // Block-local solves (all four or none).  Each solve reads its right-hand
+  // side in its own position order and writes its solution contiguously:
+  // L_B into bL -> fL (L_B order), the W rows into gS (L_S order), L_S into
+  // the U_S order, U_S in place; the reduced-system vectors live in U_S order;
+  // U_B takes bU (U_B order, f' - Z y) into uU; k_finish scatters uU and yS.
+  bool block_mode = false;
+  Csr Wr, Zr, Coffr;  // W (columns in L_B order), Z and C_off (columns in U_S order)
+  int32_t *gmapL = nullptr, *fmapU = nullptr, *finB = nullptr, *finS = nullptr;
+  double *bL = nullptr, *fL = nullptr, *gS = nullptr, *yS = nullptr, *bU = nullptr, *uU = nullptr;
   // reduced-system GMRES
   double *iV = nullptr, *it1 = nullptr, *it2 = nullptr, *iH = nullptr, *ics = nullptr, *isn = nullptr,
          *ig = nullptr, *ic = nullptr, *ipa = nullptr, *ipb = nullptr, *iscal = nullptr;
@@ -453,11 +461,10 @@ struct Segs {
   std::vector<int64_t> a_start, a_len, b_start, b_len;
 };
 
+// Level analysis and the cross-workgroup (global) schedule of one factor;
+// S.block_ok tells whether the block-local solve can take it.
 static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, int64_t lo, int64_t hi, Schedule &S,
-                          const Segs &seg, const int64_t *bs1, const int64_t *bs2, int64_t split, const double *diag,
-                          int64_t ext_col,
-                          const int32_t *rhs_map, const int32_t *sct_map, void *stmp, size_t stmpb, hipStream_t s,
-                          const char *phase) {
+                          const Segs &seg, void *stmp, size_t stmpb, hipStream_t s, const char *phase) {
   const int64_t n = T.n;
   S.nrows = n;
   if (n == 0) return 0;
@@ -521,79 +528,128 @@ static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, in
   S.ticket_base = 0;
   S.grid = std::min<int64_t>(S.nchunks, (int64_t)P->num_cu * 16);
 
-  // block-local schedule: rows sorted by (subdomain, level)
   S.nblk = P->nparts;
   const uint64_t nkeys = (uint64_t)S.nblk * (uint64_t)S.nlev;
-  const int mode = P->opt.trsv_mode;
-  const bool feasible = S.nlev <= 16384 && nkeys < (1ull << 31);
-  const bool want = mode == ILU_TRSV_BLOCK || (mode == ILU_TRSV_AUTO && n / S.nblk <= (int64_t)1 << 20);
-  if (mode == ILU_TRSV_BLOCK && !feasible)
-    return fail(ILU_ERR_INVALID_ARG, "%s: block-local solve needs <= 16384 levels (has %lld)", phase,
-                (long long)S.nlev);
-  if (feasible && want) {
-    // Rows from split on in a factor with two block-start tables (the rows of
-    // W in [L_B; W]) depend only on rows below split: they are left out of
-    // the block-local solve and computed by one parallel pass after it.
-    const int64_t nloc = bs2 ? split : n;
-    S.nloc = nloc;
-    int32_t *blk;
-    RC(tmp.alloc(&blk, nloc));
-    RC(launch_row_blocks(nloc, (int32_t)S.nblk, bs1, nullptr, split, blk, s));
-    RC(launch_block_level_keys(S.level_of, blk, nloc, S.nlev, key, val, s));
-    RC(mem.alloc(&S.blk_rows, nloc));
-    RC(radix_sort(key, val, key2, S.blk_rows, nloc, bits_for(nkeys - 1), rtmp, rtb, s));
-    int64_t *bcnt, *bptr, btot;
-    RC(tmp.alloc(&bcnt, (int64_t)nkeys));
-    RC(histogram_keys(key2, nloc, (int64_t)nkeys, bcnt, s));
-    const size_t stb2 = scan_tmp_bytes((int64_t)nkeys) + 64;
-    void *stmp2;
-    RC(tmp.alloc((char **)&stmp2, (int64_t)stb2));
-    RC(make_rp(tmp, bcnt, (int64_t)nkeys, &bptr, &btot, stmp2, stb2, s));
-    RC(mem.alloc(&S.blk_lev_ptr, (int64_t)nkeys + 1));
-    RC(launch_i64_to_i32(bptr, S.blk_lev_ptr, (int64_t)nkeys + 1, s));
-    // fixed-stride storage: G lanes of four entries per row, G the smallest
-    // power of two (<= 8) that covers the longest row; threads per workgroup
-    // cover the widest level (rows beyond take the slow path)
-    int32_t *pos, *dm;
-    RC(tmp.alloc(&pos, nloc));
-    RC(tmp.alloc(&dm, 2));
-    RC(fill_i32(dm, 0, 2, s));
-    RC(launch_lds_prepare(S.blk_rows, T.rp, T.ci, nloc, ext_col, S.blk_lev_ptr, (int64_t)nkeys, pos, dm, dm + 1,
-                          s));
-    int32_t hm[2] = {0, 0};
-    HIPCK(hipMemcpyAsync(hm, dm, sizeof(hm), hipMemcpyDeviceToHost, s));
+  S.block_ok = S.nlev <= 16384 && nkeys < (1ull << 31);
+  return 0;
+}
+
+// Block-local storage of one factor: rows sorted by (subdomain, level), the
+// fixed-stride entries and the records.  omap (row -> output index) places
+// each solution; NULL puts it at its own position.
+static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, const int64_t *bs1, const int64_t *bs2,
+                       int64_t split, const double *diag, int64_t ext_col, const int32_t *omap, hipStream_t s,
+                       const char *phase) {
+  const int64_t n = T.n;
+  S.use_block = true;
+  S.ext_col = ext_col;
+  // Rows from split on in a factor with two block-start tables (the rows of
+  // W in [L_B; W]) depend only on rows below split: they are left out of the
+  // block-local solve and computed by one parallel pass after it.
+  const int64_t nloc = bs2 ? split : n;
+  S.nloc = nloc;
+  if (nloc == 0) return 0;
+  Mem &mem = P->mem;
+  const uint64_t nkeys = (uint64_t)S.nblk * (uint64_t)S.nlev;
+  uint32_t *key, *key2;
+  int32_t *val;
+  RC(tmp.alloc(&key, nloc));
+  RC(tmp.alloc(&key2, nloc));
+  RC(tmp.alloc(&val, nloc));
+  void *rtmp;
+  const size_t rtb = radix_tmp_bytes(nloc);
+  RC(tmp.alloc((char **)&rtmp, (int64_t)rtb));
+  int32_t *blk;
+  RC(tmp.alloc(&blk, nloc));
+  RC(launch_row_blocks(nloc, (int32_t)S.nblk, bs1, nullptr, split, blk, s));
+  RC(launch_block_level_keys(S.level_of, blk, nloc, S.nlev, key, val, s));
+  RC(mem.alloc(&S.blk_rows, nloc));
+  RC(radix_sort(key, val, key2, S.blk_rows, nloc, bits_for(nkeys - 1), rtmp, rtb, s));
+  int64_t *bcnt, *bptr, btot;
+  RC(tmp.alloc(&bcnt, (int64_t)nkeys));
+  RC(histogram_keys(key2, nloc, (int64_t)nkeys, bcnt, s));
+  const size_t stb2 = scan_tmp_bytes((int64_t)nkeys) + 64;
+  void *stmp2;
+  RC(tmp.alloc((char **)&stmp2, (int64_t)stb2));
+  RC(make_rp(tmp, bcnt, (int64_t)nkeys, &bptr, &btot, stmp2, stb2, s));
+  RC(mem.alloc(&S.blk_lev_ptr, (int64_t)nkeys + 1));
+  RC(launch_i64_to_i32(bptr, S.blk_lev_ptr, (int64_t)nkeys + 1, s));
+  // fixed-stride storage: G lanes of E entries per row; threads per
+  // workgroup cover the widest level (rows beyond take the slow path)
+  int32_t *dm;
+  RC(mem.alloc(&S.pos, nloc));
+  RC(tmp.alloc(&dm, 2));
+  RC(fill_i32(dm, 0, 2, s));
+  RC(launch_lds_prepare(S.blk_rows, T.rp, T.ci, nloc, ext_col, S.blk_lev_ptr, (int64_t)nkeys, S.pos, dm, dm + 1, s));
+  int32_t hm[2] = {0, 0};
+  HIPCK(hipMemcpyAsync(hm, dm, sizeof(hm), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  // entries per lane E and lanes per row G: one lane of 2 or 4 for short
+  // rows, else lanes of 8, as few as cover the longest row (at most 8)
+  int G = 1, E = hm[0] <= 2 ? 2 : hm[0] <= 4 ? 4 : 8;
+  while (E == 8 && G < 8 && 8 * G < hm[0]) G *= 2;
+  if ((nloc + 1) * (int64_t)G * E >= ((int64_t)1 << 30))
+    return fail(ILU_ERR_INVALID_ARG, "%s: factor too large for the block solve", phase);
+  const int64_t bt = ((int64_t)std::max(hm[1], 1) * G + 63) / 64 * 64;
+  S.lds_g = G;
+  S.lds_e = E;
+  S.lds_bt = (int32_t)std::min<int64_t>(bt, 512);
+  const int64_t ne = (nloc + 1) * G * E;
+  RC(mem.alloc(&S.lds_c, ne));
+  RC(mem.alloc(&S.lds_v, ne));
+  RC(mem.alloc(&S.lds_rec, 4 * (nloc + 1)));
+  S.out_map = omap ? omap : S.pos;
+  RC(launch_lds_fill(S.blk_rows, T.rp, T.ci, T.v, diag, nloc, ext_col, S.pos, S.blk_lev_ptr, (int64_t)nkeys, G * E,
+                     S.out_map, S.lds_c, S.lds_v, S.lds_rec, s));
+  HIPCK(hipStreamSynchronize(s));
+  return 0;
+}
+
+// rows [row0, row0 + nrows) of A as a CSR of their own, columns c -> cmap[c - col_off]
+static int csr_remap(Mem &mem, const Csr &A, int64_t row0, int64_t nrows, const int32_t *cmap, int64_t col_off,
+                     Csr *out, hipStream_t s) {
+  out->n = nrows;
+  int64_t b[2] = {0, 0};
+  if (nrows > 0) {
+    HIPCK(hipMemcpyAsync(&b[0], A.rp + row0, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(&b[1], A.rp + row0 + nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
-    // entries per lane E and lanes per row G: one lane of 2 or 4 for short
-    // rows, else lanes of 8, as few as cover the longest row (at most 8)
-    int G = 1, E = hm[0] <= 2 ? 2 : hm[0] <= 4 ? 4 : 8;
-    while (E == 8 && G < 8 && 8 * G < hm[0]) G *= 2;
-    if ((nloc + 1) * (int64_t)G * E >= ((int64_t)1 << 30))
-      return fail(ILU_ERR_INVALID_ARG, "%s: factor too large for the block solve", phase);
-    int64_t bt = ((int64_t)std::max(hm[1], 1) * G + 63) / 64 * 64;
-    S.lds_g = G;
-    S.lds_e = E;
-    // one L2 prefetch helper per subdomain
-    S.lds_helpers = TRSV_HELPERS;
-    if (S.lds_helpers > 0) {
-      const int64_t hb = (S.nblk + 7) / 8 * 8;
-      RC(mem.alloc(&S.lds_prog, S.nblk));
-      RC(mem.alloc(&S.lds_sink, hb * (S.lds_helpers + 1)));
-      HIPCK(hipMemsetAsync(S.lds_prog, 0, sizeof(unsigned long long) * S.nblk, s));
-    }
-    S.lds_bt = (int32_t)std::min<int64_t>(bt, 512);
-    const int64_t ne = (nloc + 1) * G * E;
-    RC(mem.alloc(&S.lds_c, ne));
-    RC(mem.alloc(&S.lds_v, ne));
-    RC(mem.alloc(&S.lds_rec, 4 * (nloc + 1)));
-    RC(mem.alloc(&S.lds_ri, nloc + 1));
-    S.rhs_map = rhs_map;
-    S.sct_map = sct_map;
-    S.ext_col = ext_col;
-    RC(launch_lds_fill(S.blk_rows, T.rp, T.ci, T.v, diag, nloc, ext_col, pos, S.blk_lev_ptr, (int64_t)nkeys, G * E, rhs_map,
-                       sct_map, S.lds_c, S.lds_v, S.lds_rec, S.lds_ri, s));
-    HIPCK(hipStreamSynchronize(s));
-    S.use_block = true;
   }
+  out->nnz = b[1] - b[0];
+  RC(mem.alloc(&out->rp, nrows + 1));
+  RC(mem.alloc(&out->ci, out->nnz));
+  RC(mem.alloc(&out->v, out->nnz));
+  if (nrows > 0)
+    RC(launch_csr_remap(A.rp + row0, nrows, b[0], A.ci + b[0], A.v + b[0], out->nnz, cmap, col_off, out->rp, out->ci,
+                        out->v, s));
+  else
+    HIPCK(hipMemsetAsync(out->rp, 0, sizeof(int64_t), s));
+  return 0;
+}
+
+// The orders that connect the four block-local solves (see ilu_precond):
+// index maps, the renumbered copies of W, Z and C_off, and the vectors.
+static int build_block_flow(ilu_precond *P, hipStream_t s) {
+  Mem &mem = P->mem;
+  const int64_t nB = P->nB, nS = P->nS;
+  RC(mem.alloc(&P->bL, nB));
+  RC(mem.alloc(&P->fL, nB));
+  RC(mem.alloc(&P->bU, nB));
+  RC(mem.alloc(&P->uU, nB));
+  RC(mem.alloc(&P->gS, nS));
+  RC(mem.alloc(&P->yS, nS));
+  RC(mem.alloc(&P->gmapL, nB));
+  RC(mem.alloc(&P->fmapU, nB));
+  RC(mem.alloc(&P->finB, nB));
+  RC(mem.alloc(&P->finS, nS));
+  RC(launch_gather_i32(P->perm, P->sL1.blk_rows, nB, P->gmapL, s));      // r index of each L_B position
+  RC(launch_gather_i32(P->sL1.pos, P->sU1.blk_rows, nB, P->fmapU, s));   // L_B position of each U_B position
+  RC(launch_gather_i32(P->perm, P->sU1.blk_rows, nB, P->finB, s));       // z index of each U_B position
+  RC(launch_gather_i32(P->perm + nB, P->sUS.blk_rows, nS, P->finS, s));  // z index of each U_S position
+  RC(csr_remap(mem, P->L1, nB, nS, P->sL1.pos, 0, &P->Wr, s));
+  RC(csr_remap(mem, P->Zb, 0, nB, P->sUS.pos, nB, &P->Zr, s));
+  RC(csr_remap(mem, P->Coff, 0, nS, P->sUS.pos, 0, &P->Coffr, s));
+  HIPCK(hipStreamSynchronize(s));
   return 0;
 }
 
@@ -610,8 +666,11 @@ static double trsv_bytes(const Schedule &S, const Csr &T, bool diag, bool bmap, 
   return b;
 }
 
+// Block-local schedules take b in position order and write x through the
+// schedule's output map; `after` runs inside the timed region (the W rows).
 static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, int64_t split, const double *b,
-                const int32_t *bmap, double *x, double *scat, const int32_t *smap, hipStream_t s, int role) {
+                const int32_t *bmap, double *x, double *scat, const int32_t *smap, hipStream_t s, int role,
+                const std::function<int()> &after = nullptr) {
   if (S.nrows == 0) return 0;
   TrsvLaunch t;
   if (!S.use_block) S.epoch++;
@@ -641,9 +700,7 @@ static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, i
   if (!S.use_block) S.ticket_base += (unsigned long long)(S.nchunks + S.grid);
   const double bytes = trsv_bytes(S, T, diag != nullptr, bmap != nullptr, scat != nullptr);
   if (S.use_block) {
-    if (bmap != S.rhs_map || (scat && smap != S.sct_map))
-      return fail(ILU_ERR_INVALID_ARG, "internal: gather/scatter map differs from the schedule's");
-
+    if (bmap || scat) return fail(ILU_ERR_INVALID_ARG, "internal: block-local solves take no gather or scatter map");
     t.nblk = S.nblk;
     t.nlev_blk = S.nlev;
     t.blk_rows = S.blk_rows;
@@ -651,19 +708,15 @@ static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, i
     t.lds_c = S.lds_c;
     t.lds_v = S.lds_v;
     t.lds_rec = S.lds_rec;
-    t.lds_ri = S.lds_ri;
+    t.out_map = S.out_map;
     t.lds_g = S.lds_g;
     t.lds_e = S.lds_e;
     t.lds_bt = S.lds_bt;
-    t.lds_helpers = S.lds_helpers;
-    t.lds_prog = S.lds_prog;
-    t.lds_epoch = ++S.lds_epoch;
-    t.lds_sink = S.lds_sink;
     t.split_col = S.ext_col;
     t.nrows = S.nloc;
     return timed(ILU_K_TRSV_LB + role, bytes, s, [&] {
       RC(launch_trsv_lds(t, s));
-      if (S.nloc < S.nrows) RC(launch_rows_lower(T.rp, T.ci, T.v, S.nloc, S.nrows, b, bmap, x, s));
+      if (after) RC(after());
       return 0;
     });
   }
@@ -843,14 +896,34 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
     seg_s.b_start.push_back(0);
     seg_s.b_len.push_back(0);
   }
-  RC(build_schedule(P, tmp, P->L1, true, 0, n, P->sL1, seg_l1, bs_int, bs_ifc, nB, nullptr, INT64_MAX, P->perm, nullptr,
-                    stmp, stmpb, s, "levels L"));
-  RC(build_schedule(P, tmp, P->U1, false, 0, nB, P->sU1, seg_u1, bs_int, nullptr, 0, P->DB, nB, nullptr, P->perm, stmp,
-                    stmpb, s, "levels U"));
-  RC(build_schedule(P, tmp, P->LS, true, 0, nS, P->sLS, seg_s, bs_loc, nullptr, 0, nullptr, INT64_MAX, nullptr, nullptr,
-                    stmp, stmpb, s, "levels L_S"));
-  RC(build_schedule(P, tmp, P->US, false, 0, nS, P->sUS, seg_s, bs_loc, nullptr, 0, P->DS, INT64_MAX, nullptr, nullptr,
-                    stmp, stmpb, s, "levels U_S"));
+  RC(build_schedule(P, tmp, P->L1, true, 0, n, P->sL1, seg_l1, stmp, stmpb, s, "levels L"));
+  RC(build_schedule(P, tmp, P->U1, false, 0, nB, P->sU1, seg_u1, stmp, stmpb, s, "levels U"));
+  RC(build_schedule(P, tmp, P->LS, true, 0, nS, P->sLS, seg_s, stmp, stmpb, s, "levels L_S"));
+  RC(build_schedule(P, tmp, P->US, false, 0, nS, P->sUS, seg_s, stmp, stmpb, s, "levels U_S"));
+  // block-local solves for all four factors, or for none
+  {
+    const Schedule *all[4] = {&P->sL1, &P->sU1, &P->sLS, &P->sUS};
+    bool ok = true;
+    int64_t worst = 0;
+    for (const Schedule *x : all)
+      if (x->nrows > 0 && !x->block_ok) {
+        ok = false;
+        worst = std::max(worst, x->nlev);
+      }
+    const int mode = opt->trsv_mode;
+    if (mode == ILU_TRSV_BLOCK && !ok)
+      return fail(ILU_ERR_INVALID_ARG, "block-local solve needs <= 16384 levels per factor (has %lld)",
+                  (long long)worst);
+    const bool want = mode == ILU_TRSV_BLOCK || (mode == ILU_TRSV_AUTO && n / nparts <= ((int64_t)1 << 20));
+    P->block_mode = ok && want;
+  }
+  if (P->block_mode) {
+    RC(build_block(P, tmp, P->L1, P->sL1, bs_int, bs_ifc, nB, nullptr, INT64_MAX, nullptr, s, "levels L"));
+    RC(build_block(P, tmp, P->U1, P->sU1, bs_int, nullptr, 0, P->DB, nB, nullptr, s, "levels U"));
+    RC(build_block(P, tmp, P->US, P->sUS, bs_loc, nullptr, 0, P->DS, INT64_MAX, nullptr, s, "levels U_S"));
+    RC(build_block(P, tmp, P->LS, P->sLS, bs_loc, nullptr, 0, nullptr, INT64_MAX, P->sUS.pos, s, "levels L_S"));
+    RC(build_block_flow(P, s));
+  }
 
   // 7. workspaces
   RC(mem.alloc(&P->xp, n));
@@ -949,8 +1022,11 @@ static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t 
   RC(launch_scale_copy(V, nullptr, beta, V, nS, nullptr, s));
   for (int j = 0; j < k; j++) {
     double *vj = V + (int64_t)j * nS, *w = V + (int64_t)(j + 1) * nS;
-    RC(timed(ILU_K_SPMV_COFF, spmv_bytes(nS, P->Coff.nnz, false), s,
-             [&] { return launch_spmv(P->Coff.rp, P->Coff.ci, P->Coff.v, nS, vj, P->it1, s); }));
+    // D^-1 C_off v_j: the rows go to L_S position order in block mode
+    const Csr &C = P->block_mode ? P->Coffr : P->Coff;
+    RC(timed(ILU_K_SPMV_COFF, spmv_bytes(nS, C.nnz, false), s, [&] {
+      return launch_spmv_map(C.rp, C.ci, C.v, nS, vj, P->it1, P->block_mode ? P->sLS.pos : nullptr, s);
+    }));
     RC(trsv(P, P->sLS, P->LS, nullptr, 0, P->it1, nullptr, P->it2, nullptr, nullptr, s, 2));
     RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, P->it2, nullptr, P->it2, nullptr, nullptr, s, 3));
     double *pc = P->ipa, *pn = P->ipb;
@@ -967,9 +1043,32 @@ static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t 
   return launch_combine(y, V, nS, P->ic, nsteps, nS, false, s);
 }
 
+// z = M^-1 r with the block-local solves (orders as in ilu_precond)
+static int apply_block(ilu_precond *P, const double *r, double *z, hipStream_t s) {
+  const int64_t nB = P->nB, nS = P->nS;
+  // f' = L_B^-1 r_B, then g' = r_S - W f' in L_S position order
+  RC(launch_gather(r, P->gmapL, nB, P->bL, s));
+  RC(trsv(P, P->sL1, P->L1, nullptr, 0, P->bL, nullptr, P->fL, nullptr, nullptr, s, 0, [&] {
+    return launch_rows_lower(P->Wr.rp, P->Wr.ci, P->Wr.v, nS, r, P->perm + nB, P->fL, P->gS, P->sLS.pos, s);
+  }));
+  if (nS > 0) {
+    if (P->opt.method == ILU_METHOD_SCHUR) {
+      RC(inner_gmres(P, P->gS, P->yS, s));
+    } else {
+      RC(trsv(P, P->sLS, P->LS, nullptr, 0, P->gS, nullptr, P->yS, nullptr, nullptr, s, 2));
+      RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, P->yS, nullptr, P->yS, nullptr, nullptr, s, 3));
+    }
+  }
+  // f'' = f' - Z y in U_B position order, u = U_B^-1 f'', then both halves to z
+  RC(launch_upper_rhs(P->sU1.blk_rows, P->fmapU, nB, P->fL, P->Zr.rp, P->Zr.ci, P->Zr.v, P->yS, P->bU, s));
+  RC(trsv(P, P->sU1, P->U1, P->DB, nB, P->bU, nullptr, P->uU, nullptr, nullptr, s, 1));
+  return launch_finish(P->uU, P->finB, nB, P->yS, P->finS, nS, z, s);
+}
+
 static int apply_impl(ilu_precond *P, const double *r, double *z, hipStream_t s) {
   const int64_t n = P->n, nB = P->nB, nS = P->nS;
   if (n == 0) return 0;
+  if (P->block_mode) return apply_block(P, r, z, s);
   double *xp = P->xp;
   // f' = L_B^-1 r[perm_B] and g' = r[perm_S] - W f' in one level-scheduled pass
   RC(trsv(P, P->sL1, P->L1, nullptr, 0, r, P->perm, xp, nullptr, nullptr, s, 0));
@@ -983,10 +1082,7 @@ static int apply_impl(ilu_precond *P, const double *r, double *z, hipStream_t s)
     }
     RC(launch_scatter(gp, P->perm + nB, nS, z, s));
   }
-  // u = U_B^-1 (f' - Z y), scattered to z; the block-local solve takes the
-  // Z correction as its own pass first (same order of operations)
-  if (P->sU1.use_block && P->Zb.nnz > 0)
-    RC(launch_ext_correct(P->Zb.rp, P->Zb.ci, P->Zb.v, nB, nB, xp + nB, xp, s));
+  // u = U_B^-1 (f' - Z y), scattered to z
   RC(trsv(P, P->sU1, P->U1, P->DB, nB, xp, nullptr, xp, z, P->perm, s, 1));
   return 0;
 }

@@ -117,9 +117,10 @@ struct TrsvLaunch {
   const double *v;
   const double *diag;      // NULL -> unit diagonal
   int64_t split_col;       // upper solves: columns >= split_col are processed first (Z part)
-  const double *b;         // right-hand side base
-  const int32_t *b_map;    // rhs index = b_map ? b_map[row] : row
+  const double *b;         // right-hand side base (block-local: in position order)
+  const int32_t *b_map;    // rhs index = b_map ? b_map[row] : row (global solve)
   double *x;               // solution, indexed by row; columns index x too
+                           // (block-local: the output vector, see out_map)
   double *scatter_out;     // optional: scatter_out[scatter_map[row]] = x
   const int32_t *scatter_map;
   void *status;
@@ -133,26 +134,30 @@ struct TrsvLaunch {
   // block-local storage (launch_trsv_lds): fixed-stride dependency entries
   const int32_t *lds_c;    // [(nrows + 1) * G * E] window slots
   const double *lds_v;     // [(nrows + 1) * G * E]
-  const int32_t *lds_rec;  // int4 per position (+ dummy)
-  const int32_t *lds_ri;   // rhs index per position (+ dummy)
+  const int32_t *lds_rec;  // int4 per position (+ dummy): {row or ~row, output index, diagonal}
+  const int32_t *out_map;  // row -> index of its solution in x (the output index of its position)
   int32_t lds_g;           // lanes per row: 1 (E = 2, 4), or 1, 2, 4, 8 (E = 8)
   int32_t lds_e;           // entries per lane: 2, 4 or 8
   int32_t lds_bt;          // threads per workgroup (multiple of 64, <= 512)
-  int32_t lds_helpers;     // L2 prefetch workgroups per subdomain (0: none)
-  unsigned long long *lds_prog;  // [nblk] solver progress words
-  unsigned long long lds_epoch;  // distinct per launch
-  double *lds_sink;        // [grid] (never written with finite data)
 };
-constexpr int TRSV_HELPERS = 1;  // L2 prefetch workgroups per subdomain of a block-local solve
 int launch_trsv(const TrsvLaunch &t, hipStream_t s);
 int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s);
-// rows row0..n-1 of a unit lower factor whose dependencies are all solved:
-// x_r = b[bmap ? bmap[r] : r] - sum_j l_rj x_j in column order
-int launch_rows_lower(const int64_t *rp, const int32_t *ci, const double *v, int64_t row0, int64_t n, const double *b,
-                      const int32_t *bmap, double *x, hipStream_t s);
-// x[i] -= sum_j E_ij y[col_j - col_off] (rows of E in column order)
-int launch_ext_correct(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, int64_t col_off,
-                       const double *y, double *x, hipStream_t s);
+// y[q] = x[map[q]]
+int launch_gather(const double *x, const int32_t *map, int64_t n, double *y, hipStream_t s);
+int launch_gather_i32(const int32_t *x, const int32_t *map, int64_t n, int32_t *y, hipStream_t s);
+// rows [0, nrows) of a CSR (rp[0] == base) with each column c replaced by cmap[c - col_off]
+int launch_csr_remap(const int64_t *rp, int64_t nrows, int64_t base, const int32_t *ci, const double *v, int64_t nnz,
+                     const int32_t *cmap, int64_t col_off, int64_t *orp, int32_t *oci, double *ov, hipStream_t s);
+// n rows of a unit lower factor whose dependencies are all solved (columns in
+// x's order): out[omap[i]] = b[bmap[i]] - sum_j l_ij x_j in column order
+int launch_rows_lower(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
+                      const int32_t *bmap, const double *x, double *out, const int32_t *omap, hipStream_t s);
+// out[q] = f[fmap[q]] - sum_j Z_rj y_j over row r = rows[q] of Z, in column order
+int launch_upper_rhs(const int32_t *rows, const int32_t *fmap, int64_t n, const double *f, const int64_t *rp,
+                     const int32_t *ci, const double *v, const double *y, double *out, hipStream_t s);
+// z[mb[q]] = u[q] (q < nb), z[ms[q]] = y[q] (q < ns)
+int launch_finish(const double *u, const int32_t *mb, int64_t nb, const double *y, const int32_t *ms, int64_t ns,
+                  double *z, hipStream_t s);
 // block-local storage: pos[rows[q]] = q, the longest dependency row and the
 // widest level (maxent, maxw must be zeroed), then the fixed-stride fill
 int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci, int64_t n, int64_t split,
@@ -160,8 +165,7 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
                        hipStream_t s);
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
                     int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int width,
-                    const int32_t *rhs_map, const int32_t *sct_map, int32_t *oc, double *ov, int32_t *rec,
-                    int32_t *ri, hipStream_t s);
+                    const int32_t *omap, int32_t *oc, double *ov, int32_t *rec, hipStream_t s);
 // block id of each row from ascending block starts (s1 below split, s2 from split on; s2 may be NULL)
 int launch_row_blocks(int64_t nrows, int32_t nblk, const int64_t *s1, const int64_t *s2, int64_t split, int32_t *blk,
                       hipStream_t s);
@@ -172,6 +176,9 @@ int launch_i64_to_i32(const int64_t *in, int32_t *out, int64_t n, hipStream_t s)
 // ---- krylov.hip ----
 int launch_spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x, double *y,
                 hipStream_t s);
+// y[omap[i]] = (row i of the product)
+int launch_spmv_map(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x, double *y,
+                    const int32_t *omap, hipStream_t s);
 int launch_residual(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
                     const double *x, double *r, hipStream_t s);
 constexpr int RED_BLOCKS = 512;  // fixed grid of the deterministic reductions

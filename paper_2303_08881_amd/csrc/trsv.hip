@@ -102,32 +102,34 @@ __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
 // ---------------------------------------------------------------------------
 // Block-local solve.  The subdomains are independent, so each block of rows
 // (one subdomain) is solved by one workgroup that walks the block's levels
-// with a workgroup barrier between consecutive non-empty levels; there is no
+// with a workgroup barrier between consecutive levels; there is no
 // communication between workgroups.  Rows are listed block-major,
-// level-minor; lev_ptr[b * nlev + l] .. [.. + 1] delimits the positions of
-// level l in block b.
+// level-minor ("positions"); lev_ptr[b * nlev + l] .. [.. + 1] delimits the
+// positions of level l in block b.
 //
-// Storage (built at setup, "position" = index in that order):
+// Every vector the solve touches is in an order that makes the accesses of a
+// level contiguous: the right-hand side is given in position order, and the
+// solution of position q goes to out[rec.y], an index fixed at setup (q
+// itself, or the position of the row in the solve that consumes it next).
+// Storage (built at setup):
 //   ent_c/ent_v  the dependency entries of each position at a fixed stride of
 //                G*E (G lanes per row of E = 2, 4 or 8 entries each): column
 //                order, each column replaced by the slot of its position in
 //                the LDS solution window, padded with the window's zero slot
 //                and 0.0;
-//   rec          {row (or ~row for a slow row), scatter index, diagonal};
-//   rhs_idx      index of the row's right-hand side in b.
+//   rec          {row (or ~row for a slow row), output index, diagonal}.
 // A row is handled by G consecutive lanes, lane g summing entries
 // gE..gE+E-1 with fma (lane 0 starting from the right-hand side); the G
 // partial sums are combined pairwise across lanes (fixed order, so results
 // are reproducible run to run; the sum order differs from the sequential one
 // by rounding only) and the diagonal divides once.
 //
-// Latency is the whole cost of this solve (a level holds tens of rows), so
-// every load is issued LOOK levels before its use (LOOK = 10, 8, 6 for
-// E = 2, 4, 8): each thread keeps LOOK register sets that rotate by unrolling the
-// level loop LOOK times, and the right-hand-side index is loaded LOOK levels
-// before the right-hand side it locates.  All pipeline addresses come from
-// the level pointers in LDS -- none depends on a load of the same pipeline
-// stage -- and every pipeline load is unconditional (idle lanes read a dummy
+// Latency is the whole cost of this solve (a level holds tens to hundreds of
+// rows), so every load is issued LOOK levels before its use (LOOK = 10, 8, 6
+// for E = 2, 4, 8): each thread keeps LOOK register sets that rotate by
+// unrolling the level loop LOOK times.  All pipeline addresses come from the
+// level pointers in LDS -- none depends on a load of the same pipeline stage
+// -- and every pipeline load is unconditional (idle lanes read a dummy
 // position), so the number of memory operations between a load and its use
 // is fixed: the compiler's in-order waits before level l then cover only
 // level l's own loads.  LOOK times the loads and the store of a level stay
@@ -136,12 +138,10 @@ __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
 // The solution of the last XWIN positions lives in an LDS ring.  Rows with
 // more than G*E entries, with a dependency older than the ring, or beyond
 // blockDim/G rows in their level are "slow": they are summed sequentially in
-// column order from the natural-order factor and solution (written by this
-// workgroup before an earlier barrier).  Columns outside the solve (the Z
-// block of the U_B solve) run first as their own pass (k_ext_correct).  A
-// scatter role writes its solution only to the scattered output (the
-// natural-order copy is not needed afterwards); its slow rows read
-// dependencies from there.
+// column order from the natural-order factor, reading each dependency from
+// out[omap[column]] (written by this workgroup before an earlier barrier).
+// Columns outside the solve (the Z block of the U_B solve) are applied to
+// the right-hand side before the solve.
 // ---------------------------------------------------------------------------
 constexpr int XWIN = 8192;            // solution window (positions), power of two
 constexpr int BT_MAX = 512;           // threads per block-local solve
@@ -149,8 +149,8 @@ constexpr int BT_LDS_LEVELS = 16384;  // level pointers kept in LDS
 constexpr int LOOK_MAX = 10;
 
 // loads per level: E/4 (columns; one for E = 2) + E/2 (values; one for E = 2)
-// + record + right-hand side + its index, and one store: LOOK times that
-// stays within the 63 operations the counter tracks
+// + record + right-hand side, and one store: LOOK times that stays within
+// the 63 operations the counter tracks
 template <int E>
 constexpr int look_of() {
   return E == 8 ? 6 : E == 4 ? 8 : 10;
@@ -160,7 +160,6 @@ struct LdsTrsvArgs {
   const int4 *ent_c;       // [(npos + 1) * G * E / 4] window slots
   const double2 *ent_v;    // [(npos + 1) * G * E / 2]
   const int4 *rec;         // [npos + 1]
-  const int32_t *rhs_idx;  // [npos + 1]
   const int32_t *lev_ptr;  // [nblk * nlev + 1]
   int32_t nlev;
   int32_t npos;            // positions; index npos is the dummy read by idle lanes
@@ -170,17 +169,9 @@ struct LdsTrsvArgs {
   const int32_t *ci;
   const double *v;
   int64_t split;           // dependency columns are < split
-  const double *b;
-  double *x;               // solution, natural order (not written by scatter roles)
-  double *scatter_out;     // scatter roles: the solution of row r goes to scatter_out[smap[r]] only
-  const int32_t *smap;
-  // L2 prefetch helpers (see k_trsv_lds): solvers are workgroups [0, nblk),
-  // helpers start at hbase (a multiple of 8, so a helper shares its
-  // solver's XCD and L2) with a stride of hbase per helper rank
-  int32_t nblk, hbase;
-  unsigned long long *prog;  // [nblk] (epoch << 32) | level the solver has reached
-  unsigned long long epoch;
-  double *sink;              // [nblk * helpers] keeps the prefetch loads alive
+  const double *b;         // right-hand side in position order [npos]
+  double *out;             // solution of position q at out[rec[q].y]
+  const int32_t *omap;     // row -> its index in out (slow rows)
 };
 
 // window slots of a lane's entries: int2 for E = 2, E/4 int4 otherwise
@@ -224,12 +215,12 @@ __device__ __forceinline__ double group_sum(double s) {
   return s;
 }
 
-template <bool DIAG, bool SCAT>
-__device__ __forceinline__ double slow_row(const LdsTrsvArgs &a, int32_t r, int32_t ri, double d) {
-  double s = a.b[ri];
+template <bool DIAG>
+__device__ __forceinline__ double slow_row(const LdsTrsvArgs &a, int32_t r, int32_t q, double d) {
+  double s = a.b[q];
   for (int64_t p = a.rp[r]; p < a.rp[r + 1]; p++) {
     const int32_t c = a.ci[p];
-    if (c < a.split) s = fma(-a.v[p], SCAT ? a.scatter_out[a.smap[c]] : a.x[c], s);
+    if (c < a.split) s = fma(-a.v[p], a.out[a.omap[c]], s);
   }
   if (DIAG) s = s / d;
   // Drain this path's loads here: otherwise the compiler cannot tell, where
@@ -241,13 +232,15 @@ __device__ __forceinline__ double slow_row(const LdsTrsvArgs &a, int32_t r, int3
 }
 
 // Load the pipeline set of the row handled by this lane in a level whose
-// positions are [lo, hi) (idle lanes read the dummy position).
+// positions are [lo, hi) (idle lanes read the dummy position and the first
+// right-hand side).
 template <int G, int E>
-__device__ __forceinline__ void refill(const LdsTrsvArgs &a, int32_t lo, int32_t hi, int32_t j, int32_t g, int32_t ri,
+__device__ __forceinline__ void refill(const LdsTrsvArgs &a, int32_t lo, int32_t hi, int32_t j, int32_t g,
                                        PSet<E> &S) {
-  const int32_t q = lo + j;
-  const int32_t qc = q < hi ? q : a.npos;
-  const int32_t e = qc * G + g;
+  const uint32_t q = (uint32_t)(lo + j);
+  const bool in = q < (uint32_t)hi;
+  const uint32_t qc = in ? q : (uint32_t)a.npos;
+  const uint32_t e = qc * G + g;
   if constexpr (E == 2) {
     S.c.v = reinterpret_cast<const int2 *>(a.ent_c)[e];
   } else {
@@ -257,22 +250,17 @@ __device__ __forceinline__ void refill(const LdsTrsvArgs &a, int32_t lo, int32_t
 #pragma unroll
   for (int i = 0; i < E / 2; i++) S.w[i] = a.ent_v[e * (E / 2) + i];
   S.rec = a.rec[qc];
-  S.rhs = a.b[ri];
-}
-__device__ __forceinline__ int32_t load_ri(const LdsTrsvArgs &a, int32_t lo, int32_t hi, int32_t j) {
-  const int32_t q = lo + j;
-  return a.rhs_idx[q < hi ? q : a.npos];
+  S.rhs = a.b[in ? q : 0u];
 }
 
-template <int G, int E, bool DIAG, bool SCAT>
+template <int G, int E, bool DIAG>
 __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, double *win, const int32_t *lp, int32_t l, int32_t j,
-                                      int32_t g, PSet<E> &S, int32_t &RI) {
+                                      int32_t g, PSet<E> &S) {
   constexpr int LOOK = look_of<E>();
   // every LDS read of the step first, so that a single wait covers them: the
-  // bounds of levels l, l + LOOK, l + 2 LOOK and the window values
+  // bounds of levels l and l + LOOK and the window values
   const int32_t q0 = lp[l], q1 = lp[l + 1];
   const int32_t f0 = lp[l + LOOK], f1 = lp[l + LOOK + 1];
-  const int32_t i0 = lp[l + 2 * LOOK], i1 = lp[l + 2 * LOOK + 1];
   double xv[E];
 #pragma unroll
   for (int k = 0; k < E; k++) xv[k] = win[S.c.get(k)];
@@ -288,174 +276,73 @@ __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, double *win, const i
   const bool slow = S.rec.x < 0;
   const int32_t r = slow ? ~S.rec.x : S.rec.x;
   if (DIAG) s = s / rec_diag(S.rec);
-  if (mine && slow) s = slow_row<DIAG, SCAT>(a, r, a.rhs_idx[q], rec_diag(S.rec));
+  if (mine && slow) s = slow_row<DIAG>(a, r, q, rec_diag(S.rec));
   if (mine && g == 0) {
     win[q & (XWIN - 1)] = s;
-    if (SCAT)
-      a.scatter_out[S.rec.y] = s;
-    else
-      a.x[r] = s;
+    a.out[(uint32_t)S.rec.y] = s;
   }
   // rows beyond bt/G in this level: one thread each, slow path
   const int32_t cap = a.bt / G;
   for (int32_t qq = q0 + cap + (int32_t)threadIdx.x; qq < q1; qq += a.bt) {
     const int4 rc = a.rec[qq];
     const int32_t rr = rc.x < 0 ? ~rc.x : rc.x;
-    const double s2 = slow_row<DIAG, SCAT>(a, rr, a.rhs_idx[qq], rec_diag(rc));
+    const double s2 = slow_row<DIAG>(a, rr, qq, rec_diag(rc));
     win[qq & (XWIN - 1)] = s2;
-    if (SCAT)
-      a.scatter_out[rc.y] = s2;
-    else
-      a.x[rr] = s2;
+    a.out[(uint32_t)rc.y] = s2;
     __builtin_amdgcn_s_waitcnt(0);
   }
   __syncthreads();  // also for an empty level: the step stays branch-free
-  refill<G, E>(a, f0, f1, j, g, RI, S);  // RI holds the rhs index of level l + LOOK
-  // keep the next index load after the last use of RI, so both live in the
-  // same register (otherwise the loop carries a copy that waits for the load)
-  __builtin_amdgcn_sched_barrier(0);
-  RI = load_ri(a, i0, i1, j);
+  refill<G, E>(a, f0, f1, j, g, S);
 }
 
-// L2 prefetch helper: a workgroup on the solver's XCD that streams the
-// storage of the levels just ahead of the solver (entries, records,
-// right-hand-side indices and right-hand sides) through the shared L2, so
-// that the solver's own pipelined loads hit there.  It reads the solver's
-// published level, stays at most HELP_AHEAD levels ahead, issues HELP_BATCH
-// independent loads per thread before using any, and folds them into a sink
-// value so the loads are not removed.  It only reads; every wait is bounded,
-// and the solver never waits for it.
-constexpr int HELP_AHEAD = 32;
-constexpr int HELP_LEVELS = 4;  // levels per helper step
-constexpr int HELP_BATCH = 8;
-
-template <int G, int E>
-__device__ void help_prefetch(const LdsTrsvArgs &a, int32_t b) {
-  const int32_t tid = (int32_t)threadIdx.x;
-  const int32_t *lpg = a.lev_ptr + (int64_t)b * a.nlev;
-  const int4 *c4 = reinterpret_cast<const int4 *>(a.ent_c);
-  unsigned acc = 0;
-  double dacc = 0.0;
-  int32_t pf = 0;
-  long idle = 0;
-  while (pf < a.nlev) {
-    const unsigned long long pr = __hip_atomic_load(a.prog + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int32_t lvl = (pr >> 32) == a.epoch ? (int32_t)(pr & 0xffffffffu) : -1;
-    const int32_t target = min(lvl + HELP_AHEAD, a.nlev);
-    if (pf >= target) {
-      if (++idle > (1L << 20)) break;
-      __builtin_amdgcn_s_sleep(2);
-      continue;
-    }
-    idle = 0;
-    const int32_t pe = min(target, pf + HELP_LEVELS);
-    const int32_t q0 = lpg[pf], q1 = lpg[pe];
-    // entries (as int4 and double2 words), records, right-hand-side indices
-    const int64_t nc4 = (int64_t)(q1 - q0) * G * E / 4, nv2 = (int64_t)(q1 - q0) * G * E / 2;
-    const int64_t c0 = (int64_t)q0 * G * E / 4, v0 = (int64_t)q0 * G * E / 2;
-    for (int64_t i = tid; i < nv2; i += (int64_t)a.bt * HELP_BATCH) {
-      double2 w[HELP_BATCH];
-      int4 c[HELP_BATCH];
-#pragma unroll
-      for (int k = 0; k < HELP_BATCH; k++) {
-        const int64_t ii = i + (int64_t)k * a.bt;
-        w[k] = ii < nv2 ? a.ent_v[v0 + ii] : make_double2(0.0, 0.0);
-        c[k] = ii < nc4 ? c4[c0 + ii] : make_int4(0, 0, 0, 0);
-      }
-#pragma unroll
-      for (int k = 0; k < HELP_BATCH; k++) {
-        dacc += w[k].x;
-        acc ^= (unsigned)c[k].x;
-      }
-    }
-    for (int32_t q = q0 + tid; q < q1; q += a.bt * HELP_BATCH) {
-      int4 rc[HELP_BATCH];
-      int32_t ri[HELP_BATCH];
-#pragma unroll
-      for (int k = 0; k < HELP_BATCH; k++) {
-        const int32_t qq = q + k * a.bt;
-        rc[k] = qq < q1 ? a.rec[qq] : make_int4(0, 0, 0, 0);
-        ri[k] = qq < q1 ? a.rhs_idx[qq] : -1;
-      }
-      double bv[HELP_BATCH];
-#pragma unroll
-      for (int k = 0; k < HELP_BATCH; k++) bv[k] = ri[k] >= 0 ? a.b[ri[k]] : 0.0;
-#pragma unroll
-      for (int k = 0; k < HELP_BATCH; k++) {
-        acc ^= (unsigned)rc[k].x;
-        dacc += bv[k];
-      }
-    }
-    pf = pe;
-  }
-  // never true for finite data; keeps the loads
-  if (acc == 0x9e3779b9u && dacc == -1.0) a.sink[blockIdx.x] = dacc;
-}
-
-template <int G, int E, bool DIAG, bool SCAT>
+template <int G, int E, bool DIAG>
 __global__ void __launch_bounds__(BT_MAX) k_trsv_lds(LdsTrsvArgs a) {
   constexpr int LOOK = look_of<E>();
   __shared__ double win[XWIN + 1];  // slot XWIN stays 0.0: the target of padding entries
-  __shared__ int32_t lp[BT_LDS_LEVELS + 3 * LOOK_MAX + 2];
-  if ((int32_t)blockIdx.x >= a.nblk) {
-    const int32_t i = (int32_t)blockIdx.x - a.hbase;
-    if (i >= 0 && i % a.hbase < a.nblk) help_prefetch<G, E>(a, i % a.hbase);
-    return;
-  }
+  __shared__ int32_t lp[BT_LDS_LEVELS + 2 * LOOK_MAX + 2];
   const int64_t base = (int64_t)blockIdx.x * a.nlev;
   const int32_t tid = (int32_t)threadIdx.x;
   const int32_t nlev = a.nlev;
   for (int32_t l = tid; l <= nlev; l += a.bt) lp[l] = a.lev_ptr[base + l];
   for (int32_t k = tid; k <= XWIN; k += a.bt) win[k] = 0.0;
   __syncthreads();
-  if (tid < 3 * LOOK + 1) lp[nlev + 1 + tid] = lp[nlev];  // empty levels past the end
+  if (tid < 2 * LOOK + 1) lp[nlev + 1 + tid] = lp[nlev];  // empty levels past the end
   __syncthreads();
   const int32_t j = tid / G, g = tid % G;
   PSet<E> S[LOOK];
-  int32_t R[LOOK];
-  // Prologue in the loop's own load order (S0 R0 S1 R1 ..., pinned by
-  // scheduling barriers): the compiler merges the state at loop entry with
-  // the state at the back edge, and any load that looked more recent at entry
-  // would be waited for on every iteration.
-  {
-    int32_t t[LOOK];
+  // prologue in the loop's own load order (pinned by scheduling barriers):
+  // the compiler merges the state at loop entry with the state at the back
+  // edge, and any load that looked more recent at entry would be waited for
+  // on every iteration
 #pragma unroll
-    for (int k = 0; k < LOOK; k++) t[k] = load_ri(a, lp[k], lp[k + 1], j);
-#pragma unroll
-    for (int k = 0; k < LOOK; k++) {
-      refill<G, E>(a, lp[k], lp[k + 1], j, g, t[k], S[k]);
-      __builtin_amdgcn_sched_barrier(0);
-      R[k] = load_ri(a, lp[k + LOOK], lp[k + LOOK + 1], j);
-      __builtin_amdgcn_sched_barrier(0);
-    }
+  for (int k = 0; k < LOOK; k++) {
+    refill<G, E>(a, lp[k], lp[k + 1], j, g, S[k]);
+    __builtin_amdgcn_sched_barrier(0);
   }
   // LOOK levels per iteration, a whole number of iterations (the extra levels
   // are empty): the loop has a single exit, the compiler keeps the steps in
   // order and the register sets keep their names
   for (int32_t l = 0; l < nlev; l += LOOK) {
-    if (a.prog && tid == 0)  // the level reached, for the prefetch helpers
-      __hip_atomic_store(a.prog + blockIdx.x, (a.epoch << 32) | (unsigned long long)l, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
-    for (int k = 0; k < LOOK; k++) pstep<G, E, DIAG, SCAT>(a, win, lp, l + k, j, g, S[k], R[k]);
+    for (int k = 0; k < LOOK; k++) pstep<G, E, DIAG>(a, win, lp, l + k, j, g, S[k]);
   }
 }
 
-template <bool DIAG, bool SCAT>
+template <bool DIAG>
 static void launch_ge(int G, int E, unsigned grid, unsigned bt, const LdsTrsvArgs &a, hipStream_t s) {
   if (E == 2) {
-    k_trsv_lds<1, 2, DIAG, SCAT><<<grid, bt, 0, s>>>(a);
+    k_trsv_lds<1, 2, DIAG><<<grid, bt, 0, s>>>(a);
     return;
   }
   if (E == 4) {
-    k_trsv_lds<1, 4, DIAG, SCAT><<<grid, bt, 0, s>>>(a);
+    k_trsv_lds<1, 4, DIAG><<<grid, bt, 0, s>>>(a);
     return;
   }
   switch (G) {
-    case 1: k_trsv_lds<1, 8, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
-    case 2: k_trsv_lds<2, 8, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
-    case 4: k_trsv_lds<4, 8, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
-    default: k_trsv_lds<8, 8, DIAG, SCAT><<<grid, bt, 0, s>>>(a); break;
+    case 1: k_trsv_lds<1, 8, DIAG><<<grid, bt, 0, s>>>(a); break;
+    case 2: k_trsv_lds<2, 8, DIAG><<<grid, bt, 0, s>>>(a); break;
+    case 4: k_trsv_lds<4, 8, DIAG><<<grid, bt, 0, s>>>(a); break;
+    default: k_trsv_lds<8, 8, DIAG><<<grid, bt, 0, s>>>(a); break;
   }
 }
 
@@ -463,13 +350,13 @@ int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s) {
   if (t.nblk == 0 || t.nrows == 0) return 0;
   const bool ge_ok = ((t.lds_e == 2 || t.lds_e == 4) && t.lds_g == 1) ||
                      (t.lds_e == 8 && (t.lds_g == 1 || t.lds_g == 2 || t.lds_g == 4 || t.lds_g == 8));
-  if (t.nlev_blk > BT_LDS_LEVELS || t.lds_bt < 64 || t.lds_bt > BT_MAX || t.lds_bt % 64 != 0 || !ge_ok)
+  if (t.nlev_blk > BT_LDS_LEVELS || t.lds_bt < 64 || t.lds_bt > BT_MAX || t.lds_bt % 64 != 0 || !ge_ok ||
+      !t.b || !t.x || !t.out_map)
     return ILU_ERR_INVALID_ARG;
   LdsTrsvArgs a;
   a.ent_c = reinterpret_cast<const int4 *>(t.lds_c);
   a.ent_v = reinterpret_cast<const double2 *>(t.lds_v);
   a.rec = reinterpret_cast<const int4 *>(t.lds_rec);
-  a.rhs_idx = t.lds_ri;
   a.lev_ptr = t.blk_lev_ptr;
   a.nlev = (int32_t)t.nlev_blk;
   a.npos = (int32_t)t.nrows;
@@ -478,24 +365,14 @@ int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s) {
   a.v = t.v;
   a.split = t.split_col;
   a.b = t.b;
-  a.x = t.x;
-  a.scatter_out = t.scatter_out;
-  a.smap = t.scatter_map;
+  a.out = t.x;
+  a.omap = t.out_map;
   a.bt = t.lds_bt;
-  a.nblk = (int32_t)t.nblk;
-  a.hbase = (int32_t)((t.nblk + 7) / 8 * 8);
-  a.prog = t.lds_helpers > 0 ? t.lds_prog : nullptr;
-  a.epoch = t.lds_epoch;
-  a.sink = t.lds_sink;
-  const unsigned g = (unsigned)(t.nblk + (t.lds_helpers > 0 ? (int64_t)a.hbase * t.lds_helpers + (a.hbase - t.nblk)
-                                                               : 0)),
-                 bt = (unsigned)t.lds_bt;
-  switch (t.role) {
-    case 0:
-    case 2: launch_ge<false, false>(t.lds_g, t.lds_e, g, bt, a, s); break;
-    case 1: launch_ge<true, true>(t.lds_g, t.lds_e, g, bt, a, s); break;
-    default: launch_ge<true, false>(t.lds_g, t.lds_e, g, bt, a, s); break;
-  }
+  const unsigned g = (unsigned)t.nblk, bt = (unsigned)t.lds_bt;
+  if (t.diag)
+    launch_ge<true>(t.lds_g, t.lds_e, g, bt, a, s);
+  else
+    launch_ge<false>(t.lds_g, t.lds_e, g, bt, a, s);
   return check_launch("trsv_lds");
 }
 
@@ -522,11 +399,11 @@ __global__ void k_max_width(const int32_t *lev_ptr, int64_t nseg, int32_t *out) 
 }
 
 // Fill one position q (q == n: the dummy position).  lev_ptr is searched for
-// the end of q's level, which bounds what the LDS window still holds.
+// the end of q's level, which bounds what the LDS window still holds.  The
+// output index of position q is omap[rows[q]].
 __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v,
                            const double *diag, int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr,
-                           int64_t nseg, int width, const int32_t *rhs_map, const int32_t *sct_map, int32_t *oc,
-                           double *ov, int4 *rec, int32_t *ri) {
+                           int64_t nseg, int width, const int32_t *omap, int32_t *oc, double *ov, int4 *rec) {
   int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q > n) return;
   const int64_t o = q * width, cap = width;
@@ -537,7 +414,6 @@ __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t
       ov[o + k] = 0.0;
     }
     rec[q] = make_int4(0, 0, __double2loint(1.0), __double2hiint(1.0));
-    ri[q] = 0;
     return;
   }
   const int32_t r = rows[q];
@@ -569,8 +445,7 @@ __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t
   const int32_t lend = lev_ptr[lo + 1];
   const bool slow = too_long || (int64_t)mind < (int64_t)lend - XWIN;
   const double d = diag ? diag[r] : 1.0;
-  rec[q] = make_int4(slow ? ~r : r, sct_map ? sct_map[r] : 0, __double2loint(d), __double2hiint(d));
-  ri[q] = rhs_map ? rhs_map[r] : r;
+  rec[q] = make_int4(slow ? ~r : r, omap[r], __double2loint(d), __double2hiint(d));
 }
 
 int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci, int64_t n, int64_t split,
@@ -586,51 +461,117 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
 
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
                     int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int width,
-                    const int32_t *rhs_map, const int32_t *sct_map, int32_t *oc, double *ov, int32_t *rec,
-                    int32_t *ri, hipStream_t s) {
+                    const int32_t *omap, int32_t *oc, double *ov, int32_t *rec, hipStream_t s) {
   k_lds_fill<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(rows, rp, ci, v, diag, n, split, pos, lev_ptr, nseg, width,
-                                                              rhs_map, sct_map, oc, ov, reinterpret_cast<int4 *>(rec),
-                                                              ri);
+                                                              omap, oc, ov, reinterpret_cast<int4 *>(rec));
   return check_launch("lds_fill");
 }
 
-// Rows whose dependencies are all solved, one thread each, summed in column
-// order from the right-hand side: the rows of W after the block-local L_B
-// solve (g' = g - W f', Section 3.2).
-__global__ void k_rows_lower(const int64_t *rp, const int32_t *ci, const double *v, int64_t row0, int64_t n,
-                             const double *b, const int32_t *bmap, double *x) {
-  const int64_t r = row0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  double s = b[bmap ? bmap[r] : r];
-  for (int64_t p = rp[r]; p < rp[r + 1]; p++) s = fma(-v[p], x[ci[p]], s);
-  x[r] = s;
+// ---- orders of the block-local solves (setup) ----
+// y[q] = x[map[q]] for index vectors
+__global__ void k_gather_i32(const int32_t *x, const int32_t *map, int64_t n, int32_t *y) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q < n) y[q] = x[map[q]];
 }
 
-int launch_rows_lower(const int64_t *rp, const int32_t *ci, const double *v, int64_t row0, int64_t n, const double *b,
-                      const int32_t *bmap, double *x, hipStream_t s) {
-  if (n <= row0) return 0;
-  k_rows_lower<<<(unsigned)((n - row0 + 255) / 256), 256, 0, s>>>(rp, ci, v, row0, n, b, bmap, x);
+int launch_gather_i32(const int32_t *x, const int32_t *map, int64_t n, int32_t *y, hipStream_t s) {
+  if (n == 0) return 0;
+  k_gather_i32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, map, n, y);
+  return check_launch("gather_i32");
+}
+
+// CSR rows [0, nrows) of rp (entries from base on) copied with each column c
+// replaced by cmap[c - col_off]
+__global__ void k_csr_remap_rp(const int64_t *rp, int64_t nrows, int64_t base, int64_t *orp) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i <= nrows) orp[i] = rp[i] - base;
+}
+__global__ void k_csr_remap_ent(const int32_t *ci, const double *v, int64_t nnz, const int32_t *cmap, int64_t col_off,
+                                int32_t *oci, double *ov) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  oci[p] = cmap[ci[p] - col_off];
+  ov[p] = v[p];
+}
+
+int launch_csr_remap(const int64_t *rp, int64_t nrows, int64_t base, const int32_t *ci, const double *v, int64_t nnz,
+                     const int32_t *cmap, int64_t col_off, int64_t *orp, int32_t *oci, double *ov, hipStream_t s) {
+  k_csr_remap_rp<<<(unsigned)((nrows + 1 + 255) / 256), 256, 0, s>>>(rp, nrows, base, orp);
+  if (nnz > 0)
+    k_csr_remap_ent<<<(unsigned)((nnz + 255) / 256), 256, 0, s>>>(ci, v, nnz, cmap, col_off, oci, ov);
+  return check_launch("csr_remap");
+}
+
+// ---- the passes between the block-local solves ----
+// y[q] = x[map[q]]
+__global__ void k_gather(const double *x, const int32_t *map, int64_t n, double *y) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q < n) y[q] = x[map[q]];
+}
+
+int launch_gather(const double *x, const int32_t *map, int64_t n, double *y, hipStream_t s) {
+  if (n == 0) return 0;
+  k_gather<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, map, n, y);
+  return check_launch("gather");
+}
+
+// Rows whose dependencies are all solved, one thread each, summed in column
+// order from the right-hand side b[bmap[i]]: the rows of W after the
+// block-local L_B solve (g' = g - W f', Section 3.2), with W's columns already
+// in the order of x; row i goes to out[omap[i]].
+__global__ void k_rows_lower(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
+                             const int32_t *bmap, const double *x, double *out, const int32_t *omap) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = b[bmap[i]];
+  for (int64_t p = rp[i]; p < rp[i + 1]; p++) s = fma(-v[p], x[ci[p]], s);
+  out[omap[i]] = s;
+}
+
+int launch_rows_lower(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
+                      const int32_t *bmap, const double *x, double *out, const int32_t *omap, hipStream_t s) {
+  if (n == 0) return 0;
+  k_rows_lower<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, v, n, b, bmap, x, out, omap);
   return check_launch("rows_lower");
 }
 
-// x[i] -= sum_j E_ij y_j over the rows of E (columns in y's numbering),
-// sequentially in column order: the f'' = f' - Z y step of the two-level solve
-__global__ void k_ext_correct(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, int64_t col_off,
-                              const double *y, double *x) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t b = rp[i], e = rp[i + 1];
-  if (b == e) return;
-  double s = x[i];
-  for (int64_t p = b; p < e; p++) s = fma(-v[p], y[ci[p] - col_off], s);
-  x[i] = s;
+// Right-hand side of the block-local U_B solve, in its position order:
+// out[q] = f[fmap[q]] - sum_j Z_rj y_j over row r = rows[q] of Z (columns in
+// y's order), sequentially in column order: the f'' = f' - Z y step of the
+// two-level solve (Section 3.2).
+__global__ void k_upper_rhs(const int32_t *rows, const int32_t *fmap, int64_t n, const double *f, const int64_t *rp,
+                            const int32_t *ci, const double *v, const double *y, double *out) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int32_t r = rows[q];
+  double s = f[fmap[q]];
+  for (int64_t p = rp[r]; p < rp[r + 1]; p++) s = fma(-v[p], y[ci[p]], s);
+  out[q] = s;
 }
 
-int launch_ext_correct(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, int64_t col_off,
-                       const double *y, double *x, hipStream_t s) {
+int launch_upper_rhs(const int32_t *rows, const int32_t *fmap, int64_t n, const double *f, const int64_t *rp,
+                     const int32_t *ci, const double *v, const double *y, double *out, hipStream_t s) {
   if (n == 0) return 0;
-  k_ext_correct<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, v, n, col_off, y, x);
-  return check_launch("ext_correct");
+  k_upper_rhs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rows, fmap, n, f, rp, ci, v, y, out);
+  return check_launch("upper_rhs");
+}
+
+// z[mb[q]] = u[q] (q < nb) and z[ms[q]] = y[q] (q < ns): both halves of the
+// preconditioned vector back to the caller's numbering
+__global__ void k_finish(const double *u, const int32_t *mb, int64_t nb, const double *y, const int32_t *ms,
+                         int64_t ns, double *z) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nb)
+    z[mb[i]] = u[i];
+  else if (i < nb + ns)
+    z[ms[i - nb]] = y[i - nb];
+}
+
+int launch_finish(const double *u, const int32_t *mb, int64_t nb, const double *y, const int32_t *ms, int64_t ns,
+                  double *z, hipStream_t s) {
+  if (nb + ns == 0) return 0;
+  k_finish<<<(unsigned)((nb + ns + 255) / 256), 256, 0, s>>>(u, mb, nb, y, ms, ns, z);
+  return check_launch("finish");
 }
 
 int launch_trsv(const TrsvLaunch &t, hipStream_t s) {
