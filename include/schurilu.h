@@ -182,9 +182,12 @@ int ilu_export(ilu_precond_t *P, int32_t what, void *h_buf, int64_t *len);
 
 /*
  * Kernel timing (a profiling aid for benchmarks; process-global, not
- * thread-safe).  While on, each launch of the solve-phase kernels below is
- * bracketed by HIP events on the stream it is launched on; durations are
- * resolved at the next host synchronisation.  ilu_kernel_stats returns, for
+ * thread-safe).  ilu_kernel_timing(classes) times the kernel classes whose
+ * bits are set in `classes` (bit k = class k below, ILU_K_ALL = every class,
+ * 0 = off): each of their launches is bracketed by HIP events on the stream
+ * it is launched on, and durations are resolved at the next host
+ * synchronisation.  The events add a little time to every launch they
+ * bracket, so time only the classes you need.  ilu_kernel_stats returns, for
  * one kernel class, the summed duration, the number of launches and the
  * summed algorithmic bytes (each stored entry, row pointer, right-hand side
  * and solution element counted once per launch).  reset != 0 clears it.
@@ -197,7 +200,8 @@ int ilu_export(ilu_precond_t *P, int32_t what, void *h_buf, int64_t *len);
 #define ILU_K_SPMV_COFF 5 /* C_off y in the reduced-system operator              */
 #define ILU_K_MGS 6      /* one fused modified Gram-Schmidt pass                  */
 #define ILU_K_COUNT 7
-void ilu_kernel_timing(int32_t on);
+#define ILU_K_ALL ((1 << ILU_K_COUNT) - 1)
+void ilu_kernel_timing(int32_t classes);
 int ilu_kernel_stats(int32_t kind, double *total_ms, int64_t *launches, double *bytes, int32_t reset);
 
 /* Sizes: n, n_B (interior rows), n_S (interface rows), nparts. */

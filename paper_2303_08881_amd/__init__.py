@@ -27,4 +27,5 @@ from .binding import (  # noqa: F401
     lib,
     LIB_PATH,
     EXPORT,
+    KERNEL_ALL,
 )

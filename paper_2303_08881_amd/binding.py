@@ -24,6 +24,8 @@ OK, NOT_CONVERGED = 0, 1
 EXPORT = dict(perm=(0, np.int32), iperm=(1, np.int32), iface=(2, np.uint8), offsets=(3, np.int64),
               DB=(16, np.float64), DS=(29, np.float64), lev_LB=(40, np.int32), lev_UB=(41, np.int32),
               lev_LS=(42, np.int32), lev_US=(43, np.int32), schedule=(44, np.int32))
+# kernel classes of ilu_kernel_timing / ilu_kernel_stats (bit k = class k)
+KERNEL_ALL = (1 << 7) - 1
 _CSR_CODES = dict(LB=10, UB=13, Z=17, W=20, LS=23, US=26, Coff=30)
 _FIELD_T = (np.int64, np.int32, np.float64)
 

@@ -98,7 +98,7 @@ struct PendingTiming {
   int kind;
   double bytes;
 };
-static bool g_timing = false;
+static uint32_t g_timing = 0;  // bit k: kernel class k is timed
 static KStat g_kstat[ILU_K_COUNT];
 static std::vector<PendingTiming> g_pending;
 static std::vector<hipEvent_t> g_event_pool;
@@ -130,7 +130,7 @@ static void timing_collect() {
 
 template <typename F>
 static int timed(int kind, double bytes, hipStream_t s, F &&launch) {
-  if (!g_timing) return launch();
+  if (!((g_timing >> kind) & 1u)) return launch();
   hipEvent_t a = pool_event(), b = pool_event();
   if (!a || !b) return launch();
   (void)hipEventRecord(a, s);
@@ -200,7 +200,7 @@ struct ilu_precond {
   // U_B takes bU (U_B order, f' - Z y) into uU; k_finish scatters uU and yS.
   bool block_mode = false;
   Csr Wr, Zr, Coffr;  // W (columns in L_B order), Z and C_off (columns in U_S order)
-  int32_t *gmapL = nullptr, *fmapU = nullptr, *finB = nullptr, *finS = nullptr;
+  int32_t *gmapL = nullptr, *gmapW = nullptr, *fmapU = nullptr, *finB = nullptr, *finS = nullptr;
   double *bL = nullptr, *fL = nullptr, *gS = nullptr, *yS = nullptr, *bU = nullptr, *uU = nullptr;
   // reduced-system GMRES
   double *iV = nullptr, *it1 = nullptr, *it2 = nullptr, *iH = nullptr, *ics = nullptr, *isn = nullptr,
@@ -605,31 +605,22 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   return 0;
 }
 
-// rows [row0, row0 + nrows) of A as a CSR of their own, columns c -> cmap[c - col_off]
-static int csr_remap(Mem &mem, const Csr &A, int64_t row0, int64_t nrows, const int32_t *cmap, int64_t col_off,
-                     Csr *out, hipStream_t s) {
+// A CSR whose row q is row row0 + rows[q] of A, columns c -> cmap[c - col_off]
+static int csr_permute(Mem &mem, Mem &tmp, const Csr &A, int64_t row0, const int32_t *rows, int64_t nrows,
+                       const int32_t *cmap, int64_t col_off, Csr *out, void *stmp, size_t stmpb, hipStream_t s) {
   out->n = nrows;
-  int64_t b[2] = {0, 0};
-  if (nrows > 0) {
-    HIPCK(hipMemcpyAsync(&b[0], A.rp + row0, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIPCK(hipMemcpyAsync(&b[1], A.rp + row0 + nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIPCK(hipStreamSynchronize(s));
-  }
-  out->nnz = b[1] - b[0];
-  RC(mem.alloc(&out->rp, nrows + 1));
+  int64_t *len;
+  RC(tmp.alloc(&len, nrows));
+  RC(launch_csr_perm_len(A.rp, row0, rows, nrows, len, s));
+  RC(make_rp(mem, len, nrows, &out->rp, &out->nnz, stmp, stmpb, s));
   RC(mem.alloc(&out->ci, out->nnz));
   RC(mem.alloc(&out->v, out->nnz));
-  if (nrows > 0)
-    RC(launch_csr_remap(A.rp + row0, nrows, b[0], A.ci + b[0], A.v + b[0], out->nnz, cmap, col_off, out->rp, out->ci,
-                        out->v, s));
-  else
-    HIPCK(hipMemsetAsync(out->rp, 0, sizeof(int64_t), s));
-  return 0;
+  return launch_csr_perm_ent(A.rp, A.ci, A.v, row0, rows, nrows, cmap, col_off, out->rp, out->ci, out->v, s);
 }
 
 // The orders that connect the four block-local solves (see ilu_precond):
 // index maps, the renumbered copies of W, Z and C_off, and the vectors.
-static int build_block_flow(ilu_precond *P, hipStream_t s) {
+static int build_block_flow(ilu_precond *P, Mem &tmp, void *stmp, size_t stmpb, hipStream_t s) {
   Mem &mem = P->mem;
   const int64_t nB = P->nB, nS = P->nS;
   RC(mem.alloc(&P->bL, nB));
@@ -642,13 +633,17 @@ static int build_block_flow(ilu_precond *P, hipStream_t s) {
   RC(mem.alloc(&P->fmapU, nB));
   RC(mem.alloc(&P->finB, nB));
   RC(mem.alloc(&P->finS, nS));
+  RC(mem.alloc(&P->gmapW, nS));
   RC(launch_gather_i32(P->perm, P->sL1.blk_rows, nB, P->gmapL, s));      // r index of each L_B position
   RC(launch_gather_i32(P->sL1.pos, P->sU1.blk_rows, nB, P->fmapU, s));   // L_B position of each U_B position
   RC(launch_gather_i32(P->perm, P->sU1.blk_rows, nB, P->finB, s));       // z index of each U_B position
   RC(launch_gather_i32(P->perm + nB, P->sUS.blk_rows, nS, P->finS, s));  // z index of each U_S position
-  RC(csr_remap(mem, P->L1, nB, nS, P->sL1.pos, 0, &P->Wr, s));
-  RC(csr_remap(mem, P->Zb, 0, nB, P->sUS.pos, nB, &P->Zr, s));
-  RC(csr_remap(mem, P->Coff, 0, nS, P->sUS.pos, 0, &P->Coffr, s));
+  RC(launch_gather_i32(P->perm + nB, P->sLS.blk_rows, nS, P->gmapW, s));  // r index of each L_S position
+  // W rows in L_S order (columns in L_B order); Z rows in U_B order and C_off
+  // rows in L_S order (columns in U_S order)
+  RC(csr_permute(mem, tmp, P->L1, nB, P->sLS.blk_rows, nS, P->sL1.pos, 0, &P->Wr, stmp, stmpb, s));
+  RC(csr_permute(mem, tmp, P->Zb, 0, P->sU1.blk_rows, nB, P->sUS.pos, nB, &P->Zr, stmp, stmpb, s));
+  RC(csr_permute(mem, tmp, P->Coff, 0, P->sLS.blk_rows, nS, P->sUS.pos, 0, &P->Coffr, stmp, stmpb, s));
   HIPCK(hipStreamSynchronize(s));
   return 0;
 }
@@ -922,7 +917,7 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
     RC(build_block(P, tmp, P->U1, P->sU1, bs_int, nullptr, 0, P->DB, nB, nullptr, s, "levels U"));
     RC(build_block(P, tmp, P->US, P->sUS, bs_loc, nullptr, 0, P->DS, INT64_MAX, nullptr, s, "levels U_S"));
     RC(build_block(P, tmp, P->LS, P->sLS, bs_loc, nullptr, 0, nullptr, INT64_MAX, P->sUS.pos, s, "levels L_S"));
-    RC(build_block_flow(P, s));
+    RC(build_block_flow(P, tmp, stmp, stmpb, s));
   }
 
   // 7. workspaces
@@ -1022,11 +1017,10 @@ static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t 
   RC(launch_scale_copy(V, nullptr, beta, V, nS, nullptr, s));
   for (int j = 0; j < k; j++) {
     double *vj = V + (int64_t)j * nS, *w = V + (int64_t)(j + 1) * nS;
-    // D^-1 C_off v_j: the rows go to L_S position order in block mode
+    // C_off v_j (in block mode C_off's rows are in L_S order, its columns in U_S order)
     const Csr &C = P->block_mode ? P->Coffr : P->Coff;
-    RC(timed(ILU_K_SPMV_COFF, spmv_bytes(nS, C.nnz, false), s, [&] {
-      return launch_spmv_map(C.rp, C.ci, C.v, nS, vj, P->it1, P->block_mode ? P->sLS.pos : nullptr, s);
-    }));
+    RC(timed(ILU_K_SPMV_COFF, spmv_bytes(nS, C.nnz, false), s,
+             [&] { return launch_spmv(C.rp, C.ci, C.v, nS, vj, P->it1, s); }));
     RC(trsv(P, P->sLS, P->LS, nullptr, 0, P->it1, nullptr, P->it2, nullptr, nullptr, s, 2));
     RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, P->it2, nullptr, P->it2, nullptr, nullptr, s, 3));
     double *pc = P->ipa, *pn = P->ipb;
@@ -1049,7 +1043,7 @@ static int apply_block(ilu_precond *P, const double *r, double *z, hipStream_t s
   // f' = L_B^-1 r_B, then g' = r_S - W f' in L_S position order
   RC(launch_gather(r, P->gmapL, nB, P->bL, s));
   RC(trsv(P, P->sL1, P->L1, nullptr, 0, P->bL, nullptr, P->fL, nullptr, nullptr, s, 0, [&] {
-    return launch_rows_lower(P->Wr.rp, P->Wr.ci, P->Wr.v, nS, r, P->perm + nB, P->fL, P->gS, P->sLS.pos, s);
+    return launch_rows_lower(P->Wr.rp, P->Wr.ci, P->Wr.v, nS, r, P->gmapW, P->fL, P->gS, s);
   }));
   if (nS > 0) {
     if (P->opt.method == ILU_METHOD_SCHUR) {
@@ -1060,7 +1054,7 @@ static int apply_block(ilu_precond *P, const double *r, double *z, hipStream_t s
     }
   }
   // f'' = f' - Z y in U_B position order, u = U_B^-1 f'', then both halves to z
-  RC(launch_upper_rhs(P->sU1.blk_rows, P->fmapU, nB, P->fL, P->Zr.rp, P->Zr.ci, P->Zr.v, P->yS, P->bU, s));
+  RC(launch_upper_rhs(P->fmapU, nB, P->fL, P->Zr.rp, P->Zr.ci, P->Zr.v, P->yS, P->bU, s));
   RC(trsv(P, P->sU1, P->U1, P->DB, nB, P->bU, nullptr, P->uU, nullptr, nullptr, s, 1));
   return launch_finish(P->uU, P->finB, nB, P->yS, P->finS, nS, z, s);
 }
@@ -1233,9 +1227,9 @@ int fgmres_solve(const ilu_csr_t *A, ilu_precond_t *P, const double *d_b, double
   return rc;
 }
 
-void ilu_kernel_timing(int32_t on) {
-  if (!on) timing_collect();
-  g_timing = on != 0;
+void ilu_kernel_timing(int32_t classes) {
+  if (!classes) timing_collect();
+  g_timing = (uint32_t)classes & (uint32_t)ILU_K_ALL;
 }
 
 int ilu_kernel_stats(int32_t kind, double *total_ms, int64_t *launches, double *bytes, int32_t reset) {

@@ -20,14 +20,13 @@ namespace silu {
 
 constexpr int RED_THREADS = 256;
 
-// row i of the product goes to y[omap ? omap[i] : i]
 __global__ void k_spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x,
-                       double *y, const int32_t *omap) {
+                       double *y) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
   for (int64_t p = rp[i]; p < rp[i + 1]; p++) s = fma(v[p], x[ci[p]], s);
-  y[omap ? omap[i] : i] = s;
+  y[i] = s;
 }
 
 __global__ void k_residual(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
@@ -42,14 +41,7 @@ __global__ void k_residual(const int64_t *rp, const int32_t *ci, const double *v
 int launch_spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x, double *y,
                 hipStream_t s) {
   if (n == 0) return 0;
-  k_spmv<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, v, n, x, y, nullptr);
-  return check_launch("spmv");
-}
-
-int launch_spmv_map(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x, double *y,
-                    const int32_t *omap, hipStream_t s) {
-  if (n == 0) return 0;
-  k_spmv<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, v, n, x, y, omap);
+  k_spmv<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, v, n, x, y);
   return check_launch("spmv");
 }
 

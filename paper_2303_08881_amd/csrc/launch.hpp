@@ -145,16 +145,20 @@ int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s);
 // y[q] = x[map[q]]
 int launch_gather(const double *x, const int32_t *map, int64_t n, double *y, hipStream_t s);
 int launch_gather_i32(const int32_t *x, const int32_t *map, int64_t n, int32_t *y, hipStream_t s);
-// rows [0, nrows) of a CSR (rp[0] == base) with each column c replaced by cmap[c - col_off]
-int launch_csr_remap(const int64_t *rp, int64_t nrows, int64_t base, const int32_t *ci, const double *v, int64_t nnz,
-                     const int32_t *cmap, int64_t col_off, int64_t *orp, int32_t *oci, double *ov, hipStream_t s);
+// a CSR with rows reordered (new row q = old row row0 + rows[q]) and columns c -> cmap[c - col_off]:
+// the row lengths, then (orp from their scan) the entries in their old order
+int launch_csr_perm_len(const int64_t *rp, int64_t row0, const int32_t *rows, int64_t nrows, int64_t *len,
+                        hipStream_t s);
+int launch_csr_perm_ent(const int64_t *rp, const int32_t *ci, const double *v, int64_t row0, const int32_t *rows,
+                        int64_t nrows, const int32_t *cmap, int64_t col_off, const int64_t *orp, int32_t *oci,
+                        double *ov, hipStream_t s);
 // n rows of a unit lower factor whose dependencies are all solved (columns in
-// x's order): out[omap[i]] = b[bmap[i]] - sum_j l_ij x_j in column order
+// x's order): out[i] = b[bmap[i]] - sum_j l_ij x_j in column order
 int launch_rows_lower(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
-                      const int32_t *bmap, const double *x, double *out, const int32_t *omap, hipStream_t s);
-// out[q] = f[fmap[q]] - sum_j Z_rj y_j over row r = rows[q] of Z, in column order
-int launch_upper_rhs(const int32_t *rows, const int32_t *fmap, int64_t n, const double *f, const int64_t *rp,
-                     const int32_t *ci, const double *v, const double *y, double *out, hipStream_t s);
+                      const int32_t *bmap, const double *x, double *out, hipStream_t s);
+// out[q] = f[fmap[q]] - sum_j Z_qj y_j, in column order
+int launch_upper_rhs(const int32_t *fmap, int64_t n, const double *f, const int64_t *rp, const int32_t *ci,
+                     const double *v, const double *y, double *out, hipStream_t s);
 // z[mb[q]] = u[q] (q < nb), z[ms[q]] = y[q] (q < ns)
 int launch_finish(const double *u, const int32_t *mb, int64_t nb, const double *y, const int32_t *ms, int64_t ns,
                   double *z, hipStream_t s);
@@ -176,9 +180,6 @@ int launch_i64_to_i32(const int64_t *in, int32_t *out, int64_t n, hipStream_t s)
 // ---- krylov.hip ----
 int launch_spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x, double *y,
                 hipStream_t s);
-// y[omap[i]] = (row i of the product)
-int launch_spmv_map(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x, double *y,
-                    const int32_t *omap, hipStream_t s);
 int launch_residual(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
                     const double *x, double *r, hipStream_t s);
 constexpr int RED_BLOCKS = 512;  // fixed grid of the deterministic reductions

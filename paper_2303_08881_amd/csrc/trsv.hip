@@ -480,26 +480,42 @@ int launch_gather_i32(const int32_t *x, const int32_t *map, int64_t n, int32_t *
   return check_launch("gather_i32");
 }
 
-// CSR rows [0, nrows) of rp (entries from base on) copied with each column c
-// replaced by cmap[c - col_off]
-__global__ void k_csr_remap_rp(const int64_t *rp, int64_t nrows, int64_t base, int64_t *orp) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i <= nrows) orp[i] = rp[i] - base;
+// A CSR with its rows reordered (new row q = old row row0 + rows[q]) and each
+// column c replaced by cmap[c - col_off]; the entries of a row keep their
+// order.  First the row lengths, then (after a scan) the entries.
+__global__ void k_csr_perm_len(const int64_t *rp, int64_t row0, const int32_t *rows, int64_t nrows, int64_t *len) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= nrows) return;
+  const int64_t r = row0 + rows[q];
+  len[q] = rp[r + 1] - rp[r];
 }
-__global__ void k_csr_remap_ent(const int32_t *ci, const double *v, int64_t nnz, const int32_t *cmap, int64_t col_off,
-                                int32_t *oci, double *ov) {
-  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (p >= nnz) return;
-  oci[p] = cmap[ci[p] - col_off];
-  ov[p] = v[p];
+__global__ void k_csr_perm_ent(const int64_t *rp, const int32_t *ci, const double *v, int64_t row0,
+                               const int32_t *rows, int64_t nrows, const int32_t *cmap, int64_t col_off,
+                               const int64_t *orp, int32_t *oci, double *ov) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= nrows) return;
+  const int64_t r = row0 + rows[q];
+  int64_t o = orp[q];
+  for (int64_t p = rp[r]; p < rp[r + 1]; p++, o++) {
+    oci[o] = cmap[ci[p] - col_off];
+    ov[o] = v[p];
+  }
 }
 
-int launch_csr_remap(const int64_t *rp, int64_t nrows, int64_t base, const int32_t *ci, const double *v, int64_t nnz,
-                     const int32_t *cmap, int64_t col_off, int64_t *orp, int32_t *oci, double *ov, hipStream_t s) {
-  k_csr_remap_rp<<<(unsigned)((nrows + 1 + 255) / 256), 256, 0, s>>>(rp, nrows, base, orp);
-  if (nnz > 0)
-    k_csr_remap_ent<<<(unsigned)((nnz + 255) / 256), 256, 0, s>>>(ci, v, nnz, cmap, col_off, oci, ov);
-  return check_launch("csr_remap");
+int launch_csr_perm_len(const int64_t *rp, int64_t row0, const int32_t *rows, int64_t nrows, int64_t *len,
+                        hipStream_t s) {
+  if (nrows == 0) return 0;
+  k_csr_perm_len<<<(unsigned)((nrows + 255) / 256), 256, 0, s>>>(rp, row0, rows, nrows, len);
+  return check_launch("csr_perm_len");
+}
+
+int launch_csr_perm_ent(const int64_t *rp, const int32_t *ci, const double *v, int64_t row0, const int32_t *rows,
+                        int64_t nrows, const int32_t *cmap, int64_t col_off, const int64_t *orp, int32_t *oci,
+                        double *ov, hipStream_t s) {
+  if (nrows == 0) return 0;
+  k_csr_perm_ent<<<(unsigned)((nrows + 255) / 256), 256, 0, s>>>(rp, ci, v, row0, rows, nrows, cmap, col_off, orp,
+                                                                  oci, ov);
+  return check_launch("csr_perm_ent");
 }
 
 // ---- the passes between the block-local solves ----
@@ -517,42 +533,41 @@ int launch_gather(const double *x, const int32_t *map, int64_t n, double *y, hip
 
 // Rows whose dependencies are all solved, one thread each, summed in column
 // order from the right-hand side b[bmap[i]]: the rows of W after the
-// block-local L_B solve (g' = g - W f', Section 3.2), with W's columns already
-// in the order of x; row i goes to out[omap[i]].
+// block-local L_B solve (g' = g - W f', Section 3.2), with W's rows in the
+// order of out and its columns in the order of x.
 __global__ void k_rows_lower(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
-                             const int32_t *bmap, const double *x, double *out, const int32_t *omap) {
+                             const int32_t *bmap, const double *x, double *out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = b[bmap[i]];
   for (int64_t p = rp[i]; p < rp[i + 1]; p++) s = fma(-v[p], x[ci[p]], s);
-  out[omap[i]] = s;
+  out[i] = s;
 }
 
 int launch_rows_lower(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
-                      const int32_t *bmap, const double *x, double *out, const int32_t *omap, hipStream_t s) {
+                      const int32_t *bmap, const double *x, double *out, hipStream_t s) {
   if (n == 0) return 0;
-  k_rows_lower<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, v, n, b, bmap, x, out, omap);
+  k_rows_lower<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, v, n, b, bmap, x, out);
   return check_launch("rows_lower");
 }
 
 // Right-hand side of the block-local U_B solve, in its position order:
-// out[q] = f[fmap[q]] - sum_j Z_rj y_j over row r = rows[q] of Z (columns in
-// y's order), sequentially in column order: the f'' = f' - Z y step of the
+// out[q] = f[fmap[q]] - sum_j Z_qj y_j (Z's rows in that order, its columns
+// in y's order), sequentially in column order: the f'' = f' - Z y step of the
 // two-level solve (Section 3.2).
-__global__ void k_upper_rhs(const int32_t *rows, const int32_t *fmap, int64_t n, const double *f, const int64_t *rp,
-                            const int32_t *ci, const double *v, const double *y, double *out) {
+__global__ void k_upper_rhs(const int32_t *fmap, int64_t n, const double *f, const int64_t *rp, const int32_t *ci,
+                            const double *v, const double *y, double *out) {
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q >= n) return;
-  const int32_t r = rows[q];
   double s = f[fmap[q]];
-  for (int64_t p = rp[r]; p < rp[r + 1]; p++) s = fma(-v[p], y[ci[p]], s);
+  for (int64_t p = rp[q]; p < rp[q + 1]; p++) s = fma(-v[p], y[ci[p]], s);
   out[q] = s;
 }
 
-int launch_upper_rhs(const int32_t *rows, const int32_t *fmap, int64_t n, const double *f, const int64_t *rp,
-                     const int32_t *ci, const double *v, const double *y, double *out, hipStream_t s) {
+int launch_upper_rhs(const int32_t *fmap, int64_t n, const double *f, const int64_t *rp, const int32_t *ci,
+                     const double *v, const double *y, double *out, hipStream_t s) {
   if (n == 0) return 0;
-  k_upper_rhs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rows, fmap, n, f, rp, ci, v, y, out);
+  k_upper_rhs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(fmap, n, f, rp, ci, v, y, out);
   return check_launch("upper_rhs");
 }
 
