@@ -6,7 +6,8 @@
 //  * every dependency wait is bounded: after SPIN_LIMIT polls it records
 //    ILU_ERR_TIMEOUT in the status word and gives up, so no launch can hang;
 //  * cross-workgroup handoffs use agent-scope release stores and relaxed
-//    polls followed by one agent-scope acquire fence;
+//    polls, followed either by one agent-scope acquire fence or by
+//    device-scope loads of exactly the data handed over;
 //  * floating-point contraction is off for the whole library (-ffp-contract=off)
 //    and every fused multiply-add is an explicit fma(), so the rounding order of
 //    each row operation is fixed and matches the sequential definition.
@@ -51,6 +52,14 @@ __device__ inline void st_release(int *p, int v) {
 template <typename T>
 __device__ inline void st_dev(T *p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Device-scope load: reads the coherent copy (what st_dev and the stores
+// before a device-scope release wrote) without the cache invalidation of an
+// acquire fence.  A wave that has seen another wave's release flag reads
+// that wave's data this way.
+template <typename T>
+__device__ inline T ld_dev(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 __device__ inline void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }

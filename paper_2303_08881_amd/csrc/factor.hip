@@ -20,8 +20,9 @@
 //     order.  A ticket covers CHUNK consecutive local rows of one subdomain,
 //     processed one after the other by the same wave, and tickets interleave
 //     the subdomains round-robin;
-//   * a row waits on the per-row completion flag of each pivot k
-//     (agent-scope release/acquire); every wait is bounded;
+//   * a row waits on the per-row completion flag of each pivot k (agent-scope
+//     release, then device-scope loads of the pivot row); every wait is
+//     bounded;
 //   * the working row is kept sorted by column in LDS; the pivot walk is a
 //     scan of its prefix; fill is merged in place (one wave: read all, then
 //     write all);
@@ -204,9 +205,12 @@ __global__ void __launch_bounds__(WAVE, 2) k_factor_rows(FactArgs a) {
         const int32_t k = uniform_i32(pos < len ? wc[pos] : 0x7fffffff);
         if (k >= lim) break;
         // Dependencies are waited for in rounds: the lanes wait together for
-        // every pivot still ahead in the working row, then one acquire makes
-        // all their rows visible.  A fill that becomes a pivot later (marked
-        // by bit 1 of wd) starts the next round when it is reached.
+        // every pivot still ahead in the working row.  A fill that becomes a
+        // pivot later (marked by bit 1 of wd) starts the next round when it
+        // is reached.  A pivot row's D, length and U row are then read with
+        // device-scope loads: its wave wrote them with write-through stores
+        // before releasing its flag, so no acquire fence (which would drop
+        // this XCD's cached lines for every wave on it) is needed.
         //
         // The round also fetches, all in parallel, the diagonal and the U row
         // of the first WAVE pivots from pos on into an LDS cache (as many as
@@ -229,7 +233,6 @@ __global__ void __launch_bounds__(WAVE, 2) k_factor_rows(FactArgs a) {
             failed = true;
             break;
           }
-          fence_acquire();
           const int x = pos + lane;
           const int32_t kx = x < len ? wc[x] : 0x7fffffff;
           const bool piv = kx < lim;  // the pivots ahead are a prefix of [pos, len)
@@ -237,9 +240,9 @@ __global__ void __launch_bounds__(WAVE, 2) k_factor_rows(FactArgs a) {
           int64_t ub = 0;
           int ul = 0;
           if (piv) {
-            dk = a.D[kx];
-            ub = a.Urp[kx];
-            ul = a.Ulen[kx];
+            dk = ld_dev(a.D + kx);
+            ub = a.Urp[kx];  // fixed before the launch
+            ul = ld_dev(a.Ulen + kx);
           }
           // exclusive prefix sum of the row lengths over the lanes
           int off = ul;
@@ -255,8 +258,8 @@ __global__ void __launch_bounds__(WAVE, 2) k_factor_rows(FactArgs a) {
 #pragma unroll
           for (int q = 0; q < FACT_UROW; q++) {
             if (cached && q < ul) {
-              uc_[q] = a.Uc[ub + q];
-              uv_[q] = a.Uv[ub + q];
+              uc_[q] = ld_dev(a.Uc + ub + q);
+              uv_[q] = ld_dev(a.Uv + ub + q);
             }
           }
 #pragma unroll
@@ -267,8 +270,8 @@ __global__ void __launch_bounds__(WAVE, 2) k_factor_rows(FactArgs a) {
             }
           }
           for (int q = FACT_UROW; cached && q < ul; q++) {
-            cc[off + q] = a.Uc[ub + q];
-            cv[off + q] = a.Uv[ub + q];
+            cc[off + q] = ld_dev(a.Uc + ub + q);
+            cv[off + q] = ld_dev(a.Uv + ub + q);
           }
           if (cached) {
             tD[lane] = dk;
