@@ -70,6 +70,8 @@ def kernel_instance(cls: str, sched) -> str | None:
         k, diag = TRSV_ROLE[cls]
         if sched is None or not sched[4 * k]:
             return None
+        if cls == "trsv_LS" and len(sched) > 16 and sched[16]:  # L_S and U_S in one launch
+            return f"void silu::k_trsv_lds_pair<{sched[9]}, {sched[10]}>"
         return f"void silu::k_trsv_lds<{sched[4 * k + 1]}, {sched[4 * k + 2]}, {diag}>"
     return {"spmv_A": "silu::k_spmv(", "spmv_Coff": "silu::k_spmv(", "mgs": "void silu::k_mgs_step<"}.get(cls)
 

@@ -174,9 +174,10 @@ const char *ilu_last_error(void);
  *   30 C_off (interface rows, other subdomains' interface columns);
  *   16 diag of U_B [double n_B], 29 diag of U_S [double n_S];
  *   40..43 level of each row of L_B, U_B, L_S, U_S [int32];
- *   44 schedule of the L_B, U_B, L_S, U_S solves [int32 16]: for each, 1 if
+ *   44 schedule of the L_B, U_B, L_S, U_S solves [int32 20]: for each, 1 if
  *      solved block-locally (one workgroup per subdomain), lanes per row,
- *      entries per lane, threads per workgroup.
+ *      entries per lane, threads per workgroup; then 1 if L_S and U_S run as
+ *      one launch, and three zeros.
  */
 int ilu_export(ilu_precond_t *P, int32_t what, void *h_buf, int64_t *len);
 
@@ -194,7 +195,8 @@ int ilu_export(ilu_precond_t *P, int32_t what, void *h_buf, int64_t *len);
  */
 #define ILU_K_TRSV_LB 0  /* forward solve with L_B, rows of W included (one extra level) */
 #define ILU_K_TRSV_UB 1  /* backward solve with U_B, Z columns included           */
-#define ILU_K_TRSV_LS 2  /* forward solve with the local Schur factors L_S        */
+#define ILU_K_TRSV_LS 2  /* forward solve with the local Schur factors L_S (with  */
+                         /* U_S when both run in one launch; bytes of both)      */
 #define ILU_K_TRSV_US 3  /* backward solve with U_S                               */
 #define ILU_K_SPMV 4     /* y = A x in the outer Krylov loop                      */
 #define ILU_K_SPMV_COFF 5 /* C_off y in the reduced-system operator              */

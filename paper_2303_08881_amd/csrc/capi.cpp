@@ -661,14 +661,12 @@ static double trsv_bytes(const Schedule &S, const Csr &T, bool diag, bool bmap, 
   return b;
 }
 
-// Block-local schedules take b in position order and write x through the
-// schedule's output map; `after` runs inside the timed region (the W rows).
-static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, int64_t split, const double *b,
-                const int32_t *bmap, double *x, double *scat, const int32_t *smap, hipStream_t s, int role,
-                const std::function<int()> &after = nullptr) {
-  if (S.nrows == 0) return 0;
+// Launch description of one solve.  Block-local schedules take b in position
+// order and write x through the schedule's output map.
+static TrsvLaunch make_launch(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, int64_t split,
+                              const double *b, const int32_t *bmap, double *x, double *scat, const int32_t *smap,
+                              int role) {
   TrsvLaunch t;
-  if (!S.use_block) S.epoch++;
   t.nrows = S.nrows;
   t.rows = S.rows;
   t.chunk_start = S.chunk_start;
@@ -676,9 +674,7 @@ static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, i
   t.nchunks = S.nchunks;
   t.level_ptr = S.level_ptr;
   t.level_done = S.level_done;
-  t.epoch = S.epoch;
   t.ticket = S.ticket;
-  t.ticket_base = S.ticket_base;
   t.rp = T.rp;
   t.ci = T.ci;
   t.v = T.v;
@@ -692,10 +688,7 @@ static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, i
   t.status = P->status;
   t.max_waves = S.grid;
   t.role = role;
-  if (!S.use_block) S.ticket_base += (unsigned long long)(S.nchunks + S.grid);
-  const double bytes = trsv_bytes(S, T, diag != nullptr, bmap != nullptr, scat != nullptr);
   if (S.use_block) {
-    if (bmap || scat) return fail(ILU_ERR_INVALID_ARG, "internal: block-local solves take no gather or scatter map");
     t.nblk = S.nblk;
     t.nlev_blk = S.nlev;
     t.blk_rows = S.blk_rows;
@@ -709,13 +702,47 @@ static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, i
     t.lds_bt = S.lds_bt;
     t.split_col = S.ext_col;
     t.nrows = S.nloc;
+  }
+  return t;
+}
+
+// `after` runs inside the timed region (the W rows of the L_B solve).
+static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, int64_t split, const double *b,
+                const int32_t *bmap, double *x, double *scat, const int32_t *smap, hipStream_t s, int role,
+                const std::function<int()> &after = nullptr) {
+  if (S.nrows == 0) return 0;
+  TrsvLaunch t = make_launch(P, S, T, diag, split, b, bmap, x, scat, smap, role);
+  const double bytes = trsv_bytes(S, T, diag != nullptr, bmap != nullptr, scat != nullptr);
+  if (S.use_block) {
+    if (bmap || scat) return fail(ILU_ERR_INVALID_ARG, "internal: block-local solves take no gather or scatter map");
     return timed(ILU_K_TRSV_LB + role, bytes, s, [&] {
       RC(launch_trsv_lds(t, s));
       if (after) RC(after());
       return 0;
     });
   }
+  S.epoch++;
+  t.epoch = S.epoch;
+  t.ticket_base = S.ticket_base;
+  S.ticket_base += (unsigned long long)(S.nchunks + S.grid);
   return timed(ILU_K_TRSV_LB + role, bytes, s, [&] { return launch_trsv(t, s); });
+}
+
+// x = U_S^-1 L_S^-1 b (x may be b in the global mode; in block mode b is in
+// L_S order and x in U_S order): one launch when both solves are block-local
+// with the same lane shape, timed as the L_S class with the bytes of both.
+static int trsv_schur(ilu_precond *P, const double *b, double *x, hipStream_t s) {
+  if (P->nS == 0) return 0;
+  if (P->block_mode) {
+    TrsvLaunch lo = make_launch(P, P->sLS, P->LS, nullptr, 0, b, nullptr, x, nullptr, nullptr, 2);
+    TrsvLaunch up = make_launch(P, P->sUS, P->US, P->DS, INT64_MAX, x, nullptr, x, nullptr, nullptr, 3);
+    if (trsv_lds_pair_ok(lo, up)) {
+      const double bytes = trsv_bytes(P->sLS, P->LS, false, false, false) + trsv_bytes(P->sUS, P->US, true, false, false);
+      return timed(ILU_K_TRSV_LS, bytes, s, [&] { return launch_trsv_lds_pair(lo, up, s); });
+    }
+  }
+  RC(trsv(P, P->sLS, P->LS, nullptr, 0, b, nullptr, x, nullptr, nullptr, s, 2));
+  return trsv(P, P->sUS, P->US, P->DS, INT64_MAX, x, nullptr, x, nullptr, nullptr, s, 3);
 }
 
 static double spmv_bytes(int64_t n, int64_t nnz, bool resid) {
@@ -1005,8 +1032,7 @@ static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t 
   const int64_t nS = P->nS;
   const int k = P->opt.inner_iters;
   double *V = P->iV;
-  RC(trsv(P, P->sLS, P->LS, nullptr, 0, gp, nullptr, V, nullptr, nullptr, s, 2));
-  RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, V, nullptr, V, nullptr, nullptr, s, 3));
+  RC(trsv_schur(P, gp, V, s));
   if (k == 0) return launch_copy(V, y, nS, s);
   double *beta = P->iscal, *hn = P->iscal + 1, *est = P->iscal + 2;
   int *stop = P->iflags, *nsteps = P->iflags + 1;
@@ -1021,8 +1047,7 @@ static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t 
     const Csr &C = P->block_mode ? P->Coffr : P->Coff;
     RC(timed(ILU_K_SPMV_COFF, spmv_bytes(nS, C.nnz, false), s,
              [&] { return launch_spmv(C.rp, C.ci, C.v, nS, vj, P->it1, s); }));
-    RC(trsv(P, P->sLS, P->LS, nullptr, 0, P->it1, nullptr, P->it2, nullptr, nullptr, s, 2));
-    RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, P->it2, nullptr, P->it2, nullptr, nullptr, s, 3));
+    RC(trsv_schur(P, P->it1, P->it2, s));
     double *pc = P->ipa, *pn = P->ipb;
     RC(launch_sum_dot(w, vj, P->it2, V, nS, pc, s));  // w = v_j + D^-1 C_off v_j, <w, v_0>
     for (int i = 0; i <= j; i++) {
@@ -1049,8 +1074,7 @@ static int apply_block(ilu_precond *P, const double *r, double *z, hipStream_t s
     if (P->opt.method == ILU_METHOD_SCHUR) {
       RC(inner_gmres(P, P->gS, P->yS, s));
     } else {
-      RC(trsv(P, P->sLS, P->LS, nullptr, 0, P->gS, nullptr, P->yS, nullptr, nullptr, s, 2));
-      RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, P->yS, nullptr, P->yS, nullptr, nullptr, s, 3));
+      RC(trsv_schur(P, P->gS, P->yS, s));
     }
   }
   // f'' = f' - Z y in U_B position order, u = U_B^-1 f'', then both halves to z
@@ -1071,8 +1095,7 @@ static int apply_impl(ilu_precond *P, const double *r, double *z, hipStream_t s)
     if (P->opt.method == ILU_METHOD_SCHUR) {
       RC(inner_gmres(P, gp, gp, s));
     } else {
-      RC(trsv(P, P->sLS, P->LS, nullptr, 0, gp, nullptr, gp, nullptr, nullptr, s, 2));
-      RC(trsv(P, P->sUS, P->US, P->DS, INT64_MAX, gp, nullptr, gp, nullptr, nullptr, s, 3));
+      RC(trsv_schur(P, gp, gp, s));
     }
     RC(launch_scatter(gp, P->perm + nB, nS, z, s));
   }
@@ -1337,21 +1360,26 @@ int ilu_export(ilu_precond_t *P, int32_t what, void *h, int64_t *len) {
     case 41: return export_raw(P->sU1.level_of, nB, 4, h, len);
     case 42: return export_raw(P->sLS.level_of, nS, 4, h, len);
     case 43: return export_raw(P->sUS.level_of, nS, 4, h, len);
-    case 44: {  // schedule of the four solves: {block-local, lanes per row, entries per lane, threads} each
+    case 44: {  // schedule of the four solves, then whether L_S and U_S run as one launch
       const Schedule *sch[4] = {&P->sL1, &P->sU1, &P->sLS, &P->sUS};
-      int32_t v[16];
+      int32_t v[20] = {0};
       for (int k = 0; k < 4; k++) {
         v[4 * k] = sch[k]->use_block ? 1 : 0;
         v[4 * k + 1] = sch[k]->lds_g;
         v[4 * k + 2] = sch[k]->lds_e;
         v[4 * k + 3] = sch[k]->lds_bt;
       }
+      if (P->block_mode && nS > 0) {
+        const TrsvLaunch lo = make_launch(P, P->sLS, P->LS, nullptr, 0, P->gS, nullptr, P->yS, nullptr, nullptr, 2);
+        const TrsvLaunch up = make_launch(P, P->sUS, P->US, P->DS, INT64_MAX, P->yS, nullptr, P->yS, nullptr, nullptr, 3);
+        v[16] = trsv_lds_pair_ok(lo, up) ? 1 : 0;
+      }
       if (!h) {
-        *len = 16;
+        *len = 20;
         return 0;
       }
-      if (*len < 16) return fail(ILU_ERR_INVALID_ARG, "export buffer too small");
-      *len = 16;
+      if (*len < 20) return fail(ILU_ERR_INVALID_ARG, "export buffer too small");
+      *len = 20;
       memcpy(h, v, sizeof(v));
       return 0;
     }

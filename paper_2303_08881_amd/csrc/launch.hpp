@@ -142,6 +142,10 @@ struct TrsvLaunch {
 };
 int launch_trsv(const TrsvLaunch &t, hipStream_t s);
 int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s);
+// the block-local L_S and U_S solves of each subdomain in one launch, when
+// both have the same lane shape (trsv_lds_pair_ok)
+bool trsv_lds_pair_ok(const TrsvLaunch &lo, const TrsvLaunch &up);
+int launch_trsv_lds_pair(const TrsvLaunch &lo, const TrsvLaunch &up, hipStream_t s);
 // y[q] = x[map[q]]
 int launch_gather(const double *x, const int32_t *map, int64_t n, double *y, hipStream_t s);
 int launch_gather_i32(const int32_t *x, const int32_t *map, int64_t n, int32_t *y, hipStream_t s);

@@ -15,6 +15,8 @@
 // for the level before, this implies all earlier levels are complete.
 // Counters are cumulative across calls (epoch = call number), so nothing is
 // reset between solves.  Waits are bounded.
+#include <algorithm>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -295,11 +297,12 @@ __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, double *win, const i
   refill<G, E>(a, f0, f1, j, g, S);
 }
 
+// One subdomain's solve by the calling workgroup (win: XWIN + 1 doubles,
+// lp: BT_LDS_LEVELS + 2 LOOK_MAX + 2 ints of LDS); returns after the last
+// level's barrier.
 template <int G, int E, bool DIAG>
-__global__ void __launch_bounds__(BT_MAX) k_trsv_lds(LdsTrsvArgs a) {
+__device__ __forceinline__ void block_solve(const LdsTrsvArgs &a, double *win, int32_t *lp) {
   constexpr int LOOK = look_of<E>();
-  __shared__ double win[XWIN + 1];  // slot XWIN stays 0.0: the target of padding entries
-  __shared__ int32_t lp[BT_LDS_LEVELS + 2 * LOOK_MAX + 2];
   const int64_t base = (int64_t)blockIdx.x * a.nlev;
   const int32_t tid = (int32_t)threadIdx.x;
   const int32_t nlev = a.nlev;
@@ -328,6 +331,25 @@ __global__ void __launch_bounds__(BT_MAX) k_trsv_lds(LdsTrsvArgs a) {
   }
 }
 
+template <int G, int E, bool DIAG>
+__global__ void __launch_bounds__(BT_MAX) k_trsv_lds(LdsTrsvArgs a) {
+  __shared__ double win[XWIN + 1];  // slot XWIN stays 0.0: the target of padding entries
+  __shared__ int32_t lp[BT_LDS_LEVELS + 2 * LOOK_MAX + 2];
+  block_solve<G, E, DIAG>(a, win, lp);
+}
+
+// L_S then U_S of each subdomain in one launch (both with the same lane
+// shape): U_S reads the solution that this workgroup's L_S wrote before the
+// barrier between the two.
+template <int G, int E>
+__global__ void __launch_bounds__(BT_MAX) k_trsv_lds_pair(LdsTrsvArgs lo, LdsTrsvArgs up) {
+  __shared__ double win[XWIN + 1];
+  __shared__ int32_t lp[BT_LDS_LEVELS + 2 * LOOK_MAX + 2];
+  block_solve<G, E, false>(lo, win, lp);
+  __syncthreads();
+  block_solve<G, E, true>(up, win, lp);
+}
+
 template <bool DIAG>
 static void launch_ge(int G, int E, unsigned grid, unsigned bt, const LdsTrsvArgs &a, hipStream_t s) {
   if (E == 2) {
@@ -346,14 +368,12 @@ static void launch_ge(int G, int E, unsigned grid, unsigned bt, const LdsTrsvArg
   }
 }
 
-int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s) {
-  if (t.nblk == 0 || t.nrows == 0) return 0;
+static bool lds_args(const TrsvLaunch &t, LdsTrsvArgs &a) {
   const bool ge_ok = ((t.lds_e == 2 || t.lds_e == 4) && t.lds_g == 1) ||
                      (t.lds_e == 8 && (t.lds_g == 1 || t.lds_g == 2 || t.lds_g == 4 || t.lds_g == 8));
   if (t.nlev_blk > BT_LDS_LEVELS || t.lds_bt < 64 || t.lds_bt > BT_MAX || t.lds_bt % 64 != 0 || !ge_ok ||
       !t.b || !t.x || !t.out_map)
-    return ILU_ERR_INVALID_ARG;
-  LdsTrsvArgs a;
+    return false;
   a.ent_c = reinterpret_cast<const int4 *>(t.lds_c);
   a.ent_v = reinterpret_cast<const double2 *>(t.lds_v);
   a.rec = reinterpret_cast<const int4 *>(t.lds_rec);
@@ -368,12 +388,45 @@ int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s) {
   a.out = t.x;
   a.omap = t.out_map;
   a.bt = t.lds_bt;
+  return true;
+}
+
+int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s) {
+  if (t.nblk == 0 || t.nrows == 0) return 0;
+  LdsTrsvArgs a;
+  if (!lds_args(t, a)) return ILU_ERR_INVALID_ARG;
   const unsigned g = (unsigned)t.nblk, bt = (unsigned)t.lds_bt;
   if (t.diag)
     launch_ge<true>(t.lds_g, t.lds_e, g, bt, a, s);
   else
     launch_ge<false>(t.lds_g, t.lds_e, g, bt, a, s);
   return check_launch("trsv_lds");
+}
+
+bool trsv_lds_pair_ok(const TrsvLaunch &lo, const TrsvLaunch &up) {
+  return lo.nblk == up.nblk && lo.nblk > 0 && lo.nrows > 0 && up.nrows > 0 && lo.lds_g == up.lds_g &&
+         lo.lds_e == up.lds_e && !lo.diag && up.diag;
+}
+
+int launch_trsv_lds_pair(const TrsvLaunch &lo, const TrsvLaunch &up, hipStream_t s) {
+  LdsTrsvArgs a, b;
+  if (!trsv_lds_pair_ok(lo, up) || !lds_args(lo, a) || !lds_args(up, b)) return ILU_ERR_INVALID_ARG;
+  // one block size for both solves: each covers its own widest level
+  a.bt = b.bt = std::max(a.bt, b.bt);
+  const unsigned g = (unsigned)lo.nblk, bt = (unsigned)a.bt;
+  if (lo.lds_e == 2)
+    k_trsv_lds_pair<1, 2><<<g, bt, 0, s>>>(a, b);
+  else if (lo.lds_e == 4)
+    k_trsv_lds_pair<1, 4><<<g, bt, 0, s>>>(a, b);
+  else if (lo.lds_g == 1)
+    k_trsv_lds_pair<1, 8><<<g, bt, 0, s>>>(a, b);
+  else if (lo.lds_g == 2)
+    k_trsv_lds_pair<2, 8><<<g, bt, 0, s>>>(a, b);
+  else if (lo.lds_g == 4)
+    k_trsv_lds_pair<4, 8><<<g, bt, 0, s>>>(a, b);
+  else
+    k_trsv_lds_pair<8, 8><<<g, bt, 0, s>>>(a, b);
+  return check_launch("trsv_lds_pair");
 }
 
 // ---- construction of the block-local storage ----
