@@ -156,8 +156,17 @@ int fgmres_solve(const ilu_csr_t *A, ilu_precond_t *P, const double *d_b, double
 /* y = A x (device, FP64, each row summed in column order with fma). */
 int csr_spmv(const ilu_csr_t *A, const double *d_x, double *d_y, void *stream);
 
-/* Release every device allocation of P.  NULL is accepted. */
+/* Release every device allocation of P (after waiting for the device to
+ * finish with them).  NULL is accepted.  The library keeps released device
+ * blocks in a per-device cache and hands them to later allocations of at
+ * most their size and at least half of it, so repeated setups of one problem
+ * call neither hipMalloc nor hipFree. */
 void ilu_destroy(ilu_precond_t *P);
+
+/* Free every cached device block (all devices) back to the HIP runtime.
+ * Blocks still owned by a live preconditioner are not affected.  An
+ * allocation that fails also empties the cache before it gives up. */
+void ilu_memory_trim(void);
 
 /* Message for the last error of the calling thread. */
 const char *ilu_last_error(void);

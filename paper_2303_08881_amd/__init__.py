@@ -24,6 +24,7 @@ from .binding import (  # noqa: F401
     setup,
     fgmres,
     spmv,
+    memory_trim,
     lib,
     LIB_PATH,
     EXPORT,

@@ -72,6 +72,8 @@ def lib():
         L.csr_spmv.argtypes = [vp, vp, vp, vp]
         L.ilu_destroy.argtypes = [vp]
         L.ilu_destroy.restype = None
+        L.ilu_memory_trim.argtypes = []
+        L.ilu_memory_trim.restype = None
         L.ilu_last_error.argtypes = []
         L.ilu_last_error.restype = C.c_char_p
         L.ilu_export.argtypes = [vp, i32, vp, C.POINTER(i64)]
@@ -213,3 +215,8 @@ def spmv(A: DeviceCSR, x, y=None):
         y = torch.empty_like(x)
     _check(lib().csr_spmv(A.ref, _ptr(x), _ptr(y), _stream()))
     return y
+
+
+def memory_trim():
+    """ilu_memory_trim: free the library's cached device blocks."""
+    lib().ilu_memory_trim()

@@ -13,7 +13,10 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "common.hpp"
@@ -62,11 +65,84 @@ int check_launch(const char *what) {
 // ---------------------------------------------------------------------------
 // device memory owner
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Device memory cache.  hipFree synchronises the device and both it and
+// hipMalloc cost tens of microseconds per call, so freed blocks are kept per
+// device and handed out again to requests of at most their size and at
+// least half of it (repeated setups of one problem reuse them all).  Blocks
+// are returned only after the device has finished with them (Mem::release
+// synchronises first).  A failed hipMalloc empties the cache and retries;
+// ilu_memory_trim empties it on request.
+// ---------------------------------------------------------------------------
+namespace {
+struct MemCache {
+  std::mutex mu;
+  std::multimap<std::pair<int, size_t>, void *> free_;     // (device, size) -> block
+  std::unordered_map<void *, std::pair<int, size_t>> own;  // every block handed out or cached
+};
+MemCache &mem_cache() {
+  static MemCache *c = new MemCache();  // never destroyed: blocks may outlive static destructors
+  return *c;
+}
+size_t cache_round(size_t b) {
+  const size_t g = b <= ((size_t)1 << 20) ? 256 : ((size_t)2 << 20);
+  return (b + g - 1) / g * g;
+}
+void cache_trim() {
+  MemCache &c = mem_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto &kv : c.free_) {
+    (void)hipSetDevice(kv.first.first);
+    (void)hipFree(kv.second);
+    c.own.erase(kv.second);
+  }
+  c.free_.clear();
+  (void)hipSetDevice(cur);
+}
+hipError_t cache_alloc(void **p, size_t bytes) {
+  MemCache &c = mem_cache();
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const size_t want = cache_round(bytes);
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.free_.lower_bound({dev, want});
+    if (it != c.free_.end() && it->first.first == dev && it->first.second <= 2 * want) {
+      *p = it->second;
+      c.free_.erase(it);
+      return hipSuccess;
+    }
+  }
+  hipError_t e = hipMalloc(p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    cache_trim();
+    e = hipMalloc(p, want);
+  }
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.own[*p] = {dev, want};
+  }
+  return e;
+}
+void cache_free(void *p) {
+  MemCache &c = mem_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.own.find(p);
+  if (it == c.own.end()) return;
+  c.free_.emplace(it->second, p);
+}
+}  // namespace
+
 struct Mem {
   std::vector<void *> ptrs;
   ~Mem() { release(); }
   void release() {
-    for (void *p : ptrs) (void)hipFree(p);
+    if (ptrs.empty()) return;
+    (void)hipDeviceSynchronize();  // kernels queued on these blocks have finished
+    for (void *p : ptrs) cache_free(p);
     ptrs.clear();
   }
   template <typename T>
@@ -74,7 +150,7 @@ struct Mem {
     *out = nullptr;
     size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = cache_alloc(&p, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(ILU_ERR_OOM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
@@ -1021,6 +1097,7 @@ int ilu_setup(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts, const i
 
 void ilu_destroy(ilu_precond_t *P) {
   if (!P) return;
+  (void)hipSetDevice(P->device);
   if (P->host_pinned) (void)hipHostFree(P->host_pinned);
   P->host_pinned = nullptr;
   delete P->gw;
@@ -1249,6 +1326,8 @@ int fgmres_solve(const ilu_csr_t *A, ilu_precond_t *P, const double *d_b, double
   }
   return rc;
 }
+
+void ilu_memory_trim(void) { cache_trim(); }
 
 void ilu_kernel_timing(int32_t classes) {
   if (!classes) timing_collect();

@@ -263,3 +263,29 @@ def test_runs_are_deterministic():
     z3 = P2.apply(r).cpu().numpy()
     assert np.array_equal(z1.view(np.uint64), z2.view(np.uint64))
     assert np.array_equal(z1.view(np.uint64), z3.view(np.uint64))
+
+
+def test_reused_device_blocks_give_identical_results():
+    """Setups that run on device blocks released by an earlier setup (the library's block cache), and again
+    after the cache was emptied, give bitwise identical preconditioners and FGMRES solutions."""
+    m = silu()
+    A = synth.aniso7(12, Nz=16)
+    part = synth.slab_partition(12, 4, Nz=16)
+    b = torch.as_tensor(synth.uniform_rhs(A.n, 4)).cuda()
+    r = torch.as_tensor(synth.uniform_rhs(A.n, 6)).cuda()
+    opts = dict(method=oracle.SCHUR, interior_fact=oracle.ILUT, interface_fact=oracle.MILU0, inner_iters=5,
+                **ILUT_OPTS)
+    Ad = m.DeviceCSR.from_host(A)
+    runs = []
+    for k in range(3):
+        if k == 2:
+            m.memory_trim()
+        P = m.setup(Ad, part, 4, **opts)
+        z = P.apply(r).cpu().numpy()
+        out = m.fgmres(Ad, P, b, rtol=1e-8, restart=20, maxit=200)
+        runs.append((z.view(np.uint64).copy(), out["x"].cpu().numpy().view(np.uint64).copy(), out["iterations"]))
+        P.close()
+    for z, x, its in runs[1:]:
+        assert np.array_equal(z, runs[0][0])
+        assert np.array_equal(x, runs[0][1])
+        assert its == runs[0][2]
