@@ -480,7 +480,7 @@ static int run_factor(ilu_precond *P, Mem &tmp, const Csr &M, int64_t nfull, int
   RC(fill_i32(S.Ulen, 0, nfull, s));
   int64_t nchunks = 0, nstreams = 0, ninit = 0, *stream_chunk = nullptr, line = 16, plane = 16;
   int32_t *chunks = nullptr;
-  const int64_t grid = std::min<int64_t>(factor_resident_waves(P->num_cu), (int64_t)P->num_cu * 16);
+  const int64_t grid = std::min<int64_t>(factor_resident_groups(P->num_cu), (int64_t)P->num_cu * 16 / FACT_WAVES);
   if (grid < 1) return fail(ILU_ERR_HIP, "%s: no resident workgroups for the factorization", phase);
   RC(row_geometry(tmp, M, nfull, false, s, &line, &plane));
   RC(build_streams(tmp, a_start, a_len, b_start, b_len, line, plane, FACT_PART_B_CHUNK, false, grid, &nchunks,

@@ -95,6 +95,15 @@ __device__ inline bool wait_ctr_ge(const unsigned long long *ctr, unsigned long 
 
 __device__ inline int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
 
+// Orders the LDS accesses of one wave around this point (a workgroup
+// barrier for a wave that shares its workgroup with others working
+// independently): the wave's earlier LDS writes are seen by its later reads.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Values that steer the control flow of a wave must be wave-uniform in the
 // compiler's eyes (scalar registers).  With one wave per workgroup the
 // compiler drops __syncthreads(), so a value written to LDS by lane 0 and

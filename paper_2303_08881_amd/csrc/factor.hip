@@ -29,6 +29,7 @@
 //   * results go to fixed-capacity per-row slots (ELL-like, capacities from a
 //     scan) and are compacted into CSR afterwards.
 #include "common.hpp"
+#include "launch.hpp"
 
 namespace silu {
 
@@ -135,315 +136,358 @@ __device__ int emit_part(const int32_t *wc, const double *wv, const uint8_t *wd,
   return out;
 }
 
-__global__ void __launch_bounds__(WAVE, 2) k_factor_rows(FactArgs a) {
-  __shared__ int32_t wc[FACT_CAP];
-  __shared__ double wv[FACT_CAP];
-  __shared__ uint8_t wd[FACT_CAP];
-  __shared__ int32_t fins[WAVE];
-  __shared__ int32_t fcol[WAVE];
-  __shared__ double fval[WAVE];
-  // U rows of the pivots of the current round, and which slot holds whose
-  __shared__ uint8_t ws[FACT_CAP];  // slot of each working entry's cached pivot row
-  __shared__ double tD[WAVE];
-  __shared__ int32_t toff[WAVE], tlen[WAVE];
-  __shared__ int32_t cc[FACT_UCACHE];
-  __shared__ double cv[FACT_UCACHE];
+// LDS working state of one wave
+struct FactLds {
+  int32_t *wc;
+  double *wv;
+  uint8_t *wd;
+  int32_t *fins, *fcol;
+  double *fval;
+  uint8_t *ws;  // slot of each working entry's cached pivot row
+  double *tD;
+  int32_t *toff, *tlen;
+  int32_t *cc;
+  double *cv;
+};
+
+// Factor row r with one wave.  Returns false after recording an error (or
+// when a wait gave up), true once the row is stored and its flag released.
+__device__ __forceinline__ bool factor_row(const FactArgs &a, int64_t r, const FactLds &L) {
+  int32_t *const wc = L.wc;
+  double *const wv = L.wv;
+  uint8_t *const wd = L.wd;
+  int32_t *const fins = L.fins, *const fcol = L.fcol;
+  double *const fval = L.fval;
+  uint8_t *const ws = L.ws;
+  double *const tD = L.tD;
+  int32_t *const toff = L.toff, *const tlen = L.tlen;
+  int32_t *const cc = L.cc;
+  double *const cv = L.cv;
   const int lane = lane_id();
   const bool ilut = a.method == ILU_FACT_ILUT;
   const bool milu = a.method == ILU_FACT_MILU0;
+  const int64_t lim = r < a.nfull ? r : a.nfull;
+  const int64_t rb = a.rp[r];
+  int len = (int)(a.rp[r + 1] - rb);
+  if (len > FACT_CAP) {
+    if (lane == 0) raise_error(a.st, ILU_ERR_CAPACITY, r);
+    return false;
+  }
+  for (int x = lane; x < len; x += WAVE) {
+    wc[x] = a.ci[rb + x];
+    wv[x] = a.v[rb + x];
+    wd[x] = 0;
+  }
+  wave_sync();
+  double tau = 0.0, rowinf = 0.0;
+  if (ilut) {
+    double s = 0.0;
+    if (lane == 0)
+      for (int x = 0; x < len; x++) s = fma(wv[x], wv[x], s);
+    tau = uniform_f64(a.droptol * sqrt(__shfl(s, 0, WAVE)));
+  }
+  if (a.pivot_mode == ILU_PIVOT_PERTURB) {
+    double m = 0.0;
+    for (int x = lane; x < len; x += WAVE) m = fmax(m, fabs(wv[x]));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, WAVE));
+    rowinf = uniform_f64(m);
+  }
+  double drop = 0.0;  // MILU: dropped fill of this row, summed in (k, j) order (lane 0)
+  bool failed = false;
+
+  bool first = true;
+  for (int pos = 0;; pos++) {
+    // every value that decides the control flow below is made wave-uniform
+    const int32_t k = uniform_i32(pos < len ? wc[pos] : 0x7fffffff);
+    if (k >= lim) break;
+    // Dependencies are waited for in rounds: the lanes wait together for
+    // every pivot still ahead in the working row.  A fill that becomes a
+    // pivot later (marked by bit 1 of wd) starts the next round when it
+    // is reached.  A pivot row's D, length and U row are then read with
+    // device-scope loads: its wave wrote them with write-through stores
+    // before releasing its flag, so no acquire fence (which would drop
+    // this XCD's cached lines for every wave on it) is needed.
+    //
+    // The round also fetches, all in parallel, the diagonal and the U row
+    // of the first WAVE pivots from pos on into an LDS cache (as many as
+    // fit), and tags their working entries with the slot; a pivot left
+    // out is marked like a new fill and starts the next round.  Every
+    // round re-caches all pivots from its position on, so no slot of an
+    // earlier round is read after being overwritten.
+    if (first || uniform_i32((int)(wd[pos] & 2))) {
+      first = false;
+      // the pivot at pos is waited for; the pivots after it are taken as far
+      // as they are already complete (one poll each), so a row eliminates its
+      // early pivots while a later one is still being factored
+      bool ok = true;
+      if (lane == 0) ok = wait_flag_eq(&a.done[k], a.epoch, a.st, r);
+      if (!uniform_i32((int)ok)) {
+        failed = true;
+        break;
+      }
+      const int x = pos + lane;
+      const int32_t kx0 = x < len ? wc[x] : 0x7fffffff;
+      const bool ready = kx0 < lim && (x == pos || ld_relaxed(&a.done[kx0]) == a.epoch);
+      const unsigned long long waiting = ballot(kx0 < lim && !ready);
+      const int nready = waiting ? __ffsll((long long)waiting) - 1 : WAVE;  // covered pivots: lanes [0, nready)
+      const int32_t kx = lane < nready ? kx0 : 0x7fffffff;
+      const bool piv = kx < lim;  // the covered pivots are a prefix of [pos, len)
+      double dk = 0.0;
+      int64_t ub = 0;
+      int ul = 0;
+      if (piv) {
+        dk = ld_dev(a.D + kx);
+        ub = a.Urp[kx];  // fixed before the launch
+        ul = ld_dev(a.Ulen + kx);
+      }
+      // exclusive prefix sum of the row lengths over the lanes
+      int off = ul;
+      for (int o = 1; o < WAVE; o <<= 1) {
+        const int v = __shfl_up(off, o, WAVE);
+        if (lane >= o) off += v;
+      }
+      off -= ul;
+      const bool cached = piv && off + ul <= FACT_UCACHE;
+      // every load of the copy first, then the LDS stores
+      int32_t uc_[FACT_UROW];
+      double uv_[FACT_UROW];
+#pragma unroll
+      for (int q = 0; q < FACT_UROW; q++) {
+        if (cached && q < ul) {
+          uc_[q] = ld_dev(a.Uc + ub + q);
+          uv_[q] = ld_dev(a.Uv + ub + q);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < FACT_UROW; q++) {
+        if (cached && q < ul) {
+          cc[off + q] = uc_[q];
+          cv[off + q] = uv_[q];
+        }
+      }
+      for (int q = FACT_UROW; cached && q < ul; q++) {
+        cc[off + q] = ld_dev(a.Uc + ub + q);
+        cv[off + q] = ld_dev(a.Uv + ub + q);
+      }
+      if (cached) {
+        tD[lane] = dk;
+        toff[lane] = off;
+        tlen[lane] = ul;
+      }
+      wave_sync();
+      if (x < len) {
+        if (cached) {
+          ws[x] = (uint8_t)lane;
+          wd[x] &= (uint8_t)~2u;
+        } else if (kx0 < lim) {
+          wd[x] |= 2;
+        }
+      }
+      for (int y = pos + WAVE + lane; y < len; y += WAVE)
+        if (wc[y] < lim) wd[y] |= 2;
+      wave_sync();
+    }
+    const int slot = uniform_i32((int)ws[pos]);
+    const double wk = uniform_f64(wv[pos] / tD[slot]);
+    if (ilut && fabs(wk) < tau) {
+      wave_sync();
+      if (lane == 0) {
+        wv[pos] = 0.0;
+        wd[pos] = 1;
+      }
+      wave_sync();
+      continue;
+    }
+    wave_sync();
+    if (lane == 0) wv[pos] = wk;
+    wave_sync();
+    const int ub = uniform_i32(toff[slot]);
+    const int ul = uniform_i32(tlen[slot]);
+    for (int base = 0; base < ul; base += WAVE) {
+      const int j = base + lane;
+      const bool have = j < ul;
+      const int32_t c = have ? cc[ub + j] : 0x7fffffff;
+      const double u = have ? cv[ub + j] : 0.0;
+      const int idx = have ? lower_bound_lds(wc, pos + 1, len, c) : len;
+      const bool found = have && idx < len && wc[idx] == c;
+      if (found) wv[idx] = fma(-wk, u, wv[idx]);
+      const bool fill = have && !found;
+      const unsigned long long fm = ballot(fill);
+      if (fm == 0ull) {
+        wave_sync();
+        continue;
+      }
+      if (ilut) {
+        const int nf = popc64(fm);
+        if (len + nf > FACT_CAP) {
+          if (lane == 0) raise_error(a.st, ILU_ERR_CAPACITY, r);
+          return false;
+        }
+        if (fill) {
+          const int rk = mbcnt(fm);
+          fins[rk] = idx;
+          fcol[rk] = c;
+          fval[rk] = fma(-wk, u, 0.0);
+        }
+        wave_sync();
+        // Shift every working entry after the pivot to make room: the
+        // upper half of the slots first, each half read completely before
+        // it is written (destinations only move up and never cross).
+        constexpr int NS = FACT_CAP / WAVE, HS = NS / 2;
+#pragma unroll 1
+        for (int h = 1; h >= 0; h--) {
+          int32_t rc_[HS];
+          double rv_[HS];
+          uint8_t rd_[HS], rs_[HS];
+          int np_[HS];
+#pragma unroll
+          for (int qq = 0; qq < HS; qq++) {
+            const int x = pos + 1 + (h * HS + qq) * WAVE + lane;
+            np_[qq] = -1;
+            if (x < len) {
+              rc_[qq] = wc[x];
+              rv_[qq] = wv[x];
+              rd_[qq] = wd[x];
+              rs_[qq] = ws[x];
+              // number of fills inserted at or before x
+              int lo = 0, hi = nf;
+              while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (fins[mid] <= x)
+                  lo = mid + 1;
+                else
+                  hi = mid;
+              }
+              np_[qq] = x + lo;
+            }
+          }
+          wave_sync();
+#pragma unroll
+          for (int qq = 0; qq < HS; qq++) {
+            if (np_[qq] >= 0) {
+              wc[np_[qq]] = rc_[qq];
+              wv[np_[qq]] = rv_[qq];
+              wd[np_[qq]] = rd_[qq];
+              ws[np_[qq]] = rs_[qq];
+            }
+          }
+          wave_sync();
+        }
+        if (lane < nf) {
+          const int at = fins[lane] + lane;
+          wc[at] = fcol[lane];
+          wv[at] = fval[lane];
+          wd[at] = fcol[lane] < lim ? 2 : 0;  // a new pivot: not covered by the last round
+        }
+        len += nf;
+        wave_sync();
+      } else if (milu) {
+        // sum the dropped products in column order, exactly as written
+        unsigned long long m = fm;
+        while (m) {
+          const int b = __ffsll((long long)m) - 1;
+          m &= m - 1;
+          const double ubv = __shfl(u, b, WAVE);
+          if (lane == 0) drop = fma(-wk, ubv, drop);
+        }
+        wave_sync();
+      } else {
+        wave_sync();
+      }
+    }
+  }
+  if (failed) return false;
+  wave_sync();
+
+  if (r < a.nfull) {  // full row: L | d | U
+    const int pd = uniform_i32(lower_bound_lds(wc, 0, len, (int32_t)r));
+    double d = wv[pd];
+    if (milu) d = d + __shfl(drop, 0, WAVE);
+    d = uniform_f64(d);
+    if (a.pivot_mode == ILU_PIVOT_PERTURB) {
+      const double thr = a.pivot_tol * rowinf;
+      if (fabs(d) < thr) d = (d < 0.0) ? -thr : thr;
+    }
+    if (d == 0.0 || !isfinite(d)) {
+      if (lane == 0) raise_error(a.st, ILU_ERR_ZERO_PIVOT, r);
+      return false;
+    }
+    if (lane == 0) st_dev(a.D + r, d);
+    const int nl = emit_part(wc, wv, wd, 0, pd, ilut, tau, a.lfil, -1, a.Lc + a.Lrp[r], a.Lv + a.Lrp[r], false);
+    const int nu =
+        emit_part(wc, wv, wd, pd + 1, len, ilut, tau, a.lfil, -1, a.Uc + a.Urp[r], a.Uv + a.Urp[r], true);
+    if (lane == 0) {
+      st_dev(a.Llen + r, nl);
+      st_dev(a.Ulen + r, nu);
+    }
+  } else {  // partial row: L (interior columns) | Schur remainder R
+    const int pl = uniform_i32(lower_bound_lds(wc, 0, len, (int32_t)a.nfull));
+    const int pd = uniform_i32(lower_bound_lds(wc, pl, len, (int32_t)r));
+    if (milu) {
+      wave_sync();
+      if (lane == 0) wv[pd] = wv[pd] + drop;
+      wave_sync();
+    }
+    const int nl = emit_part(wc, wv, wd, 0, pl, ilut, tau, a.lfil, -1, a.Lc + a.Lrp[r], a.Lv + a.Lrp[r], false);
+    const int64_t ro = a.Rrp[r - a.nfull];
+    const int nr = emit_part(wc, wv, wd, pl, len, ilut, tau, a.lfil, pd, a.Rc + ro, a.Rv + ro, true);
+    if (lane == 0) {
+      st_dev(a.Llen + r, nl);
+      st_dev(a.Rlen + (r - a.nfull), nr);
+    }
+  }
+  wave_sync();
+  if (lane == 0) st_release(&a.done[r], a.epoch);
+  wave_sync();
+  return true;
+}
+
+// A workgroup of FACT_WAVES waves takes a chunk of rows at a time; wave w
+// factors rows first + w, first + w + FACT_WAVES, ...: a row's early pivots
+// (rows finished long before) are eliminated while the row before it is still
+// in progress on another wave.  The waves of a chunk are resident together,
+// so the waits between them always end.
+__global__ void __launch_bounds__(WAVE *FACT_WAVES, 2) k_factor_rows(FactArgs a) {
+  __shared__ int32_t wc[FACT_WAVES][FACT_CAP];
+  __shared__ double wv[FACT_WAVES][FACT_CAP];
+  __shared__ uint8_t wd[FACT_WAVES][FACT_CAP];
+  __shared__ int32_t fins[FACT_WAVES][WAVE];
+  __shared__ int32_t fcol[FACT_WAVES][WAVE];
+  __shared__ double fval[FACT_WAVES][WAVE];
+  __shared__ uint8_t ws[FACT_WAVES][FACT_CAP];
+  __shared__ double tD[FACT_WAVES][WAVE];
+  __shared__ int32_t toff[FACT_WAVES][WAVE], tlen[FACT_WAVES][WAVE];
+  __shared__ int32_t cc[FACT_WAVES][FACT_UCACHE];
+  __shared__ double cv[FACT_WAVES][FACT_UCACHE];
+  __shared__ long long sh_t;
+  const int w = (int)(threadIdx.x / WAVE);
+  const FactLds L{wc[w], wv[w], wd[w], fins[w], fcol[w], fval[w], ws[w], tD[w], toff[w], tlen[w], cc[w], cv[w]};
 
   int64_t sid = (int64_t)blockIdx.x % a.ninit;
   for (;;) {
-    // A stream is left only once it has handed out all its chunks, so every
-    // stream keeps a workgroup until then; a stream that no row depends on
-    // (interface rows of a partial factorization) may start without one.
-    int64_t t = -1;
-    for (int64_t tries = 0; tries < a.nstreams && t < 0; tries++) {
-      const int64_t c0 = a.stream_chunk[sid], nc = a.stream_chunk[sid + 1] - c0;
-      if ((int64_t)uniform_i32(ld_relaxed(reinterpret_cast<const int *>(a.ticket + sid))) < nc) {
-        const unsigned int tl = wave_ticket(a.ticket + sid);
-        if ((int64_t)tl < nc) t = c0 + (int64_t)tl;
+    __syncthreads();  // every wave is done with the previous chunk
+    if (w == 0) {
+      // A stream is left only once it has handed out all its chunks, so every
+      // stream keeps a workgroup until then; a stream that no row depends on
+      // (interface rows of a partial factorization) may start without one.
+      int64_t t = -1;
+      for (int64_t tries = 0; tries < a.nstreams && t < 0; tries++) {
+        const int64_t c0 = a.stream_chunk[sid], nc = a.stream_chunk[sid + 1] - c0;
+        if ((int64_t)uniform_i32(ld_relaxed(reinterpret_cast<const int *>(a.ticket + sid))) < nc) {
+          const unsigned int tl = wave_ticket(a.ticket + sid);
+          if ((int64_t)tl < nc) t = c0 + (int64_t)tl;
+        }
+        if (t < 0) sid = sid + 1 < a.nstreams ? sid + 1 : 0;
       }
-      if (t < 0) sid = sid + 1 < a.nstreams ? sid + 1 : 0;
+      if (ld_relaxed(&a.st->abort)) t = -1;
+      if (threadIdx.x == 0) sh_t = t;
     }
+    __syncthreads();
+    const int64_t t = sh_t;
     if (t < 0) return;
-    if (ld_relaxed(&a.st->abort)) return;
     const int2 ch = a.chunks[t];
-    for (int64_t r = ch.x; r < (int64_t)ch.x + ch.y; r++) {
-      const int64_t lim = r < a.nfull ? r : a.nfull;
-      const int64_t rb = a.rp[r];
-      int len = (int)(a.rp[r + 1] - rb);
-      if (len > FACT_CAP) {
-        if (lane == 0) raise_error(a.st, ILU_ERR_CAPACITY, r);
-        return;
-      }
-      for (int x = lane; x < len; x += WAVE) {
-        wc[x] = a.ci[rb + x];
-        wv[x] = a.v[rb + x];
-        wd[x] = 0;
-      }
-      __syncthreads();
-      double tau = 0.0, rowinf = 0.0;
-      if (ilut) {
-        double s = 0.0;
-        if (lane == 0)
-          for (int x = 0; x < len; x++) s = fma(wv[x], wv[x], s);
-        tau = uniform_f64(a.droptol * sqrt(__shfl(s, 0, WAVE)));
-      }
-      if (a.pivot_mode == ILU_PIVOT_PERTURB) {
-        double m = 0.0;
-        for (int x = lane; x < len; x += WAVE) m = fmax(m, fabs(wv[x]));
-        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, WAVE));
-        rowinf = uniform_f64(m);
-      }
-      double drop = 0.0;  // MILU: dropped fill of this row, summed in (k, j) order (lane 0)
-      bool failed = false;
-
-      bool first = true;
-      for (int pos = 0;; pos++) {
-        // every value that decides the control flow below is made wave-uniform
-        const int32_t k = uniform_i32(pos < len ? wc[pos] : 0x7fffffff);
-        if (k >= lim) break;
-        // Dependencies are waited for in rounds: the lanes wait together for
-        // every pivot still ahead in the working row.  A fill that becomes a
-        // pivot later (marked by bit 1 of wd) starts the next round when it
-        // is reached.  A pivot row's D, length and U row are then read with
-        // device-scope loads: its wave wrote them with write-through stores
-        // before releasing its flag, so no acquire fence (which would drop
-        // this XCD's cached lines for every wave on it) is needed.
-        //
-        // The round also fetches, all in parallel, the diagonal and the U row
-        // of the first WAVE pivots from pos on into an LDS cache (as many as
-        // fit), and tags their working entries with the slot; a pivot left
-        // out is marked like a new fill and starts the next round.  Every
-        // round re-caches all pivots from its position on, so no slot of an
-        // earlier round is read after being overwritten.
-        if (first || uniform_i32((int)(wd[pos] & 2))) {
-          first = false;
-          bool ok = true;
-          for (int x = pos + lane; x < len; x += WAVE) {
-            const int32_t kx = wc[x];
-            if (kx >= lim) break;
-            if (!wait_flag_eq(&a.done[kx], a.epoch, a.st, r)) {
-              ok = false;
-              break;
-            }
-          }
-          if (ballot(!ok) != 0ull) {
-            failed = true;
-            break;
-          }
-          const int x = pos + lane;
-          const int32_t kx = x < len ? wc[x] : 0x7fffffff;
-          const bool piv = kx < lim;  // the pivots ahead are a prefix of [pos, len)
-          double dk = 0.0;
-          int64_t ub = 0;
-          int ul = 0;
-          if (piv) {
-            dk = ld_dev(a.D + kx);
-            ub = a.Urp[kx];  // fixed before the launch
-            ul = ld_dev(a.Ulen + kx);
-          }
-          // exclusive prefix sum of the row lengths over the lanes
-          int off = ul;
-          for (int o = 1; o < WAVE; o <<= 1) {
-            const int v = __shfl_up(off, o, WAVE);
-            if (lane >= o) off += v;
-          }
-          off -= ul;
-          const bool cached = piv && off + ul <= FACT_UCACHE;
-          // every load of the copy first, then the LDS stores
-          int32_t uc_[FACT_UROW];
-          double uv_[FACT_UROW];
-#pragma unroll
-          for (int q = 0; q < FACT_UROW; q++) {
-            if (cached && q < ul) {
-              uc_[q] = ld_dev(a.Uc + ub + q);
-              uv_[q] = ld_dev(a.Uv + ub + q);
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < FACT_UROW; q++) {
-            if (cached && q < ul) {
-              cc[off + q] = uc_[q];
-              cv[off + q] = uv_[q];
-            }
-          }
-          for (int q = FACT_UROW; cached && q < ul; q++) {
-            cc[off + q] = ld_dev(a.Uc + ub + q);
-            cv[off + q] = ld_dev(a.Uv + ub + q);
-          }
-          if (cached) {
-            tD[lane] = dk;
-            toff[lane] = off;
-            tlen[lane] = ul;
-          }
-          __syncthreads();
-          if (x < len) {
-            if (cached) {
-              ws[x] = (uint8_t)lane;
-              wd[x] &= (uint8_t)~2u;
-            } else if (piv) {
-              wd[x] |= 2;
-            }
-          }
-          for (int y = pos + WAVE + lane; y < len; y += WAVE)
-            if (wc[y] < lim) wd[y] |= 2;
-          __syncthreads();
-        }
-        const int slot = uniform_i32((int)ws[pos]);
-        const double wk = uniform_f64(wv[pos] / tD[slot]);
-        if (ilut && fabs(wk) < tau) {
-          __syncthreads();
-          if (lane == 0) {
-            wv[pos] = 0.0;
-            wd[pos] = 1;
-          }
-          __syncthreads();
-          continue;
-        }
-        __syncthreads();
-        if (lane == 0) wv[pos] = wk;
-        __syncthreads();
-        const int ub = uniform_i32(toff[slot]);
-        const int ul = uniform_i32(tlen[slot]);
-        for (int base = 0; base < ul; base += WAVE) {
-          const int j = base + lane;
-          const bool have = j < ul;
-          const int32_t c = have ? cc[ub + j] : 0x7fffffff;
-          const double u = have ? cv[ub + j] : 0.0;
-          const int idx = have ? lower_bound_lds(wc, pos + 1, len, c) : len;
-          const bool found = have && idx < len && wc[idx] == c;
-          if (found) wv[idx] = fma(-wk, u, wv[idx]);
-          const bool fill = have && !found;
-          const unsigned long long fm = ballot(fill);
-          if (fm == 0ull) {
-            __syncthreads();
-            continue;
-          }
-          if (ilut) {
-            const int nf = popc64(fm);
-            if (len + nf > FACT_CAP) {
-              if (lane == 0) raise_error(a.st, ILU_ERR_CAPACITY, r);
-              return;
-            }
-            if (fill) {
-              const int rk = mbcnt(fm);
-              fins[rk] = idx;
-              fcol[rk] = c;
-              fval[rk] = fma(-wk, u, 0.0);
-            }
-            __syncthreads();
-            // Shift every working entry after the pivot to make room: the
-            // upper half of the slots first, each half read completely before
-            // it is written (destinations only move up and never cross).
-            constexpr int NS = FACT_CAP / WAVE, HS = NS / 2;
-#pragma unroll 1
-            for (int h = 1; h >= 0; h--) {
-              int32_t rc_[HS];
-              double rv_[HS];
-              uint8_t rd_[HS], rs_[HS];
-              int np_[HS];
-#pragma unroll
-              for (int qq = 0; qq < HS; qq++) {
-                const int x = pos + 1 + (h * HS + qq) * WAVE + lane;
-                np_[qq] = -1;
-                if (x < len) {
-                  rc_[qq] = wc[x];
-                  rv_[qq] = wv[x];
-                  rd_[qq] = wd[x];
-                  rs_[qq] = ws[x];
-                  // number of fills inserted at or before x
-                  int lo = 0, hi = nf;
-                  while (lo < hi) {
-                    int mid = (lo + hi) >> 1;
-                    if (fins[mid] <= x)
-                      lo = mid + 1;
-                    else
-                      hi = mid;
-                  }
-                  np_[qq] = x + lo;
-                }
-              }
-              __syncthreads();
-#pragma unroll
-              for (int qq = 0; qq < HS; qq++) {
-                if (np_[qq] >= 0) {
-                  wc[np_[qq]] = rc_[qq];
-                  wv[np_[qq]] = rv_[qq];
-                  wd[np_[qq]] = rd_[qq];
-                  ws[np_[qq]] = rs_[qq];
-                }
-              }
-              __syncthreads();
-            }
-            if (lane < nf) {
-              const int at = fins[lane] + lane;
-              wc[at] = fcol[lane];
-              wv[at] = fval[lane];
-              wd[at] = fcol[lane] < lim ? 2 : 0;  // a new pivot: not covered by the last round
-            }
-            len += nf;
-            __syncthreads();
-          } else if (milu) {
-            // sum the dropped products in column order, exactly as written
-            unsigned long long m = fm;
-            while (m) {
-              const int b = __ffsll((long long)m) - 1;
-              m &= m - 1;
-              const double ubv = __shfl(u, b, WAVE);
-              if (lane == 0) drop = fma(-wk, ubv, drop);
-            }
-            __syncthreads();
-          } else {
-            __syncthreads();
-          }
-        }
-      }
-      if (failed) return;
-      __syncthreads();
-
-      if (r < a.nfull) {  // full row: L | d | U
-        const int pd = uniform_i32(lower_bound_lds(wc, 0, len, (int32_t)r));
-        double d = wv[pd];
-        if (milu) d = d + __shfl(drop, 0, WAVE);
-        d = uniform_f64(d);
-        if (a.pivot_mode == ILU_PIVOT_PERTURB) {
-          const double thr = a.pivot_tol * rowinf;
-          if (fabs(d) < thr) d = (d < 0.0) ? -thr : thr;
-        }
-        if (d == 0.0 || !isfinite(d)) {
-          if (lane == 0) raise_error(a.st, ILU_ERR_ZERO_PIVOT, r);
-          return;
-        }
-        if (lane == 0) st_dev(a.D + r, d);
-        const int nl = emit_part(wc, wv, wd, 0, pd, ilut, tau, a.lfil, -1, a.Lc + a.Lrp[r], a.Lv + a.Lrp[r], false);
-        const int nu =
-            emit_part(wc, wv, wd, pd + 1, len, ilut, tau, a.lfil, -1, a.Uc + a.Urp[r], a.Uv + a.Urp[r], true);
-        if (lane == 0) {
-          st_dev(a.Llen + r, nl);
-          st_dev(a.Ulen + r, nu);
-        }
-      } else {  // partial row: L (interior columns) | Schur remainder R
-        const int pl = uniform_i32(lower_bound_lds(wc, 0, len, (int32_t)a.nfull));
-        const int pd = uniform_i32(lower_bound_lds(wc, pl, len, (int32_t)r));
-        if (milu) {
-          __syncthreads();
-          if (lane == 0) wv[pd] = wv[pd] + drop;
-          __syncthreads();
-        }
-        const int nl = emit_part(wc, wv, wd, 0, pl, ilut, tau, a.lfil, -1, a.Lc + a.Lrp[r], a.Lv + a.Lrp[r], false);
-        const int64_t ro = a.Rrp[r - a.nfull];
-        const int nr = emit_part(wc, wv, wd, pl, len, ilut, tau, a.lfil, pd, a.Rc + ro, a.Rv + ro, true);
-        if (lane == 0) {
-          st_dev(a.Llen + r, nl);
-          st_dev(a.Rlen + (r - a.nfull), nr);
-        }
-      }
-      __syncthreads();
-      if (lane == 0) st_release(&a.done[r], a.epoch);
-      __syncthreads();
-    }
+    for (int64_t r = ch.x + w; r < (int64_t)ch.x + ch.y; r += FACT_WAVES)
+      if (!factor_row(a, r, L)) break;
   }
 }
 
@@ -519,7 +563,6 @@ __global__ void k_count_rows(int64_t nrows, const int64_t *cap_rp, const int32_t
 // ---------------------------------------------------------------------------
 // host launchers (called from the runtime)
 // ---------------------------------------------------------------------------
-#include "launch.hpp"
 
 namespace silu {
 
@@ -572,15 +615,16 @@ int launch_factor_rows(const FactLaunch &f, hipStream_t s) {
   if (f.grid < f.ninit || f.ninit < 1 || f.ninit > f.nstreams) return ILU_ERR_INVALID_ARG;
   void *args[] = {&a};
   const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_factor_rows),
-                                                  dim3((unsigned)f.grid), dim3(WAVE), args, 0, s);
+                                                  dim3((unsigned)f.grid), dim3(WAVE * FACT_WAVES), args, 0, s);
   if (e != hipSuccess) return ILU_ERR_HIP;
   return check_launch("factor_rows");
 }
 
 // Workgroups of k_factor_rows that fit on the device at once.
-int factor_resident_waves(int num_cu) {
+int factor_resident_groups(int num_cu) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_factor_rows, WAVE, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_factor_rows, WAVE * FACT_WAVES, 0) != hipSuccess)
+    return 0;
   return per_cu * num_cu;
 }
 

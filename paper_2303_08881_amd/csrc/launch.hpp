@@ -70,9 +70,9 @@ struct FactLaunch {
   int *done;
   int epoch;
   void *status;
-  int64_t grid;  // workgroups, all resident (factor_resident_waves), >= ninit
+  int64_t grid;  // workgroups, all resident (factor_resident_groups), >= ninit
 };
-int factor_resident_waves(int num_cu);
+int factor_resident_groups(int num_cu);
 // histograms (2 x 32 buckets, zeroed) of log2 of each row's second-nearest and farthest lower (upper)
 // neighbour distance
 int launch_gap_hist(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, unsigned long long *hist,
@@ -85,6 +85,7 @@ int launch_compact_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len
                         int64_t col_hi, int64_t shift, hipStream_t s);
 int launch_count_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len, const int32_t *sc, int64_t col_lo,
                       int64_t col_hi, int64_t *cnt, hipStream_t s);
+constexpr int FACT_WAVES = 2;         // waves per factorization workgroup (rows of a chunk interleaved over them)
 constexpr int FACT_PART_B_CHUNK = 4;  // rows per chunk of a partial factorization's interface rows
 
 constexpr int LEVEL_CHUNK_MAX = 256;  // rows per chunk of the level sweep
