@@ -119,12 +119,13 @@ __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
 //                order, each column replaced by the slot of its position in
 //                the LDS solution window, padded with the window's zero slot
 //                and 0.0;
-//   rec          {row (or ~row for a slow row), output index, diagonal}.
+//   rec          {row (or ~row for a slow row), output index, 1 / diagonal}.
 // A row is handled by G consecutive lanes, lane g summing entries
 // gE..gE+E-1 with fma (lane 0 starting from the right-hand side); the G
 // partial sums are combined pairwise across lanes (fixed order, so results
 // are reproducible run to run; the sum order differs from the sequential one
-// by rounding only) and the diagonal divides once.
+// by rounding only) and the sum is multiplied once by the reciprocal of the
+// diagonal (within an ulp of the division).
 //
 // Latency is the whole cost of this solve (a level holds tens to hundreds of
 // rows), so every load is issued LOOK levels before its use (LOOK = 10, 8, 6
@@ -224,7 +225,7 @@ __device__ __forceinline__ double slow_row(const LdsTrsvArgs &a, int32_t r, int3
     const int32_t c = a.ci[p];
     if (c < a.split) s = fma(-a.v[p], a.out[a.omap[c]], s);
   }
-  if (DIAG) s = s / d;
+  if (DIAG) s = s * d;  // d: the reciprocal of the diagonal
   // Drain this path's loads here: otherwise the compiler cannot tell, where
   // the slow and fast paths join, that the temporaries of the slow path are
   // no longer in flight, and it would wait for every outstanding load (the
@@ -277,7 +278,7 @@ __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, double *win, const i
   s = group_sum<G>(s);
   const bool slow = S.rec.x < 0;
   const int32_t r = slow ? ~S.rec.x : S.rec.x;
-  if (DIAG) s = s / rec_diag(S.rec);
+  if (DIAG) s = s * rec_diag(S.rec);  // the record holds 1 / d
   if (mine && slow) s = slow_row<DIAG>(a, r, q, rec_diag(S.rec));
   if (mine && g == 0) {
     win[q & (XWIN - 1)] = s;
@@ -497,7 +498,9 @@ __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t
   }
   const int32_t lend = lev_ptr[lo + 1];
   const bool slow = too_long || (int64_t)mind < (int64_t)lend - XWIN;
-  const double d = diag ? diag[r] : 1.0;
+  // the reciprocal of the diagonal: the solve multiplies by it (one multiply on
+  // every level's dependent chain instead of a division)
+  const double d = diag ? 1.0 / diag[r] : 1.0;
   rec[q] = make_int4(slow ? ~r : r, omap[r], __double2loint(d), __double2hiint(d));
 }
 
