@@ -551,7 +551,7 @@ static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, in
     // of this factor's own pattern, from the bottom for L, the top for U)
     int64_t line = 16, plane = 16, nch = 0, ns = 0, ninit = 0, *sc = nullptr;
     int32_t *chunks = nullptr;
-    const int64_t grid = std::min<int64_t>(levels_resident_waves(P->num_cu), (int64_t)P->num_cu * 32);
+    const int64_t grid = std::min<int64_t>(levels_resident_groups(P->num_cu), (int64_t)P->num_cu * 32 / LEVEL_WAVES);
     if (grid < 1) return fail(ILU_ERR_HIP, "%s: no resident workgroups for the level sweep", phase);
     RC(row_geometry(tmp, T, n, !lower, s, &line, &plane));
     RC(build_streams(tmp, seg.a_start, seg.a_len, seg.b_start, seg.b_len, line, plane, 4, !lower, grid, &nch, &chunks,

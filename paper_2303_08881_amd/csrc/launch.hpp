@@ -89,9 +89,10 @@ constexpr int FACT_WAVES = 2;         // waves per factorization workgroup (rows
 constexpr int FACT_PART_B_CHUNK = 4;  // rows per chunk of a partial factorization's interface rows
 
 constexpr int LEVEL_CHUNK_MAX = 256;  // rows per chunk of the level sweep
+constexpr int LEVEL_WAVES = 2;        // waves per level-sweep workgroup, taking a chunk's rows in turn
 // Level sweep over a stream schedule (build_streams); done[] zeroed, grid
-// workgroups all resident (levels_resident_waves) and >= ninit.
-int levels_resident_waves(int num_cu);
+// workgroups all resident (levels_resident_groups) and >= ninit.
+int levels_resident_groups(int num_cu);
 int launch_levels_stream(const int64_t *rp, const int32_t *ci, bool lower, int64_t lo, int64_t hi,
                          const int32_t *chunks, int64_t nstreams, int64_t ninit, const int64_t *stream_chunk,
                          unsigned int *ticket, int32_t *level, int *done, void *status, int64_t grid, hipStream_t s);

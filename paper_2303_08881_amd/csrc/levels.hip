@@ -16,10 +16,13 @@ namespace silu {
 // level(r) = 1 + max level of the rows r depends on (0 without any).  The
 // rows come in chunks of consecutive rows (a line, from the top down for an
 // upper factor) grouped in streams, exactly like the factorization's schedule.
-// A workgroup sums one row at a time: dependencies inside its chunk come from
-// LDS, the others from the completion flag of their row, which holds
-// level + 1 (0 = not yet known) -- the value is its own payload, so no fence
-// is needed on either side.  Waits are bounded.
+// A workgroup of LEVEL_WAVES waves takes a chunk, its waves taking the rows in
+// turn, one row at a time: dependencies inside the chunk come from the
+// workgroup's LDS (polled until the other wave has written them), the others
+// from the completion flag of their row, which holds level + 1 (0 = not yet
+// known) -- the value is its own payload, so no fence is needed on either
+// side.  While one wave waits on a flag, the other works on its row.  Waits
+// are bounded.
 __device__ inline int wait_nonzero(const int *flag, Status *st, int64_t row) {
   long it = 0;
   int v;
@@ -34,28 +37,53 @@ __device__ inline int wait_nonzero(const int *flag, Status *st, int64_t row) {
   return v;
 }
 
-__global__ void __launch_bounds__(WAVE) k_levels_stream(const int64_t *rp, const int32_t *ci, bool lower, int64_t lo,
-                                                        int64_t hi, const int2 *chunks, int64_t nstreams,
-                                                        int64_t ninit, const int64_t *stream_chunk,
-                                                        unsigned int *ticket, int32_t *level, int *done, Status *st) {
+// level of an earlier row of this chunk, once its wave has stored it
+__device__ inline int32_t wait_lds_level(const volatile int32_t *slot, Status *st, int64_t row) {
+  long it = 0;
+  int32_t v;
+  while ((v = *slot) < 0) {
+    if (++it > SPIN_LIMIT) {
+      raise_error(st, ILU_ERR_TIMEOUT, row);
+      return -1;
+    }
+    if ((it & 255) == 0 && ld_relaxed(&st->abort)) return -1;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(WAVE *LEVEL_WAVES) k_levels_stream(const int64_t *rp, const int32_t *ci, bool lower,
+                                                                    int64_t lo, int64_t hi, const int2 *chunks,
+                                                                    int64_t nstreams, int64_t ninit,
+                                                                    const int64_t *stream_chunk, unsigned int *ticket,
+                                                                    int32_t *level, int *done, Status *st) {
   __shared__ int32_t clev[LEVEL_CHUNK_MAX];
+  __shared__ long long sh_t;
   const int lane = lane_id();
+  const int w = (int)(threadIdx.x / WAVE);
   int64_t sid = (int64_t)blockIdx.x % ninit;
   for (;;) {
-    int64_t t = -1;
-    for (int64_t tries = 0; tries < nstreams && t < 0; tries++) {
-      const int64_t c0 = stream_chunk[sid], nc = stream_chunk[sid + 1] - c0;
-      if ((int64_t)uniform_i32(ld_relaxed(reinterpret_cast<const int *>(ticket + sid))) < nc) {
-        const unsigned int tl = wave_ticket(ticket + sid);
-        if ((int64_t)tl < nc) t = c0 + (int64_t)tl;
+    __syncthreads();  // every wave is done with the previous chunk
+    if (w == 0) {
+      int64_t t = -1;
+      for (int64_t tries = 0; tries < nstreams && t < 0; tries++) {
+        const int64_t c0 = stream_chunk[sid], nc = stream_chunk[sid + 1] - c0;
+        if ((int64_t)uniform_i32(ld_relaxed(reinterpret_cast<const int *>(ticket + sid))) < nc) {
+          const unsigned int tl = wave_ticket(ticket + sid);
+          if ((int64_t)tl < nc) t = c0 + (int64_t)tl;
+        }
+        if (t < 0) sid = sid + 1 < nstreams ? sid + 1 : 0;
       }
-      if (t < 0) sid = sid + 1 < nstreams ? sid + 1 : 0;
+      if (ld_relaxed(&st->abort)) t = -1;
+      if (threadIdx.x == 0) sh_t = t;
     }
+    for (int i = (int)threadIdx.x; i < LEVEL_CHUNK_MAX; i += WAVE * LEVEL_WAVES) clev[i] = -1;
+    __syncthreads();
+    const int64_t t = sh_t;
     if (t < 0) return;
-    if (ld_relaxed(&st->abort)) return;
     const int2 ch = chunks[t];
     const int64_t first = ch.x;
-    for (int32_t i = 0; i < ch.y; i++) {
+    for (int32_t i = w; i < ch.y; i += LEVEL_WAVES) {
       const int64_t r = lower ? first + i : first - i;
       int32_t m = 0;
       bool ok = true;
@@ -67,7 +95,8 @@ __global__ void __launch_bounds__(WAVE) k_levels_stream(const int64_t *rp, const
             const int64_t off = lower ? c - first : first - c;  // position in this chunk
             int32_t lv;
             if (off >= 0 && off < i) {
-              lv = clev[off];
+              lv = wait_lds_level(&clev[off], st, r);
+              ok = ok && lv >= 0;
             } else {
               const int v = wait_nonzero(&done[c], st, r);
               ok = ok && v > 0;
@@ -77,21 +106,21 @@ __global__ void __launch_bounds__(WAVE) k_levels_stream(const int64_t *rp, const
           }
         }
       }
-      if (ballot(!ok)) return;
+      if (ballot(!ok)) break;
       m = uniform_i32(wave_max_int(m));
       if (lane == 0) {
         level[r] = m;
-        clev[i] = m;
         st_dev(&done[r], m + 1);
+        __hip_atomic_store(&clev[i], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
-      __syncthreads();
     }
   }
 }
 
-int levels_resident_waves(int num_cu) {
+int levels_resident_groups(int num_cu) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_levels_stream, WAVE, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_levels_stream, WAVE * LEVEL_WAVES, 0) != hipSuccess)
+    return 0;
   return per_cu * num_cu;
 }
 
@@ -107,7 +136,7 @@ int launch_levels_stream(const int64_t *rp, const int32_t *ci, bool lower, int64
                   (void *)&done, (void *)&st};
   // all workgroups resident at once, as in the factorization
   const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_levels_stream),
-                                                  dim3((unsigned)grid), dim3(WAVE), args, 0, s);
+                                                  dim3((unsigned)grid), dim3(WAVE * LEVEL_WAVES), args, 0, s);
   if (e != hipSuccess) return ILU_ERR_HIP;
   return check_launch("levels_stream");
 }
