@@ -539,21 +539,24 @@ struct Segs {
 
 // Level analysis and the cross-workgroup (global) schedule of one factor;
 // S.block_ok tells whether the block-local solve can take it.
-static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, int64_t lo, int64_t hi, Schedule &S,
-                          const Segs &seg, void *stmp, size_t stmpb, hipStream_t s, const char *phase) {
+// Rows [0, nsweep) are swept in dependency order (the segments cover them);
+// rows from nsweep on depend only on rows below nsweep (the rows of W in
+// [L_B; W]) and take their levels in one parallel pass after the sweep.
+static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, int64_t lo, int64_t hi,
+                          int64_t nsweep, Schedule &S, const Segs &seg, hipStream_t s, const char *phase) {
   const int64_t n = T.n;
   S.nrows = n;
   if (n == 0) return 0;
   Mem &mem = P->mem;
   RC(mem.alloc(&S.level_of, n));
-  {
+  if (nsweep > 0) {
     // level sweep on the factorization's kind of schedule (lines and planes
     // of this factor's own pattern, from the bottom for L, the top for U)
     int64_t line = 16, plane = 16, nch = 0, ns = 0, ninit = 0, *sc = nullptr;
     int32_t *chunks = nullptr;
     const int64_t grid = std::min<int64_t>(levels_resident_groups(P->num_cu), (int64_t)P->num_cu * 32 / LEVEL_WAVES);
     if (grid < 1) return fail(ILU_ERR_HIP, "%s: no resident workgroups for the level sweep", phase);
-    RC(row_geometry(tmp, T, n, !lower, s, &line, &plane));
+    RC(row_geometry(tmp, T, nsweep, !lower, s, &line, &plane));
     RC(build_streams(tmp, seg.a_start, seg.a_len, seg.b_start, seg.b_len, line, plane, 4, !lower, grid, &nch, &chunks,
                      &ns, &ninit, &sc, s));
     int *done;
@@ -566,6 +569,7 @@ static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, in
                             grid, s));
     RC(check_status(P, s, phase, nullptr, 0));
   }
+  RC(launch_rows_level(T.rp, T.ci, nsweep, n, lo, nsweep, S.level_of, s));
   int32_t *dmax;
   RC(tmp.alloc(&dmax, 1));
   RC(max_i32(S.level_of, n, dmax, s));
@@ -573,6 +577,19 @@ static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, in
   HIPCK(hipMemcpyAsync(&hmax, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCK(hipStreamSynchronize(s));
   S.nlev = (int64_t)hmax + 1;
+  S.nblk = P->nparts;
+  const uint64_t nkeys = (uint64_t)S.nblk * (uint64_t)S.nlev;
+  S.block_ok = S.nlev <= 16384 && nkeys < (1ull << 31);
+  return 0;
+}
+
+// The cross-workgroup schedule of one factor: rows sorted by level, the
+// level pointers and the chunk table of k_trsv.
+static int build_global(ilu_precond *P, Mem &tmp, Schedule &S, void *stmp, size_t stmpb, hipStream_t s) {
+  const int64_t n = S.nrows;
+  if (n == 0) return 0;
+  Mem &mem = P->mem;
+  const int32_t hmax = (int32_t)(S.nlev - 1);
   uint32_t *key, *key2;
   int32_t *val;
   RC(tmp.alloc(&key, n));
@@ -603,10 +620,6 @@ static int build_schedule(ilu_precond *P, Mem &tmp, const Csr &T, bool lower, in
   S.epoch = 0;
   S.ticket_base = 0;
   S.grid = std::min<int64_t>(S.nchunks, (int64_t)P->num_cu * 16);
-
-  S.nblk = P->nparts;
-  const uint64_t nkeys = (uint64_t)S.nblk * (uint64_t)S.nlev;
-  S.block_ok = S.nlev <= 16384 && nkeys < (1ull << 31);
   return 0;
 }
 
@@ -987,17 +1000,18 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
   }
   const int64_t *bs_int = P->blk_starts, *bs_ifc = P->blk_starts + (nparts + 1),
                 *bs_loc = P->blk_starts + 2 * (nparts + 1);
-  Segs seg_l1{as, al, bs, bl}, seg_u1{as, al, as, std::vector<int64_t>(nparts, 0)}, seg_s;
+  // the interior rows of L1 are swept; its W rows follow in one parallel pass
+  Segs seg_l1{as, al, as, std::vector<int64_t>(nparts, 0)}, seg_u1{as, al, as, std::vector<int64_t>(nparts, 0)}, seg_s;
   for (int k = 0; k < nparts; k++) {
     seg_s.a_start.push_back(bs[k] - nB);
     seg_s.a_len.push_back(bl[k]);
     seg_s.b_start.push_back(0);
     seg_s.b_len.push_back(0);
   }
-  RC(build_schedule(P, tmp, P->L1, true, 0, n, P->sL1, seg_l1, stmp, stmpb, s, "levels L"));
-  RC(build_schedule(P, tmp, P->U1, false, 0, nB, P->sU1, seg_u1, stmp, stmpb, s, "levels U"));
-  RC(build_schedule(P, tmp, P->LS, true, 0, nS, P->sLS, seg_s, stmp, stmpb, s, "levels L_S"));
-  RC(build_schedule(P, tmp, P->US, false, 0, nS, P->sUS, seg_s, stmp, stmpb, s, "levels U_S"));
+  RC(build_schedule(P, tmp, P->L1, true, 0, n, nB, P->sL1, seg_l1, s, "levels L"));
+  RC(build_schedule(P, tmp, P->U1, false, 0, nB, nB, P->sU1, seg_u1, s, "levels U"));
+  RC(build_schedule(P, tmp, P->LS, true, 0, nS, nS, P->sLS, seg_s, s, "levels L_S"));
+  RC(build_schedule(P, tmp, P->US, false, 0, nS, nS, P->sUS, seg_s, s, "levels U_S"));
   // block-local solves for all four factors, or for none
   {
     const Schedule *all[4] = {&P->sL1, &P->sU1, &P->sLS, &P->sUS};
@@ -1015,7 +1029,12 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
     const bool want = mode == ILU_TRSV_BLOCK || (mode == ILU_TRSV_AUTO && n / nparts <= ((int64_t)1 << 20));
     P->block_mode = ok && want;
   }
-  if (P->block_mode) {
+  if (!P->block_mode) {
+    RC(build_global(P, tmp, P->sL1, stmp, stmpb, s));
+    RC(build_global(P, tmp, P->sU1, stmp, stmpb, s));
+    RC(build_global(P, tmp, P->sLS, stmp, stmpb, s));
+    RC(build_global(P, tmp, P->sUS, stmp, stmpb, s));
+  } else {
     RC(build_block(P, tmp, P->L1, P->sL1, bs_int, bs_ifc, nB, nullptr, INT64_MAX, nullptr, s, "levels L"));
     RC(build_block(P, tmp, P->U1, P->sU1, bs_int, nullptr, 0, P->DB, nB, nullptr, s, "levels U"));
     RC(build_block(P, tmp, P->US, P->sUS, bs_loc, nullptr, 0, P->DS, INT64_MAX, nullptr, s, "levels U_S"));

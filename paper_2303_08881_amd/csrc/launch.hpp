@@ -93,6 +93,9 @@ constexpr int LEVEL_WAVES = 2;        // waves per level-sweep workgroup, taking
 // Level sweep over a stream schedule (build_streams); done[] zeroed, grid
 // workgroups all resident (levels_resident_groups) and >= ninit.
 int levels_resident_groups(int num_cu);
+// levels of rows [row0, n) of a lower factor whose dependencies (columns in [lo, hi), below the row) are known
+int launch_rows_level(const int64_t *rp, const int32_t *ci, int64_t row0, int64_t n, int64_t lo, int64_t hi,
+                      int32_t *level, hipStream_t s);
 int launch_levels_stream(const int64_t *rp, const int32_t *ci, bool lower, int64_t lo, int64_t hi,
                          const int32_t *chunks, int64_t nstreams, int64_t ninit, const int64_t *stream_chunk,
                          unsigned int *ticket, int32_t *level, int *done, void *status, int64_t grid, hipStream_t s);

@@ -141,6 +141,27 @@ int launch_levels_stream(const int64_t *rp, const int32_t *ci, bool lower, int64
   return check_launch("levels_stream");
 }
 
+// Levels of rows [row0, n) whose dependencies (columns in [lo, hi), below the
+// row) all have their levels already: one thread per row.
+__global__ void k_rows_level(const int64_t *rp, const int32_t *ci, int64_t row0, int64_t n, int64_t lo, int64_t hi,
+                             int32_t *level) {
+  const int64_t r = row0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  int32_t m = 0;
+  for (int64_t p = rp[r]; p < rp[r + 1]; p++) {
+    const int64_t c = ci[p];
+    if (c >= lo && c < hi && c < r) m = max(m, level[c] + 1);
+  }
+  level[r] = m;
+}
+
+int launch_rows_level(const int64_t *rp, const int32_t *ci, int64_t row0, int64_t n, int64_t lo, int64_t hi,
+                      int32_t *level, hipStream_t s) {
+  if (n <= row0) return 0;
+  k_rows_level<<<(unsigned)((n - row0 + 255) / 256), 256, 0, s>>>(rp, ci, row0, n, lo, hi, level);
+  return check_launch("rows_level");
+}
+
 __global__ void k_levels_to_keys(const int32_t *level, int64_t n, uint32_t *key, int32_t *val) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
