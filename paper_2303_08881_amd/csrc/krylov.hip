@@ -83,21 +83,62 @@ static bool vec2_ok(int64_t n, const void *a, const void *b, const void *c) {
   return (n & 1) == 0 && al(a) && al(b) && al(c);
 }
 
+// The vector passes below load a batch of up to VB elements per thread (pairs
+// with VEC) before using any of them: the stores of a pass may alias its
+// loads in the compiler's eyes, so a plain loop would wait for one memory
+// latency per element.  Each thread still takes its elements in the order
+// i0, i0 + stride, ..., so the partials are the same as an element-by-element
+// loop's.
+constexpr int VB = 8;
+
 template <bool VEC>
-__global__ void __launch_bounds__(RED_THREADS) k_dot_partial(const double *x, const double *y, int64_t n,
-                                                            double *partials) {
+struct Lane2 {
+  double x, y;
+};
+
+template <bool VEC>
+__device__ __forceinline__ Lane2<VEC> ld2(const double *__restrict__ p, int64_t i) {
+  if constexpr (VEC) {
+    const double2 t = reinterpret_cast<const double2 *>(p)[i];
+    return {t.x, t.y};
+  } else {
+    return {p[i], 0.0};
+  }
+}
+template <bool VEC>
+__device__ __forceinline__ void st2(double *__restrict__ p, int64_t i, const Lane2<VEC> &v) {
+  if constexpr (VEC)
+    reinterpret_cast<double2 *>(p)[i] = make_double2(v.x, v.y);
+  else
+    p[i] = v.x;
+}
+// s += a . b over one element (pair): x then y
+template <bool VEC>
+__device__ __forceinline__ double dot2(const Lane2<VEC> &a, const Lane2<VEC> &b, double s) {
+  s = fma(a.x, b.x, s);
+  if constexpr (VEC) s = fma(a.y, b.y, s);
+  return s;
+}
+
+template <bool VEC>
+__global__ void __launch_bounds__(RED_THREADS) k_dot_partial(const double *__restrict__ x,
+                                                            const double *__restrict__ y, int64_t n,
+                                                            double *__restrict__ partials) {
   double s = 0.0;
   const int64_t stride = (int64_t)RED_BLOCKS * RED_THREADS;
   const int64_t i0 = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x;
-  if (VEC) {
-    const double2 *x2 = reinterpret_cast<const double2 *>(x), *y2 = reinterpret_cast<const double2 *>(y);
-    for (int64_t i = i0; i < n / 2; i += stride) {
-      const double2 a = x2[i], b = y2[i];
-      s = fma(a.x, b.x, s);
-      s = fma(a.y, b.y, s);
-    }
-  } else {
-    for (int64_t i = i0; i < n; i += stride) s = fma(x[i], y[i], s);
+  const int64_t m = VEC ? n / 2 : n;
+  for (int64_t base = i0; base < m; base += VB * stride) {
+    Lane2<VEC> a[VB], b[VB];
+#pragma unroll
+    for (int k = 0; k < VB; k++)
+      if (base + k * stride < m) {
+        a[k] = ld2<VEC>(x, base + k * stride);
+        b[k] = ld2<VEC>(y, base + k * stride);
+      }
+#pragma unroll
+    for (int k = 0; k < VB; k++)
+      if (base + k * stride < m) s = dot2<VEC>(a[k], b[k], s);
   }
   s = block_sum(s);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -114,30 +155,31 @@ int launch_dot_partial(const double *x, const double *y, int64_t n, double *part
 // w = a + b and the partials of <w, v> in one pass, each thread summing its
 // elements in the order k_dot_partial uses
 template <bool VEC>
-__global__ void __launch_bounds__(RED_THREADS) k_sum_dot(double *w, const double *a, const double *b,
-                                                        const double *v, int64_t n, double *partials) {
+__global__ void __launch_bounds__(RED_THREADS) k_sum_dot(double *__restrict__ w, const double *__restrict__ a,
+                                                        const double *__restrict__ b, const double *__restrict__ v,
+                                                        int64_t n, double *__restrict__ partials) {
   double s = 0.0;
   const int64_t stride = (int64_t)RED_BLOCKS * RED_THREADS;
   const int64_t i0 = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x;
-  if (VEC) {
-    const double2 *a2 = reinterpret_cast<const double2 *>(a), *b2 = reinterpret_cast<const double2 *>(b),
-                  *v2 = reinterpret_cast<const double2 *>(v);
-    double2 *w2 = reinterpret_cast<double2 *>(w);
-    for (int64_t i = i0; i < n / 2; i += stride) {
-      const double2 x = a2[i], y = b2[i], u = v2[i];
-      double2 t;
-      t.x = x.x + y.x;
-      t.y = x.y + y.y;
-      w2[i] = t;
-      s = fma(t.x, u.x, s);
-      s = fma(t.y, u.y, s);
-    }
-  } else {
-    for (int64_t i = i0; i < n; i += stride) {
-      const double t = a[i] + b[i];
-      w[i] = t;
-      s = fma(t, v[i], s);
-    }
+  const int64_t m = VEC ? n / 2 : n;
+  for (int64_t base = i0; base < m; base += VB * stride) {
+    Lane2<VEC> x[VB], y[VB], u[VB];
+#pragma unroll
+    for (int k = 0; k < VB; k++)
+      if (base + k * stride < m) {
+        x[k] = ld2<VEC>(a, base + k * stride);
+        y[k] = ld2<VEC>(b, base + k * stride);
+        u[k] = ld2<VEC>(v, base + k * stride);
+      }
+#pragma unroll
+    for (int k = 0; k < VB; k++)
+      if (base + k * stride < m) {
+        Lane2<VEC> t;
+        t.x = x[k].x + y[k].x;
+        t.y = x[k].y + y[k].y;
+        st2<VEC>(w, base + k * stride, t);
+        s = dot2<VEC>(t, u[k], s);
+      }
   }
   s = block_sum(s);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -153,42 +195,50 @@ int launch_sum_dot(double *w, const double *a, const double *b, const double *v,
   return check_launch("sum_dot");
 }
 
+// One MGS pass: w -= h v_prev with h the sum of the previous pass's partials,
+// then the partials of <w, v_next> (of <w, w> without v_next).  The first
+// batch of w, v_prev and v_next is loaded before h is reduced, so the loads
+// overlap the reduction.
 template <bool VEC, bool NEXT>
-__global__ void __launch_bounds__(RED_THREADS) k_mgs_step(double *w, const double *v_prev, const double *pp,
-                                                         double *h_out, const double *v_next, int64_t n,
-                                                         double *pn) {
+__global__ void __launch_bounds__(RED_THREADS) k_mgs_step(double *__restrict__ w, const double *__restrict__ v_prev,
+                                                         const double *__restrict__ pp, double *__restrict__ h_out,
+                                                         const double *__restrict__ v_next, int64_t n,
+                                                         double *__restrict__ pn) {
   __shared__ double sh;
-  if (threadIdx.x < WAVE) {
-    double h = reduce_partials(pp);
-    if (threadIdx.x == 0) {
-      sh = h;
-      if (blockIdx.x == 0) *h_out = h;
-    }
-  }
-  __syncthreads();
-  const double h = sh;
-  double s = 0.0;
   const int64_t stride = (int64_t)RED_BLOCKS * RED_THREADS;
   const int64_t i0 = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x;
-  if (VEC) {
-    double2 *w2 = reinterpret_cast<double2 *>(w);
-    const double2 *p2 = reinterpret_cast<const double2 *>(v_prev), *n2 = reinterpret_cast<const double2 *>(v_next);
-    for (int64_t i = i0; i < n / 2; i += stride) {
-      double2 wi = w2[i];
-      const double2 vp = p2[i];
-      wi.x = fma(-h, vp.x, wi.x);
-      wi.y = fma(-h, vp.y, wi.y);
-      w2[i] = wi;
-      const double2 vn = NEXT ? n2[i] : wi;
-      s = fma(wi.x, vn.x, s);
-      s = fma(wi.y, vn.y, s);
+  const int64_t m = VEC ? n / 2 : n;
+  double s = 0.0, h = 0.0;
+  for (int64_t base = i0, batch = 0;; base += VB * stride, batch++) {
+    Lane2<VEC> wv[VB], pv[VB], nv[VB];
+#pragma unroll
+    for (int k = 0; k < VB; k++)
+      if (base + k * stride < m) {
+        wv[k] = ld2<VEC>(w, base + k * stride);
+        pv[k] = ld2<VEC>(v_prev, base + k * stride);
+        if (NEXT) nv[k] = ld2<VEC>(v_next, base + k * stride);
+      }
+    if (batch == 0) {  // every thread of the block takes this branch once
+      if (threadIdx.x < WAVE) {
+        const double hh = reduce_partials(pp);
+        if (threadIdx.x == 0) {
+          sh = hh;
+          if (blockIdx.x == 0) *h_out = hh;
+        }
+      }
+      __syncthreads();
+      h = sh;
     }
-  } else {
-    for (int64_t i = i0; i < n; i += stride) {
-      const double wi = fma(-h, v_prev[i], w[i]);
-      w[i] = wi;
-      s = fma(wi, NEXT ? v_next[i] : wi, s);
-    }
+#pragma unroll
+    for (int k = 0; k < VB; k++)
+      if (base + k * stride < m) {
+        Lane2<VEC> t;
+        t.x = fma(-h, pv[k].x, wv[k].x);
+        t.y = fma(-h, pv[k].y, wv[k].y);
+        st2<VEC>(w, base + k * stride, t);
+        s = dot2<VEC>(t, NEXT ? nv[k] : t, s);
+      }
+    if (base + VB * stride >= m) break;
   }
   s = block_sum(s);
   if (threadIdx.x == 0) pn[blockIdx.x] = s;
@@ -312,16 +362,19 @@ __global__ void __launch_bounds__(RED_THREADS) k_givens_scale(double *H, int ldh
   if (hn == 0.0) return;
   const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
   const int64_t i0 = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x;
-  if (VEC) {
-    double2 *w2 = reinterpret_cast<double2 *>(w);
-    for (int64_t i = i0; i < n / 2; i += stride) {
-      double2 t = w2[i];
-      t.x = t.x / hn;
-      t.y = t.y / hn;
-      w2[i] = t;
-    }
-  } else {
-    for (int64_t i = i0; i < n; i += stride) w[i] = w[i] / hn;
+  const int64_t m = VEC ? n / 2 : n;
+  for (int64_t base = i0; base < m; base += VB * stride) {
+    Lane2<VEC> t[VB];
+#pragma unroll
+    for (int k = 0; k < VB; k++)
+      if (base + k * stride < m) t[k] = ld2<VEC>(w, base + k * stride);
+#pragma unroll
+    for (int k = 0; k < VB; k++)
+      if (base + k * stride < m) {
+        t[k].x = t[k].x / hn;
+        t[k].y = t[k].y / hn;
+        st2<VEC>(w, base + k * stride, t[k]);
+      }
   }
 }
 
