@@ -252,7 +252,12 @@ struct GmresWork {
   double *V = nullptr, *Zb = nullptr, *r = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
          *c = nullptr, *pa = nullptr, *pb = nullptr, *scal = nullptr;  // scal: [0] bnorm [1] beta [2] hn [3] est
   int *flags = nullptr;                                                // [0] stop [1] nsteps
+  hipEvent_t ev[2] = {nullptr, nullptr};                               // read-backs of two consecutive steps
   Mem mem;
+  ~GmresWork() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 struct ilu_precond {
@@ -1240,6 +1245,7 @@ static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, doub
     RC(w.mem.alloc(&w.pb, RED_BLOCKS));
     RC(w.mem.alloc(&w.scal, 8));
     RC(w.mem.alloc(&w.flags, 4));
+    for (hipEvent_t &e : w.ev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   GmresWork &w = *P->gw;
   double *bnorm = w.scal, *beta = w.scal + 1, *hn = w.scal + 2, *est = w.scal + 3;
@@ -1274,7 +1280,26 @@ static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, doub
     while (!converged && its < maxit) {
       RC(launch_scale_copy(w.r, nullptr, beta, w.V, n, nullptr, s));
       RC(launch_init_krylov(w.g, beta, stop, nsteps, s));
-      for (int j = 0; j < m; j++) {
+      // Step j is enqueued before the estimate and stop word of step j - 1
+      // are read back (two pinned slots, one event each), so the host round
+      // trip overlaps step j.  A step enqueued after one that stopped leaves
+      // H, g and nsteps alone (the Givens kernel sees the stop word); no step
+      // is enqueued beyond maxit.
+      double *hest = P->host_pinned + 2;                          // [2] estimates
+      int *hflag = reinterpret_cast<int *>(P->host_pinned + 4);  // [2] stop words
+      int pending = -1;  // slot of the step whose results are not read yet
+      bool cycle_done = false;
+      auto consume = [&](int slot) -> int {
+        HIPCK(hipEventSynchronize(w.ev[slot]));
+        its++;
+        if (g_timing) timing_collect();
+        if (hist) hist[its] = hest[slot] / hb;
+        if (hflag[slot] == 3) return fail(ILU_ERR_BREAKDOWN, "non-finite value in the Arnoldi process at step %d", its);
+        if (hflag[slot] || its >= maxit) cycle_done = true;
+        return 0;
+      };
+      for (int j = 0; j < m && !cycle_done; j++) {
+        if (its + (pending >= 0 ? 1 : 0) >= maxit) break;
         double *vj = w.V + (int64_t)j * n, *wv = w.V + (int64_t)(j + 1) * n, *zj = w.Zb + (int64_t)j * n;
         RC(apply_impl(P, vj, zj, s));
         RC(timed(ILU_K_SPMV, spmv_bytes(n, A->nnz, false), s, [&] { return launch_spmv(rp, ci, av, n, zj, wv, s); }));
@@ -1288,17 +1313,14 @@ static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, doub
           std::swap(pc, pn);
         }
         RC(launch_givens_scale(w.H, ldh, w.cs, w.sn, w.g, j, pc, stop, nsteps, est, hn, bnorm, rtol, wv, n, s));
-        its++;
-        HIPCK(hipMemcpyAsync(P->host_pinned, est, sizeof(double), hipMemcpyDeviceToHost, s));
-        int hstop = 0;
-        HIPCK(hipMemcpyAsync(&hstop, stop, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCK(hipStreamSynchronize(s));
-        const double e = P->host_pinned[0];
-        if (g_timing) timing_collect();
-        if (hist) hist[its] = e / hb;
-        if (hstop == 3) return fail(ILU_ERR_BREAKDOWN, "non-finite value in the Arnoldi process at step %d", its);
-        if (hstop || its >= maxit) break;
+        const int slot = j & 1;
+        HIPCK(hipMemcpyAsync(hest + slot, est, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(hflag + slot, stop, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCK(hipEventRecord(w.ev[slot], s));
+        if (pending >= 0) RC(consume(pending));
+        pending = slot;
       }
+      if (pending >= 0 && !cycle_done) RC(consume(pending));
       RC(launch_backsolve(w.H, ldh, w.g, nsteps, w.c, s));
       RC(launch_combine(x, w.Zb, n, w.c, nsteps, n, true, s));
       RC(launch_residual(rp, ci, av, n, b, x, w.r, s));

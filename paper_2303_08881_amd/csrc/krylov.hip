@@ -20,22 +20,47 @@ namespace silu {
 
 constexpr int RED_THREADS = 256;
 
-__global__ void k_spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x,
-                       double *y) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int64_t p = rp[i]; p < rp[i + 1]; p++) s = fma(v[p], x[ci[p]], s);
-  y[i] = s;
+// s (+/-)= sum_p v[p] x[ci[p]] over p in [pb, pe), in column order: the
+// entries are taken SPMV_B at a time, their columns and values loaded first,
+// then the x values, so a row costs about two memory latencies, not one per
+// entry.
+constexpr int SPMV_B = 8;
+
+template <bool NEG>
+__device__ __forceinline__ double row_dot(const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                          const double *__restrict__ x, int64_t pb, int64_t pe, double s) {
+  for (int64_t p0 = pb; p0 < pe; p0 += SPMV_B) {
+    int32_t c[SPMV_B];
+    double a[SPMV_B], xv[SPMV_B];
+#pragma unroll
+    for (int k = 0; k < SPMV_B; k++)
+      if (p0 + k < pe) {
+        c[k] = ci[p0 + k];
+        a[k] = v[p0 + k];
+      }
+#pragma unroll
+    for (int k = 0; k < SPMV_B; k++)
+      if (p0 + k < pe) xv[k] = x[c[k]];
+#pragma unroll
+    for (int k = 0; k < SPMV_B; k++)
+      if (p0 + k < pe) s = fma(NEG ? -a[k] : a[k], xv[k], s);
+  }
+  return s;
 }
 
-__global__ void k_residual(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
-                           const double *x, double *r) {
+__global__ void k_spmv(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ v,
+                       int64_t n, const double *__restrict__ x, double *__restrict__ y) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double s = b[i];
-  for (int64_t p = rp[i]; p < rp[i + 1]; p++) s = fma(-v[p], x[ci[p]], s);
-  r[i] = s;
+  y[i] = row_dot<false>(ci, v, x, rp[i], rp[i + 1], 0.0);
+}
+
+__global__ void k_residual(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                           const double *__restrict__ v, int64_t n, const double *__restrict__ b,
+                           const double *__restrict__ x, double *__restrict__ r) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  r[i] = row_dot<true>(ci, v, x, rp[i], rp[i + 1], b[i]);
 }
 
 int launch_spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x, double *y,
