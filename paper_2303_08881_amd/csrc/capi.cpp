@@ -382,8 +382,11 @@ static int build_streams(Mem &tmp, const std::vector<int64_t> &a_start, const st
   *ninit_out = 0;
   *stream_chunk_out = nullptr;
   // plane length in whole chunks; planes merge until every part-A stream can
-  // have a workgroup of its own
-  int64_t per = std::max<int64_t>(1, pa / ca);
+  // have a workgroup of its own.  Without a plane longer than a line (a 2D
+  // grid, or no grid) a segment is one stream, and every workgroup that joins
+  // it takes the next line: the lines of the segment pipeline behind one
+  // another instead of running in consecutive groups on one workgroup each.
+  int64_t per = pa > ca ? std::max<int64_t>(1, pa / ca) : ((int64_t)1 << 40);
   for (;;) {
     int64_t na = 0;
     for (int k = 0; k < nseg; k++) na += (a_len[k] + ca * per - 1) / (ca * per);
