@@ -1142,7 +1142,7 @@ static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t 
   int *stop = P->iflags, *nsteps = P->iflags + 1;
   const int ldh = k + 1;
   RC(launch_dot_partial(V, V, nS, P->ipa, s));
-  RC(launch_reduce_final(P->ipa, beta, s));
+  RC(launch_reduce_final(P->ipa, nS, beta, s));
   RC(launch_init_krylov(P->ig, beta, stop, nsteps, s));
   RC(launch_scale_copy(V, nullptr, beta, V, nS, nullptr, s));
   for (int j = 0; j < k; j++) {
@@ -1261,7 +1261,7 @@ static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, doub
   double relres = 0.0;
 
   RC(launch_dot_partial(b, b, n, w.pa, s));
-  RC(launch_reduce_final(w.pa, bnorm, s));
+  RC(launch_reduce_final(w.pa, n, bnorm, s));
   RC(read_scalars(P, bnorm, 1, s));
   const double hb = P->host_pinned[0];
   if (!std::isfinite(hb)) return fail(ILU_ERR_BREAKDOWN, "non-finite ||b||");
@@ -1273,7 +1273,7 @@ static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, doub
   } else {
     RC(launch_residual(rp, ci, av, n, b, x, w.r, s));
     RC(launch_dot_partial(w.r, w.r, n, w.pa, s));
-    RC(launch_reduce_final(w.pa, beta, s));
+    RC(launch_reduce_final(w.pa, n, beta, s));
     RC(read_scalars(P, beta, 1, s));
     double hbeta = P->host_pinned[0];
     relres = hbeta / hb;
@@ -1328,7 +1328,7 @@ static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, doub
       RC(launch_combine(x, w.Zb, n, w.c, nsteps, n, true, s));
       RC(launch_residual(rp, ci, av, n, b, x, w.r, s));
       RC(launch_dot_partial(w.r, w.r, n, w.pa, s));
-      RC(launch_reduce_final(w.pa, beta, s));
+      RC(launch_reduce_final(w.pa, n, beta, s));
       RC(read_scalars(P, beta, 1, s));
       hbeta = P->host_pinned[0];
       relres = hbeta / hb;

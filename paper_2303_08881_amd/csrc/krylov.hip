@@ -4,15 +4,18 @@
 //
 // * SpMV and residual: one row per lane, entries summed in column order with
 //   fma (the sequential definition, so results are reproducible bit for bit).
-// * Reductions are deterministic: a fixed grid of RED_BLOCKS blocks writes
-//   one partial per block, and every consumer re-reduces the partials in the
-//   same fixed order, so all blocks agree on the value without atomics.
+// * Reductions are deterministic: a grid of red_blocks(n) blocks (a function
+//   of the vector length only) writes one partial per block, and every
+//   consumer re-reduces the partials in the same fixed order, so all blocks
+//   agree on the value without atomics.
 // * Modified Gram-Schmidt runs as j+1 fused passes: pass i subtracts
 //   h_{i-1} v_{i-1} from w and forms the partial dot with v_i.
 // * The Hessenberg column update, Givens rotation and residual estimate run
 //   in the first thread of the normalisation kernel; a device stop word lets
 //   the reduced-system GMRES run its fixed number of steps with no host
 //   synchronisation.
+#include <algorithm>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -92,10 +95,10 @@ __device__ double block_sum(double v) {
 
 // every caller gets the same value: lane l sums partials l, l+64, ... in
 // order, then a fixed butterfly
-__device__ double reduce_partials(const double *p) {
+__device__ double reduce_partials(const double *p, int nb) {
   const int lane = lane_id();
   double s = 0.0;
-  for (int k = lane; k < RED_BLOCKS; k += WAVE) s += p[k];
+  for (int k = lane; k < nb; k += WAVE) s += p[k];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, WAVE);
   return s;
 }
@@ -103,6 +106,16 @@ __device__ double reduce_partials(const double *p) {
 // Vector passes take 16-byte loads (two elements) when every operand allows
 // it (VEC: n even, pointers 16-byte aligned); each thread still accumulates
 // its elements in a fixed order, so the partials are the same on every run.
+constexpr int VB = 8;  // element pairs per thread loaded before use (see the vector passes below)
+
+// Blocks (and partials) of the reductions over vectors of length n: enough
+// for VB element pairs per thread, at most RED_BLOCKS.  A function of n only,
+// so every pass of one Krylov process agrees on it.
+static int red_blocks(int64_t n) {
+  const int64_t per = 2LL * VB * RED_THREADS;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(RED_BLOCKS, (n + per - 1) / per));
+}
+
 static bool vec2_ok(int64_t n, const void *a, const void *b, const void *c) {
   auto al = [](const void *p) { return p == nullptr || ((uintptr_t)p & 15) == 0; };
   return (n & 1) == 0 && al(a) && al(b) && al(c);
@@ -114,7 +127,6 @@ static bool vec2_ok(int64_t n, const void *a, const void *b, const void *c) {
 // latency per element.  Each thread still takes its elements in the order
 // i0, i0 + stride, ..., so the partials are the same as an element-by-element
 // loop's.
-constexpr int VB = 8;
 
 template <bool VEC>
 struct Lane2 {
@@ -150,7 +162,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_dot_partial(const double *__res
                                                             const double *__restrict__ y, int64_t n,
                                                             double *__restrict__ partials) {
   double s = 0.0;
-  const int64_t stride = (int64_t)RED_BLOCKS * RED_THREADS;
+  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
   const int64_t i0 = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x;
   const int64_t m = VEC ? n / 2 : n;
   for (int64_t base = i0; base < m; base += VB * stride) {
@@ -171,9 +183,9 @@ __global__ void __launch_bounds__(RED_THREADS) k_dot_partial(const double *__res
 
 int launch_dot_partial(const double *x, const double *y, int64_t n, double *partials, hipStream_t s) {
   if (vec2_ok(n, x, y, nullptr))
-    k_dot_partial<true><<<RED_BLOCKS, RED_THREADS, 0, s>>>(x, y, n, partials);
+    k_dot_partial<true><<<red_blocks(n), RED_THREADS, 0, s>>>(x, y, n, partials);
   else
-    k_dot_partial<false><<<RED_BLOCKS, RED_THREADS, 0, s>>>(x, y, n, partials);
+    k_dot_partial<false><<<red_blocks(n), RED_THREADS, 0, s>>>(x, y, n, partials);
   return check_launch("dot_partial");
 }
 
@@ -184,7 +196,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_sum_dot(double *__restrict__ w,
                                                         const double *__restrict__ b, const double *__restrict__ v,
                                                         int64_t n, double *__restrict__ partials) {
   double s = 0.0;
-  const int64_t stride = (int64_t)RED_BLOCKS * RED_THREADS;
+  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
   const int64_t i0 = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x;
   const int64_t m = VEC ? n / 2 : n;
   for (int64_t base = i0; base < m; base += VB * stride) {
@@ -214,9 +226,9 @@ int launch_sum_dot(double *w, const double *a, const double *b, const double *v,
                    hipStream_t s) {
   const bool vec = vec2_ok(n, w, a, b) && vec2_ok(n, v, nullptr, nullptr);
   if (vec)
-    k_sum_dot<true><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, a, b, v, n, partials);
+    k_sum_dot<true><<<red_blocks(n), RED_THREADS, 0, s>>>(w, a, b, v, n, partials);
   else
-    k_sum_dot<false><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, a, b, v, n, partials);
+    k_sum_dot<false><<<red_blocks(n), RED_THREADS, 0, s>>>(w, a, b, v, n, partials);
   return check_launch("sum_dot");
 }
 
@@ -230,7 +242,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_mgs_step(double *__restrict__ w
                                                          const double *__restrict__ v_next, int64_t n,
                                                          double *__restrict__ pn) {
   __shared__ double sh;
-  const int64_t stride = (int64_t)RED_BLOCKS * RED_THREADS;
+  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
   const int64_t i0 = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x;
   const int64_t m = VEC ? n / 2 : n;
   double s = 0.0, h = 0.0;
@@ -245,7 +257,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_mgs_step(double *__restrict__ w
       }
     if (batch == 0) {  // every thread of the block takes this branch once
       if (threadIdx.x < WAVE) {
-        const double hh = reduce_partials(pp);
+        const double hh = reduce_partials(pp, (int)gridDim.x);
         if (threadIdx.x == 0) {
           sh = hh;
           if (blockIdx.x == 0) *h_out = hh;
@@ -274,27 +286,27 @@ int launch_mgs_step(double *w, const double *v_prev, const double *partials_prev
   (void)stop;
   const bool vec = vec2_ok(n, w, v_prev, v_next);
   if (vec && v_next)
-    k_mgs_step<true, true><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, v_prev, partials_prev, h_out, v_next, n,
+    k_mgs_step<true, true><<<red_blocks(n), RED_THREADS, 0, s>>>(w, v_prev, partials_prev, h_out, v_next, n,
                                                               partials_next);
   else if (vec)
-    k_mgs_step<true, false><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, v_prev, partials_prev, h_out, v_next, n,
+    k_mgs_step<true, false><<<red_blocks(n), RED_THREADS, 0, s>>>(w, v_prev, partials_prev, h_out, v_next, n,
                                                                partials_next);
   else if (v_next)
-    k_mgs_step<false, true><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, v_prev, partials_prev, h_out, v_next, n,
+    k_mgs_step<false, true><<<red_blocks(n), RED_THREADS, 0, s>>>(w, v_prev, partials_prev, h_out, v_next, n,
                                                                partials_next);
   else
-    k_mgs_step<false, false><<<RED_BLOCKS, RED_THREADS, 0, s>>>(w, v_prev, partials_prev, h_out, v_next, n,
+    k_mgs_step<false, false><<<red_blocks(n), RED_THREADS, 0, s>>>(w, v_prev, partials_prev, h_out, v_next, n,
                                                                 partials_next);
   return check_launch("mgs_step");
 }
 
-__global__ void k_reduce_final(const double *partials, double *out, bool take_sqrt) {
-  double s = reduce_partials(partials);
+__global__ void k_reduce_final(const double *partials, int nb, double *out, bool take_sqrt) {
+  double s = reduce_partials(partials, nb);
   if (threadIdx.x == 0) *out = take_sqrt ? sqrt(s) : s;
 }
 
-int launch_reduce_final(const double *partials, double *out, hipStream_t s) {
-  k_reduce_final<<<1, WAVE, 0, s>>>(partials, out, true);
+int launch_reduce_final(const double *partials, int64_t n, double *out, hipStream_t s) {
+  k_reduce_final<<<1, WAVE, 0, s>>>(partials, red_blocks(n), out, true);
   return check_launch("reduce_final");
 }
 
@@ -352,7 +364,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_givens_scale(double *H, int ldh
                                                              double rtol, double *w, int64_t n) {
   __shared__ double sh;
   if (threadIdx.x < WAVE) {
-    const double hn2 = reduce_partials(pnorm);
+    const double hn2 = reduce_partials(pnorm, (int)gridDim.x);
     if (threadIdx.x == 0) sh = sqrt(hn2);
   }
   __syncthreads();
@@ -407,10 +419,10 @@ int launch_givens_scale(double *H, int ldh, double *cs, double *sn, double *g, i
                         int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol, double *w,
                         int64_t n, hipStream_t s) {
   if (vec2_ok(n, w, nullptr, nullptr))
-    k_givens_scale<true><<<RED_BLOCKS, RED_THREADS, 0, s>>>(H, ldh, cs, sn, g, j, pnorm, stop, nsteps, est, hn_out,
+    k_givens_scale<true><<<red_blocks(n), RED_THREADS, 0, s>>>(H, ldh, cs, sn, g, j, pnorm, stop, nsteps, est, hn_out,
                                                            tol_ref, rtol, w, n);
   else
-    k_givens_scale<false><<<RED_BLOCKS, RED_THREADS, 0, s>>>(H, ldh, cs, sn, g, j, pnorm, stop, nsteps, est, hn_out,
+    k_givens_scale<false><<<red_blocks(n), RED_THREADS, 0, s>>>(H, ldh, cs, sn, g, j, pnorm, stop, nsteps, est, hn_out,
                                                             tol_ref, rtol, w, n);
   return check_launch("givens_scale");
 }

@@ -191,13 +191,14 @@ int launch_spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n
                 hipStream_t s);
 int launch_residual(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
                     const double *x, double *r, hipStream_t s);
-constexpr int RED_BLOCKS = 512;  // fixed grid of the deterministic reductions
+constexpr int RED_BLOCKS = 512;  // most blocks (and partials) of the deterministic reductions
 int launch_dot_partial(const double *x, const double *y, int64_t n, double *partials, hipStream_t s);
 // w -= h v_prev with h = sum(partials_prev) (also stored to *h_out), then the
 // partial dot of the new w with v_next (with w itself when v_next is NULL)
 int launch_mgs_step(double *w, const double *v_prev, const double *partials_prev, double *h_out,
                     const double *v_next, int64_t n, double *partials_next, const int *stop, hipStream_t s);
-int launch_reduce_final(const double *partials, double *out, hipStream_t s);  // *out = sqrt(sum)
+// *out = sqrt(sum of the partials a pass over vectors of length n wrote)
+int launch_reduce_final(const double *partials, int64_t n, double *out, hipStream_t s);
 int launch_scale_copy(const double *x, const double *alpha_num, const double *alpha_den, double *y, int64_t n,
                       const int *stop, hipStream_t s);  // y = x / (*den), skipped if *den == 0
 int launch_copy(const double *x, double *y, int64_t n, hipStream_t s);

@@ -1,6 +1,8 @@
 // prims.hip -- integer primitives for the setup phase: exclusive scan, stable
 // LSD radix sort, key histogram, fills.  All results are exact integers and
 // independent of scheduling (no order-dependent atomics on outputs).
+#include <algorithm>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -273,16 +275,31 @@ int iota_i32(int32_t *p, int64_t n, hipStream_t s) {
   return check_launch("iota");
 }
 
-__global__ void k_max_i32(const int32_t *p, int64_t n, int32_t *out) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int v = i < n ? p[i] : -1;
+// max over the grid: each block folds its grid-stride share, then one atomic
+// per block (a single counter hit by every wave would serialise)
+constexpr int MAX_BLOCKS = 1024;
+__device__ inline void block_max_atomic(int v, int32_t *out) {
+  __shared__ int wm[256 / WAVE];
   v = wave_max_int(v);
-  if (lane_id() == 0 && v >= 0) atomicMax(out, v);
+  if (lane_id() == 0) wm[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int m = wm[0];
+    for (int k = 1; k < (int)(blockDim.x / WAVE); k++) m = max(m, wm[k]);
+    if (m >= 0) atomicMax(out, m);
+  }
+}
+__global__ void __launch_bounds__(256) k_max_i32(const int32_t *p, int64_t n, int32_t *out) {
+  int v = -1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v = max(v, p[i]);
+  block_max_atomic(v, out);
 }
 int max_i32(const int32_t *p, int64_t n, int32_t *d_out, hipStream_t s) {
   if (int rc = fill_i32(d_out, -1, 1, s)) return rc;
   if (n <= 0) return 0;
-  k_max_i32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, d_out);
+  const int64_t g = std::min<int64_t>((n + 255) / 256, MAX_BLOCKS);
+  k_max_i32<<<(unsigned)g, 256, 0, s>>>(p, n, d_out);
   return check_launch("max_i32");
 }
 

@@ -437,13 +437,15 @@ __global__ void k_pos_of_row(const int32_t *rows, int64_t n, int32_t *pos) {
 }
 
 // dependency entries (columns < split) of the row at each position; maximum
+// (one atomic per wave)
 __global__ void k_lds_counts(const int32_t *rows, const int64_t *rp, const int32_t *ci, int64_t n, int64_t split,
                              int32_t *maxent) {
   int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (q >= n) return;
   int32_t k = 0;
-  for (int64_t p = rp[rows[q]]; p < rp[rows[q] + 1]; p++) k += ci[p] < split;
-  atomicMax(maxent, k);
+  if (q < n)
+    for (int64_t p = rp[rows[q]]; p < rp[rows[q] + 1]; p++) k += ci[p] < split;
+  k = wave_max_int(k);
+  if (lane_id() == 0) atomicMax(maxent, k);
 }
 
 // widest level of any block
