@@ -36,7 +36,9 @@ namespace silu {
 constexpr int FACT_CAP = 512;  // working-row capacity (entries) per wave
 constexpr int FACT_UCACHE = 768;  // LDS entries caching the U rows of a round's pivots (>= FACT_CAP, so a
                                   // round's first pivot always fits)
-constexpr int FACT_UROW = 16;     // entries of a cached U row fetched by unrolled loads (the rest in a loop)
+constexpr int FACT_UROW = 20;     // entries of a cached U row fetched with the diagonal (the fill limit
+                                  // of the usual ILUT settings, so one trip to memory reads the row)
+constexpr int FACT_UTAIL = 8;     // entries per lane in each further batch of a longer row
 
 struct FactArgs {
   const int64_t *rp;
@@ -218,27 +220,46 @@ __device__ __forceinline__ bool factor_row(const FactArgs &a, int64_t r, const F
       first = false;
       // the pivot at pos is waited for; the pivots after it are taken as far
       // as they are already complete (one poll each), so a row eliminates its
-      // early pivots while a later one is still being factored
+      // early pivots while a later one is still being factored.  The poll and
+      // the slot of each candidate's U row (start and capacity, fixed before
+      // the launch) are read in one trip; the diagonal, the length and the
+      // first FACT_UROW entries of the slot (those past the length are read
+      // and ignored) in a second one.
+      const int x = pos + lane;
+      const int32_t kx0 = x < len ? wc[x] : 0x7fffffff;
+      const bool cand = kx0 < lim;  // true on lane 0: kx0 == k
+      int flag = 0, ucap = 0;
+      int64_t ub = 0;
+      if (cand) {
+        flag = ld_relaxed(&a.done[kx0]);
+        ub = a.Urp[kx0];
+        ucap = (int)(a.Urp[kx0 + 1] - ub);
+      }
       bool ok = true;
-      if (lane == 0) ok = wait_flag_eq(&a.done[k], a.epoch, a.st, r);
+      if (lane == 0 && flag != a.epoch) ok = wait_flag_eq(&a.done[k], a.epoch, a.st, r);
       if (!uniform_i32((int)ok)) {
         failed = true;
         break;
       }
-      const int x = pos + lane;
-      const int32_t kx0 = x < len ? wc[x] : 0x7fffffff;
-      const bool ready = kx0 < lim && (x == pos || ld_relaxed(&a.done[kx0]) == a.epoch);
-      const unsigned long long waiting = ballot(kx0 < lim && !ready);
+      const bool ready = cand && (x == pos || flag == a.epoch);
+      const unsigned long long waiting = ballot(cand && !ready);
       const int nready = waiting ? __ffsll((long long)waiting) - 1 : WAVE;  // covered pivots: lanes [0, nready)
-      const int32_t kx = lane < nready ? kx0 : 0x7fffffff;
-      const bool piv = kx < lim;  // the covered pivots are a prefix of [pos, len)
+      const bool piv = cand && lane < nready;  // the covered pivots are a prefix of [pos, len)
+      const int32_t kx = piv ? kx0 : 0;
       double dk = 0.0;
-      int64_t ub = 0;
       int ul = 0;
+      int32_t uc_[FACT_UROW];
+      double uv_[FACT_UROW];
       if (piv) {
         dk = ld_dev(a.D + kx);
-        ub = a.Urp[kx];  // fixed before the launch
         ul = ld_dev(a.Ulen + kx);
+#pragma unroll
+        for (int q = 0; q < FACT_UROW; q++) {
+          if (q < ucap) {
+            uc_[q] = ld_dev(a.Uc + ub + q);
+            uv_[q] = ld_dev(a.Uv + ub + q);
+          }
+        }
       }
       // exclusive prefix sum of the row lengths over the lanes
       int off = ul;
@@ -248,16 +269,6 @@ __device__ __forceinline__ bool factor_row(const FactArgs &a, int64_t r, const F
       }
       off -= ul;
       const bool cached = piv && off + ul <= FACT_UCACHE;
-      // every load of the copy first, then the LDS stores
-      int32_t uc_[FACT_UROW];
-      double uv_[FACT_UROW];
-#pragma unroll
-      for (int q = 0; q < FACT_UROW; q++) {
-        if (cached && q < ul) {
-          uc_[q] = ld_dev(a.Uc + ub + q);
-          uv_[q] = ld_dev(a.Uv + ub + q);
-        }
-      }
 #pragma unroll
       for (int q = 0; q < FACT_UROW; q++) {
         if (cached && q < ul) {
@@ -265,9 +276,24 @@ __device__ __forceinline__ bool factor_row(const FactArgs &a, int64_t r, const F
           cv[off + q] = uv_[q];
         }
       }
-      for (int q = FACT_UROW; cached && q < ul; q++) {
-        cc[off + q] = ld_dev(a.Uc + ub + q);
-        cv[off + q] = ld_dev(a.Uv + ub + q);
+      // longer rows: the rest in batches of FACT_UTAIL loads per lane
+      for (int q0 = FACT_UROW; ballot(cached && q0 < ul); q0 += FACT_UTAIL) {
+        int32_t tc_[FACT_UTAIL];
+        double tv_[FACT_UTAIL];
+#pragma unroll
+        for (int q = 0; q < FACT_UTAIL; q++) {
+          if (cached && q0 + q < ul) {
+            tc_[q] = ld_dev(a.Uc + ub + q0 + q);
+            tv_[q] = ld_dev(a.Uv + ub + q0 + q);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < FACT_UTAIL; q++) {
+          if (cached && q0 + q < ul) {
+            cc[off + q0 + q] = tc_[q];
+            cv[off + q0 + q] = tv_[q];
+          }
+        }
       }
       if (cached) {
         tD[lane] = dk;
