@@ -685,7 +685,7 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   // rows, else lanes of 8, as few as cover the longest row (at most 8)
   int G = 1, E = hm[0] <= 2 ? 2 : hm[0] <= 4 ? 4 : 8;
   while (E == 8 && G < 8 && 8 * G < hm[0]) G *= 2;
-  if ((nloc + 1) * (int64_t)G * E >= ((int64_t)1 << 30))
+  if ((nloc + 1) * (int64_t)G * E >= ((int64_t)1 << 29))  // byte offsets of the values below 2^32
     return fail(ILU_ERR_INVALID_ARG, "%s: factor too large for the block solve", phase);
   const int64_t bt = ((int64_t)std::max(hm[1], 1) * G + 63) / 64 * 64;
   S.lds_g = G;
@@ -696,7 +696,7 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   RC(mem.alloc(&S.lds_v, ne));
   RC(mem.alloc(&S.lds_rec, 4 * (nloc + 1)));
   S.out_map = omap ? omap : S.pos;
-  RC(launch_lds_fill(S.blk_rows, T.rp, T.ci, T.v, diag, nloc, ext_col, S.pos, S.blk_lev_ptr, (int64_t)nkeys, G * E,
+  RC(launch_lds_fill(S.blk_rows, T.rp, T.ci, T.v, diag, nloc, ext_col, S.pos, S.blk_lev_ptr, (int64_t)nkeys, G, E,
                      S.out_map, S.lds_c, S.lds_v, S.lds_rec, s));
   HIPCK(hipStreamSynchronize(s));
   return 0;

@@ -137,8 +137,8 @@ struct TrsvLaunch {
   const int32_t *blk_rows;     // rows sorted by (block, level)
   const int32_t *blk_lev_ptr;  // [nblk * nlev_blk + 1]
   // block-local storage (launch_trsv_lds): fixed-stride dependency entries
-  const int32_t *lds_c;    // [(nrows + 1) * G * E] window slots
-  const double *lds_v;     // [(nrows + 1) * G * E]
+  const int32_t *lds_c;    // (nrows + 1) * G * E window slots, in planes of 4 per lane (2 for E = 2)
+  const double *lds_v;     // (nrows + 1) * G * E values, in planes of 2 per lane
   const int32_t *lds_rec;  // int4 per position (+ dummy): {row or ~row, output index, diagonal}
   const int32_t *out_map;  // row -> index of its solution in x (the output index of its position)
   int32_t lds_g;           // lanes per row: 1 (E = 2, 4), or 1, 2, 4, 8 (E = 8)
@@ -177,7 +177,7 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
                        const int32_t *lev_ptr, int64_t nseg, int32_t *pos, int32_t *maxent, int32_t *maxw,
                        hipStream_t s);
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
-                    int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int width,
+                    int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G, int E,
                     const int32_t *omap, int32_t *oc, double *ov, int32_t *rec, hipStream_t s);
 // block id of each row from ascending block starts (s1 below split, s2 from split on; s2 may be NULL)
 int launch_row_blocks(int64_t nrows, int32_t nblk, const int64_t *s1, const int64_t *s2, int64_t split, int32_t *blk,

@@ -114,11 +114,15 @@ __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
 // solution of position q goes to out[rec.y], an index fixed at setup (q
 // itself, or the position of the row in the solve that consumes it next).
 // Storage (built at setup):
-//   ent_c/ent_v  the dependency entries of each position at a fixed stride of
-//                G*E (G lanes per row of E = 2, 4 or 8 entries each): column
-//                order, each column replaced by the slot of its position in
-//                the LDS solution window, padded with the window's zero slot
-//                and 0.0;
+//   ent_c/ent_v  the dependency entries of each position, G*E of them (G
+//                lanes per row of E = 2, 4 or 8 entries each): column order,
+//                each column replaced by the slot of its position in the LDS
+//                solution window, padded with the window's zero slot and 0.0.
+//                They are stored in planes, one per load of a lane (4 slots
+//                or 2 values of every lane, lanes consecutive), so that each
+//                load of a wave reads one contiguous range: a lane-major
+//                layout makes a wave's load touch a cache line per lane and
+//                the L1 tag lookups, not the bytes, bound the solve;
 //   rec          {row (or ~row for a slow row), output index, 1 / diagonal}.
 // A row is handled by G consecutive lanes, lane g summing entries
 // gE..gE+E-1 with fma (lane 0 starting from the right-hand side); the G
@@ -160,8 +164,9 @@ constexpr int look_of() {
 }
 
 struct LdsTrsvArgs {
-  const int4 *ent_c;       // [(npos + 1) * G * E / 4] window slots
-  const double2 *ent_v;    // [(npos + 1) * G * E / 2]
+  const int4 *ent_c;       // [E / 4][nent] window slots (int2 [nent] for E = 2)
+  const double2 *ent_v;    // [E / 2][nent]
+  uint32_t nent;           // lanes of entries: (npos + 1) * G
   const int4 *rec;         // [npos + 1]
   const int32_t *lev_ptr;  // [nblk * nlev + 1]
   int32_t nlev;
@@ -201,6 +206,19 @@ struct PSet {
 };
 
 __device__ __forceinline__ double rec_diag(const int4 &r) { return __hiloint2double(r.w, r.z); }
+
+// Element idx of an array whose byte size is below 2^32 (checked at setup):
+// a 32-bit byte offset from a base held in scalar registers, so a load or
+// store needs one 32-bit multiply-add for its address instead of 64-bit
+// arithmetic per lane.
+template <class T>
+__device__ __forceinline__ const T &at32(const T *base, uint32_t idx) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (idx * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ T &at32(T *base, uint32_t idx) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (idx * (uint32_t)sizeof(T)));
+}
 
 // DPP lane exchanges inside groups of 2, 4, 8 lanes (quad permutations, and
 // the mirror of 8 lanes, which pairs each lane with one of the other quad)
@@ -245,15 +263,15 @@ __device__ __forceinline__ void refill(const LdsTrsvArgs &a, int32_t lo, int32_t
   const uint32_t qc = in ? q : (uint32_t)a.npos;
   const uint32_t e = qc * G + g;
   if constexpr (E == 2) {
-    S.c.v = reinterpret_cast<const int2 *>(a.ent_c)[e];
+    S.c.v = at32(reinterpret_cast<const int2 *>(a.ent_c), e);
   } else {
 #pragma unroll
-    for (int i = 0; i < E / 4; i++) S.c.v[i] = a.ent_c[e * (E / 4) + i];
+    for (int i = 0; i < E / 4; i++) S.c.v[i] = at32(a.ent_c, i * a.nent + e);
   }
 #pragma unroll
-  for (int i = 0; i < E / 2; i++) S.w[i] = a.ent_v[e * (E / 2) + i];
-  S.rec = a.rec[qc];
-  S.rhs = a.b[in ? q : 0u];
+  for (int i = 0; i < E / 2; i++) S.w[i] = at32(a.ent_v, i * a.nent + e);
+  S.rec = at32(a.rec, qc);
+  S.rhs = at32(a.b, in ? q : 0u);
 }
 
 template <int G, int E, bool DIAG>
@@ -282,7 +300,7 @@ __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, double *win, const i
   if (mine && slow) s = slow_row<DIAG>(a, r, q, rec_diag(S.rec));
   if (mine && g == 0) {
     win[q & (XWIN - 1)] = s;
-    a.out[(uint32_t)S.rec.y] = s;
+    at32(a.out, (uint32_t)S.rec.y) = s;
   }
   // rows beyond bt/G in this level: one thread each, slow path
   const int32_t cap = a.bt / G;
@@ -377,6 +395,7 @@ static bool lds_args(const TrsvLaunch &t, LdsTrsvArgs &a) {
     return false;
   a.ent_c = reinterpret_cast<const int4 *>(t.lds_c);
   a.ent_v = reinterpret_cast<const double2 *>(t.lds_v);
+  a.nent = (uint32_t)((t.nrows + 1) * t.lds_g);
   a.rec = reinterpret_cast<const int4 *>(t.lds_rec);
   a.lev_ptr = t.blk_lev_ptr;
   a.nlev = (int32_t)t.nlev_blk;
@@ -459,15 +478,27 @@ __global__ void k_max_width(const int32_t *lev_ptr, int64_t nseg, int32_t *out) 
 // output index of position q is omap[rows[q]].
 __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v,
                            const double *diag, int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr,
-                           int64_t nseg, int width, const int32_t *omap, int32_t *oc, double *ov, int4 *rec) {
+                           int64_t nseg, int G, int E, const int32_t *omap, int32_t *oc, double *ov, int4 *rec) {
   int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q > n) return;
-  const int64_t o = q * width, cap = width;
+  const int64_t cap = (int64_t)G * E, nent = (n + 1) * G;
+  // entry k of position q belongs to lane e = q G + k / E as its entry kk =
+  // k % E; each load of the solve reads one plane (4 window slots or 2 values
+  // per lane) for consecutive lanes, so the planes are stored one after the
+  // other
+  auto at_c = [&](int64_t k) {
+    const int64_t e = q * G + k / E, kk = k % E;
+    return E == 2 ? e * 2 + kk : ((kk >> 2) * nent + e) * 4 + (kk & 3);
+  };
+  auto at_v = [&](int64_t k) {
+    const int64_t e = q * G + k / E, kk = k % E;
+    return ((kk >> 1) * nent + e) * 2 + (kk & 1);
+  };
   int64_t k = 0;
   if (q == n) {
     for (; k < cap; k++) {
-      oc[o + k] = XWIN;
-      ov[o + k] = 0.0;
+      oc[at_c(k)] = XWIN;
+      ov[at_v(k)] = 0.0;
     }
     rec[q] = make_int4(0, 0, __double2loint(1.0), __double2hiint(1.0));
     return;
@@ -479,15 +510,15 @@ __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t
       const int32_t pc = pos[ci[p]];
       mind = min(mind, pc);
       if (k < cap) {
-        oc[o + k] = pc & (XWIN - 1);
-        ov[o + k] = v[p];
+        oc[at_c(k)] = pc & (XWIN - 1);
+        ov[at_v(k)] = v[p];
       }
       k++;
     }
   const bool too_long = k > cap;
   for (; k < cap; k++) {
-    oc[o + k] = XWIN;
-    ov[o + k] = 0.0;
+    oc[at_c(k)] = XWIN;
+    ov[at_v(k)] = 0.0;
   }
   // end of q's level: the first segment boundary above q
   int64_t lo = 0, hi = nseg;
@@ -518,9 +549,9 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
 }
 
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
-                    int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int width,
+                    int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G, int E,
                     const int32_t *omap, int32_t *oc, double *ov, int32_t *rec, hipStream_t s) {
-  k_lds_fill<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(rows, rp, ci, v, diag, n, split, pos, lev_ptr, nseg, width,
+  k_lds_fill<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(rows, rp, ci, v, diag, n, split, pos, lev_ptr, nseg, G, E,
                                                               omap, oc, ov, reinterpret_cast<int4 *>(rec));
   return check_launch("lds_fill");
 }
