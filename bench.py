@@ -64,22 +64,23 @@ def source_hash(name: str) -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def kernel_instance(cls: str, sched) -> str | None:
-    """Kernel (demangled name prefix) that runs a kernel class in this workload."""
+def kernel_instance(cls: str, sched, prec: int = 0) -> str | None:
+    """Kernel (demangled name prefix) that runs a kernel class in this workload (prec: storage precision of the
+    triangular factors, 0 FP64, 1 FP32, 2 FP16)."""
     if cls in TRSV_ROLE:
         k, diag = TRSV_ROLE[cls]
         if sched is None or not sched[4 * k]:
             return None
         if cls == "trsv_LS" and len(sched) > 16 and sched[16]:  # L_S and U_S in one launch
-            return f"void silu::k_trsv_lds_pair<{sched[9]}, {sched[10]}>"
-        return f"void silu::k_trsv_lds<{sched[4 * k + 1]}, {sched[4 * k + 2]}, {diag}>"
+            return f"void silu::k_trsv_lds_pair<{sched[9]}, {sched[10]}, {prec}>"
+        return f"void silu::k_trsv_lds<{sched[4 * k + 1]}, {sched[4 * k + 2]}, {diag}, {prec}>"
     return {"spmv_A": "silu::k_spmv(", "spmv_Coff": "silu::k_spmv(", "mgs": "void silu::k_mgs_step<"}.get(cls)
 
 
-def measured_traffic(cls: str, sched):
+def measured_traffic(cls: str, sched, prec: int = 0):
     """HBM bytes per launch of a kernel class from profiles/traffic.json (counter runs of this workload), or None
     when there is none or the kernel's source changed since the counters were taken."""
-    inst = kernel_instance(cls, sched)
+    inst = kernel_instance(cls, sched, prec)
     if inst is None or not os.path.exists(TRAFFIC_JSON):
         return None
     with open(TRAFFIC_JSON) as f:
@@ -157,6 +158,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="aniso3d_128_slab16", choices=sorted(WORKLOADS))
+    ap.add_argument("--factor-prec", default="f64", choices=["f64", "f32", "f16"],
+                    help="storage precision of the triangular factors (the solves run in FP32 for f32 and f16; "
+                         "everything else stays FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=40)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -178,6 +182,8 @@ def main():
     import synth
 
     key, opts, rtol, restart = WORKLOADS[args.workload]
+    prec = {"f64": 0, "f32": 1, "f16": 2}[args.factor_prec]
+    opts = dict(opts, factor_prec=prec)
     A, b, part, nparts = synth.workload(key)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -249,9 +255,9 @@ def main():
         P = silu.setup(Ad, pd, nparts, **opts)
         sched = [int(v) for v in P.export("schedule")]
         P.close()
-        roof = {"kernel": dom, "instance": kernel_instance(dom, sched), "bound": "hbm",
+        roof = {"kernel": dom, "instance": kernel_instance(dom, sched, prec), "bound": "hbm",
                 "achieved": round(d["gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(d["gbs"] / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom, sched),
+                "frac": round(d["gbs"] / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom, sched, prec),
                 "avg_launch_us": round(d["avg_us"], 3), "bytes_per_launch": d["bytes_per_launch"],
                 "launches": d["launches"]}
 
@@ -268,10 +274,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        # arithmetic of the path: FP64 throughout, or the triangular solves in
+        # FP32 (factors stored in FP32 / FP16) beside FP64 Krylov and SpMV
+        "dtype": {0: "f64", 1: "f32+f64", 2: "f32+f64 (f16 factors)"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "description": DESCRIPTION[args.workload], "n": A.n, "nnz": A.nnz,
-                   "subdomains": nparts, "restart": restart, "rtol": rtol},
+                   "subdomains": nparts, "restart": restart, "rtol": rtol, "factor_prec": args.factor_prec},
         "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
         "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
         "setup_ms": round(float(np.mean([o["setup_ms"] for o in outs])), 3),

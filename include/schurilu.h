@@ -51,6 +51,9 @@ extern "C" {
 #define ILU_TRSV_AUTO 0    /* pick per triangular factor (see trsv_mode)       */
 #define ILU_TRSV_LEVELS 1  /* level-scheduled across workgroups, sync-free     */
 #define ILU_TRSV_BLOCK 2   /* one workgroup per subdomain, barrier per level   */
+#define ILU_PREC_F64 0     /* triangular factors stored and solved in FP64      */
+#define ILU_PREC_F32 1     /* stored in FP32, solved in FP32                     */
+#define ILU_PREC_F16 2     /* stored in FP16 (scaled per row), solved in FP32    */
 
 typedef struct {
   int64_t n;               /* rows = columns */
@@ -62,7 +65,8 @@ typedef struct {
 
 /*
  * Options.  Defaults (ilu_default_options): BJ, ILU(0) everywhere, 3 inner
- * GMRES steps (the paper's default, Section 4.1), no drop, pivot errors.
+ * GMRES steps (the paper's default, Section 4.1), no drop, pivot errors,
+ * automatic solve mode, FP64 factors.
  *  interior_fact  factor of each subdomain block A_i (BJ), or of the interior
  *                 rows plus the partial elimination of the interface rows
  *                 (SCHUR, eq. (17));
@@ -83,11 +87,24 @@ typedef struct {
  *                 ILU_ERR_ZERO_PIVOT.  ILU_PIVOT_PERTURB: a pivot with
  *                 |u_ii| < pivot_tol * max_j |a_ij| is replaced by
  *                 +-pivot_tol * max_j |a_ij| (sign of u_ii, + for 0).
- *  trsv_mode      execution of the triangular solves (results are identical
- *                 bit for bit): ILU_TRSV_BLOCK solves each subdomain in one
- *                 workgroup (chosen by AUTO when a subdomain has at most 2^20
- *                 rows and at most 16384 levels); ILU_TRSV_LEVELS spreads every
- *                 level over the whole GPU with sync-free level counters.
+ *  trsv_mode      execution of the triangular solves (results agree to
+ *                 rounding: the block-local solve splits long rows over a few
+ *                 lanes and multiplies by the reciprocal of the diagonal):
+ *                 ILU_TRSV_BLOCK solves each subdomain in one workgroup
+ *                 (chosen by AUTO when a subdomain has at most 2^20 rows and at
+ *                 most 16384 levels); ILU_TRSV_LEVELS spreads every level over
+ *                 the whole GPU with sync-free level counters.
+ *  factor_prec    storage precision of the triangular factors that the
+ *                 preconditioner solves with (L_B, U_B and its Z block, L_S,
+ *                 U_S and their diagonals; the factorization itself is FP64).
+ *                 ILU_PREC_F32 rounds them to FP32 once at setup and runs the
+ *                 triangular solves in FP32; ILU_PREC_F16 stores each entry
+ *                 divided by the largest magnitude of its row, in FP16, with
+ *                 the row scale in FP32, and solves in FP32.  Right-hand sides
+ *                 and results of the solves stay FP64 vectors, and so does
+ *                 everything else (W, C_off, SpMV, Arnoldi, Givens, the
+ *                 convergence test): the outer FGMRES, which allows a varying
+ *                 preconditioner, corrects the lower-precision apply.
  */
 typedef struct {
   int32_t method;
@@ -100,6 +117,7 @@ typedef struct {
   int32_t pivot_mode;
   double pivot_tol;
   int32_t trsv_mode;
+  int32_t factor_prec;
 } ilu_options_t;
 
 typedef struct {

@@ -18,6 +18,9 @@ from .binding import (  # noqa: F401
     TRSV_AUTO,
     TRSV_LEVELS,
     TRSV_BLOCK,
+    PREC_F64,
+    PREC_F32,
+    PREC_F16,
     SchurILUError,
     DeviceCSR,
     Precond,

@@ -238,9 +238,14 @@ struct Schedule {
   int32_t *blk_rows = nullptr, *blk_lev_ptr = nullptr;
   int32_t *pos = nullptr;            // row -> position (inverse of blk_rows)
   const int32_t *out_map = nullptr;  // row -> index of its solution in the output vector
-  // fixed-stride storage of the factor for the block-local solve
+  // storage of the factor for the block-local solve (values in the storage
+  // precision)
   int32_t *lds_c = nullptr, *lds_rec = nullptr;
-  double *lds_v = nullptr;
+  void *lds_v = nullptr;
+  // level-scheduled solve with factors stored in FP32 / FP16: the values, the
+  // FP32 diagonal and (FP16) the row scales
+  void *v_lp = nullptr;
+  float *diag_lp = nullptr, *scale_lp = nullptr;
   int32_t lds_g = 1, lds_e = 4, lds_bt = 64;
   int64_t ext_col = 0;  // dependency columns of the block-local solve are < ext_col
   int64_t nloc = 0;     // rows in the block-local solve (the rows of W follow in their own pass)
@@ -631,6 +636,20 @@ static int build_global(ilu_precond *P, Mem &tmp, Schedule &S, void *stmp, size_
   return 0;
 }
 
+// FP32 / FP16 copy of a factor (and FP32 diagonal) for the level-scheduled
+// solve.
+static int build_lowp(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, hipStream_t s) {
+  if (T.n == 0) return 0;
+  Mem &mem = P->mem;
+  const int prec = P->opt.factor_prec;
+  double *vbuf;
+  RC(mem.alloc(&vbuf, (T.nnz * (prec == ILU_PREC_F32 ? 4 : 2) + 7) / 8 + 1));
+  S.v_lp = vbuf;
+  if (diag) RC(mem.alloc(&S.diag_lp, T.n));
+  if (prec == ILU_PREC_F16) RC(mem.alloc(&S.scale_lp, T.n));
+  return launch_lowp_factor(T.rp, T.v, T.n, prec, S.v_lp, S.scale_lp, diag, S.diag_lp, s);
+}
+
 // Block-local storage of one factor: rows sorted by (subdomain, level), the
 // fixed-stride entries and the records.  omap (row -> output index) places
 // each solution; NULL puts it at its own position.
@@ -692,11 +711,15 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   S.lds_e = E;
   S.lds_bt = (int32_t)std::min<int64_t>(bt, 512);
   const int64_t ne = (nloc + 1) * G * E;
+  const int prec = P->opt.factor_prec;
+  const int64_t vbytes = prec == ILU_PREC_F64 ? 8 : prec == ILU_PREC_F32 ? 4 : 2;
   RC(mem.alloc(&S.lds_c, ne));
-  RC(mem.alloc(&S.lds_v, ne));
+  double *vstore;
+  RC(mem.alloc(&vstore, (ne * vbytes + 7) / 8));
+  S.lds_v = vstore;
   RC(mem.alloc(&S.lds_rec, 4 * (nloc + 1)));
   S.out_map = omap ? omap : S.pos;
-  RC(launch_lds_fill(S.blk_rows, T.rp, T.ci, T.v, diag, nloc, ext_col, S.pos, S.blk_lev_ptr, (int64_t)nkeys, G, E,
+  RC(launch_lds_fill(S.blk_rows, T.rp, T.ci, T.v, diag, nloc, ext_col, S.pos, S.blk_lev_ptr, (int64_t)nkeys, G, E, prec,
                      S.out_map, S.lds_c, S.lds_v, S.lds_rec, s));
   HIPCK(hipStreamSynchronize(s));
   return 0;
@@ -749,10 +772,15 @@ static int build_block_flow(ilu_precond *P, Mem &tmp, void *stmp, size_t stmpb, 
 // value), the row pointers and the level-ordered row list once, the right-hand
 // side read and the solution written once (plus the gather map, the diagonal
 // and the scatter when present).
-static double trsv_bytes(const Schedule &S, const Csr &T, bool diag, bool bmap, bool scat) {
+// Algorithmic bytes of one solve: each entry (column and value in the storage
+// precision), row pointers and row list, right-hand side and solution (FP64),
+// and the diagonal (and FP16 row scale) in the storage precision.
+static double trsv_bytes(const Schedule &S, const Csr &T, bool diag, bool bmap, bool scat, int prec = 0) {
   const double n = (double)S.nrows;
-  double b = 12.0 * (double)T.nnz + 8.0 * (n + 1) + 4.0 * n + 8.0 * n + 8.0 * n;
-  if (diag) b += 8.0 * n;
+  const double vb = prec == ILU_PREC_F64 ? 8.0 : prec == ILU_PREC_F32 ? 4.0 : 2.0;
+  double b = (4.0 + vb) * (double)T.nnz + 8.0 * (n + 1) + 4.0 * n + 8.0 * n + 8.0 * n;
+  if (prec == ILU_PREC_F16) b += 4.0 * n;
+  if (diag) b += (prec == ILU_PREC_F64 ? 8.0 : 4.0) * n;
   if (bmap) b += 4.0 * n;
   if (scat) b += 12.0 * n;
   return b;
@@ -800,6 +828,10 @@ static TrsvLaunch make_launch(ilu_precond *P, Schedule &S, const Csr &T, const d
     t.split_col = S.ext_col;
     t.nrows = S.nloc;
   }
+  t.prec = P->opt.factor_prec;
+  t.v_lp = S.v_lp;
+  t.diag_lp = S.diag_lp;
+  t.scale_lp = S.scale_lp;
   return t;
 }
 
@@ -809,7 +841,7 @@ static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, i
                 const std::function<int()> &after = nullptr) {
   if (S.nrows == 0) return 0;
   TrsvLaunch t = make_launch(P, S, T, diag, split, b, bmap, x, scat, smap, role);
-  const double bytes = trsv_bytes(S, T, diag != nullptr, bmap != nullptr, scat != nullptr);
+  const double bytes = trsv_bytes(S, T, diag != nullptr, bmap != nullptr, scat != nullptr, P->opt.factor_prec);
   if (S.use_block) {
     if (bmap || scat) return fail(ILU_ERR_INVALID_ARG, "internal: block-local solves take no gather or scatter map");
     return timed(ILU_K_TRSV_LB + role, bytes, s, [&] {
@@ -834,7 +866,9 @@ static int trsv_schur(ilu_precond *P, const double *b, double *x, hipStream_t s)
     TrsvLaunch lo = make_launch(P, P->sLS, P->LS, nullptr, 0, b, nullptr, x, nullptr, nullptr, 2);
     TrsvLaunch up = make_launch(P, P->sUS, P->US, P->DS, INT64_MAX, x, nullptr, x, nullptr, nullptr, 3);
     if (trsv_lds_pair_ok(lo, up)) {
-      const double bytes = trsv_bytes(P->sLS, P->LS, false, false, false) + trsv_bytes(P->sUS, P->US, true, false, false);
+      const int fp = P->opt.factor_prec;
+      const double bytes =
+          trsv_bytes(P->sLS, P->LS, false, false, false, fp) + trsv_bytes(P->sUS, P->US, true, false, false, fp);
       return timed(ILU_K_TRSV_LS, bytes, s, [&] { return launch_trsv_lds_pair(lo, up, s); });
     }
   }
@@ -863,6 +897,7 @@ void ilu_default_options(ilu_options_t *o) {
   o->pivot_mode = ILU_PIVOT_ERROR;
   o->pivot_tol = 0.0;
   o->trsv_mode = ILU_TRSV_AUTO;
+  o->factor_prec = ILU_PREC_F64;
 }
 
 const char *ilu_last_error(void) { return g_err.c_str(); }
@@ -1042,6 +1077,12 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
     RC(build_global(P, tmp, P->sU1, stmp, stmpb, s));
     RC(build_global(P, tmp, P->sLS, stmp, stmpb, s));
     RC(build_global(P, tmp, P->sUS, stmp, stmpb, s));
+    if (P->opt.factor_prec != ILU_PREC_F64) {
+      RC(build_lowp(P, P->sL1, P->L1, nullptr, s));
+      RC(build_lowp(P, P->sU1, P->U1, P->DB, s));
+      RC(build_lowp(P, P->sLS, P->LS, nullptr, s));
+      RC(build_lowp(P, P->sUS, P->US, P->DS, s));
+    }
   } else {
     RC(build_block(P, tmp, P->L1, P->sL1, bs_int, bs_ifc, nB, nullptr, INT64_MAX, nullptr, s, "levels L"));
     RC(build_block(P, tmp, P->U1, P->sU1, bs_int, nullptr, 0, P->DB, nB, nullptr, s, "levels U"));
@@ -1090,6 +1131,8 @@ int ilu_setup(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts, const i
   if (opt.inner_iters < 0 || opt.inner_iters > 1000) return fail(ILU_ERR_INVALID_ARG, "inner_iters out of range");
   if (!(opt.droptol >= 0.0) || !(opt.inner_rtol >= 0.0) || !(opt.pivot_tol >= 0.0))
     return fail(ILU_ERR_INVALID_ARG, "negative tolerance");
+  if (opt.factor_prec < ILU_PREC_F64 || opt.factor_prec > ILU_PREC_F16)
+    return fail(ILU_ERR_INVALID_ARG, "factor_prec must be ILU_PREC_F64, ILU_PREC_F32 or ILU_PREC_F16");
   if (opt.trsv_mode < ILU_TRSV_AUTO || opt.trsv_mode > ILU_TRSV_BLOCK)
     return fail(ILU_ERR_INVALID_ARG, "unknown trsv_mode %d", opt.trsv_mode);
   hipStream_t s = (hipStream_t)stream;

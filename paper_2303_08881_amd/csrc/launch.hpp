@@ -138,14 +138,27 @@ struct TrsvLaunch {
   const int32_t *blk_lev_ptr;  // [nblk * nlev_blk + 1]
   // block-local storage (launch_trsv_lds): fixed-stride dependency entries
   const int32_t *lds_c;    // (nrows + 1) * G * E window slots, in planes of 4 per lane (2 for E = 2)
-  const double *lds_v;     // (nrows + 1) * G * E values, in planes of 2 per lane
+  const void *lds_v;       // (nrows + 1) * G * E values in the storage precision, in planes of one
+                           // word (16 bytes or E values) per lane
   const int32_t *lds_rec;  // int4 per position (+ dummy): {row or ~row, output index, diagonal}
   const int32_t *out_map;  // row -> index of its solution in x (the output index of its position)
   int32_t lds_g;           // lanes per row: 1 (E = 2, 4), or 1, 2, 4, 8 (E = 8)
   int32_t lds_e;           // entries per lane: 2, 4 or 8
   int32_t lds_bt;          // threads per workgroup (multiple of 64, <= 512)
+  // storage precision of the factor values (0 FP64, 1 FP32, 2 FP16 scaled per
+  // row), both modes; the level-scheduled solve reads v_lp, diag_lp and
+  // scale_lp instead of v and diag when it is not 0
+  int32_t prec;
+  const void *v_lp;
+  const float *diag_lp;
+  const float *scale_lp;
 };
 int launch_trsv(const TrsvLaunch &t, hipStream_t s);
+// FP32 / FP16 copies of a factor's values (and FP32 diagonal) for the
+// level-scheduled solve; prec 1 FP32, 2 FP16 divided by the row's largest
+// magnitude (scale[n] receives it)
+int launch_lowp_factor(const int64_t *rp, const double *v, int64_t n, int prec, void *out, float *scale,
+                       const double *diag, float *diag_out, hipStream_t s);
 int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s);
 // the block-local L_S and U_S solves of each subdomain in one launch, when
 // both have the same lane shape (trsv_lds_pair_ok)
@@ -178,7 +191,7 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
                        hipStream_t s);
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
                     int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G, int E,
-                    const int32_t *omap, int32_t *oc, double *ov, int32_t *rec, hipStream_t s);
+                    int prec, const int32_t *omap, int32_t *oc, void *ov, int32_t *rec, hipStream_t s);
 // block id of each row from ascending block starts (s1 below split, s2 from split on; s2 may be NULL)
 int launch_row_blocks(int64_t nrows, int32_t nblk, const int64_t *s1, const int64_t *s2, int64_t split, int32_t *blk,
                       hipStream_t s);

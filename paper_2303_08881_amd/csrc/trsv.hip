@@ -6,7 +6,10 @@
 // Each row is one lane and sums its entries sequentially in column order with
 // fma (the columns >= split -- the Z block of the two-level solve, Section 3.2
 // -- first), then divides once: the same rounding order as the sequential
-// definition.
+// definition.  With factors stored in FP32 the same steps run in FP32; with
+// FP16 storage (each entry divided by its row's largest magnitude) the scaled
+// entries are summed in FP32 and the sum, times the row scale, is subtracted
+// from the right-hand side.  Vectors stay FP64.
 //
 // Scheduling: rows are listed level by level; a wave takes, by atomic ticket,
 // a chunk of <= 64 rows of one level.  Before computing, the chunk waits until
@@ -16,11 +19,20 @@
 // Counters are cumulative across calls (epoch = call number), so nothing is
 // reset between solves.  Waits are bounded.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace silu {
+
+// fused multiply-add in the solve's precision (FP64, or FP32 for factors
+// stored in FP32 / FP16), and an FP16 value given by its bits
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ float half_bits(uint32_t h) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)(h & 0xffffu));
+}
 // (k_trsv: cross-workgroup level-scheduled variant; k_trsv_lds: one
 // workgroup per subdomain, software-pipelined, further below)
 
@@ -45,12 +57,28 @@ struct TrsvArgs {
   double *scatter_out;
   const int32_t *scatter_map;
   Status *st;
+  const void *v_lp;       // factor values in FP32 or FP16 (P > 0)
+  const float *diag_lp;   // FP32 diagonal (P > 0)
+  const float *scale_lp;  // FP16: per-row scale of the stored values
 };
+
+// value p of the factor in the solve's arithmetic: FP64, FP32, or the FP16
+// value (entry / row scale) as FP32
+template <int P>
+__device__ __forceinline__ auto trsv_val(const TrsvArgs &a, int64_t p) {
+  if constexpr (P == 0)
+    return a.v[p];
+  else if constexpr (P == 1)
+    return static_cast<const float *>(a.v_lp)[p];
+  else
+    return (float)__builtin_bit_cast(_Float16, static_cast<const uint16_t *>(a.v_lp)[p]);
+}
 
 // ROLE only names the instantiation (0: L_B and W rows, 1: U_B with Z,
 // 2: L_S, 3: U_S) so profilers report the four solves separately.
-template <int ROLE>
+template <int ROLE, int P>
 __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
+  using A = typename std::conditional<P == 0, double, float>::type;
   const int lane = lane_id();
   for (;;) {
     const unsigned long long t = wave_ticket(a.ticket) - a.ticket_base;
@@ -77,22 +105,32 @@ __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
       fence_acquire();
     }
     if (valid) {
-      double s = rhs;
-      if (a.diag) {
+      // FP16 storage: the scaled entries are summed first, then the sum
+      // times the row scale is subtracted from the right-hand side
+      A s = P == 2 ? A(0) : (A)rhs;
+      const A sg = P == 2 ? A(1) : A(-1);
+      const bool diag = P == 0 ? a.diag != nullptr : a.diag_lp != nullptr;
+      if (diag) {
         for (int64_t p = rb; p < re; p++) {
           const int32_t c = a.ci[p];
-          if (c >= a.split_col) s = fma(-a.v[p], a.x[c], s);
+          if (c >= a.split_col) s = fma_t(sg * trsv_val<P>(a, p), (A)a.x[c], s);
         }
         for (int64_t p = rb; p < re; p++) {
           const int32_t c = a.ci[p];
-          if (c < a.split_col) s = fma(-a.v[p], a.x[c], s);
+          if (c < a.split_col) s = fma_t(sg * trsv_val<P>(a, p), (A)a.x[c], s);
         }
-        s = s / a.diag[r];
       } else {
-        for (int64_t p = rb; p < re; p++) s = fma(-a.v[p], a.x[a.ci[p]], s);
+        for (int64_t p = rb; p < re; p++) s = fma_t(sg * trsv_val<P>(a, p), (A)a.x[a.ci[p]], s);
       }
-      a.x[r] = s;
-      if (a.scatter_out) a.scatter_out[a.scatter_map[r]] = s;
+      if constexpr (P == 2) s = fma_t(-a.scale_lp[r], s, (A)rhs);
+      if (diag) {
+        if constexpr (P == 0)
+          s = s / a.diag[r];
+        else
+          s = s / a.diag_lp[r];
+      }
+      a.x[r] = (double)s;
+      if (a.scatter_out) a.scatter_out[a.scatter_map[r]] = (double)s;
     }
     __syncthreads();
     if (lane == 0)
@@ -158,14 +196,14 @@ constexpr int LOOK_MAX = 10;
 // loads per level: E/4 (columns; one for E = 2) + E/2 (values; one for E = 2)
 // + record + right-hand side, and one store: LOOK times that stays within
 // the 63 operations the counter tracks
-template <int E>
+template <int E, int P = 0>
 constexpr int look_of() {
-  return E == 8 ? 6 : E == 4 ? 8 : 10;
+  return P == 0 ? (E == 8 ? 6 : E == 4 ? 8 : 10) : (P == 1 && E == 8) ? 8 : 10;
 }
 
 struct LdsTrsvArgs {
   const int4 *ent_c;       // [E / 4][nent] window slots (int2 [nent] for E = 2)
-  const double2 *ent_v;    // [E / 2][nent]
+  const void *ent_v;       // [E / vpw][nent] words of vpw values (see VWord)
   uint32_t nent;           // lanes of entries: (npos + 1) * G
   const int4 *rec;         // [npos + 1]
   const int32_t *lev_ptr;  // [nblk * nlev + 1]
@@ -197,15 +235,87 @@ struct Cols<2> {
   __device__ __forceinline__ int32_t get(int k) const { return k == 0 ? v.x : v.y; }
 };
 
+// Storage precision of the factor values (ilu_options_t factor_prec):
+// P = 0 FP64; P = 1 FP32; P = 2 FP16 scaled per row (each stored value is the
+// entry divided by the largest magnitude of its row, which the record holds).
+// P = 1 and 2 solve in FP32: window, products and sums; right-hand side and
+// solution vectors stay FP64.
+template <int P>
+struct Acc {
+  using T = float;
+};
+template <>
+struct Acc<0> {
+  using T = double;
+};
+
+
+// A lane's E values in NW words of vpw values each (one load per word):
+// FP64 double2; FP32 float2 (E = 2) or float4; FP16 one word of E halves.
+template <int P, int E>
+struct VWord;
 template <int E>
+struct VWord<0, E> {
+  using W = double2;
+  static constexpr int NW = E / 2;
+  __device__ static __forceinline__ double get(const W *w, int k) { return (k & 1) ? w[k >> 1].y : w[k >> 1].x; }
+};
+template <>
+struct VWord<1, 2> {
+  using W = float2;
+  static constexpr int NW = 1;
+  __device__ static __forceinline__ float get(const W *w, int k) { return k ? w[0].y : w[0].x; }
+};
+template <int E>
+struct VWord<1, E> {
+  using W = float4;
+  static constexpr int NW = E / 4;
+  __device__ static __forceinline__ float get(const W *w, int k) {
+    const float4 &q = w[k >> 2];
+    return (k & 3) == 0 ? q.x : (k & 3) == 1 ? q.y : (k & 3) == 2 ? q.z : q.w;
+  }
+};
+template <>
+struct VWord<2, 2> {
+  using W = uint32_t;
+  static constexpr int NW = 1;
+  __device__ static __forceinline__ float get(const W *w, int k) { return half_bits(w[0] >> (16 * k)); }
+};
+template <>
+struct VWord<2, 4> {
+  using W = uint2;
+  static constexpr int NW = 1;
+  __device__ static __forceinline__ float get(const W *w, int k) {
+    return half_bits((k >> 1 ? w[0].y : w[0].x) >> (16 * (k & 1)));
+  }
+};
+template <>
+struct VWord<2, 8> {
+  using W = uint4;
+  static constexpr int NW = 1;
+  __device__ static __forceinline__ float get(const W *w, int k) {
+    const uint32_t u = (k >> 1) == 0 ? w[0].x : (k >> 1) == 1 ? w[0].y : (k >> 1) == 2 ? w[0].z : w[0].w;
+    return half_bits(u >> (16 * (k & 1)));
+  }
+};
+
+template <int E, int P>
 struct PSet {
   Cols<E> c;
-  double2 w[E / 2];
+  typename VWord<P, E>::W w[VWord<P, E>::NW];
   int4 rec;
   double rhs;
 };
 
-__device__ __forceinline__ double rec_diag(const int4 &r) { return __hiloint2double(r.w, r.z); }
+// record: {row or ~row, output index, 1 / diagonal (FP64 in z|w; FP32 in z),
+// row scale (FP32 in w, FP16 storage)}
+template <int P>
+__device__ __forceinline__ double rec_diag(const int4 &r) {
+  if constexpr (P == 0)
+    return __hiloint2double(r.w, r.z);
+  else
+    return (double)__int_as_float(r.z);
+}
 
 // Element idx of an array whose byte size is below 2^32 (checked at setup):
 // a 32-bit byte offset from a base held in scalar registers, so a load or
@@ -228,11 +338,22 @@ __device__ __forceinline__ double dpp_f64(double v) {
   const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
 template <int G>
 __device__ __forceinline__ double group_sum(double s) {
   if (G >= 2) s = s + dpp_f64<0xB1>(s);   // quad_perm [1,0,3,2]
   if (G >= 4) s = s + dpp_f64<0x4E>(s);   // quad_perm [2,3,0,1]
   if (G >= 8) s = s + dpp_f64<0x141>(s);  // row_half_mirror
+  return s;
+}
+template <int G>
+__device__ __forceinline__ float group_sum(float s) {
+  if (G >= 2) s = s + dpp_f32<0xB1>(s);
+  if (G >= 4) s = s + dpp_f32<0x4E>(s);
+  if (G >= 8) s = s + dpp_f32<0x141>(s);
   return s;
 }
 
@@ -255,9 +376,9 @@ __device__ __forceinline__ double slow_row(const LdsTrsvArgs &a, int32_t r, int3
 // Load the pipeline set of the row handled by this lane in a level whose
 // positions are [lo, hi) (idle lanes read the dummy position and the first
 // right-hand side).
-template <int G, int E>
+template <int G, int E, int P>
 __device__ __forceinline__ void refill(const LdsTrsvArgs &a, int32_t lo, int32_t hi, int32_t j, int32_t g,
-                                       PSet<E> &S) {
+                                       PSet<E, P> &S) {
   const uint32_t q = (uint32_t)(lo + j);
   const bool in = q < (uint32_t)hi;
   const uint32_t qc = in ? q : (uint32_t)a.npos;
@@ -268,77 +389,88 @@ __device__ __forceinline__ void refill(const LdsTrsvArgs &a, int32_t lo, int32_t
 #pragma unroll
     for (int i = 0; i < E / 4; i++) S.c.v[i] = at32(a.ent_c, i * a.nent + e);
   }
+  using VW = VWord<P, E>;
 #pragma unroll
-  for (int i = 0; i < E / 2; i++) S.w[i] = at32(a.ent_v, i * a.nent + e);
+  for (int i = 0; i < VW::NW; i++) S.w[i] = at32(reinterpret_cast<const typename VW::W *>(a.ent_v), i * a.nent + e);
   S.rec = at32(a.rec, qc);
   S.rhs = at32(a.b, in ? q : 0u);
 }
 
-template <int G, int E, bool DIAG>
-__device__ __forceinline__ void pstep(const LdsTrsvArgs &a, double *win, const int32_t *lp, int32_t l, int32_t j,
-                                      int32_t g, PSet<E> &S) {
-  constexpr int LOOK = look_of<E>();
+template <int G, int E, bool DIAG, int P>
+__device__ __forceinline__ void pstep(const LdsTrsvArgs &a, typename Acc<P>::T *win, const int32_t *lp, int32_t l,
+                                      int32_t j, int32_t g, PSet<E, P> &S) {
+  using A = typename Acc<P>::T;
+  using VW = VWord<P, E>;
+  constexpr int LOOK = look_of<E, P>();
   // every LDS read of the step first, so that a single wait covers them: the
   // bounds of levels l and l + LOOK and the window values
   const int32_t q0 = lp[l], q1 = lp[l + 1];
   const int32_t f0 = lp[l + LOOK], f1 = lp[l + LOOK + 1];
-  double xv[E];
+  A xv[E];
 #pragma unroll
   for (int k = 0; k < E; k++) xv[k] = win[S.c.get(k)];
   const int32_t q = q0 + j;
   const bool mine = q < q1;
-  double s = g == 0 ? S.rhs : 0.0;
+  A s;
+  if constexpr (P == 2) {
+    // scaled entries: the row sum times the row's scale, subtracted once
+    s = A(0);
 #pragma unroll
-  for (int i = 0; i < E / 2; i++) {
-    s = fma(-S.w[i].x, xv[2 * i], s);
-    s = fma(-S.w[i].y, xv[2 * i + 1], s);
+    for (int k = 0; k < E; k++) s = fma_t(VW::get(S.w, k), xv[k], s);
+    s = group_sum<G>(s);
+    s = fma_t(-__int_as_float(S.rec.w), s, (A)S.rhs);
+  } else {
+    s = g == 0 ? (A)S.rhs : A(0);
+#pragma unroll
+    for (int k = 0; k < E; k++) s = fma_t(-(A)VW::get(S.w, k), xv[k], s);
+    s = group_sum<G>(s);
   }
-  s = group_sum<G>(s);
   const bool slow = S.rec.x < 0;
   const int32_t r = slow ? ~S.rec.x : S.rec.x;
-  if (DIAG) s = s * rec_diag(S.rec);  // the record holds 1 / d
-  if (mine && slow) s = slow_row<DIAG>(a, r, q, rec_diag(S.rec));
+  if (DIAG) s = s * (A)rec_diag<P>(S.rec);  // the record holds 1 / d
+  if (mine && slow) s = (A)slow_row<DIAG>(a, r, q, rec_diag<P>(S.rec));
   if (mine && g == 0) {
     win[q & (XWIN - 1)] = s;
-    at32(a.out, (uint32_t)S.rec.y) = s;
+    at32(a.out, (uint32_t)S.rec.y) = (double)s;
   }
   // rows beyond bt/G in this level: one thread each, slow path
   const int32_t cap = a.bt / G;
   for (int32_t qq = q0 + cap + (int32_t)threadIdx.x; qq < q1; qq += a.bt) {
     const int4 rc = a.rec[qq];
     const int32_t rr = rc.x < 0 ? ~rc.x : rc.x;
-    const double s2 = slow_row<DIAG>(a, rr, qq, rec_diag(rc));
+    const A s2 = (A)slow_row<DIAG>(a, rr, qq, rec_diag<P>(rc));
     win[qq & (XWIN - 1)] = s2;
-    a.out[(uint32_t)rc.y] = s2;
+    a.out[(uint32_t)rc.y] = (double)s2;
     __builtin_amdgcn_s_waitcnt(0);
   }
   __syncthreads();  // also for an empty level: the step stays branch-free
-  refill<G, E>(a, f0, f1, j, g, S);
+  refill<G, E, P>(a, f0, f1, j, g, S);
 }
 
-// One subdomain's solve by the calling workgroup (win: XWIN + 1 doubles,
-// lp: BT_LDS_LEVELS + 2 LOOK_MAX + 2 ints of LDS); returns after the last
-// level's barrier.
-template <int G, int E, bool DIAG>
-__device__ __forceinline__ void block_solve(const LdsTrsvArgs &a, double *win, int32_t *lp) {
-  constexpr int LOOK = look_of<E>();
+// One subdomain's solve by the calling workgroup (win: XWIN + 1 values of the
+// solve's precision, lp: BT_LDS_LEVELS + 2 LOOK_MAX + 2 ints of LDS); returns
+// after the last level's barrier.
+template <int G, int E, bool DIAG, int P>
+__device__ __forceinline__ void block_solve(const LdsTrsvArgs &a, typename Acc<P>::T *win, int32_t *lp) {
+  using A = typename Acc<P>::T;
+  constexpr int LOOK = look_of<E, P>();
   const int64_t base = (int64_t)blockIdx.x * a.nlev;
   const int32_t tid = (int32_t)threadIdx.x;
   const int32_t nlev = a.nlev;
   for (int32_t l = tid; l <= nlev; l += a.bt) lp[l] = a.lev_ptr[base + l];
-  for (int32_t k = tid; k <= XWIN; k += a.bt) win[k] = 0.0;
+  for (int32_t k = tid; k <= XWIN; k += a.bt) win[k] = A(0);
   __syncthreads();
   if (tid < 2 * LOOK + 1) lp[nlev + 1 + tid] = lp[nlev];  // empty levels past the end
   __syncthreads();
   const int32_t j = tid / G, g = tid % G;
-  PSet<E> S[LOOK];
+  PSet<E, P> S[LOOK];
   // prologue in the loop's own load order (pinned by scheduling barriers):
   // the compiler merges the state at loop entry with the state at the back
   // edge, and any load that looked more recent at entry would be waited for
   // on every iteration
 #pragma unroll
   for (int k = 0; k < LOOK; k++) {
-    refill<G, E>(a, lp[k], lp[k + 1], j, g, S[k]);
+    refill<G, E, P>(a, lp[k], lp[k + 1], j, g, S[k]);
     __builtin_amdgcn_sched_barrier(0);
   }
   // LOOK levels per iteration, a whole number of iterations (the extra levels
@@ -346,45 +478,72 @@ __device__ __forceinline__ void block_solve(const LdsTrsvArgs &a, double *win, i
   // order and the register sets keep their names
   for (int32_t l = 0; l < nlev; l += LOOK) {
 #pragma unroll
-    for (int k = 0; k < LOOK; k++) pstep<G, E, DIAG>(a, win, lp, l + k, j, g, S[k]);
+    for (int k = 0; k < LOOK; k++) pstep<G, E, DIAG, P>(a, win, lp, l + k, j, g, S[k]);
   }
 }
 
-template <int G, int E, bool DIAG>
+template <int G, int E, bool DIAG, int P>
 __global__ void __launch_bounds__(BT_MAX) k_trsv_lds(LdsTrsvArgs a) {
-  __shared__ double win[XWIN + 1];  // slot XWIN stays 0.0: the target of padding entries
+  __shared__ typename Acc<P>::T win[XWIN + 1];  // slot XWIN stays 0: the target of padding entries
   __shared__ int32_t lp[BT_LDS_LEVELS + 2 * LOOK_MAX + 2];
-  block_solve<G, E, DIAG>(a, win, lp);
+  block_solve<G, E, DIAG, P>(a, win, lp);
 }
 
 // L_S then U_S of each subdomain in one launch (both with the same lane
 // shape): U_S reads the solution that this workgroup's L_S wrote before the
 // barrier between the two.
-template <int G, int E>
+template <int G, int E, int P>
 __global__ void __launch_bounds__(BT_MAX) k_trsv_lds_pair(LdsTrsvArgs lo, LdsTrsvArgs up) {
-  __shared__ double win[XWIN + 1];
+  __shared__ typename Acc<P>::T win[XWIN + 1];
   __shared__ int32_t lp[BT_LDS_LEVELS + 2 * LOOK_MAX + 2];
-  block_solve<G, E, false>(lo, win, lp);
+  block_solve<G, E, false, P>(lo, win, lp);
   __syncthreads();
-  block_solve<G, E, true>(up, win, lp);
+  block_solve<G, E, true, P>(up, win, lp);
 }
 
-template <bool DIAG>
-static void launch_ge(int G, int E, unsigned grid, unsigned bt, const LdsTrsvArgs &a, hipStream_t s) {
+template <bool DIAG, int P>
+static void launch_ge_p(int G, int E, unsigned grid, unsigned bt, const LdsTrsvArgs &a, hipStream_t s) {
   if (E == 2) {
-    k_trsv_lds<1, 2, DIAG><<<grid, bt, 0, s>>>(a);
+    k_trsv_lds<1, 2, DIAG, P><<<grid, bt, 0, s>>>(a);
     return;
   }
   if (E == 4) {
-    k_trsv_lds<1, 4, DIAG><<<grid, bt, 0, s>>>(a);
+    k_trsv_lds<1, 4, DIAG, P><<<grid, bt, 0, s>>>(a);
     return;
   }
   switch (G) {
-    case 1: k_trsv_lds<1, 8, DIAG><<<grid, bt, 0, s>>>(a); break;
-    case 2: k_trsv_lds<2, 8, DIAG><<<grid, bt, 0, s>>>(a); break;
-    case 4: k_trsv_lds<4, 8, DIAG><<<grid, bt, 0, s>>>(a); break;
-    default: k_trsv_lds<8, 8, DIAG><<<grid, bt, 0, s>>>(a); break;
+    case 1: k_trsv_lds<1, 8, DIAG, P><<<grid, bt, 0, s>>>(a); break;
+    case 2: k_trsv_lds<2, 8, DIAG, P><<<grid, bt, 0, s>>>(a); break;
+    case 4: k_trsv_lds<4, 8, DIAG, P><<<grid, bt, 0, s>>>(a); break;
+    default: k_trsv_lds<8, 8, DIAG, P><<<grid, bt, 0, s>>>(a); break;
   }
+}
+
+template <bool DIAG>
+static void launch_ge(int G, int E, int prec, unsigned grid, unsigned bt, const LdsTrsvArgs &a, hipStream_t s) {
+  if (prec == 1)
+    launch_ge_p<DIAG, 1>(G, E, grid, bt, a, s);
+  else if (prec == 2)
+    launch_ge_p<DIAG, 2>(G, E, grid, bt, a, s);
+  else
+    launch_ge_p<DIAG, 0>(G, E, grid, bt, a, s);
+}
+
+template <int P>
+static void launch_pair_p(int G, int E, unsigned g, unsigned bt, const LdsTrsvArgs &a, const LdsTrsvArgs &b,
+                          hipStream_t s) {
+  if (E == 2)
+    k_trsv_lds_pair<1, 2, P><<<g, bt, 0, s>>>(a, b);
+  else if (E == 4)
+    k_trsv_lds_pair<1, 4, P><<<g, bt, 0, s>>>(a, b);
+  else if (G == 1)
+    k_trsv_lds_pair<1, 8, P><<<g, bt, 0, s>>>(a, b);
+  else if (G == 2)
+    k_trsv_lds_pair<2, 8, P><<<g, bt, 0, s>>>(a, b);
+  else if (G == 4)
+    k_trsv_lds_pair<4, 8, P><<<g, bt, 0, s>>>(a, b);
+  else
+    k_trsv_lds_pair<8, 8, P><<<g, bt, 0, s>>>(a, b);
 }
 
 static bool lds_args(const TrsvLaunch &t, LdsTrsvArgs &a) {
@@ -394,7 +553,7 @@ static bool lds_args(const TrsvLaunch &t, LdsTrsvArgs &a) {
       !t.b || !t.x || !t.out_map)
     return false;
   a.ent_c = reinterpret_cast<const int4 *>(t.lds_c);
-  a.ent_v = reinterpret_cast<const double2 *>(t.lds_v);
+  a.ent_v = t.lds_v;
   a.nent = (uint32_t)((t.nrows + 1) * t.lds_g);
   a.rec = reinterpret_cast<const int4 *>(t.lds_rec);
   a.lev_ptr = t.blk_lev_ptr;
@@ -417,15 +576,15 @@ int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s) {
   if (!lds_args(t, a)) return ILU_ERR_INVALID_ARG;
   const unsigned g = (unsigned)t.nblk, bt = (unsigned)t.lds_bt;
   if (t.diag)
-    launch_ge<true>(t.lds_g, t.lds_e, g, bt, a, s);
+    launch_ge<true>(t.lds_g, t.lds_e, t.prec, g, bt, a, s);
   else
-    launch_ge<false>(t.lds_g, t.lds_e, g, bt, a, s);
+    launch_ge<false>(t.lds_g, t.lds_e, t.prec, g, bt, a, s);
   return check_launch("trsv_lds");
 }
 
 bool trsv_lds_pair_ok(const TrsvLaunch &lo, const TrsvLaunch &up) {
   return lo.nblk == up.nblk && lo.nblk > 0 && lo.nrows > 0 && up.nrows > 0 && lo.lds_g == up.lds_g &&
-         lo.lds_e == up.lds_e && !lo.diag && up.diag;
+         lo.lds_e == up.lds_e && lo.prec == up.prec && !lo.diag && up.diag;
 }
 
 int launch_trsv_lds_pair(const TrsvLaunch &lo, const TrsvLaunch &up, hipStream_t s) {
@@ -434,18 +593,12 @@ int launch_trsv_lds_pair(const TrsvLaunch &lo, const TrsvLaunch &up, hipStream_t
   // one block size for both solves: each covers its own widest level
   a.bt = b.bt = std::max(a.bt, b.bt);
   const unsigned g = (unsigned)lo.nblk, bt = (unsigned)a.bt;
-  if (lo.lds_e == 2)
-    k_trsv_lds_pair<1, 2><<<g, bt, 0, s>>>(a, b);
-  else if (lo.lds_e == 4)
-    k_trsv_lds_pair<1, 4><<<g, bt, 0, s>>>(a, b);
-  else if (lo.lds_g == 1)
-    k_trsv_lds_pair<1, 8><<<g, bt, 0, s>>>(a, b);
-  else if (lo.lds_g == 2)
-    k_trsv_lds_pair<2, 8><<<g, bt, 0, s>>>(a, b);
-  else if (lo.lds_g == 4)
-    k_trsv_lds_pair<4, 8><<<g, bt, 0, s>>>(a, b);
+  if (lo.prec == 1)
+    launch_pair_p<1>(lo.lds_g, lo.lds_e, g, bt, a, b, s);
+  else if (lo.prec == 2)
+    launch_pair_p<2>(lo.lds_g, lo.lds_e, g, bt, a, b, s);
   else
-    k_trsv_lds_pair<8, 8><<<g, bt, 0, s>>>(a, b);
+    launch_pair_p<0>(lo.lds_g, lo.lds_e, g, bt, a, b, s);
   return check_launch("trsv_lds_pair");
 }
 
@@ -478,32 +631,50 @@ __global__ void k_max_width(const int32_t *lev_ptr, int64_t nseg, int32_t *out) 
 // output index of position q is omap[rows[q]].
 __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v,
                            const double *diag, int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr,
-                           int64_t nseg, int G, int E, const int32_t *omap, int32_t *oc, double *ov, int4 *rec) {
+                           int64_t nseg, int G, int E, int prec, const int32_t *omap, int32_t *oc, void *ov,
+                           int4 *rec) {
   int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q > n) return;
   const int64_t cap = (int64_t)G * E, nent = (n + 1) * G;
   // entry k of position q belongs to lane e = q G + k / E as its entry kk =
-  // k % E; each load of the solve reads one plane (4 window slots or 2 values
-  // per lane) for consecutive lanes, so the planes are stored one after the
-  // other
+  // k % E; each load of the solve reads one plane (4 window slots, or one
+  // word of vpw values, per lane) for consecutive lanes, so the planes are
+  // stored one after the other
+  const int vsize = prec == 0 ? 8 : prec == 1 ? 4 : 2;
+  const int64_t vpw = E < 16 / vsize ? E : 16 / vsize;
   auto at_c = [&](int64_t k) {
     const int64_t e = q * G + k / E, kk = k % E;
     return E == 2 ? e * 2 + kk : ((kk >> 2) * nent + e) * 4 + (kk & 3);
   };
-  auto at_v = [&](int64_t k) {
+  auto put_v = [&](int64_t k, double x) {
     const int64_t e = q * G + k / E, kk = k % E;
-    return ((kk >> 1) * nent + e) * 2 + (kk & 1);
+    const int64_t at = ((kk / vpw) * nent + e) * vpw + kk % vpw;
+    if (prec == 0)
+      static_cast<double *>(ov)[at] = x;
+    else if (prec == 1)
+      static_cast<float *>(ov)[at] = (float)x;
+    else
+      static_cast<uint16_t *>(ov)[at] = __builtin_bit_cast(uint16_t, (_Float16)(float)x);
   };
   int64_t k = 0;
   if (q == n) {
     for (; k < cap; k++) {
       oc[at_c(k)] = XWIN;
-      ov[at_v(k)] = 0.0;
+      put_v(k, 0.0);
     }
-    rec[q] = make_int4(0, 0, __double2loint(1.0), __double2hiint(1.0));
+    rec[q] = prec == 0 ? make_int4(0, 0, __double2loint(1.0), __double2hiint(1.0))
+                       : make_int4(0, 0, __float_as_int(1.0f), __float_as_int(1.0f));
     return;
   }
   const int32_t r = rows[q];
+  // FP16 storage: the entries divided by the largest magnitude of the row
+  double scale = 1.0;
+  if (prec == 2) {
+    double m = 0.0;
+    for (int64_t p = rp[r]; p < rp[r + 1]; p++)
+      if (ci[p] < split) m = fmax(m, fabs(v[p]));
+    if (m > 0.0) scale = (double)(float)m;
+  }
   int32_t mind = 0x7fffffff;
   for (int64_t p = rp[r]; p < rp[r + 1]; p++)
     if (ci[p] < split) {
@@ -511,14 +682,14 @@ __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t
       mind = min(mind, pc);
       if (k < cap) {
         oc[at_c(k)] = pc & (XWIN - 1);
-        ov[at_v(k)] = v[p];
+        put_v(k, prec == 2 ? v[p] / scale : v[p]);
       }
       k++;
     }
   const bool too_long = k > cap;
   for (; k < cap; k++) {
     oc[at_c(k)] = XWIN;
-    ov[at_v(k)] = 0.0;
+    put_v(k, 0.0);
   }
   // end of q's level: the first segment boundary above q
   int64_t lo = 0, hi = nseg;
@@ -534,7 +705,39 @@ __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t
   // the reciprocal of the diagonal: the solve multiplies by it (one multiply on
   // every level's dependent chain instead of a division)
   const double d = diag ? 1.0 / diag[r] : 1.0;
-  rec[q] = make_int4(slow ? ~r : r, omap[r], __double2loint(d), __double2hiint(d));
+  const int32_t rr = slow ? ~r : r;
+  rec[q] = prec == 0 ? make_int4(rr, omap[r], __double2loint(d), __double2hiint(d))
+                     : make_int4(rr, omap[r], __float_as_int((float)d), __float_as_int((float)scale));
+}
+
+// Factor values of the level-scheduled solve in FP32, or in FP16 divided by
+// the row's largest magnitude (the scale, rounded to FP32, is stored per row);
+// the diagonal (if any) in FP32.  One thread per row.
+__global__ void k_lowp_factor(const int64_t *rp, const double *v, int64_t n, int prec, void *out, float *scale,
+                              const double *diag, float *diag_out) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double sc = 1.0;
+  if (prec == 2) {
+    double m = 0.0;
+    for (int64_t p = rp[r]; p < rp[r + 1]; p++) m = fmax(m, fabs(v[p]));
+    if (m > 0.0) sc = (double)(float)m;
+    scale[r] = (float)sc;
+  }
+  for (int64_t p = rp[r]; p < rp[r + 1]; p++) {
+    if (prec == 1)
+      static_cast<float *>(out)[p] = (float)v[p];
+    else
+      static_cast<uint16_t *>(out)[p] = __builtin_bit_cast(uint16_t, (_Float16)(float)(v[p] / sc));
+  }
+  if (diag) diag_out[r] = (float)diag[r];
+}
+
+int launch_lowp_factor(const int64_t *rp, const double *v, int64_t n, int prec, void *out, float *scale,
+                       const double *diag, float *diag_out, hipStream_t s) {
+  if (n == 0) return 0;
+  k_lowp_factor<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, v, n, prec, out, scale, diag, diag_out);
+  return check_launch("lowp_factor");
 }
 
 int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci, int64_t n, int64_t split,
@@ -550,9 +753,9 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
 
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
                     int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G, int E,
-                    const int32_t *omap, int32_t *oc, double *ov, int32_t *rec, hipStream_t s) {
+                    int prec, const int32_t *omap, int32_t *oc, void *ov, int32_t *rec, hipStream_t s) {
   k_lds_fill<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(rows, rp, ci, v, diag, n, split, pos, lev_ptr, nseg, G, E,
-                                                              omap, oc, ov, reinterpret_cast<int4 *>(rec));
+                                                              prec, omap, oc, ov, reinterpret_cast<int4 *>(rec));
   return check_launch("lds_fill");
 }
 
@@ -701,13 +904,27 @@ int launch_trsv(const TrsvLaunch &t, hipStream_t s) {
   a.scatter_out = t.scatter_out;
   a.scatter_map = t.scatter_map;
   a.st = (Status *)t.status;
+  a.v_lp = t.v_lp;
+  a.diag_lp = t.prec != 0 && t.diag ? t.diag_lp : nullptr;
+  a.scale_lp = t.scale_lp;
+  if (t.prec != 0 && (!t.v_lp || (t.diag && !t.diag_lp) || (t.prec == 2 && !t.scale_lp))) return ILU_ERR_INVALID_ARG;
   const int64_t grid = t.nchunks < t.max_waves ? t.nchunks : t.max_waves;
-  switch (t.role) {
-    case 0: k_trsv<0><<<(unsigned)grid, WAVE, 0, s>>>(a); break;
-    case 1: k_trsv<1><<<(unsigned)grid, WAVE, 0, s>>>(a); break;
-    case 2: k_trsv<2><<<(unsigned)grid, WAVE, 0, s>>>(a); break;
-    default: k_trsv<3><<<(unsigned)grid, WAVE, 0, s>>>(a); break;
+  const unsigned gr = (unsigned)grid;
+#define SILU_TRSV_ROLES(P_)                                 \
+  switch (t.role) {                                         \
+    case 0: k_trsv<0, P_><<<gr, WAVE, 0, s>>>(a); break;    \
+    case 1: k_trsv<1, P_><<<gr, WAVE, 0, s>>>(a); break;    \
+    case 2: k_trsv<2, P_><<<gr, WAVE, 0, s>>>(a); break;    \
+    default: k_trsv<3, P_><<<gr, WAVE, 0, s>>>(a); break;   \
   }
+  if (t.prec == 1) {
+    SILU_TRSV_ROLES(1)
+  } else if (t.prec == 2) {
+    SILU_TRSV_ROLES(2)
+  } else {
+    SILU_TRSV_ROLES(0)
+  }
+#undef SILU_TRSV_ROLES
   return check_launch("trsv");
 }
 

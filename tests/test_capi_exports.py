@@ -38,3 +38,4 @@ def test_default_options_without_gpu():
     o = _Opts()
     silu.lib().ilu_default_options(ctypes.byref(o))
     assert (o.method, o.interior_fact, o.inner_iters, o.pivot_mode) == (silu.BJ, silu.ILU0, 3, silu.PIVOT_ERROR)
+    assert (o.trsv_mode, o.factor_prec) == (silu.TRSV_AUTO, silu.PREC_F64)

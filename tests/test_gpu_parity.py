@@ -142,6 +142,40 @@ def test_fgmres_matches(built, idx, mode):
     np.testing.assert_allclose(xg, ro["x"], rtol=0, atol=1e-5 * np.abs(ro["x"]).max())
 
 
+# Triangular factors stored in FP32, or in FP16 scaled per row, with the
+# solves in FP32 and everything else in FP64.  The apply then differs from the
+# FP64 oracle's by the rounding of the stored factors: unit roundoff 2^-24
+# (FP32) or 2^-11 (FP16) per entry, times the growth through the solves, which
+# stays below about 10 on these well-scaled factors (measured: at most 3.4e-7
+# and 7.1e-4).  FGMRES, flexible in its preconditioner, still reaches the FP64
+# tolerance, within two iterations of the oracle's count (measured: equal).
+PREC_TOL = {"f32": 1e-5, "f16": 5e-3}
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+@pytest.mark.parametrize("mode", ["block", "levels"])
+@pytest.mark.parametrize("idx", [1, 6, 7], ids=lambda i: _ids()[i])
+def test_low_precision_factors(built, idx, mode, prec):
+    A, b, part, p, o, P_o, Ad, _ = built(idx)
+    m = silu()
+    fp = m.PREC_F32 if prec == "f32" else m.PREC_F16
+    mode_ = m.TRSV_BLOCK if mode == "block" else m.TRSV_LEVELS
+    print(f"[parity] low precision {prec} case {idx} trsv {mode}", flush=True)
+    P_g = m.setup(Ad, part, p, trsv_mode=mode_, factor_prec=fp, **o)
+    r = synth.uniform_rhs(A.n, 100 + idx)
+    zo = P_o.apply(r)
+    zg = P_g.apply(torch.as_tensor(r).cuda()).cpu().numpy()
+    err = np.abs(zg - zo).max() / np.abs(zo).max()
+    assert err <= PREC_TOL[prec], err
+    assert err > 0.0  # the factors really are rounded
+    restart = 30 if A.n < 5000 else 50
+    ro = oracle.fgmres(A, P_o, b, rtol=1e-8, restart=restart, maxit=600)
+    rg = m.fgmres(Ad, P_g, torch.as_tensor(b).cuda(), rtol=1e-8, restart=restart, maxit=600)
+    assert rg["converged"] and rg["iterations"] <= ro["iterations"] + 2, (rg["iterations"], ro["iterations"])
+    xg = rg["x"].cpu().numpy()
+    assert np.linalg.norm(oracle.residual(A, b, xg)) / np.linalg.norm(b) <= 1e-8
+
+
 def test_spmv_bit_exact():
     A = synth.random_sparse(5003, 11, 41, band=60)
     x = synth.uniform_rhs(A.n, 9)
@@ -170,6 +204,9 @@ def test_errors_are_reported():
     Po = oracle.Precond(Z, None, 1, pivot_mode=oracle.PIVOT_PERTURB, pivot_tol=1e-3)
     r = np.array([1.0, 2.0])
     np.testing.assert_allclose(P.apply(torch.as_tensor(r).cuda()).cpu().numpy(), Po.apply(r), rtol=1e-14)
+    with pytest.raises(m.SchurILUError) as e:
+        m.setup(m.DeviceCSR.from_host(synth.aniso5(6)), factor_prec=3)
+    assert e.value.code == -1
 
 
 @pytest.mark.parametrize("kind", ["one_row", "all_interface", "empty_part"])
