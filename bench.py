@@ -47,6 +47,7 @@ WORKLOADS = {
                            dict(method=1, interior_fact=2, interface_fact=1, droptol=1e-3, lfil=20, inner_iters=10),
                            1e-8, 50),
     "aniso2d_64": ("aniso2d_64", dict(method=0, interior_fact=0), 1e-8, 30),
+    "rot9_512": ("rot9_512", dict(method=0, interior_fact=0), 1e-10, 30),
 }
 DESCRIPTION = {
     "aniso3d_128_slab16": "3D 7-point -(u_xx + 0.1 u_yy + 0.01 u_zz), 128^3 (n=2097152, nnz=14581760), "
@@ -54,6 +55,9 @@ DESCRIPTION = {
                           "local Schur complements MILU(0), reduced system GMRES(10); FGMRES(50) to rtol 1e-8; "
                           "b = U(-1,1) seed 2",
     "aniso2d_64": "2D 5-point -(u_xx + 0.01 u_yy), 64^2, one block, ILU(0), FGMRES(30) to rtol 1e-8, b = A 1",
+    "rot9_512": "2D 9-point rotated anisotropic diffusion (eps 1e-3, theta pi/6), 512^2 (n=262144), one block, "
+                "ILU(0), FGMRES(30) to rtol 1e-10, b = U(-1,1) seed 3 (the mixed-precision operator at a quarter "
+                "of its side)",
 }
 
 

@@ -104,6 +104,13 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// value of v on lane l (l wave-uniform): two scalar reads, no LDS
+__device__ inline double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
 // Values that steer the control flow of a wave must be wave-uniform in the
 // compiler's eyes (scalar registers).  With one wave per workgroup the
 // compiler drops __syncthreads(), so a value written to LDS by lane 0 and

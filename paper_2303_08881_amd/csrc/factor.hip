@@ -146,8 +146,6 @@ struct FactLds {
   int32_t *fins, *fcol;
   double *fval;
   uint8_t *ws;  // slot of each working entry's cached pivot row
-  double *tD;
-  int32_t *toff, *tlen;
   int32_t *cc;
   double *cv;
 };
@@ -161,8 +159,6 @@ __device__ __forceinline__ bool factor_row(const FactArgs &a, int64_t r, const F
   int32_t *const fins = L.fins, *const fcol = L.fcol;
   double *const fval = L.fval;
   uint8_t *const ws = L.ws;
-  double *const tD = L.tD;
-  int32_t *const toff = L.toff, *const tlen = L.tlen;
   int32_t *const cc = L.cc;
   double *const cv = L.cv;
   const int lane = lane_id();
@@ -197,6 +193,10 @@ __device__ __forceinline__ bool factor_row(const FactArgs &a, int64_t r, const F
   double drop = 0.0;  // MILU: dropped fill of this row, summed in (k, j) order (lane 0)
   bool failed = false;
 
+  // the round's slot table in registers: lane s holds the diagonal, the
+  // cache offset and the length of the U row cached in slot s
+  double t_dk = 0.0;
+  int t_off = 0, t_len = 0;
   bool first = true;
   for (int pos = 0;; pos++) {
     // every value that decides the control flow below is made wave-uniform
@@ -296,9 +296,9 @@ __device__ __forceinline__ bool factor_row(const FactArgs &a, int64_t r, const F
         }
       }
       if (cached) {
-        tD[lane] = dk;
-        toff[lane] = off;
-        tlen[lane] = ul;
+        t_dk = dk;
+        t_off = off;
+        t_len = ul;
       }
       wave_sync();
       if (x < len) {
@@ -313,22 +313,21 @@ __device__ __forceinline__ bool factor_row(const FactArgs &a, int64_t r, const F
         if (wc[y] < lim) wd[y] |= 2;
       wave_sync();
     }
+    // Only lane 0 writes wv[pos] and wd[pos] below, and nothing before the
+    // row is stored reads them again (lookups and shifts start at pos + 1);
+    // the wave's LDS operations execute in order, so no wait is needed.
     const int slot = uniform_i32((int)ws[pos]);
-    const double wk = uniform_f64(wv[pos] / tD[slot]);
+    const double wk = uniform_f64(wv[pos] / readlane_f64(t_dk, slot));
     if (ilut && fabs(wk) < tau) {
-      wave_sync();
       if (lane == 0) {
         wv[pos] = 0.0;
         wd[pos] = 1;
       }
-      wave_sync();
       continue;
     }
-    wave_sync();
     if (lane == 0) wv[pos] = wk;
-    wave_sync();
-    const int ub = uniform_i32(toff[slot]);
-    const int ul = uniform_i32(tlen[slot]);
+    const int ub = __builtin_amdgcn_readlane(t_off, slot);
+    const int ul = __builtin_amdgcn_readlane(t_len, slot);
     for (int base = 0; base < ul; base += WAVE) {
       const int j = base + lane;
       const bool have = j < ul;
@@ -481,13 +480,11 @@ __global__ void __launch_bounds__(WAVE *FACT_WAVES, 2) k_factor_rows(FactArgs a)
   __shared__ int32_t fcol[FACT_WAVES][WAVE];
   __shared__ double fval[FACT_WAVES][WAVE];
   __shared__ uint8_t ws[FACT_WAVES][FACT_CAP];
-  __shared__ double tD[FACT_WAVES][WAVE];
-  __shared__ int32_t toff[FACT_WAVES][WAVE], tlen[FACT_WAVES][WAVE];
   __shared__ int32_t cc[FACT_WAVES][FACT_UCACHE];
   __shared__ double cv[FACT_WAVES][FACT_UCACHE];
   __shared__ long long sh_t;
   const int w = (int)(threadIdx.x / WAVE);
-  const FactLds L{wc[w], wv[w], wd[w], fins[w], fcol[w], fval[w], ws[w], tD[w], toff[w], tlen[w], cc[w], cv[w]};
+  const FactLds L{wc[w], wv[w], wd[w], fins[w], fcol[w], fval[w], ws[w], cc[w], cv[w]};
 
   int64_t sid = (int64_t)blockIdx.x % a.ninit;
   for (;;) {
