@@ -289,7 +289,7 @@ struct ilu_precond {
   int32_t *gmapL = nullptr, *gmapW = nullptr, *fmapU = nullptr, *finB = nullptr, *finS = nullptr;
   double *bL = nullptr, *fL = nullptr, *gS = nullptr, *yS = nullptr, *bU = nullptr, *uU = nullptr;
   // reduced-system GMRES
-  double *iV = nullptr, *it1 = nullptr, *it2 = nullptr, *iH = nullptr, *ics = nullptr, *isn = nullptr,
+  double *iV = nullptr, *iW = nullptr, *it1 = nullptr, *it2 = nullptr, *iH = nullptr, *ics = nullptr, *isn = nullptr,
          *ig = nullptr, *ic = nullptr, *ipa = nullptr, *ipb = nullptr, *iscal = nullptr;
   int *iflags = nullptr;
   Status *status = nullptr;
@@ -1096,6 +1096,7 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
   if (schur && nS > 0) {
     const int k = std::max(opt->inner_iters, 0);
     RC(mem.alloc(&P->iV, (int64_t)(k + 1) * nS));
+    RC(mem.alloc(&P->iW, nS));
     RC(mem.alloc(&P->it1, nS));
     RC(mem.alloc(&P->it2, nS));
     RC(mem.alloc(&P->iH, (int64_t)(k + 1) * (k + 1)));
@@ -1188,12 +1189,14 @@ static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t 
   RC(launch_reduce_final(P->ipa, nS, beta, s));
   RC(launch_init_krylov(P->ig, beta, stop, nsteps, s));
   RC(launch_scale_copy(V, nullptr, beta, V, nS, nullptr, s));
+  // C_off (in block mode its rows are in L_S order, its columns in U_S order)
+  const Csr &C = P->block_mode ? P->Coffr : P->Coff;
+  // C_off v_0; later products come with the normalisation of the step before
+  RC(timed(ILU_K_SPMV_COFF, spmv_bytes(nS, C.nnz, false), s,
+           [&] { return launch_spmv(C.rp, C.ci, C.v, nS, V, P->it1, s); }));
+  double *w = P->iW;  // the new direction, orthogonalised apart from the basis
   for (int j = 0; j < k; j++) {
-    double *vj = V + (int64_t)j * nS, *w = V + (int64_t)(j + 1) * nS;
-    // C_off v_j (in block mode C_off's rows are in L_S order, its columns in U_S order)
-    const Csr &C = P->block_mode ? P->Coffr : P->Coff;
-    RC(timed(ILU_K_SPMV_COFF, spmv_bytes(nS, C.nnz, false), s,
-             [&] { return launch_spmv(C.rp, C.ci, C.v, nS, vj, P->it1, s); }));
+    double *vj = V + (int64_t)j * nS, *vn = V + (int64_t)(j + 1) * nS;
     RC(trsv_schur(P, P->it1, P->it2, s));
     double *pc = P->ipa, *pn = P->ipb;
     RC(launch_sum_dot(w, vj, P->it2, V, nS, pc, s));  // w = v_j + D^-1 C_off v_j, <w, v_0>
@@ -1202,8 +1205,16 @@ static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t 
       RC(launch_mgs_step(w, V + (int64_t)i * nS, pc, P->iH + i + (int64_t)ldh * j, vnext, nS, pn, stop, s));
       std::swap(pc, pn);
     }
-    RC(launch_givens_scale(P->iH, ldh, P->ics, P->isn, P->ig, j, pc, stop, nsteps, est, hn, beta,
-                           P->opt.inner_rtol, w, nS, s));
+    if (j + 1 < k) {
+      // v_{j+1} = w / ||w|| and C_off v_{j+1} in one launch
+      RC(timed(ILU_K_SPMV_COFF, spmv_bytes(nS, C.nnz, false) + 16.0 * (double)nS, s, [&] {
+        return launch_givens_scale_spmv(P->iH, ldh, P->ics, P->isn, P->ig, j, pc, stop, nsteps, est, hn, beta,
+                                        P->opt.inner_rtol, w, vn, nS, C.rp, C.ci, C.v, P->it1, s);
+      }));
+    } else {
+      RC(launch_givens_scale(P->iH, ldh, P->ics, P->isn, P->ig, j, pc, stop, nsteps, est, hn, beta,
+                             P->opt.inner_rtol, w, nS, s));
+    }
   }
   RC(launch_backsolve(P->iH, ldh, P->ig, nsteps, P->ic, s));
   return launch_combine(y, V, nS, P->ic, nsteps, nS, false, s);

@@ -427,6 +427,100 @@ int launch_givens_scale(double *H, int ldh, double *cs, double *sn, double *g, i
   return check_launch("givens_scale");
 }
 
+// k_givens_scale for a w kept apart from the basis (wt), fused with the next
+// Arnoldi step's sparse product: every block writes its slice of
+// v = wt / ||wt|| and computes y = C v for its rows, reading each needed
+// element as wt[c] / ||wt|| -- the same division as the stored value, so y is
+// bit for bit the product with the stored v.  wt is only read, so the blocks
+// need no ordering.  A zero norm leaves v = wt (as k_givens_scale leaves w).
+template <bool VEC>
+__global__ void __launch_bounds__(RED_THREADS)
+    k_givens_scale_spmv(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm, int *stop,
+                        int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol,
+                        const double *__restrict__ wt, double *__restrict__ v, int64_t n,
+                        const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                        const double *__restrict__ cv, double *__restrict__ y, int npart) {
+  __shared__ double sh;
+  if (threadIdx.x < WAVE) {
+    const double hn2 = reduce_partials(pnorm, npart);
+    if (threadIdx.x == 0) sh = sqrt(hn2);
+  }
+  __syncthreads();
+  const double hn = sh;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !*stop) {
+    *hn_out = hn;
+    double *col = H + (int64_t)ldh * j;
+    col[j + 1] = hn;
+    for (int i = 0; i < j; i++) {
+      const double a = col[i], b = col[i + 1];
+      col[i] = fma(cs[i], a, sn[i] * b);
+      col[i + 1] = fma(-sn[i], a, cs[i] * b);
+    }
+    const double a = col[j], b = col[j + 1];
+    const double r = sqrt(fma(a, a, b * b));
+    cs[j] = a / r;
+    sn[j] = b / r;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    *nsteps = j + 1;
+    const double e = fabs(g[j + 1]);
+    *est = e;
+    if (!isfinite(hn) || !isfinite(e))
+      *stop = 3;
+    else if (hn == 0.0)
+      *stop = 1;
+    else if (e <= rtol * (*tol_ref))
+      *stop = 2;
+  }
+  const bool scale = hn != 0.0;
+  const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
+  const int64_t i0 = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x;
+  const int64_t m = VEC ? n / 2 : n;
+  for (int64_t base = i0; base < m; base += VB * stride) {
+    Lane2<VEC> t[VB];
+#pragma unroll
+    for (int k = 0; k < VB; k++)
+      if (base + k * stride < m) t[k] = ld2<VEC>(wt, base + k * stride);
+#pragma unroll
+    for (int k = 0; k < VB; k++)
+      if (base + k * stride < m) {
+        if (scale) {
+          t[k].x = t[k].x / hn;
+          t[k].y = t[k].y / hn;
+        }
+        st2<VEC>(v, base + k * stride, t[k]);
+      }
+  }
+  // one row per thread (the grid covers the rows), entries in column order
+  for (int64_t i = i0; i < n; i += stride) {
+    double acc = 0.0;
+    for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+      const double x = scale ? wt[ci[p]] / hn : wt[ci[p]];
+      acc = fma(cv[p], x, acc);
+    }
+    y[i] = acc;
+  }
+}
+
+int launch_givens_scale_spmv(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm,
+                             int *stop, int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol,
+                             const double *wt, double *v, int64_t n, const int64_t *rp, const int32_t *ci,
+                             const double *cv, double *y, hipStream_t s) {
+  // a grid of one thread per row for the product; the norm partials come
+  // from a grid of red_blocks(n)
+  const int np = red_blocks(n);
+  const unsigned grid = (unsigned)std::max<int64_t>(np, (n + RED_THREADS - 1) / RED_THREADS);
+  if (vec2_ok(n, wt, v, nullptr))
+    k_givens_scale_spmv<true><<<grid, RED_THREADS, 0, s>>>(H, ldh, cs, sn, g, j, pnorm, stop, nsteps, est, hn_out,
+                                                           tol_ref, rtol, wt, v, n, rp, ci, cv, y, np);
+  else
+    k_givens_scale_spmv<false><<<grid, RED_THREADS, 0, s>>>(H, ldh, cs, sn, g, j, pnorm, stop, nsteps, est, hn_out,
+                                                            tol_ref, rtol, wt, v, n, rp, ci, cv, y, np);
+  return check_launch("givens_scale_spmv");
+}
+
 // R c = g by back substitution (sizes from *nsteps)
 __global__ void k_backsolve(const double *H, int ldh, const double *g, const int *nsteps, double *c) {
   if (threadIdx.x != 0) return;

@@ -221,6 +221,12 @@ int launch_scatter(const double *x, const int32_t *map, int64_t n, double *z, hi
 int launch_givens_scale(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm, int *stop,
                         int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol, double *w,
                         int64_t n, hipStream_t s);
+// the same with w kept apart (wt): v = wt / ||wt||, and y = C v for the next
+// step (C in CSR), in one launch
+int launch_givens_scale_spmv(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm,
+                             int *stop, int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol,
+                             const double *wt, double *v, int64_t n, const int64_t *rp, const int32_t *ci,
+                             const double *cv, double *y, hipStream_t s);
 // w = a + b and the partials of <w, v>
 int launch_sum_dot(double *w, const double *a, const double *b, const double *v, int64_t n, double *partials,
                    hipStream_t s);
