@@ -75,9 +75,11 @@ def kernel_instance(cls: str, sched, prec: int = 0) -> str | None:
         k, diag = TRSV_ROLE[cls]
         if sched is None or not sched[4 * k]:
             return None
-        if cls == "trsv_LS" and len(sched) > 16 and sched[16]:  # L_S and U_S in one launch
-            return f"void silu::k_trsv_lds_pair<{sched[9]}, {sched[10]}, {prec}>"
-        return f"void silu::k_trsv_lds<{sched[4 * k + 1]}, {sched[4 * k + 2]}, {diag}, {prec}>"
+        fast = lambda b: "true" if (sched[17] >> b) & 1 else "false"  # noqa: E731
+        if cls == "trsv_LS" and sched[16]:  # L_S and U_S in one launch (fast only if both are)
+            both = "true" if (sched[17] >> 2) & (sched[17] >> 3) & 1 else "false"
+            return f"void silu::k_trsv_lds_pair<{sched[9]}, {sched[10]}, {prec}, {both}>"
+        return f"void silu::k_trsv_lds<{sched[4 * k + 1]}, {sched[4 * k + 2]}, {diag}, {prec}, {fast(k)}>"
     return {"spmv_A": "silu::k_spmv(", "spmv_Coff": "silu::k_spmv(", "mgs": "void silu::k_mgs_step<"}.get(cls)
 
 

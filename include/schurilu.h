@@ -204,7 +204,9 @@ const char *ilu_last_error(void);
  *   44 schedule of the L_B, U_B, L_S, U_S solves [int32 20]: for each, 1 if
  *      solved block-locally (one workgroup per subdomain), lanes per row,
  *      entries per lane, threads per workgroup; then 1 if L_S and U_S run as
- *      one launch, and three zeros.
+ *      one launch, a bit mask of the block-local solves that run without the
+ *      slow-row and wide-level checks (bit k for solve k: no slow row, every
+ *      level within the workgroup), the factor storage precision, and a zero.
  */
 int ilu_export(ilu_precond_t *P, int32_t what, void *h_buf, int64_t *len);
 

@@ -247,6 +247,7 @@ struct Schedule {
   void *v_lp = nullptr;
   float *diag_lp = nullptr, *scale_lp = nullptr;
   int32_t lds_g = 1, lds_e = 4, lds_bt = 64;
+  bool lds_fast = false;  // no slow row and no level wider than the workgroup
   int64_t ext_col = 0;  // dependency columns of the block-local solve are < ext_col
   int64_t nloc = 0;     // rows in the block-local solve (the rows of W follow in their own pass)
 };
@@ -710,6 +711,7 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   S.lds_g = G;
   S.lds_e = E;
   S.lds_bt = (int32_t)std::min<int64_t>(bt, 512);
+  const bool fits = bt <= 512;
   const int64_t ne = (nloc + 1) * G * E;
   const int prec = P->opt.factor_prec;
   const int64_t vbytes = prec == ILU_PREC_F64 ? 8 : prec == ILU_PREC_F32 ? 4 : 2;
@@ -719,9 +721,13 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   S.lds_v = vstore;
   RC(mem.alloc(&S.lds_rec, 4 * (nloc + 1)));
   S.out_map = omap ? omap : S.pos;
+  RC(fill_i32(dm, 0, 1, s));  // reused as the slow-row flag
   RC(launch_lds_fill(S.blk_rows, T.rp, T.ci, T.v, diag, nloc, ext_col, S.pos, S.blk_lev_ptr, (int64_t)nkeys, G, E, prec,
-                     S.out_map, S.lds_c, S.lds_v, S.lds_rec, s));
+                     S.out_map, S.lds_c, S.lds_v, S.lds_rec, dm, s));
+  int32_t any_slow = 1;
+  HIPCK(hipMemcpyAsync(&any_slow, dm, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCK(hipStreamSynchronize(s));
+  S.lds_fast = fits && any_slow == 0;
   return 0;
 }
 
@@ -825,6 +831,7 @@ static TrsvLaunch make_launch(ilu_precond *P, Schedule &S, const Csr &T, const d
     t.lds_g = S.lds_g;
     t.lds_e = S.lds_e;
     t.lds_bt = S.lds_bt;
+    t.lds_fast = S.lds_fast ? 1 : 0;
     t.split_col = S.ext_col;
     t.nrows = S.nloc;
   }
@@ -1551,6 +1558,8 @@ int ilu_export(ilu_precond_t *P, int32_t what, void *h, int64_t *len) {
         const TrsvLaunch up = make_launch(P, P->sUS, P->US, P->DS, INT64_MAX, P->yS, nullptr, P->yS, nullptr, nullptr, 3);
         v[16] = trsv_lds_pair_ok(lo, up) ? 1 : 0;
       }
+      for (int k = 0; k < 4; k++) v[17] |= (sch[k]->use_block && sch[k]->lds_fast ? 1 : 0) << k;
+      v[18] = P->opt.factor_prec;
       if (!h) {
         *len = 20;
         return 0;

@@ -145,6 +145,7 @@ struct TrsvLaunch {
   int32_t lds_g;           // lanes per row: 1 (E = 2, 4), or 1, 2, 4, 8 (E = 8)
   int32_t lds_e;           // entries per lane: 2, 4 or 8
   int32_t lds_bt;          // threads per workgroup (multiple of 64, <= 512)
+  int32_t lds_fast;        // no slow row, every level within bt / G rows: the solve skips both checks
   // storage precision of the factor values (0 FP64, 1 FP32, 2 FP16 scaled per
   // row), both modes; the level-scheduled solve reads v_lp, diag_lp and
   // scale_lp instead of v and diag when it is not 0
@@ -191,7 +192,8 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
                        hipStream_t s);
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
                     int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G, int E,
-                    int prec, const int32_t *omap, int32_t *oc, void *ov, int32_t *rec, hipStream_t s);
+                    int prec, const int32_t *omap, int32_t *oc, void *ov, int32_t *rec, int *any_slow,
+                    hipStream_t s);
 // block id of each row from ascending block starts (s1 below split, s2 from split on; s2 may be NULL)
 int launch_row_blocks(int64_t nrows, int32_t nblk, const int64_t *s1, const int64_t *s2, int64_t split, int32_t *blk,
                       hipStream_t s);

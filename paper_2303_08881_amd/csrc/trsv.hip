@@ -396,7 +396,9 @@ __device__ __forceinline__ void refill(const LdsTrsvArgs &a, int32_t lo, int32_t
   S.rhs = at32(a.b, in ? q : 0u);
 }
 
-template <int G, int E, bool DIAG, int P>
+// FAST: the factor has no slow row and every level fits the workgroup (known
+// at setup), so the step carries neither check.
+template <int G, int E, bool DIAG, int P, bool FAST>
 __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, typename Acc<P>::T *win, const int32_t *lp, int32_t l,
                                       int32_t j, int32_t g, PSet<E, P> &S) {
   using A = typename Acc<P>::T;
@@ -425,23 +427,27 @@ __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, typename Acc<P>::T *
     for (int k = 0; k < E; k++) s = fma_t(-(A)VW::get(S.w, k), xv[k], s);
     s = group_sum<G>(s);
   }
-  const bool slow = S.rec.x < 0;
-  const int32_t r = slow ? ~S.rec.x : S.rec.x;
   if (DIAG) s = s * (A)rec_diag<P>(S.rec);  // the record holds 1 / d
-  if (mine && slow) s = (A)slow_row<DIAG>(a, r, q, rec_diag<P>(S.rec));
+  if constexpr (!FAST) {
+    const bool slow = S.rec.x < 0;
+    const int32_t r = slow ? ~S.rec.x : S.rec.x;
+    if (mine && slow) s = (A)slow_row<DIAG>(a, r, q, rec_diag<P>(S.rec));
+  }
   if (mine && g == 0) {
     win[q & (XWIN - 1)] = s;
     at32(a.out, (uint32_t)S.rec.y) = (double)s;
   }
-  // rows beyond bt/G in this level: one thread each, slow path
-  const int32_t cap = a.bt / G;
-  for (int32_t qq = q0 + cap + (int32_t)threadIdx.x; qq < q1; qq += a.bt) {
-    const int4 rc = a.rec[qq];
-    const int32_t rr = rc.x < 0 ? ~rc.x : rc.x;
-    const A s2 = (A)slow_row<DIAG>(a, rr, qq, rec_diag<P>(rc));
-    win[qq & (XWIN - 1)] = s2;
-    a.out[(uint32_t)rc.y] = (double)s2;
-    __builtin_amdgcn_s_waitcnt(0);
+  if constexpr (!FAST) {
+    // rows beyond bt/G in this level: one thread each, slow path
+    const int32_t cap = a.bt / G;
+    for (int32_t qq = q0 + cap + (int32_t)threadIdx.x; qq < q1; qq += a.bt) {
+      const int4 rc = a.rec[qq];
+      const int32_t rr = rc.x < 0 ? ~rc.x : rc.x;
+      const A s2 = (A)slow_row<DIAG>(a, rr, qq, rec_diag<P>(rc));
+      win[qq & (XWIN - 1)] = s2;
+      a.out[(uint32_t)rc.y] = (double)s2;
+      __builtin_amdgcn_s_waitcnt(0);
+    }
   }
   __syncthreads();  // also for an empty level: the step stays branch-free
   refill<G, E, P>(a, f0, f1, j, g, S);
@@ -450,7 +456,7 @@ __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, typename Acc<P>::T *
 // One subdomain's solve by the calling workgroup (win: XWIN + 1 values of the
 // solve's precision, lp: BT_LDS_LEVELS + 2 LOOK_MAX + 2 ints of LDS); returns
 // after the last level's barrier.
-template <int G, int E, bool DIAG, int P>
+template <int G, int E, bool DIAG, int P, bool FAST>
 __device__ __forceinline__ void block_solve(const LdsTrsvArgs &a, typename Acc<P>::T *win, int32_t *lp) {
   using A = typename Acc<P>::T;
   constexpr int LOOK = look_of<E, P>();
@@ -478,72 +484,88 @@ __device__ __forceinline__ void block_solve(const LdsTrsvArgs &a, typename Acc<P
   // order and the register sets keep their names
   for (int32_t l = 0; l < nlev; l += LOOK) {
 #pragma unroll
-    for (int k = 0; k < LOOK; k++) pstep<G, E, DIAG, P>(a, win, lp, l + k, j, g, S[k]);
+    for (int k = 0; k < LOOK; k++) pstep<G, E, DIAG, P, FAST>(a, win, lp, l + k, j, g, S[k]);
   }
 }
 
-template <int G, int E, bool DIAG, int P>
+template <int G, int E, bool DIAG, int P, bool FAST>
 __global__ void __launch_bounds__(BT_MAX) k_trsv_lds(LdsTrsvArgs a) {
   __shared__ typename Acc<P>::T win[XWIN + 1];  // slot XWIN stays 0: the target of padding entries
   __shared__ int32_t lp[BT_LDS_LEVELS + 2 * LOOK_MAX + 2];
-  block_solve<G, E, DIAG, P>(a, win, lp);
+  block_solve<G, E, DIAG, P, FAST>(a, win, lp);
 }
 
 // L_S then U_S of each subdomain in one launch (both with the same lane
 // shape): U_S reads the solution that this workgroup's L_S wrote before the
 // barrier between the two.
-template <int G, int E, int P>
+template <int G, int E, int P, bool FAST>
 __global__ void __launch_bounds__(BT_MAX) k_trsv_lds_pair(LdsTrsvArgs lo, LdsTrsvArgs up) {
   __shared__ typename Acc<P>::T win[XWIN + 1];
   __shared__ int32_t lp[BT_LDS_LEVELS + 2 * LOOK_MAX + 2];
-  block_solve<G, E, false, P>(lo, win, lp);
+  block_solve<G, E, false, P, FAST>(lo, win, lp);
   __syncthreads();
-  block_solve<G, E, true, P>(up, win, lp);
+  block_solve<G, E, true, P, FAST>(up, win, lp);
 }
 
-template <bool DIAG, int P>
+template <bool DIAG, int P, bool FAST>
 static void launch_ge_p(int G, int E, unsigned grid, unsigned bt, const LdsTrsvArgs &a, hipStream_t s) {
   if (E == 2) {
-    k_trsv_lds<1, 2, DIAG, P><<<grid, bt, 0, s>>>(a);
+    k_trsv_lds<1, 2, DIAG, P, FAST><<<grid, bt, 0, s>>>(a);
     return;
   }
   if (E == 4) {
-    k_trsv_lds<1, 4, DIAG, P><<<grid, bt, 0, s>>>(a);
+    k_trsv_lds<1, 4, DIAG, P, FAST><<<grid, bt, 0, s>>>(a);
     return;
   }
   switch (G) {
-    case 1: k_trsv_lds<1, 8, DIAG, P><<<grid, bt, 0, s>>>(a); break;
-    case 2: k_trsv_lds<2, 8, DIAG, P><<<grid, bt, 0, s>>>(a); break;
-    case 4: k_trsv_lds<4, 8, DIAG, P><<<grid, bt, 0, s>>>(a); break;
-    default: k_trsv_lds<8, 8, DIAG, P><<<grid, bt, 0, s>>>(a); break;
+    case 1: k_trsv_lds<1, 8, DIAG, P, FAST><<<grid, bt, 0, s>>>(a); break;
+    case 2: k_trsv_lds<2, 8, DIAG, P, FAST><<<grid, bt, 0, s>>>(a); break;
+    case 4: k_trsv_lds<4, 8, DIAG, P, FAST><<<grid, bt, 0, s>>>(a); break;
+    default: k_trsv_lds<8, 8, DIAG, P, FAST><<<grid, bt, 0, s>>>(a); break;
   }
 }
 
-template <bool DIAG>
-static void launch_ge(int G, int E, int prec, unsigned grid, unsigned bt, const LdsTrsvArgs &a, hipStream_t s) {
+template <bool DIAG, bool FAST>
+static void launch_ge_f(int G, int E, int prec, unsigned grid, unsigned bt, const LdsTrsvArgs &a, hipStream_t s) {
   if (prec == 1)
-    launch_ge_p<DIAG, 1>(G, E, grid, bt, a, s);
+    launch_ge_p<DIAG, 1, FAST>(G, E, grid, bt, a, s);
   else if (prec == 2)
-    launch_ge_p<DIAG, 2>(G, E, grid, bt, a, s);
+    launch_ge_p<DIAG, 2, FAST>(G, E, grid, bt, a, s);
   else
-    launch_ge_p<DIAG, 0>(G, E, grid, bt, a, s);
+    launch_ge_p<DIAG, 0, FAST>(G, E, grid, bt, a, s);
+}
+template <bool DIAG>
+static void launch_ge(int G, int E, int prec, bool fast, unsigned grid, unsigned bt, const LdsTrsvArgs &a,
+                      hipStream_t s) {
+  if (fast)
+    launch_ge_f<DIAG, true>(G, E, prec, grid, bt, a, s);
+  else
+    launch_ge_f<DIAG, false>(G, E, prec, grid, bt, a, s);
 }
 
-template <int P>
-static void launch_pair_p(int G, int E, unsigned g, unsigned bt, const LdsTrsvArgs &a, const LdsTrsvArgs &b,
-                          hipStream_t s) {
+template <int P, bool FAST>
+static void launch_pair_pf(int G, int E, unsigned g, unsigned bt, const LdsTrsvArgs &a, const LdsTrsvArgs &b,
+                           hipStream_t s) {
   if (E == 2)
-    k_trsv_lds_pair<1, 2, P><<<g, bt, 0, s>>>(a, b);
+    k_trsv_lds_pair<1, 2, P, FAST><<<g, bt, 0, s>>>(a, b);
   else if (E == 4)
-    k_trsv_lds_pair<1, 4, P><<<g, bt, 0, s>>>(a, b);
+    k_trsv_lds_pair<1, 4, P, FAST><<<g, bt, 0, s>>>(a, b);
   else if (G == 1)
-    k_trsv_lds_pair<1, 8, P><<<g, bt, 0, s>>>(a, b);
+    k_trsv_lds_pair<1, 8, P, FAST><<<g, bt, 0, s>>>(a, b);
   else if (G == 2)
-    k_trsv_lds_pair<2, 8, P><<<g, bt, 0, s>>>(a, b);
+    k_trsv_lds_pair<2, 8, P, FAST><<<g, bt, 0, s>>>(a, b);
   else if (G == 4)
-    k_trsv_lds_pair<4, 8, P><<<g, bt, 0, s>>>(a, b);
+    k_trsv_lds_pair<4, 8, P, FAST><<<g, bt, 0, s>>>(a, b);
   else
-    k_trsv_lds_pair<8, 8, P><<<g, bt, 0, s>>>(a, b);
+    k_trsv_lds_pair<8, 8, P, FAST><<<g, bt, 0, s>>>(a, b);
+}
+template <int P>
+static void launch_pair_p(int G, int E, bool fast, unsigned g, unsigned bt, const LdsTrsvArgs &a,
+                          const LdsTrsvArgs &b, hipStream_t s) {
+  if (fast)
+    launch_pair_pf<P, true>(G, E, g, bt, a, b, s);
+  else
+    launch_pair_pf<P, false>(G, E, g, bt, a, b, s);
 }
 
 static bool lds_args(const TrsvLaunch &t, LdsTrsvArgs &a) {
@@ -576,9 +598,9 @@ int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s) {
   if (!lds_args(t, a)) return ILU_ERR_INVALID_ARG;
   const unsigned g = (unsigned)t.nblk, bt = (unsigned)t.lds_bt;
   if (t.diag)
-    launch_ge<true>(t.lds_g, t.lds_e, t.prec, g, bt, a, s);
+    launch_ge<true>(t.lds_g, t.lds_e, t.prec, t.lds_fast != 0, g, bt, a, s);
   else
-    launch_ge<false>(t.lds_g, t.lds_e, t.prec, g, bt, a, s);
+    launch_ge<false>(t.lds_g, t.lds_e, t.prec, t.lds_fast != 0, g, bt, a, s);
   return check_launch("trsv_lds");
 }
 
@@ -593,12 +615,13 @@ int launch_trsv_lds_pair(const TrsvLaunch &lo, const TrsvLaunch &up, hipStream_t
   // one block size for both solves: each covers its own widest level
   a.bt = b.bt = std::max(a.bt, b.bt);
   const unsigned g = (unsigned)lo.nblk, bt = (unsigned)a.bt;
+  const bool fast = lo.lds_fast && up.lds_fast;
   if (lo.prec == 1)
-    launch_pair_p<1>(lo.lds_g, lo.lds_e, g, bt, a, b, s);
+    launch_pair_p<1>(lo.lds_g, lo.lds_e, fast, g, bt, a, b, s);
   else if (lo.prec == 2)
-    launch_pair_p<2>(lo.lds_g, lo.lds_e, g, bt, a, b, s);
+    launch_pair_p<2>(lo.lds_g, lo.lds_e, fast, g, bt, a, b, s);
   else
-    launch_pair_p<0>(lo.lds_g, lo.lds_e, g, bt, a, b, s);
+    launch_pair_p<0>(lo.lds_g, lo.lds_e, fast, g, bt, a, b, s);
   return check_launch("trsv_lds_pair");
 }
 
@@ -632,7 +655,7 @@ __global__ void k_max_width(const int32_t *lev_ptr, int64_t nseg, int32_t *out) 
 __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v,
                            const double *diag, int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr,
                            int64_t nseg, int G, int E, int prec, const int32_t *omap, int32_t *oc, void *ov,
-                           int4 *rec) {
+                           int4 *rec, int *any_slow) {
   int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q > n) return;
   const int64_t cap = (int64_t)G * E, nent = (n + 1) * G;
@@ -702,6 +725,7 @@ __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t
   }
   const int32_t lend = lev_ptr[lo + 1];
   const bool slow = too_long || (int64_t)mind < (int64_t)lend - XWIN;
+  if (slow) atomicOr(any_slow, 1);
   // the reciprocal of the diagonal: the solve multiplies by it (one multiply on
   // every level's dependent chain instead of a division)
   const double d = diag ? 1.0 / diag[r] : 1.0;
@@ -753,9 +777,11 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
 
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
                     int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G, int E,
-                    int prec, const int32_t *omap, int32_t *oc, void *ov, int32_t *rec, hipStream_t s) {
+                    int prec, const int32_t *omap, int32_t *oc, void *ov, int32_t *rec, int *any_slow,
+                    hipStream_t s) {
   k_lds_fill<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(rows, rp, ci, v, diag, n, split, pos, lev_ptr, nseg, G, E,
-                                                              prec, omap, oc, ov, reinterpret_cast<int4 *>(rec));
+                                                              prec, omap, oc, ov, reinterpret_cast<int4 *>(rec),
+                                                              any_slow);
   return check_launch("lds_fill");
 }
 

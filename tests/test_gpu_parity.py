@@ -176,6 +176,47 @@ def test_low_precision_factors(built, idx, mode, prec):
     assert np.linalg.norm(oracle.residual(A, b, xg)) / np.linalg.norm(b) <= 1e-8
 
 
+def _far_coupled(n, far, width_rows):
+    """Diagonally dominant matrix whose rows i >= far couple to row i - far (and back): with natural ordering the
+    first `far` rows form one level, and the coupled rows depend on positions `far` back."""
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        ent = {i: 4.0}
+        if i % width_rows and i - 1 >= 0:
+            ent[i - 1] = -1.0
+        if i % width_rows != width_rows - 1 and i + 1 < n:
+            ent[i + 1] = -1.0
+        if i >= far:
+            ent[i - far] = -0.5
+        if i + far < n:
+            ent[i + far] = -0.5
+        for c in sorted(ent):
+            rows.append(i)
+            cols.append(c)
+            vals.append(ent[c])
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, np.array(rows) + 1, 1)
+    return synth.CSR(n, np.cumsum(rp), np.array(cols, np.int32), np.array(vals))
+
+
+# The block-local solve has a check-free variant (no slow row, every level
+# within the workgroup) and a general one.  These matrices take the general
+# one: a level of 2000 independent rows (wider than a 512-thread workgroup),
+# and dependencies about 9600 positions back (older than the 8192-position
+# window).
+@pytest.mark.parametrize("kind", ["wide_level", "old_dependency"])
+def test_block_solve_general_path(kind):
+    m = silu()
+    A = _far_coupled(4000, 2000, 1) if kind == "wide_level" else _far_coupled(12000, 9080, 100)
+    print(f"[parity] block solve general path {kind} n={A.n}", flush=True)
+    P_o = oracle.Precond(A, None, 1, method=oracle.BJ, interior_fact=oracle.ILU0)
+    P_g = m.setup(m.DeviceCSR.from_host(A), None, 1, method=m.BJ, interior_fact=m.ILU0, trsv_mode=m.TRSV_BLOCK)
+    r = synth.uniform_rhs(A.n, 11)
+    zo = P_o.apply(r)
+    zg = P_g.apply(torch.as_tensor(r).cuda()).cpu().numpy()
+    np.testing.assert_allclose(zg, zo, rtol=1e-12, atol=1e-12 * np.abs(zo).max())
+
+
 def test_spmv_bit_exact():
     A = synth.random_sparse(5003, 11, 41, band=60)
     x = synth.uniform_rhs(A.n, 9)
