@@ -428,6 +428,11 @@ __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, typename Acc<P>::T *
     s = group_sum<G>(s);
   }
   if (DIAG) s = s * (A)rec_diag<P>(S.rec);  // the record holds 1 / d
+  // Rows of at most 2 entries: every lane computes its sum (idle lanes on the
+  // dummy position's zero entries), so the window reads are issued with the
+  // reads of the level bounds instead of after the test of `mine`, which
+  // waits for those (for longer rows this placement measured slower).
+  if constexpr (E == 2) asm volatile("" : "+v"(s));
   if constexpr (!FAST) {
     const bool slow = S.rec.x < 0;
     const int32_t r = slow ? ~S.rec.x : S.rec.x;
