@@ -322,6 +322,29 @@ def test_full_slab_apply_and_fgmres(slab_full):
     assert np.linalg.norm(oracle.residual(A, b, xg)) / np.linalg.norm(b) <= 1e-8
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_full_slab_low_precision(slab_full, prec):
+    """FP32 / FP16 factor storage at n = 2,097,152: apply within the bound of test_low_precision_factors, and FGMRES
+    to the same tolerance within two iterations of the FP64 path (itself within one of the oracle)."""
+    A, b, part, p, P_o, Ad, P_64 = slab_full
+    m = silu()
+    fp = m.PREC_F32 if prec == "f32" else m.PREC_F16
+    print(f"[parity] full slab, factors in {prec}", flush=True)
+    P_g = m.setup(Ad, torch.as_tensor(part).cuda(), p, factor_prec=fp, **SLAB_OPTS)
+    r = synth.uniform_rhs(A.n, 11)
+    zo = P_o.apply(r)
+    zg = P_g.apply(torch.as_tensor(r).cuda()).cpu().numpy()
+    err = np.abs(zg - zo).max() / np.abs(zo).max()
+    assert 0.0 < err <= PREC_TOL[prec], err
+    bd = torch.as_tensor(b).cuda()
+    r64 = m.fgmres(Ad, P_64, bd, rtol=1e-8, restart=50, maxit=600)
+    rg = m.fgmres(Ad, P_g, bd, rtol=1e-8, restart=50, maxit=600)
+    assert rg["converged"] and rg["iterations"] <= r64["iterations"] + 2, (rg["iterations"], r64["iterations"])
+    xg = rg["x"].cpu().numpy()
+    assert np.linalg.norm(oracle.residual(A, b, xg)) / np.linalg.norm(b) <= 1e-8
+
+
 def test_runs_are_deterministic():
     """Two setups of the same system give bitwise identical factors; two applies identical vectors."""
     m = silu()
