@@ -138,7 +138,9 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str) -> None:
 def cpu_baseline(A, b, part, nparts, opts, rtol, restart, gpu_iters, sample_iters):
     import oracle
 
-    o = dict(opts)
+    # the oracle is FP64 throughout: the storage precision of the GPU's
+    # triangular factors is not one of its options
+    o = {k: v for k, v in opts.items() if k != "factor_prec"}
     t0 = time.perf_counter()
     P = oracle.Precond(A, part, nparts, **o)
     t_setup = time.perf_counter() - t0
