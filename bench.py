@@ -16,6 +16,8 @@ is timed, with HIP events on the stream the kernels run on
 measured solves.  The CPU baseline times the
 FP64 oracle on the host on a bounded sample (its full setup plus a few outer
 iterations) and scales it to one solve with the GPU's iteration count.
+`--factor-prec f32|f16` stores the triangular factors in FP32 / FP16 (solves
+in FP32, everything else FP64); `--workload` picks another synthetic system.
 """
 from __future__ import annotations
 
@@ -292,6 +294,9 @@ def main():
         "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
         "setup_ms": round(float(np.mean([o["setup_ms"] for o in outs])), 3),
         "solve_ms": round(float(np.mean([o["solve_ms"] for o in outs])), 3),
+        # warm solves/s: a new right-hand side for factors already on the
+        # device (the solve part of each step alone)
+        "warm_solves_per_s": round(1e3 / float(np.mean([o["solve_ms"] for o in outs])), 4),
         "iterations": int(np.median(its)),
         "relres": max(o["relres"] for o in outs),
         "converged": all(o["converged"] for o in outs),
