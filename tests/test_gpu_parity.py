@@ -268,8 +268,13 @@ def test_edge_partitions(kind):
         np.testing.assert_array_equal(Pg.export("perm"), Po.export("perm"))
         np.testing.assert_array_equal(Pg.export("offsets"), Po.export("offsets"))
         r = synth.uniform_rhs(A.n, 4)
-        np.testing.assert_allclose(Pg.apply(torch.as_tensor(r).cuda()).cpu().numpy(), Po.apply(r), rtol=1e-10,
-                                   atol=1e-14)
+        zo = Po.apply(r)
+        np.testing.assert_allclose(Pg.apply(torch.as_tensor(r).cuda()).cpu().numpy(), zo, rtol=1e-10, atol=1e-14)
+        # the same degenerate shapes with factors stored in FP32 and FP16
+        for fp, tol in ((m.PREC_F32, PREC_TOL["f32"]), (m.PREC_F16, PREC_TOL["f16"])):
+            Pl = m.setup(m.DeviceCSR.from_host(A), part, p, factor_prec=fp, **o)
+            zl = Pl.apply(torch.as_tensor(r).cuda()).cpu().numpy()
+            assert np.abs(zl - zo).max() <= tol * np.abs(zo).max(), (fp, np.abs(zl - zo).max())
 
 
 # ---- the 128^3 slab workload at full size, as the benchmark runs it ----
