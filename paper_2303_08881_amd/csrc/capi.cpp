@@ -240,7 +240,8 @@ struct Schedule {
   const int32_t *out_map = nullptr;  // row -> index of its solution in the output vector
   // storage of the factor for the block-local solve (values in the storage
   // precision)
-  int32_t *lds_c = nullptr, *lds_rec = nullptr;
+  uint16_t *lds_c = nullptr;
+  int32_t *lds_rec = nullptr;
   void *lds_v = nullptr;
   // level-scheduled solve with factors stored in FP32 / FP16: the values, the
   // FP32 diagonal and (FP16) the row scales
@@ -715,7 +716,7 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   const int64_t ne = (nloc + 1) * G * E;
   const int prec = P->opt.factor_prec;
   const int64_t vbytes = prec == ILU_PREC_F64 ? 8 : prec == ILU_PREC_F32 ? 4 : 2;
-  RC(mem.alloc(&S.lds_c, ne));
+  RC(mem.alloc(&S.lds_c, ne));  // 16-bit window slots
   double *vstore;
   RC(mem.alloc(&vstore, (ne * vbytes + 7) / 8));
   S.lds_v = vstore;

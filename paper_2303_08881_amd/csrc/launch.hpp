@@ -137,7 +137,7 @@ struct TrsvLaunch {
   const int32_t *blk_rows;     // rows sorted by (block, level)
   const int32_t *blk_lev_ptr;  // [nblk * nlev_blk + 1]
   // block-local storage (launch_trsv_lds): fixed-stride dependency entries
-  const int32_t *lds_c;    // (nrows + 1) * G * E window slots, in planes of 4 per lane (2 for E = 2)
+  const void *lds_c;       // (nrows + 1) * G * E 16-bit window slots, one word of E per lane
   const void *lds_v;       // (nrows + 1) * G * E values in the storage precision, in planes of one
                            // word (16 bytes or E values) per lane
   const int32_t *lds_rec;  // int4 per position (+ dummy): {row or ~row, output index, diagonal}
@@ -192,7 +192,7 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
                        hipStream_t s);
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
                     int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G, int E,
-                    int prec, const int32_t *omap, int32_t *oc, void *ov, int32_t *rec, int *any_slow,
+                    int prec, const int32_t *omap, uint16_t *oc, void *ov, int32_t *rec, int *any_slow,
                     hipStream_t s);
 // block id of each row from ascending block starts (s1 below split, s2 from split on; s2 may be NULL)
 int launch_row_blocks(int64_t nrows, int32_t nblk, const int64_t *s1, const int64_t *s2, int64_t split, int32_t *blk,

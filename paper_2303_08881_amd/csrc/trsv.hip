@@ -156,11 +156,13 @@ __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
 //                lanes per row of E = 2, 4 or 8 entries each): column order,
 //                each column replaced by the slot of its position in the LDS
 //                solution window, padded with the window's zero slot and 0.0.
-//                They are stored in planes, one per load of a lane (4 slots
-//                or 2 values of every lane, lanes consecutive), so that each
-//                load of a wave reads one contiguous range: a lane-major
-//                layout makes a wave's load touch a cache line per lane and
-//                the L1 tag lookups, not the bytes, bound the solve;
+//                A lane's slots (16 bits each) form one word and its values
+//                words of 16 bytes (or of E values), stored in planes, one
+//                per load of a lane (lanes consecutive), so that each load
+//                of a wave reads one contiguous range: a lane-major layout
+//                makes a wave's load touch a cache line per lane, and the
+//                bytes every lane loads pass the CU's vector memory path,
+//                whose rate bounds the interior solves;
 //   rec          {row (or ~row for a slow row), output index, 1 / diagonal}.
 // A row is handled by G consecutive lanes, lane g summing entries
 // gE..gE+E-1 with fma (lane 0 starting from the right-hand side); the G
@@ -202,7 +204,7 @@ constexpr int look_of() {
 }
 
 struct LdsTrsvArgs {
-  const int4 *ent_c;       // [E / 4][nent] window slots (int2 [nent] for E = 2)
+  const void *ent_c;       // [nent] words of E 16-bit window slots (Cols<E>::W)
   const void *ent_v;       // [E / vpw][nent] words of vpw values (see VWord)
   uint32_t nent;           // lanes of entries: (npos + 1) * G
   const int4 *rec;         // [npos + 1]
@@ -220,19 +222,32 @@ struct LdsTrsvArgs {
   const int32_t *omap;     // row -> its index in out (slow rows)
 };
 
-// window slots of a lane's entries: int2 for E = 2, E/4 int4 otherwise
+// window slots of a lane's entries, 16 bits each (a slot is at most XWIN),
+// in one word per lane: uint32 for E = 2, uint2 for E = 4, uint4 for E = 8
 template <int E>
-struct Cols {
-  int4 v[E / 4];
+struct Cols;
+template <>
+struct Cols<2> {
+  using W = uint32_t;
+  W v;
+  __device__ __forceinline__ int32_t get(int k) const { return (int32_t)((v >> (16 * k)) & 0xffffu); }
+};
+template <>
+struct Cols<4> {
+  using W = uint2;
+  W v;
   __device__ __forceinline__ int32_t get(int k) const {
-    const int4 &q = v[k / 4];
-    return (k & 3) == 0 ? q.x : (k & 3) == 1 ? q.y : (k & 3) == 2 ? q.z : q.w;
+    return (int32_t)(((k >> 1 ? v.y : v.x) >> (16 * (k & 1))) & 0xffffu);
   }
 };
 template <>
-struct Cols<2> {
-  int2 v;
-  __device__ __forceinline__ int32_t get(int k) const { return k == 0 ? v.x : v.y; }
+struct Cols<8> {
+  using W = uint4;
+  W v;
+  __device__ __forceinline__ int32_t get(int k) const {
+    const uint32_t u = (k >> 1) == 0 ? v.x : (k >> 1) == 1 ? v.y : (k >> 1) == 2 ? v.z : v.w;
+    return (int32_t)((u >> (16 * (k & 1))) & 0xffffu);
+  }
 };
 
 // Storage precision of the factor values (ilu_options_t factor_prec):
@@ -383,12 +398,7 @@ __device__ __forceinline__ void refill(const LdsTrsvArgs &a, int32_t lo, int32_t
   const bool in = q < (uint32_t)hi;
   const uint32_t qc = in ? q : (uint32_t)a.npos;
   const uint32_t e = qc * G + g;
-  if constexpr (E == 2) {
-    S.c.v = at32(reinterpret_cast<const int2 *>(a.ent_c), e);
-  } else {
-#pragma unroll
-    for (int i = 0; i < E / 4; i++) S.c.v[i] = at32(a.ent_c, i * a.nent + e);
-  }
+  S.c.v = at32(reinterpret_cast<const typename Cols<E>::W *>(a.ent_c), e);
   using VW = VWord<P, E>;
 #pragma unroll
   for (int i = 0; i < VW::NW; i++) S.w[i] = at32(reinterpret_cast<const typename VW::W *>(a.ent_v), i * a.nent + e);
@@ -579,7 +589,7 @@ static bool lds_args(const TrsvLaunch &t, LdsTrsvArgs &a) {
   if (t.nlev_blk > BT_LDS_LEVELS || t.lds_bt < 64 || t.lds_bt > BT_MAX || t.lds_bt % 64 != 0 || !ge_ok ||
       !t.b || !t.x || !t.out_map)
     return false;
-  a.ent_c = reinterpret_cast<const int4 *>(t.lds_c);
+  a.ent_c = t.lds_c;
   a.ent_v = t.lds_v;
   a.nent = (uint32_t)((t.nrows + 1) * t.lds_g);
   a.rec = reinterpret_cast<const int4 *>(t.lds_rec);
@@ -659,21 +669,19 @@ __global__ void k_max_width(const int32_t *lev_ptr, int64_t nseg, int32_t *out) 
 // output index of position q is omap[rows[q]].
 __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v,
                            const double *diag, int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr,
-                           int64_t nseg, int G, int E, int prec, const int32_t *omap, int32_t *oc, void *ov,
+                           int64_t nseg, int G, int E, int prec, const int32_t *omap, uint16_t *oc, void *ov,
                            int4 *rec, int *any_slow) {
   int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q > n) return;
   const int64_t cap = (int64_t)G * E, nent = (n + 1) * G;
   // entry k of position q belongs to lane e = q G + k / E as its entry kk =
-  // k % E; each load of the solve reads one plane (4 window slots, or one
-  // word of vpw values, per lane) for consecutive lanes, so the planes are
-  // stored one after the other
+  // k % E.  A lane's E window slots (16 bits each) form one word, lanes
+  // consecutive; its values form words of vpw values, and each load of the
+  // solve reads one plane of such words for consecutive lanes, so the planes
+  // are stored one after the other
   const int vsize = prec == 0 ? 8 : prec == 1 ? 4 : 2;
   const int64_t vpw = E < 16 / vsize ? E : 16 / vsize;
-  auto at_c = [&](int64_t k) {
-    const int64_t e = q * G + k / E, kk = k % E;
-    return E == 2 ? e * 2 + kk : ((kk >> 2) * nent + e) * 4 + (kk & 3);
-  };
+  auto at_c = [&](int64_t k) { return (q * G + k / E) * E + k % E; };
   auto put_v = [&](int64_t k, double x) {
     const int64_t e = q * G + k / E, kk = k % E;
     const int64_t at = ((kk / vpw) * nent + e) * vpw + kk % vpw;
@@ -709,7 +717,7 @@ __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t
       const int32_t pc = pos[ci[p]];
       mind = min(mind, pc);
       if (k < cap) {
-        oc[at_c(k)] = pc & (XWIN - 1);
+        oc[at_c(k)] = (uint16_t)(pc & (XWIN - 1));
         put_v(k, prec == 2 ? v[p] / scale : v[p]);
       }
       k++;
@@ -782,7 +790,7 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
 
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
                     int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G, int E,
-                    int prec, const int32_t *omap, int32_t *oc, void *ov, int32_t *rec, int *any_slow,
+                    int prec, const int32_t *omap, uint16_t *oc, void *ov, int32_t *rec, int *any_slow,
                     hipStream_t s) {
   k_lds_fill<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(rows, rp, ci, v, diag, n, split, pos, lev_ptr, nseg, G, E,
                                                               prec, omap, oc, ov, reinterpret_cast<int4 *>(rec),
