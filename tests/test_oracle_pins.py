@@ -397,3 +397,148 @@ def test_error_paths():
     assert np.all(np.isfinite(P.apply(np.ones(2))))
     with pytest.raises(oracle.OracleError):
         oracle.Precond(A, np.full(A.n, 3, np.int32), 2, method=oracle.BJ)
+
+
+# ---------------------------------------------------------------- pivots (Section 4.1 reading R7)
+@pytest.mark.parametrize("a00, a01, tol, u00", [
+    (0.0, 1.0, 1e-3, 1e-3),      # zero pivot -> +tol * max_j |a_0j|
+    (-1e-6, 1.0, 1e-3, -1e-3),   # small negative pivot keeps its sign
+    (1.5e-3, 1.0, 1e-3, 1.5e-3),  # above the threshold: untouched
+    (0.0, 4.0, 1e-3, 4e-3),      # threshold scales with the row's largest magnitude
+])
+def test_perturbed_pivot_hand_values(a00, a01, tol, u00):
+    # [[a00, a01], [1, 1]]: u_00 as listed; then l_10 = 1 / u_00 and
+    # u_11 = 1 - l_10 * a01 (row 1's largest magnitude is 1, so u_11 is never perturbed).
+    A = CSR.from_dense(np.array([[a00, a01], [1.0, 1.0]]))
+    F = oracle.factor(A, method=oracle.ILU0, pivot_mode=oracle.PIVOT_PERTURB, pivot_tol=tol)
+    np.testing.assert_allclose(F["D"][0], u00, rtol=1e-15)
+    np.testing.assert_allclose(F["L"][2], [1.0 / u00], rtol=1e-15)
+    np.testing.assert_allclose(F["D"][1], 1.0 - a01 / u00, rtol=1e-12)
+
+
+def test_perturbed_pivot_hand_example_values():
+    # [[0, 1], [1, 1]] with tol 1e-3: u_00 = 1e-3, l_10 = 1000, u_11 = -999.
+    A = CSR.from_dense(np.array([[0.0, 1.0], [1.0, 1.0]]))
+    F = oracle.factor(A, method=oracle.ILU0, pivot_mode=oracle.PIVOT_PERTURB, pivot_tol=1e-3)
+    np.testing.assert_allclose(F["D"], [1e-3, -999.0], rtol=1e-13)
+    np.testing.assert_allclose(F["L"][2], [1000.0], rtol=1e-13)
+
+
+# ---------------------------------------------------------------- partial ILUT rows (Section 3.2, eq. (17))
+def _partial_example():
+    # One interior row (nfull = 1) and five partially eliminated rows.
+    #   row 0 = [4, 0, 2, 0, 0, 0]                        -> u_00 = 4, U row {2: 2}
+    #   row 1 = [1, 8, 2, -1, 0.5, 2^-10]                 (||a_1||_2 = sqrt(70.25 + 2^-20))
+    #   row 2 = [2^-9, 0, 8, 0, 0, 0]
+    #   rows 3..5 = 8 on the diagonal.
+    M = np.zeros((6, 6))
+    M[0, 0], M[0, 2] = 4.0, 2.0
+    M[1] = [1.0, 8.0, 2.0, -1.0, 0.5, 2.0 ** -10]
+    M[2, 0], M[2, 2] = 2.0 ** -9, 8.0
+    for r in (3, 4, 5):
+        M[r, r] = 8.0
+    return CSR.from_dense(M)
+
+
+def test_partial_ilut_schur_part_hand_values():
+    # droptol 2^-6: tau_1 = 2^-6 sqrt(70.25 + 2^-20) = 0.13096.
+    # Row 1: w_0 = 1/4 = 0.25 >= tau_1 is kept and eliminated: w_2 = 2 - 0.25 * 2 = 1.5.
+    # Its Schur part (columns >= 1, off the diagonal) then holds 1.5, -1, 0.5 and 2^-10;
+    # 2^-10 < tau_1 is dropped.  With lfil = 2 the two largest (1.5, -1) are kept and the
+    # diagonal 8 is kept on top of them, not counted.
+    # Row 2: w_0 = 2^-9 / 4 = 2^-11 < tau_2 = 2^-6 * 8: the multiplier is dropped before
+    # elimination, so neither W nor fill appears.
+    A = _partial_example()
+    F = oracle.factor(A, nfull=1, method=oracle.ILUT, droptol=2.0 ** -6, lfil=2)
+    np.testing.assert_array_equal(F["R"][0], [0, 3, 4, 5, 6, 7])
+    np.testing.assert_array_equal(F["R"][1], [1, 2, 3, 2, 3, 4, 5])
+    np.testing.assert_array_equal(F["R"][2], [8.0, 1.5, -1.0, 8.0, 8.0, 8.0, 8.0])
+    np.testing.assert_array_equal(F["L"][0], [0, 0, 1, 1, 1, 1, 1])
+    np.testing.assert_array_equal(F["L"][2], [0.25])
+    # no fill limit: 0.5 stays, 2^-10 is still below tau_1
+    F = oracle.factor(A, nfull=1, method=oracle.ILUT, droptol=2.0 ** -6, lfil=-1)
+    np.testing.assert_array_equal(F["R"][1], [1, 2, 3, 4, 2, 3, 4, 5])
+    np.testing.assert_array_equal(F["R"][2], [8.0, 1.5, -1.0, 0.5, 8.0, 8.0, 8.0, 8.0])
+    # lfil = 0: only the diagonal of each Schur row survives
+    F = oracle.factor(A, nfull=1, method=oracle.ILUT, droptol=2.0 ** -6, lfil=0)
+    np.testing.assert_array_equal(F["R"][1], [1, 2, 3, 4, 5])
+    np.testing.assert_array_equal(F["L"][1].size, 0)
+
+
+def test_partial_ilut_w_part_fill_limit():
+    # [[4,0,0,1],[2,4,0,0],[0,0,4,1],[1,-3,2,8]], nfull = 3, lfil = 2, droptol 0.
+    # Full rows: U row 0 = {3: 1}; row 1: l_10 = 2/4 = 0.5, fill u_13 = -0.5 * 1 = -0.5;
+    # U row 2 = {3: 1}.  Partial row 3 eliminates columns 0, 1, 2 with every multiplier:
+    # w_0 = 1/4, w_1 = -3/4, w_2 = 2/4, and its Schur entry is
+    # 8 - 0.25 * 1 - (-0.75) * (-0.5) - 0.5 * 1 = 6.875.  The cap then keeps the two
+    # largest multipliers (-0.75 at column 1, 0.5 at column 2) in W.
+    M = np.array([[4.0, 0, 0, 1], [2, 4, 0, 0], [0, 0, 4, 1], [1, -3, 2, 8]])
+    F = oracle.factor(CSR.from_dense(M), nfull=3, method=oracle.ILUT, droptol=0.0, lfil=2)
+    L = csr_dense(*F["L"], 4)
+    np.testing.assert_array_equal(L[3], [0.0, -0.75, 0.5, 0.0])
+    np.testing.assert_array_equal(F["R"][2], [6.875])
+    np.testing.assert_array_equal(L[1], [0.5, 0, 0, 0])
+    np.testing.assert_array_equal(csr_dense(*F["U"], 3, 4)[1], [0, 0, 0, -0.5])
+
+
+# ---------------------------------------------------------------- CSR validation (reading R10)
+def _valid_3x3():
+    return CSR.from_dense(np.array([[4.0, 1, 0], [1, 4, 1], [0, 1, 4]]))
+
+
+@pytest.mark.parametrize("defect", ["missing_diag", "duplicate", "unsorted", "col_negative", "col_too_big",
+                                    "row_ptr_start", "row_ptr_decreasing"])
+def test_validate_rejects_each_defect(defect):
+    A = _valid_3x3()
+    assert oracle.validate(A) == 0
+    rp, ci, v = A.row_ptr.copy(), A.col.copy(), A.val.copy()
+    if defect == "missing_diag":   # row 1 = {0, 2}: no (1, 1)
+        rp = np.array([0, 2, 4, 6]); ci = np.array([0, 1, 0, 2, 1, 2]); v = np.ones(6)
+    elif defect == "duplicate":
+        ci[2], ci[3] = 1, 1  # row 1 = {0, 1, 1, 2}: the diagonal twice
+    elif defect == "unsorted":
+        ci[2], ci[3] = ci[3], ci[2]
+    elif defect == "col_negative":
+        ci[4] = -1
+    elif defect == "col_too_big":
+        ci[4] = 3
+    elif defect == "row_ptr_start":
+        rp = rp.copy(); rp[0] = 1
+    elif defect == "row_ptr_decreasing":
+        rp = rp.copy(); rp[2] = rp[1] - 1
+    assert oracle.validate(CSR(3, rp, ci.astype(np.int32), v)) == oracle.ERR_CSR, defect
+
+
+# ---------------------------------------------------------------- inner GMRES early exit (reading R5)
+def test_inner_rtol_stops_at_the_krylov_least_squares_step():
+    # With inner_rtol the reduced-system GMRES stops at the first step j whose residual
+    # min_{y in K_j} ||rhs - T y|| is <= inner_rtol ||rhs||.  The residuals r_j are computed
+    # densely here; inner_rtol sits at the geometric mean of r_1 and r_2, so exactly two
+    # steps are taken and the result is the 2-step least-squares solution, not the k-step one.
+    A = synth.aniso7(8)
+    part = synth.slab_partition(8, 4)
+    k = 6
+    base = dict(method=oracle.SCHUR, interior_fact=oracle.ILU0, interface_fact=oracle.MILU0, inner_iters=k)
+    P = oracle.Precond(A, part, 4, **base)
+    perm = P.export("perm")
+    n, nB = A.n, int(P.export("offsets")[4])
+    nS = n - nB
+    r = synth.uniform_rhs(n, 8)
+    LB = csr_dense(*P.csr("LB"), nB) + np.eye(nB)
+    W = csr_dense(*P.csr("W"), nS, nB)
+    D = (csr_dense(*P.csr("LS"), nS) + np.eye(nS)) @ (csr_dense(*P.csr("US"), nS) + np.diag(P.export("DS")))
+    T = np.eye(nS) + np.linalg.solve(D, csr_dense(*P.csr("Coff"), nS))
+    rhs = np.linalg.solve(D, r[perm[nB:]] - W @ np.linalg.solve(LB, r[perm[:nB]]))
+    beta = np.linalg.norm(rhs)
+
+    def ls(j):
+        K = np.stack([np.linalg.matrix_power(T, i) @ rhs for i in range(j)], axis=1)
+        c = np.linalg.lstsq(T @ K, rhs, rcond=None)[0]
+        return K @ c, np.linalg.norm(rhs - T @ (K @ c))
+
+    (y1, r1), (y2, r2), (yk, rk) = ls(1), ls(2), ls(k)
+    assert r1 > r2 > rk and r1 / r2 < 1e3
+    tol = math.sqrt(r1 * r2) / beta
+    z = oracle.Precond(A, part, 4, inner_rtol=tol, **base).apply(r)
+    np.testing.assert_allclose(z[perm[nB:]], y2, rtol=1e-9, atol=1e-12)
+    assert np.linalg.norm(y2 - yk) > 1e-6 * np.linalg.norm(yk)
