@@ -82,7 +82,8 @@ def kernel_instance(cls: str, sched, prec: int = 0) -> str | None:
             both = "true" if (sched[17] >> 2) & (sched[17] >> 3) & 1 else "false"
             return f"void silu::k_trsv_lds_pair<{sched[9]}, {sched[10]}, {prec}, {both}>"
         return f"void silu::k_trsv_lds<{sched[4 * k + 1]}, {sched[4 * k + 2]}, {diag}, {prec}, {fast(k)}>"
-    return {"spmv_A": "silu::k_spmv(", "spmv_Coff": "silu::k_spmv(", "mgs": "void silu::k_mgs_step<"}.get(cls)
+    return {"spmv_A": "void silu::k_spmv<0>", "spmv_Coff": "void silu::k_spmv<1>",
+            "mgs": "void silu::k_mgs_step<"}.get(cls)
 
 
 def measured_traffic(cls: str, sched, prec: int = 0):
@@ -137,29 +138,100 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str) -> None:
     print(json.dumps(out["calibration"]))
 
 
-def cpu_baseline(A, b, part, nparts, opts, rtol, restart, gpu_iters, sample_iters):
-    import oracle
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    # the oracle is FP64 throughout: the storage precision of the GPU's
-    # triangular factors is not one of its options
-    o = {k: v for k, v in opts.items() if k != "factor_prec"}
+
+def cpu_worker(workload: str, factor_prec: str, sample_iters: int) -> None:
+    """One oracle process of the CPU baseline: full setup plus a bounded number of FGMRES iterations on the
+    workload's system; prints its timings as one JSON line."""
+    import oracle
+    import synth
+
+    key, opts, rtol, restart = WORKLOADS[workload]
+    A, b, part, nparts = synth.workload(key)
     t0 = time.perf_counter()
-    P = oracle.Precond(A, part, nparts, **o)
+    P = oracle.Precond(A, part if nparts > 1 else None, nparts, **opts)
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
     out = oracle.fgmres(A, P, b, rtol=rtol, restart=restart, maxit=sample_iters)
     t_iter = (time.perf_counter() - t0) / max(out["iterations"], 1)
-    per_solve = t_setup + gpu_iters * t_iter
+    print(json.dumps({"t_setup": t_setup, "t_iter": t_iter, "iterations": out["iterations"]}), flush=True)
+
+
+def _run_workers(workload, factor_prec, sample_iters, count):
+    import subprocess
+
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker", "--workload", workload,
+           "--factor-prec", factor_prec, "--cpu-sample-iters", str(sample_iters)]
+    env = dict(os.environ, OMP_NUM_THREADS="1", HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, env=env, text=True) for _ in range(count)]
+    outs = []
+    for p in procs:
+        so, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle worker failed with status {p.returncode}")
+        outs.append(json.loads(so.strip().splitlines()[-1]))
+    return outs
+
+
+def cpu_baseline(workload, factor_prec, gpu_iters, sample_iters, cores):
+    """The FP64 oracle, unchanged, on the host: one process alone (the one-core rate), then `cores` processes at
+    once, each on the same bounded sample (its full setup plus `sample_iters` FGMRES iterations); every process's
+    timings are scaled to one solve with the GPU's iteration count and the all-core rate is their sum."""
+    one = _run_workers(workload, factor_prec, sample_iters, 1)[0]
+    rate = lambda o: 1.0 / (o["t_setup"] + gpu_iters * o["t_iter"])  # noqa: E731
+    many = _run_workers(workload, factor_prec, sample_iters, cores) if cores > 1 else [one]
     return {
-        "value": 1.0 / per_solve,
+        "value": sum(rate(o) for o in many),
         "unit": "solves/s",
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
-        "sample": f"full oracle setup ({t_setup:.1f} s) + {out['iterations']} FGMRES iterations "
-                  f"({t_iter:.3f} s each) on the same system, scaled to {gpu_iters} iterations per solve",
-        "oracle_setup_s": t_setup,
-        "oracle_s_per_iteration": t_iter,
+        "sample": f"{cores} oracle processes at once, each: full setup + {many[0]['iterations']} FGMRES iterations "
+                  f"of this workload, scaled to {gpu_iters} iterations per solve; rate = sum over processes",
+        "cpu_model": cpu_model(),
+        "one_core_value": rate(one),
+        "oracle_setup_s": one["t_setup"],
+        "oracle_s_per_iteration": one["t_iter"],
+        "all_core_setup_s": float(np.median([o["t_setup"] for o in many])),
+        "all_core_s_per_iteration": float(np.median([o["t_iter"] for o in many])),
     }
+
+
+def chain_probe(silu, dev, levels=8192, reps=20):
+    """Per-level time of the block-local triangular solve on a tridiagonal matrix (one row per level, so every
+    level is one dependent step with no bandwidth to speak of): the floor of a level-scheduled chain."""
+    import ctypes as C
+
+    import torch
+
+    import synth
+
+    T = synth.aniso5(levels, 1.0, Ny=1)  # tridiagonal: L and U are chains of `levels` levels
+    Ad = silu.DeviceCSR.from_host(T, dev)
+    P = silu.setup(Ad, None, 1, method=silu.BJ, interior_fact=silu.ILU0, trsv_mode=silu.TRSV_BLOCK)
+    r = torch.ones(T.n, dtype=torch.float64, device=dev)
+    z = torch.empty_like(r)
+    lib = silu.lib()
+    P.apply(r, z)
+    torch.cuda.synchronize()
+    lib.ilu_kernel_stats(0, None, None, None, 1)
+    lib.ilu_kernel_timing(1)
+    for _ in range(reps):
+        P.apply(r, z)
+    torch.cuda.synchronize()
+    lib.ilu_kernel_timing(0)
+    ms, cnt = C.c_double(), C.c_int64()
+    lib.ilu_kernel_stats(0, C.byref(ms), C.byref(cnt), None, 1)
+    P.close()
+    return 1e3 * ms.value / max(cnt.value, 1) / levels
 
 
 def main():
@@ -173,11 +245,17 @@ def main():
                          "everything else stays FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=40)
+    ap.add_argument("--cpu-cores", type=int, default=min(16, os.cpu_count() or 1),
+                    help="oracle processes of the all-core CPU baseline")
+    ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device copy before the steps (scale for counter runs)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter files and exit")
     args = ap.parse_args()
+    if args.cpu_worker:
+        cpu_worker(args.workload, args.factor_prec, args.cpu_sample_iters)
+        return
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload)
         return
@@ -270,6 +348,21 @@ def main():
                 "frac": round(d["gbs"] / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom, sched, prec),
                 "avg_launch_us": round(d["avg_us"], 3), "bytes_per_launch": d["bytes_per_launch"],
                 "launches": d["launches"]}
+        if dom in TRSV_ROLE:
+            # level-chain bound of the dominant solve: its levels per launch times
+            # the per-level time of a one-row-per-level chain
+            lev = {"trsv_LB_W": ["lev_LB"], "trsv_UB_Z": ["lev_UB"], "trsv_US": ["lev_US"],
+                   "trsv_LS": ["lev_LS", "lev_US"] if sched[16] else ["lev_LS"]}[dom]
+            P = silu.setup(Ad, pd, nparts, **opts)
+            lv = [P.export(k) for k in lev]
+            P.close()
+            # block-local: each subdomain's chain runs on its own workgroup, so a
+            # launch lasts as long as the longest per-subdomain chain
+            nlev = sum(int(v.max()) + 1 if v.size else 0 for v in lv)
+            t_level = chain_probe(silu, dev)
+            roof.update(chain_levels=nlev, level_step_us=round(t_level, 5),
+                        chain_bound_us=round(nlev * t_level, 3),
+                        chain_frac=round(nlev * t_level / d["avg_us"], 4))
 
     its = [o["iterations"] for o in outs]
     lat_ms = np.array(lat) * 1e3
@@ -307,8 +400,8 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(A, b, part if nparts > 1 else None, nparts, opts, rtol, restart,
-                                              result["iterations"], args.cpu_sample_iters)
+        result["cpu_baseline"] = cpu_baseline(args.workload, args.factor_prec, result["iterations"],
+                                              args.cpu_sample_iters, args.cpu_cores)
     print(json.dumps(result), flush=True)
 
 

@@ -95,8 +95,9 @@ typedef struct {
  *                 most 16384 levels); ILU_TRSV_LEVELS spreads every level over
  *                 the whole GPU with sync-free level counters.
  *  factor_prec    storage precision of the triangular factors that the
- *                 preconditioner solves with (L_B, U_B and its Z block, L_S,
- *                 U_S and their diagonals; the factorization itself is FP64).
+ *                 preconditioner solves with (L_B, U_B, L_S, U_S and their
+ *                 diagonals; the factorization itself is FP64, and the W rows
+ *                 and Z columns stay FP64 in both solve modes).
  *                 ILU_PREC_F32 rounds them to FP32 once at setup and runs the
  *                 triangular solves in FP32; ILU_PREC_F16 stores each entry
  *                 divided by the largest magnitude of its row, in FP16, with
@@ -181,9 +182,12 @@ int csr_spmv(const ilu_csr_t *A, const double *d_x, double *d_y, void *stream);
  * call neither hipMalloc nor hipFree. */
 void ilu_destroy(ilu_precond_t *P);
 
-/* Free every cached device block (all devices) back to the HIP runtime.
- * Blocks still owned by a live preconditioner are not affected.  An
- * allocation that fails also empties the cache before it gives up. */
+/* Free every cached device block (all devices) back to the HIP runtime, and
+ * the HIP events kept for kernel timing.  Blocks still owned by a live
+ * preconditioner are not affected.  An allocation that fails also empties
+ * the cache before it gives up.  A process should destroy its handles and
+ * call this before it exits: a HIP call made from a finaliser that runs
+ * after the runtime's own exit handlers is undefined. */
 void ilu_memory_trim(void);
 
 /* Message for the last error of the calling thread. */

@@ -7,8 +7,10 @@ device; the current torch stream is passed to every call.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -135,12 +137,31 @@ def _options(method=BJ, interior_fact=ILU0, interface_fact=ILU0, droptol=0.0, lf
                  pivot_tol, trsv_mode, factor_prec)
 
 
+# Every live handle, so that the exit hook below can release them while the
+# HIP runtime (and any profiler attached to it) is still up.
+_live: "weakref.WeakSet[Precond]" = weakref.WeakSet()
+
+
+@atexit.register
+def _release_at_exit():
+    """Destroy live handles and return the library's cached device blocks before
+    interpreter teardown, so no HIP call runs from a finaliser after the
+    runtime's own exit handlers."""
+    if _lib is None:
+        return
+    for p in list(_live):
+        p.close()
+    _lib.ilu_kernel_timing(0)
+    _lib.ilu_memory_trim()
+
+
 class Precond:
     """Handle returned by ilu_setup; owns the device memory of the preconditioner."""
 
     def __init__(self, handle, n):
         self._h = handle
         self.n = n
+        _live.add(self)
 
     def __del__(self):
         self.close()

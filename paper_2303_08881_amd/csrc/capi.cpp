@@ -640,7 +640,7 @@ static int build_global(ilu_precond *P, Mem &tmp, Schedule &S, void *stmp, size_
 
 // FP32 / FP16 copy of a factor (and FP32 diagonal) for the level-scheduled
 // solve.
-static int build_lowp(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, hipStream_t s) {
+static int build_lowp(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, int64_t col_lim, hipStream_t s) {
   if (T.n == 0) return 0;
   Mem &mem = P->mem;
   const int prec = P->opt.factor_prec;
@@ -649,7 +649,7 @@ static int build_lowp(ilu_precond *P, Schedule &S, const Csr &T, const double *d
   S.v_lp = vbuf;
   if (diag) RC(mem.alloc(&S.diag_lp, T.n));
   if (prec == ILU_PREC_F16) RC(mem.alloc(&S.scale_lp, T.n));
-  return launch_lowp_factor(T.rp, T.v, T.n, prec, S.v_lp, S.scale_lp, diag, S.diag_lp, s);
+  return launch_lowp_factor(T.rp, T.ci, T.v, T.n, col_lim, prec, S.v_lp, S.scale_lp, diag, S.diag_lp, s);
 }
 
 // Block-local storage of one factor: rows sorted by (subdomain, level), the
@@ -775,21 +775,17 @@ static int build_block_flow(ilu_precond *P, Mem &tmp, void *stmp, size_t stmpb, 
   return 0;
 }
 
-// Algorithmic bytes of one triangular solve: every stored entry (column and
-// value), the row pointers and the level-ordered row list once, the right-hand
-// side read and the solution written once (plus the gather map, the diagonal
-// and the scatter when present).
-// Algorithmic bytes of one solve: each entry (column and value in the storage
-// precision), row pointers and row list, right-hand side and solution (FP64),
-// and the diagonal (and FP16 row scale) in the storage precision.
-static double trsv_bytes(const Schedule &S, const Csr &T, bool diag, bool bmap, bool scat, int prec = 0) {
-  const double n = (double)S.nrows;
+// Algorithmic bytes of one triangular solve, counted as the survey's
+// measurement table does: each strict-triangle entry once (int32 column and
+// the value in the storage precision), int32 row pointers, the right-hand
+// side read and the solution written once (FP64 vectors), and the diagonal
+// of an upper solve in the storage precision (FP64 8, FP32 4, FP16 2 bytes
+// per row).  Gather and scatter maps, the FP16 row scales and the layout's
+// padding are the kernel's own overheads, not algorithmic bytes.
+static double trsv_bytes(int64_t n, int64_t nnz, bool diag, int prec) {
   const double vb = prec == ILU_PREC_F64 ? 8.0 : prec == ILU_PREC_F32 ? 4.0 : 2.0;
-  double b = (4.0 + vb) * (double)T.nnz + 8.0 * (n + 1) + 4.0 * n + 8.0 * n + 8.0 * n;
-  if (prec == ILU_PREC_F16) b += 4.0 * n;
-  if (diag) b += (prec == ILU_PREC_F64 ? 8.0 : 4.0) * n;
-  if (bmap) b += 4.0 * n;
-  if (scat) b += 12.0 * n;
+  double b = (4.0 + vb) * (double)nnz + 4.0 * (double)(n + 1) + 16.0 * (double)n;
+  if (diag) b += vb * (double)n;
   return b;
 }
 
@@ -837,6 +833,7 @@ static TrsvLaunch make_launch(ilu_precond *P, Schedule &S, const Csr &T, const d
     t.nrows = S.nloc;
   }
   t.prec = P->opt.factor_prec;
+  t.f64_row = role == 0 ? P->nB : INT64_MAX;
   t.v_lp = S.v_lp;
   t.diag_lp = S.diag_lp;
   t.scale_lp = S.scale_lp;
@@ -849,7 +846,9 @@ static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, i
                 const std::function<int()> &after = nullptr) {
   if (S.nrows == 0) return 0;
   TrsvLaunch t = make_launch(P, S, T, diag, split, b, bmap, x, scat, smap, role);
-  const double bytes = trsv_bytes(S, T, diag != nullptr, bmap != nullptr, scat != nullptr, P->opt.factor_prec);
+  // the block-local U_B solve reads no Z entry (Z y is applied before it)
+  const int64_t nnz = T.nnz - (S.use_block && role == 1 ? P->Zb.nnz : 0);
+  const double bytes = trsv_bytes(S.nrows, nnz, diag != nullptr, P->opt.factor_prec);
   if (S.use_block) {
     if (bmap || scat) return fail(ILU_ERR_INVALID_ARG, "internal: block-local solves take no gather or scatter map");
     return timed(ILU_K_TRSV_LB + role, bytes, s, [&] {
@@ -875,8 +874,7 @@ static int trsv_schur(ilu_precond *P, const double *b, double *x, hipStream_t s)
     TrsvLaunch up = make_launch(P, P->sUS, P->US, P->DS, INT64_MAX, x, nullptr, x, nullptr, nullptr, 3);
     if (trsv_lds_pair_ok(lo, up)) {
       const int fp = P->opt.factor_prec;
-      const double bytes =
-          trsv_bytes(P->sLS, P->LS, false, false, false, fp) + trsv_bytes(P->sUS, P->US, true, false, false, fp);
+      const double bytes = trsv_bytes(P->sLS.nrows, P->LS.nnz, false, fp) + trsv_bytes(P->sUS.nrows, P->US.nnz, true, fp);
       return timed(ILU_K_TRSV_LS, bytes, s, [&] { return launch_trsv_lds_pair(lo, up, s); });
     }
   }
@@ -884,8 +882,10 @@ static int trsv_schur(ilu_precond *P, const double *b, double *x, hipStream_t s)
   return trsv(P, P->sUS, P->US, P->DS, INT64_MAX, x, nullptr, x, nullptr, nullptr, s, 3);
 }
 
+// Algorithmic bytes of one SpMV: 12 per entry, int32 row pointers, x and y
+// once each (and b for the residual form).
 static double spmv_bytes(int64_t n, int64_t nnz, bool resid) {
-  return 12.0 * (double)nnz + 8.0 * (double)(n + 1) + 16.0 * (double)n + (resid ? 8.0 * (double)n : 0.0);
+  return 12.0 * (double)nnz + 4.0 * (double)(n + 1) + 16.0 * (double)n + (resid ? 8.0 * (double)n : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1086,10 +1086,10 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
     RC(build_global(P, tmp, P->sLS, stmp, stmpb, s));
     RC(build_global(P, tmp, P->sUS, stmp, stmpb, s));
     if (P->opt.factor_prec != ILU_PREC_F64) {
-      RC(build_lowp(P, P->sL1, P->L1, nullptr, s));
-      RC(build_lowp(P, P->sU1, P->U1, P->DB, s));
-      RC(build_lowp(P, P->sLS, P->LS, nullptr, s));
-      RC(build_lowp(P, P->sUS, P->US, P->DS, s));
+      RC(build_lowp(P, P->sL1, P->L1, nullptr, INT64_MAX, s));
+      RC(build_lowp(P, P->sU1, P->U1, P->DB, nB, s));
+      RC(build_lowp(P, P->sLS, P->LS, nullptr, INT64_MAX, s));
+      RC(build_lowp(P, P->sUS, P->US, P->DS, INT64_MAX, s));
     }
   } else {
     RC(build_block(P, tmp, P->L1, P->sL1, bs_int, bs_ifc, nB, nullptr, INT64_MAX, nullptr, s, "levels L"));
@@ -1201,7 +1201,7 @@ static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t 
   const Csr &C = P->block_mode ? P->Coffr : P->Coff;
   // C_off v_0; later products come with the normalisation of the step before
   RC(timed(ILU_K_SPMV_COFF, spmv_bytes(nS, C.nnz, false), s,
-           [&] { return launch_spmv(C.rp, C.ci, C.v, nS, V, P->it1, s); }));
+           [&] { return launch_spmv(C.rp, C.ci, C.v, nS, V, P->it1, s, SPMV_COFF); }));
   double *w = P->iW;  // the new direction, orthogonalised apart from the basis
   for (int j = 0; j < k; j++) {
     double *vj = V + (int64_t)j * nS, *vn = V + (int64_t)(j + 1) * nS;
@@ -1289,28 +1289,42 @@ static int read_scalars(ilu_precond *P, const double *d, int cnt, hipStream_t s)
   return 0;
 }
 
+// Krylov workspace of FGMRES(m) on vectors of length n; n and m are set
+// last, so a partly built workspace never passes for a complete one.
+static int gmres_work_alloc(GmresWork &w, int64_t n, int m) {
+  RC(w.mem.alloc(&w.V, (int64_t)(m + 1) * n));
+  RC(w.mem.alloc(&w.Zb, (int64_t)m * n));
+  RC(w.mem.alloc(&w.r, n));
+  RC(w.mem.alloc(&w.H, (int64_t)(m + 1) * (m + 1)));
+  RC(w.mem.alloc(&w.cs, m + 1));
+  RC(w.mem.alloc(&w.sn, m + 1));
+  RC(w.mem.alloc(&w.g, m + 2));
+  RC(w.mem.alloc(&w.c, m + 1));
+  RC(w.mem.alloc(&w.pa, RED_BLOCKS));
+  RC(w.mem.alloc(&w.pb, RED_BLOCKS));
+  RC(w.mem.alloc(&w.scal, 8));
+  RC(w.mem.alloc(&w.flags, 4));
+  for (hipEvent_t &e : w.ev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  w.n = n;
+  w.m = m;
+  return 0;
+}
+
 static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, double *x, double rtol, int m, int maxit,
                        hipStream_t s, ilu_result_t *res, double *hist) {
   const int64_t n = A->n;
   if (!P->gw || P->gw->n != n || P->gw->m != m) {
+    // The sizes are recorded only once every buffer and event exists: a
+    // workspace left behind by a failed allocation is dropped, never reused.
     delete P->gw;
-    P->gw = new GmresWork();
-    GmresWork &w = *P->gw;
-    w.n = n;
-    w.m = m;
-    RC(w.mem.alloc(&w.V, (int64_t)(m + 1) * n));
-    RC(w.mem.alloc(&w.Zb, (int64_t)m * n));
-    RC(w.mem.alloc(&w.r, n));
-    RC(w.mem.alloc(&w.H, (int64_t)(m + 1) * (m + 1)));
-    RC(w.mem.alloc(&w.cs, m + 1));
-    RC(w.mem.alloc(&w.sn, m + 1));
-    RC(w.mem.alloc(&w.g, m + 2));
-    RC(w.mem.alloc(&w.c, m + 1));
-    RC(w.mem.alloc(&w.pa, RED_BLOCKS));
-    RC(w.mem.alloc(&w.pb, RED_BLOCKS));
-    RC(w.mem.alloc(&w.scal, 8));
-    RC(w.mem.alloc(&w.flags, 4));
-    for (hipEvent_t &e : w.ev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    P->gw = nullptr;
+    GmresWork *nw = new GmresWork();
+    const int rc = gmres_work_alloc(*nw, n, m);
+    if (rc) {
+      delete nw;
+      return rc;
+    }
+    P->gw = nw;
   }
   GmresWork &w = *P->gw;
   double *bnorm = w.scal, *beta = w.scal + 1, *hn = w.scal + 2, *est = w.scal + 3;
@@ -1367,7 +1381,7 @@ static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, doub
         if (its + (pending >= 0 ? 1 : 0) >= maxit) break;
         double *vj = w.V + (int64_t)j * n, *wv = w.V + (int64_t)(j + 1) * n, *zj = w.Zb + (int64_t)j * n;
         RC(apply_impl(P, vj, zj, s));
-        RC(timed(ILU_K_SPMV, spmv_bytes(n, A->nnz, false), s, [&] { return launch_spmv(rp, ci, av, n, zj, wv, s); }));
+        RC(timed(ILU_K_SPMV, spmv_bytes(n, A->nnz, false), s, [&] { return launch_spmv(rp, ci, av, n, zj, wv, s, SPMV_A); }));
         double *pc = w.pa, *pn = w.pb;
         RC(launch_dot_partial(wv, w.V, n, pc, s));
         for (int i = 0; i <= j; i++) {
@@ -1433,7 +1447,12 @@ int fgmres_solve(const ilu_csr_t *A, ilu_precond_t *P, const double *d_b, double
   return rc;
 }
 
-void ilu_memory_trim(void) { cache_trim(); }
+void ilu_memory_trim(void) {
+  timing_collect();
+  for (hipEvent_t e : g_event_pool) (void)hipEventDestroy(e);
+  g_event_pool.clear();
+  cache_trim();
+}
 
 void ilu_kernel_timing(int32_t classes) {
   if (!classes) timing_collect();

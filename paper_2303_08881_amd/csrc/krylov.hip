@@ -51,6 +51,8 @@ __device__ __forceinline__ double row_dot(const int32_t *__restrict__ ci, const 
   return s;
 }
 
+// TAG only names the instance (SpmvTag): the same code for A and C_off
+template <int TAG>
 __global__ void k_spmv(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ v,
                        int64_t n, const double *__restrict__ x, double *__restrict__ y) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -67,9 +69,15 @@ __global__ void k_residual(const int64_t *__restrict__ rp, const int32_t *__rest
 }
 
 int launch_spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x, double *y,
-                hipStream_t s) {
+                hipStream_t s, SpmvTag tag) {
   if (n == 0) return 0;
-  k_spmv<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, v, n, x, y);
+  const unsigned g = (unsigned)((n + 255) / 256);
+  if (tag == SPMV_A)
+    k_spmv<SPMV_A><<<g, 256, 0, s>>>(rp, ci, v, n, x, y);
+  else if (tag == SPMV_COFF)
+    k_spmv<SPMV_COFF><<<g, 256, 0, s>>>(rp, ci, v, n, x, y);
+  else
+    k_spmv<SPMV_USER><<<g, 256, 0, s>>>(rp, ci, v, n, x, y);
   return check_launch("spmv");
 }
 

@@ -153,13 +153,14 @@ struct TrsvLaunch {
   const void *v_lp;
   const float *diag_lp;
   const float *scale_lp;
+  int64_t f64_row = INT64_MAX;  // level-scheduled lower solve: rows from here on (W) stay FP64
 };
 int launch_trsv(const TrsvLaunch &t, hipStream_t s);
 // FP32 / FP16 copies of a factor's values (and FP32 diagonal) for the
-// level-scheduled solve; prec 1 FP32, 2 FP16 divided by the row's largest
-// magnitude (scale[n] receives it)
-int launch_lowp_factor(const int64_t *rp, const double *v, int64_t n, int prec, void *out, float *scale,
-                       const double *diag, float *diag_out, hipStream_t s);
+// level-scheduled solve; prec 1 FP32, 2 FP16 divided by the largest
+// magnitude of the row's entries in columns < col_lim (scale[n] receives it)
+int launch_lowp_factor(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, int64_t col_lim, int prec,
+                       void *out, float *scale, const double *diag, float *diag_out, hipStream_t s);
 int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s);
 // the block-local L_S and U_S solves of each subdomain in one launch, when
 // both have the same lane shape (trsv_lds_pair_ok)
@@ -202,8 +203,11 @@ int launch_block_level_keys(const int32_t *level, const int32_t *blk, int64_t n,
 int launch_i64_to_i32(const int64_t *in, int32_t *out, int64_t n, hipStream_t s);
 
 // ---- krylov.hip ----
+// kernel instance of a product, so that profilers report the outer matrix and
+// the reduced system's coupling apart
+enum SpmvTag { SPMV_A = 0, SPMV_COFF = 1, SPMV_USER = 2 };
 int launch_spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x, double *y,
-                hipStream_t s);
+                hipStream_t s, SpmvTag tag = SPMV_USER);
 int launch_residual(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
                     const double *x, double *r, hipStream_t s);
 constexpr int RED_BLOCKS = 512;  // most blocks (and partials) of the deterministic reductions

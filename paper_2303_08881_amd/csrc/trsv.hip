@@ -60,6 +60,7 @@ struct TrsvArgs {
   const void *v_lp;       // factor values in FP32 or FP16 (P > 0)
   const float *diag_lp;   // FP32 diagonal (P > 0)
   const float *scale_lp;  // FP16: per-row scale of the stored values
+  int64_t f64_row;        // P > 0: rows from here on (the W rows) are solved in FP64
 };
 
 // value p of the factor in the solve's arithmetic: FP64, FP32, or the FP16
@@ -105,24 +106,34 @@ __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
       fence_acquire();
     }
     if (valid) {
-      // FP16 storage: the scaled entries are summed first, then the sum
-      // times the row scale is subtracted from the right-hand side
-      A s = P == 2 ? A(0) : (A)rhs;
-      const A sg = P == 2 ? A(1) : A(-1);
       const bool diag = P == 0 ? a.diag != nullptr : a.diag_lp != nullptr;
-      if (diag) {
+      // The Z block of an upper solve (columns >= split) is applied first, in
+      // FP64 whatever the storage precision: only the triangular factors
+      // themselves are stored in lower precision.
+      double rz = rhs;
+      if (diag)
         for (int64_t p = rb; p < re; p++) {
           const int32_t c = a.ci[p];
-          if (c >= a.split_col) s = fma_t(sg * trsv_val<P>(a, p), (A)a.x[c], s);
+          if (c >= a.split_col) rz = fma(-a.v[p], a.x[c], rz);
         }
-        for (int64_t p = rb; p < re; p++) {
-          const int32_t c = a.ci[p];
-          if (c < a.split_col) s = fma_t(sg * trsv_val<P>(a, p), (A)a.x[c], s);
-        }
+      A s;
+      if (P != 0 && r >= a.f64_row) {
+        // rows of W (below the last triangular row of a lower solve) stay
+        // FP64 in every storage precision
+        double t = rz;
+        for (int64_t p = rb; p < re; p++) t = fma(-a.v[p], a.x[a.ci[p]], t);
+        s = (A)t;
       } else {
-        for (int64_t p = rb; p < re; p++) s = fma_t(sg * trsv_val<P>(a, p), (A)a.x[a.ci[p]], s);
+        // FP16 storage: the scaled entries are summed first, then the sum
+        // times the row scale is subtracted from the right-hand side
+        s = P == 2 ? A(0) : (A)rz;
+        const A sg = P == 2 ? A(1) : A(-1);
+        for (int64_t p = rb; p < re; p++) {
+          const int32_t c = a.ci[p];
+          if (!diag || c < a.split_col) s = fma_t(sg * trsv_val<P>(a, p), (A)a.x[c], s);
+        }
+        if constexpr (P == 2) s = fma_t(-a.scale_lp[r], s, (A)rz);
       }
-      if constexpr (P == 2) s = fma_t(-a.scale_lp[r], s, (A)rhs);
       if (diag) {
         if constexpr (P == 0)
           s = s / a.diag[r];
@@ -750,14 +761,15 @@ __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t
 // Factor values of the level-scheduled solve in FP32, or in FP16 divided by
 // the row's largest magnitude (the scale, rounded to FP32, is stored per row);
 // the diagonal (if any) in FP32.  One thread per row.
-__global__ void k_lowp_factor(const int64_t *rp, const double *v, int64_t n, int prec, void *out, float *scale,
-                              const double *diag, float *diag_out) {
+__global__ void k_lowp_factor(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, int64_t col_lim,
+                              int prec, void *out, float *scale, const double *diag, float *diag_out) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= n) return;
   double sc = 1.0;
   if (prec == 2) {
     double m = 0.0;
-    for (int64_t p = rp[r]; p < rp[r + 1]; p++) m = fmax(m, fabs(v[p]));
+    for (int64_t p = rp[r]; p < rp[r + 1]; p++)
+      if (ci[p] < col_lim) m = fmax(m, fabs(v[p]));
     if (m > 0.0) sc = (double)(float)m;
     scale[r] = (float)sc;
   }
@@ -770,10 +782,10 @@ __global__ void k_lowp_factor(const int64_t *rp, const double *v, int64_t n, int
   if (diag) diag_out[r] = (float)diag[r];
 }
 
-int launch_lowp_factor(const int64_t *rp, const double *v, int64_t n, int prec, void *out, float *scale,
-                       const double *diag, float *diag_out, hipStream_t s) {
+int launch_lowp_factor(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, int64_t col_lim, int prec,
+                       void *out, float *scale, const double *diag, float *diag_out, hipStream_t s) {
   if (n == 0) return 0;
-  k_lowp_factor<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, v, n, prec, out, scale, diag, diag_out);
+  k_lowp_factor<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, v, n, col_lim, prec, out, scale, diag, diag_out);
   return check_launch("lowp_factor");
 }
 
@@ -946,6 +958,7 @@ int launch_trsv(const TrsvLaunch &t, hipStream_t s) {
   a.v_lp = t.v_lp;
   a.diag_lp = t.prec != 0 && t.diag ? t.diag_lp : nullptr;
   a.scale_lp = t.scale_lp;
+  a.f64_row = t.f64_row;
   if (t.prec != 0 && (!t.v_lp || (t.diag && !t.diag_lp) || (t.prec == 2 && !t.scale_lp))) return ILU_ERR_INVALID_ARG;
   const int64_t grid = t.nchunks < t.max_waves ? t.nchunks : t.max_waves;
   const unsigned gr = (unsigned)grid;

@@ -3,12 +3,12 @@ import bench
 import synth
 
 
-def test_cpu_baseline_runs_the_oracle_with_gpu_options_present():
-    A, b, part, p = synth.workload("aniso2d_64")
-    opts = dict(bench.WORKLOADS["aniso2d_64"][1], factor_prec=1)
-    out = bench.cpu_baseline(A, b, None, 1, opts, 1e-8, 30, 20, 5)
-    assert out["kind"] == "oracle" and out["value"] > 0 and out["cores"] >= 1
-    assert "FGMRES iterations" in out["sample"]
+def test_cpu_baseline_runs_the_oracle_in_worker_processes():
+    # the oracle runs in child processes (one alone, then two at once), each on the bounded sample
+    out = bench.cpu_baseline("aniso2d_64", "f32", 20, 5, 2)
+    assert out["kind"] == "oracle" and out["cores"] == 2
+    assert out["value"] > out["one_core_value"] > 0
+    assert "FGMRES iterations" in out["sample"] and out["cpu_model"]
 
 
 def test_kernel_instance_names():
@@ -20,3 +20,5 @@ def test_kernel_instance_names():
     sched[17] = 1  # only L_B check-free
     assert bench.kernel_instance("trsv_LS", sched, 2) == "void silu::k_trsv_lds_pair<1, 2, 2, false>"
     assert bench.kernel_instance("mgs", sched) == "void silu::k_mgs_step<"
+    assert bench.kernel_instance("spmv_A", sched) == "void silu::k_spmv<0>"
+    assert bench.kernel_instance("spmv_Coff", sched) == "void silu::k_spmv<1>"
