@@ -239,6 +239,96 @@ int ilu_export(ilu_precond_t *P, int32_t what, void *h_buf, int64_t *len);
 void ilu_kernel_timing(int32_t classes);
 int ilu_kernel_stats(int32_t kind, double *total_ms, int64_t *launches, double *bytes, int32_t reset);
 
+/*
+ * ---- Batched systems (one persistent launch) ----
+ * Many independent systems A_k x_k = b_k, each preconditioned by its own
+ * ILU(0) and solved by right-preconditioned GMRES(m) to its own relative
+ * tolerance: the block-Jacobi view of Section 3.1 with every block a system
+ * of its own (own right-hand side, own convergence).  One workgroup takes
+ * one system whole, largest first; the ILU(0) factorization (Section 2.3) and
+ * the GMRES iterations of every system run in a single kernel launch, which
+ * needs no host synchronisation and can be captured in a HIP graph.
+ *
+ * The batch is given as one block-diagonal CSR: the rows of system k are
+ * [h_sys_row[k], h_sys_row[k+1]) and its columns must lie in the same range
+ * (global numbering).  Limits, checked at setup (ILU_ERR_CAPACITY): at most
+ * 16 entries per row and 4 strictly below (and above) the diagonal, at most
+ * 1024 levels per triangular factor of a system, and each dependency of a
+ * triangular row at most 2048 positions behind the end of the row's level
+ * in level order (any 2D/3D stencil of side <= 1000 qualifies).
+ */
+typedef struct ilu_batch ilu_batch_t;
+
+/*
+ * ilu_batch_setup -- analyse the pattern of the batch once: validate it, the
+ * levels of A's strict lower and upper parts in every system (as the
+ * single-system setup does, one segment per system), the level-sorted
+ * positions of both triangular solves, and the largest-first system order.
+ * The pattern is copied; values are passed to each solve.  restart: the
+ * largest GMRES restart that later solves may use (1..32), sizing the Krylov
+ * basis ((restart + 1) n doubles).  Synchronises `stream`.
+ */
+int ilu_batch_setup(const ilu_csr_t *A, const int64_t *h_sys_row, int32_t nsys, int32_t restart, void *stream,
+                    ilu_batch_t **B);
+
+/*
+ * ilu_batch_solve -- enqueue one persistent launch on `stream` (no host
+ * synchronisation, no allocation): for every system, the ILU(0) factors of
+ * the values d_val (nnz doubles on the setup's pattern), then GMRES(restart)
+ * from the initial guess in d_x (n doubles, overwritten by the solution) for
+ * the right-hand side d_b until ||b_k - A_k x_k|| <= rtol ||b_k|| or maxit
+ * Arnoldi steps.  Read the per-system outcome with ilu_batch_results.
+ */
+int ilu_batch_solve(ilu_batch_t *B, const double *d_val, const double *d_b, double *d_x, double rtol,
+                    int32_t restart, int32_t maxit, void *stream);
+
+/*
+ * ilu_batch_results -- synchronise `stream` and copy, per system: the
+ * iteration count (Arnoldi steps over all cycles), the true relative residual
+ * at exit, and the status (0 converged, ILU_NOT_CONVERGED, ILU_ERR_ZERO_PIVOT
+ * or ILU_ERR_BREAKDOWN).  Any pointer may be NULL.
+ */
+int ilu_batch_results(ilu_batch_t *B, int32_t *h_iters, double *h_relres, int32_t *h_status, void *stream);
+
+/*
+ * ilu_batch_schedule -- launch shape of later solves: levels of at most
+ * `merge` rows (0..64) run on one wavefront with a wavefront barrier instead
+ * of a workgroup barrier; `wpc` workgroups per CU stay resident (1 up to what
+ * the kernel's resources allow).  Neither changes any arithmetic: results
+ * are bit-identical for every schedule.
+ */
+int ilu_batch_schedule(ilu_batch_t *B, int32_t merge, int32_t wpc);
+
+/*
+ * ilu_batch_tune -- the autotuner: run one full solve per candidate schedule
+ * (merge in {0, 16, 32, 64}, every feasible wpc), timed with device events,
+ * and keep the fastest.  Overwrites d_x (which must hold the initial guess
+ * before each later solve).  Out: the chosen merge, wpc and its time (ms).
+ */
+int ilu_batch_tune(ilu_batch_t *B, const double *d_val, const double *d_b, double *d_x, double rtol,
+                   int32_t restart, int32_t maxit, void *stream, int32_t *h_merge, int32_t *h_wpc, double *h_ms);
+
+/*
+ * ilu_batch_capture / ilu_batch_replay -- capture one ilu_batch_solve with
+ * these arguments into a HIP graph kept in B (stream must not be the default
+ * stream), and launch that graph on `stream`.  A replay reads the values,
+ * right-hand sides and initial guess found at those addresses when it runs.
+ */
+int ilu_batch_capture(ilu_batch_t *B, const double *d_val, const double *d_b, double *d_x, double rtol,
+                      int32_t restart, int32_t maxit, void *stream);
+int ilu_batch_replay(ilu_batch_t *B, void *stream);
+
+/*
+ * ilu_batch_export -- for parity tests: 0 the factor values of the last
+ * solve on A's pattern [double nnz] (strict lower part L, diagonal and
+ * strict upper part of U), 1 the level of each row in L [int32 n], 2 in U
+ * [int32 n], 3 the schedule [int32 4]: entries per row and triangle, merge,
+ * workgroups per CU, grid.  Same buffer protocol as ilu_export.
+ */
+int ilu_batch_export(ilu_batch_t *B, int32_t what, void *h_buf, int64_t *len);
+
+void ilu_batch_destroy(ilu_batch_t *B);
+
 /* Sizes: n, n_B (interior rows), n_S (interface rows), nparts. */
 int ilu_info(ilu_precond_t *P, int64_t *n, int64_t *nB, int64_t *nS, int32_t *nparts);
 

@@ -15,7 +15,7 @@ import numpy as np
 from .build import LIB, build
 
 ILU0, MILU0, ILUT = 0, 1, 2
-BJ, SCHUR = 0, 1
+BJ, SCHUR, RAP = 0, 1, 2
 PIVOT_ERROR, PIVOT_PERTURB = 0, 1
 OK, NOT_CONVERGED = 0, 1
 ERR_INVALID_ARG, ERR_CSR, ERR_ZERO_PIVOT, ERR_OOM, ERR_BREAKDOWN = -1, -2, -3, -4, -6
@@ -34,7 +34,8 @@ class _CSR(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("interior_fact", C.c_int32), ("interface_fact", C.c_int32),
                 ("droptol", C.c_double), ("lfil", C.c_int32), ("inner_iters", C.c_int32),
-                ("inner_rtol", C.c_double), ("pivot_mode", C.c_int32), ("pivot_tol", C.c_double)]
+                ("inner_rtol", C.c_double), ("pivot_mode", C.c_int32), ("pivot_tol", C.c_double),
+                ("smooth_fact", C.c_int32)]
 
 
 class _Res(C.Structure):
@@ -67,7 +68,10 @@ def lib():
         L.orc_setup.argtypes = [vp, vp, i32, vp, C.POINTER(vp), C.POINTER(i64)]
         L.orc_apply.argtypes = [vp, vp, vp]
         L.orc_apply.restype = None
+        L.orc_rap_matvec.argtypes = [vp, vp, vp]
+        L.orc_rap_matvec.restype = None
         L.orc_fgmres.argtypes = [vp, vp, vp, vp, d, i32, i32, vp, vp]
+        L.orc_gmres.argtypes = [vp, vp, vp, vp, d, i32, i32, vp, vp]
         L.orc_free.argtypes = [vp]
         L.orc_free.restype = None
         L.orc_export.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(i64)]
@@ -96,10 +100,11 @@ class Options:
     inner_rtol: float = 0.0
     pivot_mode: int = PIVOT_ERROR
     pivot_tol: float = 0.0
+    smooth_fact: int = ILU0
 
     def c(self):
         return _Opts(self.method, self.interior_fact, self.interface_fact, self.droptol, self.lfil,
-                     self.inner_iters, self.inner_rtol, self.pivot_mode, self.pivot_tol)
+                     self.inner_iters, self.inner_rtol, self.pivot_mode, self.pivot_tol, self.smooth_fact)
 
 
 class _Mat:
@@ -235,6 +240,13 @@ class Precond:
         lib().orc_apply(self._h, _p(r), _p(z))
         return z
 
+    def rap_matvec(self, v):
+        """R A P v on the interface unknowns (multiplicative method only)."""
+        v = np.ascontiguousarray(v, np.float64)
+        out = np.empty(v.size)
+        lib().orc_rap_matvec(self._h, _p(v), _p(out))
+        return out
+
     def export(self, what):
         code = X[what] if isinstance(what, str) else what
         ptr, ln = C.c_void_p(), C.c_int64()
@@ -258,12 +270,22 @@ class Precond:
 
 
 def fgmres(A, P: Precond, b, x0=None, rtol=1e-8, restart=30, maxit=1000, history=False):
+    """Flexible GMRES(restart), right preconditioned (Section 4.1)."""
+    return _krylov(lib().orc_fgmres, A, P, b, x0, rtol, restart, maxit, history)
+
+
+def gmres(A, P: Precond, b, x0=None, rtol=1e-8, restart=20, maxit=1000, history=False):
+    """GMRES(restart), right preconditioned with the fixed P (the batched systems)."""
+    return _krylov(lib().orc_gmres, A, P, b, x0, rtol, restart, maxit, history)
+
+
+def _krylov(fn, A, P, b, x0, rtol, restart, maxit, history):
     m = _Mat(A)
     b = np.ascontiguousarray(b, np.float64)
     x = np.zeros(m.n) if x0 is None else np.array(x0, dtype=np.float64)
     res = _Res()
     hist = np.full(maxit + 1, np.nan) if history else None
-    rc = lib().orc_fgmres(m.ref, P._h, _p(b), _p(x), rtol, restart, maxit, C.byref(res), _p(hist))
+    rc = fn(m.ref, P._h, _p(b), _p(x), rtol, restart, maxit, C.byref(res), _p(hist))
     if rc < 0:
         raise OracleError(rc)
     out = dict(x=x, iterations=res.iterations, converged=bool(res.converged), relres=res.final_relres, rc=rc)

@@ -15,6 +15,12 @@
  *   Section 3.2, eq. (18)-(19)    reduced system preconditioned by the local
  *                                 Schur factors, solved by a few GMRES steps
  *   Section 4.1                   right-preconditioned flexible GMRES(m)
+ *   Section 2.2.3, Alg. 2         multiplicative two-level solve: smoother,
+ *                                 restriction R, coarse correction with
+ *                                 S = R A P, interpolation P
+ *   Section 3.3, eq. (20)-(29)    R = (-W L_B^-1, I), P = (-U_B^-1 Z; I) from
+ *                                 the (M)ILU(0) factors of each A_i, RAP
+ *                                 unformed, L_S U_S as its preconditioner
  *
  * Where the paper is silent this file reads it as follows:
  *  - a row is an interface row when it is coupled to another subdomain in
@@ -515,6 +521,10 @@ struct orc_precond {
   /* inner GMRES workspace */
   double *V, *H, *cs, *sn, *gg, *c;
   double *w1, *w2;
+  /* RAP: the smoother, the matrix, and work vectors */
+  orc_precond *smoother;
+  orc_csr A;
+  double *ru, *rw, *rx;
 };
 
 typedef struct {
@@ -573,6 +583,10 @@ void orc_free(orc_precond *P) {
   free(P->c);
   free(P->w1);
   free(P->w2);
+  orc_free(P->smoother);
+  free(P->ru);
+  free(P->rw);
+  free(P->rx);
   free(P);
 }
 
@@ -581,8 +595,9 @@ int orc_setup(const orc_csr *A, const int32_t *part_in, int32_t nparts, const or
   *out = NULL;
   int rc = orc_validate(A);
   if (rc) return rc;
-  if (!opt || nparts < 1 || (opt->method != ORC_BJ && opt->method != ORC_SCHUR)) return ORC_ERR_INVALID_ARG;
-  if (opt->method == ORC_SCHUR && opt->inner_iters < 0) return ORC_ERR_INVALID_ARG;
+  if (!opt || nparts < 1 || (opt->method != ORC_BJ && opt->method != ORC_SCHUR && opt->method != ORC_RAP))
+    return ORC_ERR_INVALID_ARG;
+  if (opt->method != ORC_BJ && opt->inner_iters < 0) return ORC_ERR_INVALID_ARG;
   const int64_t n = A->n;
   orc_precond *P = (orc_precond *)calloc(1, sizeof(orc_precond));
   if (!P) return ORC_ERR_OOM;
@@ -700,7 +715,7 @@ int orc_setup(const orc_csr *A, const int32_t *part_in, int32_t nparts, const or
   orc_levels(nS, P->US.rp, P->US.ci, 0, 0, nS, P->lev_us);
 
   {
-    const int64_t k = schur ? opt->inner_iters : 0;
+    const int64_t k = opt->method != ORC_BJ ? opt->inner_iters : 0;
     P->f = (double *)malloc(sizeof(double) * (size_t)(nB + 1));
     P->g = (double *)malloc(sizeof(double) * (size_t)(nS + 1));
     P->t = (double *)malloc(sizeof(double) * (size_t)(nS + 1));
@@ -715,6 +730,23 @@ int orc_setup(const orc_csr *A, const int32_t *part_in, int32_t nparts, const or
     P->w2 = (double *)malloc(sizeof(double) * (size_t)(nS + 1));
     if (!P->f || !P->g || !P->t || !P->y || !P->V || !P->H || !P->cs || !P->sn || !P->gg || !P->c || !P->w1 ||
         !P->w2) {
+      rc = ORC_ERR_OOM;
+      goto fail;
+    }
+  }
+  if (opt->method == ORC_RAP) {
+    /* the multiplicative method: the factors above (block-Jacobi form of each
+     * A_i with interior_fact) give L_B, U_B, W, Z, L_S and U_S; the smoother is
+     * a second block-Jacobi factorization with smooth_fact */
+    orc_options so = *opt;
+    so.method = ORC_BJ;
+    so.interior_fact = opt->smooth_fact;
+    if ((rc = orc_setup(A, part_in, nparts, &so, &P->smoother, bad_row))) goto fail;
+    P->A = *A;
+    P->ru = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    P->rw = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    P->rx = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    if (!P->ru || !P->rw || !P->rx) {
       rc = ORC_ERR_OOM;
       goto fail;
     }
@@ -762,10 +794,48 @@ static void givens(double a, double b, double *c, double *s, double *r) {
   *s = b / rr;
 }
 
-/* k steps of GMRES (zero initial guess, modified Gram-Schmidt, Givens) on
- * (I + D^{-1} C_off) y = D^{-1} g'.  Stops early only on an exact breakdown
- * or when |g_{j+1}| <= inner_rtol * ||rhs||. */
-static void inner_gmres(orc_precond *P, const double *gp, double *y) {
+/* out = R A P v for an interface vector v: P v = (-U_B^{-1} Z v; v), one
+ * product with A in the original numbering, then R w = w_S - W L_B^{-1} w_B
+ * (Section 3.3, eq. (21) and (28)); R, P and RAP stay unformed. */
+void orc_rap_matvec(orc_precond *P, const double *v, double *out) {
+  const int64_t n = P->n, nB = P->nB, nS = P->nS;
+  double *t = P->f, *u = P->ru, *w = P->rw;
+  for (int64_t i = 0; i < nB; i++) { /* t = -Z v */
+    double s = 0.0;
+    for (int64_t p = P->Z.rp[i]; p < P->Z.rp[i + 1]; p++) s = fma(-P->Z.v[p], v[P->Z.ci[p] - nB], s);
+    t[i] = s;
+  }
+  trsv_upper(&P->UB, P->DB, t, t); /* y_B = -U_B^{-1} Z v */
+  for (int64_t i = 0; i < nB; i++) u[P->perm[i]] = t[i];
+  for (int64_t i = 0; i < nS; i++) u[P->perm[nB + i]] = v[i];
+  orc_spmv(&P->A, u, w);
+  for (int64_t i = 0; i < nB; i++) t[i] = w[P->perm[i]];
+  trsv_lower_unit(&P->LB, t, t);
+  for (int64_t i = 0; i < nS; i++) {
+    double s = w[P->perm[nB + i]];
+    for (int64_t p = P->W.rp[i]; p < P->W.rp[i + 1]; p++) s = fma(-P->W.v[p], t[P->W.ci[p]], s);
+    out[i] = s;
+  }
+  (void)n;
+}
+
+/* the reduced operator of the multiplicative method, preconditioned by the
+ * local Schur factors: y = (L_S U_S)^{-1} R A P v */
+static void rap_op(orc_precond *P, const double *v, double *y) {
+  orc_rap_matvec(P, v, P->w1);
+  schur_factor_solve(P, P->w1, y);
+}
+
+/* y = v + D^{-1} C_off v for the additive method */
+static void schur_op(orc_precond *P, const double *v, double *y) { reduced_matvec(P, v, y); }
+
+/* k steps of GMRES (zero initial guess, modified Gram-Schmidt, Givens) on the
+ * left-preconditioned reduced system op(y) = D^{-1} g': op is
+ * I + D^{-1} C_off for the additive method (eq. (18)) and D^{-1} R A P for the
+ * multiplicative one.  Stops early only on an exact breakdown or when
+ * |g_{j+1}| <= inner_rtol * ||rhs||. */
+static void inner_gmres(orc_precond *P, const double *gp, double *y,
+                        void (*op)(orc_precond *, const double *, double *)) {
   const int64_t nS = P->nS;
   const int32_t k = P->opt.inner_iters;
   double *V = P->V, *H = P->H;
@@ -783,7 +853,7 @@ static void inner_gmres(orc_precond *P, const double *gp, double *y) {
   int32_t m = 0;
   for (int32_t j = 0; j < k; j++) {
     double *w = V + (int64_t)(j + 1) * nS;
-    reduced_matvec(P, V + (int64_t)j * nS, w);
+    op(P, V + (int64_t)j * nS, w);
     for (int32_t i = 0; i <= j; i++) {
       double h = dot(nS, w, V + (int64_t)i * nS);
       H[i + ldh * j] = h;
@@ -819,9 +889,41 @@ static void inner_gmres(orc_precond *P, const double *gp, double *y) {
   }
 }
 
+/* Multiplicative two-level solve (Alg. 2; the GPU form of Section 3.3):
+ * x = smoother(r); res = r - A x; the restriction g = res_S - W L_B^{-1} res_B;
+ * v from k GMRES steps on (L_S U_S)^{-1} R A P v = (L_S U_S)^{-1} g; then the
+ * interpolation z = x + P v = x + (-U_B^{-1} Z v; v). */
+static void rap_apply(orc_precond *P, const double *r, double *z) {
+  const int64_t n = P->n, nB = P->nB, nS = P->nS;
+  double *f = P->f, *g = P->g, *y = P->y, *x = P->rx, *res = P->rw;
+  orc_apply(P->smoother, r, x);
+  orc_residual(&P->A, r, x, res);
+  for (int64_t i = 0; i < nB; i++) f[i] = res[P->perm[i]];
+  trsv_lower_unit(&P->LB, f, f);
+  for (int64_t i = 0; i < nS; i++) {
+    double s = res[P->perm[nB + i]];
+    for (int64_t p = P->W.rp[i]; p < P->W.rp[i + 1]; p++) s = fma(-P->W.v[p], f[P->W.ci[p]], s);
+    g[i] = s;
+  }
+  inner_gmres(P, g, y, rap_op);
+  for (int64_t i = 0; i < nB; i++) { /* f = -Z v */
+    double s = 0.0;
+    for (int64_t p = P->Z.rp[i]; p < P->Z.rp[i + 1]; p++) s = fma(-P->Z.v[p], y[P->Z.ci[p] - nB], s);
+    f[i] = s;
+  }
+  trsv_upper(&P->UB, P->DB, f, f);
+  for (int64_t i = 0; i < nB; i++) z[P->perm[i]] = x[P->perm[i]] + f[i];
+  for (int64_t i = 0; i < nS; i++) z[P->perm[nB + i]] = x[P->perm[nB + i]] + y[i];
+  (void)n;
+}
+
 void orc_apply(orc_precond *P, const double *r, double *z) {
   const int64_t nB = P->nB, nS = P->nS;
   double *f = P->f, *g = P->g, *y = P->y;
+  if (P->opt.method == ORC_RAP) {
+    rap_apply(P, r, z);
+    return;
+  }
   for (int64_t i = 0; i < nB; i++) f[i] = r[P->perm[i]];
   for (int64_t i = 0; i < nS; i++) g[i] = r[P->perm[nB + i]];
   trsv_lower_unit(&P->LB, f, f); /* f' = L_B^{-1} f */
@@ -831,7 +933,7 @@ void orc_apply(orc_precond *P, const double *r, double *z) {
     g[i] = s;
   }
   if (P->opt.method == ORC_SCHUR)
-    inner_gmres(P, g, y);
+    inner_gmres(P, g, y, schur_op);
   else
     schur_factor_solve(P, g, y);
   for (int64_t i = 0; i < nB; i++) { /* f'' = f' - Z y */
@@ -1000,5 +1102,140 @@ out:
   free(g);
   free(c);
   free(r);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* GMRES(m), right preconditioned, with a fixed preconditioner               */
+/* ------------------------------------------------------------------------ */
+/* The batched systems use plain GMRES: the Arnoldi process runs on A M^{-1}
+ * (w = A (M^{-1} v_j)), only the basis V is kept, and at the end of a cycle
+ * the correction is x += M^{-1} (V c) -- one more preconditioner solve per
+ * cycle instead of m stored preconditioned vectors.  Orthogonalization,
+ * rotations, the convergence test and the iteration count are those of the
+ * flexible variant above. */
+int orc_gmres(const orc_csr *A, orc_precond *P, const double *b, double *x, double rtol, int32_t restart,
+              int32_t maxit, orc_result *res, double *hist) {
+  const int64_t n = A->n;
+  if (restart < 1 || maxit < 0 || rtol < 0) return ORC_ERR_INVALID_ARG;
+  const int32_t m = restart;
+  double *V = (double *)malloc(sizeof(double) * (size_t)((m + 1) * n + 1));
+  double *H = (double *)calloc((size_t)((m + 1) * (m + 1)), sizeof(double));
+  double *cs = (double *)malloc(sizeof(double) * (size_t)(m + 1));
+  double *sn = (double *)malloc(sizeof(double) * (size_t)(m + 1));
+  double *g = (double *)malloc(sizeof(double) * (size_t)(m + 2));
+  double *c = (double *)malloc(sizeof(double) * (size_t)(m + 1));
+  double *r = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+  double *z = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+  double *u = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+  int rc = ORC_OK;
+  if (!V || !H || !cs || !sn || !g || !c || !r || !z || !u) {
+    rc = ORC_ERR_OOM;
+    goto out;
+  }
+  const int64_t ldh = m + 1;
+  const double bnorm = nrm2(n, b);
+  int32_t its = 0;
+  int converged = 0;
+  double relres = 0.0;
+  if (bnorm == 0.0) {
+    for (int64_t i = 0; i < n; i++) x[i] = 0.0;
+    converged = 1;
+    if (hist) hist[0] = 0.0;
+    goto finish;
+  }
+  orc_residual(A, b, x, r);
+  double beta = nrm2(n, r);
+  relres = beta / bnorm;
+  if (hist) hist[0] = relres;
+  if (!isfinite(beta)) {
+    rc = ORC_ERR_BREAKDOWN;
+    goto out;
+  }
+  if (beta <= rtol * bnorm) {
+    converged = 1;
+    goto finish;
+  }
+  while (its < maxit) {
+    for (int64_t i = 0; i < n; i++) V[i] = r[i] / beta;
+    g[0] = beta;
+    int32_t jm = 0;
+    int stop = 0;
+    for (int32_t j = 0; j < m && !stop; j++) {
+      double *w = V + (int64_t)(j + 1) * n;
+      orc_apply(P, V + (int64_t)j * n, z); /* z = M^{-1} v_j */
+      orc_spmv(A, z, w);                   /* w = A z */
+      for (int32_t i = 0; i <= j; i++) {
+        double h = dot(n, w, V + (int64_t)i * n);
+        H[i + ldh * j] = h;
+        const double *vi = V + (int64_t)i * n;
+        for (int64_t l = 0; l < n; l++) w[l] = fma(-h, vi[l], w[l]);
+      }
+      double hn = nrm2(n, w);
+      H[(j + 1) + ldh * j] = hn;
+      for (int32_t i = 0; i < j; i++) {
+        double a = H[i + ldh * j], bb = H[(i + 1) + ldh * j];
+        H[i + ldh * j] = fma(cs[i], a, sn[i] * bb);
+        H[(i + 1) + ldh * j] = fma(-sn[i], a, cs[i] * bb);
+      }
+      double rr;
+      givens(H[j + ldh * j], H[(j + 1) + ldh * j], &cs[j], &sn[j], &rr);
+      H[j + ldh * j] = rr;
+      H[(j + 1) + ldh * j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      its++;
+      jm = j + 1;
+      if (!isfinite(hn) || !isfinite(g[j + 1])) {
+        rc = ORC_ERR_BREAKDOWN;
+        goto out;
+      }
+      if (hist) hist[its] = fabs(g[j + 1]) / bnorm;
+      if (hn == 0.0) stop = 1;
+      else
+        for (int64_t l = 0; l < n; l++) w[l] = w[l] / hn;
+      if (fabs(g[j + 1]) <= rtol * bnorm || its >= maxit) stop = 1;
+    }
+    for (int32_t i = jm - 1; i >= 0; i--) {
+      double s = g[i];
+      for (int32_t l = i + 1; l < jm; l++) s = fma(-H[i + ldh * l], c[l], s);
+      c[i] = s / H[i + ldh * i];
+    }
+    for (int64_t l = 0; l < n; l++) u[l] = 0.0; /* u = V c, then x += M^{-1} u */
+    for (int32_t i = 0; i < jm; i++) {
+      const double *vi = V + (int64_t)i * n;
+      for (int64_t l = 0; l < n; l++) u[l] = fma(c[i], vi[l], u[l]);
+    }
+    orc_apply(P, u, z);
+    for (int64_t l = 0; l < n; l++) x[l] = x[l] + z[l];
+    orc_residual(A, b, x, r);
+    beta = nrm2(n, r);
+    relres = beta / bnorm;
+    if (!isfinite(beta)) {
+      rc = ORC_ERR_BREAKDOWN;
+      goto out;
+    }
+    if (beta <= rtol * bnorm) {
+      converged = 1;
+      break;
+    }
+  }
+finish:
+  if (res) {
+    res->iterations = its;
+    res->converged = converged;
+    res->final_relres = relres;
+  }
+  rc = converged ? ORC_OK : ORC_NOT_CONVERGED;
+out:
+  free(V);
+  free(H);
+  free(cs);
+  free(sn);
+  free(g);
+  free(c);
+  free(r);
+  free(z);
+  free(u);
   return rc;
 }

@@ -32,7 +32,7 @@ enum {
   ORC_ERR_BREAKDOWN = -6
 };
 
-enum { ORC_BJ = 0, ORC_SCHUR = 1 };
+enum { ORC_BJ = 0, ORC_SCHUR = 1, ORC_RAP = 2 };
 enum { ORC_ILU0 = 0, ORC_MILU0 = 1, ORC_ILUT = 2 };
 enum { ORC_PIVOT_ERROR = 0, ORC_PIVOT_PERTURB = 1 };
 
@@ -54,6 +54,8 @@ typedef struct {
   double inner_rtol;      /* SCHUR: early exit of the inner GMRES (0 = never) */
   int32_t pivot_mode;
   double pivot_tol;
+  int32_t smooth_fact;    /* RAP only: factor of the smoother (ILU(0) in the paper); the coarse
+                             factors R, P and L_S U_S come from interior_fact */
 } orc_options;
 
 typedef struct {
@@ -94,8 +96,15 @@ void orc_fact_free(orc_fact *F);
 int orc_setup(const orc_csr *A, const int32_t *part, int32_t nparts, const orc_options *opt,
               orc_precond **P, int64_t *bad_row);
 void orc_apply(orc_precond *P, const double *r, double *z);
+/* RAP only: out = R A P v for an interface vector v (local interface numbering),
+ * unformed: -U_B^{-1} Z v, one SpMV with A, L_B^{-1} and W (exposed for pins). */
+void orc_rap_matvec(orc_precond *P, const double *v, double *out);
 int orc_fgmres(const orc_csr *A, orc_precond *P, const double *b, double *x, double rtol,
                int32_t restart, int32_t maxit, orc_result *res, double *hist /* maxit+1 or NULL */);
+/* GMRES(m) right preconditioned with a fixed M: Arnoldi on A M^{-1}, only V
+ * kept, x += M^{-1} (V c) at the end of each cycle (the batched systems). */
+int orc_gmres(const orc_csr *A, orc_precond *P, const double *b, double *x, double rtol, int32_t restart,
+              int32_t maxit, orc_result *res, double *hist /* maxit+1 or NULL */);
 void orc_free(orc_precond *P);
 /* Internal arrays for parity tests; see the ORC_X_* codes. */
 int orc_export(const orc_precond *P, int32_t what, const void **ptr, int64_t *len);

@@ -21,12 +21,16 @@ from .binding import (  # noqa: F401
     PREC_F64,
     PREC_F32,
     PREC_F16,
+    OK,
+    NOT_CONVERGED,
     SchurILUError,
     DeviceCSR,
     Precond,
     setup,
     fgmres,
     spmv,
+    Batch,
+    batch_setup,
     memory_trim,
     lib,
     LIB_PATH,

@@ -84,6 +84,17 @@ def lib():
         L.ilu_kernel_timing.argtypes = [i32]
         L.ilu_kernel_timing.restype = None
         L.ilu_kernel_stats.argtypes = [i32, C.POINTER(d), C.POINTER(i64), C.POINTER(d), i32]
+        L.ilu_batch_setup.argtypes = [vp, vp, i32, i32, vp, C.POINTER(vp)]
+        L.ilu_batch_solve.argtypes = [vp, vp, vp, vp, d, i32, i32, vp]
+        L.ilu_batch_results.argtypes = [vp, vp, vp, vp, vp]
+        L.ilu_batch_schedule.argtypes = [vp, i32, i32]
+        L.ilu_batch_tune.argtypes = [vp, vp, vp, vp, d, i32, i32, vp, C.POINTER(i32), C.POINTER(i32),
+                                     C.POINTER(d)]
+        L.ilu_batch_capture.argtypes = [vp, vp, vp, vp, d, i32, i32, vp]
+        L.ilu_batch_replay.argtypes = [vp, vp]
+        L.ilu_batch_export.argtypes = [vp, i32, vp, C.POINTER(i64)]
+        L.ilu_batch_destroy.argtypes = [vp]
+        L.ilu_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -140,6 +151,7 @@ def _options(method=BJ, interior_fact=ILU0, interface_fact=ILU0, droptol=0.0, lf
 # Every live handle, so that the exit hook below can release them while the
 # HIP runtime (and any profiler attached to it) is still up.
 _live: "weakref.WeakSet[Precond]" = weakref.WeakSet()
+_live_batches: "weakref.WeakSet[Batch]" = weakref.WeakSet()
 
 
 @atexit.register
@@ -149,7 +161,7 @@ def _release_at_exit():
     runtime's own exit handlers."""
     if _lib is None:
         return
-    for p in list(_live):
+    for p in list(_live) + list(_live_batches):
         p.close()
     _lib.ilu_kernel_timing(0)
     _lib.ilu_memory_trim()
@@ -213,15 +225,22 @@ def setup(A: DeviceCSR, part=None, nparts=1, **opts) -> Precond:
     return Precond(h, A.n)
 
 
-def fgmres(A: DeviceCSR, P: Precond, b, x0=None, rtol=1e-8, restart=30, maxit=1000, history=False):
-    """fgmres_solve: right-preconditioned FGMRES(restart); returns a dict."""
+def fgmres(A: DeviceCSR, P: Precond, b, x0=None, rtol=1e-8, restart=30, maxit=1000, history=False, x=None):
+    """fgmres_solve: right-preconditioned FGMRES(restart); returns a dict.  A given x holds x0 on entry (unless x0
+    is passed too) and receives the solution."""
+    return _fgmres(lib().fgmres_solve, A, P, b, x0, rtol, restart, maxit, history, x)
+
+
+def _fgmres(fn, A, P, b, x0, rtol, restart, maxit, history, x):
     torch = _torch()
-    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    if x is None:
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+    elif x0 is not None:
+        x.copy_(x0)
     res = _Res()
     hist = np.full(maxit + 1, np.nan) if history else None
     hp = hist.ctypes.data_as(C.c_void_p) if history else None
-    rc = lib().fgmres_solve(A.ref, P._h, _ptr(b), _ptr(x), float(rtol), int(restart), int(maxit), _stream(),
-                            C.byref(res), hp)
+    rc = fn(A.ref, P._h, _ptr(b), _ptr(x), float(rtol), int(restart), int(maxit), _stream(), C.byref(res), hp)
     _check(rc, allow_not_converged=True)
     out = dict(x=x, iterations=res.iterations, converged=bool(res.converged), relres=res.final_relres,
                setup_ms=res.setup_ms, solve_ms=res.solve_ms, rc=rc)
@@ -237,6 +256,74 @@ def spmv(A: DeviceCSR, x, y=None):
         y = torch.empty_like(x)
     _check(lib().csr_spmv(A.ref, _ptr(x), _ptr(y), _stream()))
     return y
+
+
+class Batch:
+    """Handle of ilu_batch_setup: many independent systems, ILU(0) + GMRES(m) each, solved in one persistent
+    launch.  Arguments of solve / tune / capture are device tensors on the setup's pattern."""
+
+    def __init__(self, handle, n, nnz, nsys):
+        self._h = handle
+        self.n, self.nnz, self.nsys = n, nnz, nsys
+        _live_batches.add(self)
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ilu_batch_destroy(self._h)
+        self._h = None
+
+    def solve(self, val, b, x, rtol=1e-8, restart=20, maxit=1000):
+        """ilu_batch_solve: enqueue the factor + solve launch (x: initial guess in, solution out)."""
+        _check(lib().ilu_batch_solve(self._h, _ptr(val), _ptr(b), _ptr(x), float(rtol), int(restart), int(maxit),
+                                     _stream()))
+
+    def results(self):
+        """ilu_batch_results: (iterations, relres, status) per system, after the stream has finished."""
+        it = np.zeros(self.nsys, np.int32)
+        rr = np.zeros(self.nsys, np.float64)
+        st = np.zeros(self.nsys, np.int32)
+        _check(lib().ilu_batch_results(self._h, it.ctypes.data_as(C.c_void_p), rr.ctypes.data_as(C.c_void_p),
+                                       st.ctypes.data_as(C.c_void_p), _stream()))
+        return it, rr, st
+
+    def schedule(self, merge, wpc):
+        _check(lib().ilu_batch_schedule(self._h, int(merge), int(wpc)))
+
+    def tune(self, val, b, x, rtol=1e-8, restart=20, maxit=1000):
+        """ilu_batch_tune: time every candidate schedule, keep the fastest; returns (merge, wpc, ms)."""
+        mg, w, ms = C.c_int32(), C.c_int32(), C.c_double()
+        _check(lib().ilu_batch_tune(self._h, _ptr(val), _ptr(b), _ptr(x), float(rtol), int(restart), int(maxit),
+                                    _stream(), C.byref(mg), C.byref(w), C.byref(ms)))
+        return mg.value, w.value, ms.value
+
+    def capture(self, val, b, x, rtol=1e-8, restart=20, maxit=1000):
+        """ilu_batch_capture on the current (non-default) stream."""
+        _check(lib().ilu_batch_capture(self._h, _ptr(val), _ptr(b), _ptr(x), float(rtol), int(restart),
+                                       int(maxit), _stream()))
+
+    def replay(self):
+        _check(lib().ilu_batch_replay(self._h, _stream()))
+
+    def export(self, what):
+        """'lu' factor values, 'lev_L' / 'lev_U' row levels, 'schedule' [E, merge, wpc, grid]."""
+        code, dt = dict(lu=(0, np.float64), lev_L=(1, np.int32), lev_U=(2, np.int32), schedule=(3, np.int32))[what]
+        ln = C.c_int64(0)
+        _check(lib().ilu_batch_export(self._h, code, None, C.byref(ln)))
+        out = np.zeros(ln.value, dtype=dt)
+        _check(lib().ilu_batch_export(self._h, code, out.ctypes.data_as(C.c_void_p), C.byref(ln)))
+        return out
+
+
+def batch_setup(A: DeviceCSR, sys_row, restart=20) -> Batch:
+    """ilu_batch_setup: A block diagonal (global columns), sys_row the first row of each system (host, nsys+1)."""
+    sr = np.ascontiguousarray(sys_row, dtype=np.int64)
+    h = C.c_void_p()
+    _check(lib().ilu_batch_setup(A.ref, sr.ctypes.data_as(C.c_void_p), int(len(sr) - 1), int(restart), _stream(),
+                                 C.byref(h)))
+    return Batch(h, A.n, A.nnz, len(sr) - 1)
 
 
 def memory_trim():

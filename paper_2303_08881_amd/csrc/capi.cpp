@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -253,13 +254,19 @@ struct Schedule {
   int64_t nloc = 0;     // rows in the block-local solve (the rows of W follow in their own pass)
 };
 
-struct GmresWork {
+// Buffers of one FGMRES(m) process on vectors of length n.  With the two
+// events the host reads each step's residual estimate one step late (the
+// read-back overlaps the next step); without them it reads it synchronously.
+struct KrylovBufs {
   int64_t n = 0;
   int m = 0;
   double *V = nullptr, *Zb = nullptr, *r = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
          *c = nullptr, *pa = nullptr, *pb = nullptr, *scal = nullptr;  // scal: [0] bnorm [1] beta [2] hn [3] est
   int *flags = nullptr;                                                // [0] stop [1] nsteps
   hipEvent_t ev[2] = {nullptr, nullptr};                               // read-backs of two consecutive steps
+};
+
+struct GmresWork : KrylovBufs {
   Mem mem;
   ~GmresWork() {
     for (hipEvent_t e : ev)
@@ -1310,6 +1317,9 @@ static int gmres_work_alloc(GmresWork &w, int64_t n, int m) {
   return 0;
 }
 
+static int fgmres_core(const ilu_csr_t *A, ilu_precond *P, KrylovBufs &w, const double *b, double *x, double rtol,
+                       int m, int maxit, hipStream_t s, ilu_result_t *res, double *hist);
+
 static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, double *x, double rtol, int m, int maxit,
                        hipStream_t s, ilu_result_t *res, double *hist) {
   const int64_t n = A->n;
@@ -1326,7 +1336,12 @@ static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, doub
     }
     P->gw = nw;
   }
-  GmresWork &w = *P->gw;
+  return fgmres_core(A, P, *P->gw, b, x, rtol, m, maxit, s, res, hist);
+}
+
+static int fgmres_core(const ilu_csr_t *A, ilu_precond *P, KrylovBufs &w, const double *b, double *x, double rtol,
+                       int m, int maxit, hipStream_t s, ilu_result_t *res, double *hist) {
+  const int64_t n = A->n;
   double *bnorm = w.scal, *beta = w.scal + 1, *hn = w.scal + 2, *est = w.scal + 3;
   int *stop = w.flags, *nsteps = w.flags + 1;
   const int ldh = m + 1;
@@ -1369,7 +1384,11 @@ static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, doub
       int pending = -1;  // slot of the step whose results are not read yet
       bool cycle_done = false;
       auto consume = [&](int slot) -> int {
-        HIPCK(hipEventSynchronize(w.ev[slot]));
+        if (w.ev[slot]) {
+          HIPCK(hipEventSynchronize(w.ev[slot]));
+        } else {
+          HIPCK(hipStreamSynchronize(s));
+        }
         its++;
         if (g_timing) timing_collect();
         if (hist) hist[its] = hest[slot] / hb;
@@ -1395,6 +1414,10 @@ static int fgmres_impl(const ilu_csr_t *A, ilu_precond *P, const double *b, doub
         const int slot = j & 1;
         HIPCK(hipMemcpyAsync(hest + slot, est, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCK(hipMemcpyAsync(hflag + slot, stop, sizeof(int), hipMemcpyDeviceToHost, s));
+        if (!w.ev[slot]) {  // no events: read this step's results now
+          RC(consume(slot));
+          continue;
+        }
         HIPCK(hipEventRecord(w.ev[slot], s));
         if (pending >= 0) RC(consume(pending));
         pending = slot;
@@ -1476,6 +1499,425 @@ int ilu_info(ilu_precond_t *P, int64_t *n, int64_t *nB, int64_t *nS, int32_t *np
   if (nS) *nS = P->nS;
   if (nparts) *nparts = P->nparts;
   return 0;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched systems: ILU(0) + GMRES(m) of many independent systems in one
+// persistent launch (batch.hip).  Setup analyses the pattern once: levels of
+// A's strict lower and upper parts per system (the level sweep of the
+// single-system setup, with one segment per system), the (system, level)
+// sorted positions of both solves and their ring slots, and a largest-first
+// order of the systems.  A solve is one reset kernel and the persistent
+// kernel, with no host synchronisation: it can be captured in a HIP graph.
+// ---------------------------------------------------------------------------
+static int export_raw(const void *d, int64_t cnt, size_t es, void *h, int64_t *len);
+
+struct ilu_batch {
+  ilu_precond core;  // device memory, status word, CU count, level sweeps
+  int32_t nsys = 0;
+  int64_t n = 0, nnz = 0;
+  int E = 2, m_alloc = 0, merge = 32, wpc = 1;
+  int64_t grid = 1;
+  std::vector<int64_t> h_sys_row;
+  int64_t *sys_row = nullptr, *rp = nullptr, *dpos = nullptr, *Lsrc = nullptr, *Usrc = nullptr;
+  int32_t *ci = nullptr, *order = nullptr, *nlevL = nullptr, *nlevU = nullptr, *levL = nullptr, *levU = nullptr,
+          *Lrow = nullptr, *Urow = nullptr, *iters = nullptr, *bstatus = nullptr;
+  uint8_t *wide = nullptr;
+  uint32_t *Lslot = nullptr, *Uslot = nullptr;
+  unsigned int *ticket = nullptr;
+  double *lu = nullptr, *Lval = nullptr, *Uval = nullptr, *Udiag = nullptr, *V = nullptr, *y = nullptr, *z = nullptr,
+         *t = nullptr, *relres = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  ~ilu_batch() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+// Positions of one triangular solve of every system: rows sorted by (system,
+// level), the per-system level tables, and the per-position entries.
+static int batch_solve_order(ilu_batch *B, Mem &tmp, const Csr &A, const int32_t *row_sys, bool upper, int E,
+                             void *stmp, size_t stmpb, hipStream_t s, int32_t **prow, uint32_t **pslot,
+                             int64_t **psrc, int32_t **nlev, int32_t **lev, int32_t *err, bool refill_only,
+                             Schedule &S) {
+  ilu_precond *P = &B->core;
+  Mem &mem = P->mem;
+  const int64_t n = A.n;
+  const int levmax1 = BATCH_LEVMAX + 1;
+  if (!refill_only) {
+    Segs seg;
+    for (int k = 0; k < B->nsys; k++) {
+      seg.a_start.push_back(B->h_sys_row[k]);
+      seg.a_len.push_back(B->h_sys_row[k + 1] - B->h_sys_row[k]);
+      seg.b_start.push_back(0);
+      seg.b_len.push_back(0);
+    }
+    RC(build_schedule(P, tmp, A, !upper, 0, n, n, S, seg, s, upper ? "batch levels U" : "batch levels L"));
+    if (S.nlev > BATCH_LEVMAX)
+      return fail(ILU_ERR_CAPACITY, "batched solve: %lld levels in one triangular factor (at most %d)",
+                  (long long)S.nlev, BATCH_LEVMAX);
+  }
+  const uint64_t nkeys = (uint64_t)B->nsys * (uint64_t)S.nlev;
+  if (nkeys >= (1ull << 31)) return fail(ILU_ERR_CAPACITY, "batched solve: too many (system, level) pairs");
+  uint32_t *key, *key2;
+  int32_t *val, *rows, *inv;
+  RC(tmp.alloc(&key, n));
+  RC(tmp.alloc(&key2, n));
+  RC(tmp.alloc(&val, n));
+  RC(tmp.alloc(&rows, n));
+  RC(tmp.alloc(&inv, n));
+  void *rtmp;
+  const size_t rtb = radix_tmp_bytes(n);
+  RC(tmp.alloc((char **)&rtmp, (int64_t)rtb));
+  RC(launch_block_level_keys(S.level_of, row_sys, n, S.nlev, key, val, s));
+  RC(radix_sort(key, val, key2, rows, n, bits_for(nkeys - 1), rtmp, rtb, s));
+  RC(launch_inverse_perm(n, rows, inv, s));
+  int64_t *cnt, *bptr, btot;
+  RC(tmp.alloc(&cnt, (int64_t)nkeys));
+  RC(histogram_keys(key2, n, (int64_t)nkeys, cnt, s));
+  const size_t stb2 = scan_tmp_bytes((int64_t)nkeys) + 64;
+  void *stmp2;
+  RC(tmp.alloc((char **)&stmp2, (int64_t)stb2));
+  RC(make_rp(tmp, cnt, (int64_t)nkeys, &bptr, &btot, stmp2, stb2, s));
+  int32_t *bptr32;
+  RC(tmp.alloc(&bptr32, (int64_t)nkeys + 1));
+  RC(launch_i64_to_i32(bptr, bptr32, (int64_t)nkeys + 1, s));
+  if (!*nlev) {
+    RC(mem.alloc(nlev, B->nsys));
+    RC(mem.alloc(lev, (int64_t)B->nsys * levmax1));
+  }
+  RC(launch_batch_levels(bptr32, S.nlev, B->sys_row, B->nsys, levmax1, *lev, *nlev, B->wide, upper, s));
+  if (!*prow) RC(mem.alloc(prow, n));
+  RC(mem.alloc(pslot, n * (E / 2)));
+  RC(mem.alloc(psrc, n * E));
+  RC(launch_batch_fill(rows, n, B->sys_row, row_sys, inv, S.level_of, *lev, levmax1, A.rp, A.ci, upper, E, *prow,
+                       *pslot, *psrc, B->dpos, err, s));
+  (void)stmp;
+  (void)stmpb;
+  return 0;
+}
+
+static int batch_setup_impl(ilu_batch *B, const ilu_csr_t *A, int32_t restart, hipStream_t s) {
+  ilu_precond *P = &B->core;
+  Mem &mem = P->mem;
+  Mem tmp;
+  const int64_t n = A->n, nnz = A->nnz;
+  HIPCK(hipGetDevice(&P->device));
+  {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, P->device) == hipSuccess && cu > 0)
+      P->num_cu = cu;
+  }
+  RC(mem.alloc(&P->status, 1));
+  HIPCK(hipMemsetAsync(P->status, 0, sizeof(Status), s));
+  RC(mem.alloc(&B->sys_row, B->nsys + 1));
+  HIPCK(hipMemcpyAsync(B->sys_row, B->h_sys_row.data(), sizeof(int64_t) * (B->nsys + 1), hipMemcpyHostToDevice, s));
+  int32_t *row_sys;
+  RC(mem.alloc(&row_sys, n));
+  RC(launch_row_sys(B->sys_row, B->nsys, row_sys, s));
+  // 1. validation (the system of a row plays the partition; columns outside
+  //    the row's system are rejected below)
+  int32_t *err;
+  RC(tmp.alloc(&err, 3));
+  RC(fill_i32(err, 0x7fffffff, 2, s));
+  RC(fill_i32(err + 2, 0, 1, s));
+  RC(launch_validate(A->d_row_ptr, A->d_col, n, nnz, row_sys, B->nsys, err, s));
+  int32_t herr[3];
+  HIPCK(hipMemcpyAsync(herr, err, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  if (herr[0] != 0x7fffffff)
+    return fail(ILU_ERR_CSR, "invalid CSR at row %d (row pointers, unsorted/duplicate/out-of-range columns, or "
+                "missing diagonal)", herr[0]);
+  // 2. the pattern, owned by the handle
+  RC(mem.alloc(&B->rp, n + 1));
+  RC(mem.alloc(&B->ci, nnz));
+  HIPCK(hipMemcpyAsync(B->rp, A->d_row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+  HIPCK(hipMemcpyAsync(B->ci, A->d_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1), hipMemcpyDeviceToDevice, s));
+  Csr Ap;
+  Ap.n = n;
+  Ap.nnz = nnz;
+  Ap.rp = B->rp;
+  Ap.ci = B->ci;
+  RC(mem.alloc(&B->dpos, n));
+  RC(mem.alloc(&B->wide, B->nsys));
+  // 3. levels, positions and entries of both solves; E = 2 entries per row
+  //    and triangle when that suffices, else 4
+  const size_t stmpb = scan_tmp_bytes(n + 1) + 64;
+  void *stmp;
+  RC(tmp.alloc((char **)&stmp, (int64_t)stmpb));
+  Schedule SL, SU;
+  for (int E = 2;; E = 4) {
+    RC(fill_i32(err + 2, 0, 1, s));
+    const bool again = E == 4;
+    RC(batch_solve_order(B, tmp, Ap, row_sys, false, E, stmp, stmpb, s, &B->Lrow, &B->Lslot, &B->Lsrc, &B->nlevL,
+                         &B->levL, err + 2, again, SL));
+    RC(batch_solve_order(B, tmp, Ap, row_sys, true, E, stmp, stmpb, s, &B->Urow, &B->Uslot, &B->Usrc, &B->nlevU,
+                         &B->levU, err + 2, again, SU));
+    HIPCK(hipMemcpyAsync(herr + 2, err + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    B->E = E;
+    if (!(herr[2] & 2) || E == 4) break;
+  }
+  if (herr[2] & 4) return fail(ILU_ERR_INVALID_ARG, "batched systems: a column lies outside its row's system");
+  if (herr[2] & 2)
+    return fail(ILU_ERR_CAPACITY, "batched solve: a row has more than 4 entries in a triangle or more than %d in all",
+                BATCH_RMAX);
+  if (herr[2] & 1) return fail(ILU_ERR_CAPACITY, "batched solve: a dependency lies beyond the %d-position ring",
+                               BATCH_RING);
+  // level arrays of the rows, kept for export
+  B->core.sL1 = SL;
+  B->core.sU1 = SU;
+  // 4. largest-first order of the systems
+  {
+    std::vector<int32_t> ord(B->nsys);
+    for (int k = 0; k < B->nsys; k++) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+      return B->h_sys_row[a + 1] - B->h_sys_row[a] > B->h_sys_row[b + 1] - B->h_sys_row[b];
+    });
+    RC(mem.alloc(&B->order, B->nsys));
+    HIPCK(hipMemcpyAsync(B->order, ord.data(), sizeof(int32_t) * B->nsys, hipMemcpyHostToDevice, s));
+  }
+  // 5. factor values, repacked entries, Krylov workspace, results
+  RC(mem.alloc(&B->lu, nnz));
+  RC(mem.alloc(&B->Lval, n * B->E));
+  RC(mem.alloc(&B->Uval, n * B->E));
+  RC(mem.alloc(&B->Udiag, n));
+  RC(mem.alloc(&B->V, (int64_t)(restart + 1) * n));
+  RC(mem.alloc(&B->y, n));
+  RC(mem.alloc(&B->z, n));
+  RC(mem.alloc(&B->t, n));
+  RC(mem.alloc(&B->iters, B->nsys));
+  RC(mem.alloc(&B->bstatus, B->nsys));
+  RC(mem.alloc(&B->relres, B->nsys));
+  RC(mem.alloc(&B->ticket, 1));
+  RC(fill_i32(B->iters, 0, B->nsys, s));
+  RC(fill_i32(B->bstatus, 0, B->nsys, s));
+  B->m_alloc = restart;
+  const int per = batch_resident_groups(P->num_cu, B->E) / std::max(P->num_cu, 1);
+  if (per < 1) return fail(ILU_ERR_HIP, "batched solve: no resident workgroups");
+  B->wpc = std::min(per, 2);
+  B->grid = std::min<int64_t>(B->nsys, (int64_t)B->wpc * P->num_cu);
+  HIPCK(hipStreamSynchronize(s));
+  return 0;
+}
+
+static int batch_launch(ilu_batch *B, const double *val, const double *b, double *x, double rtol, int m, int maxit,
+                        hipStream_t s) {
+  BatchLaunch L;
+  L.nsys = B->nsys;
+  L.sys_row = B->sys_row;
+  L.order = B->order;
+  L.nlevL = B->nlevL;
+  L.nlevU = B->nlevU;
+  L.levL = B->levL;
+  L.levU = B->levU;
+  L.wide = B->wide;
+  L.rp = B->rp;
+  L.ci = B->ci;
+  L.av = val;
+  L.dpos = B->dpos;
+  L.lu = B->lu;
+  L.Lrow = B->Lrow;
+  L.Urow = B->Urow;
+  L.Lslot = B->Lslot;
+  L.Uslot = B->Uslot;
+  L.Lsrc = B->Lsrc;
+  L.Usrc = B->Usrc;
+  L.Lval = B->Lval;
+  L.Uval = B->Uval;
+  L.Udiag = B->Udiag;
+  L.b = b;
+  L.x = x;
+  L.V = B->V;
+  L.y = B->y;
+  L.z = B->z;
+  L.t = B->t;
+  L.rtol = rtol;
+  L.m = m;
+  L.maxit = maxit;
+  L.merge = B->merge;
+  L.E = B->E;
+  L.grid = B->grid;
+  L.ticket = B->ticket;
+  L.iters = B->iters;
+  L.status = B->bstatus;
+  L.relres = B->relres;
+  const int rc = launch_batch_solve(L, s);
+  if (rc == ILU_ERR_INVALID_ARG) return fail(rc, "batched solve: bad restart or grid");
+  return rc;
+}
+
+static int batch_check_args(ilu_batch *B, const double *val, const double *b, double *x, double rtol, int m,
+                            int maxit) {
+  if (!B) return fail(ILU_ERR_INVALID_ARG, "NULL batch handle");
+  if (B->n > 0 && (!val || !b || !x)) return fail(ILU_ERR_INVALID_ARG, "NULL vector");
+  if (m < 1 || m > B->m_alloc || m > BATCH_MMAX || maxit < 0 || !(rtol >= 0.0))
+    return fail(ILU_ERR_INVALID_ARG, "restart must be in [1, %d] (the setup's restart) and maxit, rtol >= 0",
+                std::min(B->m_alloc, BATCH_MMAX));
+  return 0;
+}
+
+extern "C" {
+
+int ilu_batch_setup(const ilu_csr_t *A, const int64_t *h_sys_row, int32_t nsys, int32_t restart, void *stream,
+                    ilu_batch_t **out) {
+  if (!out) return fail(ILU_ERR_INVALID_ARG, "B must not be NULL");
+  *out = nullptr;
+  if (!A || A->n < 1 || A->nnz < 1 || !A->d_row_ptr || !A->d_col || !h_sys_row || nsys < 1)
+    return fail(ILU_ERR_INVALID_ARG, "invalid batch description");
+  if (A->n >= 0x7fffffff || A->nnz >= ((int64_t)1 << 40)) return fail(ILU_ERR_INVALID_ARG, "batch too large");
+  if (restart < 1 || restart > BATCH_MMAX)
+    return fail(ILU_ERR_INVALID_ARG, "restart must be in [1, %d] for the batched solve", BATCH_MMAX);
+  if (h_sys_row[0] != 0 || h_sys_row[nsys] != A->n)
+    return fail(ILU_ERR_INVALID_ARG, "system offsets must start at 0 and end at n");
+  for (int32_t k = 0; k < nsys; k++)
+    if (h_sys_row[k + 1] <= h_sys_row[k]) return fail(ILU_ERR_INVALID_ARG, "system %d is empty", k);
+  ilu_batch *B = new ilu_batch();
+  ilu_default_options(&B->core.opt);
+  B->nsys = nsys;
+  B->n = A->n;
+  B->nnz = A->nnz;
+  B->core.n = A->n;
+  B->h_sys_row.assign(h_sys_row, h_sys_row + nsys + 1);
+  hipStream_t s = (hipStream_t)stream;
+  const int rc = batch_setup_impl(B, A, restart, s);
+  if (rc) {
+    (void)hipStreamSynchronize(s);
+    delete B;
+    return rc;
+  }
+  *out = B;
+  return 0;
+}
+
+int ilu_batch_solve(ilu_batch_t *B, const double *d_val, const double *d_b, double *d_x, double rtol,
+                    int32_t restart, int32_t maxit, void *stream) {
+  RC(batch_check_args(B, d_val, d_b, d_x, rtol, restart, maxit));
+  HIPCK(hipSetDevice(B->core.device));
+  return batch_launch(B, d_val, d_b, d_x, rtol, restart, maxit, (hipStream_t)stream);
+}
+
+int ilu_batch_schedule(ilu_batch_t *B, int32_t merge, int32_t wpc) {
+  if (!B) return fail(ILU_ERR_INVALID_ARG, "NULL batch handle");
+  const int per = batch_resident_groups(B->core.num_cu, B->E) / std::max(B->core.num_cu, 1);
+  if (merge < 0 || merge > WAVE || wpc < 1 || wpc > per)
+    return fail(ILU_ERR_INVALID_ARG, "merge must be in [0, %d] and workgroups per CU in [1, %d]", WAVE, per);
+  B->merge = merge;
+  B->wpc = wpc;
+  B->grid = std::min<int64_t>(B->nsys, (int64_t)wpc * B->core.num_cu);
+  return 0;
+}
+
+int ilu_batch_tune(ilu_batch_t *B, const double *d_val, const double *d_b, double *d_x, double rtol,
+                   int32_t restart, int32_t maxit, void *stream, int32_t *h_merge, int32_t *h_wpc, double *h_ms) {
+  RC(batch_check_args(B, d_val, d_b, d_x, rtol, restart, maxit));
+  HIPCK(hipSetDevice(B->core.device));
+  hipStream_t s = (hipStream_t)stream;
+  const int per = batch_resident_groups(B->core.num_cu, B->E) / std::max(B->core.num_cu, 1);
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  double best = 1e300;
+  int bm = B->merge, bw = B->wpc;
+  const int merges[] = {0, 16, 32, 64};
+  int rc = 0;
+  for (int w = 1; w <= per && !rc; w++)
+    for (int mg : merges) {
+      if ((rc = ilu_batch_schedule(B, mg, w))) break;
+      (void)hipEventRecord(e0, s);
+      if ((rc = batch_launch(B, d_val, d_b, d_x, rtol, restart, maxit, s))) break;
+      (void)hipEventRecord(e1, s);
+      float ms = 0.f;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = fail(ILU_ERR_HIP, "batched tuning: event timing failed");
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        bm = mg;
+        bw = w;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  RC(rc);
+  RC(ilu_batch_schedule(B, bm, bw));
+  if (h_merge) *h_merge = bm;
+  if (h_wpc) *h_wpc = bw;
+  if (h_ms) *h_ms = best;
+  return 0;
+}
+
+int ilu_batch_capture(ilu_batch_t *B, const double *d_val, const double *d_b, double *d_x, double rtol,
+                      int32_t restart, int32_t maxit, void *stream) {
+  RC(batch_check_args(B, d_val, d_b, d_x, rtol, restart, maxit));
+  if (!stream) return fail(ILU_ERR_INVALID_ARG, "graph capture needs a stream other than the default one");
+  HIPCK(hipSetDevice(B->core.device));
+  hipStream_t s = (hipStream_t)stream;
+  if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->gexec = nullptr;
+  B->graph = nullptr;
+  HIPCK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  const int rc = batch_launch(B, d_val, d_b, d_x, rtol, restart, maxit, s);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return silu_hip_fail(e, __LINE__);
+  B->graph = g;
+  HIPCK(hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0));
+  return 0;
+}
+
+int ilu_batch_replay(ilu_batch_t *B, void *stream) {
+  if (!B || !B->gexec) return fail(ILU_ERR_INVALID_ARG, "no captured batch solve");
+  HIPCK(hipSetDevice(B->core.device));
+  HIPCK(hipGraphLaunch(B->gexec, (hipStream_t)stream));
+  return 0;
+}
+
+int ilu_batch_results(ilu_batch_t *B, int32_t *h_iters, double *h_relres, int32_t *h_status, void *stream) {
+  if (!B) return fail(ILU_ERR_INVALID_ARG, "NULL batch handle");
+  HIPCK(hipSetDevice(B->core.device));
+  hipStream_t s = (hipStream_t)stream;
+  if (h_iters) HIPCK(hipMemcpyAsync(h_iters, B->iters, sizeof(int32_t) * B->nsys, hipMemcpyDeviceToHost, s));
+  if (h_relres) HIPCK(hipMemcpyAsync(h_relres, B->relres, sizeof(double) * B->nsys, hipMemcpyDeviceToHost, s));
+  if (h_status) HIPCK(hipMemcpyAsync(h_status, B->bstatus, sizeof(int32_t) * B->nsys, hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  return 0;
+}
+
+int ilu_batch_export(ilu_batch_t *B, int32_t what, void *h_buf, int64_t *len) {
+  if (!B || !len) return fail(ILU_ERR_INVALID_ARG, "NULL argument");
+  switch (what) {
+    case 0: return export_raw(B->lu, B->nnz, 8, h_buf, len);
+    case 1: return export_raw(B->core.sL1.level_of, B->n, 4, h_buf, len);
+    case 2: return export_raw(B->core.sU1.level_of, B->n, 4, h_buf, len);
+    case 3: {
+      const int32_t v[4] = {B->E, B->merge, B->wpc, (int32_t)B->grid};
+      if (!h_buf) {
+        *len = 4;
+        return 0;
+      }
+      if (*len < 4) return fail(ILU_ERR_INVALID_ARG, "export buffer too small");
+      *len = 4;
+      memcpy(h_buf, v, sizeof(v));
+      return 0;
+    }
+    default: return fail(ILU_ERR_INVALID_ARG, "unknown batch export code %d", what);
+  }
+}
+
+void ilu_batch_destroy(ilu_batch_t *B) {
+  if (!B) return;
+  (void)hipSetDevice(B->core.device);
+  delete B;
 }
 
 static int export_csr(const Csr &c, int field, void *h, int64_t *len) {

@@ -202,6 +202,48 @@ int launch_block_level_keys(const int32_t *level, const int32_t *blk, int64_t n,
                             int32_t *val, hipStream_t s);
 int launch_i64_to_i32(const int64_t *in, int32_t *out, int64_t n, hipStream_t s);
 
+// ---- batch.hip ----
+constexpr int BATCH_THREADS = 256;  // threads per workgroup of the batched solve
+constexpr int BATCH_RING = 2048;    // solution ring of a batched triangular solve (positions)
+constexpr int BATCH_MMAX = 32;      // largest restart of the batched GMRES
+constexpr int BATCH_LEVMAX = 1024;  // levels per triangular factor of one batched system
+constexpr int BATCH_RMAX = 16;      // entries per row of a batched system
+struct BatchLaunch {
+  int32_t nsys;
+  const int64_t *sys_row;
+  const int32_t *order;
+  const int32_t *nlevL, *nlevU, *levL, *levU;
+  const uint8_t *wide;
+  const int64_t *rp;
+  const int32_t *ci;
+  const double *av;
+  const int64_t *dpos;
+  double *lu;
+  const int32_t *Lrow, *Urow;
+  const uint32_t *Lslot, *Uslot;
+  const int64_t *Lsrc, *Usrc;
+  double *Lval, *Uval, *Udiag;
+  const double *b;
+  double *x;
+  double *V, *y, *z, *t;
+  double rtol;
+  int m, maxit, merge, E;
+  int64_t grid;
+  unsigned int *ticket;
+  int32_t *iters, *status;
+  double *relres;
+};
+// reset of the ticket counter, then the persistent factor + solve kernel
+int launch_batch_solve(const BatchLaunch &L, hipStream_t s);
+int batch_resident_groups(int num_cu, int E);
+int launch_row_sys(const int64_t *sys_row, int32_t nsys, int32_t *row_sys, hipStream_t s);
+int launch_batch_levels(const int32_t *blk_lev_ptr, int64_t nlev_all, const int64_t *sys_row, int32_t nsys,
+                        int levmax1, int32_t *levrel, int32_t *nlev, uint8_t *wide, bool or_wide, hipStream_t s);
+int launch_batch_fill(const int32_t *pos_rows, int64_t n, const int64_t *sys_row, const int32_t *row_sys,
+                      const int32_t *inv_pos, const int32_t *lev_of, const int32_t *levrel, int levmax1,
+                      const int64_t *rp, const int32_t *ci, bool upper, int E, int32_t *prow, uint32_t *pslot,
+                      int64_t *psrc, int64_t *dpos, int32_t *err, hipStream_t s);
+
 // ---- krylov.hip ----
 // kernel instance of a product, so that profilers report the outer matrix and
 // the reduced system's coupling apart

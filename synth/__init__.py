@@ -17,5 +17,7 @@ from .generators import (  # noqa: F401
     uniform_rhs,
     random_sparse,
     convdiff_batch_params,
+    convdiff_batch,
+    block_diagonal,
     workload,
 )

@@ -176,6 +176,26 @@ def convdiff_batch_params(count: int, seed: int = 4):
     return out
 
 
+def block_diagonal(mats):
+    """One block-diagonal CSR of the given systems (global column numbering) and the first row of each system
+    ([len(mats) + 1] int64)."""
+    sys_row = np.zeros(len(mats) + 1, dtype=np.int64)
+    np.cumsum([m.n for m in mats], out=sys_row[1:])
+    nnz = np.zeros(len(mats) + 1, dtype=np.int64)
+    np.cumsum([m.nnz for m in mats], out=nnz[1:])
+    rp = np.concatenate([m.row_ptr[:-1] + nnz[k] for k, m in enumerate(mats)] + [nnz[-1:]])
+    col = np.concatenate([m.col.astype(np.int64) + sys_row[k] for k, m in enumerate(mats)]).astype(np.int32)
+    val = np.concatenate([m.val for m in mats])
+    return CSR(int(sys_row[-1]), rp.astype(np.int64), col, val), sys_row
+
+
+def convdiff_batch(count: int, seed: int = 4):
+    """The batched workload: `count` convection-diffusion systems with the parameters of
+    convdiff_batch_params, as a list of CSR matrices, and their right-hand sides b_k = A_k 1."""
+    mats = [convdiff5(*p) for p in convdiff_batch_params(count, seed)]
+    return mats, [m.matvec(np.ones(m.n)) for m in mats]
+
+
 # --------------------------------------------------------------------------
 # partitions
 # --------------------------------------------------------------------------

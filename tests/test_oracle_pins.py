@@ -542,3 +542,200 @@ def test_inner_rtol_stops_at_the_krylov_least_squares_step():
     z = oracle.Precond(A, part, 4, inner_rtol=tol, **base).apply(r)
     np.testing.assert_allclose(z[perm[nB:]], y2, rtol=1e-9, atol=1e-12)
     assert np.linalg.norm(y2 - yk) > 1e-6 * np.linalg.norm(yk)
+
+
+# ---------------------------------------------------------------- GMRES(m) of the batched systems
+def _bj_factors(P, n):
+    L = csr_dense(*P.csr("LB"), n) + np.eye(n)
+    U = csr_dense(*P.csr("UB"), n) + np.diag(P.export("DB"))
+    return L @ U
+
+
+def _gmres_ls(A, M, b, x0, k):
+    # x0 + M^-1 y, y minimising ||r0 - A M^-1 y|| over the Krylov space K_k(A M^-1, r0)
+    T = A @ np.linalg.inv(M)
+    r0 = b - A @ x0
+    K = np.stack([np.linalg.matrix_power(T, j) @ r0 for j in range(k)], axis=1)
+    c = np.linalg.lstsq(T @ K, r0, rcond=None)[0]
+    return x0 + np.linalg.solve(M, K @ c)
+
+
+def test_gmres_is_right_preconditioned_krylov_least_squares():
+    # k < restart steps from x0 = 0, then a second cycle of 3 steps from that iterate:
+    # each cycle's x is the least-squares solution over its own Krylov space.
+    A = synth.convdiff5(9, 0.05, 0.7, 20.0)
+    b = synth.uniform_rhs(A.n, 12)
+    P = oracle.Precond(A, None, 1, method=oracle.BJ, interior_fact=oracle.ILU0)
+    Ad, M = A.dense(), _bj_factors(P, A.n)
+    k = 6
+    out = oracle.gmres(A, P, b, rtol=0.0, restart=20, maxit=k)
+    assert out["iterations"] == k and not out["converged"]
+    x1 = _gmres_ls(Ad, M, b, np.zeros(A.n), k)
+    np.testing.assert_allclose(out["x"], x1, rtol=1e-9, atol=1e-12 * np.abs(x1).max())
+    out = oracle.gmres(A, P, b, rtol=0.0, restart=k, maxit=k + 3)
+    x2 = _gmres_ls(Ad, M, b, x1, 3)
+    np.testing.assert_allclose(out["x"], x2, rtol=1e-9, atol=1e-12 * np.abs(x2).max())
+    # the flexible variant with a fixed preconditioner reaches the same iterates
+    outf = oracle.fgmres(A, P, b, rtol=0.0, restart=k, maxit=k + 3)
+    np.testing.assert_allclose(outf["x"], x2, rtol=1e-9, atol=1e-12 * np.abs(x2).max())
+
+
+def test_gmres_exact_preconditioner_and_implicit_residual():
+    # ILU(0) of a tridiagonal matrix is its exact LU, so M = A and one step solves
+    # the system; on a general system the Givens estimate equals the true residual.
+    T = CSR.from_dense(3 * np.eye(30) - np.eye(30, k=1) - 0.5 * np.eye(30, k=-1))
+    b = synth.uniform_rhs(30, 13)
+    P = oracle.Precond(T, None, 1, method=oracle.BJ, interior_fact=oracle.ILU0)
+    out = oracle.gmres(T, P, b, rtol=1e-12, restart=20, maxit=50)
+    assert out["converged"] and out["iterations"] == 1
+    A = synth.convdiff5(12, 0.01, 2.0, 35.0)
+    b = synth.uniform_rhs(A.n, 14)
+    P = oracle.Precond(A, None, 1, method=oracle.BJ, interior_fact=oracle.ILU0)
+    out = oracle.gmres(A, P, b, rtol=1e-10, restart=20, maxit=17, history=True)
+    true = np.linalg.norm(b - A.dense() @ out["x"]) / np.linalg.norm(b)
+    np.testing.assert_allclose(out["history"][-1], true, rtol=1e-6)
+
+
+# ---------------------------------------------------------------- multiplicative RAP-ILU (Alg. 2, Section 3.3)
+def _rap_pieces(P, A, nB):
+    """Dense R, P (permuted numbering) and the permuted A, from the exported factors."""
+    n = A.n
+    nS = n - nB
+    perm = P.export("perm")
+    Ap = A.dense()[np.ix_(perm, perm)]
+    LB = csr_dense(*P.csr("LB"), nB) + np.eye(nB)
+    UB = csr_dense(*P.csr("UB"), nB) + np.diag(P.export("DB"))
+    Zm = csr_dense(*P.csr("Z"), nB, n)[:, nB:]
+    W = csr_dense(*P.csr("W"), nS, nB)
+    R = np.hstack([-W @ np.linalg.inv(LB), np.eye(nS)])
+    Pm = np.vstack([-np.linalg.solve(UB, Zm), np.eye(nS)])
+    return Ap, R, Pm, LB, UB, W, Zm
+
+
+@pytest.mark.parametrize("coarse", [oracle.ILU0, oracle.MILU0])
+def test_rap_matvec_is_the_galerkin_product(coarse):
+    # eq. (28): R A P with R = (-W L_B^-1, I) and P = (-U_B^-1 Z; I), unformed in the oracle
+    A = synth.aniso7(8, Nz=12)
+    part = synth.slab_partition(8, 3, Nz=12)
+    P = oracle.Precond(A, part, 3, method=oracle.RAP, interior_fact=coarse, inner_iters=3)
+    nB = int(P.export("offsets")[3])
+    Ap, R, Pm, *_ = _rap_pieces(P, A, nB)
+    nS = A.n - nB
+    S2 = np.stack([P.rap_matvec(np.eye(nS)[:, j]) for j in range(nS)], axis=1)
+    np.testing.assert_allclose(S2, R @ Ap @ Pm, atol=1e-12 * np.abs(S2).max())
+
+
+def _cylinder_laplacian(nx, ny):
+    """Graph Laplacian of an nx-by-ny grid closed in y (a cylinder): every row sums to zero."""
+    n = nx * ny
+    d = np.zeros((n, n))
+    for y in range(ny):
+        for x in range(nx):
+            i = x + nx * y
+            for j in ([i - 1] if x > 0 else []) + ([i + 1] if x < nx - 1 else []) + \
+                     [x + nx * ((y + 1) % ny), x + nx * ((y - 1) % ny)]:
+                d[i, j] = -1.0
+    np.fill_diagonal(d, -d.sum(axis=1))
+    return CSR.from_dense(d)
+
+
+def test_rap_milu_keeps_constants():
+    # With MILU(0) factors H 1 = 0, so P 1 = 1 when the interior rows have zero row sums, and
+    # the constant vector passes the coarse operator as the local Schur factors pass it:
+    # R A P 1 = L_S U_S 1 + C_off 1 (Section 3.3; C_off couples the subdomains' interfaces and
+    # lies in no local factor).  Standard ILU(0) factors do not have this property.  The
+    # cylinder puts interface rows at both ends of every slab, so no subdomain block is singular.
+    A = _cylinder_laplacian(12, 12)
+    part = (np.arange(A.n) // 48).astype(np.int32)  # three slabs of four grid lines
+    out = {}
+    for coarse in (oracle.MILU0, oracle.ILU0):
+        P = oracle.Precond(A, part, 3, method=oracle.RAP, interior_fact=coarse, inner_iters=3)
+        nB = int(P.export("offsets")[3])
+        nS = A.n - nB
+        one = np.ones(nS)
+        LS = csr_dense(*P.csr("LS"), nS) + np.eye(nS)
+        US = csr_dense(*P.csr("US"), nS) + np.diag(P.export("DS"))
+        Coff = csr_dense(*P.csr("Coff"), nS)
+        out[coarse] = np.abs(P.rap_matvec(one) - (LS @ (US @ one) + Coff @ one)).max()
+        if coarse == oracle.MILU0:
+            Ap, R, Pm, *_ = _rap_pieces(P, A, nB)
+            np.testing.assert_allclose(Pm @ one, np.ones(A.n), atol=1e-13)  # P 1 = 1
+    assert out[oracle.MILU0] <= 1e-13
+    assert out[oracle.ILU0] > 1e-3
+
+
+def test_rap_remark_difference_of_schur_complements():
+    # Remark 1(3): with R = (-E B~^-1, I) and P = (-B~^-1 F; I), S_A2 = R A P and
+    # S_A1 = C - E B~^-1 F differ by E B~^-1 B B~^-1 F - E B~^-1 F.  With dense E and F
+    # blocks the (M)ILU(0) factors drop nothing in them (W U_B = E, L_B Z = F), so the
+    # oracle's R and P are exactly these, while B~^-1 = (L_B U_B)^-1 != B^-1 (B drops fill).
+    nb, ni = 6, 2  # interior and interface rows per subdomain
+    n = 2 * (nb + ni)
+    d = np.zeros((n, n))
+    rng = synth.uniform01(77, 4 * n * n).reshape(4, n, n) - 0.5
+    for k in range(2):
+        o = k * (nb + ni)
+        I = np.arange(o, o + nb)
+        F = np.arange(o + nb, o + nb + ni)
+        for i in range(nb - 1):
+            d[I[i], I[i + 1]], d[I[i + 1], I[i]] = rng[0, I[i], I[i + 1]], rng[0, I[i + 1], I[i]]
+        d[I[0], I[nb - 1]], d[I[nb - 1], I[0]] = 0.4, 0.3  # long-range coupling: ILU(0) drops fill in B
+        d[np.ix_(F, I)] = rng[1][np.ix_(F, I)]
+        d[np.ix_(I, F)] = rng[2][np.ix_(I, F)]
+        d[np.ix_(F, F)] = rng[3][np.ix_(F, F)]
+    o1, o2 = nb, (nb + ni) + nb  # cross-subdomain coupling of the interface rows
+    d[o1, o2], d[o2, o1], d[o1 + 1, o2 + 1], d[o2 + 1, o1 + 1] = -0.2, -0.25, 0.15, -0.1
+    np.fill_diagonal(d, 0.0)
+    np.fill_diagonal(d, np.abs(d).sum(axis=1) + 1.0)
+    A = CSR.from_dense(d)
+    part = (np.arange(n) // (nb + ni)).astype(np.int32)
+    P = oracle.Precond(A, part, 2, method=oracle.RAP, interior_fact=oracle.ILU0, inner_iters=3)
+    nB = int(P.export("offsets")[2])
+    assert nB == 2 * nb
+    Ap, R, Pm, LB, UB, W, Zm = _rap_pieces(P, A, nB)
+    B, Fm, E, Cm = Ap[:nB, :nB], Ap[:nB, nB:], Ap[nB:, :nB], Ap[nB:, nB:]
+    Bt = np.linalg.inv(LB @ UB)
+    np.testing.assert_allclose(W @ UB, E, atol=1e-13)
+    np.testing.assert_allclose(LB @ Zm, Fm, atol=1e-13)
+    S2 = np.stack([P.rap_matvec(np.eye(n - nB)[:, j]) for j in range(n - nB)], axis=1)
+    S1 = Cm - E @ Bt @ Fm
+    diff = E @ Bt @ B @ Bt @ Fm - E @ Bt @ Fm
+    assert np.abs(diff).max() > 1e-4  # B~^-1 really is inexact
+    np.testing.assert_allclose(S2 - S1, diff, atol=1e-12)
+
+
+def test_rap_apply_closed_form():
+    # Remark 1(2) with this smoother: z = S r + P (RAP)^-1 R (r - A S r), S the block-Jacobi
+    # ILU(0) smoother; the reduced GMRES takes n_S steps, so it solves R A P v = R(...) exactly.
+    A = synth.aniso7(6, Nz=8)
+    part = synth.slab_partition(6, 2, Nz=8)
+    Pb = oracle.Precond(A, part, 2, method=oracle.BJ, interior_fact=oracle.ILU0)
+    probe = oracle.Precond(A, part, 2, method=oracle.RAP, interior_fact=oracle.MILU0, inner_iters=1)
+    nB = int(probe.export("offsets")[2])
+    nS = A.n - nB
+    P = oracle.Precond(A, part, 2, method=oracle.RAP, interior_fact=oracle.MILU0, inner_iters=nS)
+    Ap, R, Pm, *_ = _rap_pieces(P, A, nB)
+    perm = P.export("perm")
+    r = synth.uniform_rhs(A.n, 31)
+    x = Pb.apply(r)
+    res = r - A.dense() @ x
+    v = np.linalg.solve(R @ Ap @ Pm, R @ res[perm])
+    zref = x.copy()
+    zref[perm] += Pm @ v
+    np.testing.assert_allclose(P.apply(r), zref, rtol=1e-8, atol=1e-10 * np.abs(zref).max())
+
+
+def test_rap_milu_converges_faster_than_block_jacobi():
+    # the paper's Fig. 3: on 2D Poisson with many subdomains RAP-MILU(0) needs far fewer
+    # iterations than BJ-ILU(0) (soft: only the ordering is checked)
+    A = synth.aniso5(48, 1.0)
+    part = (np.arange(A.n) // (48 * 6)).astype(np.int32)  # 8 horizontal slabs
+    b = synth.uniform_rhs(A.n, 5)
+    its = {}
+    for name, o in (("bj", dict(method=oracle.BJ)), ("rap", dict(method=oracle.RAP, interior_fact=oracle.MILU0,
+                                                                   inner_iters=3))):
+        P = oracle.Precond(A, part, 8, **o)
+        out = oracle.fgmres(A, P, b, rtol=1e-8, restart=50, maxit=2000)
+        assert out["converged"]
+        its[name] = out["iterations"]
+    assert its["rap"] < its["bj"], its
