@@ -234,12 +234,245 @@ def chain_probe(silu, dev, levels=8192, reps=20):
     return 1e3 * ms.value / max(cnt.value, 1) / levels
 
 
+# ---------------------------------------------------------------------------
+# batched systems: 512 convection-diffusion systems, ILU(0) + GMRES(20) each, one persistent launch
+# ---------------------------------------------------------------------------
+BATCH_COUNT, BATCH_SEED, BATCH_RESTART, BATCH_RTOL, BATCH_MAXIT = 512, 4, 20, 1e-8, 5000
+
+
+def batch_algorithmic_bytes(mats, its, m):
+    """Algorithmic bytes of one batched launch, counted as the measurement table does: per system the ILU(0)
+    numeric factorization (12 bytes read and 8 written per entry), and per GMRES iteration one SpMV
+    (12 nnz + 4(n+1) + 16n), the L and U solves (12 nnz(strict L or U) + 4(n+1) + 16n, + 8n for U's diagonal)
+    and the MGS step of its Arnoldi index j (2j + 4) 8n; plus per restart cycle the true residual and the
+    update x += M^-1 V c (V read once, two solves)."""
+    total = 0.0
+    for M, it in zip(mats, its):
+        n, nnz = M.n, M.nnz
+        rows = np.repeat(np.arange(n), np.diff(M.row_ptr))
+        nl = int(np.count_nonzero(M.col < rows))
+        nu = int(np.count_nonzero(M.col > rows))
+        spmv = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n
+        trsv = 12.0 * (nl + nu) + 8.0 * (n + 1) + 32.0 * n + 8.0 * n
+        total += 20.0 * nnz
+        cycles = -(-int(it) // m) if it else 0
+        for k in range(int(it)):
+            j = k % m
+            total += spmv + trsv + (2 * j + 4) * 8.0 * n
+        total += cycles * (spmv + 8.0 * n + trsv + 8.0 * n * (m + 1))
+    return total
+
+
+def batch_cpu_worker(first: int, count: int) -> None:
+    """Oracle process of the batched baseline: ILU(0) + GMRES(20) of systems first .. first+count-1."""
+    import oracle
+    import synth
+
+    params = synth.convdiff_batch_params(BATCH_COUNT, BATCH_SEED)[first:first + count]
+    t = 0.0
+    done = 0
+    for p in params:
+        M = synth.convdiff5(*p)
+        b = M.matvec(np.ones(M.n))
+        t0 = time.perf_counter()
+        P = oracle.Precond(M, None, 1, method=oracle.BJ, interior_fact=oracle.ILU0)
+        oracle.gmres(M, P, b, rtol=BATCH_RTOL, restart=BATCH_RESTART, maxit=BATCH_MAXIT)
+        t += time.perf_counter() - t0
+        done += 1
+    print(json.dumps({"systems": done, "seconds": t}), flush=True)
+
+
+def bench_batch(args) -> None:
+    import torch
+
+    import paper_2303_08881_amd as silu
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    mats, bs = synth.convdiff_batch(BATCH_COUNT, BATCH_SEED)
+    A, sr = synth.block_diagonal(mats)
+    Ad = silu.DeviceCSR.from_host(A, dev)
+    bd = torch.as_tensor(np.concatenate(bs)).to(dev)
+    x = torch.zeros_like(bd)
+    side = torch.cuda.Stream()
+    m = BATCH_RESTART
+    with torch.cuda.stream(side):
+        B = silu.batch_setup(Ad, sr, restart=m)
+        merge, wpc, tune_ms = B.tune(Ad.val, bd, x, rtol=BATCH_RTOL, restart=m, maxit=BATCH_MAXIT)
+        x.zero_()
+        B.capture(Ad.val, bd, x, rtol=BATCH_RTOL, restart=m, maxit=BATCH_MAXIT)
+        for _ in range(max(args.warmup, 1)):
+            x.zero_()
+            B.replay()
+        side.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        launch_ms = []
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            x.zero_()
+            e0.record()
+            B.replay()
+            e1.record()
+            e1.synchronize()
+            launch_ms.append(e0.elapsed_time(e1))
+        side.synchronize()
+        total = time.perf_counter() - t_start
+    its, rel, st = B.results()
+    sched = [int(v) for v in B.export("schedule")]
+    nbytes = batch_algorithmic_bytes(mats, its, m)
+    avg_ms = float(np.mean(launch_ms))
+    gbs = nbytes / (avg_ms * 1e-3) / 1e9
+    result = {
+        "metric": "solves/s + p50/p99 latency at rtol 1e-8; TRSV/SpMV HBM GB/s vs plain FP64",
+        "value": round(BATCH_COUNT * args.steps / total, 2),
+        "unit": "systems/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(total / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "convdiff_batch512",
+                   "description": "512 independent 2D 5-point upwind convection-diffusion systems, sides "
+                                  "log-uniform in [32, 256], eps log-U[1e-3, 1], theta U[0, pi), Pe U[0, 50], "
+                                  "seed 4; ILU(0) + GMRES(20) to rtol 1e-8 each, factorization and solve of "
+                                  "all systems in one persistent launch, replayed from a HIP graph",
+                   "systems": BATCH_COUNT, "n": A.n, "nnz": A.nnz, "restart": m, "rtol": BATCH_RTOL},
+        "launch_ms_p50": round(float(np.percentile(launch_ms, 50)), 3),
+        "launch_ms_p99": round(float(np.percentile(launch_ms, 99)), 3),
+        "schedule": {"entries_per_row": sched[0], "merge": sched[1], "workgroups_per_cu": sched[2],
+                     "grid": sched[3], "tuned_ms": round(tune_ms, 3)},
+        "iterations": {"min": int(its.min()), "median": int(np.median(its)), "max": int(its.max()),
+                       "total": int(its.sum())},
+        "all_converged": bool(np.all(st == 0)), "max_relres": float(rel.max()),
+        "roofline": {"kernel": "k_batch_solve", "bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None,
+                     "avg_launch_us": round(avg_ms * 1e3, 1), "bytes_per_launch": nbytes},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        import subprocess
+
+        sample = 16
+        cmd = [sys.executable, os.path.abspath(__file__), "--batch-cpu-worker", "0", str(sample)]
+        env = dict(os.environ, OMP_NUM_THREADS="1", HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+        so = subprocess.run(cmd, stdout=subprocess.PIPE, env=env, text=True, check=True).stdout
+        o = json.loads(so.strip().splitlines()[-1])
+        result["cpu_baseline"] = {"value": round(o["systems"] / o["seconds"], 3), "unit": "systems/s", "cores": 1,
+                                  "kind": "oracle",
+                                  "sample": f"the first {sample} of the 512 systems (setup + GMRES(20) each), one "
+                                            "process", "cpu_model": cpu_model()}
+    print(json.dumps(result), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# serving: Poisson arrivals of mixed requests, resident factors per matrix id
+# ---------------------------------------------------------------------------
+SERVE_REQUESTS, SERVE_SLOTS, SERVE_RESTART, SERVE_RTOL, SERVE_MAXIT = 64, 4, 50, 1e-8, 2000
+SERVE_BUDGET = 96 << 30
+
+
+def bench_serve(args) -> None:
+    import threading
+
+    import torch
+
+    import paper_2303_08881_amd as silu
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    reqs = synth.request_stream(SERVE_REQUESTS, seed=5)
+    mats, ddev = {}, {}
+    for r in reqs:
+        if r.matrix_id not in mats:
+            A, part, p = synth.build_matrix(r)
+            mats[r.matrix_id] = (A, p)
+            ddev[r.matrix_id] = (silu.DeviceCSR.from_host(A, dev), torch.as_tensor(part).to(dev), p)
+    bs = [torch.as_tensor(synth.uniform_rhs(mats[r.matrix_id][0].n, r.rhs_seed)).to(dev) for r in reqs]
+    xs = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    base = dict(method=silu.SCHUR, interior_fact=silu.ILU0, interface_fact=silu.MILU0, inner_iters=3)
+
+    def run(slots, prec, arrivals=None):
+        """One pass over the stream on a fresh server; arrivals None = all queued at once (closed loop)."""
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        S = silu.Server(slots=slots, budget_bytes=SERVE_BUDGET, factor_prec=prec, **base)
+        recs = []
+        waiter = threading.Thread(target=lambda: recs.extend(S.wait() for _ in reqs))
+        t0 = time.perf_counter()
+        waiter.start()
+        for q, r in enumerate(reqs):
+            if arrivals is not None:
+                delay = t0 + arrivals[q] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            Ad, pd, p = ddev[r.matrix_id]
+            S.submit(r.matrix_id, bs[q], xs[q], A=Ad, part=pd, nparts=p, rtol=SERVE_RTOL, restart=SERVE_RESTART,
+                     maxit=SERVE_MAXIT, sync=False)
+        waiter.join()
+        st = S.stats()
+        S.close()
+        first = min(rec["submit_us"] for rec in recs)
+        last = max(rec["done_us"] for rec in recs)
+        lat = np.array([(rec["done_us"] - rec["submit_us"]) * 1e-3 for rec in recs])
+        return {"solves_per_s": round(len(recs) / ((last - first) * 1e-6), 3),
+                "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                "all_converged": all(rec["status"] == 0 for rec in recs),
+                "max_relres": max(rec["final_relres"] for rec in recs),
+                "iterations_total": int(sum(rec["iterations"] for rec in recs)),
+                "setup_ms_total": round(sum(rec["setup_ms"] for rec in recs), 2),
+                "solve_ms_total": round(sum(rec["solve_ms"] for rec in recs), 2),
+                "hits": st["hits"], "misses": st["misses"], "peak_bytes": st["peak_bytes"]}
+
+    for _ in range(max(args.warmup, 1)):
+        run(SERVE_SLOTS, silu.PREC_F32)
+    t_start = time.perf_counter()
+    closed = [run(SERVE_SLOTS, silu.PREC_F32) for _ in range(args.steps)]
+    total = time.perf_counter() - t_start
+    cap = float(np.median([c["solves_per_s"] for c in closed]))
+    sweep = []
+    for frac in (0.25, 0.5, 0.75, 1.0, 1.25):
+        rate = frac * cap
+        res = run(SERVE_SLOTS, silu.PREC_F32, synth.arrival_times(len(reqs), rate))
+        sweep.append(dict(offered_per_s=round(rate, 3), **res))
+    plain = run(1, silu.PREC_F64)
+    serial32 = run(1, silu.PREC_F32)
+    ns = sorted(a.n for a, _ in mats.values())
+    result = {
+        "metric": "solves/s + p50/p99 latency at rtol 1e-8; TRSV/SpMV HBM GB/s vs plain FP64",
+        "value": round(cap, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(total / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "serve_mixed64",
+                   "description": "64 requests (seed 5): half anisotropic 2D/3D diffusion, half power-law "
+                                  "nonsymmetric, n log-U[1e3, 1e6], 70% new right-hand sides for one of the "
+                                  "last 32 matrix ids; two-level ILU (ILU(0) interior, MILU(0) local Schur "
+                                  "complements, 3 inner GMRES steps) with FP32 factors inside FP64 FGMRES(50) "
+                                  "to rtol 1e-8; 4 slots, device-memory budget 96 GiB; one step = the whole "
+                                  "stream queued at once on a fresh server",
+                   "requests": len(reqs), "matrices": len(mats), "n_min": ns[0], "n_max": ns[-1],
+                   "slots": SERVE_SLOTS},
+        "p50_ms": closed[-1]["p50_ms"], "p99_ms": closed[-1]["p99_ms"],
+        "closed_loop": closed[-1],
+        "rate_sweep": sweep,
+        "plain_fp64_one_slot": plain,
+        "fp32_one_slot": serial32,
+        "speedup_vs_plain_fp64": round(cap / plain["solves_per_s"], 3),
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="aniso3d_128_slab16", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="aniso3d_128_slab16",
+                    choices=sorted(WORKLOADS) + ["convdiff_batch512", "serve_mixed64"])
+    ap.add_argument("--batch-cpu-worker", nargs=2, type=int, help=argparse.SUPPRESS)
     ap.add_argument("--factor-prec", default="f64", choices=["f64", "f32", "f16"],
                     help="storage precision of the triangular factors (the solves run in FP32 for f32 and f16; "
                          "everything else stays FP64)")
@@ -256,6 +489,9 @@ def main():
     if args.cpu_worker:
         cpu_worker(args.workload, args.factor_prec, args.cpu_sample_iters)
         return
+    if args.batch_cpu_worker:
+        batch_cpu_worker(*args.batch_cpu_worker)
+        return
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload)
         return
@@ -263,6 +499,12 @@ def main():
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the subdomains of this solver live on one "
               "device at their real per-GPU shape and no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "convdiff_batch512":
+        bench_batch(args)
+        return
+    if args.workload == "serve_mixed64":
+        bench_serve(args)
+        return
 
     import torch
 

@@ -40,8 +40,12 @@ extern "C" {
 #define ILU_ERR_TIMEOUT (-8)    /* a bounded dependency wait expired (internal error) */
 
 /* ---- option values ---- */
-#define ILU_METHOD_BJ 0    /* block Jacobi: Section 2.1, Alg. 4                    */
-#define ILU_METHOD_SCHUR 1 /* additive two-level: Alg. 1, Section 3.2, Alg. 5      */
+#define ILU_METHOD_BJ 0    /* block Jacobi: Section 2.1, algorithm "Block Jacobi ILU on GPU" */
+#define ILU_METHOD_SCHUR 1 /* additive two-level: algorithm "Additive block ILU solve",
+                              Section 3.2, algorithm "Additive SCHUR-ILU on GPU"          */
+#define ILU_METHOD_RAP 2   /* multiplicative two-level: Section 2.2.3, algorithm
+                              "Two-level multiplicative solve"; Section 3.3, eqs.
+                              (20)-(29), algorithm "Multiplicative RAP-ILU on GPU"       */
 #define ILU_FACT_ILU0 0    /* ILU(0) on the pattern of the block                    */
 #define ILU_FACT_MILU0 1   /* modified ILU(0): dropped fill added to the diagonal,
                               Section 2.3 eq. (16)                                  */
@@ -70,18 +74,24 @@ typedef struct {
  *  interior_fact  factor of each subdomain block A_i (BJ), or of the interior
  *                 rows plus the partial elimination of the interface rows
  *                 (SCHUR, eq. (17));
+ *                 RAP: the factor of each whole block A_i (interior and
+ *                 interface rows), whose (1,1), (2,1), (1,2) and (2,2) blocks
+ *                 give L_B U_B, W~, Z~ and L_S U_S (eq. (20)); MILU(0) makes
+ *                 the coarse preconditioner keep RAP 1 = L_S U_S 1;
  *  interface_fact SCHUR only: factor of each local Schur complement S~_i,
  *                 whose triangular factors precondition the reduced system
  *                 (eq. (18)-(19));
+ *  smooth_fact    RAP only: factor of the smoother, a second block-Jacobi
+ *                 factorization of every A_i (ILU(0) in the paper);
  *  droptol, lfil  ILUT: an entry w_j of row i is dropped when
  *                 |w_j| < droptol * ||a_i||_2; at most lfil entries are kept
  *                 in the L part and in the U part of each row (the Schur part
  *                 of a partially eliminated row counts as its U part); the
  *                 diagonal is always kept.  lfil < 0 means no limit (only for
  *                 n <= 8192).
- *  inner_iters    SCHUR: GMRES steps on the reduced system per apply;
+ *  inner_iters    SCHUR, RAP: GMRES steps on the reduced system per apply;
  *                 0 applies the local Schur factors once (block Jacobi on S).
- *  inner_rtol     SCHUR: stop the inner GMRES once its residual estimate is
+ *  inner_rtol     SCHUR, RAP: stop the inner GMRES once its residual estimate is
  *                 <= inner_rtol times the norm of its right-hand side.
  *  pivot_mode     ILU_PIVOT_ERROR: a zero pivot fails setup with
  *                 ILU_ERR_ZERO_PIVOT.  ILU_PIVOT_PERTURB: a pivot with
@@ -119,6 +129,7 @@ typedef struct {
   double pivot_tol;
   int32_t trsv_mode;
   int32_t factor_prec;
+  int32_t smooth_fact;
 } ilu_options_t;
 
 typedef struct {
@@ -135,8 +146,10 @@ typedef struct ilu_precond ilu_precond_t;
 void ilu_default_options(ilu_options_t *opt);
 
 /*
- * ilu_setup -- build the preconditioner P of A (Alg. 4 setup for BJ, Alg. 5
- * setup for SCHUR), entirely on the device.
+ * ilu_setup -- build the preconditioner P of A (the setup procedures of the
+ * algorithms named at ILU_METHOD_*), entirely on the device.  RAP also keeps
+ * a copy of A (its coarse operator multiplies by A) and builds the smoother's
+ * factors as a second block-Jacobi preconditioner inside P.
  *  A        device CSR (validated on the device: ILU_ERR_CSR on bad input).
  *  d_part   device int32[n], subdomain of each row (0 <= part < nparts), or
  *           NULL for a single subdomain.  Rows coupled to another subdomain
@@ -154,12 +167,25 @@ int ilu_setup(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts, const i
 
 /*
  * ilu_apply -- z = M^{-1} r (device vectors of length n, original numbering),
- * asynchronous on `stream`.  BJ: gather, L solve, U solve, scatter (Alg. 4).
- * SCHUR: f' = L_B^-1 f, g' = g - W f', inner GMRES on the reduced system,
- * u = U_B^-1 (f' - Z y), scatter (Section 3.2).  r and z must not alias.
- * Not re-entrant per handle (the workspace lives in P).
+ * asynchronous on `stream`.  BJ: gather, L solve, U solve, scatter (Section
+ * 3.1).  SCHUR: f' = L_B^-1 f, g' = g - W f', inner GMRES on the reduced
+ * system, u = U_B^-1 (f' - Z y), scatter (Section 3.2).  RAP: x = the
+ * smoother's block-Jacobi solve of r; g = R (r - A x); v from the inner GMRES
+ * on (L_S U_S)^-1 R A P v = (L_S U_S)^-1 g; z = x + P v (Section 3.3).  r and
+ * z must not alias.  Not re-entrant per handle (the workspace lives in P).
  */
 int ilu_apply(ilu_precond_t *P, const double *d_r, double *d_z, void *stream);
+
+/*
+ * ilu_rap_matvec -- out = R A P v with R = (-W~ L_B^-1, I) and
+ * P = (-U_B^-1 Z~; I) left unformed (Section 3.3, eqs. (21) and (28)): one
+ * U_B solve with the Z~ columns, one product with A, one L_B solve with the
+ * W~ rows.  Only for a RAP handle (ILU_ERR_INVALID_ARG otherwise).  d_v and
+ * d_out: device vectors of length n_S in the interface numbering (interface
+ * row i is original row perm[n_B + i], see ilu_export code 0); they must not
+ * alias.  Asynchronous on `stream`; shares P's workspace like ilu_apply.
+ */
+int ilu_rap_matvec(ilu_precond_t *P, const double *d_v, double *d_out, void *stream);
 
 /*
  * fgmres_solve -- right-preconditioned flexible GMRES(restart) for A x = b
@@ -328,6 +354,70 @@ int ilu_batch_replay(ilu_batch_t *B, void *stream);
 int ilu_batch_export(ilu_batch_t *B, int32_t what, void *h_buf, int64_t *len);
 
 void ilu_batch_destroy(ilu_batch_t *B);
+
+/*
+ * ---- Serving: continuous batching of solve requests ----
+ * A server owns `slots` worker threads on the current device, each with its
+ * own stream, and a cache of preconditioners keyed by a caller-chosen matrix
+ * id.  A request is one solve A x = b (fgmres_solve with the server's
+ * options); for an id already resident the setup is skipped.  Requests that
+ * arrive while others run start as soon as a slot is free and the device
+ * bytes they need fit into the budget beside the resident factors and the
+ * other running requests; idle factors are evicted least-recently-used first
+ * to make room.  Two requests for one id never run at once (a handle is not
+ * re-entrant): the later one waits.  Each request issues the same kernels as
+ * a lone call would, so its result does not depend on the mix.
+ */
+typedef struct ilu_server ilu_server_t;
+
+typedef struct {
+  int64_t ticket;
+  int64_t matrix_id;
+  int32_t status;       /* the solve's return code: 0, ILU_NOT_CONVERGED or ILU_ERR_*      */
+  int32_t iterations;
+  double final_relres;
+  int32_t cache_hit;    /* 1: the factors of matrix_id were resident                      */
+  int32_t slot;         /* worker that ran it (-1: rejected before running)               */
+  double submit_us;     /* host steady clock, microseconds since ilu_server_create        */
+  double start_us;
+  double done_us;
+  double setup_ms;      /* device time of the setup (0 on a cache hit)                    */
+  double solve_ms;      /* device time of the solve                                      */
+} ilu_request_t;
+
+/* slots in [1, 64]; budget_bytes: device bytes that resident factors and
+ * running requests may hold together; opt: options of every setup (NULL =
+ * defaults).  Threads start at once; the calling thread's device is used. */
+int ilu_server_create(int32_t slots, int64_t budget_bytes, const ilu_options_t *opt, ilu_server_t **S);
+
+/*
+ * Queue one solve.  A: the matrix (device CSR) when matrix_id is not resident,
+ * else ignored (may be NULL; a request for an unknown id without A completes
+ * with ILU_ERR_INVALID_ARG).  d_part/nparts as in ilu_setup (used only when
+ * the setup runs).  d_b, d_x: device vectors of the matrix's size, x0 in and
+ * the solution out.  A, d_part, d_b and d_x must stay valid until the request
+ * has completed.  *ticket receives the request's ticket (0, 1, ... in
+ * submission order).  Returns at once.
+ */
+int ilu_server_submit(ilu_server_t *S, int64_t matrix_id, const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
+                      const double *d_b, double *d_x, double rtol, int32_t restart, int32_t maxit, int64_t *ticket);
+
+/* Block until the request `ticket` has completed (ticket < 0: the next one to
+ * complete, in completion order) and copy its record to *out; the ticket is
+ * then collected.  If the request failed (out->status < 0) ilu_last_error()
+ * holds its message.  Returns ILU_ERR_INVALID_ARG for an unknown or already
+ * collected ticket, or when nothing is outstanding. */
+int ilu_server_wait(ilu_server_t *S, int64_t ticket, ilu_request_t *out);
+
+/* Counters, first `count` of: [0] bytes held (resident factors + running
+ * reservations), [1] peak of [0], [2] resident matrices, [3] cache hits,
+ * [4] misses, [5] evictions, [6] queued requests, [7] running requests,
+ * [8] budget. */
+int ilu_server_stats(ilu_server_t *S, int64_t *h_stats, int32_t count);
+
+/* Finish every queued request, stop the workers and free all resident
+ * factors.  Records not collected are dropped. */
+void ilu_server_destroy(ilu_server_t *S);
 
 /* Sizes: n, n_B (interior rows), n_S (interface rows), nparts. */
 int ilu_info(ilu_precond_t *P, int64_t *n, int64_t *nB, int64_t *nS, int32_t *nparts);

@@ -10,6 +10,7 @@ from __future__ import annotations
 from .binding import (  # noqa: F401
     BJ,
     SCHUR,
+    RAP,
     ILU0,
     MILU0,
     ILUT,
@@ -31,6 +32,7 @@ from .binding import (  # noqa: F401
     spmv,
     Batch,
     batch_setup,
+    Server,
     memory_trim,
     lib,
     LIB_PATH,

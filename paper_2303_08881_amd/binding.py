@@ -1,7 +1,7 @@
 """ctypes binding of the C ABI in include/schurilu.h.
 
 Names follow the C entry points: ``setup`` -> ilu_setup, ``Precond.apply`` ->
-ilu_apply, ``fgmres`` -> fgmres_solve, ``spmv`` -> csr_spmv,
+ilu_apply, ``Precond.rap_matvec`` -> ilu_rap_matvec, ``fgmres`` -> fgmres_solve, ``spmv`` -> csr_spmv,
 ``Precond.export`` -> ilu_export.  Tensors must live on the current HIP
 device; the current torch stream is passed to every call.
 """
@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libschurilu.so")
 
-BJ, SCHUR = 0, 1
+BJ, SCHUR, RAP = 0, 1, 2
 ILU0, MILU0, ILUT = 0, 1, 2
 PIVOT_ERROR, PIVOT_PERTURB = 0, 1
 TRSV_AUTO, TRSV_LEVELS, TRSV_BLOCK = 0, 1, 2
@@ -48,7 +48,14 @@ class _Opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("interior_fact", C.c_int32), ("interface_fact", C.c_int32),
                 ("droptol", C.c_double), ("lfil", C.c_int32), ("inner_iters", C.c_int32),
                 ("inner_rtol", C.c_double), ("pivot_mode", C.c_int32), ("pivot_tol", C.c_double),
-                ("trsv_mode", C.c_int32), ("factor_prec", C.c_int32)]
+                ("trsv_mode", C.c_int32), ("factor_prec", C.c_int32), ("smooth_fact", C.c_int32)]
+
+
+class _Req(C.Structure):
+    _fields_ = [("ticket", C.c_int64), ("matrix_id", C.c_int64), ("status", C.c_int32), ("iterations", C.c_int32),
+                ("final_relres", C.c_double), ("cache_hit", C.c_int32), ("slot", C.c_int32),
+                ("submit_us", C.c_double), ("start_us", C.c_double), ("done_us", C.c_double),
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
 
 
 class _Res(C.Structure):
@@ -71,6 +78,7 @@ def lib():
         L.ilu_default_options.restype = None
         L.ilu_setup.argtypes = [vp, vp, i32, vp, vp, C.POINTER(vp)]
         L.ilu_apply.argtypes = [vp, vp, vp, vp]
+        L.ilu_rap_matvec.argtypes = [vp, vp, vp, vp]
         L.fgmres_solve.argtypes = [vp, vp, vp, vp, d, i32, i32, vp, vp, vp]
         L.csr_spmv.argtypes = [vp, vp, vp, vp]
         L.ilu_destroy.argtypes = [vp]
@@ -93,6 +101,12 @@ def lib():
         L.ilu_batch_capture.argtypes = [vp, vp, vp, vp, d, i32, i32, vp]
         L.ilu_batch_replay.argtypes = [vp, vp]
         L.ilu_batch_export.argtypes = [vp, i32, vp, C.POINTER(i64)]
+        L.ilu_server_create.argtypes = [i32, i64, vp, C.POINTER(vp)]
+        L.ilu_server_submit.argtypes = [vp, i64, vp, vp, i32, vp, vp, d, i32, i32, C.POINTER(i64)]
+        L.ilu_server_wait.argtypes = [vp, i64, vp]
+        L.ilu_server_stats.argtypes = [vp, vp, i32]
+        L.ilu_server_destroy.argtypes = [vp]
+        L.ilu_server_destroy.restype = None
         L.ilu_batch_destroy.argtypes = [vp]
         L.ilu_batch_destroy.restype = None
         _lib = L
@@ -143,15 +157,17 @@ class DeviceCSR:
 
 
 def _options(method=BJ, interior_fact=ILU0, interface_fact=ILU0, droptol=0.0, lfil=-1, inner_iters=3,
-             inner_rtol=0.0, pivot_mode=PIVOT_ERROR, pivot_tol=0.0, trsv_mode=TRSV_AUTO, factor_prec=PREC_F64):
+             inner_rtol=0.0, pivot_mode=PIVOT_ERROR, pivot_tol=0.0, trsv_mode=TRSV_AUTO, factor_prec=PREC_F64,
+             smooth_fact=ILU0):
     return _Opts(method, interior_fact, interface_fact, droptol, lfil, inner_iters, inner_rtol, pivot_mode,
-                 pivot_tol, trsv_mode, factor_prec)
+                 pivot_tol, trsv_mode, factor_prec, smooth_fact)
 
 
 # Every live handle, so that the exit hook below can release them while the
 # HIP runtime (and any profiler attached to it) is still up.
 _live: "weakref.WeakSet[Precond]" = weakref.WeakSet()
 _live_batches: "weakref.WeakSet[Batch]" = weakref.WeakSet()
+_live_servers: "weakref.WeakSet[Server]" = weakref.WeakSet()
 
 
 @atexit.register
@@ -161,7 +177,7 @@ def _release_at_exit():
     runtime's own exit handlers."""
     if _lib is None:
         return
-    for p in list(_live) + list(_live_batches):
+    for p in list(_live_servers) + list(_live) + list(_live_batches):
         p.close()
     _lib.ilu_kernel_timing(0)
     _lib.ilu_memory_trim()
@@ -189,6 +205,14 @@ class Precond:
             z = torch.empty_like(r)
         _check(lib().ilu_apply(self._h, _ptr(r), _ptr(z), _stream()))
         return z
+
+    def rap_matvec(self, v, out=None):
+        """ilu_rap_matvec: out = R A P v (RAP handles; interface numbering, length n_S)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(v)
+        _check(lib().ilu_rap_matvec(self._h, _ptr(v), _ptr(out), _stream()))
+        return out
 
     def info(self):
         n, nB, nS, npart = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
@@ -329,3 +353,68 @@ def batch_setup(A: DeviceCSR, sys_row, restart=20) -> Batch:
 def memory_trim():
     """ilu_memory_trim: free the library's cached device blocks."""
     lib().ilu_memory_trim()
+
+
+SERVER_STATS = ("bytes", "peak_bytes", "resident", "hits", "misses", "evictions", "queued", "running", "budget")
+
+
+class Server:
+    """Handle of ilu_server_create: `slots` workers with their own streams, resident factors per matrix id, admission
+    by a device-memory budget.  Every request is one fgmres_solve with the server's options."""
+
+    def __init__(self, slots=4, budget_bytes=16 << 30, **opts):
+        h = C.c_void_p()
+        o = _options(**opts)
+        _check(lib().ilu_server_create(int(slots), int(budget_bytes), C.byref(o), C.byref(h)))
+        self._h = h
+        self._keep = {}  # ticket -> the device tensors a queued or running request reads
+        _live_servers.add(self)
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ilu_server_destroy(self._h)
+        self._h = None
+        self._keep = {}
+
+    def submit(self, matrix_id, b, x, A: DeviceCSR | None = None, part=None, nparts=1, rtol=1e-8, restart=50,
+               maxit=1000, sync=True) -> int:
+        """ilu_server_submit; returns the ticket.  A is needed only for an id that is not resident.  With sync the
+        current stream is synchronised first, so the server's streams see b and x as written."""
+        torch = _torch()
+        if sync:
+            torch.cuda.current_stream().synchronize()
+        keep = [b, x]
+        aref = None
+        pp = C.c_void_p(0)
+        if A is not None:
+            aref = A.ref
+            keep.append(A)
+            if part is not None:
+                if not (isinstance(part, torch.Tensor) and part.is_cuda):
+                    part = torch.as_tensor(np.asarray(part, dtype=np.int32)).to(A.val.device)
+                    torch.cuda.current_stream().synchronize()
+                keep.append(part)
+                pp = C.c_void_p(part.data_ptr())
+        t = C.c_int64()
+        _check(lib().ilu_server_submit(self._h, int(matrix_id), aref, pp, int(nparts), _ptr(b), _ptr(x), float(rtol),
+                                       int(restart), int(maxit), C.byref(t)))
+        self._keep[t.value] = keep
+        return t.value
+
+    def wait(self, ticket=-1) -> dict:
+        """ilu_server_wait: the record of `ticket` (or of the next request to complete) as a dict."""
+        r = _Req()
+        _check(lib().ilu_server_wait(self._h, int(ticket), C.byref(r)))
+        self._keep.pop(r.ticket, None)
+        out = {f: getattr(r, f) for f, _ in _Req._fields_}
+        if r.status < 0:
+            out["error"] = lib().ilu_last_error().decode()
+        return out
+
+    def stats(self) -> dict:
+        v = np.zeros(len(SERVER_STATS), dtype=np.int64)
+        _check(lib().ilu_server_stats(self._h, v.ctypes.data_as(C.c_void_p), len(SERVER_STATS)))
+        return dict(zip(SERVER_STATS, (int(x) for x in v)))

@@ -40,6 +40,18 @@ static int fail(int code, const char *fmt, ...) {
   return code;
 }
 
+namespace silu {
+int api_fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+}  // namespace silu
+
 int silu_hip_fail(hipError_t e, int line) {
   return fail(ILU_ERR_HIP, "HIP error '%s' (capi.cpp:%d)", hipGetErrorString(e), line);
 }
@@ -139,24 +151,30 @@ void cache_free(void *p) {
 
 struct Mem {
   std::vector<void *> ptrs;
+  size_t bytes = 0;  // requested bytes of the blocks held
   ~Mem() { release(); }
-  void release() {
+  // sync = false: the owner has already waited for every stream that used
+  // these blocks, so the device-wide wait (which would also wait for other
+  // streams' unrelated work) is skipped
+  void release(bool sync = true) {
     if (ptrs.empty()) return;
-    (void)hipDeviceSynchronize();  // kernels queued on these blocks have finished
+    if (sync) (void)hipDeviceSynchronize();  // kernels queued on these blocks have finished
     for (void *p : ptrs) cache_free(p);
     ptrs.clear();
+    bytes = 0;
   }
   template <typename T>
   int alloc(T **out, int64_t count) {
     *out = nullptr;
-    size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    size_t nb = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
     void *p = nullptr;
-    hipError_t e = cache_alloc(&p, bytes);
+    hipError_t e = cache_alloc(&p, nb);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      return fail(ILU_ERR_OOM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+      return fail(ILU_ERR_OOM, "device allocation of %zu bytes failed: %s", nb, hipGetErrorString(e));
     }
     ptrs.push_back(p);
+    bytes += nb;
     *out = (T *)p;
     return 0;
   }
@@ -306,6 +324,14 @@ struct ilu_precond {
   int64_t *blk_starts = nullptr;  // device: interior starts, interface starts, interface starts (local)
   double setup_ms = 0.0;
   GmresWork *gw = nullptr;
+  // multiplicative (RAP) method: a copy of A, the smoother (a block-Jacobi
+  // preconditioner of its own), and work vectors of length n (rx: the
+  // smoothed iterate, rw, ru: products with A) and n_S (ry: the coarse
+  // correction in the level-scheduled mode)
+  Csr Acp;
+  ilu_precond *smoother = nullptr;
+  double *rx = nullptr, *rw = nullptr, *ru = nullptr, *ry = nullptr;
+  ~ilu_precond();
 };
 
 // ---------------------------------------------------------------------------
@@ -895,6 +921,50 @@ static double spmv_bytes(int64_t n, int64_t nnz, bool resid) {
   return 12.0 * (double)nnz + 4.0 * (double)(n + 1) + 16.0 * (double)n + (resid ? 8.0 * (double)n : 0.0);
 }
 
+ilu_precond::~ilu_precond() {
+  if (host_pinned) (void)hipHostFree(host_pinned);
+  host_pinned = nullptr;
+  delete gw;
+  delete smoother;
+}
+
+namespace silu {
+int64_t precond_bytes(const ilu_precond *P) {
+  if (!P) return 0;
+  int64_t b = (int64_t)P->mem.bytes;
+  if (P->gw) b += (int64_t)P->gw->mem.bytes;
+  return b + precond_bytes(P->smoother);
+}
+
+static void release_nosync(ilu_precond *P) {
+  if (!P) return;
+  P->mem.release(false);
+  if (P->gw) P->gw->mem.release(false);
+  release_nosync(P->smoother);
+}
+
+void precond_destroy_idle(ilu_precond *P) {
+  if (!P) return;
+  (void)hipSetDevice(P->device);
+  release_nosync(P);
+  delete P;
+}
+
+int dev_alloc(void **p, size_t bytes) {
+  const hipError_t e = cache_alloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(ILU_ERR_OOM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+  }
+  return 0;
+}
+
+void dev_free(void *p) {
+  if (p) cache_free(p);
+}
+}  // namespace silu
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -913,6 +983,7 @@ void ilu_default_options(ilu_options_t *o) {
   o->pivot_tol = 0.0;
   o->trsv_mode = ILU_TRSV_AUTO;
   o->factor_prec = ILU_PREC_F64;
+  o->smooth_fact = ILU_FACT_ILU0;
 }
 
 const char *ilu_last_error(void) { return g_err.c_str(); }
@@ -1108,7 +1179,25 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
 
   // 7. workspaces
   RC(mem.alloc(&P->xp, n));
-  if (schur && nS > 0) {
+  const bool rap = opt->method == ILU_METHOD_RAP;
+  if (rap) {
+    // the coarse operator R A P multiplies by A itself: keep a copy
+    P->Acp.n = n;
+    P->Acp.nnz = A->nnz;
+    RC(mem.alloc(&P->Acp.rp, n + 1));
+    RC(mem.alloc(&P->Acp.ci, A->nnz));
+    RC(mem.alloc(&P->Acp.v, A->nnz));
+    HIPCK(hipMemcpyAsync(P->Acp.rp, A->d_row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+    if (A->nnz) {
+      HIPCK(hipMemcpyAsync(P->Acp.ci, A->d_col, sizeof(int32_t) * A->nnz, hipMemcpyDeviceToDevice, s));
+      HIPCK(hipMemcpyAsync(P->Acp.v, A->d_val, sizeof(double) * A->nnz, hipMemcpyDeviceToDevice, s));
+    }
+    RC(mem.alloc(&P->rx, n));
+    RC(mem.alloc(&P->rw, n));
+    RC(mem.alloc(&P->ru, n));
+    RC(mem.alloc(&P->ry, nS));
+  }
+  if ((schur || rap) && nS > 0) {
     const int k = std::max(opt->inner_iters, 0);
     RC(mem.alloc(&P->iV, (int64_t)(k + 1) * nS));
     RC(mem.alloc(&P->iW, nS));
@@ -1125,6 +1214,7 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
     RC(mem.alloc(&P->iflags, 4));
   }
   HIPCK(hipStreamSynchronize(s));
+  tmp.release(false);  // the stream has finished with the temporaries
   return 0;
 }
 
@@ -1139,9 +1229,9 @@ int ilu_setup(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts, const i
   ilu_options_t opt;
   ilu_default_options(&opt);
   if (opt_in) opt = *opt_in;
-  if (opt.method != ILU_METHOD_BJ && opt.method != ILU_METHOD_SCHUR)
+  if (opt.method != ILU_METHOD_BJ && opt.method != ILU_METHOD_SCHUR && opt.method != ILU_METHOD_RAP)
     return fail(ILU_ERR_INVALID_ARG, "unknown method %d", opt.method);
-  for (int f : {opt.interior_fact, opt.interface_fact})
+  for (int f : {opt.interior_fact, opt.interface_fact, opt.smooth_fact})
     if (f != ILU_FACT_ILU0 && f != ILU_FACT_MILU0 && f != ILU_FACT_ILUT)
       return fail(ILU_ERR_INVALID_ARG, "unknown factorization %d", f);
   if (opt.inner_iters < 0 || opt.inner_iters > 1000) return fail(ILU_ERR_INVALID_ARG, "inner_iters out of range");
@@ -1163,6 +1253,17 @@ int ilu_setup(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts, const i
   }
   (void)hipEventRecord(e0, s);
   int rc = setup_impl(A, d_part, nparts, &opt, s, P);
+  if (rc == 0 && opt.method == ILU_METHOD_RAP) {
+    // the smoother: block Jacobi on the same subdomains with smooth_fact
+    ilu_options_t so = opt;
+    so.method = ILU_METHOD_BJ;
+    so.interior_fact = opt.smooth_fact;
+    P->smoother = new ilu_precond();
+    P->smoother->n = A->n;
+    P->smoother->nparts = nparts;
+    P->smoother->opt = so;
+    rc = setup_impl(A, d_part, nparts, &so, s, P->smoother);
+  }
   (void)hipEventRecord(e1, s);
   if (rc == 0) {
     float ms = 0.f;
@@ -1181,12 +1282,11 @@ int ilu_setup(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts, const i
   return 0;
 }
 
+
+
 void ilu_destroy(ilu_precond_t *P) {
   if (!P) return;
   (void)hipSetDevice(P->device);
-  if (P->host_pinned) (void)hipHostFree(P->host_pinned);
-  P->host_pinned = nullptr;
-  delete P->gw;
   delete P;
 }
 
@@ -1253,12 +1353,114 @@ static int apply_block(ilu_precond *P, const double *r, double *z, hipStream_t s
   // f'' = f' - Z y in U_B position order, u = U_B^-1 f'', then both halves to z
   RC(launch_upper_rhs(P->fmapU, nB, P->fL, P->Zr.rp, P->Zr.ci, P->Zr.v, P->yS, P->bU, s));
   RC(trsv(P, P->sU1, P->U1, P->DB, nB, P->bU, nullptr, P->uU, nullptr, nullptr, s, 1));
-  return launch_finish(P->uU, P->finB, nB, P->yS, P->finS, nS, z, s);
+  return launch_finish(P->uU, P->finB, nB, P->yS, P->finS, nS, nullptr, z, s);
+}
+
+// ---- multiplicative two-level method (Section 3.3) ----
+// out = R A P v with R = (-W L_B^-1, I) and P = (-U_B^-1 Z; I) unformed
+// (eq. (28)): a U_B solve with the Z columns, the product with A, an L_B
+// solve with the W rows.  Block mode: v in U_S position order, out in L_S
+// position order (the orders of the reduced-system vectors); level-scheduled
+// mode: both in the interface numbering.  Uses xp, bL, fL, bU, uU, ru, rw.
+static int rap_product(ilu_precond *P, const double *v, double *out, hipStream_t s) {
+  const int64_t n = P->n, nB = P->nB, nS = P->nS;
+  const Csr &A = P->Acp;
+  auto product = [&] {
+    return timed(ILU_K_SPMV, spmv_bytes(n, A.nnz, false), s,
+                 [&] { return launch_spmv(A.rp, A.ci, A.v, n, P->ru, P->rw, s, SPMV_A); });
+  };
+  if (P->block_mode) {
+    // P v: u = -U_B^-1 Z v in U_B order, then (u; v) in A's numbering
+    RC(launch_upper_rhs(P->fmapU, nB, nullptr, P->Zr.rp, P->Zr.ci, P->Zr.v, v, P->bU, s));
+    RC(trsv(P, P->sU1, P->U1, P->DB, nB, P->bU, nullptr, P->uU, nullptr, nullptr, s, 1));
+    RC(launch_finish(P->uU, P->finB, nB, v, P->finS, nS, nullptr, P->ru, s));
+    RC(product());
+    // R w = w_S - W L_B^-1 w_B, in L_S order
+    RC(launch_gather(P->rw, P->gmapL, nB, P->bL, s));
+    return trsv(P, P->sL1, P->L1, nullptr, 0, P->bL, nullptr, P->fL, nullptr, nullptr, s, 0, [&] {
+      return launch_rows_lower(P->Wr.rp, P->Wr.ci, P->Wr.v, nS, P->rw, P->gmapW, P->fL, out, s);
+    });
+  }
+  // the U solve of [U_B | Z] with a zero interior right-hand side and v in
+  // the interface slots gives -U_B^-1 Z v; both halves land in ru
+  double *xp = P->xp;
+  RC(fill_f64(xp, 0.0, nB, s));
+  RC(launch_copy(v, xp + nB, nS, s));
+  RC(launch_scatter(v, P->perm + nB, nS, P->ru, s));
+  RC(trsv(P, P->sU1, P->U1, P->DB, nB, xp, nullptr, xp, P->ru, P->perm, s, 1));
+  RC(product());
+  // [L_B; W] in one pass: xp_B = L_B^-1 w_B, xp_S = w_S - W xp_B
+  RC(trsv(P, P->sL1, P->L1, nullptr, 0, P->rw, P->perm, xp, nullptr, nullptr, s, 0));
+  return launch_copy(xp + nB, out, nS, s);
+}
+
+// k GMRES steps on (L_S U_S)^-1 R A P v = (L_S U_S)^-1 g (zero initial guess,
+// modified Gram-Schmidt, Givens; the early exits of inner_gmres), y = v
+static int inner_gmres_rap(ilu_precond *P, const double *gp, double *y, hipStream_t s) {
+  const int64_t nS = P->nS;
+  const int k = P->opt.inner_iters;
+  double *V = P->iV;
+  RC(trsv_schur(P, gp, V, s));
+  if (k == 0) return launch_copy(V, y, nS, s);
+  double *beta = P->iscal, *hn = P->iscal + 1, *est = P->iscal + 2;
+  int *stop = P->iflags, *nsteps = P->iflags + 1;
+  const int ldh = k + 1;
+  RC(launch_dot_partial(V, V, nS, P->ipa, s));
+  RC(launch_reduce_final(P->ipa, nS, beta, s));
+  RC(launch_init_krylov(P->ig, beta, stop, nsteps, s));
+  RC(launch_scale_copy(V, nullptr, beta, V, nS, nullptr, s));
+  for (int j = 0; j < k; j++) {
+    double *vj = V + (int64_t)j * nS, *w = V + (int64_t)(j + 1) * nS;
+    RC(rap_product(P, vj, P->it1, s));
+    RC(trsv_schur(P, P->it1, w, s));
+    double *pc = P->ipa, *pn = P->ipb;
+    RC(launch_dot_partial(w, V, nS, pc, s));
+    for (int i = 0; i <= j; i++) {
+      const double *vnext = i < j ? V + (int64_t)(i + 1) * nS : nullptr;
+      RC(launch_mgs_step(w, V + (int64_t)i * nS, pc, P->iH + i + (int64_t)ldh * j, vnext, nS, pn, stop, s));
+      std::swap(pc, pn);
+    }
+    RC(launch_givens_scale(P->iH, ldh, P->ics, P->isn, P->ig, j, pc, stop, nsteps, est, hn, beta,
+                           P->opt.inner_rtol, w, nS, s));
+  }
+  RC(launch_backsolve(P->iH, ldh, P->ig, nsteps, P->ic, s));
+  return launch_combine(y, V, nS, P->ic, nsteps, nS, false, s);
+}
+
+static int apply_impl(ilu_precond *P, const double *r, double *z, hipStream_t s);
+
+// x = the smoother's solve of r; g = R (r - A x); v from inner_gmres_rap;
+// z = x + P v
+static int apply_rap(ilu_precond *P, const double *r, double *z, hipStream_t s) {
+  const int64_t n = P->n, nB = P->nB, nS = P->nS;
+  const Csr &A = P->Acp;
+  RC(apply_impl(P->smoother, r, P->rx, s));
+  if (nS == 0) return launch_copy(P->rx, z, n, s);
+  RC(launch_residual(A.rp, A.ci, A.v, n, r, P->rx, P->rw, s));
+  if (P->block_mode) {
+    RC(launch_gather(P->rw, P->gmapL, nB, P->bL, s));
+    RC(trsv(P, P->sL1, P->L1, nullptr, 0, P->bL, nullptr, P->fL, nullptr, nullptr, s, 0, [&] {
+      return launch_rows_lower(P->Wr.rp, P->Wr.ci, P->Wr.v, nS, P->rw, P->gmapW, P->fL, P->gS, s);
+    }));
+    RC(inner_gmres_rap(P, P->gS, P->yS, s));
+    RC(launch_upper_rhs(P->fmapU, nB, nullptr, P->Zr.rp, P->Zr.ci, P->Zr.v, P->yS, P->bU, s));
+    RC(trsv(P, P->sU1, P->U1, P->DB, nB, P->bU, nullptr, P->uU, nullptr, nullptr, s, 1));
+    return launch_finish(P->uU, P->finB, nB, P->yS, P->finS, nS, P->rx, z, s);
+  }
+  double *xp = P->xp;
+  RC(trsv(P, P->sL1, P->L1, nullptr, 0, P->rw, P->perm, xp, nullptr, nullptr, s, 0));
+  RC(inner_gmres_rap(P, xp + nB, P->ry, s));
+  RC(fill_f64(xp, 0.0, nB, s));
+  RC(launch_copy(P->ry, xp + nB, nS, s));
+  RC(launch_scatter(P->ry, P->perm + nB, nS, z, s));
+  RC(trsv(P, P->sU1, P->U1, P->DB, nB, xp, nullptr, xp, z, P->perm, s, 1));
+  return launch_add(P->rx, z, n, s);
 }
 
 static int apply_impl(ilu_precond *P, const double *r, double *z, hipStream_t s) {
   const int64_t n = P->n, nB = P->nB, nS = P->nS;
   if (n == 0) return 0;
+  if (P->opt.method == ILU_METHOD_RAP) return apply_rap(P, r, z, s);
   if (P->block_mode) return apply_block(P, r, z, s);
   double *xp = P->xp;
   // f' = L_B^-1 r[perm_B] and g' = r[perm_S] - W f' in one level-scheduled pass
@@ -1282,6 +1484,21 @@ int ilu_apply(ilu_precond_t *P, const double *d_r, double *d_z, void *stream) {
   if (d_r == d_z && P->n > 0) return fail(ILU_ERR_INVALID_ARG, "r and z must not alias");
   HIPCK(hipSetDevice(P->device));
   return apply_impl(P, d_r, d_z, (hipStream_t)stream);
+}
+
+int ilu_rap_matvec(ilu_precond_t *P, const double *d_v, double *d_out, void *stream) {
+  if (!P || P->opt.method != ILU_METHOD_RAP) return fail(ILU_ERR_INVALID_ARG, "ilu_rap_matvec needs a RAP handle");
+  if (P->nS == 0) return 0;
+  if (!d_v || !d_out) return fail(ILU_ERR_INVALID_ARG, "NULL argument");
+  if (d_v == d_out) return fail(ILU_ERR_INVALID_ARG, "v and out must not alias");
+  HIPCK(hipSetDevice(P->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nS = P->nS;
+  if (!P->block_mode) return rap_product(P, d_v, d_out, s);
+  // interface numbering to the U_S position order and back from L_S order
+  RC(launch_gather(d_v, P->sUS.blk_rows, nS, P->yS, s));
+  RC(rap_product(P, P->yS, P->gS, s));
+  return launch_scatter(P->gS, P->sLS.blk_rows, nS, d_out, s);
 }
 
 int csr_spmv(const ilu_csr_t *A, const double *d_x, double *d_y, void *stream) {

@@ -345,6 +345,16 @@ int launch_copy(const double *x, double *y, int64_t n, hipStream_t s) {
   return check_launch("copy");
 }
 
+__global__ void k_add(const double *x, double *z, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) z[i] = x[i] + z[i];
+}
+int launch_add(const double *x, double *z, int64_t n, hipStream_t s) {
+  if (n == 0) return 0;
+  k_add<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, z, n);
+  return check_launch("add");
+}
+
 __global__ void k_scatter(const double *x, const int32_t *map, int64_t n, double *z) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) z[map[i]] = x[i];

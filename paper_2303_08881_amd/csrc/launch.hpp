@@ -4,9 +4,20 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct ilu_precond;
+
 namespace silu {
 
 int check_launch(const char *what);  // records a HIP launch error, returns ILU_ERR_HIP or 0
+
+// ---- capi.cpp: runtime services for the serving engine (serve.cpp) ----
+int api_fail(int code, const char *fmt, ...);  // sets ilu_last_error of this thread, returns code
+int64_t precond_bytes(const ::ilu_precond *P);   // device bytes held by a handle (factors, schedules, workspaces)
+// destroy a handle with no work queued on its blocks (its streams were
+// synchronised), without the device-wide wait of ilu_destroy
+void precond_destroy_idle(::ilu_precond *P);
+int dev_alloc(void **p, size_t bytes);  // from the library's device block cache
+void dev_free(void *p);
 
 // ---- prims.hip ----
 // out[0..n] = exclusive scan of in[0..n-1], out[n] = total (out may not alias in)
@@ -180,12 +191,13 @@ int launch_csr_perm_ent(const int64_t *rp, const int32_t *ci, const double *v, i
 // x's order): out[i] = b[bmap[i]] - sum_j l_ij x_j in column order
 int launch_rows_lower(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *b,
                       const int32_t *bmap, const double *x, double *out, hipStream_t s);
-// out[q] = f[fmap[q]] - sum_j Z_qj y_j, in column order
+// out[q] = f[fmap[q]] - sum_j Z_qj y_j, in column order (f NULL: out = -Z y)
 int launch_upper_rhs(const int32_t *fmap, int64_t n, const double *f, const int64_t *rp, const int32_t *ci,
                      const double *v, const double *y, double *out, hipStream_t s);
-// z[mb[q]] = u[q] (q < nb), z[ms[q]] = y[q] (q < ns)
+// z[mb[q]] = u[q] (q < nb), z[ms[q]] = y[q] (q < ns); with add non-NULL,
+// z[t] = add[t] + (that value)
 int launch_finish(const double *u, const int32_t *mb, int64_t nb, const double *y, const int32_t *ms, int64_t ns,
-                  double *z, hipStream_t s);
+                  const double *add, double *z, hipStream_t s);
 // block-local storage: pos[rows[q]] = q, the longest dependency row and the
 // widest level (maxent, maxw must be zeroed), then the fixed-stride fill
 int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci, int64_t n, int64_t split,
@@ -263,6 +275,8 @@ int launch_reduce_final(const double *partials, int64_t n, double *out, hipStrea
 int launch_scale_copy(const double *x, const double *alpha_num, const double *alpha_den, double *y, int64_t n,
                       const int *stop, hipStream_t s);  // y = x / (*den), skipped if *den == 0
 int launch_copy(const double *x, double *y, int64_t n, hipStream_t s);
+// z[i] = x[i] + z[i]
+int launch_add(const double *x, double *z, int64_t n, hipStream_t s);
 int launch_scatter(const double *x, const int32_t *map, int64_t n, double *z, hipStream_t s);
 // Givens step of Hessenberg column j (norm h_{j+1,j} = sqrt of the summed
 // partials; skipped when *stop is set) and w = w / h_{j+1,j} (skipped when it is 0)

@@ -897,12 +897,13 @@ int launch_rows_lower(const int64_t *rp, const int32_t *ci, const double *v, int
 // Right-hand side of the block-local U_B solve, in its position order:
 // out[q] = f[fmap[q]] - sum_j Z_qj y_j (Z's rows in that order, its columns
 // in y's order), sequentially in column order: the f'' = f' - Z y step of the
-// two-level solve (Section 3.2).
+// two-level solve (Section 3.2).  f == NULL reads as zero: out = -Z y, the
+// interior half of the prolongation P y = (-U_B^-1 Z y; y) of Section 3.3.
 __global__ void k_upper_rhs(const int32_t *fmap, int64_t n, const double *f, const int64_t *rp, const int32_t *ci,
                             const double *v, const double *y, double *out) {
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q >= n) return;
-  double s = f[fmap[q]];
+  double s = f ? f[fmap[q]] : 0.0;
   for (int64_t p = rp[q]; p < rp[q + 1]; p++) s = fma(-v[p], y[ci[p]], s);
   out[q] = s;
 }
@@ -915,20 +916,30 @@ int launch_upper_rhs(const int32_t *fmap, int64_t n, const double *f, const int6
 }
 
 // z[mb[q]] = u[q] (q < nb) and z[ms[q]] = y[q] (q < ns): both halves of the
-// preconditioned vector back to the caller's numbering
+// preconditioned vector back to the caller's numbering.  With `add`, each
+// element is added to add[] at the same index (the multiplicative method's
+// z = x + P y, Section 3.3).
 __global__ void k_finish(const double *u, const int32_t *mb, int64_t nb, const double *y, const int32_t *ms,
-                         int64_t ns, double *z) {
+                         int64_t ns, const double *add, double *z) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < nb)
-    z[mb[i]] = u[i];
-  else if (i < nb + ns)
-    z[ms[i - nb]] = y[i - nb];
+  int32_t t;
+  double v;
+  if (i < nb) {
+    t = mb[i];
+    v = u[i];
+  } else if (i < nb + ns) {
+    t = ms[i - nb];
+    v = y[i - nb];
+  } else {
+    return;
+  }
+  z[t] = add ? add[t] + v : v;
 }
 
 int launch_finish(const double *u, const int32_t *mb, int64_t nb, const double *y, const int32_t *ms, int64_t ns,
-                  double *z, hipStream_t s) {
+                  const double *add, double *z, hipStream_t s) {
   if (nb + ns == 0) return 0;
-  k_finish<<<(unsigned)((nb + ns + 255) / 256), 256, 0, s>>>(u, mb, nb, y, ms, ns, z);
+  k_finish<<<(unsigned)((nb + ns + 255) / 256), 256, 0, s>>>(u, mb, nb, y, ms, ns, add, z);
   return check_launch("finish");
 }
 

@@ -21,3 +21,10 @@ from .generators import (  # noqa: F401
     block_diagonal,
     workload,
 )
+from .serving import (  # noqa: F401
+    Request,
+    request_stream,
+    build_matrix,
+    general_sparse,
+    arrival_times,
+)

@@ -1,8 +1,10 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
 Bars: permutations, interface flags, offsets, level sets and factor
-sparsity patterns bit-exact; factor values, triangular solves and the
-preconditioner apply within 1e-12 relative (FP64); FGMRES within one
+sparsity patterns bit-exact; factor values, triangular solves, the RAP
+product and the block-Jacobi apply within 1e-12 relative (FP64); the SCHUR
+and RAP applies, whose inner GMRES divides by its own dot products (summed
+in another order than the oracle's), within 1e-10; FGMRES within one
 iteration of the oracle and a true relative residual <= rtol.
 """
 import numpy as np
@@ -56,13 +58,17 @@ CONFIGS = [
     ("random_blocks", dict(method=oracle.BJ, interior_fact=oracle.ILUT, **ILUT_OPTS)),
     ("random_blocks", dict(method=oracle.SCHUR, interior_fact=oracle.ILUT, interface_fact=oracle.MILU0,
                            inner_iters=5, **ILUT_OPTS)),
+    # the multiplicative method: RAP-MILU (MILU(0) coarse factors, ILU(0) smoother) and RAP-ILU
+    ("aniso3d_slabs", dict(method=oracle.RAP, interior_fact=oracle.MILU0, smooth_fact=oracle.ILU0, inner_iters=3)),
+    ("random_blocks", dict(method=oracle.RAP, interior_fact=oracle.ILU0, smooth_fact=oracle.ILU0, inner_iters=5)),
 ]
+RAP_IDX = [i for i, (_, o) in enumerate(CONFIGS) if o["method"] == oracle.RAP]
 
 
 def _ids():
     out = []
     for name, o in CONFIGS:
-        m = "schur" if o["method"] == oracle.SCHUR else "bj"
+        m = {oracle.BJ: "bj", oracle.SCHUR: "schur", oracle.RAP: "rap"}[o["method"]]
         f = {0: "ilu0", 1: "milu0", 2: "ilut"}[o["interior_fact"]]
         out.append(f"{name}-{m}-{f}")
     return out
@@ -122,8 +128,23 @@ def test_apply_matches(built, idx, mode):
     r = synth.uniform_rhs(A.n, 100 + idx)
     zo = P_o.apply(r)
     zg = P_g.apply(torch.as_tensor(r).cuda()).cpu().numpy()
+    # an inner GMRES (SCHUR, RAP) divides by its own dot products: 1e-10 there
     tol = 1e-12 if o["method"] == oracle.BJ else 1e-10
     np.testing.assert_allclose(zg, zo, rtol=tol, atol=tol * np.abs(zo).max())
+
+
+@pytest.mark.parametrize("mode", ["block", "levels"])
+@pytest.mark.parametrize("idx", RAP_IDX, ids=lambda i: _ids()[i])
+def test_rap_matvec_matches(built, idx, mode):
+    # R A P v with R, P unformed (Section 3.3, eq. (28)): two triangular solves and one product with A, each
+    # summed in the oracle's order, so FP64 rounding differences only (block mode multiplies by 1/u_ii)
+    A, b, part, p, o, P_o, Ad, P_g = built(idx, mode)
+    nS = P_g.info()["nS"]
+    assert nS > 0
+    v = synth.uniform_rhs(nS, 300 + idx)
+    out_o = P_o.rap_matvec(v)
+    out_g = P_g.rap_matvec(torch.as_tensor(v).cuda()).cpu().numpy()
+    np.testing.assert_allclose(out_g, out_o, rtol=1e-12, atol=1e-12 * np.abs(out_o).max())
 
 
 @pytest.mark.parametrize("mode", ["block", "levels"])
