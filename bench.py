@@ -50,6 +50,7 @@ WORKLOADS = {
                            1e-8, 50),
     "aniso2d_64": ("aniso2d_64", dict(method=0, interior_fact=0), 1e-8, 30),
     "rot9_512": ("rot9_512", dict(method=0, interior_fact=0), 1e-10, 30),
+    "rot9_2048": ("rot9_2048", dict(method=0, interior_fact=0), 1e-10, 30),
 }
 DESCRIPTION = {
     "aniso3d_128_slab16": "3D 7-point -(u_xx + 0.1 u_yy + 0.01 u_zz), 128^3 (n=2097152, nnz=14581760), "
@@ -60,6 +61,8 @@ DESCRIPTION = {
     "rot9_512": "2D 9-point rotated anisotropic diffusion (eps 1e-3, theta pi/6), 512^2 (n=262144), one block, "
                 "ILU(0), FGMRES(30) to rtol 1e-10, b = U(-1,1) seed 3 (the mixed-precision operator at a quarter "
                 "of its side)",
+    "rot9_2048": "2D 9-point rotated anisotropic diffusion (eps 1e-3, theta pi/6), 2048^2 (n=4194304, "
+                 "nnz=37724164), one block, ILU(0), FGMRES(30) to rtol 1e-10, b = U(-1,1) seed 3",
 }
 
 
@@ -476,6 +479,8 @@ def main():
     ap.add_argument("--factor-prec", default="f64", choices=["f64", "f32", "f16"],
                     help="storage precision of the triangular factors (the solves run in FP32 for f32 and f16; "
                          "everything else stays FP64)")
+    ap.add_argument("--trsv-mode", default="auto", choices=["auto", "levels", "block"],
+                    help="triangular solve execution (ilu_options_t.trsv_mode)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=40)
     ap.add_argument("--cpu-cores", type=int, default=min(16, os.cpu_count() or 1),
@@ -513,7 +518,7 @@ def main():
 
     key, opts, rtol, restart = WORKLOADS[args.workload]
     prec = {"f64": 0, "f32": 1, "f16": 2}[args.factor_prec]
-    opts = dict(opts, factor_prec=prec)
+    opts = dict(opts, factor_prec=prec, trsv_mode={"auto": 0, "levels": 1, "block": 2}[args.trsv_mode])
     A, b, part, nparts = synth.workload(key)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -624,7 +629,8 @@ def main():
         "dtype": {0: "f64", 1: "f32+f64", 2: "f32+f64 (f16 factors)"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "description": DESCRIPTION[args.workload], "n": A.n, "nnz": A.nnz,
-                   "subdomains": nparts, "restart": restart, "rtol": rtol, "factor_prec": args.factor_prec},
+                   "subdomains": nparts, "restart": restart, "rtol": rtol, "factor_prec": args.factor_prec,
+                   "trsv_mode": args.trsv_mode},
         "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
         "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
         "setup_ms": round(float(np.mean([o["setup_ms"] for o in outs])), 3),

@@ -5,9 +5,11 @@
  *   Section 2 (eq. (2)-(3))      p-way row partition, local systems A_i
  *   Section 2.2.1, Fig. 1         interior / interface labelling and the
  *                                 reordering to [[B, F], [E, C]]
- *   Section 2.2.2, Alg. 1         additive two-level solve
+ *   Section 2.2.2, algorithm      additive two-level solve
+ *   "Additive block ILU solve"
  *   Section 2.3, eq. (11)-(16)    MILU: dropped fill compensated on the diagonal
- *   Section 3.1, Alg. 4           block-Jacobi ILU setup / solve
+ *   Section 3.1, algorithm        block-Jacobi ILU setup / solve
+ *   "Block Jacobi ILU on GPU"
  *   Section 3.2, eq. (17)         partial ILU: L_B, U_B, W = E U_B^-1,
  *                                 Z = L_B^-1 F and the Schur rows in one pass
  *   Section 3.2 (one-solve form)  f' = L_B^-1 f, g' = g - W f', S y = g',
@@ -15,9 +17,9 @@
  *   Section 3.2, eq. (18)-(19)    reduced system preconditioned by the local
  *                                 Schur factors, solved by a few GMRES steps
  *   Section 4.1                   right-preconditioned flexible GMRES(m)
- *   Section 2.2.3, Alg. 2         multiplicative two-level solve: smoother,
- *                                 restriction R, coarse correction with
- *                                 S = R A P, interpolation P
+ *   Section 2.2.3, algorithm      multiplicative two-level solve: smoother,
+ *   "Two-level multiplicative     restriction R, coarse correction with
+ *   solve"                        S = R A P, interpolation P
  *   Section 3.3, eq. (20)-(29)    R = (-W L_B^-1, I), P = (-U_B^-1 Z; I) from
  *                                 the (M)ILU(0) factors of each A_i, RAP
  *                                 unformed, L_S U_S as its preconditioner
@@ -889,7 +891,8 @@ static void inner_gmres(orc_precond *P, const double *gp, double *y,
   }
 }
 
-/* Multiplicative two-level solve (Alg. 2; the GPU form of Section 3.3):
+/* Multiplicative two-level solve (algorithm "Two-level multiplicative solve";
+ * the GPU form of Section 3.3):
  * x = smoother(r); res = r - A x; the restriction g = res_S - W L_B^{-1} res_B;
  * v from k GMRES steps on (L_S U_S)^{-1} R A P v = (L_S U_S)^{-1} g; then the
  * interpolation z = x + P v = x + (-U_B^{-1} Z v; v). */

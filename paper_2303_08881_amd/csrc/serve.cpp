@@ -21,6 +21,13 @@
 // Each request runs the same library calls (ilu_setup, fgmres_solve) on its
 // slot's stream as a caller would alone, and every kernel on the path is
 // deterministic, so its result does not depend on what else is running.
+//
+// Setups run one at a time: the factorization and the level analysis are
+// launched cooperatively with a grid of every workgroup the device can hold
+// and rely on a workgroup per row stream being resident, which two such
+// launches side by side could not both be sure of.  Solves never wait on a
+// workgroup that has not started (their waits follow ticket order), so they
+// overlap with each other and with the one running setup.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -100,6 +107,7 @@ struct ilu_server {
   ilu_options_t opt{};
   Clock::time_point t0;
   std::mutex mu;
+  std::mutex setup_mu;  // one setup on the device at a time
   std::condition_variable cv_work, cv_done;
   std::deque<Req *> queue;
   std::unordered_map<int64_t, Entry *> cache;
@@ -225,6 +233,7 @@ void run(ilu_server *S, Req *r, hipStream_t st) {
     }
     if (!rc) {
       e->A = ilu_csr_t{A.n, A.nnz, (const int64_t *)e->rp, (const int32_t *)e->ci, (const double *)e->v};
+      std::lock_guard<std::mutex> lk(S->setup_mu);
       rc = ilu_setup(&e->A, r->part, r->nparts, &S->opt, st, &e->P);
     }
   }

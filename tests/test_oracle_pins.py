@@ -596,7 +596,7 @@ def test_gmres_exact_preconditioner_and_implicit_residual():
     np.testing.assert_allclose(out["history"][-1], true, rtol=1e-6)
 
 
-# ---------------------------------------------------------------- multiplicative RAP-ILU (Alg. 2, Section 3.3)
+# ---------------------------------------------------------------- multiplicative RAP-ILU ("Two-level multiplicative solve", Section 3.3)
 def _rap_pieces(P, A, nB):
     """Dense R, P (permuted numbering) and the permuted A, from the exported factors."""
     n = A.n
