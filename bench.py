@@ -130,14 +130,36 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str) -> None:
                                                   "write_factor": cw},
            "kernels": {}}
     for name in fetch:
-        src = "trsv.hip" if "k_trsv" in name else "krylov.hip" if ("k_spmv" in name or "k_mgs" in name) else None
+        src = ("trsv.hip" if "k_trsv" in name else "krylov.hip" if ("k_spmv" in name or "k_mgs" in name)
+               else "batch.hip" if "k_batch_solve" in name else None)
         if src is None:
             continue
         fb, wb = fetch[name] * cf, write.get(name, 0.0) * cw
         out["kernels"][name] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
                                 "source_sha": source_hash(src)}
-    with open(TRAFFIC_JSON, "w") as f:
+    with open(traffic_json(workload), "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
+
+
+def traffic_json(workload: str) -> str:
+    """Counter summary file of a workload (the default workload keeps the historical name)."""
+    if workload == "aniso3d_128_slab16":
+        return TRAFFIC_JSON
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+
+
+def batch_traffic():
+    """HBM bytes per launch of the batched kernel from its counter runs, or None (no file, or the kernel's
+    source has changed since)."""
+    try:
+        with open(traffic_json("convdiff_batch512")) as f:
+            tj = json.load(f)
+    except OSError:
+        return None
+    for name, rec in tj.get("kernels", {}).items():
+        if "k_batch_solve" in name and rec.get("source_sha") == source_hash("batch.hip"):
+            return rec["bytes_per_launch"]
+    return None
     print(json.dumps(out["calibration"]))
 
 
@@ -285,6 +307,17 @@ def batch_cpu_worker(first: int, count: int) -> None:
     print(json.dumps({"systems": done, "seconds": t}), flush=True)
 
 
+def copy_calibration(dev) -> None:
+    """One 256 MiB device copy: the known traffic that scales the counter runs."""
+    import torch
+
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def bench_batch(args) -> None:
     import torch
 
@@ -293,6 +326,8 @@ def bench_batch(args) -> None:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        copy_calibration(dev)
     mats, bs = synth.convdiff_batch(BATCH_COUNT, BATCH_SEED)
     A, sr = synth.block_diagonal(mats)
     Ad = silu.DeviceCSR.from_host(A, dev)
@@ -347,7 +382,7 @@ def bench_batch(args) -> None:
                        "total": int(its.sum())},
         "all_converged": bool(np.all(st == 0)), "max_relres": float(rel.max()),
         "roofline": {"kernel": "k_batch_solve", "bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None,
+                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": batch_traffic(),
                      "avg_launch_us": round(avg_ms * 1e3, 1), "bytes_per_launch": nbytes},
         "cpu_baseline": None,
     }
@@ -402,7 +437,14 @@ def bench_serve(args) -> None:
         torch.cuda.synchronize()
         S = silu.Server(slots=slots, budget_bytes=SERVE_BUDGET, factor_prec=prec, **base)
         recs = []
-        waiter = threading.Thread(target=lambda: recs.extend(S.wait() for _ in reqs))
+        submitted = threading.Semaphore(0)
+
+        def collect():
+            for _ in reqs:
+                submitted.acquire()  # a completion can only follow a submission
+                recs.append(S.wait())
+
+        waiter = threading.Thread(target=collect)
         t0 = time.perf_counter()
         waiter.start()
         for q, r in enumerate(reqs):
@@ -413,6 +455,7 @@ def bench_serve(args) -> None:
             Ad, pd, p = ddev[r.matrix_id]
             S.submit(r.matrix_id, bs[q], xs[q], A=Ad, part=pd, nparts=p, rtol=SERVE_RTOL, restart=SERVE_RESTART,
                      maxit=SERVE_MAXIT, sync=False)
+            submitted.release()
         waiter.join()
         st = S.stats()
         S.close()
@@ -534,11 +577,7 @@ def main():
         return out
 
     if args.copy_calibration:
-        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration(dev)
     import ctypes as C
 
     lib = silu.lib()

@@ -101,9 +101,10 @@ typedef struct {
  *                 rounding: the block-local solve splits long rows over a few
  *                 lanes and multiplies by the reciprocal of the diagonal):
  *                 ILU_TRSV_BLOCK solves each subdomain in one workgroup
- *                 (chosen by AUTO when a subdomain has at most 2^20 rows and at
- *                 most 16384 levels); ILU_TRSV_LEVELS spreads every level over
- *                 the whole GPU with sync-free level counters.
+ *                 (chosen by AUTO when every factor has at most 16384 levels
+ *                 and a subdomain has at most 2^20 rows or at most 1024 rows
+ *                 per level on average); ILU_TRSV_LEVELS spreads every level
+ *                 over the whole GPU with sync-free level counters.
  *  factor_prec    storage precision of the triangular factors that the
  *                 preconditioner solves with (L_B, U_B, L_S, U_S and their
  *                 diagonals; the factorization itself is FP64, and the W rows

@@ -23,12 +23,16 @@
 // last XW positions in an LDS ring (dependencies of a row are read from the
 // ring by precomputed slot), every row in one thread, entries summed in
 // column order with fma and the upper solve ending in one true division:
-// the sequential definition's rounding.  Row data are loaded two levels ahead
-// of their use (three register sets rotating through an unrolled loop, so the
-// loads in flight never have to be waited for early), and the right-hand side,
-// which needs the row id, one level ahead.  Levels of at most `merge` rows
-// run on the first wavefront alone, with a wavefront barrier instead of a
-// workgroup one.
+// the sequential definition's rounding.  Every vector a solve reads is in
+// its position order and every index it needs is stored per position: the
+// lower solve reads a copy of its right-hand side gathered into L position
+// order and writes its solution at the rows' U positions, the upper solve
+// reads that and writes the natural order.  So every load of a level
+// depends on the level pointers alone (LDS) and is issued LOOK levels ahead
+// of its use (LOOK register sets rotating through an unrolled loop): a level
+// waits for loads issued LOOK - 1 levels earlier, never for one it has just
+// issued.  Levels of at most `merge` rows run on the first wavefront alone,
+// with a wavefront barrier instead of a workgroup one.
 //
 // Reductions are deterministic: every thread sums its strided elements in
 // order, the 64 lanes of a wavefront combine by a fixed butterfly and the
@@ -53,13 +57,24 @@ constexpr int MMAX = BATCH_MMAX;   // largest restart length
 constexpr int LEVMAX = BATCH_LEVMAX;
 constexpr int RMAX = BATCH_RMAX;   // entries per row of A (factorization registers)
 
+// levels of loads in flight in a triangular solve (register sets per thread)
+template <int E>
+constexpr int look_of() {
+  return E == 2 ? 8 : 6;
+}
+// Empty levels kept past the last one.  run() reads the pointers of levels
+// up to nlev + 2 LOOK - 2 (a trip's last refill is LOOK levels past a level
+// that may itself be LOOK - 1 past the end), so the pad is 2 LOOK entries.
+constexpr int LOOK_PAD = 16;
+static_assert(LOOK_PAD >= 2 * look_of<2>() && LOOK_PAD >= 2 * look_of<4>(), "level pointer pad too short");
+
 struct Shared {
   double ring[XW + 1];
   double H[(MMAX + 1) * (MMAX + 1)];
   double cs[MMAX + 1], sn[MMAX + 1], g[MMAX + 2], c[MMAX + 1];
   double red[BNW];
   double scal[4];
-  int32_t levL[LEVMAX + 1], levU[LEVMAX + 1];
+  int32_t levL[LEVMAX + 1 + LOOK_PAD], levU[LEVMAX + 1 + LOOK_PAD];
   int32_t flag[4];
   int32_t sys;
 };
@@ -88,62 +103,61 @@ __device__ __forceinline__ double wg_sum(Shared &S, double v) {
 // Row data of one position of a triangular solve (one register set).
 template <int E>
 struct RowSet {
-  int32_t row;
   uint32_t slot[E / 2];
   double val[E];
   double diag;
   double rhs;
-  bool ok;
+  int32_t out;
 };
 
 // One triangular solve of a system: positions [0, n) in level order, level l
-// holding positions lev[l] .. lev[l+1].  UP: upper with diagonal, else unit
-// lower.  rhs and out are natural-order vectors of the system.
+// holding positions lev[l] .. lev[l+1] (lev padded with LOOK_PAD copies of
+// n).  UP: upper with diagonal, else unit lower.  rhs is in position order;
+// the solution of position q goes to out[outi[q]].
 template <int E, bool UP>
 struct Solve {
-  const int32_t *row;    // [n] row (system-local) of each position
   const uint32_t *slot;  // [n * E/2] ring slots of the entries, two per word
   const double *val;     // [n * E] entry values (padding: 0 with slot XW)
   const double *diag;    // [n] diagonal (UP)
+  const int32_t *outi;   // [n] index of each position's solution in out
   const int32_t *lev;    // LDS level pointers
   int nlev;
-  const double *rhs;
+  int n;                 // positions
+  const double *rhs;     // [n] right-hand side in position order
   double *out;
   int merge;
 
-  __device__ __forceinline__ void load_a(RowSet<E> &s, int l) const {
-    s.ok = false;
-    if (l >= nlev) return;
-    const int p0 = lev[l], w = lev[l + 1] - p0;
-    const int t = (int)threadIdx.x;
-    if (t >= w) return;
-    const int q = p0 + t;
-    s.ok = true;
-    s.row = row[q];
+  // Loads of level l for this thread: its position if the level has one for
+  // it, else position 0 (every system has one), so the loads never branch.
+  __device__ __forceinline__ void load(RowSet<E> &s, int l) const {
+    const int q = lev[l] + (int)threadIdx.x;
+    const int qc = (q < lev[l + 1] && q < n) ? q : 0;
 #pragma unroll
-    for (int k = 0; k < E / 2; k++) s.slot[k] = slot[(size_t)q * (E / 2) + k];
+    for (int k = 0; k < E / 2; k++) s.slot[k] = slot[(size_t)qc * (E / 2) + k];
 #pragma unroll
-    for (int k = 0; k < E; k++) s.val[k] = val[(size_t)q * E + k];
-    if (UP) s.diag = diag[q];
+    for (int k = 0; k < E; k++) s.val[k] = val[(size_t)qc * E + k];
+    if (UP) s.diag = diag[qc];
+    s.rhs = rhs[qc];
+    s.out = outi[qc];
   }
-  __device__ __forceinline__ void load_b(RowSet<E> &s) const {
-    if (s.ok) s.rhs = rhs[s.row];
-  }
-  // compute level l with register set s (loaded by load_a / load_b)
-  __device__ __forceinline__ void compute(Shared &S, RowSet<E> &s, int l, bool &prev_small) const {
+  // Every lane forms its sum (idle lanes on position 0's data, whose ring
+  // slots and diagonal are valid), and only the store depends on the lane:
+  // with the loads' uses outside any divergent branch, the compiler waits
+  // for exactly the register set at hand, not for every load in flight.
+  __device__ __forceinline__ void compute(Shared &S, const RowSet<E> &s, int l, bool &prev_small) const {
     const int p0 = lev[l], w = lev[l + 1] - p0;
     const bool small = w <= merge;
     if (!(small && prev_small)) __syncthreads();
-    if (s.ok) {
-      double acc = s.rhs;
+    double acc = s.rhs;
 #pragma unroll
-      for (int k = 0; k < E; k++) {
-        const int sl = (int)((s.slot[k >> 1] >> (16 * (k & 1))) & 0xffffu);
-        acc = __builtin_fma(-s.val[k], S.ring[sl], acc);
-      }
-      if (UP) acc = acc / s.diag;
+    for (int k = 0; k < E; k++) {
+      const int sl = (int)((s.slot[k >> 1] >> (16 * (k & 1))) & 0xffffu);
+      acc = __builtin_fma(-s.val[k], S.ring[sl], acc);
+    }
+    if (UP) acc = acc / s.diag;
+    if ((int)threadIdx.x < w) {
       S.ring[(p0 + (int)threadIdx.x) & (XW - 1)] = acc;
-      out[s.row] = acc;
+      out[s.out] = acc;
     }
     if (small) wave_sync();
     prev_small = small;
@@ -155,15 +169,14 @@ struct Solve {
       const int p0 = lev[l], p1 = lev[l + 1];
       __syncthreads();
       for (int q = p0 + (int)threadIdx.x; q < p1; q += BT) {
-        const int r = row[q];
-        double acc = rhs[r];
+        double acc = rhs[q];
         for (int k = 0; k < E; k++) {
           const int sl = (int)((slot[(size_t)q * (E / 2) + (k >> 1)] >> (16 * (k & 1))) & 0xffffu);
           acc = __builtin_fma(-val[(size_t)q * E + k], S.ring[sl], acc);
         }
         if (UP) acc = acc / diag[q];
         S.ring[q & (XW - 1)] = acc;
-        out[r] = acc;
+        out[outi[q]] = acc;
       }
     }
     __syncthreads();
@@ -174,23 +187,26 @@ struct Solve {
       run_wide(S);
       return;
     }
-    RowSet<E> s0, s1, s2;
+    constexpr int LOOK = look_of<E>();
+    RowSet<E> R[LOOK];
     bool prev_small = false;
-    load_a(s0, 0);
-    load_a(s1, 1);
-    load_b(s0);
-    for (int l = 0; l < nlev; l += 3) {
-      load_a(s2, l + 2);
-      load_b(s1);
-      compute(S, s0, l, prev_small);
-      if (l + 1 >= nlev) break;
-      load_a(s0, l + 3);
-      load_b(s2);
-      compute(S, s1, l + 1, prev_small);
-      if (l + 2 >= nlev) break;
-      load_a(s1, l + 4);
-      load_b(s0);
-      compute(S, s2, l + 2, prev_small);
+    // prologue in the loop's own load order, pinned by scheduling barriers:
+    // the compiler merges the wait state at loop entry with the one at the
+    // back edge, and a load that looked more recent at entry would be waited
+    // for on every trip
+#pragma unroll
+    for (int k = 0; k < LOOK; k++) {
+      load(R[k], k);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // LOOK levels per trip (the levels past the end are empty), so the
+    // register sets keep their names and each refill is LOOK levels ahead
+    for (int l = 0; l < nlev; l += LOOK) {
+#pragma unroll
+      for (int k = 0; k < LOOK; k++) {
+        compute(S, R[k], l + k, prev_small);
+        load(R[k], l + k + LOOK);
+      }
     }
     __syncthreads();
   }
@@ -210,14 +226,15 @@ struct BatchArgs {
   const double *av;
   const int64_t *dpos;  // [n] CSR index of each row's diagonal
   double *lu;           // [nnz] factor values on A's pattern
-  const int32_t *Lrow, *Urow;
+  const int32_t *Lrow, *Urow;  // [n] system-local row of each L (U) position
+  const int32_t *Lout;         // [n] system-local U position of each L position's row
   const uint32_t *Lslot, *Uslot;
   const int64_t *Lsrc, *Usrc;  // [n * E] CSR index of each entry, -1 for padding
   double *Lval, *Uval, *Udiag;
   const double *b;
   double *x;
-  double *V;             // [(m + 1) * n]
-  double *y, *z, *t;     // [n] work vectors
+  double *V;                 // [(m + 1) * n]
+  double *y, *u, *z, *t;     // [n] work vectors
   double rtol;
   int m, maxit, merge;
   unsigned int *ticket;
@@ -242,8 +259,10 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
     const int n = (int)(a.sys_row[sys + 1] - r0);
     const int nlL = a.nlevL[sys], nlU = a.nlevU[sys];
     const bool wide = a.wide[sys] != 0;
-    for (int l = tid; l <= nlL; l += BT) S.levL[l] = a.levL[(size_t)sys * (LEVMAX + 1) + l];
-    for (int l = tid; l <= nlU; l += BT) S.levU[l] = a.levU[(size_t)sys * (LEVMAX + 1) + l];
+    for (int l = tid; l <= nlL + LOOK_PAD; l += BT)
+      S.levL[l] = a.levL[(size_t)sys * (LEVMAX + 1) + (l <= nlL ? l : nlL)];
+    for (int l = tid; l <= nlU + LOOK_PAD; l += BT)
+      S.levU[l] = a.levU[(size_t)sys * (LEVMAX + 1) + (l <= nlU ? l : nlU)];
     if (tid == 0) S.flag[0] = 0;
     if (tid <= 0) S.ring[XW] = 0.0;
     __syncthreads();
@@ -321,25 +340,29 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
     __syncthreads();
 
     const double *b = a.b + r0;
-    double *x = a.x + r0, *y = a.y + r0, *z = a.z + r0, *t = a.t + r0;
+    double *x = a.x + r0, *y = a.y + r0, *u = a.u + r0, *z = a.z + r0, *t = a.t + r0;
     double *V = a.V + (size_t)(a.m + 1) * (size_t)r0;
     const int64_t *rp = a.rp + r0;
     const int32_t *ci = a.ci;
     const double *av = a.av;
-    const Solve<E, false> SL{a.Lrow + r0, a.Lslot + (size_t)r0 * (E / 2), a.Lval + (size_t)r0 * E, nullptr,
-                             S.levL, nlL, nullptr, y, a.merge};
-    const Solve<E, true> SU{a.Urow + r0, a.Uslot + (size_t)r0 * (E / 2), a.Uval + (size_t)r0 * E,
-                            a.Udiag + r0, S.levU, nlU, y, z, a.merge};
-    // z = M^-1 v (v natural order): y = L^-1 v, z = U^-1 y
+    const int32_t *Lrow = a.Lrow + r0;
+    // L: rhs y (L order), solution to u at the rows' U positions; U: rhs u, solution to z (natural order)
+    const Solve<E, false> SL{a.Lslot + (size_t)r0 * (E / 2), a.Lval + (size_t)r0 * E, nullptr, a.Lout + r0,
+                             S.levL, nlL, n, y, u, a.merge};
+    const Solve<E, true> SU{a.Uslot + (size_t)r0 * (E / 2), a.Uval + (size_t)r0 * E, a.Udiag + r0, a.Urow + r0,
+                            S.levU, nlU, n, u, z, a.merge};
+    // z = M^-1 v (v natural order): y = v gathered into L order, u = L^-1 y, z = U^-1 u
     auto precond = [&](const double *v) {
-      Solve<E, false> L = SL;
-      L.rhs = v;
-      L.run(S, wide);
+#pragma unroll 8
+      for (int q = tid; q < n; q += BT) y[q] = v[Lrow[q]];
+      __syncthreads();
+      SL.run(S, wide);
       SU.run(S, wide);
     };
     // t = b - A x, returns ||t||
     auto residual = [&]() {
       double p = 0.0;
+      #pragma unroll 4
       for (int i = tid; i < n; i += BT) {
         double s = b[i];
         for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = __builtin_fma(-av[k], x[ci[k] - r0], s);
@@ -350,12 +373,14 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
     };
 
     double pb = 0.0;
+    #pragma unroll 4
     for (int i = tid; i < n; i += BT) pb = __builtin_fma(b[i], b[i], pb);
     const double bnorm = sqrt(wg_sum(S, pb));
     int its = 0, st = 0;
     bool conv = false;
     double rel = 0.0;
     if (bnorm == 0.0) {
+      #pragma unroll 4
       for (int i = tid; i < n; i += BT) x[i] = 0.0;
       conv = true;
     } else if (!__builtin_isfinite(bnorm)) {
@@ -367,6 +392,7 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
       else if (beta <= a.rtol * bnorm) conv = true;
       const int ldh = a.m + 1;
       while (!st && !conv && its < a.maxit) {
+        #pragma unroll 4
         for (int i = tid; i < n; i += BT) V[i] = t[i] / beta;
         if (tid == 0) S.g[0] = beta;
         int jm = 0;
@@ -377,6 +403,7 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
           precond(vj);
           // w = A z, then the first dot <w, v_0>
           double p = 0.0;
+          #pragma unroll 4
           for (int i = tid; i < n; i += BT) {
             double s = 0.0;
             for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = __builtin_fma(av[k], z[ci[k] - r0], s);
@@ -385,14 +412,35 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
           }
           double h = wg_sum(S, p);
           // modified Gram-Schmidt: pass i removes h_{i-1} v_{i-1} and forms <w, v_i>
+          // (with w itself in the last pass).  Eight elements per thread are
+          // loaded before any is used, so a workgroup keeps about 48 KB in
+          // flight (one workgroup streams a whole system's vectors); the sum
+          // runs in the same order as the plain strided loop.
           for (int i = 0; i <= j; i++) {
             if (tid == 0) S.H[i + ldh * j] = h;
-            const double *vi = V + (size_t)i * n, *vn = i < j ? V + (size_t)(i + 1) * n : w;
+            const bool self = i == j;
+            const double *vi = V + (size_t)i * n, *vn = self ? w : V + (size_t)(i + 1) * n;
             double q = 0.0;
-            for (int e = tid; e < n; e += BT) {
+            int e = tid;
+            for (; e + 7 * BT < n; e += 8 * BT) {
+              double wv[8], av[8], cv[8];
+#pragma unroll
+              for (int u = 0; u < 8; u++) {
+                wv[u] = w[e + u * BT];
+                av[u] = vi[e + u * BT];
+                cv[u] = self ? 0.0 : vn[e + u * BT];
+              }
+#pragma unroll
+              for (int u = 0; u < 8; u++) {
+                const double wn = __builtin_fma(-h, av[u], wv[u]);
+                w[e + u * BT] = wn;
+                q = __builtin_fma(wn, self ? wn : cv[u], q);
+              }
+            }
+            for (; e < n; e += BT) {
               const double wn = __builtin_fma(-h, vi[e], w[e]);
               w[e] = wn;
-              q = __builtin_fma(wn, vn[e], q);
+              q = __builtin_fma(wn, self ? wn : vn[e], q);
             }
             h = wg_sum(S, q);
           }
@@ -413,21 +461,27 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
             H[(j + 1) + ldh * j] = 0.0;
             S.g[j + 1] = -S.sn[j] * S.g[j];
             S.g[j] = S.cs[j] * S.g[j];
+            // bit 0: exact breakdown (w = 0, nothing to normalise), bit 1: the
+            // estimate reached the tolerance or the step limit; 4: non-finite
             int f = 0;
-            if (!__builtin_isfinite(hn) || !__builtin_isfinite(S.g[j + 1])) f = 3;
-            else if (hn == 0.0) f = 1;
-            if (f != 3 && (fabs(S.g[j + 1]) <= a.rtol * bnorm || its + 1 >= a.maxit)) f |= 2;
+            if (!__builtin_isfinite(hn) || !__builtin_isfinite(S.g[j + 1])) {
+              f = 4;
+            } else {
+              if (hn == 0.0) f = 1;
+              if (fabs(S.g[j + 1]) <= a.rtol * bnorm || its + 1 >= a.maxit) f |= 2;
+            }
             S.flag[1] = f;
           }
           __syncthreads();
           const int f = S.flag[1];
           its++;
           jm = j + 1;
-          if (f == 3) {
+          if (f == 4) {
             st = ILU_ERR_BREAKDOWN;
             break;
           }
           if (!(f & 1))
+            #pragma unroll 4
             for (int i = tid; i < n; i += BT) w[i] = w[i] / hn;
           if (f) stop = true;
         }
@@ -441,6 +495,7 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
           }
         }
         __syncthreads();
+        #pragma unroll 4
         for (int e = tid; e < n; e += BT) {
           double u = 0.0;
           for (int i = 0; i < jm; i++) u = __builtin_fma(S.c[i], V[(size_t)i * n + e], u);
@@ -448,6 +503,7 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
         }
         __syncthreads();
         precond(t);
+        #pragma unroll 4
         for (int e = tid; e < n; e += BT) x[e] = x[e] + z[e];
         __syncthreads();
         beta = residual();
@@ -486,6 +542,7 @@ int launch_batch_solve(const BatchLaunch &L, hipStream_t s) {
   a.lu = L.lu;
   a.Lrow = L.Lrow;
   a.Urow = L.Urow;
+  a.Lout = L.Lout;
   a.Lslot = L.Lslot;
   a.Uslot = L.Uslot;
   a.Lsrc = L.Lsrc;
@@ -497,6 +554,7 @@ int launch_batch_solve(const BatchLaunch &L, hipStream_t s) {
   a.x = L.x;
   a.V = L.V;
   a.y = L.y;
+  a.u = L.u;
   a.z = L.z;
   a.t = L.t;
   a.rtol = L.rtol;
@@ -581,6 +639,22 @@ int launch_batch_fill(const int32_t *pos_rows, int64_t n, const int64_t *sys_row
   k_batch_fill<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(pos_rows, n, sys_row, row_sys, inv_pos, lev_of, levrel,
                                                            levmax1, rp, ci, upper, E, prow, pslot, psrc, dpos, err);
   return check_launch("batch_fill");
+}
+
+// out[q] = the system-local U position of the row at L position q
+__global__ void k_batch_lout(const int32_t *lrows, const int32_t *upos, const int64_t *sys_row,
+                             const int32_t *row_sys, int64_t n, int32_t *out) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int32_t r = lrows[q];
+  out[q] = (int32_t)(upos[r] - sys_row[row_sys[r]]);
+}
+
+int launch_batch_lout(const int32_t *lrows, const int32_t *upos, const int64_t *sys_row, const int32_t *row_sys,
+                      int64_t n, int32_t *out, hipStream_t s) {
+  if (n == 0) return 0;
+  k_batch_lout<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(lrows, upos, sys_row, row_sys, n, out);
+  return check_launch("batch_lout");
 }
 
 // system of every row (rows of system k are [sys_row[k], sys_row[k+1]))

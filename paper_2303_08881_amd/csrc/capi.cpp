@@ -741,11 +741,14 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   while (E == 8 && G < 8 && 8 * G < hm[0]) G *= 2;
   if ((nloc + 1) * (int64_t)G * E >= ((int64_t)1 << 29))  // byte offsets of the values below 2^32
     return fail(ILU_ERR_INVALID_ARG, "%s: factor too large for the block solve", phase);
+  // threads cover the widest level: up to 512, or 1024 for one-lane rows of
+  // at most 4 entries (the wide instance, 16 waves)
   const int64_t bt = ((int64_t)std::max(hm[1], 1) * G + 63) / 64 * 64;
+  const int64_t bt_cap = (G == 1 && E <= 4) ? 1024 : 512;
   S.lds_g = G;
   S.lds_e = E;
-  S.lds_bt = (int32_t)std::min<int64_t>(bt, 512);
-  const bool fits = bt <= 512;
+  S.lds_bt = (int32_t)std::min<int64_t>(bt, bt_cap);
+  const bool fits = bt <= bt_cap;
   const int64_t ne = (nloc + 1) * G * E;
   const int prec = P->opt.factor_prec;
   const int64_t vbytes = prec == ILU_PREC_F64 ? 8 : prec == ILU_PREC_F32 ? 4 : 2;
@@ -1155,7 +1158,13 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
     if (mode == ILU_TRSV_BLOCK && !ok)
       return fail(ILU_ERR_INVALID_ARG, "block-local solve needs <= 16384 levels per factor (has %lld)",
                   (long long)worst);
-    const bool want = mode == ILU_TRSV_BLOCK || (mode == ILU_TRSV_AUTO && n / nparts <= ((int64_t)1 << 20));
+    // AUTO: block-local unless a subdomain is large AND its levels are wide
+    // on average (beyond the 1024 threads of the widest workgroup); a level-
+    // scheduled solve pays a cross-CU wait per level, one workgroup does not
+    const int64_t nlev = std::max<int64_t>(std::max(P->sL1.nlev, P->sU1.nlev), 1);
+    const bool narrow = n / nparts / nlev <= 1024;
+    const bool want = mode == ILU_TRSV_BLOCK ||
+                      (mode == ILU_TRSV_AUTO && (n / nparts <= ((int64_t)1 << 20) || narrow));
     P->block_mode = ok && want;
   }
   if (!P->block_mode) {
@@ -1740,12 +1749,12 @@ struct ilu_batch {
   std::vector<int64_t> h_sys_row;
   int64_t *sys_row = nullptr, *rp = nullptr, *dpos = nullptr, *Lsrc = nullptr, *Usrc = nullptr;
   int32_t *ci = nullptr, *order = nullptr, *nlevL = nullptr, *nlevU = nullptr, *levL = nullptr, *levU = nullptr,
-          *Lrow = nullptr, *Urow = nullptr, *iters = nullptr, *bstatus = nullptr;
+          *Lrow = nullptr, *Urow = nullptr, *Lout = nullptr, *iters = nullptr, *bstatus = nullptr;
   uint8_t *wide = nullptr;
   uint32_t *Lslot = nullptr, *Uslot = nullptr;
   unsigned int *ticket = nullptr;
-  double *lu = nullptr, *Lval = nullptr, *Uval = nullptr, *Udiag = nullptr, *V = nullptr, *y = nullptr, *z = nullptr,
-         *t = nullptr, *relres = nullptr;
+  double *lu = nullptr, *Lval = nullptr, *Uval = nullptr, *Udiag = nullptr, *V = nullptr, *y = nullptr, *u = nullptr,
+         *z = nullptr, *t = nullptr, *relres = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   ~ilu_batch() {
@@ -1759,7 +1768,7 @@ struct ilu_batch {
 static int batch_solve_order(ilu_batch *B, Mem &tmp, const Csr &A, const int32_t *row_sys, bool upper, int E,
                              void *stmp, size_t stmpb, hipStream_t s, int32_t **prow, uint32_t **pslot,
                              int64_t **psrc, int32_t **nlev, int32_t **lev, int32_t *err, bool refill_only,
-                             Schedule &S) {
+                             Schedule &S, int32_t **rows_out, int32_t **inv_out) {
   ilu_precond *P = &B->core;
   Mem &mem = P->mem;
   const int64_t n = A.n;
@@ -1812,6 +1821,8 @@ static int batch_solve_order(ilu_batch *B, Mem &tmp, const Csr &A, const int32_t
   RC(mem.alloc(psrc, n * E));
   RC(launch_batch_fill(rows, n, B->sys_row, row_sys, inv, S.level_of, *lev, levmax1, A.rp, A.ci, upper, E, *prow,
                        *pslot, *psrc, B->dpos, err, s));
+  *rows_out = rows;  // global row at each position, and the position of each row (setup temporaries)
+  *inv_out = inv;
   (void)stmp;
   (void)stmpb;
   return 0;
@@ -1866,13 +1877,14 @@ static int batch_setup_impl(ilu_batch *B, const ilu_csr_t *A, int32_t restart, h
   void *stmp;
   RC(tmp.alloc((char **)&stmp, (int64_t)stmpb));
   Schedule SL, SU;
+  int32_t *rowsL = nullptr, *invL = nullptr, *rowsU = nullptr, *invU = nullptr;
   for (int E = 2;; E = 4) {
     RC(fill_i32(err + 2, 0, 1, s));
     const bool again = E == 4;
     RC(batch_solve_order(B, tmp, Ap, row_sys, false, E, stmp, stmpb, s, &B->Lrow, &B->Lslot, &B->Lsrc, &B->nlevL,
-                         &B->levL, err + 2, again, SL));
+                         &B->levL, err + 2, again, SL, &rowsL, &invL));
     RC(batch_solve_order(B, tmp, Ap, row_sys, true, E, stmp, stmpb, s, &B->Urow, &B->Uslot, &B->Usrc, &B->nlevU,
-                         &B->levU, err + 2, again, SU));
+                         &B->levU, err + 2, again, SU, &rowsU, &invU));
     HIPCK(hipMemcpyAsync(herr + 2, err + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
     B->E = E;
@@ -1884,6 +1896,11 @@ static int batch_setup_impl(ilu_batch *B, const ilu_csr_t *A, int32_t restart, h
                 BATCH_RMAX);
   if (herr[2] & 1) return fail(ILU_ERR_CAPACITY, "batched solve: a dependency lies beyond the %d-position ring",
                                BATCH_RING);
+  // the lower solve writes each solution at its row's U position
+  RC(mem.alloc(&B->Lout, n));
+  RC(launch_batch_lout(rowsL, invU, B->sys_row, row_sys, n, B->Lout, s));
+  (void)invL;
+  (void)rowsU;
   // level arrays of the rows, kept for export
   B->core.sL1 = SL;
   B->core.sU1 = SU;
@@ -1904,6 +1921,7 @@ static int batch_setup_impl(ilu_batch *B, const ilu_csr_t *A, int32_t restart, h
   RC(mem.alloc(&B->Udiag, n));
   RC(mem.alloc(&B->V, (int64_t)(restart + 1) * n));
   RC(mem.alloc(&B->y, n));
+  RC(mem.alloc(&B->u, n));
   RC(mem.alloc(&B->z, n));
   RC(mem.alloc(&B->t, n));
   RC(mem.alloc(&B->iters, B->nsys));
@@ -1939,6 +1957,7 @@ static int batch_launch(ilu_batch *B, const double *val, const double *b, double
   L.lu = B->lu;
   L.Lrow = B->Lrow;
   L.Urow = B->Urow;
+  L.Lout = B->Lout;
   L.Lslot = B->Lslot;
   L.Uslot = B->Uslot;
   L.Lsrc = B->Lsrc;
@@ -1950,6 +1969,7 @@ static int batch_launch(ilu_batch *B, const double *val, const double *b, double
   L.x = x;
   L.V = B->V;
   L.y = B->y;
+  L.u = B->u;
   L.z = B->z;
   L.t = B->t;
   L.rtol = rtol;

@@ -231,13 +231,13 @@ struct BatchLaunch {
   const double *av;
   const int64_t *dpos;
   double *lu;
-  const int32_t *Lrow, *Urow;
+  const int32_t *Lrow, *Urow, *Lout;
   const uint32_t *Lslot, *Uslot;
   const int64_t *Lsrc, *Usrc;
   double *Lval, *Uval, *Udiag;
   const double *b;
   double *x;
-  double *V, *y, *z, *t;
+  double *V, *y, *u, *z, *t;
   double rtol;
   int m, maxit, merge, E;
   int64_t grid;
@@ -249,6 +249,9 @@ struct BatchLaunch {
 int launch_batch_solve(const BatchLaunch &L, hipStream_t s);
 int batch_resident_groups(int num_cu, int E);
 int launch_row_sys(const int64_t *sys_row, int32_t nsys, int32_t *row_sys, hipStream_t s);
+// out[q] = upos[lrows[q]] - (first row of that row's system): where the lower solve writes each solution
+int launch_batch_lout(const int32_t *lrows, const int32_t *upos, const int64_t *sys_row, const int32_t *row_sys,
+                      int64_t n, int32_t *out, hipStream_t s);
 int launch_batch_levels(const int32_t *blk_lev_ptr, int64_t nlev_all, const int64_t *sys_row, int32_t nsys,
                         int levmax1, int32_t *levrel, int32_t *nlev, uint8_t *wide, bool or_wide, hipStream_t s);
 int launch_batch_fill(const int32_t *pos_rows, int64_t n, const int64_t *sys_row, const int32_t *row_sys,

@@ -203,6 +203,8 @@ __global__ void __launch_bounds__(WAVE) k_trsv(TrsvArgs a) {
 // ---------------------------------------------------------------------------
 constexpr int XWIN = 8192;            // solution window (positions), power of two
 constexpr int BT_MAX = 512;           // threads per block-local solve
+constexpr int BT_WIDE = 1024;         // one-lane rows of at most 4 entries: up to 16 waves (one block whose
+                                      // levels are wider than 512 rows, e.g. a single large subdomain)
 constexpr int BT_LDS_LEVELS = 16384;  // level pointers kept in LDS
 constexpr int LOOK_MAX = 10;
 
@@ -419,12 +421,12 @@ __device__ __forceinline__ void refill(const LdsTrsvArgs &a, int32_t lo, int32_t
 
 // FAST: the factor has no slow row and every level fits the workgroup (known
 // at setup), so the step carries neither check.
-template <int G, int E, bool DIAG, int P, bool FAST>
+template <int G, int E, bool DIAG, int P, bool FAST, int LK = 0>
 __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, typename Acc<P>::T *win, const int32_t *lp, int32_t l,
                                       int32_t j, int32_t g, PSet<E, P> &S) {
   using A = typename Acc<P>::T;
   using VW = VWord<P, E>;
-  constexpr int LOOK = look_of<E, P>();
+  constexpr int LOOK = LK ? LK : look_of<E, P>();
   // every LDS read of the step first, so that a single wait covers them: the
   // bounds of levels l and l + LOOK and the window values
   const int32_t q0 = lp[l], q1 = lp[l + 1];
@@ -482,10 +484,11 @@ __device__ __forceinline__ void pstep(const LdsTrsvArgs &a, typename Acc<P>::T *
 // One subdomain's solve by the calling workgroup (win: XWIN + 1 values of the
 // solve's precision, lp: BT_LDS_LEVELS + 2 LOOK_MAX + 2 ints of LDS); returns
 // after the last level's barrier.
-template <int G, int E, bool DIAG, int P, bool FAST>
+// LK: pipeline depth (0: look_of)
+template <int G, int E, bool DIAG, int P, bool FAST, int LK = 0>
 __device__ __forceinline__ void block_solve(const LdsTrsvArgs &a, typename Acc<P>::T *win, int32_t *lp) {
   using A = typename Acc<P>::T;
-  constexpr int LOOK = look_of<E, P>();
+  constexpr int LOOK = LK ? LK : look_of<E, P>();
   const int64_t base = (int64_t)blockIdx.x * a.nlev;
   const int32_t tid = (int32_t)threadIdx.x;
   const int32_t nlev = a.nlev;
@@ -510,7 +513,7 @@ __device__ __forceinline__ void block_solve(const LdsTrsvArgs &a, typename Acc<P
   // order and the register sets keep their names
   for (int32_t l = 0; l < nlev; l += LOOK) {
 #pragma unroll
-    for (int k = 0; k < LOOK; k++) pstep<G, E, DIAG, P, FAST>(a, win, lp, l + k, j, g, S[k]);
+    for (int k = 0; k < LOOK; k++) pstep<G, E, DIAG, P, FAST, LK>(a, win, lp, l + k, j, g, S[k]);
   }
 }
 
@@ -519,6 +522,22 @@ __global__ void __launch_bounds__(BT_MAX) k_trsv_lds(LdsTrsvArgs a) {
   __shared__ typename Acc<P>::T win[XWIN + 1];  // slot XWIN stays 0: the target of padding entries
   __shared__ int32_t lp[BT_LDS_LEVELS + 2 * LOOK_MAX + 2];
   block_solve<G, E, DIAG, P, FAST>(a, win, lp);
+}
+
+// The same solve with up to 1024 threads, for one-lane rows (E <= 4): levels
+// of up to 1024 rows stay on the pipelined path instead of the slow one.  Four
+// waves per SIMD leave 128 registers per lane, so 4-entry rows keep a 5-level
+// (FP64) or 7-level (FP32, FP16) pipeline, without register spills; the 16
+// waves of a workgroup hide latency among themselves.
+template <int E, int P>
+constexpr int look_wide() {
+  return E == 4 ? (P == 0 ? 5 : 7) : look_of<E, P>();
+}
+template <int E, bool DIAG, int P, bool FAST>
+__global__ void __launch_bounds__(BT_WIDE) k_trsv_lds_wide(LdsTrsvArgs a) {
+  __shared__ typename Acc<P>::T win[XWIN + 1];
+  __shared__ int32_t lp[BT_LDS_LEVELS + 2 * LOOK_MAX + 2];
+  block_solve<1, E, DIAG, P, FAST, look_wide<E, P>()>(a, win, lp);
 }
 
 // L_S then U_S of each subdomain in one launch (both with the same lane
@@ -535,6 +554,13 @@ __global__ void __launch_bounds__(BT_MAX) k_trsv_lds_pair(LdsTrsvArgs lo, LdsTrs
 
 template <bool DIAG, int P, bool FAST>
 static void launch_ge_p(int G, int E, unsigned grid, unsigned bt, const LdsTrsvArgs &a, hipStream_t s) {
+  if (bt > (unsigned)BT_MAX) {  // lds_args admits this for G = 1, E <= 4 only
+    if (E == 2)
+      k_trsv_lds_wide<2, DIAG, P, FAST><<<grid, bt, 0, s>>>(a);
+    else
+      k_trsv_lds_wide<4, DIAG, P, FAST><<<grid, bt, 0, s>>>(a);
+    return;
+  }
   if (E == 2) {
     k_trsv_lds<1, 2, DIAG, P, FAST><<<grid, bt, 0, s>>>(a);
     return;
@@ -597,7 +623,8 @@ static void launch_pair_p(int G, int E, bool fast, unsigned g, unsigned bt, cons
 static bool lds_args(const TrsvLaunch &t, LdsTrsvArgs &a) {
   const bool ge_ok = ((t.lds_e == 2 || t.lds_e == 4) && t.lds_g == 1) ||
                      (t.lds_e == 8 && (t.lds_g == 1 || t.lds_g == 2 || t.lds_g == 4 || t.lds_g == 8));
-  if (t.nlev_blk > BT_LDS_LEVELS || t.lds_bt < 64 || t.lds_bt > BT_MAX || t.lds_bt % 64 != 0 || !ge_ok ||
+  const int bt_cap = (t.lds_g == 1 && t.lds_e <= 4) ? BT_WIDE : BT_MAX;
+  if (t.nlev_blk > BT_LDS_LEVELS || t.lds_bt < 64 || t.lds_bt > bt_cap || t.lds_bt % 64 != 0 || !ge_ok ||
       !t.b || !t.x || !t.out_map)
     return false;
   a.ent_c = t.lds_c;
@@ -632,7 +659,8 @@ int launch_trsv_lds(const TrsvLaunch &t, hipStream_t s) {
 
 bool trsv_lds_pair_ok(const TrsvLaunch &lo, const TrsvLaunch &up) {
   return lo.nblk == up.nblk && lo.nblk > 0 && lo.nrows > 0 && up.nrows > 0 && lo.lds_g == up.lds_g &&
-         lo.lds_e == up.lds_e && lo.prec == up.prec && !lo.diag && up.diag;
+         lo.lds_e == up.lds_e && lo.prec == up.prec && !lo.diag && up.diag && lo.lds_bt <= BT_MAX &&
+         up.lds_bt <= BT_MAX;
 }
 
 int launch_trsv_lds_pair(const TrsvLaunch &lo, const TrsvLaunch &up, hipStream_t s) {

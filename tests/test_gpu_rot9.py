@@ -1,9 +1,10 @@
 """The mixed-precision workload at its full size: 2D rotated anisotropic 9-point diffusion on a 2048 x 2048 grid
 (n = 4,194,304, nnz = 37,724,164, eps 1e-3, theta pi/6), one block, ILU(0), FGMRES(30) to rtol 1e-10.
 
-One block of 4.19M rows is more than the block-local solve takes, so the solves run level-scheduled over the
-whole GPU (6,142 levels per factor, sync-free level counters).  Bars: level of every row bit-exact, factors
-within 1e-12, the FP64 apply within 1e-12 of the oracle's; with FP32 / FP16 factor storage the apply error
+The one block of 4.19M rows has 6,142 levels per factor, 683 rows each on average, so the default solve runs
+it on one workgroup of 1024 threads (the level-scheduled solve over the whole GPU, with a cross-CU wait per
+level, is checked too).  Bars: level of every row bit-exact, factors within 1e-12, the FP64 apply within
+1e-12 of the oracle's in both solve modes; with FP32 / FP16 factor storage the apply error
 against the FP64 oracle is printed and bounded, and FGMRES (FP64 Krylov, SpMV and convergence test) still
 reaches the true relative residual 1e-10.  The oracle's full FGMRES at this size takes minutes, so iteration
 counts are compared between the GPU precisions only.
@@ -53,7 +54,8 @@ def test_rot9_setup_matches(rot9):
         np.testing.assert_allclose(vg, vo, rtol=1e-12, atol=1e-12 * np.abs(vo).max(), err_msg=name)
     np.testing.assert_allclose(P_g.export("DB"), P_o.export("DB"), rtol=1e-12)
     sched = P_g.export("schedule")
-    assert sched[0] == 0 and sched[4] == 0, sched  # level-scheduled over the GPU, not block-local
+    # block-local, one workgroup of 1024 threads covering the widest level (1024 rows)
+    assert sched[0] == 1 and sched[4] == 1 and sched[3] == 1024 and sched[7] == 1024, sched
 
 
 def test_rot9_apply_fp64(rot9):
@@ -62,6 +64,19 @@ def test_rot9_apply_fp64(rot9):
     zo = P_o.apply(r)
     zg = P_g.apply(torch.as_tensor(r).cuda()).cpu().numpy()
     np.testing.assert_allclose(zg, zo, rtol=1e-12, atol=1e-12 * np.abs(zo).max())
+
+
+def test_rot9_level_scheduled_apply(rot9):
+    # every level spread over the whole GPU: the oracle's operations in its order, so the apply is bit-exact
+    m, A, b, P_o, Ad, P_g = rot9
+    P_l = m.setup(Ad, None, 1, trsv_mode=m.TRSV_LEVELS, **OPTS)
+    sched = P_l.export("schedule")
+    assert sched[0] == 0 and sched[4] == 0, sched
+    r = synth.uniform_rhs(A.n, 13)
+    zo = P_o.apply(r)
+    zg = P_l.apply(torch.as_tensor(r).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(zg, zo)
+    P_l.close()
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])

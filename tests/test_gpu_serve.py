@@ -115,16 +115,20 @@ def test_budget_evicts_and_rejects(stream):
     reqs, mats, dev, bs = stream
     m = silu()
     new = [r for r in reqs if r.new]
-    big = max(new, key=lambda r: mats[r.matrix_id][0].n)
-    # bytes of the largest matrix's resident factors, measured on a lone server
-    _, _, st = serve([big], dev, [bs[big.index]], slots=1, serial=True)
-    one = st["bytes"]
-    assert one > 0
-    # room for about two resident matrices plus one running request: the others are evicted on the way
-    budget = int(2.5 * one) + (64 << 20)
+    # each matrix alone: its peak (the reservation while it runs) and its resident bytes afterwards
+    peaks, resident = [], []
+    for r in new:
+        _, _, st = serve([r], dev, [bs[r.index]], slots=1, serial=True)
+        peaks.append(st["peak_bytes"])
+        resident.append(st["bytes"])
+    assert min(resident) > 0
+    # room for the largest request alone: serving all of them must evict idle factors on the way
+    budget = max(peaks) + (1 << 20)
+    assert sum(resident) > budget
     recs, xs, st = serve(new, dev, [bs[r.index] for r in new], slots=2, serial=False, budget=budget)
     assert all(rec["status"] == 0 for rec in recs), [rec["status"] for rec in recs]
     assert st["evictions"] >= 1 and st["peak_bytes"] <= budget and st["bytes"] <= budget, st
+    big = new[int(np.argmax(peaks))]
     # a request larger than the whole budget, and one for an id never given a matrix
     S = m.Server(slots=1, budget_bytes=1 << 20, **opts())
     A, part, p = dev[big.matrix_id]
