@@ -199,6 +199,27 @@ int ilu_rap_matvec(ilu_precond_t *P, const double *d_v, double *d_out, void *str
 int fgmres_solve(const ilu_csr_t *A, ilu_precond_t *P, const double *d_b, double *d_x, double rtol,
                  int32_t restart, int32_t maxit, void *stream, ilu_result_t *res, double *h_hist);
 
+/*
+ * fgmres_solve_noalloc -- fgmres_solve for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, arithmetic and results
+ * as fgmres_solve (x bit for bit), but the Krylov workspace -- the basis V,
+ * the preconditioned directions Z, the residual, the Hessenberg and Givens
+ * scalars and the reduction partials, (2 restart + 2) n doubles plus a few KB
+ * -- lives in one fixed 64 MiB device array per GPU, held from the library's
+ * load until the process ends, and no call allocates (no hipMalloc, hipFree,
+ * host-pinned allocation or HIP event).  Each step's residual estimate is
+ * read back synchronously.  P must come from ilu_setup (which allocates its
+ * own buffers), and kernel timing must be off.  Errors: ILU_ERR_CAPACITY
+ * when the workspace exceeds the array (for example restart 50 allows
+ * n <= 82,000), ILU_ERR_INVALID_ARG as fgmres_solve.  res->solve_ms is host
+ * time.  All calls on one GPU share its array: calls that overlap in time on
+ * one device (several host threads or streams) race and give undefined
+ * results.
+ */
+int fgmres_solve_noalloc(const ilu_csr_t *A, ilu_precond_t *P, const double *d_b, double *d_x, double rtol,
+                         int32_t restart, int32_t maxit, void *stream, ilu_result_t *res, double *h_hist);
+
 /* y = A x (device, FP64, each row summed in column order with fma). */
 int csr_spmv(const ilu_csr_t *A, const double *d_x, double *d_y, void *stream);
 

@@ -1696,6 +1696,92 @@ int fgmres_solve(const ilu_csr_t *A, ilu_precond_t *P, const double *d_b, double
   return rc;
 }
 
+// ---------------------------------------------------------------------------
+// FGMRES with no allocation: the Krylov workspace lives in one fixed device
+// array per GPU instead of blocks allocated on the first call.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+// Host code must not use this name as a device address: the address of each
+// device's copy comes from hipGetSymbolAddress (noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Address of the current device's copy of `scratch` (looked up once per device).
+static int noalloc_scratch(int dev, char **out) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(ILU_ERR_INVALID_ARG, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(ILU_ERR_HIP, "hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (char *)g_scratch_ptr[dev];
+  return 0;
+}
+
+// Carve the buffers of fgmres_core from `base` (256-byte aligned pieces);
+// with base == nullptr only the size is computed.  No events: each step's
+// results are read back synchronously.
+static size_t noalloc_layout(char *base, int64_t n, int m, KrylovBufs &w) {
+  size_t off = 0;
+  auto take = [&](size_t count, size_t es) -> char * {
+    off = (off + 255) & ~(size_t)255;
+    char *p = base ? base + off : nullptr;
+    off += std::max<size_t>(count, 1) * es;
+    return p;
+  };
+  w.V = (double *)take((size_t)(m + 1) * (size_t)n, 8);
+  w.Zb = (double *)take((size_t)m * (size_t)n, 8);
+  w.r = (double *)take((size_t)n, 8);
+  w.H = (double *)take((size_t)(m + 1) * (size_t)(m + 1), 8);
+  w.cs = (double *)take((size_t)m + 1, 8);
+  w.sn = (double *)take((size_t)m + 1, 8);
+  w.g = (double *)take((size_t)m + 2, 8);
+  w.c = (double *)take((size_t)m + 1, 8);
+  w.pa = (double *)take(RED_BLOCKS, 8);
+  w.pb = (double *)take(RED_BLOCKS, 8);
+  w.scal = (double *)take(8, 8);
+  w.flags = (int *)take(4, sizeof(int));
+  w.n = n;
+  w.m = m;
+  w.ev[0] = w.ev[1] = nullptr;
+  return off;
+}
+
+int fgmres_solve_noalloc(const ilu_csr_t *A, ilu_precond_t *P, const double *d_b, double *d_x, double rtol,
+                         int32_t restart, int32_t maxit, void *stream, ilu_result_t *res, double *h_hist) {
+  if (!A || !P || A->n != P->n) return fail(ILU_ERR_INVALID_ARG, "matrix and preconditioner sizes differ");
+  if (A->n > 0 && (!d_b || !d_x)) return fail(ILU_ERR_INVALID_ARG, "NULL vector");
+  if (restart < 1 || restart > 1000 || maxit < 0 || !(rtol >= 0.0))
+    return fail(ILU_ERR_INVALID_ARG, "restart/maxit/rtol out of range");
+  if (g_timing)
+    return fail(ILU_ERR_INVALID_ARG, "kernel timing creates HIP events: switch it off for the allocation-free solve");
+  KrylovBufs w;
+  const size_t need = noalloc_layout(nullptr, A->n, restart, w);
+  if (need > NOALLOC_BYTES)
+    return fail(ILU_ERR_CAPACITY,
+                "allocation-free FGMRES(%d) on n = %lld needs %zu bytes of workspace; the fixed array holds %zu "
+                "((2 restart + 2) n doubles must stay below it)",
+                restart, (long long)A->n, need, NOALLOC_BYTES);
+  HIPCK(hipSetDevice(P->device));
+  char *base = nullptr;
+  RC(noalloc_scratch(P->device, &base));
+  noalloc_layout(base, A->n, restart, w);
+  hipStream_t s = (hipStream_t)stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int rc = fgmres_core(A, P, w, d_b, d_x, rtol, restart, maxit, s, res, h_hist);
+  HIPCK(hipStreamSynchronize(s));
+  if (res) {
+    res->setup_ms = P->setup_ms;
+    res->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return rc;
+}
+
 void ilu_memory_trim(void) {
   timing_collect();
   for (hipEvent_t e : g_event_pool) (void)hipEventDestroy(e);
