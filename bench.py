@@ -48,6 +48,8 @@ WORKLOADS = {
     "aniso3d_128_slab16": ("aniso3d_128_slab16",
                            dict(method=1, interior_fact=2, interface_fact=1, droptol=1e-3, lfil=20, inner_iters=10),
                            1e-8, 50),
+    "aniso3d_128_slab16_rap": ("aniso3d_128_slab16",
+                               dict(method=2, interior_fact=1, smooth_fact=0, inner_iters=10), 1e-8, 50),
     "aniso2d_64": ("aniso2d_64", dict(method=0, interior_fact=0), 1e-8, 30),
     "rot9_512": ("rot9_512", dict(method=0, interior_fact=0), 1e-10, 30),
     "rot9_2048": ("rot9_2048", dict(method=0, interior_fact=0), 1e-10, 30),
@@ -57,6 +59,9 @@ DESCRIPTION = {
                           "16 z-slab subdomains; two-level additive Schur ILU: interior ILUT(1e-3, 20), "
                           "local Schur complements MILU(0), reduced system GMRES(10); FGMRES(50) to rtol 1e-8; "
                           "b = U(-1,1) seed 2",
+    "aniso3d_128_slab16_rap": "the 128^3 16-slab operator and right-hand side with the multiplicative two-level "
+                              "method: MILU(0) of each block for R, P and L_S U_S, ILU(0) smoother, GMRES(10) on "
+                              "the unformed R A P; FGMRES(50) to rtol 1e-8",
     "aniso2d_64": "2D 5-point -(u_xx + 0.01 u_yy), 64^2, one block, ILU(0), FGMRES(30) to rtol 1e-8, b = A 1",
     "rot9_512": "2D 9-point rotated anisotropic diffusion (eps 1e-3, theta pi/6), 512^2 (n=262144), one block, "
                 "ILU(0), FGMRES(30) to rtol 1e-10, b = U(-1,1) seed 3 (the mixed-precision operator at a quarter "

@@ -349,9 +349,10 @@ int ilu_batch_schedule(ilu_batch_t *B, int32_t merge, int32_t wpc);
 
 /*
  * ilu_batch_tune -- the autotuner: run one full solve per candidate schedule
- * (merge in {0, 16, 32, 64}, every feasible wpc), timed with device events,
- * and keep the fastest.  Overwrites d_x (which must hold the initial guess
- * before each later solve).  Out: the chosen merge, wpc and its time (ms).
+ * (merge in {0, 16, 32, 64}, every feasible wpc), each from the initial
+ * guess in d_x, timed with device events, and keep the fastest.  d_x holds
+ * the initial guess again on return.  Out: the chosen merge, wpc and its
+ * time (ms).
  */
 int ilu_batch_tune(ilu_batch_t *B, const double *d_val, const double *d_b, double *d_x, double rtol,
                    int32_t restart, int32_t maxit, void *stream, int32_t *h_merge, int32_t *h_wpc, double *h_ms);

@@ -56,6 +56,7 @@ constexpr int XW = BATCH_RING;     // solution ring (positions), power of two; s
 constexpr int MMAX = BATCH_MMAX;   // largest restart length
 constexpr int LEVMAX = BATCH_LEVMAX;
 constexpr int RMAX = BATCH_RMAX;   // entries per row of A (factorization registers)
+constexpr int MGS_U = 12;          // elements per thread loaded at once in an MGS pass
 
 // levels of loads in flight in a triangular solve (register sets per thread)
 template <int E>
@@ -412,8 +413,8 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
           }
           double h = wg_sum(S, p);
           // modified Gram-Schmidt: pass i removes h_{i-1} v_{i-1} and forms <w, v_i>
-          // (with w itself in the last pass).  Eight elements per thread are
-          // loaded before any is used, so a workgroup keeps about 48 KB in
+          // (with w itself in the last pass).  MGS_U elements per thread are
+          // loaded before any is used, so a workgroup keeps about 72 KB in
           // flight (one workgroup streams a whole system's vectors); the sum
           // runs in the same order as the plain strided loop.
           for (int i = 0; i <= j; i++) {
@@ -422,16 +423,16 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
             const double *vi = V + (size_t)i * n, *vn = self ? w : V + (size_t)(i + 1) * n;
             double q = 0.0;
             int e = tid;
-            for (; e + 7 * BT < n; e += 8 * BT) {
-              double wv[8], av[8], cv[8];
+            for (; e + (MGS_U - 1) * BT < n; e += MGS_U * BT) {
+              double wv[MGS_U], av[MGS_U], cv[MGS_U];
 #pragma unroll
-              for (int u = 0; u < 8; u++) {
+              for (int u = 0; u < MGS_U; u++) {
                 wv[u] = w[e + u * BT];
                 av[u] = vi[e + u * BT];
                 cv[u] = self ? 0.0 : vn[e + u * BT];
               }
 #pragma unroll
-              for (int u = 0; u < 8; u++) {
+              for (int u = 0; u < MGS_U; u++) {
                 const double wn = __builtin_fma(-h, av[u], wv[u]);
                 w[e + u * BT] = wn;
                 q = __builtin_fma(wn, self ? wn : cv[u], q);

@@ -2140,6 +2140,13 @@ int ilu_batch_tune(ilu_batch_t *B, const double *d_val, const double *d_b, doubl
   HIPCK(hipSetDevice(B->core.device));
   hipStream_t s = (hipStream_t)stream;
   const int per = batch_resident_groups(B->core.num_cu, B->E) / std::max(B->core.num_cu, 1);
+  // every candidate starts from the caller's initial guess (a solve
+  // overwrites x, and a converged x would make the next candidate's solve
+  // end at once)
+  Mem tmp;
+  double *x0 = nullptr;
+  RC(tmp.alloc(&x0, B->n));
+  HIPCK(hipMemcpyAsync(x0, d_x, sizeof(double) * B->n, hipMemcpyDeviceToDevice, s));
   hipEvent_t e0, e1;
   HIPCK(hipEventCreate(&e0));
   HIPCK(hipEventCreate(&e1));
@@ -2150,6 +2157,10 @@ int ilu_batch_tune(ilu_batch_t *B, const double *d_val, const double *d_b, doubl
   for (int w = 1; w <= per && !rc; w++)
     for (int mg : merges) {
       if ((rc = ilu_batch_schedule(B, mg, w))) break;
+      if (hipMemcpyAsync(d_x, x0, sizeof(double) * B->n, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        rc = fail(ILU_ERR_HIP, "batched tuning: restoring the initial guess failed");
+        break;
+      }
       (void)hipEventRecord(e0, s);
       if ((rc = batch_launch(B, d_val, d_b, d_x, rtol, restart, maxit, s))) break;
       (void)hipEventRecord(e1, s);
@@ -2166,6 +2177,9 @@ int ilu_batch_tune(ilu_batch_t *B, const double *d_val, const double *d_b, doubl
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (!rc && hipMemcpyAsync(d_x, x0, sizeof(double) * B->n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    rc = fail(ILU_ERR_HIP, "batched tuning: restoring the initial guess failed");
+  (void)hipStreamSynchronize(s);
   RC(rc);
   RC(ilu_batch_schedule(B, bm, bw));
   if (h_merge) *h_merge = bm;

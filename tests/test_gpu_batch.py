@@ -124,7 +124,9 @@ def test_batch_tuner_picks_a_valid_schedule(batch_run):
     assert merge in (0, 16, 32, 64) and wpc >= 1 and ms > 0
     sch = B.export("schedule")
     assert sch[1] == merge and sch[2] == wpc
-    x.zero_()
+    assert float(x.abs().max()) == 0.0  # the initial guess is back
+    # every candidate ran the whole solve: the chosen one's iterations are the batch's
+    np.testing.assert_array_equal(B.results()[0], r["its"])
     B.solve(Ad.val, bd, x, rtol=1e-8, restart=20, maxit=2000)
     np.testing.assert_array_equal(x.cpu().numpy(), r["x"])
 
