@@ -342,7 +342,7 @@ def bench_batch(args) -> None:
     m = BATCH_RESTART
     with torch.cuda.stream(side):
         B = silu.batch_setup(Ad, sr, restart=m)
-        merge, wpc, tune_ms = B.tune(Ad.val, bd, x, rtol=BATCH_RTOL, restart=m, maxit=BATCH_MAXIT)
+        merge, wpc, threads, tune_ms = B.tune(Ad.val, bd, x, rtol=BATCH_RTOL, restart=m, maxit=BATCH_MAXIT)
         x.zero_()
         B.capture(Ad.val, bd, x, rtol=BATCH_RTOL, restart=m, maxit=BATCH_MAXIT)
         for _ in range(max(args.warmup, 1)):
@@ -382,7 +382,7 @@ def bench_batch(args) -> None:
         "launch_ms_p50": round(float(np.percentile(launch_ms, 50)), 3),
         "launch_ms_p99": round(float(np.percentile(launch_ms, 99)), 3),
         "schedule": {"entries_per_row": sched[0], "merge": sched[1], "workgroups_per_cu": sched[2],
-                     "grid": sched[3], "tuned_ms": round(tune_ms, 3)},
+                     "grid": sched[3], "threads": sched[4], "tuned_ms": round(tune_ms, 3)},
         "iterations": {"min": int(its.min()), "median": int(np.median(its)), "max": int(its.max()),
                        "total": int(its.sum())},
         "all_converged": bool(np.all(st == 0)), "max_relres": float(rel.max()),

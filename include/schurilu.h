@@ -342,20 +342,24 @@ int ilu_batch_results(ilu_batch_t *B, int32_t *h_iters, double *h_relres, int32_
  * ilu_batch_schedule -- launch shape of later solves: levels of at most
  * `merge` rows (0..64) run on one wavefront with a wavefront barrier instead
  * of a workgroup barrier; `wpc` workgroups per CU stay resident (1 up to what
- * the kernel's resources allow).  Neither changes any arithmetic: results
- * are bit-identical for every schedule.
+ * the kernel's resources allow); `threads` per workgroup, 256 or 512 (a
+ * system's vector passes stream twice the data at once with 512).  merge and
+ * wpc change no arithmetic: results are bit-identical for every merge and
+ * wpc.  The thread count changes the order in which a workgroup sums its dot
+ * products, so results for 256 and 512 threads agree to rounding.
  */
-int ilu_batch_schedule(ilu_batch_t *B, int32_t merge, int32_t wpc);
+int ilu_batch_schedule(ilu_batch_t *B, int32_t merge, int32_t wpc, int32_t threads);
 
 /*
  * ilu_batch_tune -- the autotuner: run one full solve per candidate schedule
- * (merge in {0, 16, 32, 64}, every feasible wpc), each from the initial
- * guess in d_x, timed with device events, and keep the fastest.  d_x holds
- * the initial guess again on return.  Out: the chosen merge, wpc and its
- * time (ms).
+ * (threads in {256, 512}, merge in {0, 16, 32, 64}, every feasible wpc),
+ * each from the initial guess in d_x, timed with device events, and keep the
+ * fastest.  d_x holds the initial guess again on return.  Out: the chosen
+ * merge, wpc, threads and its time (ms).
  */
 int ilu_batch_tune(ilu_batch_t *B, const double *d_val, const double *d_b, double *d_x, double rtol,
-                   int32_t restart, int32_t maxit, void *stream, int32_t *h_merge, int32_t *h_wpc, double *h_ms);
+                   int32_t restart, int32_t maxit, void *stream, int32_t *h_merge, int32_t *h_wpc,
+                   int32_t *h_threads, double *h_ms);
 
 /*
  * ilu_batch_capture / ilu_batch_replay -- capture one ilu_batch_solve with
@@ -371,8 +375,9 @@ int ilu_batch_replay(ilu_batch_t *B, void *stream);
  * ilu_batch_export -- for parity tests: 0 the factor values of the last
  * solve on A's pattern [double nnz] (strict lower part L, diagonal and
  * strict upper part of U), 1 the level of each row in L [int32 n], 2 in U
- * [int32 n], 3 the schedule [int32 4]: entries per row and triangle, merge,
- * workgroups per CU, grid.  Same buffer protocol as ilu_export.
+ * [int32 n], 3 the schedule [int32 5]: entries per row and triangle, merge,
+ * workgroups per CU, grid, threads per workgroup.  Same buffer protocol as
+ * ilu_export.
  */
 int ilu_batch_export(ilu_batch_t *B, int32_t what, void *h_buf, int64_t *len);
 

@@ -95,9 +95,9 @@ def lib():
         L.ilu_batch_setup.argtypes = [vp, vp, i32, i32, vp, C.POINTER(vp)]
         L.ilu_batch_solve.argtypes = [vp, vp, vp, vp, d, i32, i32, vp]
         L.ilu_batch_results.argtypes = [vp, vp, vp, vp, vp]
-        L.ilu_batch_schedule.argtypes = [vp, i32, i32]
+        L.ilu_batch_schedule.argtypes = [vp, i32, i32, i32]
         L.ilu_batch_tune.argtypes = [vp, vp, vp, vp, d, i32, i32, vp, C.POINTER(i32), C.POINTER(i32),
-                                     C.POINTER(d)]
+                                     C.POINTER(i32), C.POINTER(d)]
         L.ilu_batch_capture.argtypes = [vp, vp, vp, vp, d, i32, i32, vp]
         L.ilu_batch_replay.argtypes = [vp, vp]
         L.ilu_batch_export.argtypes = [vp, i32, vp, C.POINTER(i64)]
@@ -313,15 +313,15 @@ class Batch:
                                        st.ctypes.data_as(C.c_void_p), _stream()))
         return it, rr, st
 
-    def schedule(self, merge, wpc):
-        _check(lib().ilu_batch_schedule(self._h, int(merge), int(wpc)))
+    def schedule(self, merge, wpc, threads=256):
+        _check(lib().ilu_batch_schedule(self._h, int(merge), int(wpc), int(threads)))
 
     def tune(self, val, b, x, rtol=1e-8, restart=20, maxit=1000):
-        """ilu_batch_tune: time every candidate schedule, keep the fastest; returns (merge, wpc, ms)."""
-        mg, w, ms = C.c_int32(), C.c_int32(), C.c_double()
+        """ilu_batch_tune: time every candidate schedule, keep the fastest; returns (merge, wpc, threads, ms)."""
+        mg, w, th, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
         _check(lib().ilu_batch_tune(self._h, _ptr(val), _ptr(b), _ptr(x), float(rtol), int(restart), int(maxit),
-                                    _stream(), C.byref(mg), C.byref(w), C.byref(ms)))
-        return mg.value, w.value, ms.value
+                                    _stream(), C.byref(mg), C.byref(w), C.byref(th), C.byref(ms)))
+        return mg.value, w.value, th.value, ms.value
 
     def capture(self, val, b, x, rtol=1e-8, restart=20, maxit=1000):
         """ilu_batch_capture on the current (non-default) stream."""
@@ -332,7 +332,7 @@ class Batch:
         _check(lib().ilu_batch_replay(self._h, _stream()))
 
     def export(self, what):
-        """'lu' factor values, 'lev_L' / 'lev_U' row levels, 'schedule' [E, merge, wpc, grid]."""
+        """'lu' factor values, 'lev_L' / 'lev_U' row levels, 'schedule' [E, merge, wpc, grid, threads]."""
         code, dt = dict(lu=(0, np.float64), lev_L=(1, np.int32), lev_U=(2, np.int32), schedule=(3, np.int32))[what]
         ln = C.c_int64(0)
         _check(lib().ilu_batch_export(self._h, code, None, C.byref(ln)))

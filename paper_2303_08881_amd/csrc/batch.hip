@@ -50,18 +50,23 @@ namespace silu {
 
 namespace {
 
-constexpr int BT = BATCH_THREADS;  // threads per workgroup
-constexpr int BNW = BT / WAVE;     // wavefronts per workgroup
+// BT (template parameter of the kernel): threads per workgroup, 256 or 512
 constexpr int XW = BATCH_RING;     // solution ring (positions), power of two; slot XW reads 0
 constexpr int MMAX = BATCH_MMAX;   // largest restart length
 constexpr int LEVMAX = BATCH_LEVMAX;
 constexpr int RMAX = BATCH_RMAX;   // entries per row of A (factorization registers)
-constexpr int MGS_U = 12;          // elements per thread loaded at once in an MGS pass
+// elements per thread and vector loaded at once in an MGS pass (about 72 KB
+// (256 threads) or 96 KB (512) of a workgroup in flight, within the registers)
+template <int BT>
+constexpr int mgs_u() {
+  return BT == 512 ? 8 : 12;
+}
 
-// levels of loads in flight in a triangular solve (register sets per thread)
-template <int E>
+// levels of loads in flight in a triangular solve (register sets per thread;
+// 512 threads leave at most 256 registers a lane)
+template <int E, int BT = 256>
 constexpr int look_of() {
-  return E == 2 ? 8 : 6;
+  return E == 2 ? (BT == 512 ? 7 : 8) : 6;
 }
 // Empty levels kept past the last one.  run() reads the pointers of levels
 // up to nlev + 2 LOOK - 2 (a trip's last refill is LOOK levels past a level
@@ -69,11 +74,12 @@ constexpr int look_of() {
 constexpr int LOOK_PAD = 16;
 static_assert(LOOK_PAD >= 2 * look_of<2>() && LOOK_PAD >= 2 * look_of<4>(), "level pointer pad too short");
 
+template <int BT>
 struct Shared {
   double ring[XW + 1];
   double H[(MMAX + 1) * (MMAX + 1)];
   double cs[MMAX + 1], sn[MMAX + 1], g[MMAX + 2], c[MMAX + 1];
-  double red[BNW];
+  double red[BT / WAVE];
   double scal[4];
   int32_t levL[LEVMAX + 1 + LOOK_PAD], levU[LEVMAX + 1 + LOOK_PAD];
   int32_t flag[4];
@@ -90,15 +96,64 @@ __device__ __forceinline__ void wave_sync_global() {
 }
 
 // Sum of v over the workgroup, the same value in every thread.
-__device__ __forceinline__ double wg_sum(Shared &S, double v) {
+template <int BT>
+__device__ __forceinline__ double wg_sum(Shared<BT> &S, double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
   if (lane_id() == 0) S.red[threadIdx.x / WAVE] = v;
   __syncthreads();
   double t = 0.0;
 #pragma unroll
-  for (int w = 0; w < BNW; w++) t += S.red[w];
+  for (int w = 0; w < BT / WAVE; w++) t += S.red[w];
   __syncthreads();
   return t;
+}
+
+// Row products with a system's CSR rows [0, n) (at most ROW entries each,
+// columns in [r0, r0 + n)), U rows per thread at a time: every load of a chunk
+// is issued before any of its values is used -- row bounds, then all entries
+// (a padding slot re-reads the row's first entry), then the x values they pick
+// -- so a chunk costs three trips to memory instead of a dependent chain per
+// entry.  Row i is summed from init(i) in column order with fma (entries
+// negated when NEG), the sequential definition's rounding; use(i, s) gets the
+// sum, rows in the plain strided order.
+template <int BT, int ROW, int U, bool NEG, typename Init, typename Use>
+__device__ __forceinline__ void csr_rows(int n, const int64_t *rp, const int32_t *ci, const double *av, int64_t r0,
+                                         const double *x, Init init, Use use) {
+  for (int base = (int)threadIdx.x; base < n; base += U * BT) {
+    int64_t lo[U], hi[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int i = base + u * BT;
+      lo[u] = i < n ? rp[i] : 0;
+      hi[u] = i < n ? rp[i + 1] : 0;
+    }
+    int32_t c[U][ROW];
+    double v[U][ROW];
+#pragma unroll
+    for (int u = 0; u < U; u++)
+#pragma unroll
+      for (int k = 0; k < ROW; k++) {
+        const int64_t p = lo[u] + k < hi[u] ? lo[u] + k : lo[u];
+        c[u][k] = (int32_t)(ci[p] - r0);
+        v[u][k] = av[p];
+      }
+    double xv[U][ROW];
+#pragma unroll
+    for (int u = 0; u < U; u++)
+#pragma unroll
+      for (int k = 0; k < ROW; k++) xv[u][k] = x[c[u][k]];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int i = base + u * BT;
+      if (i < n) {
+        double s = init(i);
+#pragma unroll
+        for (int k = 0; k < ROW; k++)
+          if (lo[u] + k < hi[u]) s = __builtin_fma(NEG ? -v[u][k] : v[u][k], xv[u][k], s);
+        use(i, s);
+      }
+    }
+  }
 }
 
 // Row data of one position of a triangular solve (one register set).
@@ -115,7 +170,7 @@ struct RowSet {
 // holding positions lev[l] .. lev[l+1] (lev padded with LOOK_PAD copies of
 // n).  UP: upper with diagonal, else unit lower.  rhs is in position order;
 // the solution of position q goes to out[outi[q]].
-template <int E, bool UP>
+template <int E, bool UP, int BT>
 struct Solve {
   const uint32_t *slot;  // [n * E/2] ring slots of the entries, two per word
   const double *val;     // [n * E] entry values (padding: 0 with slot XW)
@@ -145,7 +200,7 @@ struct Solve {
   // slots and diagonal are valid), and only the store depends on the lane:
   // with the loads' uses outside any divergent branch, the compiler waits
   // for exactly the register set at hand, not for every load in flight.
-  __device__ __forceinline__ void compute(Shared &S, const RowSet<E> &s, int l, bool &prev_small) const {
+  __device__ __forceinline__ void compute(Shared<BT> &S, const RowSet<E> &s, int l, bool &prev_small) const {
     const int p0 = lev[l], w = lev[l + 1] - p0;
     const bool small = w <= merge;
     if (!(small && prev_small)) __syncthreads();
@@ -165,7 +220,7 @@ struct Solve {
   }
 
   // levels wider than the workgroup: plain loop, no prefetch
-  __device__ void run_wide(Shared &S) const {
+  __device__ void run_wide(Shared<BT> &S) const {
     for (int l = 0; l < nlev; l++) {
       const int p0 = lev[l], p1 = lev[l + 1];
       __syncthreads();
@@ -183,12 +238,12 @@ struct Solve {
     __syncthreads();
   }
 
-  __device__ void run(Shared &S, bool wide) const {
+  __device__ void run(Shared<BT> &S, bool wide) const {
     if (wide) {
       run_wide(S);
       return;
     }
-    constexpr int LOOK = look_of<E>();
+    constexpr int LOOK = look_of<E, BT>();
     RowSet<E> R[LOOK];
     bool prev_small = false;
     // prologue in the loop's own load order, pinned by scheduling barriers:
@@ -243,9 +298,9 @@ struct BatchArgs {
   double *relres;
 };
 
-template <int E>
+template <int E, int BT>
 __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
-  __shared__ Shared S;
+  __shared__ Shared<BT> S;
   const int tid = (int)threadIdx.x;
   for (;;) {
     if (tid == 0) {
@@ -348,9 +403,9 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
     const double *av = a.av;
     const int32_t *Lrow = a.Lrow + r0;
     // L: rhs y (L order), solution to u at the rows' U positions; U: rhs u, solution to z (natural order)
-    const Solve<E, false> SL{a.Lslot + (size_t)r0 * (E / 2), a.Lval + (size_t)r0 * E, nullptr, a.Lout + r0,
+    const Solve<E, false, BT> SL{a.Lslot + (size_t)r0 * (E / 2), a.Lval + (size_t)r0 * E, nullptr, a.Lout + r0,
                              S.levL, nlL, n, y, u, a.merge};
-    const Solve<E, true> SU{a.Uslot + (size_t)r0 * (E / 2), a.Uval + (size_t)r0 * E, a.Udiag + r0, a.Urow + r0,
+    const Solve<E, true, BT> SU{a.Uslot + (size_t)r0 * (E / 2), a.Uval + (size_t)r0 * E, a.Udiag + r0, a.Urow + r0,
                             S.levU, nlU, n, u, z, a.merge};
     // z = M^-1 v (v natural order): y = v gathered into L order, u = L^-1 y, z = U^-1 u
     auto precond = [&](const double *v) {
@@ -361,15 +416,16 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
       SU.run(S, wide);
     };
     // t = b - A x, returns ||t||
+    constexpr int ROW = 2 * E + 1;         // entries per row: the diagonal and at most E on each side
+    constexpr int SPMV_U = E == 2 ? 4 : 1;  // rows per thread and chunk of a product (registers)
     auto residual = [&]() {
       double p = 0.0;
-      #pragma unroll 4
-      for (int i = tid; i < n; i += BT) {
-        double s = b[i];
-        for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = __builtin_fma(-av[k], x[ci[k] - r0], s);
-        t[i] = s;
-        p = __builtin_fma(s, s, p);
-      }
+      csr_rows<BT, ROW, SPMV_U, true>(
+          n, rp, ci, av, r0, x, [&](int i) { return b[i]; },
+          [&](int i, double s) {
+            t[i] = s;
+            p = __builtin_fma(s, s, p);
+          });
       return sqrt(wg_sum(S, p));
     };
 
@@ -404,35 +460,35 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
           precond(vj);
           // w = A z, then the first dot <w, v_0>
           double p = 0.0;
-          #pragma unroll 4
-          for (int i = tid; i < n; i += BT) {
-            double s = 0.0;
-            for (int64_t k = rp[i]; k < rp[i + 1]; k++) s = __builtin_fma(av[k], z[ci[k] - r0], s);
-            w[i] = s;
-            p = __builtin_fma(s, V[i], p);
-          }
+          csr_rows<BT, ROW, SPMV_U, false>(
+              n, rp, ci, av, r0, z, [](int) { return 0.0; },
+              [&](int i, double s) {
+                w[i] = s;
+                p = __builtin_fma(s, V[i], p);
+              });
           double h = wg_sum(S, p);
           // modified Gram-Schmidt: pass i removes h_{i-1} v_{i-1} and forms <w, v_i>
-          // (with w itself in the last pass).  MGS_U elements per thread are
-          // loaded before any is used, so a workgroup keeps about 72 KB in
-          // flight (one workgroup streams a whole system's vectors); the sum
-          // runs in the same order as the plain strided loop.
+          // (with w itself in the last pass).  mgs_u elements per thread and
+          // vector are loaded before any is used, so a workgroup keeps tens of
+          // KB in flight (one workgroup streams a whole system's vectors); the
+          // sum runs in the same order as the plain strided loop.
           for (int i = 0; i <= j; i++) {
             if (tid == 0) S.H[i + ldh * j] = h;
             const bool self = i == j;
             const double *vi = V + (size_t)i * n, *vn = self ? w : V + (size_t)(i + 1) * n;
             double q = 0.0;
             int e = tid;
-            for (; e + (MGS_U - 1) * BT < n; e += MGS_U * BT) {
-              double wv[MGS_U], av[MGS_U], cv[MGS_U];
+            constexpr int MU = mgs_u<BT>();
+            for (; e + (MU - 1) * BT < n; e += MU * BT) {
+              double wv[MU], av[MU], cv[MU];
 #pragma unroll
-              for (int u = 0; u < MGS_U; u++) {
+              for (int u = 0; u < MU; u++) {
                 wv[u] = w[e + u * BT];
                 av[u] = vi[e + u * BT];
                 cv[u] = self ? 0.0 : vn[e + u * BT];
               }
 #pragma unroll
-              for (int u = 0; u < MGS_U; u++) {
+              for (int u = 0; u < MU; u++) {
                 const double wn = __builtin_fma(-h, av[u], wv[u]);
                 w[e + u * BT] = wn;
                 q = __builtin_fma(wn, self ? wn : cv[u], q);
@@ -566,19 +622,32 @@ int launch_batch_solve(const BatchLaunch &L, hipStream_t s) {
   a.iters = L.iters;
   a.status = L.status;
   a.relres = L.relres;
-  if (L.m < 1 || L.m > MMAX || L.grid < 1) return ILU_ERR_INVALID_ARG;
+  if (L.m < 1 || L.m > MMAX || L.grid < 1 || (L.bt != 256 && L.bt != 512)) return ILU_ERR_INVALID_ARG;
   k_batch_reset<<<1, 64, 0, s>>>(L.ticket);
-  if (L.E == 2)
-    k_batch_solve<2><<<(unsigned)L.grid, BT, 0, s>>>(a);
-  else
-    k_batch_solve<4><<<(unsigned)L.grid, BT, 0, s>>>(a);
+  const unsigned g = (unsigned)L.grid;
+  if (L.E == 2) {
+    if (L.bt == 512)
+      k_batch_solve<2, 512><<<g, 512, 0, s>>>(a);
+    else
+      k_batch_solve<2, 256><<<g, 256, 0, s>>>(a);
+  } else {
+    if (L.bt == 512)
+      k_batch_solve<4, 512><<<g, 512, 0, s>>>(a);
+    else
+      k_batch_solve<4, 256><<<g, 256, 0, s>>>(a);
+  }
   return check_launch("batch_solve");
 }
 
-int batch_resident_groups(int num_cu, int E) {
+int batch_resident_groups(int num_cu, int E, int bt) {
   int per = 0;
-  hipError_t e = E == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_solve<2>, BT, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_solve<4>, BT, 0);
+  hipError_t e;
+  if (E == 2)
+    e = bt == 512 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_solve<2, 512>, 512, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_solve<2, 256>, 256, 0);
+  else
+    e = bt == 512 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_solve<4, 512>, 512, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_solve<4, 256>, 256, 0);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 0;
@@ -683,7 +752,7 @@ __global__ void k_batch_levels(const int32_t *blk_lev_ptr, int64_t nlev_all, con
   for (int64_t l = threadIdx.x; l < nlev_all; l += blockDim.x) {
     const int64_t a = blk_lev_ptr[(int64_t)k * nlev_all + l], b = blk_lev_ptr[(int64_t)k * nlev_all + l + 1];
     if (b > a) atomicMax(&cnt, (int)l + 1);
-    if (b - a > BT) wflag = 1;
+    if (b - a > BATCH_THREADS) wflag = 1;
     if (l < levmax1) levrel[(int64_t)k * levmax1 + l] = (int32_t)(a - r0);
   }
   __syncthreads();

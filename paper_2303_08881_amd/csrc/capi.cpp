@@ -1830,7 +1830,7 @@ struct ilu_batch {
   ilu_precond core;  // device memory, status word, CU count, level sweeps
   int32_t nsys = 0;
   int64_t n = 0, nnz = 0;
-  int E = 2, m_alloc = 0, merge = 32, wpc = 1;
+  int E = 2, m_alloc = 0, merge = 32, wpc = 1, bt = BATCH_THREADS;
   int64_t grid = 1;
   std::vector<int64_t> h_sys_row;
   int64_t *sys_row = nullptr, *rp = nullptr, *dpos = nullptr, *Lsrc = nullptr, *Usrc = nullptr;
@@ -2017,7 +2017,7 @@ static int batch_setup_impl(ilu_batch *B, const ilu_csr_t *A, int32_t restart, h
   RC(fill_i32(B->iters, 0, B->nsys, s));
   RC(fill_i32(B->bstatus, 0, B->nsys, s));
   B->m_alloc = restart;
-  const int per = batch_resident_groups(P->num_cu, B->E) / std::max(P->num_cu, 1);
+  const int per = batch_resident_groups(P->num_cu, B->E, B->bt) / std::max(P->num_cu, 1);
   if (per < 1) return fail(ILU_ERR_HIP, "batched solve: no resident workgroups");
   B->wpc = std::min(per, 2);
   B->grid = std::min<int64_t>(B->nsys, (int64_t)B->wpc * P->num_cu);
@@ -2063,6 +2063,7 @@ static int batch_launch(ilu_batch *B, const double *val, const double *b, double
   L.maxit = maxit;
   L.merge = B->merge;
   L.E = B->E;
+  L.bt = B->bt;
   L.grid = B->grid;
   L.ticket = B->ticket;
   L.iters = B->iters;
@@ -2123,23 +2124,25 @@ int ilu_batch_solve(ilu_batch_t *B, const double *d_val, const double *d_b, doub
   return batch_launch(B, d_val, d_b, d_x, rtol, restart, maxit, (hipStream_t)stream);
 }
 
-int ilu_batch_schedule(ilu_batch_t *B, int32_t merge, int32_t wpc) {
+int ilu_batch_schedule(ilu_batch_t *B, int32_t merge, int32_t wpc, int32_t threads) {
   if (!B) return fail(ILU_ERR_INVALID_ARG, "NULL batch handle");
-  const int per = batch_resident_groups(B->core.num_cu, B->E) / std::max(B->core.num_cu, 1);
+  if (threads != 256 && threads != 512) return fail(ILU_ERR_INVALID_ARG, "threads must be 256 or 512");
+  const int per = batch_resident_groups(B->core.num_cu, B->E, threads) / std::max(B->core.num_cu, 1);
   if (merge < 0 || merge > WAVE || wpc < 1 || wpc > per)
     return fail(ILU_ERR_INVALID_ARG, "merge must be in [0, %d] and workgroups per CU in [1, %d]", WAVE, per);
   B->merge = merge;
   B->wpc = wpc;
+  B->bt = threads;
   B->grid = std::min<int64_t>(B->nsys, (int64_t)wpc * B->core.num_cu);
   return 0;
 }
 
 int ilu_batch_tune(ilu_batch_t *B, const double *d_val, const double *d_b, double *d_x, double rtol,
-                   int32_t restart, int32_t maxit, void *stream, int32_t *h_merge, int32_t *h_wpc, double *h_ms) {
+                   int32_t restart, int32_t maxit, void *stream, int32_t *h_merge, int32_t *h_wpc,
+                   int32_t *h_threads, double *h_ms) {
   RC(batch_check_args(B, d_val, d_b, d_x, rtol, restart, maxit));
   HIPCK(hipSetDevice(B->core.device));
   hipStream_t s = (hipStream_t)stream;
-  const int per = batch_resident_groups(B->core.num_cu, B->E) / std::max(B->core.num_cu, 1);
   // every candidate starts from the caller's initial guess (a solve
   // overwrites x, and a converged x would make the next candidate's solve
   // end at once)
@@ -2151,12 +2154,14 @@ int ilu_batch_tune(ilu_batch_t *B, const double *d_val, const double *d_b, doubl
   HIPCK(hipEventCreate(&e0));
   HIPCK(hipEventCreate(&e1));
   double best = 1e300;
-  int bm = B->merge, bw = B->wpc;
+  int bm = B->merge, bw = B->wpc, bb = B->bt;
   const int merges[] = {0, 16, 32, 64};
   int rc = 0;
+  for (int th : {256, 512}) {
+    const int per = batch_resident_groups(B->core.num_cu, B->E, th) / std::max(B->core.num_cu, 1);
   for (int w = 1; w <= per && !rc; w++)
     for (int mg : merges) {
-      if ((rc = ilu_batch_schedule(B, mg, w))) break;
+      if ((rc = ilu_batch_schedule(B, mg, w, th))) break;
       if (hipMemcpyAsync(d_x, x0, sizeof(double) * B->n, hipMemcpyDeviceToDevice, s) != hipSuccess) {
         rc = fail(ILU_ERR_HIP, "batched tuning: restoring the initial guess failed");
         break;
@@ -2173,17 +2178,21 @@ int ilu_batch_tune(ilu_batch_t *B, const double *d_val, const double *d_b, doubl
         best = ms;
         bm = mg;
         bw = w;
+        bb = th;
       }
     }
+    if (rc) break;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (!rc && hipMemcpyAsync(d_x, x0, sizeof(double) * B->n, hipMemcpyDeviceToDevice, s) != hipSuccess)
     rc = fail(ILU_ERR_HIP, "batched tuning: restoring the initial guess failed");
   (void)hipStreamSynchronize(s);
   RC(rc);
-  RC(ilu_batch_schedule(B, bm, bw));
+  RC(ilu_batch_schedule(B, bm, bw, bb));
   if (h_merge) *h_merge = bm;
   if (h_wpc) *h_wpc = bw;
+  if (h_threads) *h_threads = bb;
   if (h_ms) *h_ms = best;
   return 0;
 }
@@ -2237,13 +2246,13 @@ int ilu_batch_export(ilu_batch_t *B, int32_t what, void *h_buf, int64_t *len) {
     case 1: return export_raw(B->core.sL1.level_of, B->n, 4, h_buf, len);
     case 2: return export_raw(B->core.sU1.level_of, B->n, 4, h_buf, len);
     case 3: {
-      const int32_t v[4] = {B->E, B->merge, B->wpc, (int32_t)B->grid};
+      const int32_t v[5] = {B->E, B->merge, B->wpc, (int32_t)B->grid, B->bt};
       if (!h_buf) {
-        *len = 4;
+        *len = 5;
         return 0;
       }
-      if (*len < 4) return fail(ILU_ERR_INVALID_ARG, "export buffer too small");
-      *len = 4;
+      if (*len < 5) return fail(ILU_ERR_INVALID_ARG, "export buffer too small");
+      *len = 5;
       memcpy(h_buf, v, sizeof(v));
       return 0;
     }

@@ -215,7 +215,7 @@ int launch_block_level_keys(const int32_t *level, const int32_t *blk, int64_t n,
 int launch_i64_to_i32(const int64_t *in, int32_t *out, int64_t n, hipStream_t s);
 
 // ---- batch.hip ----
-constexpr int BATCH_THREADS = 256;  // threads per workgroup of the batched solve
+constexpr int BATCH_THREADS = 256;  // default threads per workgroup of the batched solve (256 or 512)
 constexpr int BATCH_RING = 2048;    // solution ring of a batched triangular solve (positions)
 constexpr int BATCH_MMAX = 32;      // largest restart of the batched GMRES
 constexpr int BATCH_LEVMAX = 1024;  // levels per triangular factor of one batched system
@@ -239,7 +239,7 @@ struct BatchLaunch {
   double *x;
   double *V, *y, *u, *z, *t;
   double rtol;
-  int m, maxit, merge, E;
+  int m, maxit, merge, E, bt;
   int64_t grid;
   unsigned int *ticket;
   int32_t *iters, *status;
@@ -247,7 +247,7 @@ struct BatchLaunch {
 };
 // reset of the ticket counter, then the persistent factor + solve kernel
 int launch_batch_solve(const BatchLaunch &L, hipStream_t s);
-int batch_resident_groups(int num_cu, int E);
+int batch_resident_groups(int num_cu, int E, int bt);  // bt: 256 or 512 threads per workgroup
 int launch_row_sys(const int64_t *sys_row, int32_t nsys, int32_t *row_sys, hipStream_t s);
 // out[q] = upos[lrows[q]] - (first row of that row's system): where the lower solve writes each solution
 int launch_batch_lout(const int32_t *lrows, const int32_t *upos, const int64_t *sys_row, const int32_t *row_sys,

@@ -99,6 +99,16 @@ def test_batch_schedules_and_graph_replay_are_bit_identical(batch_run):
         B.solve(Ad.val, bd, x, rtol=1e-8, restart=20, maxit=2000)
         np.testing.assert_array_equal(x.cpu().numpy(), ref, err_msg=f"schedule {merge} {wpc}")
         np.testing.assert_array_equal(B.results()[0], r["its"])
+    # 512 threads per workgroup: dot products summed over 8 wavefronts instead of 4, so x agrees to rounding
+    # (and the iteration counts within one); back to 256 threads for the graph replays below
+    B.schedule(32, 1, 512)
+    assert B.export("schedule")[4] == 512
+    x = torch.zeros_like(bd)
+    B.solve(Ad.val, bd, x, rtol=1e-8, restart=20, maxit=2000)
+    its512, rel512, st512 = B.results()
+    assert np.all(st512 == 0) and np.all(np.abs(its512 - r["its"]) <= 1)
+    np.testing.assert_allclose(x.cpu().numpy(), ref, rtol=0, atol=1e-6 * np.abs(ref).max())
+    B.schedule(32, 1, 256)
     side = torch.cuda.Stream()
     x = torch.zeros_like(bd)
     with torch.cuda.stream(side):
@@ -120,15 +130,19 @@ def test_batch_tuner_picks_a_valid_schedule(batch_run):
     r = batch_run
     B, Ad, bd = r["B"], r["Ad"], r["bd"]
     x = torch.zeros_like(bd)
-    merge, wpc, ms = B.tune(Ad.val, bd, x, rtol=1e-8, restart=20, maxit=2000)
-    assert merge in (0, 16, 32, 64) and wpc >= 1 and ms > 0
+    merge, wpc, threads, ms = B.tune(Ad.val, bd, x, rtol=1e-8, restart=20, maxit=2000)
+    assert merge in (0, 16, 32, 64) and wpc >= 1 and threads in (256, 512) and ms > 0
     sch = B.export("schedule")
-    assert sch[1] == merge and sch[2] == wpc
+    assert sch[1] == merge and sch[2] == wpc and sch[4] == threads
     assert float(x.abs().max()) == 0.0  # the initial guess is back
-    # every candidate ran the whole solve: the chosen one's iterations are the batch's
-    np.testing.assert_array_equal(B.results()[0], r["its"])
+    # every candidate ran the whole solve: the last one's iteration counts are the batch's (to one)
+    assert np.all(np.abs(B.results()[0] - r["its"]) <= 1)
     B.solve(Ad.val, bd, x, rtol=1e-8, restart=20, maxit=2000)
-    np.testing.assert_array_equal(x.cpu().numpy(), r["x"])
+    if threads == 256:
+        np.testing.assert_array_equal(x.cpu().numpy(), r["x"])
+    else:
+        np.testing.assert_allclose(x.cpu().numpy(), r["x"], rtol=0, atol=1e-6 * np.abs(r["x"]).max())
+    B.schedule(32, 1, 256)
 
 
 def test_batch_status_codes():
