@@ -58,6 +58,8 @@ extern "C" {
 #define ILU_PREC_F64 0     /* triangular factors stored and solved in FP64      */
 #define ILU_PREC_F32 1     /* stored in FP32, solved in FP32                     */
 #define ILU_PREC_F16 2     /* stored in FP16 (scaled per row), solved in FP32    */
+#define ILU_ARNOLDI_AUTO 0     /* one cooperative launch per Arnoldi step when the vectors fit */
+#define ILU_ARNOLDI_PER_PASS 1 /* one launch per Gram-Schmidt pass                             */
 
 typedef struct {
   int64_t n;               /* rows = columns */
@@ -70,7 +72,7 @@ typedef struct {
 /*
  * Options.  Defaults (ilu_default_options): BJ, ILU(0) everywhere, 3 inner
  * GMRES steps (the paper's default, Section 4.1), no drop, pivot errors,
- * automatic solve mode, FP64 factors.
+ * automatic solve mode, FP64 factors, one-launch Arnoldi steps.
  *  interior_fact  factor of each subdomain block A_i (BJ), or of the interior
  *                 rows plus the partial elimination of the interface rows
  *                 (SCHUR, eq. (17));
@@ -117,6 +119,19 @@ typedef struct {
  *                 everything else (W, C_off, SpMV, Arnoldi, Givens, the
  *                 convergence test): the outer FGMRES, which allows a varying
  *                 preconditioner, corrects the lower-precision apply.
+ *  arnoldi_mode   how the modified Gram-Schmidt of each Arnoldi step runs, in
+ *                 fgmres_solve and in the reduced-system GMRES of ilu_apply
+ *                 (results agree to the grouping of the dot-product sums):
+ *                 ILU_ARNOLDI_AUTO takes one cooperative launch per step
+ *                 (every pass of the step inside it, the new direction held
+ *                 on chip, grid-wide barriers between the passes) when the
+ *                 vectors fit it (even length, up to 2^21 rows on a 256-CU
+ *                 device), and one launch per pass otherwise;
+ *                 ILU_ARNOLDI_PER_PASS always takes one launch per pass.  A
+ *                 cooperative launch holds its workgroups resident while they
+ *                 wait for each other: solves that run at the same time on one
+ *                 device (several streams) should use ILU_ARNOLDI_PER_PASS,
+ *                 as the request server does for its handles.
  */
 typedef struct {
   int32_t method;
@@ -131,6 +146,7 @@ typedef struct {
   int32_t trsv_mode;
   int32_t factor_prec;
   int32_t smooth_fact;
+  int32_t arnoldi_mode;
 } ilu_options_t;
 
 typedef struct {
@@ -281,7 +297,7 @@ int ilu_export(ilu_precond_t *P, int32_t what, void *h_buf, int64_t *len);
 #define ILU_K_TRSV_US 3  /* backward solve with U_S                               */
 #define ILU_K_SPMV 4     /* y = A x in the outer Krylov loop                      */
 #define ILU_K_SPMV_COFF 5 /* C_off y in the reduced-system operator              */
-#define ILU_K_MGS 6      /* one fused modified Gram-Schmidt pass                  */
+#define ILU_K_MGS 6      /* outer Gram-Schmidt: a step's launch, or one pass's     */
 #define ILU_K_COUNT 7
 #define ILU_K_ALL ((1 << ILU_K_COUNT) - 1)
 void ilu_kernel_timing(int32_t classes);

@@ -22,6 +22,8 @@ from .binding import (  # noqa: F401
     PREC_F64,
     PREC_F32,
     PREC_F16,
+    ARNOLDI_AUTO,
+    ARNOLDI_PER_PASS,
     OK,
     NOT_CONVERGED,
     SchurILUError,

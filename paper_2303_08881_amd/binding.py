@@ -22,6 +22,7 @@ ILU0, MILU0, ILUT = 0, 1, 2
 PIVOT_ERROR, PIVOT_PERTURB = 0, 1
 TRSV_AUTO, TRSV_LEVELS, TRSV_BLOCK = 0, 1, 2
 PREC_F64, PREC_F32, PREC_F16 = 0, 1, 2
+ARNOLDI_AUTO, ARNOLDI_PER_PASS = 0, 1
 OK, NOT_CONVERGED = 0, 1
 
 EXPORT = dict(perm=(0, np.int32), iperm=(1, np.int32), iface=(2, np.uint8), offsets=(3, np.int64),
@@ -48,7 +49,8 @@ class _Opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("interior_fact", C.c_int32), ("interface_fact", C.c_int32),
                 ("droptol", C.c_double), ("lfil", C.c_int32), ("inner_iters", C.c_int32),
                 ("inner_rtol", C.c_double), ("pivot_mode", C.c_int32), ("pivot_tol", C.c_double),
-                ("trsv_mode", C.c_int32), ("factor_prec", C.c_int32), ("smooth_fact", C.c_int32)]
+                ("trsv_mode", C.c_int32), ("factor_prec", C.c_int32), ("smooth_fact", C.c_int32),
+                ("arnoldi_mode", C.c_int32)]
 
 
 class _Req(C.Structure):
@@ -158,9 +160,9 @@ class DeviceCSR:
 
 def _options(method=BJ, interior_fact=ILU0, interface_fact=ILU0, droptol=0.0, lfil=-1, inner_iters=3,
              inner_rtol=0.0, pivot_mode=PIVOT_ERROR, pivot_tol=0.0, trsv_mode=TRSV_AUTO, factor_prec=PREC_F64,
-             smooth_fact=ILU0):
+             smooth_fact=ILU0, arnoldi_mode=ARNOLDI_AUTO):
     return _Opts(method, interior_fact, interface_fact, droptol, lfil, inner_iters, inner_rtol, pivot_mode,
-                 pivot_tol, trsv_mode, factor_prec, smooth_fact)
+                 pivot_tol, trsv_mode, factor_prec, smooth_fact, arnoldi_mode)
 
 
 # Every live handle, so that the exit hook below can release them while the

@@ -281,7 +281,11 @@ struct KrylovBufs {
   double *V = nullptr, *Zb = nullptr, *r = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
          *c = nullptr, *pa = nullptr, *pb = nullptr, *scal = nullptr;  // scal: [0] bnorm [1] beta [2] hn [3] est
   int *flags = nullptr;                                                // [0] stop [1] nsteps
-  hipEvent_t ev[2] = {nullptr, nullptr};                               // read-backs of two consecutive steps
+  // one-launch orthogonalisation: its sum slots (arnoldi_slots(m) words) and
+  // the launches since they were reset
+  unsigned long long *aslots = nullptr;
+  unsigned long long alaunch = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};  // read-backs of two consecutive steps
 };
 
 struct GmresWork : KrylovBufs {
@@ -319,6 +323,8 @@ struct ilu_precond {
   double *iV = nullptr, *iW = nullptr, *it1 = nullptr, *it2 = nullptr, *iH = nullptr, *ics = nullptr, *isn = nullptr,
          *ig = nullptr, *ic = nullptr, *ipa = nullptr, *ipb = nullptr, *iscal = nullptr;
   int *iflags = nullptr;
+  unsigned long long *islots = nullptr, ilaunch = 0;  // sum slots of the one-launch orthogonalisation
+  bool arnoldi_coop = true;  // Arnoldi orthogonalisation as one cooperative launch per step (arnoldi_mode)
   Status *status = nullptr;
   double *host_pinned = nullptr;  // 8 doubles for read-backs
   int64_t *blk_starts = nullptr;  // device: interior starts, interface starts, interface starts (local)
@@ -987,6 +993,7 @@ void ilu_default_options(ilu_options_t *o) {
   o->trsv_mode = ILU_TRSV_AUTO;
   o->factor_prec = ILU_PREC_F64;
   o->smooth_fact = ILU_FACT_ILU0;
+  o->arnoldi_mode = ILU_ARNOLDI_AUTO;
 }
 
 const char *ilu_last_error(void) { return g_err.c_str(); }
@@ -1221,6 +1228,9 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
     RC(mem.alloc(&P->ipb, RED_BLOCKS));
     RC(mem.alloc(&P->iscal, 8));
     RC(mem.alloc(&P->iflags, 4));
+    RC(mem.alloc(&P->islots, arnoldi_slots(std::max(k, 1))));
+    RC(launch_arnoldi_reset(P->islots, std::max(k, 1), s));
+    P->ilaunch = 0;
   }
   HIPCK(hipStreamSynchronize(s));
   tmp.release(false);  // the stream has finished with the temporaries
@@ -1250,11 +1260,14 @@ int ilu_setup(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts, const i
     return fail(ILU_ERR_INVALID_ARG, "factor_prec must be ILU_PREC_F64, ILU_PREC_F32 or ILU_PREC_F16");
   if (opt.trsv_mode < ILU_TRSV_AUTO || opt.trsv_mode > ILU_TRSV_BLOCK)
     return fail(ILU_ERR_INVALID_ARG, "unknown trsv_mode %d", opt.trsv_mode);
+  if (opt.arnoldi_mode != ILU_ARNOLDI_AUTO && opt.arnoldi_mode != ILU_ARNOLDI_PER_PASS)
+    return fail(ILU_ERR_INVALID_ARG, "unknown arnoldi_mode %d", opt.arnoldi_mode);
   hipStream_t s = (hipStream_t)stream;
   ilu_precond *P = new ilu_precond();
   P->n = A->n;
   P->nparts = nparts;
   P->opt = opt;
+  P->arnoldi_coop = opt.arnoldi_mode == ILU_ARNOLDI_AUTO;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     delete P;
@@ -1299,6 +1312,60 @@ void ilu_destroy(ilu_precond_t *P) {
   delete P;
 }
 
+// The sum slots of the one-launch orthogonalisation start empty with every
+// solve and apply (a launch that gave up on a wait leaves some behind).
+static int reset_arnoldi(ilu_precond *P, KrylovBufs *w, hipStream_t s) {
+  if (w && w->aslots && P->arnoldi_coop) {
+    RC(launch_arnoldi_reset(w->aslots, w->m, s));
+    w->alaunch = 0;
+  }
+  if (P->islots && P->arnoldi_coop) {
+    RC(launch_arnoldi_reset(P->islots, std::max(P->opt.inner_iters, 1), s));
+    P->ilaunch = 0;
+  }
+  return 0;
+}
+
+// Orthogonalisation of Arnoldi step j: w (or a + b, stored to w, when a is
+// given) minus its modified Gram-Schmidt projections on v_0..v_j (v_i at
+// V + i n), H column j to hcol, and the partials of <w, w> for the Givens
+// step (*pnorm; *npart of them, 0 meaning a per-pass reduction's count).
+// One cooperative launch when the handle allows it and the vectors fit,
+// else a dot pass (fused with the sum) and one launch per MGS pass.
+// kind >= 0: the launches are timed as that kernel class.
+static int orthogonalize(ilu_precond *P, double *w, const double *a, const double *b, const double *V, int64_t n,
+                         int j, double *hcol, double *pa, double *pb, unsigned long long *slots, int passes,
+                         unsigned long long *launches, int *stop, int kind, hipStream_t s, double **pnorm,
+                         int *npart) {
+  auto run = [&](double bytes, auto &&f) -> int { return kind >= 0 ? timed(kind, bytes, s, f) : f(); };
+  if (P->arnoldi_coop && slots && arnoldi_fits(n, w, a, b, V, P->num_cu)) {
+    ArnoldiOut o;
+    // v_0..v_j, w (or a and b) read, w written
+    const double bytes = 8.0 * (double)n * (double)(j + 3 + (a ? 1 : 0));
+    RC(run(bytes, [&] {
+      return launch_arnoldi(w, a, b, V, n, j, hcol, slots, passes, launches, pa, P->num_cu, P->status, &o, s);
+    }));
+    if (o.done) {
+      *pnorm = o.pnorm;
+      *npart = o.npart;
+      return 0;
+    }
+  }
+  double *pc = pa, *pn = pb;
+  if (a)
+    RC(launch_sum_dot(w, a, b, V, n, pc, s));
+  else
+    RC(launch_dot_partial(w, V, n, pc, s));
+  for (int i = 0; i <= j; i++) {
+    const double *vnext = i < j ? V + (int64_t)(i + 1) * n : nullptr;
+    RC(run(32.0 * (double)n, [&] { return launch_mgs_step(w, V + (int64_t)i * n, pc, hcol + i, vnext, n, pn, stop, s); }));
+    std::swap(pc, pn);
+  }
+  *pnorm = pc;
+  *npart = 0;
+  return 0;
+}
+
 // y = the reduced-system GMRES approximation for rhs g' (both in interface numbering)
 static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t s) {
   const int64_t nS = P->nS;
@@ -1322,22 +1389,20 @@ static int inner_gmres(ilu_precond *P, const double *gp, double *y, hipStream_t 
   for (int j = 0; j < k; j++) {
     double *vj = V + (int64_t)j * nS, *vn = V + (int64_t)(j + 1) * nS;
     RC(trsv_schur(P, P->it1, P->it2, s));
-    double *pc = P->ipa, *pn = P->ipb;
-    RC(launch_sum_dot(w, vj, P->it2, V, nS, pc, s));  // w = v_j + D^-1 C_off v_j, <w, v_0>
-    for (int i = 0; i <= j; i++) {
-      const double *vnext = i < j ? V + (int64_t)(i + 1) * nS : nullptr;
-      RC(launch_mgs_step(w, V + (int64_t)i * nS, pc, P->iH + i + (int64_t)ldh * j, vnext, nS, pn, stop, s));
-      std::swap(pc, pn);
-    }
+    // w = v_j + D^-1 C_off v_j, orthogonalised against v_0..v_j
+    double *pc = nullptr;
+    int np = 0;
+    RC(orthogonalize(P, w, vj, P->it2, V, nS, j, P->iH + (int64_t)ldh * j, P->ipa, P->ipb, P->islots, k,
+                     &P->ilaunch, stop, -1, s, &pc, &np));
     if (j + 1 < k) {
       // v_{j+1} = w / ||w|| and C_off v_{j+1} in one launch
       RC(timed(ILU_K_SPMV_COFF, spmv_bytes(nS, C.nnz, false) + 16.0 * (double)nS, s, [&] {
         return launch_givens_scale_spmv(P->iH, ldh, P->ics, P->isn, P->ig, j, pc, stop, nsteps, est, hn, beta,
-                                        P->opt.inner_rtol, w, vn, nS, C.rp, C.ci, C.v, P->it1, s);
+                                        P->opt.inner_rtol, w, vn, nS, C.rp, C.ci, C.v, P->it1, s, np);
       }));
     } else {
       RC(launch_givens_scale(P->iH, ldh, P->ics, P->isn, P->ig, j, pc, stop, nsteps, est, hn, beta,
-                             P->opt.inner_rtol, w, nS, s));
+                             P->opt.inner_rtol, w, nS, s, np));
     }
   }
   RC(launch_backsolve(P->iH, ldh, P->ig, nsteps, P->ic, s));
@@ -1422,15 +1487,12 @@ static int inner_gmres_rap(ilu_precond *P, const double *gp, double *y, hipStrea
     double *vj = V + (int64_t)j * nS, *w = V + (int64_t)(j + 1) * nS;
     RC(rap_product(P, vj, P->it1, s));
     RC(trsv_schur(P, P->it1, w, s));
-    double *pc = P->ipa, *pn = P->ipb;
-    RC(launch_dot_partial(w, V, nS, pc, s));
-    for (int i = 0; i <= j; i++) {
-      const double *vnext = i < j ? V + (int64_t)(i + 1) * nS : nullptr;
-      RC(launch_mgs_step(w, V + (int64_t)i * nS, pc, P->iH + i + (int64_t)ldh * j, vnext, nS, pn, stop, s));
-      std::swap(pc, pn);
-    }
+    double *pc = nullptr;
+    int np = 0;
+    RC(orthogonalize(P, w, nullptr, nullptr, V, nS, j, P->iH + (int64_t)ldh * j, P->ipa, P->ipb, P->islots, k,
+                     &P->ilaunch, stop, -1, s, &pc, &np));
     RC(launch_givens_scale(P->iH, ldh, P->ics, P->isn, P->ig, j, pc, stop, nsteps, est, hn, beta,
-                           P->opt.inner_rtol, w, nS, s));
+                           P->opt.inner_rtol, w, nS, s, np));
   }
   RC(launch_backsolve(P->iH, ldh, P->ig, nsteps, P->ic, s));
   return launch_combine(y, V, nS, P->ic, nsteps, nS, false, s);
@@ -1492,6 +1554,7 @@ int ilu_apply(ilu_precond_t *P, const double *d_r, double *d_z, void *stream) {
   if (!P || (P->n > 0 && (!d_r || !d_z))) return fail(ILU_ERR_INVALID_ARG, "NULL argument");
   if (d_r == d_z && P->n > 0) return fail(ILU_ERR_INVALID_ARG, "r and z must not alias");
   HIPCK(hipSetDevice(P->device));
+  RC(reset_arnoldi(P, nullptr, (hipStream_t)stream));
   return apply_impl(P, d_r, d_z, (hipStream_t)stream);
 }
 
@@ -1537,6 +1600,7 @@ static int gmres_work_alloc(GmresWork &w, int64_t n, int m) {
   RC(w.mem.alloc(&w.pb, RED_BLOCKS));
   RC(w.mem.alloc(&w.scal, 8));
   RC(w.mem.alloc(&w.flags, 4));
+  RC(w.mem.alloc(&w.aslots, arnoldi_slots(m)));
   for (hipEvent_t &e : w.ev) HIPCK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   w.n = n;
   w.m = m;
@@ -1577,6 +1641,7 @@ static int fgmres_core(const ilu_csr_t *A, ilu_precond *P, KrylovBufs &w, const 
   int its = 0, converged = 0;
   double relres = 0.0;
 
+  RC(reset_arnoldi(P, &w, s));
   RC(launch_dot_partial(b, b, n, w.pa, s));
   RC(launch_reduce_final(w.pa, n, bnorm, s));
   RC(read_scalars(P, bnorm, 1, s));
@@ -1627,16 +1692,11 @@ static int fgmres_core(const ilu_csr_t *A, ilu_precond *P, KrylovBufs &w, const 
         double *vj = w.V + (int64_t)j * n, *wv = w.V + (int64_t)(j + 1) * n, *zj = w.Zb + (int64_t)j * n;
         RC(apply_impl(P, vj, zj, s));
         RC(timed(ILU_K_SPMV, spmv_bytes(n, A->nnz, false), s, [&] { return launch_spmv(rp, ci, av, n, zj, wv, s, SPMV_A); }));
-        double *pc = w.pa, *pn = w.pb;
-        RC(launch_dot_partial(wv, w.V, n, pc, s));
-        for (int i = 0; i <= j; i++) {
-          const double *vnext = i < j ? w.V + (int64_t)(i + 1) * n : nullptr;
-          RC(timed(ILU_K_MGS, 32.0 * (double)n, s, [&] {
-            return launch_mgs_step(wv, w.V + (int64_t)i * n, pc, w.H + i + (int64_t)ldh * j, vnext, n, pn, stop, s);
-          }));
-          std::swap(pc, pn);
-        }
-        RC(launch_givens_scale(w.H, ldh, w.cs, w.sn, w.g, j, pc, stop, nsteps, est, hn, bnorm, rtol, wv, n, s));
+        double *pc = nullptr;
+        int np = 0;
+        RC(orthogonalize(P, wv, nullptr, nullptr, w.V, n, j, w.H + (int64_t)ldh * j, w.pa, w.pb, w.aslots, m,
+                         &w.alaunch, stop, ILU_K_MGS, s, &pc, &np));
+        RC(launch_givens_scale(w.H, ldh, w.cs, w.sn, w.g, j, pc, stop, nsteps, est, hn, bnorm, rtol, wv, n, s, np));
         const int slot = j & 1;
         HIPCK(hipMemcpyAsync(hest + slot, est, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCK(hipMemcpyAsync(hflag + slot, stop, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1746,6 +1806,7 @@ static size_t noalloc_layout(char *base, int64_t n, int m, KrylovBufs &w) {
   w.pb = (double *)take(RED_BLOCKS, 8);
   w.scal = (double *)take(8, 8);
   w.flags = (int *)take(4, sizeof(int));
+  w.aslots = (unsigned long long *)take((size_t)arnoldi_slots(m), sizeof(unsigned long long));
   w.n = n;
   w.m = m;
   w.ev[0] = w.ev[1] = nullptr;

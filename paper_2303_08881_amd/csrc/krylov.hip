@@ -379,10 +379,10 @@ template <bool VEC>
 __global__ void __launch_bounds__(RED_THREADS) k_givens_scale(double *H, int ldh, double *cs, double *sn, double *g,
                                                              int j, const double *pnorm, int *stop, int *nsteps,
                                                              double *est, double *hn_out, const double *tol_ref,
-                                                             double rtol, double *w, int64_t n) {
+                                                             double rtol, double *w, int64_t n, int npart) {
   __shared__ double sh;
   if (threadIdx.x < WAVE) {
-    const double hn2 = reduce_partials(pnorm, (int)gridDim.x);
+    const double hn2 = reduce_partials(pnorm, npart);
     if (threadIdx.x == 0) sh = sqrt(hn2);
   }
   __syncthreads();
@@ -435,13 +435,14 @@ __global__ void __launch_bounds__(RED_THREADS) k_givens_scale(double *H, int ldh
 
 int launch_givens_scale(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm, int *stop,
                         int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol, double *w,
-                        int64_t n, hipStream_t s) {
+                        int64_t n, hipStream_t s, int npart) {
+  const int np = npart > 0 ? npart : red_blocks(n);
   if (vec2_ok(n, w, nullptr, nullptr))
     k_givens_scale<true><<<red_blocks(n), RED_THREADS, 0, s>>>(H, ldh, cs, sn, g, j, pnorm, stop, nsteps, est, hn_out,
-                                                           tol_ref, rtol, w, n);
+                                                           tol_ref, rtol, w, n, np);
   else
     k_givens_scale<false><<<red_blocks(n), RED_THREADS, 0, s>>>(H, ldh, cs, sn, g, j, pnorm, stop, nsteps, est, hn_out,
-                                                            tol_ref, rtol, w, n);
+                                                            tol_ref, rtol, w, n, np);
   return check_launch("givens_scale");
 }
 
@@ -525,10 +526,10 @@ __global__ void __launch_bounds__(RED_THREADS)
 int launch_givens_scale_spmv(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm,
                              int *stop, int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol,
                              const double *wt, double *v, int64_t n, const int64_t *rp, const int32_t *ci,
-                             const double *cv, double *y, hipStream_t s) {
-  // a grid of one thread per row for the product; the norm partials come
-  // from a grid of red_blocks(n)
-  const int np = red_blocks(n);
+                             const double *cv, double *y, hipStream_t s, int npart) {
+  // a grid of one thread per row for the product; npart norm partials
+  // (red_blocks(n) when 0: those of a per-pass reduction)
+  const int np = npart > 0 ? npart : red_blocks(n);
   const unsigned grid = (unsigned)std::max<int64_t>(np, (n + RED_THREADS - 1) / RED_THREADS);
   if (vec2_ok(n, wt, v, nullptr))
     k_givens_scale_spmv<true><<<grid, RED_THREADS, 0, s>>>(H, ldh, cs, sn, g, j, pnorm, stop, nsteps, est, hn_out,
@@ -537,6 +538,300 @@ int launch_givens_scale_spmv(double *H, int ldh, double *cs, double *sn, double 
     k_givens_scale_spmv<false><<<grid, RED_THREADS, 0, s>>>(H, ldh, cs, sn, g, j, pnorm, stop, nsteps, est, hn_out,
                                                             tol_ref, rtol, wt, v, n, rp, ci, cv, y, np);
   return check_launch("givens_scale_spmv");
+}
+
+// ---- one Arnoldi orthogonalisation per launch -----------------------------
+// The modified Gram-Schmidt of step j as one launch instead of a dot launch
+// and j + 1 pass launches.  Each workgroup keeps its slice of w in registers
+// for the whole step: w is read and written once, each v_i is streamed once
+// (v_{i+1} is loaded while the blocks wait for the sum of pass i).  Pass i:
+// h_i = <w, v_i>, w -= h_i v_i, as in the one-launch-per-pass route; the
+// partials of <w, w> are left for the Givens kernel.
+//
+// The grid-wide sums need no counter: block b writes its partial of pass i to
+// its own slot, and a slot holding a signalling-NaN pattern (which no
+// arithmetic produces) has not been written yet, so the value is its own
+// ready flag and one round of device-scope loads both waits for and gathers
+// the partials.  A dedicated ninth wave does this (its loads never queue
+// behind the data waves' prefetches).  Above 64 blocks the sum has two
+// levels: the first block of each group of 16 sums its group's slots into a
+// group slot, and every block gathers the group slots.  All sums run in one
+// fixed order, so every block gets the same h_i and every run the same bits;
+// the result equals the per-pass route's up to the grouping of these sums.
+// Slots are never reused within a launch (one row of slots per pass); two
+// sets alternate between launches, and each launch resets the other set for
+// the next one (the kernel boundary orders the resets before its loads).
+// Every wait is bounded (SPIN_LIMIT polls, then ILU_ERR_TIMEOUT in the status
+// word and no further waiting).  The launch is an ordinary one (a cooperative
+// launch costs about 20 us, this kernel a few us a pass) whose grid fits on
+// the device at once (one workgroup per CU at most, checked against the
+// occupancy): on an otherwise idle device every block runs from the start,
+// and a block held back by other work is waited for.
+constexpr int ARN_T = 512;             // data threads per workgroup
+constexpr int ARN_TT = ARN_T + WAVE;   // plus the wave that gathers the sums
+constexpr int ARN_KMAX = 8;            // element pairs per thread and vector (16 would spill registers)
+constexpr int ARN_GROUP = 16;          // blocks per first-level group above ARN_FLAT blocks
+constexpr int ARN_FLAT = WAVE;
+constexpr unsigned long long ARN_EMPTY = 0x7ff4000000000000ull;  // a signalling NaN: "not written yet"
+
+struct ArnoldiArgs {
+  double *w;              // in (unless a): the new direction; out: orthogonalised against v_0..v_j
+  const double *a, *b;    // when a is set, w starts as a + b (and is only written)
+  const double *V;        // v_i at V + i n
+  int64_t n;              // even, every vector 16-byte aligned
+  int j;
+  double *hcol;           // H[0..j] of column j
+  unsigned long long *slots;  // this launch's set: [npass][slot_row] (first level, then groups)
+  unsigned long long *next;   // the other set, reset here for the next launch
+  int npass;              // rows of slots per set (>= j + 1)
+  int slot_row;           // slots per pass: RED_BLOCKS block slots + RED_BLOCKS / ARN_GROUP group slots
+  double *pnorm;          // [gridDim.x] partials of <w, w>
+  Status *st;
+};
+
+__device__ __forceinline__ bool arn_ready(unsigned long long v) { return v != ARN_EMPTY; }
+
+// Wave-wide wait until the slots [0, cnt) at p are all written, then their
+// sum (lane-strided in slot order, then a butterfly: the same value in every
+// lane).  Returns false after a timed-out wait (the sum is then garbage).
+__device__ __forceinline__ bool arn_gather(const unsigned long long *p, int cnt, Status *st, bool live,
+                                           double *sum) {
+  const int lane = lane_id();
+  double t = 0.0;
+  bool ok = true;
+  for (int k0 = 0; k0 < cnt; k0 += WAVE) {
+    const int k = k0 + lane;
+    unsigned long long v = 0;
+    long it = 0;
+    for (;;) {
+      v = k < cnt ? ld_dev(p + k) : 0ull;
+      const bool ready = k >= cnt || arn_ready(v);
+      if (!ballot(!ready) || !live) break;
+      if (++it > SPIN_LIMIT) {
+        if (lane == 0) raise_error(st, ILU_ERR_TIMEOUT, -1);
+        ok = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (!ok) break;
+    if (k < cnt) t += __longlong_as_double((long long)v);
+  }
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, WAVE);
+  *sum = t;
+  return ok;
+}
+
+template <int K, bool SUM>
+__global__ void __launch_bounds__(ARN_TT) k_arnoldi(ArnoldiArgs a) {
+  __shared__ double red[ARN_T / WAVE];
+  __shared__ double hsh;
+  const bool gatherer = threadIdx.x >= ARN_T;  // the ninth wave (wave-uniform)
+  const uint32_t G = gridDim.x;
+  const uint32_t m = (uint32_t)(a.n / 2);  // element pairs (n < 2^31)
+  const uint32_t stride = G * (uint32_t)ARN_T;
+  const uint32_t t0 = blockIdx.x * (uint32_t)ARN_T + (gatherer ? 0u : threadIdx.x);
+  const double2 *V2 = reinterpret_cast<const double2 *>(a.V);
+  const bool grouped = G > (uint32_t)ARN_FLAT;
+  const int ngroups = (int)((G + ARN_GROUP - 1) / ARN_GROUP);
+  // reset this block's slots of the other set for the next launch
+  if (gatherer) {
+    for (int p = lane_id(); p < a.npass; p += WAVE) {
+      unsigned long long *row = a.next + (size_t)p * a.slot_row;
+      st_dev(row + blockIdx.x, ARN_EMPTY);
+      if (blockIdx.x % ARN_GROUP == 0) st_dev(row + RED_BLOCKS + blockIdx.x / ARN_GROUP, ARN_EMPTY);
+    }
+  }
+  // pair k of this thread: t0 + k stride; past the end the loads read pair 0
+  // and the values are replaced by zeros, so no load is conditional
+  auto at = [&](int k) -> uint32_t {
+    const uint32_t p = t0 + (uint32_t)k * stride;
+    return p < m ? p : 0u;
+  };
+  auto in = [&](int k) -> bool { return !gatherer && t0 + (uint32_t)k * stride < m; };
+  double2 w[K], v[K], u[K];
+  double s = 0.0;
+  if (!gatherer) {
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      if constexpr (SUM) {
+        const double2 x = reinterpret_cast<const double2 *>(a.a)[at(k)];
+        const double2 y = reinterpret_cast<const double2 *>(a.b)[at(k)];
+        w[k] = make_double2(x.x + y.x, x.y + y.y);
+      } else {
+        w[k] = reinterpret_cast<const double2 *>(a.w)[at(k)];
+      }
+      v[k] = V2[at(k)];
+    }
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      if (!in(k)) {
+        w[k] = make_double2(0.0, 0.0);
+        v[k] = w[k];
+      }
+      s = fma(w[k].x, v[k].x, s);
+      s = fma(w[k].y, v[k].y, s);
+    }
+  }
+  bool live = true;  // the gathering wave's: no wait has timed out
+  for (int i = 0;; i++) {
+    // data waves: this pass's partial to LDS, then v_{i+1} on its way
+    if (!gatherer) {
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, WAVE);
+      if (lane_id() == 0) red[threadIdx.x / WAVE] = s;
+      if (i < a.j) {
+#pragma unroll
+        for (int k = 0; k < K; k++) u[k] = V2[(size_t)(i + 1) * m + at(k)];
+      }
+    }
+    __syncthreads();
+    if (gatherer) {
+      unsigned long long *row = a.slots + (size_t)i * a.slot_row;
+      double t = 0.0;
+      for (int k = 0; k < ARN_T / WAVE; k++) t += red[k];
+      if (lane_id() == 0) st_dev(row + blockIdx.x, (unsigned long long)__double_as_longlong(t));
+      double h = 0.0;
+      if (!grouped) {
+        live = arn_gather(row, (int)G, a.st, live, &h) && live;
+      } else {
+        if (blockIdx.x % ARN_GROUP == 0) {
+          const int cnt = (int)min((uint32_t)ARN_GROUP, G - blockIdx.x);
+          double gs = 0.0;
+          live = arn_gather(row + blockIdx.x, cnt, a.st, live, &gs) && live;
+          if (lane_id() == 0)
+            st_dev(row + RED_BLOCKS + blockIdx.x / ARN_GROUP, (unsigned long long)__double_as_longlong(gs));
+        }
+        live = arn_gather(row + RED_BLOCKS, ngroups, a.st, live, &h) && live;
+      }
+      if (lane_id() == 0) hsh = h;
+    }
+    __syncthreads();
+    const double h = hsh;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.hcol[i] = h;
+    if (!gatherer) {
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        w[k].x = fma(-h, v[k].x, w[k].x);
+        w[k].y = fma(-h, v[k].y, w[k].y);
+      }
+    }
+    if (i == a.j) break;
+    if (!gatherer) {
+      s = 0.0;
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        v[k] = in(k) ? u[k] : make_double2(0.0, 0.0);
+        s = fma(w[k].x, v[k].x, s);
+        s = fma(w[k].y, v[k].y, s);
+      }
+    }
+  }
+  // the partials of <w, w> for the Givens kernel, and w
+  if (!gatherer) {
+    s = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      s = fma(w[k].x, w[k].x, s);
+      s = fma(w[k].y, w[k].y, s);
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, WAVE);
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = s;
+    double2 *W2 = reinterpret_cast<double2 *>(a.w);
+#pragma unroll
+    for (int k = 0; k < K; k++)
+      if (in(k)) W2[at(k)] = w[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < ARN_T / WAVE; k++) t += red[k];
+    a.pnorm[blockIdx.x] = t;
+  }
+}
+
+__global__ void k_arnoldi_reset(unsigned long long *p, int64_t cnt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < cnt) p[i] = ARN_EMPTY;
+}
+
+int64_t arnoldi_slots(int passes) { return 2LL * passes * (RED_BLOCKS + RED_BLOCKS / ARN_GROUP); }
+
+int launch_arnoldi_reset(unsigned long long *slots, int passes, hipStream_t s) {
+  const int64_t cnt = arnoldi_slots(passes);
+  k_arnoldi_reset<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(slots, cnt);
+  return check_launch("arnoldi_reset");
+}
+
+template <int K, bool SUM>
+static int arnoldi_capacity(int num_cu) {
+  static int per_cu = -1;  // resident workgroups per CU of this instance (a property of the code object)
+  if (per_cu < 0) {
+    int p = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, k_arnoldi<K, SUM>, ARN_TT, 0) != hipSuccess) p = 0;
+    per_cu = p;
+  }
+  return std::min(per_cu, 1) * num_cu;
+}
+
+template <int K, bool SUM>
+static bool arnoldi_launch_k(const ArnoldiArgs &a, unsigned grid, int num_cu, hipStream_t s) {
+  if ((int)grid > arnoldi_capacity<K, SUM>(num_cu)) return false;
+  k_arnoldi<K, SUM><<<grid, ARN_TT, 0, s>>>(a);
+  return true;
+}
+
+template <bool SUM>
+static bool arnoldi_launch(int K, const ArnoldiArgs &a, unsigned grid, int num_cu, hipStream_t s) {
+  switch (K) {
+    case 1: return arnoldi_launch_k<1, SUM>(a, grid, num_cu, s);
+    case 2: return arnoldi_launch_k<2, SUM>(a, grid, num_cu, s);
+    case 4: return arnoldi_launch_k<4, SUM>(a, grid, num_cu, s);
+    default: return arnoldi_launch_k<8, SUM>(a, grid, num_cu, s);
+  }
+}
+
+// Launch shape of the one-launch orthogonalisation for vectors of length n:
+// the fewest workgroups that hold the vectors at ARN_KMAX element pairs per
+// thread (fewer blocks make shorter sums), at most one per CU and per slot;
+// K pairs per thread.  False when the kernel cannot take the vectors.
+static bool arnoldi_shape(int64_t n, const void *w, const void *a, const void *b, const void *V, int num_cu,
+                          int64_t *grid, int *K) {
+  auto al = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+  if (n < 2 || (n & 1) || n >= ((int64_t)1 << 31) || !al(w) || !al(V) || (a && (!al(a) || !al(b))) || num_cu < 1)
+    return false;
+  const int64_t m = n / 2;
+  const int64_t per = (int64_t)ARN_T * ARN_KMAX;
+  *grid = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(num_cu, RED_BLOCKS), (m + per - 1) / per));
+  *K = 1;
+  while ((int64_t)*K * *grid * ARN_T < m) *K *= 2;
+  return *K <= ARN_KMAX;
+}
+
+bool arnoldi_fits(int64_t n, const void *w, const void *a, const void *b, const void *V, int num_cu) {
+  int64_t grid;
+  int K;
+  return arnoldi_shape(n, w, a, b, V, num_cu, &grid, &K);
+}
+
+int launch_arnoldi(double *w, const double *a, const double *b, const double *V, int64_t n, int j, double *hcol,
+                   unsigned long long *slots, int passes, unsigned long long *launches, double *pnorm, int num_cu,
+                   void *status, ArnoldiOut *out, hipStream_t s) {
+  out->done = false;
+  int64_t grid;
+  int K;
+  if (j < 0 || j + 1 > passes || !arnoldi_shape(n, w, a, b, V, num_cu, &grid, &K)) return 0;
+  const int64_t set = (int64_t)(*launches & 1ull) * passes * (RED_BLOCKS + RED_BLOCKS / ARN_GROUP);
+  const int64_t other = (int64_t)((*launches + 1) & 1ull) * passes * (RED_BLOCKS + RED_BLOCKS / ARN_GROUP);
+  ArnoldiArgs args{w,     a,      b,    V,     n, j, hcol, slots + set, slots + other, passes,
+                   RED_BLOCKS + RED_BLOCKS / ARN_GROUP, pnorm, static_cast<Status *>(status)};
+  const bool ok = a ? arnoldi_launch<true>(K, args, (unsigned)grid, num_cu, s)
+                    : arnoldi_launch<false>(K, args, (unsigned)grid, num_cu, s);
+  if (!ok) return 0;
+  *launches += 1;
+  out->done = true;
+  out->pnorm = pnorm;
+  out->npart = (int)grid;
+  return check_launch("arnoldi");
 }
 
 // R c = g by back substitution (sizes from *nsteps)

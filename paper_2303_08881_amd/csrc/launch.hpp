@@ -282,16 +282,39 @@ int launch_copy(const double *x, double *y, int64_t n, hipStream_t s);
 int launch_add(const double *x, double *z, int64_t n, hipStream_t s);
 int launch_scatter(const double *x, const int32_t *map, int64_t n, double *z, hipStream_t s);
 // Givens step of Hessenberg column j (norm h_{j+1,j} = sqrt of the summed
-// partials; skipped when *stop is set) and w = w / h_{j+1,j} (skipped when it is 0)
+// partials; skipped when *stop is set) and w = w / h_{j+1,j} (skipped when it
+// is 0).  npart: number of norm partials (0: red_blocks(n), a per-pass
+// reduction's).
 int launch_givens_scale(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm, int *stop,
                         int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol, double *w,
-                        int64_t n, hipStream_t s);
+                        int64_t n, hipStream_t s, int npart = 0);
 // the same with w kept apart (wt): v = wt / ||wt||, and y = C v for the next
 // step (C in CSR), in one launch
 int launch_givens_scale_spmv(double *H, int ldh, double *cs, double *sn, double *g, int j, const double *pnorm,
                              int *stop, int *nsteps, double *est, double *hn_out, const double *tol_ref, double rtol,
                              const double *wt, double *v, int64_t n, const int64_t *rp, const int32_t *ci,
-                             const double *cv, double *y, hipStream_t s);
+                             const double *cv, double *y, hipStream_t s, int npart = 0);
+// The orthogonalisation of Arnoldi step j in one launch: w (or a + b when a
+// is given, stored to w) minus its MGS projections on v_0..v_j (v_i at
+// V + i n), h_i to hcol[i], and the partials of <w, w> in pnorm (out->npart
+// of them, at most RED_BLOCKS).  slots holds arnoldi_slots(passes) words
+// (passes >= j + 1), all reset by launch_arnoldi_reset before the first
+// launch; *launches counts the launches since then (advanced here).
+// out->done is false (and nothing is launched) when the shape does not fit
+// the kernel (odd n, unaligned vectors, n beyond its registers) or the grid
+// does not fit on the device: the caller then runs the passes.
+struct ArnoldiOut {
+  bool done = false;
+  double *pnorm = nullptr;
+  int npart = 0;
+};
+int64_t arnoldi_slots(int passes);
+int launch_arnoldi_reset(unsigned long long *slots, int passes, hipStream_t s);
+int launch_arnoldi(double *w, const double *a, const double *b, const double *V, int64_t n, int j, double *hcol,
+                   unsigned long long *slots, int passes, unsigned long long *launches, double *pnorm, int num_cu,
+                   void *status, ArnoldiOut *out, hipStream_t s);
+// whether launch_arnoldi can take these vectors (the device may still refuse the grid)
+bool arnoldi_fits(int64_t n, const void *w, const void *a, const void *b, const void *V, int num_cu);
 // w = a + b and the partials of <w, v>
 int launch_sum_dot(double *w, const double *a, const double *b, const double *v, int64_t n, double *partials,
                    hipStream_t s);
