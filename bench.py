@@ -90,8 +90,9 @@ def kernel_instance(cls: str, sched, prec: int = 0) -> str | None:
             both = "true" if (sched[17] >> 2) & (sched[17] >> 3) & 1 else "false"
             return f"void silu::k_trsv_lds_pair<{sched[9]}, {sched[10]}, {prec}, {both}>"
         return f"void silu::k_trsv_lds<{sched[4 * k + 1]}, {sched[4 * k + 2]}, {diag}, {prec}, {fast(k)}>"
+    # the outer orthogonalisation: one k_arnoldi launch per Arnoldi step (w from the product, not a sum)
     return {"spmv_A": "void silu::k_spmv<0>", "spmv_Coff": "void silu::k_spmv<1>",
-            "mgs": "void silu::k_mgs_step<"}.get(cls)
+            "mgs": "void silu::k_arnoldi<"}.get(cls)
 
 
 def measured_traffic(cls: str, sched, prec: int = 0):
@@ -103,6 +104,8 @@ def measured_traffic(cls: str, sched, prec: int = 0):
     with open(TRAFFIC_JSON) as f:
         tj = json.load(f)
     for name, rec in tj.get("kernels", {}).items():
+        if cls == "mgs" and ", false>" not in name:
+            continue
         if name.startswith(inst) and rec.get("source_sha") == source_hash(KERNEL_SOURCE[cls]):
             return rec["bytes_per_launch"]
     return None
@@ -135,7 +138,8 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str) -> None:
                                                   "write_factor": cw},
            "kernels": {}}
     for name in fetch:
-        src = ("trsv.hip" if "k_trsv" in name else "krylov.hip" if ("k_spmv" in name or "k_mgs" in name)
+        src = ("trsv.hip" if "k_trsv" in name
+               else "krylov.hip" if ("k_spmv" in name or "k_mgs" in name or "k_arnoldi" in name)
                else "batch.hip" if "k_batch_solve" in name else None)
         if src is None:
             continue
@@ -165,7 +169,6 @@ def batch_traffic():
         if "k_batch_solve" in name and rec.get("source_sha") == source_hash("batch.hip"):
             return rec["bytes_per_launch"]
     return None
-    print(json.dumps(out["calibration"]))
 
 
 def cpu_model() -> str:

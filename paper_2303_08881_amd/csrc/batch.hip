@@ -174,7 +174,7 @@ template <int E, bool UP, int BT>
 struct Solve {
   const uint32_t *slot;  // [n * E/2] ring slots of the entries, two per word
   const double *val;     // [n * E] entry values (padding: 0 with slot XW)
-  const double *diag;    // [n] diagonal (UP)
+  const double *diag;    // [n] reciprocal of the diagonal (UP)
   const int32_t *outi;   // [n] index of each position's solution in out
   const int32_t *lev;    // LDS level pointers
   int nlev;
@@ -210,7 +210,7 @@ struct Solve {
       const int sl = (int)((s.slot[k >> 1] >> (16 * (k & 1))) & 0xffffu);
       acc = __builtin_fma(-s.val[k], S.ring[sl], acc);
     }
-    if (UP) acc = acc / s.diag;
+    if (UP) acc = acc * s.diag;
     if ((int)threadIdx.x < w) {
       S.ring[(p0 + (int)threadIdx.x) & (XW - 1)] = acc;
       out[s.out] = acc;
@@ -230,7 +230,7 @@ struct Solve {
           const int sl = (int)((slot[(size_t)q * (E / 2) + (k >> 1)] >> (16 * (k & 1))) & 0xffffu);
           acc = __builtin_fma(-val[(size_t)q * E + k], S.ring[sl], acc);
         }
-        if (UP) acc = acc / diag[q];
+        if (UP) acc = acc * diag[q];
         S.ring[q & (XW - 1)] = acc;
         out[outi[q]] = acc;
       }
@@ -238,12 +238,31 @@ struct Solve {
     __syncthreads();
   }
 
+  // The pipelined solve runs on the first ST threads: a level wider than
+  // BATCH_THREADS rows marks the system wide (run_wide), so more threads would
+  // only load the dummy position's data, and every level's loads pass
+  // through the CU's vector memory path.  The other threads keep the
+  // workgroup barriers in step (the same levels, the same merge test).
+  static constexpr int ST = BT < BATCH_THREADS ? BT : BATCH_THREADS;
   __device__ void run(Shared<BT> &S, bool wide) const {
     if (wide) {
       run_wide(S);
       return;
     }
-    constexpr int LOOK = look_of<E, BT>();
+    constexpr int LOOK = look_of<E, BT>();  // the register budget is that of BT threads
+    if (ST < BT && (int)threadIdx.x >= ST) {
+      bool prev_small = false;
+      for (int l = 0; l < nlev; l += LOOK) {
+#pragma unroll
+        for (int k = 0; k < LOOK; k++) {
+          const bool small = lev[l + k + 1] - lev[l + k] <= merge;
+          if (!(small && prev_small)) __syncthreads();
+          prev_small = small;
+        }
+      }
+      __syncthreads();
+      return;
+    }
     RowSet<E> R[LOOK];
     bool prev_small = false;
     // prologue in the loop's own load order, pinned by scheduling barriers:
@@ -391,7 +410,7 @@ __global__ void __launch_bounds__(BT) k_batch_solve(BatchArgs a) {
         a.Lval[g * E + e] = sl >= 0 ? a.lu[sl] : 0.0;
         a.Uval[g * E + e] = su >= 0 ? a.lu[su] : 0.0;
       }
-      a.Udiag[g] = a.lu[a.dpos[r0 + a.Urow[g]]];
+      a.Udiag[g] = 1.0 / a.lu[a.dpos[r0 + a.Urow[g]]];
     }
     __syncthreads();
 

@@ -19,6 +19,6 @@ def test_kernel_instance_names():
     assert bench.kernel_instance("trsv_LS", sched) == "void silu::k_trsv_lds_pair<1, 2, 0, true>"
     sched[17] = 1  # only L_B check-free
     assert bench.kernel_instance("trsv_LS", sched, 2) == "void silu::k_trsv_lds_pair<1, 2, 2, false>"
-    assert bench.kernel_instance("mgs", sched) == "void silu::k_mgs_step<"
+    assert bench.kernel_instance("mgs", sched) == "void silu::k_arnoldi<"
     assert bench.kernel_instance("spmv_A", sched) == "void silu::k_spmv<0>"
     assert bench.kernel_instance("spmv_Coff", sched) == "void silu::k_spmv<1>"
