@@ -693,10 +693,12 @@ static int build_lowp(ilu_precond *P, Schedule &S, const Csr &T, const double *d
 
 // Block-local storage of one factor: rows sorted by (subdomain, level), the
 // fixed-stride entries and the records.  omap (row -> output index) places
-// each solution; NULL puts it at its own position.
+// each solution; NULL puts it at its own position.  row_blk, when given,
+// replaces the subdomains by S.nblk sets of rows of its own (independent of
+// each other), one workgroup each.
 static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, const int64_t *bs1, const int64_t *bs2,
                        int64_t split, const double *diag, int64_t ext_col, const int32_t *omap, hipStream_t s,
-                       const char *phase) {
+                       const char *phase, const int32_t *row_blk = nullptr) {
   const int64_t n = T.n;
   S.use_block = true;
   S.ext_col = ext_col;
@@ -716,9 +718,13 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   void *rtmp;
   const size_t rtb = radix_tmp_bytes(nloc);
   RC(tmp.alloc((char **)&rtmp, (int64_t)rtb));
-  int32_t *blk;
-  RC(tmp.alloc(&blk, nloc));
-  RC(launch_row_blocks(nloc, (int32_t)S.nblk, bs1, nullptr, split, blk, s));
+  const int32_t *blk = row_blk;
+  if (!blk) {
+    int32_t *b;
+    RC(tmp.alloc(&b, nloc));
+    RC(launch_row_blocks(nloc, (int32_t)S.nblk, bs1, nullptr, split, b, s));
+    blk = b;
+  }
   RC(launch_block_level_keys(S.level_of, blk, nloc, S.nlev, key, val, s));
   RC(mem.alloc(&S.blk_rows, nloc));
   RC(radix_sort(key, val, key2, S.blk_rows, nloc, bits_for(nkeys - 1), rtmp, rtb, s));
@@ -771,6 +777,35 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   HIPCK(hipMemcpyAsync(&any_slow, dm, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCK(hipStreamSynchronize(s));
   S.lds_fast = fits && any_slow == 0;
+  return 0;
+}
+
+// The reduced system's rows split into the connected components of the
+// pattern of L_S + U_S: rows in different components never meet in a
+// triangular solve (the two interface planes of a slab, for instance), so
+// each component can be solved by its own workgroup, with half as many rows
+// per level or fewer.  Used when it gives a few more workgroups (more than
+// one component in some subdomain, at most 4 per subdomain on average and
+// one per CU); *ncomp = 0 keeps one workgroup per subdomain.  Components
+// never span subdomains (the local Schur factors are block diagonal) and
+// are numbered by their first row.
+static int schur_components(ilu_precond *P, Mem &tmp, int32_t **comp, int64_t *ncomp, void *stmp, size_t stmpb,
+                            hipStream_t s) {
+  const int64_t nS = P->nS;
+  *comp = nullptr;
+  *ncomp = 0;
+  if (nS == 0) return 0;
+  int32_t *lab, *root;
+  int64_t *isroot, *rank, total = 0;
+  RC(tmp.alloc(&lab, nS));
+  RC(tmp.alloc(&root, nS));
+  RC(tmp.alloc(&isroot, nS));
+  RC(launch_cc_label(P->LS.rp, P->LS.ci, P->US.rp, P->US.ci, nS, lab, root, isroot, s));
+  RC(make_rp(tmp, isroot, nS, &rank, &total, stmp, stmpb, s));
+  if (total <= P->nparts || total > std::min<int64_t>(4LL * P->nparts, P->num_cu)) return 0;
+  RC(tmp.alloc(comp, nS));
+  RC(launch_cc_number(root, rank, nS, *comp, s));
+  *ncomp = total;
   return 0;
 }
 
@@ -1188,8 +1223,17 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
   } else {
     RC(build_block(P, tmp, P->L1, P->sL1, bs_int, bs_ifc, nB, nullptr, INT64_MAX, nullptr, s, "levels L"));
     RC(build_block(P, tmp, P->U1, P->sU1, bs_int, nullptr, 0, P->DB, nB, nullptr, s, "levels U"));
-    RC(build_block(P, tmp, P->US, P->sUS, bs_loc, nullptr, 0, P->DS, INT64_MAX, nullptr, s, "levels U_S"));
-    RC(build_block(P, tmp, P->LS, P->sLS, bs_loc, nullptr, 0, nullptr, INT64_MAX, P->sUS.pos, s, "levels L_S"));
+    int32_t *scomp = nullptr;
+    int64_t ncomp = 0;
+    RC(schur_components(P, tmp, &scomp, &ncomp, stmp, stmpb, s));
+    if (ncomp > 0 && (uint64_t)ncomp * (uint64_t)std::max(P->sLS.nlev, P->sUS.nlev) < (1ull << 31)) {
+      P->sLS.nblk = P->sUS.nblk = ncomp;
+    } else {
+      scomp = nullptr;
+    }
+    RC(build_block(P, tmp, P->US, P->sUS, bs_loc, nullptr, 0, P->DS, INT64_MAX, nullptr, s, "levels U_S", scomp));
+    RC(build_block(P, tmp, P->LS, P->sLS, bs_loc, nullptr, 0, nullptr, INT64_MAX, P->sUS.pos, s, "levels L_S",
+                   scomp));
     RC(build_block_flow(P, tmp, stmp, stmpb, s));
   }
 

@@ -212,6 +212,13 @@ int launch_row_blocks(int64_t nrows, int32_t nblk, const int64_t *s1, const int6
                       hipStream_t s);
 int launch_block_level_keys(const int32_t *level, const int32_t *blk, int64_t n, int64_t nlev, uint32_t *key,
                             int32_t *val, hipStream_t s);
+// Connected components of the union of two patterns on rows [0, n) (edges
+// (r, c) with c in [0, n); rp2 may be NULL): root[i] = the smallest row of
+// i's component, isroot[i] = 1 for those rows (lab: n words of scratch).
+int launch_cc_label(const int64_t *rp1, const int32_t *ci1, const int64_t *rp2, const int32_t *ci2, int64_t n,
+                    int32_t *lab, int32_t *root, int64_t *isroot, hipStream_t s);
+// comp[i] = rank[root[i]] (rank: exclusive scan of isroot)
+int launch_cc_number(const int32_t *root, const int64_t *rank, int64_t n, int32_t *comp, hipStream_t s);
 int launch_i64_to_i32(const int64_t *in, int32_t *out, int64_t n, hipStream_t s);
 
 // ---- batch.hip ----

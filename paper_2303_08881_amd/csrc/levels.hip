@@ -205,6 +205,82 @@ int launch_row_blocks(int64_t nrows, int32_t nblk, const int64_t *s1, const int6
   return check_launch("row_blocks");
 }
 
+// ---- connected components of a symmetric pattern (union-find) ----------
+// Every label points to a smaller or equal index, so a find follows a
+// strictly decreasing chain and ends; a union hooks the larger root under
+// the smaller with a compare-and-swap and retries from what it finds when
+// another thread got there first, so one pass over the edges joins every
+// component (no iteration to a fixed point).  Labels are read with
+// device-scope loads: a stale copy only sends a find along an older, longer
+// chain, and the swap sees the current value.
+__device__ __forceinline__ int32_t cc_find(const int32_t *lab, int32_t x) {
+  for (;;) {
+    const int32_t p = ld_dev(lab + x);
+    if (p == x) return x;
+    x = p;
+  }
+}
+
+__global__ void k_cc_init(int32_t *lab, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) lab[i] = (int32_t)i;
+}
+
+// edges (r, c) of rows [0, n) with columns in [0, n), c != r
+__global__ void k_cc_hook(const int64_t *rp, const int32_t *ci, int64_t n, int32_t *lab) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int64_t p = rp[r]; p < rp[r + 1]; p++) {
+    const int64_t c = ci[p];
+    if (c < 0 || c >= n || c == r) continue;
+    int32_t a = cc_find(lab, (int32_t)r), b = cc_find(lab, (int32_t)c);
+    while (a != b) {
+      if (a < b) {
+        const int32_t t = a;
+        a = b;
+        b = t;
+      }
+      // a > b: hook root a under b, unless a is no longer a root
+      const int32_t old = atomicCAS(lab + a, a, b);
+      if (old == a) break;
+      a = cc_find(lab, old);
+      b = cc_find(lab, b);
+    }
+  }
+}
+
+// root[i] = the smallest index of i's component; isroot[i] = (root[i] == i)
+__global__ void k_cc_flatten(const int32_t *lab, int64_t n, int32_t *root, int64_t *isroot) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t r = cc_find(lab, (int32_t)i);
+  root[i] = r;
+  isroot[i] = r == (int32_t)i ? 1 : 0;
+}
+
+// comp[i] = number of the component of i (roots numbered in index order)
+__global__ void k_cc_number(const int32_t *root, const int64_t *rank, int64_t n, int32_t *comp) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) comp[i] = (int32_t)rank[root[i]];
+}
+
+int launch_cc_label(const int64_t *rp1, const int32_t *ci1, const int64_t *rp2, const int32_t *ci2, int64_t n,
+                    int32_t *lab, int32_t *root, int64_t *isroot, hipStream_t s) {
+  if (n == 0) return 0;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  k_cc_init<<<g, 256, 0, s>>>(lab, n);
+  k_cc_hook<<<g, 256, 0, s>>>(rp1, ci1, n, lab);
+  if (rp2) k_cc_hook<<<g, 256, 0, s>>>(rp2, ci2, n, lab);
+  k_cc_flatten<<<g, 256, 0, s>>>(lab, n, root, isroot);
+  return check_launch("cc_label");
+}
+
+int launch_cc_number(const int32_t *root, const int64_t *rank, int64_t n, int32_t *comp, hipStream_t s) {
+  if (n == 0) return 0;
+  k_cc_number<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(root, rank, n, comp);
+  return check_launch("cc_number");
+}
+
 __global__ void k_block_level_keys(const int32_t *level, const int32_t *blk, int64_t n, int64_t nlev, uint32_t *key,
                                    int32_t *val) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
