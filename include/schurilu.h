@@ -274,7 +274,10 @@ const char *ilu_last_error(void);
  *      entries per lane, threads per workgroup; then 1 if L_S and U_S run as
  *      one launch, a bit mask of the block-local solves that run without the
  *      slow-row and wide-level checks (bit k for solve k: no slow row, every
- *      level within the workgroup), the factor storage precision, and a zero.
+ *      level within the workgroup), the factor storage precision, and the
+ *      workgroups of the block-local L_S and U_S solves (one per subdomain,
+ *      or one per connected component of L_S + U_S when a subdomain has a
+ *      few; 0 when they are not block-local).
  */
 int ilu_export(ilu_precond_t *P, int32_t what, void *h_buf, int64_t *len);
 

@@ -2473,6 +2473,7 @@ int ilu_export(ilu_precond_t *P, int32_t what, void *h, int64_t *len) {
       }
       for (int k = 0; k < 4; k++) v[17] |= (sch[k]->use_block && sch[k]->lds_fast ? 1 : 0) << k;
       v[18] = P->opt.factor_prec;
+      v[19] = P->sLS.use_block ? (int32_t)P->sLS.nblk : 0;
       if (!h) {
         *len = 20;
         return 0;

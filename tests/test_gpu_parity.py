@@ -271,6 +271,17 @@ def test_errors_are_reported():
     assert e.value.code == -1
 
 
+def test_reduced_system_components(built):
+    # 12 x 12 x 16 grid, 4 z-slabs: the interface rows of each inner slab are two planes that L_S + U_S never
+    # couple, those of each end slab one plane, so the block-local L_S and U_S solves run on 6 workgroups
+    # (connected components found on the device; the count is the connected_components of the pattern)
+    idx = [i for i, (nm, o) in enumerate(CONFIGS) if nm == "aniso3d_slabs" and o["method"] == oracle.SCHUR][0]
+    A, b, part, p, o, P_o, Ad, P_g = built(idx, "block")
+    assert P_g.export("schedule")[19] == 6
+    idx_bj = [i for i, (nm, o) in enumerate(CONFIGS) if nm == "aniso3d_slabs" and o["method"] == oracle.BJ][0]
+    assert built(idx_bj, "block")[7].export("schedule")[19] == 0  # no reduced system
+
+
 @pytest.mark.parametrize("kind", ["one_row", "all_interface", "empty_part"])
 def test_edge_partitions(kind):
     m = silu()
@@ -331,6 +342,8 @@ def test_full_slab_setup_matches(slab_full):
         np.testing.assert_allclose(P_g.export(name), P_o.export(name), rtol=1e-12, err_msg=name)
     sched = P_g.export("schedule")
     assert all(sched[4 * k] == 1 for k in range(4)), sched  # the benchmark's block-local solves
+    # one workgroup per interface plane: 2 for each of the 14 inner slabs, 1 for each end slab
+    assert sched[19] == 30, sched
 
 
 @pytest.mark.slow
