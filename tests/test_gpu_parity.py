@@ -278,8 +278,12 @@ def test_reduced_system_components(built):
     idx = [i for i, (nm, o) in enumerate(CONFIGS) if nm == "aniso3d_slabs" and o["method"] == oracle.SCHUR][0]
     A, b, part, p, o, P_o, Ad, P_g = built(idx, "block")
     assert P_g.export("schedule")[19] == 6
+    # block Jacobi splits each whole-block factor the same way: its interface part has the same 6 components
     idx_bj = [i for i, (nm, o) in enumerate(CONFIGS) if nm == "aniso3d_slabs" and o["method"] == oracle.BJ][0]
-    assert built(idx_bj, "block")[7].export("schedule")[19] == 0  # no reduced system
+    assert built(idx_bj, "block")[7].export("schedule")[19] == 6
+    # one subdomain: no interface rows, no reduced-system solve
+    idx_one = [i for i, (nm, o) in enumerate(CONFIGS) if nm == "aniso2d_64"][0]
+    assert built(idx_one, "block")[7].export("schedule")[19] == 0
 
 
 @pytest.mark.parametrize("kind", ["one_row", "all_interface", "empty_part"])
