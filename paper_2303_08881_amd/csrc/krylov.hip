@@ -764,12 +764,13 @@ int launch_arnoldi_reset(unsigned long long *slots, int passes, hipStream_t s) {
 
 template <int K, bool SUM>
 static int arnoldi_capacity(int num_cu) {
-  static int per_cu = -1;  // resident workgroups per CU of this instance (a property of the code object)
-  if (per_cu < 0) {
+  // resident workgroups per CU of this instance, a property of the code
+  // object: asked once (a thread-safe static initialisation)
+  static const int per_cu = [] {
     int p = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, k_arnoldi<K, SUM>, ARN_TT, 0) != hipSuccess) p = 0;
-    per_cu = p;
-  }
+    return p;
+  }();
   return std::min(per_cu, 1) * num_cu;
 }
 

@@ -210,13 +210,18 @@ int launch_row_blocks(int64_t nrows, int32_t nblk, const int64_t *s1, const int6
 // strictly decreasing chain and ends; a union hooks the larger root under
 // the smaller with a compare-and-swap and retries from what it finds when
 // another thread got there first, so one pass over the edges joins every
-// component (no iteration to a fixed point).  Labels are read with
-// device-scope loads: a stale copy only sends a find along an older, longer
-// chain, and the swap sees the current value.
-__device__ __forceinline__ int32_t cc_find(const int32_t *lab, int32_t x) {
+// component (no iteration to a fixed point).  A find halves its path: a
+// label that is not a root is pointed at its grandparent, still an ancestor
+// in the same tree (only roots are ever hooked), which keeps the chains
+// short on path-like patterns.  Labels are read with device-scope loads: a
+// stale copy only sends a find along an older, longer chain, and the swap
+// sees the current value.
+__device__ __forceinline__ int32_t cc_find(int32_t *lab, int32_t x) {
   for (;;) {
     const int32_t p = ld_dev(lab + x);
     if (p == x) return x;
+    const int32_t gp = ld_dev(lab + p);
+    if (gp != p) st_dev(lab + x, gp);
     x = p;
   }
 }
@@ -250,7 +255,7 @@ __global__ void k_cc_hook(const int64_t *rp, const int32_t *ci, int64_t n, int32
 }
 
 // root[i] = the smallest index of i's component; isroot[i] = (root[i] == i)
-__global__ void k_cc_flatten(const int32_t *lab, int64_t n, int32_t *root, int64_t *isroot) {
+__global__ void k_cc_flatten(int32_t *lab, int64_t n, int32_t *root, int64_t *isroot) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int32_t r = cc_find(lab, (int32_t)i);

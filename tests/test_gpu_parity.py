@@ -286,6 +286,24 @@ def test_reduced_system_components(built):
     assert built(idx_one, "block")[7].export("schedule")[19] == 0
 
 
+def test_components_of_long_chains():
+    # 512 x 64 grid, 4 bands of 16 lines (x fastest): the interface rows are the lines next to a neighbouring
+    # band, 6 lines of 512 rows, each a chain in L_S + U_S (the union-find sees paths 512 long); the apply still
+    # matches the oracle
+    m = silu()
+    A = synth.aniso5(512, 0.1, Ny=64)
+    part = synth.block_partition(A.n, 4)
+    o = dict(method=oracle.SCHUR, interior_fact=oracle.ILU0, interface_fact=oracle.ILU0, inner_iters=3)
+    P_o = oracle.Precond(A, part, 4, **o)
+    P_g = m.setup(m.DeviceCSR.from_host(A), part, 4, trsv_mode=m.TRSV_BLOCK, **o)
+    assert P_g.info()["nS"] == 6 * 512
+    assert P_g.export("schedule")[19] == 6
+    r = synth.uniform_rhs(A.n, 9)
+    zo = P_o.apply(r)
+    zg = P_g.apply(torch.as_tensor(r).cuda()).cpu().numpy()
+    np.testing.assert_allclose(zg, zo, rtol=1e-10, atol=1e-10 * np.abs(zo).max())
+
+
 @pytest.mark.parametrize("kind", ["one_row", "all_interface", "empty_part"])
 def test_edge_partitions(kind):
     m = silu()
