@@ -37,9 +37,11 @@ HBM_PEAK_GBS = 8000.0
 KERNELS = ["trsv_LB_W", "trsv_UB_Z", "trsv_LS", "trsv_US", "spmv_A", "spmv_Coff", "mgs"]
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 CSRC = os.path.join(ROOT, "paper_2303_08881_amd", "csrc")
-# source file of each kernel class (traffic figures are void once it changes)
-KERNEL_SOURCE = {"trsv_LB_W": "trsv.hip", "trsv_UB_Z": "trsv.hip", "trsv_LS": "trsv.hip", "trsv_US": "trsv.hip",
-                 "spmv_A": "krylov.hip", "spmv_Coff": "krylov.hip", "mgs": "krylov.hip"}
+# source files of each kernel class (traffic figures are void once one changes)
+TRSV_SOURCES = ("trsv.hip", "trsv_split.hip", "trsv_lds.hpp")
+KERNEL_SOURCE = {"trsv_LB_W": TRSV_SOURCES, "trsv_UB_Z": TRSV_SOURCES, "trsv_LS": TRSV_SOURCES,
+                 "trsv_US": TRSV_SOURCES, "spmv_A": ("krylov.hip",), "spmv_Coff": ("krylov.hip",),
+                 "mgs": ("krylov.hip",)}
 # block-local solve instance of each class: k_trsv_lds<G, E, DIAG> (schedule index, DIAG)
 TRSV_ROLE = {"trsv_LB_W": (0, "false"), "trsv_UB_Z": (1, "true"), "trsv_LS": (2, "false"), "trsv_US": (3, "true")}
 COPY_BYTES = 256 << 20  # the calibration copy: 256 MiB read, 256 MiB written
@@ -71,11 +73,15 @@ DESCRIPTION = {
 }
 
 
-def source_hash(name: str) -> str:
+def source_hash(names) -> str:
+    """Hash of one source file, or of several in the given order."""
     import hashlib
 
-    with open(os.path.join(CSRC, name), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ((names,) if isinstance(names, str) else names):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def kernel_instance(cls: str, sched, prec: int = 0) -> str | None:
@@ -89,6 +95,8 @@ def kernel_instance(cls: str, sched, prec: int = 0) -> str | None:
         if cls == "trsv_LS" and sched[16]:  # L_S and U_S in one launch (fast only if both are)
             both = "true" if (sched[17] >> 2) & (sched[17] >> 3) & 1 else "false"
             return f"void silu::k_trsv_lds_pair<{sched[9]}, {sched[10]}, {prec}, {both}>"
+        if k < 2 and len(sched) > 21 and sched[20 + k] > 1:  # L_B or U_B split over workgroups
+            return f"void silu::k_trsv_lds_x<{sched[4 * k + 1]}, {sched[4 * k + 2]}, {diag}, {prec}>"
         return f"void silu::k_trsv_lds<{sched[4 * k + 1]}, {sched[4 * k + 2]}, {diag}, {prec}, {fast(k)}>"
     # the outer orthogonalisation: one k_arnoldi launch per Arnoldi step (w from the product, not a sum)
     return {"spmv_A": "void silu::k_spmv<0>", "spmv_Coff": "void silu::k_spmv<1>",
@@ -138,7 +146,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str) -> None:
                                                   "write_factor": cw},
            "kernels": {}}
     for name in fetch:
-        src = ("trsv.hip" if "k_trsv" in name
+        src = (TRSV_SOURCES if "k_trsv" in name
                else "krylov.hip" if ("k_spmv" in name or "k_mgs" in name or "k_arnoldi" in name)
                else "batch.hip" if "k_batch_solve" in name else None)
         if src is None:

@@ -58,7 +58,7 @@ extern "C" {
 #define ILU_PREC_F64 0     /* triangular factors stored and solved in FP64      */
 #define ILU_PREC_F32 1     /* stored in FP32, solved in FP32                     */
 #define ILU_PREC_F16 2     /* stored in FP16 (scaled per row), solved in FP32    */
-#define ILU_ARNOLDI_AUTO 0     /* one cooperative launch per Arnoldi step when the vectors fit */
+#define ILU_ARNOLDI_AUTO 0     /* one launch per Arnoldi step when the vectors fit          */
 #define ILU_ARNOLDI_PER_PASS 1 /* one launch per Gram-Schmidt pass                             */
 
 typedef struct {
@@ -122,16 +122,28 @@ typedef struct {
  *  arnoldi_mode   how the modified Gram-Schmidt of each Arnoldi step runs, in
  *                 fgmres_solve and in the reduced-system GMRES of ilu_apply
  *                 (results agree to the grouping of the dot-product sums):
- *                 ILU_ARNOLDI_AUTO takes one cooperative launch per step
- *                 (every pass of the step inside it, the new direction held
- *                 on chip, grid-wide barriers between the passes) when the
- *                 vectors fit it (even length, up to 2^21 rows on a 256-CU
- *                 device), and one launch per pass otherwise;
- *                 ILU_ARNOLDI_PER_PASS always takes one launch per pass.  A
- *                 cooperative launch holds its workgroups resident while they
- *                 wait for each other: solves that run at the same time on one
- *                 device (several streams) should use ILU_ARNOLDI_PER_PASS,
- *                 as the request server does for its handles.
+ *                 ILU_ARNOLDI_AUTO takes one launch per step (every pass of
+ *                 the step inside it, the new direction held on chip, the
+ *                 workgroups waiting for each other's partial sums between
+ *                 the passes) when the vectors fit it (even length, up to
+ *                 2^21 rows on a 256-CU device), and one launch per pass
+ *                 otherwise; ILU_ARNOLDI_PER_PASS always takes one launch per
+ *                 pass.  Such a launch needs all its workgroups resident at
+ *                 once: solves that run at the same time on one device
+ *                 (several streams) should use ILU_ARNOLDI_PER_PASS, as the
+ *                 request server does for its handles.
+ *  block_split    workgroups per subdomain in the block-local L_B and U_B
+ *                 solves (results are identical for every value): 1 gives
+ *                 each subdomain one workgroup; K >= 2 (at most 64) splits
+ *                 its rows into K consecutive ranges, one workgroup each,
+ *                 which solve their levels side by side and pass the values
+ *                 that a later range needs from an earlier one through
+ *                 device memory (each such value read by one range only;
+ *                 otherwise, or when a range's level needs more than 64 of
+ *                 them, the solve stays unsplit); 0 (auto) takes 2 for
+ *                 subdomains of at least 32768 rows when twice the number of
+ *                 subdomains fits the CUs.  The solves of one handle must not
+ *                 run at the same time (they share the exchange buffers).
  */
 typedef struct {
   int32_t method;
@@ -147,6 +159,7 @@ typedef struct {
   int32_t factor_prec;
   int32_t smooth_fact;
   int32_t arnoldi_mode;
+  int32_t block_split;
 } ilu_options_t;
 
 typedef struct {
@@ -269,7 +282,7 @@ const char *ilu_last_error(void);
  *   30 C_off (interface rows, other subdomains' interface columns);
  *   16 diag of U_B [double n_B], 29 diag of U_S [double n_S];
  *   40..43 level of each row of L_B, U_B, L_S, U_S [int32];
- *   44 schedule of the L_B, U_B, L_S, U_S solves [int32 20]: for each, 1 if
+ *   44 schedule of the L_B, U_B, L_S, U_S solves [int32 22]: for each, 1 if
  *      solved block-locally (one workgroup per subdomain), lanes per row,
  *      entries per lane, threads per workgroup; then 1 if L_S and U_S run as
  *      one launch, a bit mask of the block-local solves that run without the
@@ -277,7 +290,9 @@ const char *ilu_last_error(void);
  *      level within the workgroup), the factor storage precision, and the
  *      workgroups of the block-local L_S and U_S solves (one per subdomain,
  *      or one per connected component of L_S + U_S when a subdomain has a
- *      few; 0 when they are not block-local).
+ *      few; 0 when they are not block-local), and the workgroups per
+ *      subdomain of the block-local L_B and U_B solves (block_split; 0 when
+ *      they are not block-local).
  */
 int ilu_export(ilu_precond_t *P, int32_t what, void *h_buf, int64_t *len);
 

@@ -50,7 +50,7 @@ class _Opts(C.Structure):
                 ("droptol", C.c_double), ("lfil", C.c_int32), ("inner_iters", C.c_int32),
                 ("inner_rtol", C.c_double), ("pivot_mode", C.c_int32), ("pivot_tol", C.c_double),
                 ("trsv_mode", C.c_int32), ("factor_prec", C.c_int32), ("smooth_fact", C.c_int32),
-                ("arnoldi_mode", C.c_int32)]
+                ("arnoldi_mode", C.c_int32), ("block_split", C.c_int32)]
 
 
 class _Req(C.Structure):
@@ -160,9 +160,9 @@ class DeviceCSR:
 
 def _options(method=BJ, interior_fact=ILU0, interface_fact=ILU0, droptol=0.0, lfil=-1, inner_iters=3,
              inner_rtol=0.0, pivot_mode=PIVOT_ERROR, pivot_tol=0.0, trsv_mode=TRSV_AUTO, factor_prec=PREC_F64,
-             smooth_fact=ILU0, arnoldi_mode=ARNOLDI_AUTO):
+             smooth_fact=ILU0, arnoldi_mode=ARNOLDI_AUTO, block_split=0):
     return _Opts(method, interior_fact, interface_fact, droptol, lfil, inner_iters, inner_rtol, pivot_mode,
-                 pivot_tol, trsv_mode, factor_prec, smooth_fact, arnoldi_mode)
+                 pivot_tol, trsv_mode, factor_prec, smooth_fact, arnoldi_mode, block_split)
 
 
 # Every live handle, so that the exit hook below can release them while the

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 INC = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libschurilu.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["prims.hip", "setup.hip", "factor.hip", "levels.hip", "trsv.hip", "krylov.hip", "batch.hip", "capi.cpp", "serve.cpp"]
+SOURCES = ["prims.hip", "setup.hip", "factor.hip", "levels.hip", "trsv.hip", "trsv_split.hip", "krylov.hip",
+           "batch.hip", "capi.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -270,6 +270,14 @@ struct Schedule {
   bool lds_fast = false;  // no slow row and no level wider than the workgroup
   int64_t ext_col = 0;  // dependency columns of the block-local solve are < ext_col
   int64_t nloc = 0;     // rows in the block-local solve (the rows of W follow in their own pass)
+  // each block split over split_k workgroups (nblk counts the parts): the
+  // exchange slots, the exports ({position, slot}) and imports by (part,
+  // level), their number and the start-order ticket
+  int32_t split_k = 1;
+  double *xv = nullptr;
+  int32_t *xe = nullptr, *elp = nullptr, *ilp = nullptr;
+  int64_t nimp = 0;
+  unsigned long long *xticket = nullptr;
 };
 
 // Buffers of one FGMRES(m) process on vectors of length n.  With the two
@@ -324,7 +332,7 @@ struct ilu_precond {
          *ig = nullptr, *ic = nullptr, *ipa = nullptr, *ipb = nullptr, *iscal = nullptr;
   int *iflags = nullptr;
   unsigned long long *islots = nullptr, ilaunch = 0;  // sum slots of the one-launch orthogonalisation
-  bool arnoldi_coop = true;  // Arnoldi orthogonalisation as one cooperative launch per step (arnoldi_mode)
+  bool arnoldi_coop = true;  // Arnoldi orthogonalisation as one launch per step (arnoldi_mode)
   Status *status = nullptr;
   double *host_pinned = nullptr;  // 8 doubles for read-backs
   int64_t *blk_starts = nullptr;  // device: interior starts, interface starts, interface starts (local)
@@ -698,7 +706,7 @@ static int build_lowp(ilu_precond *P, Schedule &S, const Csr &T, const double *d
 // each other), one workgroup each.
 static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, const int64_t *bs1, const int64_t *bs2,
                        int64_t split, const double *diag, int64_t ext_col, const int32_t *omap, hipStream_t s,
-                       const char *phase, const int32_t *row_blk = nullptr) {
+                       const char *phase, const int32_t *row_blk = nullptr, const int32_t *xrow = nullptr) {
   const int64_t n = T.n;
   S.use_block = true;
   S.ext_col = ext_col;
@@ -771,13 +779,200 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   RC(mem.alloc(&S.lds_rec, 4 * (nloc + 1)));
   S.out_map = omap ? omap : S.pos;
   RC(fill_i32(dm, 0, 1, s));  // reused as the slow-row flag
+  // with xrow (a split block), dependencies across parts name import slots
   RC(launch_lds_fill(S.blk_rows, T.rp, T.ci, T.v, diag, nloc, ext_col, S.pos, S.blk_lev_ptr, (int64_t)nkeys, G, E, prec,
-                     S.out_map, S.lds_c, S.lds_v, S.lds_rec, dm, s));
+                     S.out_map, S.lds_c, S.lds_v, S.lds_rec, dm, xrow ? row_blk : nullptr, xrow, S.ilp, S.nlev, s));
   int32_t any_slow = 1;
   HIPCK(hipMemcpyAsync(&any_slow, dm, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCK(hipStreamSynchronize(s));
   S.lds_fast = fits && any_slow == 0;
   return 0;
+}
+
+// Workgroups per subdomain of the block-local solve of an interior factor
+// (nloc rows in the block-local solve): block_split, or under 0 (auto) two
+// for subdomains of at least 32768 rows while the parts fit the CUs.
+static int32_t split_parts(const ilu_precond *P, const Schedule &S, int64_t nloc) {
+  const int32_t k = P->opt.block_split;
+  if (k == 1 || nloc == 0 || P->nparts < 1 || S.nlev > SPLIT_LEVELS) return 1;
+  if (k >= 2) return k;
+  return (nloc / P->nparts >= 32768 && 2LL * P->nparts <= P->num_cu) ? 2 : 1;
+}
+
+// The split of each subdomain's block-local solve over K workgroups
+// (trsv_split.hip): the part of each row (K ranges of the block, numbered
+// from its end for a backward solve) and the values parts pass to each
+// other, sorted by (importing part, level that first needs them).  Leaves
+// the schedule unsplit (*ok = false) when a row would be imported by two
+// parts, an import by a part that does not come later, an import that
+// would leave its part's LDS ring before it is read, or more than 64
+// imports for one level of one part.  *part, *xrow (row -> import index, or
+// -1) and *isrc (import -> source row) live in tmp and feed build_block and
+// build_exports.
+static int build_split(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, const int64_t *bs, int64_t nloc,
+                       int64_t ext_col, int32_t K, bool backward, hipStream_t s, int32_t **part_out,
+                       int32_t **xrow_out, int32_t **isrc_out, bool *ok) {
+  *ok = false;
+  const int64_t nblk = (int64_t)P->nparts * K, nlev = S.nlev;
+  const uint64_t nkeys = (uint64_t)nblk * (uint64_t)nlev;
+  if (nloc == 0 || nkeys >= (1ull << 31) || nlev > SPLIT_LEVELS) return 0;
+  int32_t *part, *xrow, *bad;
+  int64_t *cnt, *off, m = 0;
+  RC(tmp.alloc(&part, nloc));
+  RC(tmp.alloc(&cnt, nloc));
+  RC(tmp.alloc(&bad, 4));
+  RC(fill_i32(bad, 0, 4, s));
+  RC(launch_split_parts(bs, P->nparts, nloc, K, backward, part, s));
+  RC(launch_cross_count(T.rp, T.ci, nloc, ext_col, part, cnt, s));
+  size_t stb = scan_tmp_bytes(std::max<int64_t>(nloc, (int64_t)nkeys)) + 64;
+  void *stmp;
+  RC(tmp.alloc((char **)&stmp, (int64_t)stb));
+  RC(make_rp(tmp, cnt, nloc, &off, &m, stmp, stb, s));
+  if (m >= ((int64_t)1 << 31)) return 0;
+  const int64_t mm = std::max<int64_t>(m, 1);
+  uint32_t *src, *k1, *k2;
+  int32_t *key, *v1, *v2;
+  RC(tmp.alloc(&src, mm));
+  RC(tmp.alloc(&key, mm));
+  RC(tmp.alloc(&k1, mm));
+  RC(tmp.alloc(&v1, mm));
+  RC(tmp.alloc(&k2, mm));
+  RC(tmp.alloc(&v2, mm));
+  RC(launch_cross_emit(T.rp, T.ci, nloc, ext_col, part, S.level_of, nlev, off, src, key, s));
+  const size_t rtb = radix_tmp_bytes(mm);
+  void *rtmp;
+  RC(tmp.alloc((char **)&rtmp, (int64_t)rtb));
+  // by key, then (stable) by source row: each source's records in key order
+  RC(radix_sort(reinterpret_cast<const uint32_t *>(key), reinterpret_cast<const int32_t *>(src), k1, v1, m,
+                bits_for(nkeys - 1), rtmp, rtb, s));
+  RC(radix_sort(reinterpret_cast<const uint32_t *>(v1), reinterpret_cast<const int32_t *>(k1), k2, v2, m,
+                bits_for((uint64_t)std::max<int64_t>(nloc - 1, 1)), rtmp, rtb, s));
+  int64_t *head, *rank, nimp = 0;
+  RC(tmp.alloc(&head, mm));
+  RC(launch_cross_heads(k2, v2, m, part, nlev, head, bad, s));
+  const size_t stb2 = scan_tmp_bytes(mm) + 64;
+  void *stmp2;
+  RC(tmp.alloc((char **)&stmp2, (int64_t)stb2));
+  RC(make_rp(tmp, head, m, &rank, &nimp, stmp2, stb2, s));
+  const int64_t ni = std::max<int64_t>(nimp, 1);
+  uint32_t *isrc, *ikey, *ikey2;
+  int32_t *isrc2;
+  RC(tmp.alloc(&isrc, ni));
+  RC(tmp.alloc(&ikey, ni));
+  RC(tmp.alloc(&ikey2, ni));
+  RC(tmp.alloc(&isrc2, ni));
+  RC(launch_cross_compact(k2, v2, m, head, rank, isrc, ikey, s));
+  const size_t rtb2 = radix_tmp_bytes(ni);
+  void *rtmp2;
+  RC(tmp.alloc((char **)&rtmp2, (int64_t)rtb2));
+  // imports by (part, level), source rows ascending within each
+  RC(radix_sort(ikey, reinterpret_cast<const int32_t *>(isrc), ikey2, isrc2, nimp, bits_for(nkeys - 1), rtmp2, rtb2,
+                s));
+  int64_t *icnt, *iptr, itot = 0;
+  RC(tmp.alloc(&icnt, (int64_t)nkeys));
+  RC(histogram_keys(ikey2, nimp, (int64_t)nkeys, icnt, s));
+  RC(make_rp(tmp, icnt, (int64_t)nkeys, &iptr, &itot, stmp, stb, s));
+  int32_t *ilp;
+  RC(P->mem.alloc(&ilp, (int64_t)nkeys + 1));
+  RC(launch_i64_to_i32(iptr, ilp, (int64_t)nkeys + 1, s));
+  RC(tmp.alloc(&xrow, nloc));
+  RC(fill_i32(xrow, -1, nloc, s));
+  RC(launch_cross_slots(isrc2, nimp, xrow, s));
+  RC(launch_cross_check(T.rp, T.ci, nloc, ext_col, part, S.level_of, nlev, xrow, ilp, bad, s));
+  RC(launch_cross_width(ilp, (int64_t)nkeys, bad, s));
+  int32_t hb[4] = {0, 0, 0, 0};
+  HIPCK(hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  if (hb[0] || hb[1] || hb[2] || hb[3] || nimp + 64 * nblk >= ((int64_t)1 << 29)) return 0;
+  // the slots, then a pad of 64 words per part for the idle lanes of its import wave
+  RC(P->mem.alloc(&S.xv, nimp + 64 * nblk));
+  RC(launch_fill_unset(S.xv, nimp + 64 * nblk, s));
+  RC(P->mem.alloc(&S.xticket, 1));
+  HIPCK(hipMemsetAsync(S.xticket, 0, sizeof(unsigned long long), s));
+  S.ilp = ilp;
+  S.nimp = nimp;
+  S.split_k = K;
+  S.nblk = nblk;
+  *part_out = part;
+  *xrow_out = xrow;
+  *isrc_out = isrc2;
+  *ok = true;
+  return 0;
+}
+
+// The exports of a split solve, once the positions are known: one per
+// import, sorted by (exporting part, level of the source row) and stored as
+// {position, slot}.  *ok = false when a level of a part exports more than 64
+// rows (one lane each in the exchange wave).
+static int build_exports(ilu_precond *P, Mem &tmp, Schedule &S, const int32_t *part, const int32_t *isrc,
+                         hipStream_t s, bool *ok) {
+  *ok = false;
+  const int64_t nimp = S.nimp, nkeys = S.nblk * S.nlev, ni = std::max<int64_t>(nimp, 1);
+  uint32_t *key, *key2;
+  int32_t *val, *egi, *bad;
+  RC(tmp.alloc(&key, ni));
+  RC(tmp.alloc(&val, ni));
+  RC(tmp.alloc(&key2, ni));
+  RC(tmp.alloc(&egi, ni));
+  RC(tmp.alloc(&bad, 4));
+  RC(fill_i32(bad, 0, 4, s));
+  RC(launch_export_keys(isrc, nimp, part, S.level_of, S.nlev, key, val, s));
+  const size_t rtb = radix_tmp_bytes(ni);
+  void *rtmp;
+  RC(tmp.alloc((char **)&rtmp, (int64_t)rtb));
+  RC(radix_sort(key, val, key2, egi, nimp, bits_for((uint64_t)nkeys - 1), rtmp, rtb, s));
+  int64_t *cnt, *ptr, tot = 0;
+  RC(tmp.alloc(&cnt, nkeys));
+  RC(histogram_keys(key2, nimp, nkeys, cnt, s));
+  const size_t stb = scan_tmp_bytes(nkeys) + 64;
+  void *stmp;
+  RC(tmp.alloc((char **)&stmp, (int64_t)stb));
+  RC(make_rp(tmp, cnt, nkeys, &ptr, &tot, stmp, stb, s));
+  int32_t *elp, *xe;
+  RC(P->mem.alloc(&elp, nkeys + 1));
+  RC(launch_i64_to_i32(ptr, elp, nkeys + 1, s));
+  RC(launch_cross_width(elp, nkeys, bad, s));
+  int32_t hb[4] = {0, 0, 0, 0};
+  HIPCK(hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  if (hb[3]) return 0;
+  RC(P->mem.alloc(&xe, 2 * (nimp + 1)));
+  RC(launch_export_fill(egi, isrc, S.pos, nimp, xe, s));
+  S.elp = elp;
+  S.xe = xe;
+  *ok = true;
+  return 0;
+}
+
+// Block-local storage of an interior factor (L_B with the W rows after it,
+// or U_B), split over several workgroups per subdomain when split_parts
+// asks for it and the split applies; unsplit otherwise.
+static int build_block_interior(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, const int64_t *bs1,
+                                const int64_t *bs2, int64_t split, const double *diag, int64_t ext_col,
+                                bool backward, hipStream_t s, const char *phase) {
+  const int64_t nloc = bs2 ? split : T.n;
+  const int32_t K = split_parts(P, S, nloc);
+  if (K > 1) {
+    int32_t *part = nullptr, *xrow = nullptr, *isrc = nullptr;
+    bool ok = false;
+    RC(build_split(P, tmp, T, S, bs1, nloc, ext_col, K, backward, s, &part, &xrow, &isrc, &ok));
+    if (ok) {
+      RC(build_block(P, tmp, T, S, bs1, bs2, split, diag, ext_col, nullptr, s, phase, part, xrow));
+      // check-free factors only, the compute threads and the two exchange waves within 512
+      if (S.lds_fast && S.lds_bt <= 384) {
+        RC(build_exports(P, tmp, S, part, isrc, s, &ok));
+        if (ok) return 0;
+      }
+    }
+    // build the unsplit solve
+    S.split_k = 1;
+    S.xv = nullptr;
+    S.xe = S.elp = S.ilp = nullptr;
+    S.nimp = 0;
+    S.xticket = nullptr;
+    S.nblk = P->nparts;
+  }
+  return build_block(P, tmp, T, S, bs1, bs2, split, diag, ext_col, nullptr, s, phase);
 }
 
 // The reduced system's rows split into the connected components of the
@@ -908,6 +1103,14 @@ static TrsvLaunch make_launch(ilu_precond *P, Schedule &S, const Csr &T, const d
     t.lds_fast = S.lds_fast ? 1 : 0;
     t.split_col = S.ext_col;
     t.nrows = S.nloc;
+    if (S.split_k > 1) {
+      t.xv = S.xv;
+      t.xe = S.xe;
+      t.elp = S.elp;
+      t.ilp = S.ilp;
+      t.nimp = S.nimp;
+      t.xticket = S.xticket;
+    }
   }
   t.prec = P->opt.factor_prec;
   t.f64_row = role == 0 ? P->nB : INT64_MAX;
@@ -929,7 +1132,7 @@ static int trsv(ilu_precond *P, Schedule &S, const Csr &T, const double *diag, i
   if (S.use_block) {
     if (bmap || scat) return fail(ILU_ERR_INVALID_ARG, "internal: block-local solves take no gather or scatter map");
     return timed(ILU_K_TRSV_LB + role, bytes, s, [&] {
-      RC(launch_trsv_lds(t, s));
+      RC(t.xv ? launch_trsv_lds_split(t, s) : launch_trsv_lds(t, s));
       if (after) RC(after());
       return 0;
     });
@@ -1029,6 +1232,7 @@ void ilu_default_options(ilu_options_t *o) {
   o->factor_prec = ILU_PREC_F64;
   o->smooth_fact = ILU_FACT_ILU0;
   o->arnoldi_mode = ILU_ARNOLDI_AUTO;
+  o->block_split = 0;
 }
 
 const char *ilu_last_error(void) { return g_err.c_str(); }
@@ -1221,8 +1425,8 @@ static int setup_impl(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts,
       RC(build_lowp(P, P->sUS, P->US, P->DS, INT64_MAX, s));
     }
   } else {
-    RC(build_block(P, tmp, P->L1, P->sL1, bs_int, bs_ifc, nB, nullptr, INT64_MAX, nullptr, s, "levels L"));
-    RC(build_block(P, tmp, P->U1, P->sU1, bs_int, nullptr, 0, P->DB, nB, nullptr, s, "levels U"));
+    RC(build_block_interior(P, tmp, P->L1, P->sL1, bs_int, bs_ifc, nB, nullptr, INT64_MAX, false, s, "levels L"));
+    RC(build_block_interior(P, tmp, P->U1, P->sU1, bs_int, nullptr, 0, P->DB, nB, true, s, "levels U"));
     int32_t *scomp = nullptr;
     int64_t ncomp = 0;
     RC(schur_components(P, tmp, &scomp, &ncomp, stmp, stmpb, s));
@@ -1306,6 +1510,8 @@ int ilu_setup(const ilu_csr_t *A, const int32_t *d_part, int32_t nparts, const i
     return fail(ILU_ERR_INVALID_ARG, "unknown trsv_mode %d", opt.trsv_mode);
   if (opt.arnoldi_mode != ILU_ARNOLDI_AUTO && opt.arnoldi_mode != ILU_ARNOLDI_PER_PASS)
     return fail(ILU_ERR_INVALID_ARG, "unknown arnoldi_mode %d", opt.arnoldi_mode);
+  if (opt.block_split < 0 || opt.block_split > 64)
+    return fail(ILU_ERR_INVALID_ARG, "block_split must be in [0, 64] (is %d)", opt.block_split);
   hipStream_t s = (hipStream_t)stream;
   ilu_precond *P = new ilu_precond();
   P->n = A->n;
@@ -1374,7 +1580,7 @@ static int reset_arnoldi(ilu_precond *P, KrylovBufs *w, hipStream_t s) {
 // given) minus its modified Gram-Schmidt projections on v_0..v_j (v_i at
 // V + i n), H column j to hcol, and the partials of <w, w> for the Givens
 // step (*pnorm; *npart of them, 0 meaning a per-pass reduction's count).
-// One cooperative launch when the handle allows it and the vectors fit,
+// One launch per step when the handle allows it and the vectors fit,
 // else a dot pass (fused with the sum) and one launch per MGS pass.
 // kind >= 0: the launches are timed as that kernel class.
 static int orthogonalize(ilu_precond *P, double *w, const double *a, const double *b, const double *V, int64_t n,
@@ -2264,28 +2470,28 @@ int ilu_batch_tune(ilu_batch_t *B, const double *d_val, const double *d_b, doubl
   int rc = 0;
   for (int th : {256, 512}) {
     const int per = batch_resident_groups(B->core.num_cu, B->E, th) / std::max(B->core.num_cu, 1);
-  for (int w = 1; w <= per && !rc; w++)
-    for (int mg : merges) {
-      if ((rc = ilu_batch_schedule(B, mg, w, th))) break;
-      if (hipMemcpyAsync(d_x, x0, sizeof(double) * B->n, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-        rc = fail(ILU_ERR_HIP, "batched tuning: restoring the initial guess failed");
-        break;
+    for (int w = 1; w <= per && !rc; w++)
+      for (int mg : merges) {
+        if ((rc = ilu_batch_schedule(B, mg, w, th))) break;
+        if (hipMemcpyAsync(d_x, x0, sizeof(double) * B->n, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+          rc = fail(ILU_ERR_HIP, "batched tuning: restoring the initial guess failed");
+          break;
+        }
+        (void)hipEventRecord(e0, s);
+        if ((rc = batch_launch(B, d_val, d_b, d_x, rtol, restart, maxit, s))) break;
+        (void)hipEventRecord(e1, s);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          rc = fail(ILU_ERR_HIP, "batched tuning: event timing failed");
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          bm = mg;
+          bw = w;
+          bb = th;
+        }
       }
-      (void)hipEventRecord(e0, s);
-      if ((rc = batch_launch(B, d_val, d_b, d_x, rtol, restart, maxit, s))) break;
-      (void)hipEventRecord(e1, s);
-      float ms = 0.f;
-      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        rc = fail(ILU_ERR_HIP, "batched tuning: event timing failed");
-        break;
-      }
-      if (ms < best) {
-        best = ms;
-        bm = mg;
-        bw = w;
-        bb = th;
-      }
-    }
     if (rc) break;
   }
   (void)hipEventDestroy(e0);
@@ -2459,7 +2665,7 @@ int ilu_export(ilu_precond_t *P, int32_t what, void *h, int64_t *len) {
     case 43: return export_raw(P->sUS.level_of, nS, 4, h, len);
     case 44: {  // schedule of the four solves, then whether L_S and U_S run as one launch
       const Schedule *sch[4] = {&P->sL1, &P->sU1, &P->sLS, &P->sUS};
-      int32_t v[20] = {0};
+      int32_t v[22] = {0};
       for (int k = 0; k < 4; k++) {
         v[4 * k] = sch[k]->use_block ? 1 : 0;
         v[4 * k + 1] = sch[k]->lds_g;
@@ -2474,12 +2680,14 @@ int ilu_export(ilu_precond_t *P, int32_t what, void *h, int64_t *len) {
       for (int k = 0; k < 4; k++) v[17] |= (sch[k]->use_block && sch[k]->lds_fast ? 1 : 0) << k;
       v[18] = P->opt.factor_prec;
       v[19] = P->sLS.use_block ? (int32_t)P->sLS.nblk : 0;
+      v[20] = P->sL1.use_block ? P->sL1.split_k : 0;
+      v[21] = P->sU1.use_block ? P->sU1.split_k : 0;
       if (!h) {
-        *len = 20;
+        *len = 22;
         return 0;
       }
-      if (*len < 20) return fail(ILU_ERR_INVALID_ARG, "export buffer too small");
-      *len = 20;
+      if (*len < 22) return fail(ILU_ERR_INVALID_ARG, "export buffer too small");
+      *len = 22;
       memcpy(h, v, sizeof(v));
       return 0;
     }

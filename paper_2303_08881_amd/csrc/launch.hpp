@@ -165,6 +165,15 @@ struct TrsvLaunch {
   const float *diag_lp;
   const float *scale_lp;
   int64_t f64_row = INT64_MAX;  // level-scheduled lower solve: rows from here on (W) stay FP64
+  // block split over several workgroups (launch_trsv_lds_split; nblk counts
+  // the parts): exchange slots, the exports ({position, slot}) and imports by
+  // (part, level), their number, and the start-order ticket
+  double *xv = nullptr;
+  const int32_t *xe = nullptr;
+  const int32_t *elp = nullptr;
+  const int32_t *ilp = nullptr;
+  int64_t nimp = 0;
+  unsigned long long *xticket = nullptr;
 };
 int launch_trsv(const TrsvLaunch &t, hipStream_t s);
 // FP32 / FP16 copies of a factor's values (and FP32 diagonal) for the
@@ -206,7 +215,46 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
                     int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G, int E,
                     int prec, const int32_t *omap, uint16_t *oc, void *ov, int32_t *rec, int *any_slow,
-                    hipStream_t s);
+                    const int32_t *part, const int32_t *xrow, const int32_t *ilp, int64_t nlev, hipStream_t s);
+// ---- block-local solve split over several workgroups per block (trsv_split.hip) ----
+constexpr int SPLIT_LEVELS = 4096;  // levels a split solve takes (its pointers are held in LDS)
+// the split solve (TrsvLaunch with xv, xidx, ilp, nimp, xticket; check-free factors only)
+int launch_trsv_lds_split(const TrsvLaunch &t, hipStream_t s);
+// part of each of n rows: K equal ranges of its block (starts bs[0..nblk]),
+// numbered from the block's end for a backward solve
+int launch_split_parts(const int64_t *bs, int32_t nblk, int64_t n, int32_t K, bool backward, int32_t *part,
+                       hipStream_t s);
+// per row: dependencies (columns < split) on rows of other parts
+int launch_cross_count(const int64_t *rp, const int32_t *ci, int64_t n, int64_t split, const int32_t *part,
+                       int64_t *cnt, hipStream_t s);
+// one record per such dependency: source row, importing part * nlev + level
+int launch_cross_emit(const int64_t *rp, const int32_t *ci, int64_t n, int64_t split, const int32_t *part,
+                      const int32_t *level, int64_t nlev, const int64_t *off, uint32_t *src, int32_t *key,
+                      hipStream_t s);
+// on records sorted by (source, key): head flags; bad[0] a source read by two
+// parts, bad[1] a source not in an earlier part
+int launch_cross_heads(const uint32_t *src, const int32_t *key, int64_t m, const int32_t *part, int64_t nlev,
+                       int64_t *head, int32_t *bad, hipStream_t s);
+int launch_cross_compact(const uint32_t *src, const int32_t *key, int64_t m, const int64_t *head, const int64_t *rank,
+                         uint32_t *isrc, uint32_t *ikey, hipStream_t s);
+// xrow[source row] = import index (xrow preset to -1)
+int launch_cross_slots(const int32_t *isrc, int64_t nimp, int32_t *xrow, hipStream_t s);
+// bad[2]: an import out of its part's LDS ring when read; bad[3]: more than
+// 64 imports needed by one level of one part
+int launch_cross_check(const int64_t *rp, const int32_t *ci, int64_t n, int64_t split, const int32_t *part,
+                       const int32_t *level, int64_t nlev, const int32_t *xrow, const int32_t *ilp, int32_t *bad,
+                       hipStream_t s);
+int launch_cross_width(const int32_t *ilp, int64_t nkeys, int32_t *bad, hipStream_t s);
+// the n words of the exchange array set to "not written"
+int launch_fill_unset(double *xv, int64_t n, hipStream_t s);
+// exports, one per import gi (source row isrc[gi]): key part * nlev + level
+// of the source row, value gi
+int launch_export_keys(const int32_t *isrc, int64_t nimp, const int32_t *part, const int32_t *level, int64_t nlev,
+                       uint32_t *key, int32_t *val, hipStream_t s);
+// xe[e] = {position of the source row, slot} for exports sorted by key
+// (egi: their import indices), and the idle entry xe[nimp] = {0, 0}
+int launch_export_fill(const int32_t *egi, const int32_t *isrc, const int32_t *pos, int64_t nimp, int32_t *xe,
+                       hipStream_t s);
 // block id of each row from ascending block starts (s1 below split, s2 from split on; s2 may be NULL)
 int launch_row_blocks(int64_t nrows, int32_t nblk, const int64_t *s1, const int64_t *s2, int64_t split, int32_t *blk,
                       hipStream_t s);

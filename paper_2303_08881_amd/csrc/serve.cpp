@@ -27,7 +27,8 @@
 // and rely on a workgroup per row stream being resident, which two such
 // launches side by side could not both be sure of.  For the same reason the
 // server's handles orthogonalise their Arnoldi steps with one launch per
-// pass instead of one cooperative launch per step.  Solves then never wait
+// pass instead of one launch per step whose workgroups wait for each
+// other.  Solves then never wait
 // on a workgroup that has not started (their waits follow ticket order), so
 // they overlap with each other and with the one running setup.
 #include <hip/hip_runtime.h>
@@ -340,7 +341,7 @@ int ilu_server_create(int32_t slots, int64_t budget_bytes, const ilu_options_t *
   ilu_default_options(&S->opt);
   if (opt) S->opt = *opt;
   // the slots' solves run side by side: their Arnoldi steps take one launch
-  // per pass, never a cooperative launch that waits for its whole grid
+  // per pass, never a launch per step that waits for its whole grid
   S->opt.arnoldi_mode = ILU_ARNOLDI_PER_PASS;
   S->t0 = Clock::now();
   for (int i = 0; i < slots; i++) S->workers.emplace_back(worker_main, S, i);

@@ -22,3 +22,9 @@ def test_kernel_instance_names():
     assert bench.kernel_instance("mgs", sched) == "void silu::k_arnoldi<"
     assert bench.kernel_instance("spmv_A", sched) == "void silu::k_spmv<0>"
     assert bench.kernel_instance("spmv_Coff", sched) == "void silu::k_spmv<1>"
+    # L_B and U_B split over two workgroups per subdomain (schedule entries 20 and 21)
+    split = sched[:17] + [15, 0, 0, 2, 2]
+    assert bench.kernel_instance("trsv_LB_W", split) == "void silu::k_trsv_lds_x<2, 8, false, 0>"
+    assert bench.kernel_instance("trsv_UB_Z", split, 1) == "void silu::k_trsv_lds_x<2, 8, true, 1>"
+    assert bench.kernel_instance("trsv_UB_Z", sched[:17] + [15, 0, 0, 2, 1]) == \
+        "void silu::k_trsv_lds<2, 8, true, 0, true>"

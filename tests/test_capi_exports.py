@@ -39,4 +39,4 @@ def test_default_options_without_gpu():
     silu.lib().ilu_default_options(ctypes.byref(o))
     assert (o.method, o.interior_fact, o.inner_iters, o.pivot_mode) == (silu.BJ, silu.ILU0, 3, silu.PIVOT_ERROR)
     assert (o.trsv_mode, o.factor_prec) == (silu.TRSV_AUTO, silu.PREC_F64)
-    assert (o.smooth_fact, o.arnoldi_mode) == (silu.ILU0, silu.ARNOLDI_AUTO)
+    assert (o.smooth_fact, o.arnoldi_mode, o.block_split) == (silu.ILU0, silu.ARNOLDI_AUTO, 0)

@@ -1,4 +1,4 @@
-"""The Arnoldi orthogonalisation as one cooperative launch per step, against one launch per pass.
+"""The Arnoldi orthogonalisation as one launch per step, against one launch per pass.
 
 Both routes run the modified Gram-Schmidt of a step in the same order (pass i: h_i = <w, v_i>, then
 w -= h_i v_i; Section 4.1's GMRES and the reduced-system GMRES of Section 3.2) and differ only in how the
