@@ -883,10 +883,10 @@ static int build_split(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   int32_t hb[4] = {0, 0, 0, 0};
   HIPCK(hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
   HIPCK(hipStreamSynchronize(s));
-  if (hb[0] || hb[1] || hb[2] || hb[3] || nimp + 64 * nblk >= ((int64_t)1 << 29)) return 0;
-  // the slots, then a pad of 64 words per part for the idle lanes of its import wave
-  RC(P->mem.alloc(&S.xv, nimp + 64 * nblk));
-  RC(launch_fill_unset(S.xv, nimp + 64 * nblk, s));
+  if (hb[0] || hb[1] || hb[2] || hb[3] || nimp + 128 * nblk >= ((int64_t)1 << 29)) return 0;
+  // the slots, then a pad of 128 words per part for the idle lanes of its loader wave
+  RC(P->mem.alloc(&S.xv, nimp + 128 * nblk));
+  RC(launch_fill_unset(S.xv, nimp + 128 * nblk, s));
   RC(P->mem.alloc(&S.xticket, 1));
   HIPCK(hipMemsetAsync(S.xticket, 0, sizeof(unsigned long long), s));
   S.ilp = ilp;

@@ -51,8 +51,9 @@ namespace silu {
 static_assert(XLEVELS == SPLIT_LEVELS, "split solve level capacity");
 
 struct XchgArgs {
-  double *xv;                  // [nimp + 64 nblk] exchange slots, then 64 words per part, one per lane of
-                               // its exchange wave, that its idle lanes load and store instead
+  double *xv;                  // [nimp + 128 nblk] exchange slots, then 128 words per part, two per lane of
+                               // its loader wave, that its idle lanes load (the first 64, never written
+                               // during a solve) and store (the other 64) instead
   const int2 *xe;              // [nimp + 1] exports by (part, level): {position, slot}; entry nimp is idle
   const int32_t *elp;          // [nblk * nlev + 1] exports by (part, level at which the part solves the row)
   const int32_t *ilp;          // [nblk * nlev + 1] imports by (part, level that first needs them)
@@ -100,12 +101,13 @@ __device__ __forceinline__ double wait_import(const XchgArgs &x, uint32_t ii) {
 // solve; this lane's export entry of step l + 1 (loaded AHEAD steps
 // earlier) into the LDS staging ring of the export wave; then the loads of
 // the imports of level l + 1 + AHEAD and of the export entries of step
-// l + 1 + AHEAD.  Lanes with nothing to move load and store their own word
+// l + 1 + AHEAD.  Lanes with nothing to move load and store their own words
 // of the part's pad instead (never a word shared with other lanes or
-// parts), so a step issues the same three operations every time (a store,
-// then two loads) and the wave's waits are for the loads of AHEAD steps
-// before.  The reset is a plain store: the next solve is another launch,
-// which sees it.
+// parts; words they load are never stored to, so these device-scope loads
+// find clean lines), so a step issues the same three operations every time
+// (a store, then two loads) and the wave's waits are for the loads of AHEAD
+// steps before.  The reset is a plain store: the next solve is another
+// launch, which sees it.
 template <int AHEAD, class A>
 __device__ __forceinline__ void lstep(const XchgArgs &x, A *win, int2 *xent, const int32_t *ip, const int32_t *ep,
                                       int32_t ibase, int32_t l, uint32_t pad, int32_t lane, int2 &ev, double &iv) {
@@ -118,7 +120,7 @@ __device__ __forceinline__ void lstep(const XchgArgs &x, A *win, int2 *xent, con
   if (real && is_unset(v)) v = wait_import(x, (uint32_t)ii);
   if (real) win[XWIN + 1 + ((ii - ibase) & (IWIN - 1))] = (A)v;
   xent[((l + 1) & 1) * WAVE + lane] = ev;
-  at32(x.xv, real ? (uint32_t)ii : pad) = __longlong_as_double((long long)XCHG_UNSET);
+  at32(x.xv, real ? (uint32_t)ii : pad + WAVE) = __longlong_as_double((long long)XCHG_UNSET);
   const uint32_t jj = (uint32_t)(m0 + lane), fe = (uint32_t)(f0 + lane);
   iv = ld_dev(&at32(x.xv, jj < (uint32_t)m1 ? jj : pad));
   ev = at32(x.xe, fe < (uint32_t)f1 ? fe : x.nimp);
@@ -196,7 +198,7 @@ __global__ void __launch_bounds__(BT_MAX) k_trsv_lds_x(LdsTrsvArgs a, XchgArgs x
     for (int32_t l = 0; l < steps; l++) __syncthreads();
   } else if (tid < a.bt + WAVE) {
     const int32_t lane = tid - a.bt, ibase = ip[0];
-    const uint32_t pad = x.nimp + (uint32_t)(WAVE * part + lane);
+    const uint32_t pad = x.nimp + (uint32_t)(2 * WAVE * part + lane);  // loads; pad + WAVE: stores
     int2 ev[AHEAD];    // ev[m % AHEAD]: this lane's export entry of step m
     double iv[AHEAD];  // iv[m % AHEAD]: this lane's import of level m
     // the first loads, in the steps' own order of memory operations (a store
@@ -206,7 +208,7 @@ __global__ void __launch_bounds__(BT_MAX) k_trsv_lds_x(LdsTrsvArgs a, XchgArgs x
 #pragma unroll
     for (int k = 0; k < AHEAD; k++) {
       const int32_t m = k == 0 ? AHEAD : k;
-      at32(x.xv, pad) = 0.0;
+      at32(x.xv, pad + WAVE) = 0.0;
       const uint32_t jj = (uint32_t)(ip[m] + lane), fe = (uint32_t)(ep[m] + lane);
       iv[k] = ld_dev(&at32(x.xv, jj < (uint32_t)ip[m + 1] ? jj : pad));
       ev[k] = at32(x.xe, fe < (uint32_t)ep[m + 1] ? fe : x.nimp);
