@@ -275,7 +275,8 @@ struct Schedule {
   // level), their number and the start-order ticket
   int32_t split_k = 1;
   double *xv = nullptr;
-  int32_t *xe = nullptr, *elp = nullptr, *ilp = nullptr;
+  int32_t *xe = nullptr, *elp = nullptr, *ilp = nullptr, *lrange = nullptr;
+  int64_t xlevels = 0;  // the most levels of any part
   int64_t nimp = 0;
   unsigned long long *xticket = nullptr;
 };
@@ -790,13 +791,18 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
 }
 
 // Workgroups per subdomain of the block-local solve of an interior factor
-// (nloc rows in the block-local solve): block_split, or under 0 (auto) two
-// for subdomains of at least 32768 rows while the parts fit the CUs.
-static int32_t split_parts(const ilu_precond *P, const Schedule &S, int64_t nloc) {
+// (nloc rows in the block-local solve): block_split, or under 0 (auto) one
+// per 262,144 rows of a subdomain, at least two for subdomains of 32,768
+// rows and more, at most 64, while the parts fit the CUs.
+static int32_t split_parts(const ilu_precond *P, int64_t nloc) {
   const int32_t k = P->opt.block_split;
-  if (k == 1 || nloc == 0 || P->nparts < 1 || S.nlev > SPLIT_LEVELS) return 1;
+  if (k == 1 || nloc == 0 || P->nparts < 1) return 1;
   if (k >= 2) return k;
-  return (nloc / P->nparts >= 32768 && 2LL * P->nparts <= P->num_cu) ? 2 : 1;
+  const int64_t rows = nloc / P->nparts;
+  if (rows < 32768) return 1;
+  int64_t n = std::max<int64_t>(2, std::min<int64_t>(64, rows / 262144));
+  while (n > 1 && P->nparts * n > P->num_cu) n--;
+  return (int32_t)n;
 }
 
 // The split of each subdomain's block-local solve over K workgroups
@@ -815,7 +821,7 @@ static int build_split(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   *ok = false;
   const int64_t nblk = (int64_t)P->nparts * K, nlev = S.nlev;
   const uint64_t nkeys = (uint64_t)nblk * (uint64_t)nlev;
-  if (nloc == 0 || nkeys >= (1ull << 31) || nlev > SPLIT_LEVELS) return 0;
+  if (nloc == 0 || nkeys >= (1ull << 31)) return 0;
   int32_t *part, *xrow, *bad;
   int64_t *cnt, *off, m = 0;
   RC(tmp.alloc(&part, nloc));
@@ -823,6 +829,25 @@ static int build_split(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   RC(tmp.alloc(&bad, 4));
   RC(fill_i32(bad, 0, 4, s));
   RC(launch_split_parts(bs, P->nparts, nloc, K, backward, part, s));
+  // each part walks its own levels only: at most SPLIT_LEVELS of them
+  int32_t *lmin, *lmax;
+  RC(tmp.alloc(&lmin, nblk));
+  RC(tmp.alloc(&lmax, nblk));
+  RC(fill_i32(lmin, INT32_MAX, nblk, s));
+  RC(fill_i32(lmax, -1, nblk, s));
+  RC(launch_part_levels(part, S.level_of, nloc, lmin, lmax, s));
+  std::vector<int32_t> hmin(nblk), hmax(nblk), hr(2 * nblk);
+  HIPCK(hipMemcpyAsync(hmin.data(), lmin, sizeof(int32_t) * nblk, hipMemcpyDeviceToHost, s));
+  HIPCK(hipMemcpyAsync(hmax.data(), lmax, sizeof(int32_t) * nblk, hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  int64_t most = 0;
+  for (int64_t p = 0; p < nblk; p++) {
+    const bool empty = hmax[p] < 0;
+    hr[2 * p] = empty ? 0 : hmin[p];
+    hr[2 * p + 1] = empty ? 0 : hmax[p] - hmin[p] + 1;
+    most = std::max<int64_t>(most, hr[2 * p + 1]);
+  }
+  if (most > SPLIT_LEVELS) return 0;
   RC(launch_cross_count(T.rp, T.ci, nloc, ext_col, part, cnt, s));
   size_t stb = scan_tmp_bytes(std::max<int64_t>(nloc, (int64_t)nkeys)) + 64;
   void *stmp;
@@ -889,6 +914,10 @@ static int build_split(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   RC(launch_fill_unset(S.xv, nimp + 128 * nblk, s));
   RC(P->mem.alloc(&S.xticket, 1));
   HIPCK(hipMemsetAsync(S.xticket, 0, sizeof(unsigned long long), s));
+  RC(P->mem.alloc(&S.lrange, 2 * nblk));
+  HIPCK(hipMemcpyAsync(S.lrange, hr.data(), sizeof(int32_t) * 2 * nblk, hipMemcpyHostToDevice, s));
+  HIPCK(hipStreamSynchronize(s));  // hr is host memory on this stack
+  S.xlevels = most;
   S.ilp = ilp;
   S.nimp = nimp;
   S.split_k = K;
@@ -951,7 +980,7 @@ static int build_block_interior(ilu_precond *P, Mem &tmp, const Csr &T, Schedule
                                 const int64_t *bs2, int64_t split, const double *diag, int64_t ext_col,
                                 bool backward, hipStream_t s, const char *phase) {
   const int64_t nloc = bs2 ? split : T.n;
-  const int32_t K = split_parts(P, S, nloc);
+  const int32_t K = split_parts(P, nloc);
   if (K > 1) {
     int32_t *part = nullptr, *xrow = nullptr, *isrc = nullptr;
     bool ok = false;
@@ -967,7 +996,8 @@ static int build_block_interior(ilu_precond *P, Mem &tmp, const Csr &T, Schedule
     // build the unsplit solve
     S.split_k = 1;
     S.xv = nullptr;
-    S.xe = S.elp = S.ilp = nullptr;
+    S.xe = S.elp = S.ilp = S.lrange = nullptr;
+    S.xlevels = 0;
     S.nimp = 0;
     S.xticket = nullptr;
     S.nblk = P->nparts;
@@ -1107,6 +1137,8 @@ static TrsvLaunch make_launch(ilu_precond *P, Schedule &S, const Csr &T, const d
       t.xv = S.xv;
       t.xe = S.xe;
       t.elp = S.elp;
+      t.lrange = S.lrange;
+      t.xlevels = S.xlevels;
       t.ilp = S.ilp;
       t.nimp = S.nimp;
       t.xticket = S.xticket;

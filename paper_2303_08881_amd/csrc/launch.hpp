@@ -172,6 +172,8 @@ struct TrsvLaunch {
   const int32_t *xe = nullptr;
   const int32_t *elp = nullptr;
   const int32_t *ilp = nullptr;
+  const int32_t *lrange = nullptr;  // int2 per part: first level, number of levels
+  int64_t xlevels = 0;              // the most levels of any part
   int64_t nimp = 0;
   unsigned long long *xticket = nullptr;
 };
@@ -217,7 +219,7 @@ int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, c
                     int prec, const int32_t *omap, uint16_t *oc, void *ov, int32_t *rec, int *any_slow,
                     const int32_t *part, const int32_t *xrow, const int32_t *ilp, int64_t nlev, hipStream_t s);
 // ---- block-local solve split over several workgroups per block (trsv_split.hip) ----
-constexpr int SPLIT_LEVELS = 4096;  // levels a split solve takes (its pointers are held in LDS)
+constexpr int SPLIT_LEVELS = 4096;  // levels of one part of a split solve (its pointers are held in LDS)
 // the split solve (TrsvLaunch with xv, xidx, ilp, nimp, xticket; check-free factors only)
 int launch_trsv_lds_split(const TrsvLaunch &t, hipStream_t s);
 // part of each of n rows: K equal ranges of its block (starts bs[0..nblk]),
@@ -245,6 +247,9 @@ int launch_cross_check(const int64_t *rp, const int32_t *ci, int64_t n, int64_t 
                        const int32_t *level, int64_t nlev, const int32_t *xrow, const int32_t *ilp, int32_t *bad,
                        hipStream_t s);
 int launch_cross_width(const int32_t *ilp, int64_t nkeys, int32_t *bad, hipStream_t s);
+// lowest and highest level of each part's rows (lmin preset to INT32_MAX, lmax to -1)
+int launch_part_levels(const int32_t *part, const int32_t *level, int64_t n, int32_t *lmin, int32_t *lmax,
+                       hipStream_t s);
 // the n words of the exchange array set to "not written"
 int launch_fill_unset(double *xv, int64_t n, hipStream_t s);
 // exports, one per import gi (source row isrc[gi]): key part * nlev + level

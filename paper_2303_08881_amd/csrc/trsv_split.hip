@@ -57,6 +57,7 @@ struct XchgArgs {
   const int2 *xe;              // [nimp + 1] exports by (part, level): {position, slot}; entry nimp is idle
   const int32_t *elp;          // [nblk * nlev + 1] exports by (part, level at which the part solves the row)
   const int32_t *ilp;          // [nblk * nlev + 1] imports by (part, level that first needs them)
+  const int2 *lrange;          // [nblk] first level of each part and its number of levels (<= XLEVELS)
   uint32_t nimp;
   uint32_t nblk;
   unsigned long long *ticket;  // start order of the parts (grows by nblk per solve)
@@ -163,8 +164,12 @@ __global__ void __launch_bounds__(BT_MAX) k_trsv_lds_x(LdsTrsvArgs a, XchgArgs x
   const int32_t tid = (int32_t)threadIdx.x, nth = a.bt + 2 * WAVE;
   if (tid == 0) part = (int32_t)(atomicAdd(x.ticket, 1ull) % (unsigned long long)x.nblk);
   __syncthreads();
-  const int64_t base = (int64_t)part * a.nlev;
-  const int32_t nlev = a.nlev;
+  // this part's own levels only: its rows lie in levels lo .. lo + nlev - 1
+  // (the others are empty for it; what it needs from other parts comes
+  // through the exchange, not through their levels)
+  const int2 lr = x.lrange[part];
+  const int64_t base = (int64_t)part * a.nlev + lr.x;
+  const int32_t nlev = lr.y;
   for (int32_t l = tid; l <= nlev; l += nth) {
     lp[l] = a.lev_ptr[base + l];
     ip[l] = x.ilp[base + l];
@@ -174,6 +179,16 @@ __global__ void __launch_bounds__(BT_MAX) k_trsv_lds_x(LdsTrsvArgs a, XchgArgs x
   for (int32_t k = tid; k <= XWIN + IWIN; k += nth) win[k] = A(0);
   if (tid < 2 * WAVE) xent[tid] = make_int2(0, 0);
   __syncthreads();
+  if (tid >= a.bt && tid < a.bt + WAVE) {
+    // the imports of the part's first level, before its first step
+    const int32_t ii = ip[0] + (tid - a.bt);
+    if (ii < ip[1]) {
+      double v = ld_dev(&at32(x.xv, (uint32_t)ii));
+      if (is_unset(v)) v = wait_import(x, (uint32_t)ii);
+      win[XWIN + 1 + ((ii - ip[0]) & (IWIN - 1))] = (A)v;
+      at32(x.xv, (uint32_t)ii) = __longlong_as_double((long long)XCHG_UNSET);
+    }
+  }
   if (tid < XPAD - 2) {
     lp[nlev + 1 + tid] = lp[nlev];
     ip[nlev + 1 + tid] = ip[nlev];
@@ -264,8 +279,9 @@ int launch_trsv_lds_split(const TrsvLaunch &t, hipStream_t s) {
   if (t.nblk == 0 || t.nrows == 0) return 0;
   const bool ge_ok = ((t.lds_e == 2 || t.lds_e == 4) && t.lds_g == 1) ||
                      (t.lds_e == 8 && (t.lds_g == 1 || t.lds_g == 2 || t.lds_g == 4 || t.lds_g == 8));
-  if (!t.lds_fast || !ge_ok || t.nlev_blk > XLEVELS || t.lds_bt < 64 || t.lds_bt > BT_MAX - 2 * WAVE || t.lds_bt % 64 != 0 ||
-      !t.b || !t.x || !t.out_map || !t.xv || !t.xe || !t.elp || !t.ilp || !t.xticket || t.nblk > (int64_t)UINT32_MAX)
+  if (!t.lds_fast || !ge_ok || t.xlevels > XLEVELS || t.lds_bt < 64 || t.lds_bt > BT_MAX - 2 * WAVE ||
+      t.lds_bt % 64 != 0 || !t.b || !t.x || !t.out_map || !t.xv || !t.xe || !t.elp || !t.ilp || !t.lrange ||
+      !t.xticket || t.nblk > (int64_t)UINT32_MAX)
     return ILU_ERR_INVALID_ARG;
   LdsTrsvArgs a{};
   a.ent_c = t.lds_c;
@@ -283,8 +299,15 @@ int launch_trsv_lds_split(const TrsvLaunch &t, hipStream_t s) {
   a.b = t.b;
   a.out = t.x;
   a.omap = t.out_map;
-  XchgArgs x{t.xv,           reinterpret_cast<const int2 *>(t.xe), t.elp, t.ilp, (uint32_t)t.nimp, (uint32_t)t.nblk,
-             t.xticket, static_cast<Status *>(t.status)};
+  XchgArgs x{t.xv,
+             reinterpret_cast<const int2 *>(t.xe),
+             t.elp,
+             t.ilp,
+             reinterpret_cast<const int2 *>(t.lrange),
+             (uint32_t)t.nimp,
+             (uint32_t)t.nblk,
+             t.xticket,
+             static_cast<Status *>(t.status)};
   const unsigned g = (unsigned)t.nblk, bt = (unsigned)t.lds_bt + 2 * WAVE;  // compute, loader and export waves
   if (t.diag)
     launch_x<true>(t.lds_g, t.lds_e, t.prec, g, bt, a, x, s);
@@ -449,6 +472,34 @@ int launch_cross_check(const int64_t *rp, const int32_t *ci, int64_t n, int64_t 
   k_cross_check<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, n, split, part, level, nlev, xrow, ilp, bad);
   return check_launch("cross_check");
 }
+// lowest and highest level of each part's rows (lmin preset to INT_MAX, lmax
+// to -1).  Consecutive rows mostly share a part: a wave whose rows all do
+// reduces first and updates the part once (a few parts take every row, and
+// one atomic per row on so few words serialises).
+__global__ void k_part_levels(const int32_t *part, const int32_t *level, int64_t n, int32_t *lmin, int32_t *lmax) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool in = r < n;
+  const int32_t p = in ? part[r] : -1, lv = in ? level[r] : 0;
+  const int32_t p0 = __shfl(p, 0, WAVE);
+  if (__all(p == p0) && p0 >= 0) {
+    const int32_t mx = wave_max_int(lv), mn = -wave_max_int(-lv);
+    if (lane_id() == 0) {
+      atomicMin(&lmin[p0], mn);
+      atomicMax(&lmax[p0], mx);
+    }
+  } else if (in) {
+    atomicMin(&lmin[p], lv);
+    atomicMax(&lmax[p], lv);
+  }
+}
+
+int launch_part_levels(const int32_t *part, const int32_t *level, int64_t n, int32_t *lmin, int32_t *lmax,
+                       hipStream_t s) {
+  if (n == 0) return 0;
+  k_part_levels<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(part, level, n, lmin, lmax);
+  return check_launch("part_levels");
+}
+
 __global__ void k_export_keys(const int32_t *isrc, int64_t nimp, const int32_t *part, const int32_t *level,
                               int64_t nlev, uint32_t *key, int32_t *val) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;

@@ -1,9 +1,10 @@
 """The mixed-precision workload at its full size: 2D rotated anisotropic 9-point diffusion on a 2048 x 2048 grid
 (n = 4,194,304, nnz = 37,724,164, eps 1e-3, theta pi/6), one block, ILU(0), FGMRES(30) to rtol 1e-10.
 
-The one block of 4.19M rows has 6,142 levels per factor, 683 rows each on average, so the default solve runs
-it on one workgroup of 1024 threads (the level-scheduled solve over the whole GPU, with a cross-CU wait per
-level, is checked too).  Bars: level of every row bit-exact, factors within 1e-12, the FP64 apply within
+The one block of 4.19M rows has 6,142 levels per factor, 683 rows each on average.  The default solve splits
+it into 16 bands of 128 grid lines, one workgroup each, each band walking its own 2,300 levels and taking the
+last line of the band before it through device memory (one workgroup of 1024 threads for the whole block, and
+the level-scheduled solve over the whole GPU with a cross-CU wait per level, are checked too).  Bars: level of every row bit-exact, factors within 1e-12, the FP64 apply within
 1e-12 of the oracle's in both solve modes; with FP32 / FP16 factor storage the apply error
 against the FP64 oracle is printed and bounded, and FGMRES (FP64 Krylov, SpMV and convergence test) still
 reaches the true relative residual 1e-10.  The oracle's full FGMRES at this size takes minutes, so iteration
@@ -54,8 +55,21 @@ def test_rot9_setup_matches(rot9):
         np.testing.assert_allclose(vg, vo, rtol=1e-12, atol=1e-12 * np.abs(vo).max(), err_msg=name)
     np.testing.assert_allclose(P_g.export("DB"), P_o.export("DB"), rtol=1e-12)
     sched = P_g.export("schedule")
-    # block-local, one workgroup of 1024 threads covering the widest level (1024 rows)
-    assert sched[0] == 1 and sched[4] == 1 and sched[3] == 1024 and sched[7] == 1024, sched
+    # block-local, the block split into 16 bands of 128 grid lines (levels of at most 128 rows per band)
+    assert sched[0] == 1 and sched[4] == 1 and (sched[20], sched[21]) == (16, 16), sched
+    assert sched[3] <= 384 and sched[7] <= 384, sched
+
+
+def test_rot9_one_workgroup_identical(rot9):
+    # the whole block on one workgroup of 1024 threads (the widest level has 1024 rows): the same arithmetic
+    # for every row, so the same apply to the bit
+    m, A, b, P_o, Ad, P_g = rot9
+    P_1 = m.setup(Ad, None, 1, block_split=1, **OPTS)
+    sched = P_1.export("schedule")
+    assert sched[3] == 1024 and sched[7] == 1024 and (sched[20], sched[21]) == (1, 1), sched
+    r = torch.as_tensor(synth.uniform_rhs(A.n, 17)).cuda()
+    np.testing.assert_array_equal(P_1.apply(r).cpu().numpy(), P_g.apply(r).cpu().numpy())
+    P_1.close()
 
 
 def test_rot9_apply_fp64(rot9):
