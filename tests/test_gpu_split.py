@@ -177,6 +177,44 @@ def test_split_auto():
     assert (s0[20], s0[21]) == (1, 1), s0
 
 
+def _block_diag(B, copies):
+    n = B.n
+    rp = np.concatenate([[0]] + [B.row_ptr[1:] + c * B.nnz for c in range(copies)]).astype(np.int64)
+    col = np.concatenate([B.col + c * n for c in range(copies)]).astype(np.int32)
+    return synth.CSR(n * copies, rp, col, np.tile(B.val, copies))
+
+
+@pytest.mark.parametrize("kind", ["more_parts_than_cus", "empty_parts"])
+def test_split_extremes(kind):
+    # more_parts_than_cus: 32 independent 128 x 16 grids, 16 parts each (one grid line per part): 512
+    # workgroups, more than the device holds at once, so parts wait on parts that started before them while
+    # others have not started yet.  empty_parts: a 10-row tridiagonal block in 16 parts, most of them empty.
+    m = silu()
+    if kind == "more_parts_than_cus":
+        B = synth.aniso5(128, Ny=16)
+        A = _block_diag(B, 32)
+        part, p, k = (np.arange(A.n) // B.n).astype(np.int32), 32, 16
+    else:
+        A, part, p, k = synth.aniso5(10, Ny=1), None, 1, 16
+    opts = dict(method=oracle.BJ, interior_fact=oracle.ILU0)
+    Po = oracle.Precond(A, part, p, **opts)
+    off = Po.export("offsets")
+    want = [k if split_applies(*Po.csr(f)[:2], Po.export(lv), off, p, k, bw) else 1
+            for f, lv, bw in (("LB", "lev_LB", False), ("UB", "lev_UB", True))]
+    assert want == [k, k]
+    print(f"[split] {kind}", flush=True)
+    P1 = _setup(m, A, part, p, opts, 1)
+    Pk = _setup(m, A, part, p, opts, k)
+    sk = Pk.export("schedule")
+    assert [sk[20], sk[21]] == want, sk
+    r = torch.as_tensor(synth.uniform_rhs(A.n, 19)).cuda()
+    z1 = P1.apply(r).cpu().numpy()
+    for rep in range(3):
+        np.testing.assert_array_equal(Pk.apply(r).cpu().numpy(), z1, err_msg=f"apply {rep}")
+    zo = Po.apply(r.cpu().numpy())
+    np.testing.assert_allclose(z1, zo, rtol=1e-12, atol=1e-12 * np.abs(zo).max())
+
+
 def test_split_option_range():
     m = silu()
     A = synth.aniso5(8)
