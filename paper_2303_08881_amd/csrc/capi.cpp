@@ -513,6 +513,70 @@ static int row_geometry(Mem &tmp, const Csr &M, int64_t nrows, bool upper, hipSt
 
 // Factor M (rows < nfull full, the rest partial) with the schedule of the
 // given segments.  Scratch goes to `tmp`.
+// ILU(0) / MILU(0) of a matrix of full rows by levels of its lower pattern,
+// one launch per level (launch_factor_level: the same factors as the
+// dependency-flag kernel, without a memory round trip per row on the chain).
+// The levels come from the level analysis's sweep over the factorization's
+// own row schedule.  *done = false (nothing factored) when the pattern has
+// too many levels for one launch each to pay: more than 65,536, or fewer
+// than 16 rows per level on average.
+static int factor_by_levels(ilu_precond *P, Mem &tmp, const Csr &M, const FactLaunch &f,
+                            const std::vector<int64_t> &a_start, const std::vector<int64_t> &a_len,
+                            const std::vector<int64_t> &b_start, const std::vector<int64_t> &b_len, hipStream_t s,
+                            bool *done) {
+  *done = false;
+  const int64_t n = M.n;
+  if (n == 0) return 0;
+  int64_t line = 16, plane = 16, nch = 0, ns = 0, ninit = 0, *sc = nullptr;
+  int32_t *chunks = nullptr, *level;
+  const int64_t grid = std::min<int64_t>(levels_resident_groups(P->num_cu), (int64_t)P->num_cu * 32 / LEVEL_WAVES);
+  if (grid < 1) return 0;
+  RC(tmp.alloc(&level, n));
+  RC(row_geometry(tmp, M, n, false, s, &line, &plane));
+  RC(build_streams(tmp, a_start, a_len, b_start, b_len, line, plane, FACT_PART_B_CHUNK, false, grid, &nch, &chunks,
+                   &ns, &ninit, &sc, s));
+  int *flag;
+  unsigned int *ticket;
+  RC(tmp.alloc(&flag, n));
+  RC(tmp.alloc(&ticket, std::max<int64_t>(ns, 1)));
+  HIPCK(hipMemsetAsync(flag, 0, sizeof(int) * n, s));
+  HIPCK(hipMemsetAsync(ticket, 0, sizeof(unsigned int) * std::max<int64_t>(ns, 1), s));
+  RC(launch_levels_stream(M.rp, M.ci, true, 0, n, chunks, ns, ninit, sc, ticket, level, flag, P->status, grid, s));
+  RC(check_status(P, s, "factorization levels", nullptr, 0));
+  int32_t *dmax, hmax = 0;
+  RC(tmp.alloc(&dmax, 1));
+  RC(max_i32(level, n, dmax, s));
+  HIPCK(hipMemcpyAsync(&hmax, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  const int64_t nlev = (int64_t)hmax + 1;
+  if (nlev > 65536 || n < 16 * nlev) return 0;
+  // rows sorted by level
+  uint32_t *key, *key2;
+  int32_t *val, *rows;
+  RC(tmp.alloc(&key, n));
+  RC(tmp.alloc(&key2, n));
+  RC(tmp.alloc(&val, n));
+  RC(tmp.alloc(&rows, n));
+  RC(launch_levels_to_keys(level, n, key, val, s));
+  const size_t rtb = radix_tmp_bytes(n);
+  void *rtmp;
+  RC(tmp.alloc((char **)&rtmp, (int64_t)rtb));
+  RC(radix_sort(key, val, key2, rows, n, bits_for((uint64_t)hmax), rtmp, rtb, s));
+  int64_t *cnt, *lp, tot = 0;
+  RC(tmp.alloc(&cnt, nlev));
+  RC(histogram_keys(key2, n, nlev, cnt, s));
+  const size_t stb = scan_tmp_bytes(nlev) + 64;
+  void *stmp;
+  RC(tmp.alloc((char **)&stmp, (int64_t)stb));
+  RC(make_rp(tmp, cnt, nlev, &lp, &tot, stmp, stb, s));
+  std::vector<int64_t> hlp(nlev + 1);
+  HIPCK(hipMemcpyAsync(hlp.data(), lp, sizeof(int64_t) * (nlev + 1), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  for (int64_t l = 0; l < nlev; l++) RC(launch_factor_level(f, rows + hlp[l], hlp[l + 1] - hlp[l], s));
+  *done = true;
+  return 0;
+}
+
 static int run_factor(ilu_precond *P, Mem &tmp, const Csr &M, int64_t nfull, int32_t method,
                       const std::vector<int64_t> &a_start, const std::vector<int64_t> &a_len,
                       const std::vector<int64_t> &b_start, const std::vector<int64_t> &b_len, Slots &S,
@@ -541,6 +605,32 @@ static int run_factor(ilu_precond *P, Mem &tmp, const Csr &M, int64_t nfull, int
   RC(tmp.alloc(&S.Rlen, n - nfull));
   RC(tmp.alloc(&S.D, nfull));
   RC(fill_i32(S.Ulen, 0, nfull, s));
+  if (method != ILU_FACT_ILUT && nfull == n && n > 0) {
+    FactLaunch f{};
+    f.rp = M.rp;
+    f.ci = M.ci;
+    f.v = M.v;
+    f.n = n;
+    f.nfull = nfull;
+    f.method = method;
+    f.droptol = P->opt.droptol;
+    f.lfil = P->opt.lfil;
+    f.pivot_mode = P->opt.pivot_mode;
+    f.pivot_tol = P->opt.pivot_tol;
+    f.Lrp = S.Lrp;
+    f.Lc = S.Lc;
+    f.Lv = S.Lv;
+    f.Llen = S.Llen;
+    f.Urp = S.Urp;
+    f.Uc = S.Uc;
+    f.Uv = S.Uv;
+    f.Ulen = S.Ulen;
+    f.D = S.D;
+    f.status = P->status;
+    bool done = false;
+    RC(factor_by_levels(P, tmp, M, f, a_start, a_len, b_start, b_len, s, &done));
+    if (done) return check_status(P, s, phase, row_map, row_off);
+  }
   int64_t nchunks = 0, nstreams = 0, ninit = 0, *stream_chunk = nullptr, line = 16, plane = 16;
   int32_t *chunks = nullptr;
   const int64_t grid = std::min<int64_t>(factor_resident_groups(P->num_cu), (int64_t)P->num_cu * 16 / FACT_WAVES);

@@ -596,6 +596,105 @@ int launch_fact_caps(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nf
   return check_launch("fact_caps");
 }
 
+// ILU(0) / MILU(0) of full rows, one level of the lower pattern per launch:
+// every pivot row of a level lies in an earlier level, so it is complete
+// when the launch starts, and no row waits.  One thread per row, working
+// directly in the row's output slots (L entries in column order, then U).
+// The operations are factor_row's, in its order: pivots in column order,
+// w_k / d_k, one fma per updated entry, the dropped products of MILU(0)
+// summed in (pivot, column) order, the same pivot test.  So the factors are
+// identical to the dependency-flag kernel's, without its per-row round trips.
+__global__ void k_factor_level(FactLaunch f, const int32_t *rows, int64_t cnt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int64_t r = rows[i];
+  const bool milu = f.method == ILU_FACT_MILU0;
+  const int64_t rb = f.rp[r], re = f.rp[r + 1], lb = f.Lrp[r], ub = f.Urp[r];
+  int nl = 0, nu = 0;
+  double d = 0.0, rowinf = 0.0;
+  for (int64_t e = rb; e < re; e++) {
+    const int32_t c = f.ci[e];
+    const double x = f.v[e];
+    rowinf = fmax(rowinf, fabs(x));
+    if (c < r) {
+      f.Lc[lb + nl] = c;
+      f.Lv[lb + nl] = x;
+      nl++;
+    } else if (c == r) {
+      d = x;
+    } else {
+      f.Uc[ub + nu] = c;
+      f.Uv[ub + nu] = x;
+      nu++;
+    }
+  }
+  double drop = 0.0;
+  for (int p = 0; p < nl; p++) {
+    const int32_t k = f.Lc[lb + p];
+    const double wk = f.Lv[lb + p] / f.D[k];
+    f.Lv[lb + p] = wk;
+    // row k's U entries (ascending) against this row's entries after column k
+    // (ascending): the L entries after p, the diagonal, the U entries
+    const int64_t kb = f.Urp[k];
+    const int kl = f.Ulen[k];
+    int q = p + 1;  // next candidate: L entry q (< nl), then the diagonal (q == nl), then U entry q - nl - 1
+    for (int t = 0; t < kl; t++) {
+      const int32_t uc = f.Uc[kb + t];
+      const double u = f.Uv[kb + t];
+      for (;;) {  // advance to the first entry at or past uc
+        const int32_t cq = q < nl ? f.Lc[lb + q] : q == nl ? (int32_t)r : q - nl - 1 < nu ? f.Uc[ub + q - nl - 1]
+                                                                                           : INT32_MAX;
+        if (cq >= uc) break;
+        q++;
+      }
+      const int32_t cq = q < nl ? f.Lc[lb + q] : q == nl ? (int32_t)r : q - nl - 1 < nu ? f.Uc[ub + q - nl - 1]
+                                                                                         : INT32_MAX;
+      if (cq == uc) {
+        if (q < nl)
+          f.Lv[lb + q] = fma(-wk, u, f.Lv[lb + q]);
+        else if (q == nl)
+          d = fma(-wk, u, d);
+        else
+          f.Uv[ub + q - nl - 1] = fma(-wk, u, f.Uv[ub + q - nl - 1]);
+      } else if (milu) {
+        drop = fma(-wk, u, drop);
+      }
+    }
+  }
+  if (milu) d = d + drop;
+  if (f.pivot_mode == ILU_PIVOT_PERTURB) {
+    const double thr = f.pivot_tol * rowinf;
+    if (fabs(d) < thr) d = (d < 0.0) ? -thr : thr;
+  }
+  if (d == 0.0 || !isfinite(d)) {
+    raise_error(static_cast<Status *>(f.status), ILU_ERR_ZERO_PIVOT, r);
+    return;
+  }
+  f.D[r] = d;
+  f.Llen[r] = nl;
+  f.Ulen[r] = nu;
+}
+
+int launch_factor_level(const FactLaunch &f, const int32_t *rows, int64_t cnt, hipStream_t s) {
+  if (cnt == 0) return 0;
+  k_factor_level<<<(unsigned)((cnt + 127) / 128), 128, 0, s>>>(f, rows, cnt);
+  return check_launch("factor_level");
+}
+
+// longest row of rows [0, n)
+__global__ void k_row_len_max(const int64_t *rp, int64_t n, int *out) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int len = r < n ? (int)(rp[r + 1] - rp[r]) : 0;
+  len = wave_max_int(len);
+  if (lane_id() == 0) atomicMax(out, len);
+}
+
+int launch_row_len_max(const int64_t *rp, int64_t n, int *out, hipStream_t s) {
+  if (n == 0) return 0;
+  k_row_len_max<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, n, out);
+  return check_launch("row_len_max");
+}
+
 int launch_factor_rows(const FactLaunch &f, hipStream_t s) {
   FactArgs a;
   a.rp = f.rp;

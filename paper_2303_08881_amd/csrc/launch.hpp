@@ -91,6 +91,12 @@ int launch_gap_hist(const int64_t *rp, const int32_t *ci, int64_t n, bool upper,
 int launch_fact_caps(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nfull, int32_t method, int32_t lfil,
                      int64_t *Lcap, int64_t *Ucap, int64_t *Rcap, hipStream_t s);
 int launch_factor_rows(const FactLaunch &f, hipStream_t s);
+// ILU(0) / MILU(0) of the full rows rows[0 .. cnt) of one level of the lower
+// pattern (every earlier level already factored): the same factors as
+// launch_factor_rows
+int launch_factor_level(const FactLaunch &f, const int32_t *rows, int64_t cnt, hipStream_t s);
+// *out = max(*out, longest of rows [0, n))
+int launch_row_len_max(const int64_t *rp, int64_t n, int *out, hipStream_t s);
 int launch_compact_rows(int64_t nrows, const int64_t *cap_rp, const int32_t *len, const int32_t *sc,
                         const double *sv, const int64_t *out_rp, int32_t *oc, double *ov, int64_t col_lo,
                         int64_t col_hi, int64_t shift, hipStream_t s);

@@ -55,7 +55,8 @@ def test_setup_rejects_bad_csr(defect):
 
 
 def test_working_row_capacity_is_reported():
-    # one row of 700 entries (an arrow matrix) outgrows the factorization's on-chip working row
+    # one row of 700 entries (an arrow matrix) outgrows the on-chip working row of the threshold
+    # factorization; ILU(0), factored level by level in the rows' own output slots, has no such limit
     n = 700
     d = np.eye(n) * 4.0
     d[n - 1, :] = -1.0 / n
@@ -65,8 +66,12 @@ def test_working_row_capacity_is_reported():
     m = silu()
     print("[errors] capacity", flush=True)
     with pytest.raises(m.SchurILUError) as e:
-        m.setup(m.DeviceCSR.from_host(A))
+        m.setup(m.DeviceCSR.from_host(A), interior_fact=m.ILUT, droptol=0.0, lfil=-1)
     assert e.value.code == ERR_CAPACITY
+    P = m.setup(m.DeviceCSR.from_host(A))
+    r = synth.uniform_rhs(n, 5)
+    zo = oracle.Precond(A, None, 1).apply(r)
+    np.testing.assert_allclose(P.apply(torch.as_tensor(r).cuda()).cpu().numpy(), zo, rtol=1e-12, atol=1e-14)
 
 
 @pytest.mark.parametrize("bad", [np.nan, np.inf])
