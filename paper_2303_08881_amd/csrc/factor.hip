@@ -598,16 +598,21 @@ int launch_fact_caps(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nf
 
 // ILU(0) / MILU(0) of full rows, one level of the lower pattern per launch:
 // every pivot row of a level lies in an earlier level, so it is complete
-// when the launch starts, and no row waits.  One thread per row, working
-// directly in the row's output slots (L entries in column order, then U).
-// The operations are factor_row's, in its order: pivots in column order,
+// when the launch starts, and no row waits.  One thread per row.  The
+// operations are factor_row's, in its order: pivots in column order,
 // w_k / d_k, one fma per updated entry, the dropped products of MILU(0)
 // summed in (pivot, column) order, the same pivot test.  So the factors are
-// identical to the dependency-flag kernel's, without its per-row round trips.
-__global__ void k_factor_level(FactLaunch f, const int32_t *rows, int64_t cnt) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
-  const int64_t r = rows[i];
+// identical to the dependency-flag kernel's, without its per-row round
+// trips.  A row of at most FL_ROW entries is held in registers, the
+// diagonals and U-row extents of all its pivots are fetched in one round,
+// and each pivot's U row (at most FL_U entries) in one more; longer rows
+// work in their output slots in memory instead.
+constexpr int FL_ROW = 12;
+constexpr int FL_U = 12;
+
+// the general row: working in the output slots (L entries in column order,
+// then U), any length
+__device__ void factor_level_row_mem(const FactLaunch &f, int64_t r) {
   const bool milu = f.method == ILU_FACT_MILU0;
   const int64_t rb = f.rp[r], re = f.rp[r + 1], lb = f.Lrp[r], ub = f.Urp[r];
   int nl = 0, nu = 0;
@@ -633,22 +638,20 @@ __global__ void k_factor_level(FactLaunch f, const int32_t *rows, int64_t cnt) {
     const int32_t k = f.Lc[lb + p];
     const double wk = f.Lv[lb + p] / f.D[k];
     f.Lv[lb + p] = wk;
-    // row k's U entries (ascending) against this row's entries after column k
-    // (ascending): the L entries after p, the diagonal, the U entries
+    // row k's U entries (ascending) against this row's entries after column
+    // k (ascending): the L entries after p, the diagonal, the U entries
     const int64_t kb = f.Urp[k];
     const int kl = f.Ulen[k];
-    int q = p + 1;  // next candidate: L entry q (< nl), then the diagonal (q == nl), then U entry q - nl - 1
+    int q = p + 1;  // L entry q (< nl), the diagonal (q == nl), U entry q - nl - 1
     for (int t = 0; t < kl; t++) {
       const int32_t uc = f.Uc[kb + t];
       const double u = f.Uv[kb + t];
-      for (;;) {  // advance to the first entry at or past uc
-        const int32_t cq = q < nl ? f.Lc[lb + q] : q == nl ? (int32_t)r : q - nl - 1 < nu ? f.Uc[ub + q - nl - 1]
-                                                                                           : INT32_MAX;
+      int32_t cq;
+      for (;;) {
+        cq = q < nl ? f.Lc[lb + q] : q == nl ? (int32_t)r : q - nl - 1 < nu ? f.Uc[ub + q - nl - 1] : INT32_MAX;
         if (cq >= uc) break;
         q++;
       }
-      const int32_t cq = q < nl ? f.Lc[lb + q] : q == nl ? (int32_t)r : q - nl - 1 < nu ? f.Uc[ub + q - nl - 1]
-                                                                                         : INT32_MAX;
       if (cq == uc) {
         if (q < nl)
           f.Lv[lb + q] = fma(-wk, u, f.Lv[lb + q]);
@@ -669,6 +672,113 @@ __global__ void k_factor_level(FactLaunch f, const int32_t *rows, int64_t cnt) {
   if (d == 0.0 || !isfinite(d)) {
     raise_error(static_cast<Status *>(f.status), ILU_ERR_ZERO_PIVOT, r);
     return;
+  }
+  f.D[r] = d;
+  f.Llen[r] = nl;
+  f.Ulen[r] = nu;
+}
+
+__global__ void __launch_bounds__(128) k_factor_level(FactLaunch f, const int32_t *rows, int64_t cnt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int64_t r = rows[i];
+  const int64_t rb = f.rp[r];
+  const int len = (int)(f.rp[r + 1] - rb);
+  if (len > FL_ROW) {
+    factor_level_row_mem(f, r);
+    return;
+  }
+  const bool milu = f.method == ILU_FACT_MILU0;
+  // the row, in column order, in registers
+  int32_t c[FL_ROW];
+  double w[FL_ROW];
+#pragma unroll
+  for (int e = 0; e < FL_ROW; e++) {
+    c[e] = e < len ? f.ci[rb + e] : INT32_MAX;
+    w[e] = e < len ? f.v[rb + e] : 0.0;
+  }
+  double rowinf = 0.0;
+  int nl = 0;
+#pragma unroll
+  for (int e = 0; e < FL_ROW; e++) {
+    rowinf = fmax(rowinf, fabs(w[e]));
+    nl += c[e] < r;
+  }
+  // every pivot's diagonal and U-row extent in one round
+  double dk[FL_ROW];
+  int64_t kb[FL_ROW];
+  int kl[FL_ROW];
+#pragma unroll
+  for (int e = 0; e < FL_ROW; e++) {
+    const bool piv = e < nl;
+    const int32_t k = piv ? c[e] : 0;
+    dk[e] = piv ? f.D[k] : 1.0;
+    kb[e] = piv ? f.Urp[k] : 0;
+    kl[e] = piv ? f.Ulen[k] : 0;
+  }
+  bool fits = true;
+#pragma unroll
+  for (int e = 0; e < FL_ROW; e++) fits = fits && kl[e] <= FL_U;
+  if (!fits) {
+    factor_level_row_mem(f, r);
+    return;
+  }
+  double drop = 0.0;
+#pragma unroll
+  for (int p = 0; p < FL_ROW; p++) {
+    if (p < nl) {
+      int32_t uc[FL_U];
+      double uv[FL_U];
+#pragma unroll
+      for (int t = 0; t < FL_U; t++) {
+        uc[t] = t < kl[p] ? f.Uc[kb[p] + t] : INT32_MAX;
+        uv[t] = t < kl[p] ? f.Uv[kb[p] + t] : 0.0;
+      }
+      const double wk = w[p] / dk[p];
+      w[p] = wk;
+      // each U entry (in column order) updates the row entry of its column,
+      // or is a dropped fill
+#pragma unroll
+      for (int t = 0; t < FL_U; t++) {
+        if (t < kl[p]) {
+          bool hit = false;
+#pragma unroll
+          for (int e = 0; e < FL_ROW; e++) {
+            if (e > p && c[e] == uc[t]) {
+              w[e] = fma(-wk, uv[t], w[e]);
+              hit = true;
+            }
+          }
+          if (!hit && milu) drop = fma(-wk, uv[t], drop);
+        }
+      }
+    }
+  }
+  double d = 0.0;
+#pragma unroll
+  for (int e = 0; e < FL_ROW; e++)
+    if (c[e] == r) d = w[e];
+  if (milu) d = d + drop;
+  if (f.pivot_mode == ILU_PIVOT_PERTURB) {
+    const double thr = f.pivot_tol * rowinf;
+    if (fabs(d) < thr) d = (d < 0.0) ? -thr : thr;
+  }
+  if (d == 0.0 || !isfinite(d)) {
+    raise_error(static_cast<Status *>(f.status), ILU_ERR_ZERO_PIVOT, r);
+    return;
+  }
+  const int64_t lb = f.Lrp[r], ub = f.Urp[r];
+  int nu = 0;
+#pragma unroll
+  for (int e = 0; e < FL_ROW; e++) {
+    if (e < nl) {
+      f.Lc[lb + e] = c[e];
+      f.Lv[lb + e] = w[e];
+    } else if (e < len && c[e] > r) {
+      f.Uc[ub + nu] = c[e];
+      f.Uv[ub + nu] = w[e];
+      nu++;
+    }
   }
   f.D[r] = d;
   f.Llen[r] = nl;
