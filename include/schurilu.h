@@ -138,13 +138,13 @@ typedef struct {
  *                 its rows into K consecutive ranges, one workgroup each,
  *                 which solve their levels side by side and pass the values
  *                 that a later range needs from an earlier one through
- *                 device memory.  The solve stays unsplit when a value would
- *                 be read by two ranges, a range's level would need more
- *                 than 64 of them, a range would span more than 4096 levels,
- *                 or a level of a range would be wider than 384 threads.
- *                 0 (auto) takes one range per 262,144 rows of a subdomain,
+ *                 device memory.  The solve stays unsplit when a range's
+ *                 level would need more than 64 such values, a range would
+ *                 span more than 4096 levels, or a level of a range would be
+ *                 wider than 384 threads.
+ *                 0 (auto) takes one range per 24,576 rows of a subdomain,
  *                 at least 2 for subdomains of 32,768 rows or more, at most
- *                 64, while the ranges of all subdomains fit the CUs.  The
+ *                 16, while the ranges of all subdomains fit the CUs.  The
  *                 solves of one handle must not run at the same time (they
  *                 share the exchange buffers).
  */

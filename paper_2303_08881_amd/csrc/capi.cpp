@@ -797,7 +797,8 @@ static int build_lowp(ilu_precond *P, Schedule &S, const Csr &T, const double *d
 // each other), one workgroup each.
 static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, const int64_t *bs1, const int64_t *bs2,
                        int64_t split, const double *diag, int64_t ext_col, const int32_t *omap, hipStream_t s,
-                       const char *phase, const int32_t *row_blk = nullptr, const int32_t *xrow = nullptr) {
+                       const char *phase, const int32_t *row_blk = nullptr, const int32_t *xrow = nullptr,
+                       int32_t K1 = 0) {
   const int64_t n = T.n;
   S.use_block = true;
   S.ext_col = ext_col;
@@ -872,7 +873,8 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   RC(fill_i32(dm, 0, 1, s));  // reused as the slow-row flag
   // with xrow (a split block), dependencies across parts name import slots
   RC(launch_lds_fill(S.blk_rows, T.rp, T.ci, T.v, diag, nloc, ext_col, S.pos, S.blk_lev_ptr, (int64_t)nkeys, G, E, prec,
-                     S.out_map, S.lds_c, S.lds_v, S.lds_rec, dm, xrow ? row_blk : nullptr, xrow, S.ilp, S.nlev, s));
+                     S.out_map, S.lds_c, S.lds_v, S.lds_rec, dm, xrow ? row_blk : nullptr, xrow, K1, S.ilp, S.nlev,
+                     s));
   int32_t any_slow = 1;
   HIPCK(hipMemcpyAsync(&any_slow, dm, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCK(hipStreamSynchronize(s));
@@ -882,15 +884,17 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
 
 // Workgroups per subdomain of the block-local solve of an interior factor
 // (nloc rows in the block-local solve): block_split, or under 0 (auto) one
-// per 262,144 rows of a subdomain, at least two for subdomains of 32,768
-// rows and more, at most 64, while the parts fit the CUs.
+// per 24,576 rows of a subdomain, at least two for subdomains of 32,768
+// rows and more, at most 16 (more parts shorten each part's levels but
+// lengthen the chain of parts that each trail the one before), while the
+// parts fit the CUs.
 static int32_t split_parts(const ilu_precond *P, int64_t nloc) {
   const int32_t k = P->opt.block_split;
   if (k == 1 || nloc == 0 || P->nparts < 1) return 1;
   if (k >= 2) return k;
   const int64_t rows = nloc / P->nparts;
   if (rows < 32768) return 1;
-  int64_t n = std::max<int64_t>(2, std::min<int64_t>(64, rows / 262144));
+  int64_t n = std::max<int64_t>(2, std::min<int64_t>(16, rows / 24576));
   while (n > 1 && P->nparts * n > P->num_cu) n--;
   return (int32_t)n;
 }
@@ -898,13 +902,14 @@ static int32_t split_parts(const ilu_precond *P, int64_t nloc) {
 // The split of each subdomain's block-local solve over K workgroups
 // (trsv_split.hip): the part of each row (K ranges of the block, numbered
 // from its end for a backward solve) and the values parts pass to each
-// other, sorted by (importing part, level that first needs them).  Leaves
-// the schedule unsplit (*ok = false) when a row would be imported by two
-// parts, an import by a part that does not come later, an import that
-// would leave its part's LDS ring before it is read, or more than 64
-// imports for one level of one part.  *part, *xrow (row -> import index, or
-// -1) and *isrc (import -> source row) live in tmp and feed build_block and
-// build_exports.
+// other, one import per (source row, importing part), sorted by (importing
+// part, level that first needs them).  Leaves the schedule unsplit (*ok =
+// false) for a part spanning more than SPLIT_LEVELS levels, an import by a
+// part that does not come later, an import that would leave its part's LDS
+// ring before it is read, or more than 64 imports for one level of one
+// part.  *part, *xrow ((row, later part of its subdomain) -> import index,
+// or -1) and *isrc (import -> source row) live in tmp and feed build_block
+// and build_exports.
 static int build_split(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, const int64_t *bs, int64_t nloc,
                        int64_t ext_col, int32_t K, bool backward, hipStream_t s, int32_t **part_out,
                        int32_t **xrow_out, int32_t **isrc_out, bool *ok) {
@@ -990,15 +995,15 @@ static int build_split(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   int32_t *ilp;
   RC(P->mem.alloc(&ilp, (int64_t)nkeys + 1));
   RC(launch_i64_to_i32(iptr, ilp, (int64_t)nkeys + 1, s));
-  RC(tmp.alloc(&xrow, nloc));
-  RC(fill_i32(xrow, -1, nloc, s));
-  RC(launch_cross_slots(isrc2, nimp, xrow, s));
-  RC(launch_cross_check(T.rp, T.ci, nloc, ext_col, part, S.level_of, nlev, xrow, ilp, bad, s));
+  RC(tmp.alloc(&xrow, nloc * (K - 1)));
+  RC(fill_i32(xrow, -1, nloc * (K - 1), s));
+  RC(launch_cross_slots(isrc2, ikey2, nimp, part, nlev, K - 1, xrow, s));
+  RC(launch_cross_check(T.rp, T.ci, nloc, ext_col, part, S.level_of, nlev, xrow, K - 1, ilp, bad, s));
   RC(launch_cross_width(ilp, (int64_t)nkeys, bad, s));
   int32_t hb[4] = {0, 0, 0, 0};
   HIPCK(hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
   HIPCK(hipStreamSynchronize(s));
-  if (hb[0] || hb[1] || hb[2] || hb[3] || nimp + 128 * nblk >= ((int64_t)1 << 29)) return 0;
+  if (hb[1] || hb[2] || hb[3] || nimp + 128 * nblk >= ((int64_t)1 << 29)) return 0;
   // the slots, then a pad of 128 words per part for the idle lanes of its loader wave
   RC(P->mem.alloc(&S.xv, nimp + 128 * nblk));
   RC(launch_fill_unset(S.xv, nimp + 128 * nblk, s));
@@ -1076,7 +1081,7 @@ static int build_block_interior(ilu_precond *P, Mem &tmp, const Csr &T, Schedule
     bool ok = false;
     RC(build_split(P, tmp, T, S, bs1, nloc, ext_col, K, backward, s, &part, &xrow, &isrc, &ok));
     if (ok) {
-      RC(build_block(P, tmp, T, S, bs1, bs2, split, diag, ext_col, nullptr, s, phase, part, xrow));
+      RC(build_block(P, tmp, T, S, bs1, bs2, split, diag, ext_col, nullptr, s, phase, part, xrow, K - 1));
       // check-free factors only, the compute threads and the two exchange waves within 512
       if (S.lds_fast && S.lds_bt <= 384) {
         RC(build_exports(P, tmp, S, part, isrc, s, &ok));

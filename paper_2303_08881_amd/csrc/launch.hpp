@@ -223,7 +223,8 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
                     int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G, int E,
                     int prec, const int32_t *omap, uint16_t *oc, void *ov, int32_t *rec, int *any_slow,
-                    const int32_t *part, const int32_t *xrow, const int32_t *ilp, int64_t nlev, hipStream_t s);
+                    const int32_t *part, const int32_t *xrow, int32_t K1, const int32_t *ilp, int64_t nlev,
+                    hipStream_t s);
 // ---- block-local solve split over several workgroups per block (trsv_split.hip) ----
 constexpr int SPLIT_LEVELS = 4096;  // levels of one part of a split solve (its pointers are held in LDS)
 // the split solve (TrsvLaunch with xv, xidx, ilp, nimp, xticket; check-free factors only)
@@ -239,19 +240,21 @@ int launch_cross_count(const int64_t *rp, const int32_t *ci, int64_t n, int64_t 
 int launch_cross_emit(const int64_t *rp, const int32_t *ci, int64_t n, int64_t split, const int32_t *part,
                       const int32_t *level, int64_t nlev, const int64_t *off, uint32_t *src, int32_t *key,
                       hipStream_t s);
-// on records sorted by (source, key): head flags; bad[0] a source read by two
-// parts, bad[1] a source not in an earlier part
+// on records sorted by (source, key): head flags (one import per source and
+// importing part); bad[1] a source not in an earlier part
 int launch_cross_heads(const uint32_t *src, const int32_t *key, int64_t m, const int32_t *part, int64_t nlev,
                        int64_t *head, int32_t *bad, hipStream_t s);
 int launch_cross_compact(const uint32_t *src, const int32_t *key, int64_t m, const int64_t *head, const int64_t *rank,
                          uint32_t *isrc, uint32_t *ikey, hipStream_t s);
-// xrow[source row] = import index (xrow preset to -1)
-int launch_cross_slots(const int32_t *isrc, int64_t nimp, int32_t *xrow, hipStream_t s);
+// xrow[source row * K1 + importing part - part of the row - 1] = import index
+// (xrow preset to -1; K1 = parts per subdomain - 1)
+int launch_cross_slots(const int32_t *isrc, const uint32_t *ikey, int64_t nimp, const int32_t *part, int64_t nlev,
+                       int32_t K1, int32_t *xrow, hipStream_t s);
 // bad[2]: an import out of its part's LDS ring when read; bad[3]: more than
 // 64 imports needed by one level of one part
 int launch_cross_check(const int64_t *rp, const int32_t *ci, int64_t n, int64_t split, const int32_t *part,
-                       const int32_t *level, int64_t nlev, const int32_t *xrow, const int32_t *ilp, int32_t *bad,
-                       hipStream_t s);
+                       const int32_t *level, int64_t nlev, const int32_t *xrow, int32_t K1, const int32_t *ilp,
+                       int32_t *bad, hipStream_t s);
 int launch_cross_width(const int32_t *ilp, int64_t nkeys, int32_t *bad, hipStream_t s);
 // lowest and highest level of each part's rows (lmin preset to INT32_MAX, lmax to -1)
 int launch_part_levels(const int32_t *part, const int32_t *level, int64_t n, int32_t *lmin, int32_t *lmax,

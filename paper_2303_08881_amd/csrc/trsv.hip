@@ -334,13 +334,14 @@ __global__ void k_max_width(const int32_t *lev_ptr, int64_t nseg, int32_t *out) 
 // the end of q's level, which bounds what the LDS window still holds.  The
 // output index of position q is omap[rows[q]].  With part (a block split
 // over workgroups), a dependency on a row of another part names the LDS
-// ring slot of its import: xrow[column] is the import's index, counted from
-// the first import of the row's part, ilp[part * nlev].
+// ring slot of its import: xrow[column * K1 + part of the row - part of the
+// column - 1] is the import's index, counted from the first import of the
+// row's part, ilp[part * nlev].
 __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v,
                            const double *diag, int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr,
                            int64_t nseg, int G, int E, int prec, const int32_t *omap, uint16_t *oc, void *ov,
-                           int4 *rec, int *any_slow, const int32_t *part, const int32_t *xrow, const int32_t *ilp,
-                           int64_t nlev) {
+                           int4 *rec, int *any_slow, const int32_t *part, const int32_t *xrow, int32_t K1,
+                           const int32_t *ilp, int64_t nlev) {
   int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q > n) return;
   const int64_t cap = (int64_t)G * E, nent = (n + 1) * G;
@@ -388,7 +389,7 @@ __global__ void k_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t
       const int32_t c = ci[p];
       int32_t slot;
       if (part && part[c] != part[r]) {
-        slot = XWIN + 1 + ((xrow[c] - ibase) & (IWIN - 1));
+        slot = XWIN + 1 + ((xrow[(int64_t)c * K1 + (part[r] - part[c] - 1)] - ibase) & (IWIN - 1));
       } else {
         const int32_t pc = pos[c];
         mind = min(mind, pc);
@@ -470,10 +471,11 @@ int launch_lds_prepare(const int32_t *rows, const int64_t *rp, const int32_t *ci
 int launch_lds_fill(const int32_t *rows, const int64_t *rp, const int32_t *ci, const double *v, const double *diag,
                     int64_t n, int64_t split, const int32_t *pos, const int32_t *lev_ptr, int64_t nseg, int G, int E,
                     int prec, const int32_t *omap, uint16_t *oc, void *ov, int32_t *rec, int *any_slow,
-                    const int32_t *part, const int32_t *xrow, const int32_t *ilp, int64_t nlev, hipStream_t s) {
+                    const int32_t *part, const int32_t *xrow, int32_t K1, const int32_t *ilp, int64_t nlev,
+                    hipStream_t s) {
   k_lds_fill<<<(unsigned)((n + 1 + 255) / 256), 256, 0, s>>>(rows, rp, ci, v, diag, n, split, pos, lev_ptr, nseg, G, E,
                                                               prec, omap, oc, ov, reinterpret_cast<int4 *>(rec),
-                                                              any_slow, part, xrow, ilp, nlev);
+                                                              any_slow, part, xrow, K1, ilp, nlev);
   return check_launch("lds_fill");
 }
 

@@ -13,8 +13,9 @@
 // workgroups walk the levels side by side, each with about 1/K of the rows.
 //
 // Exchange.  Each value a part needs from another part (an "import") has
-// its own slot in a device array.  The part that solves the row writes the
-// value there with a device-scope store; until then the slot holds a
+// its own slot in a device array (a row that several parts need has a slot
+// for each).  The part that solves the row writes the value there with a
+// device-scope store; until then the slot holds a
 // signalling-NaN pattern, which no arithmetic produces.  Every value is its
 // own flag: no fence and no counter.  In the importing part one extra wave
 // does nothing else: it loads the imports of a level AHEAD levels (several
@@ -24,9 +25,8 @@
 // beside the solution window (entries name the ring by their own window
 // slots) and puts the pattern back for the next solve.  So the compute
 // waves' pipeline holds no device-scope load: an importing part runs as fast
-// as the others once it trails the part it reads from by AHEAD levels.  Each
-// imported row has exactly one importing part (checked at setup), so a slot
-// has one writer and one reader per solve.  Solves of one factor must
+// as the others once it trails the part it reads from by AHEAD levels.  A
+// slot has one writer and one reader per solve.  Solves of one factor must
 // therefore not overlap in time (they do not: a handle's solves run in
 // stream order).
 //
@@ -375,18 +375,17 @@ __global__ void k_cross_emit(const int64_t *rp, const int32_t *ci, int64_t n, in
   }
 }
 
-// Records sorted by source row, and by key within a source: the first of
-// each source is an import (its part, and the earliest level that needs it).
-// bad[0]: a source read by two parts; bad[1]: a source in a part that does
-// not come before the importing one.
+// Records sorted by source row, and by key within a source (so by importing
+// part, then level): the first record of each (source, importing part) is an
+// import, with the earliest level that needs it.  bad[1]: a source in a part
+// that does not come before the importing one.
 __global__ void k_cross_heads(const uint32_t *src, const int32_t *key, int64_t m, const int32_t *part, int64_t nlev,
                               int64_t *head, int32_t *bad) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= m) return;
-  const bool h = i == 0 || src[i] != src[i - 1];
-  head[i] = h ? 1 : 0;
   const int32_t imp = (int32_t)(key[i] / nlev);
-  if (!h && imp != (int32_t)(key[i - 1] / nlev)) atomicOr(&bad[0], 1);
+  const bool h = i == 0 || src[i] != src[i - 1] || imp != (int32_t)(key[i - 1] / nlev);
+  head[i] = h ? 1 : 0;
   if (h && part[src[i]] >= imp) atomicOr(&bad[1], 1);
 }
 
@@ -398,10 +397,15 @@ __global__ void k_cross_compact(const uint32_t *src, const int32_t *key, int64_t
   ikey[rank[i]] = (uint32_t)key[i];
 }
 
-// slot of each imported row (imports sorted by (part, level)), -1 elsewhere
-__global__ void k_cross_slots(const int32_t *isrc, int64_t nimp, int32_t *xrow) {
+// Import index of each (source row, importing part): xrow[row * K1 + (part
+// - part[row] - 1)], the importing part being one of the K1 = K - 1 later
+// parts of the row's subdomain (-1 where that part imports nothing of it).
+__global__ void k_cross_slots(const int32_t *isrc, const uint32_t *ikey, int64_t nimp, const int32_t *part,
+                              int64_t nlev, int32_t K1, int32_t *xrow) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < nimp) xrow[isrc[i]] = (int32_t)i;
+  if (i >= nimp) return;
+  const int32_t r = isrc[i], imp = (int32_t)(ikey[i] / nlev);
+  xrow[(int64_t)r * K1 + (imp - part[r] - 1)] = (int32_t)i;
 }
 
 // Every import must still be in its part's LDS ring when a row reads it:
@@ -410,7 +414,7 @@ __global__ void k_cross_slots(const int32_t *isrc, int64_t nimp, int32_t *xrow) 
 // during level l).  Also: no import needed at level 0 (level 0 has no
 // dependency at all, so this only guards the layout).
 __global__ void k_cross_check(const int64_t *rp, const int32_t *ci, int64_t n, int64_t split, const int32_t *part,
-                              const int32_t *level, int64_t nlev, const int32_t *xrow, const int32_t *ilp,
+                              const int32_t *level, int64_t nlev, const int32_t *xrow, int32_t K1, const int32_t *ilp,
                               int32_t *bad) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= n) return;
@@ -418,7 +422,7 @@ __global__ void k_cross_check(const int64_t *rp, const int32_t *ci, int64_t n, i
   for (int64_t p = rp[r]; p < rp[r + 1]; p++) {
     const int32_t c = ci[p];
     if (c < split && part[c] != part[r]) {
-      const int32_t gi = xrow[c];
+      const int32_t gi = xrow[(int64_t)c * K1 + (part[r] - part[c] - 1)];
       const int64_t in = level[r] + 1 < nlev ? ilp[kb + 2] : ilp[kb + 1];
       if (gi < 0 || level[r] == 0 || (int64_t)gi < in - IWIN) atomicOr(&bad[2], 1);
     }
@@ -460,16 +464,17 @@ int launch_cross_compact(const uint32_t *src, const int32_t *key, int64_t m, con
   k_cross_compact<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(src, key, m, head, rank, isrc, ikey);
   return check_launch("cross_compact");
 }
-int launch_cross_slots(const int32_t *isrc, int64_t nimp, int32_t *xrow, hipStream_t s) {
+int launch_cross_slots(const int32_t *isrc, const uint32_t *ikey, int64_t nimp, const int32_t *part, int64_t nlev,
+                       int32_t K1, int32_t *xrow, hipStream_t s) {
   if (nimp == 0) return 0;
-  k_cross_slots<<<(unsigned)((nimp + 255) / 256), 256, 0, s>>>(isrc, nimp, xrow);
+  k_cross_slots<<<(unsigned)((nimp + 255) / 256), 256, 0, s>>>(isrc, ikey, nimp, part, nlev, K1, xrow);
   return check_launch("cross_slots");
 }
 int launch_cross_check(const int64_t *rp, const int32_t *ci, int64_t n, int64_t split, const int32_t *part,
-                       const int32_t *level, int64_t nlev, const int32_t *xrow, const int32_t *ilp, int32_t *bad,
-                       hipStream_t s) {
+                       const int32_t *level, int64_t nlev, const int32_t *xrow, int32_t K1, const int32_t *ilp,
+                       int32_t *bad, hipStream_t s) {
   if (n == 0) return 0;
-  k_cross_check<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, n, split, part, level, nlev, xrow, ilp, bad);
+  k_cross_check<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rp, ci, n, split, part, level, nlev, xrow, K1, ilp, bad);
   return check_launch("cross_check");
 }
 // lowest and highest level of each part's rows (lmin preset to INT_MAX, lmax

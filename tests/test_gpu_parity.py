@@ -366,8 +366,8 @@ def test_full_slab_setup_matches(slab_full):
     assert all(sched[4 * k] == 1 for k in range(4)), sched  # the benchmark's block-local solves
     # one workgroup per interface plane: 2 for each of the 14 inner slabs, 1 for each end slab
     assert sched[19] == 30, sched
-    # the interior solves split over two workgroups per subdomain (98,304 interior rows each)
-    assert (sched[20], sched[21]) == (2, 2), sched
+    # the interior solves split over four workgroups per subdomain (98,304 interior rows each)
+    assert (sched[20], sched[21]) == (4, 4), sched
 
 
 @pytest.mark.slow

@@ -5,8 +5,8 @@ A split solve does the arithmetic of every row exactly as the unsplit one (the s
 the same combination of the lanes' sums), so applies are bit-identical for any number of parts, and so are
 whole FGMRES solves.  Each part takes the values it needs from earlier parts through device memory, and the
 reader of each exchange slot resets it for the next solve, so every case applies several times in a row.
-Where a split does not apply (a row needed by two parts, too many imports for one level) the setup keeps the
-solve unsplit; the schedule export says which, and the results agree either way.
+Where a split does not apply (too many imports for one level, a part too long) the setup keeps the solve
+unsplit; the schedule export says which, and the results agree either way.
 """
 import numpy as np
 import pytest
@@ -44,8 +44,8 @@ def _case(name):
     raise KeyError(name)
 
 
-# (workload, options, parts per subdomain); with 3 or 4 parts the slabs' planes (a part is less than two of
-# them) are read by two later parts, so those solves stay unsplit
+# (workload, options, parts per subdomain); with 3 or 4 parts a slab's part is less than two planes, and some
+# rows are read by two later parts (one import each)
 CASES = [
     ("slabs", SCHUR_ILUT, 2),
     ("slabs", SCHUR_ILUT, 3),
@@ -67,37 +67,40 @@ def _ids():
 def split_applies(rp, ci, lev, bs, nparts, k, backward):
     """Whether a k-way split of a block-local solve applies, from the oracle's factor and levels: the parts
     are k equal ranges of each block (counted from its end for a backward solve); every row that a part
-    needs from another part is needed by that part only and lies in an earlier part; no level of a part
-    needs more than 64 of them; and each is still in the part's ring of the last IWIN imports (in the order
-    of the level that first needs them) when a row of level l reads it, with the imports of level l + 1
-    already going in."""
+    needs from another part lies in an earlier part (one import per row and importing part); no part spans
+    more than 4096 levels; no level of a part needs more than 64 imports; and each import is still in the
+    part's ring of the last IWIN imports (in the order of the level that first needs them) when a row of
+    level l reads it, with the imports of level l + 1 already going in."""
     n = len(rp) - 1
     nlev = int(lev.max()) + 1
-    if nlev > 8192:
-        return False
     blk = np.searchsorted(bs[:nparts + 1], np.arange(n), side="right") - 1
     b0, ln = bs[blk], bs[blk + 1] - bs[blk]
     kk = ((np.arange(n) - b0) * k) // ln
     prt = blk * k + (k - 1 - kk if backward else kk)
+    for p_ in range(nparts * k):
+        lv = lev[prt == p_]
+        if lv.size and lv.max() - lv.min() + 1 > 4096:
+            return False
     rows = np.repeat(np.arange(n), np.diff(rp))
     cols = ci.astype(np.int64)
     rows, cols = rows[cols < n], cols[cols < n]
     cross = prt[cols] != prt[rows]
     r, c = rows[cross], cols[cross]
-    importer, need = {}, {}
+    need = {}
     for cc, rr in zip(c.tolist(), r.tolist()):
-        if importer.setdefault(cc, prt[rr]) != prt[rr] or prt[cc] >= prt[rr]:
+        if prt[cc] >= prt[rr]:
             return False
         key = prt[rr] * nlev + lev[rr]
-        need[cc] = min(need.get(cc, key), key)
-    order = sorted(need, key=lambda x: (need[x], x))
+        imp = (cc, prt[rr])
+        need[imp] = min(need.get(imp, key), key)
+    order = sorted(need, key=lambda x: (need[x], x[0]))
     gi = {x: i for i, x in enumerate(order)}
     cnt = np.bincount([need[x] for x in order], minlength=nparts * k * nlev)
     if cnt.max(initial=0) > 64:
         return False
     ilp = np.concatenate([[0], np.cumsum(cnt)])
-    return all(lev[rr] > 0 and gi[cc] >= ilp[prt[rr] * nlev + lev[rr] + (2 if lev[rr] + 1 < nlev else 1)] - IWIN
-               for cc, rr in zip(c.tolist(), r.tolist()))
+    return all(lev[rr] > 0 and gi[(cc, prt[rr])] >= ilp[prt[rr] * nlev + lev[rr] + (2 if lev[rr] + 1 < nlev else 1)]
+               - IWIN for cc, rr in zip(c.tolist(), r.tolist()))
 
 
 def _setup(m, A, part, p, opts, k, **kw):
@@ -159,7 +162,7 @@ def test_split_fgmres_identical():
 
 def test_split_auto():
     # 64 x 64 x 32, 2 z-slabs, the interior factored by ILUT: blocks of 61,440 rows take two workgroups each by
-    # default (levels of at most 64 rows per part)
+    # default (one per 24,576 rows; levels of at most 64 rows per part)
     m = silu()
     A = synth.aniso7(64, Nz=32)
     part = torch.as_tensor(synth.slab_partition(64, 2, Nz=32)).cuda()
