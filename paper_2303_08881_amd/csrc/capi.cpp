@@ -178,6 +178,13 @@ struct Mem {
     *out = (T *)p;
     return 0;
   }
+  // take over every block of `from` (which is left empty)
+  void adopt(Mem &from) {
+    ptrs.insert(ptrs.end(), from.ptrs.begin(), from.ptrs.end());
+    bytes += from.bytes;
+    from.ptrs.clear();
+    from.bytes = 0;
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -798,7 +805,7 @@ static int build_lowp(ilu_precond *P, Schedule &S, const Csr &T, const double *d
 static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, const int64_t *bs1, const int64_t *bs2,
                        int64_t split, const double *diag, int64_t ext_col, const int32_t *omap, hipStream_t s,
                        const char *phase, const int32_t *row_blk = nullptr, const int32_t *xrow = nullptr,
-                       int32_t K1 = 0) {
+                       int32_t K1 = 0, Mem *into = nullptr) {
   const int64_t n = T.n;
   S.use_block = true;
   S.ext_col = ext_col;
@@ -808,7 +815,7 @@ static int build_block(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   const int64_t nloc = bs2 ? split : n;
   S.nloc = nloc;
   if (nloc == 0) return 0;
-  Mem &mem = P->mem;
+  Mem &mem = into ? *into : P->mem;  // the split's attempt keeps its blocks apart until it succeeds
   const uint64_t nkeys = (uint64_t)S.nblk * (uint64_t)S.nlev;
   uint32_t *key, *key2;
   int32_t *val;
@@ -910,8 +917,8 @@ static int32_t split_parts(const ilu_precond *P, int64_t nloc) {
 // part.  *part, *xrow ((row, later part of its subdomain) -> import index,
 // or -1) and *isrc (import -> source row) live in tmp and feed build_block
 // and build_exports.
-static int build_split(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, const int64_t *bs, int64_t nloc,
-                       int64_t ext_col, int32_t K, bool backward, hipStream_t s, int32_t **part_out,
+static int build_split(ilu_precond *P, Mem &tmp, Mem &keep, const Csr &T, Schedule &S, const int64_t *bs,
+                       int64_t nloc, int64_t ext_col, int32_t K, bool backward, hipStream_t s, int32_t **part_out,
                        int32_t **xrow_out, int32_t **isrc_out, bool *ok) {
   *ok = false;
   const int64_t nblk = (int64_t)P->nparts * K, nlev = S.nlev;
@@ -993,7 +1000,7 @@ static int build_split(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   RC(histogram_keys(ikey2, nimp, (int64_t)nkeys, icnt, s));
   RC(make_rp(tmp, icnt, (int64_t)nkeys, &iptr, &itot, stmp, stb, s));
   int32_t *ilp;
-  RC(P->mem.alloc(&ilp, (int64_t)nkeys + 1));
+  RC(keep.alloc(&ilp, (int64_t)nkeys + 1));
   RC(launch_i64_to_i32(iptr, ilp, (int64_t)nkeys + 1, s));
   RC(tmp.alloc(&xrow, nloc * (K - 1)));
   RC(fill_i32(xrow, -1, nloc * (K - 1), s));
@@ -1005,11 +1012,11 @@ static int build_split(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
   HIPCK(hipStreamSynchronize(s));
   if (hb[1] || hb[2] || hb[3] || nimp + 128 * nblk >= ((int64_t)1 << 29)) return 0;
   // the slots, then a pad of 128 words per part for the idle lanes of its loader wave
-  RC(P->mem.alloc(&S.xv, nimp + 128 * nblk));
+  RC(keep.alloc(&S.xv, nimp + 128 * nblk));
   RC(launch_fill_unset(S.xv, nimp + 128 * nblk, s));
-  RC(P->mem.alloc(&S.xticket, 1));
+  RC(keep.alloc(&S.xticket, 1));
   HIPCK(hipMemsetAsync(S.xticket, 0, sizeof(unsigned long long), s));
-  RC(P->mem.alloc(&S.lrange, 2 * nblk));
+  RC(keep.alloc(&S.lrange, 2 * nblk));
   HIPCK(hipMemcpyAsync(S.lrange, hr.data(), sizeof(int32_t) * 2 * nblk, hipMemcpyHostToDevice, s));
   HIPCK(hipStreamSynchronize(s));  // hr is host memory on this stack
   S.xlevels = most;
@@ -1028,7 +1035,7 @@ static int build_split(ilu_precond *P, Mem &tmp, const Csr &T, Schedule &S, cons
 // import, sorted by (exporting part, level of the source row) and stored as
 // {position, slot}.  *ok = false when a level of a part exports more than 64
 // rows (one lane each in the exchange wave).
-static int build_exports(ilu_precond *P, Mem &tmp, Schedule &S, const int32_t *part, const int32_t *isrc,
+static int build_exports(Mem &tmp, Mem &keep, Schedule &S, const int32_t *part, const int32_t *isrc,
                          hipStream_t s, bool *ok) {
   *ok = false;
   const int64_t nimp = S.nimp, nkeys = S.nblk * S.nlev, ni = std::max<int64_t>(nimp, 1);
@@ -1053,14 +1060,14 @@ static int build_exports(ilu_precond *P, Mem &tmp, Schedule &S, const int32_t *p
   RC(tmp.alloc((char **)&stmp, (int64_t)stb));
   RC(make_rp(tmp, cnt, nkeys, &ptr, &tot, stmp, stb, s));
   int32_t *elp, *xe;
-  RC(P->mem.alloc(&elp, nkeys + 1));
+  RC(keep.alloc(&elp, nkeys + 1));
   RC(launch_i64_to_i32(ptr, elp, nkeys + 1, s));
   RC(launch_cross_width(elp, nkeys, bad, s));
   int32_t hb[4] = {0, 0, 0, 0};
   HIPCK(hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
   HIPCK(hipStreamSynchronize(s));
   if (hb[3]) return 0;
-  RC(P->mem.alloc(&xe, 2 * (nimp + 1)));
+  RC(keep.alloc(&xe, 2 * (nimp + 1)));
   RC(launch_export_fill(egi, isrc, S.pos, nimp, xe, s));
   S.elp = elp;
   S.xe = xe;
@@ -1079,15 +1086,20 @@ static int build_block_interior(ilu_precond *P, Mem &tmp, const Csr &T, Schedule
   if (K > 1) {
     int32_t *part = nullptr, *xrow = nullptr, *isrc = nullptr;
     bool ok = false;
-    RC(build_split(P, tmp, T, S, bs1, nloc, ext_col, K, backward, s, &part, &xrow, &isrc, &ok));
+    Mem trial;  // the attempt's device blocks: kept only if the split applies
+    RC(build_split(P, tmp, trial, T, S, bs1, nloc, ext_col, K, backward, s, &part, &xrow, &isrc, &ok));
     if (ok) {
-      RC(build_block(P, tmp, T, S, bs1, bs2, split, diag, ext_col, nullptr, s, phase, part, xrow, K - 1));
+      RC(build_block(P, tmp, T, S, bs1, bs2, split, diag, ext_col, nullptr, s, phase, part, xrow, K - 1, &trial));
       // check-free factors only, the compute threads and the two exchange waves within 512
-      if (S.lds_fast && S.lds_bt <= 384) {
-        RC(build_exports(P, tmp, S, part, isrc, s, &ok));
-        if (ok) return 0;
-      }
+      ok = S.lds_fast && S.lds_bt <= 384;
+      if (ok) RC(build_exports(tmp, trial, S, part, isrc, s, &ok));
     }
+    if (ok) {
+      P->mem.adopt(trial);
+      return 0;
+    }
+    HIPCK(hipStreamSynchronize(s));  // the attempt's kernels are done with its blocks
+    trial.release(false);
     // build the unsplit solve
     S.split_k = 1;
     S.xv = nullptr;
