@@ -58,6 +58,12 @@ CONFIGS = [
     ("random_blocks", dict(method=oracle.BJ, interior_fact=oracle.ILUT, **ILUT_OPTS)),
     ("random_blocks", dict(method=oracle.SCHUR, interior_fact=oracle.ILUT, interface_fact=oracle.MILU0,
                            inner_iters=5, **ILUT_OPTS)),
+    # (M)ILU(0) interiors with the rows of the local Schur complements (partial rows; with MILU(0) the dropped
+    # fill of such a row goes to its diagonal), and rows of more than 12 entries in the random blocks
+    ("aniso3d_slabs", dict(method=oracle.SCHUR, interior_fact=oracle.MILU0, interface_fact=oracle.MILU0,
+                           inner_iters=3)),
+    ("random_blocks", dict(method=oracle.SCHUR, interior_fact=oracle.ILU0, interface_fact=oracle.ILU0,
+                           inner_iters=5)),
     # the multiplicative method: RAP-MILU (MILU(0) coarse factors, ILU(0) smoother) and RAP-ILU
     ("aniso3d_slabs", dict(method=oracle.RAP, interior_fact=oracle.MILU0, smooth_fact=oracle.ILU0, inner_iters=3)),
     ("random_blocks", dict(method=oracle.RAP, interior_fact=oracle.ILU0, smooth_fact=oracle.ILU0, inner_iters=5)),
