@@ -520,13 +520,17 @@ static int row_geometry(Mem &tmp, const Csr &M, int64_t nrows, bool upper, hipSt
 
 // Factor M (rows < nfull full, the rest partial) with the schedule of the
 // given segments.  Scratch goes to `tmp`.
-// ILU(0) / MILU(0) of a matrix of full rows by levels of its lower pattern,
-// one launch per level (launch_factor_level: the same factors as the
-// dependency-flag kernel, without a memory round trip per row on the chain).
+// ILU(0) / MILU(0) by levels of the lower pattern over the interior columns
+// (partial rows, those of the local Schur complement, take interior pivots
+// only and are needed by no row), one launch per level
+// (launch_factor_level: the same factors as the dependency-flag kernel,
+// without a memory round trip per row on the chain).
 // The levels come from the level analysis's sweep over the factorization's
 // own row schedule.  *done = false (nothing factored) when the pattern has
 // too many levels for one launch each to pay: more than 65,536, or fewer
-// than 16 rows per level on average.
+// than 16 rows per level on average; with partial rows, also when a row has
+// more than FACT_LEVEL_PARTIAL_ROW entries.
+constexpr int FACT_LEVEL_PARTIAL_ROW = 32;
 static int factor_by_levels(ilu_precond *P, Mem &tmp, const Csr &M, const FactLaunch &f,
                             const std::vector<int64_t> &a_start, const std::vector<int64_t> &a_len,
                             const std::vector<int64_t> &b_start, const std::vector<int64_t> &b_len, hipStream_t s,
@@ -534,6 +538,17 @@ static int factor_by_levels(ilu_precond *P, Mem &tmp, const Csr &M, const FactLa
   *done = false;
   const int64_t n = M.n;
   if (n == 0) return 0;
+  if (f.nfull < n) {
+    // with the rows of local Schur complements, only matrices of short rows:
+    // one thread per row pays for a long row (a power-law hub) on the chain
+    int *dlen, hlen = 0;
+    RC(tmp.alloc(&dlen, 1));
+    HIPCK(hipMemsetAsync(dlen, 0, sizeof(int), s));
+    RC(launch_row_len_max(M.rp, n, dlen, s));
+    HIPCK(hipMemcpyAsync(&hlen, dlen, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    if (hlen > FACT_LEVEL_PARTIAL_ROW) return 0;
+  }
   int64_t line = 16, plane = 16, nch = 0, ns = 0, ninit = 0, *sc = nullptr;
   int32_t *chunks = nullptr, *level;
   const int64_t grid = std::min<int64_t>(levels_resident_groups(P->num_cu), (int64_t)P->num_cu * 32 / LEVEL_WAVES);
@@ -548,7 +563,10 @@ static int factor_by_levels(ilu_precond *P, Mem &tmp, const Csr &M, const FactLa
   RC(tmp.alloc(&ticket, std::max<int64_t>(ns, 1)));
   HIPCK(hipMemsetAsync(flag, 0, sizeof(int) * n, s));
   HIPCK(hipMemsetAsync(ticket, 0, sizeof(unsigned int) * std::max<int64_t>(ns, 1), s));
-  RC(launch_levels_stream(M.rp, M.ci, true, 0, n, chunks, ns, ninit, sc, ticket, level, flag, P->status, grid, s));
+  // a row's pivots are its interior columns below it (partial rows: every
+  // interior column), so only those count
+  RC(launch_levels_stream(M.rp, M.ci, true, 0, f.nfull, chunks, ns, ninit, sc, ticket, level, flag, P->status, grid,
+                          s));
   RC(check_status(P, s, "factorization levels", nullptr, 0));
   int32_t *dmax, hmax = 0;
   RC(tmp.alloc(&dmax, 1));
@@ -612,7 +630,7 @@ static int run_factor(ilu_precond *P, Mem &tmp, const Csr &M, int64_t nfull, int
   RC(tmp.alloc(&S.Rlen, n - nfull));
   RC(tmp.alloc(&S.D, nfull));
   RC(fill_i32(S.Ulen, 0, nfull, s));
-  if (method != ILU_FACT_ILUT && nfull == n && n > 0) {
+  if (method != ILU_FACT_ILUT && n > 0) {
     FactLaunch f{};
     f.rp = M.rp;
     f.ci = M.ci;
@@ -632,6 +650,10 @@ static int run_factor(ilu_precond *P, Mem &tmp, const Csr &M, int64_t nfull, int
     f.Uc = S.Uc;
     f.Uv = S.Uv;
     f.Ulen = S.Ulen;
+    f.Rrp = S.Rrp;
+    f.Rc = S.Rc;
+    f.Rv = S.Rv;
+    f.Rlen = S.Rlen;
     f.D = S.D;
     f.status = P->status;
     bool done = false;

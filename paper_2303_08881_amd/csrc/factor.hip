@@ -596,8 +596,8 @@ int launch_fact_caps(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nf
   return check_launch("fact_caps");
 }
 
-// ILU(0) / MILU(0) of full rows, one level of the lower pattern per launch:
-// every pivot row of a level lies in an earlier level, so it is complete
+// ILU(0) / MILU(0), one level of the lower pattern (over the interior
+// columns) per launch: every pivot row of a level lies in an earlier level, so it is complete
 // when the launch starts, and no row waits.  One thread per row.  The
 // operations are factor_row's, in its order: pivots in column order,
 // w_k / d_k, one fma per updated entry, the dropped products of MILU(0)
@@ -678,14 +678,76 @@ __device__ void factor_level_row_mem(const FactLaunch &f, int64_t r) {
   f.Ulen[r] = nu;
 }
 
+// A partial row (r >= nfull, a row of the local Schur complement), in
+// memory: eliminated by its interior pivots (columns < nfull) only, as
+// factor_row does, into its L entries (interior columns) and its remainder
+// R (columns >= nfull, the diagonal among them; with MILU(0) the dropped
+// products are added to the diagonal).  No pivot test: R is not a pivot.
+__device__ void factor_level_partial_mem(const FactLaunch &f, int64_t r) {
+  const bool milu = f.method == ILU_FACT_MILU0;
+  const int64_t rb = f.rp[r], re = f.rp[r + 1], lb = f.Lrp[r], ro = f.Rrp[r - f.nfull];
+  int nl = 0, nr = 0;
+  for (int64_t e = rb; e < re; e++) {
+    const int32_t c = f.ci[e];
+    const double x = f.v[e];
+    if (c < f.nfull) {
+      f.Lc[lb + nl] = c;
+      f.Lv[lb + nl] = x;
+      nl++;
+    } else {
+      f.Rc[ro + nr] = c;
+      f.Rv[ro + nr] = x;
+      nr++;
+    }
+  }
+  double drop = 0.0;
+  for (int p = 0; p < nl; p++) {
+    const int32_t k = f.Lc[lb + p];
+    const double wk = f.Lv[lb + p] / f.D[k];
+    f.Lv[lb + p] = wk;
+    const int64_t kb = f.Urp[k];
+    const int kl = f.Ulen[k];
+    int q = p + 1;  // L entry q (< nl), else R entry q - nl
+    for (int t = 0; t < kl; t++) {
+      const int32_t uc = f.Uc[kb + t];
+      const double u = f.Uv[kb + t];
+      int32_t cq;
+      for (;;) {
+        cq = q < nl ? f.Lc[lb + q] : q - nl < nr ? f.Rc[ro + q - nl] : INT32_MAX;
+        if (cq >= uc) break;
+        q++;
+      }
+      if (cq == uc) {
+        if (q < nl)
+          f.Lv[lb + q] = fma(-wk, u, f.Lv[lb + q]);
+        else
+          f.Rv[ro + q - nl] = fma(-wk, u, f.Rv[ro + q - nl]);
+      } else if (milu) {
+        drop = fma(-wk, u, drop);
+      }
+    }
+  }
+  if (milu)
+    for (int q = 0; q < nr; q++)
+      if (f.Rc[ro + q] == r) f.Rv[ro + q] = f.Rv[ro + q] + drop;
+  f.Llen[r] = nl;
+  f.Rlen[r - f.nfull] = nr;
+}
+
 __global__ void __launch_bounds__(128) k_factor_level(FactLaunch f, const int32_t *rows, int64_t cnt) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= cnt) return;
   const int64_t r = rows[i];
   const int64_t rb = f.rp[r];
   const int len = (int)(f.rp[r + 1] - rb);
+  // a partial row's pivots are its interior columns, a full row's those below it
+  const bool part = r >= f.nfull;
+  const int64_t lim = part ? f.nfull : r;
   if (len > FL_ROW) {
-    factor_level_row_mem(f, r);
+    if (part)
+      factor_level_partial_mem(f, r);
+    else
+      factor_level_row_mem(f, r);
     return;
   }
   const bool milu = f.method == ILU_FACT_MILU0;
@@ -702,7 +764,7 @@ __global__ void __launch_bounds__(128) k_factor_level(FactLaunch f, const int32_
 #pragma unroll
   for (int e = 0; e < FL_ROW; e++) {
     rowinf = fmax(rowinf, fabs(w[e]));
-    nl += c[e] < r;
+    nl += c[e] < lim;
   }
   // every pivot's diagonal and U-row extent in one round
   double dk[FL_ROW];
@@ -720,7 +782,10 @@ __global__ void __launch_bounds__(128) k_factor_level(FactLaunch f, const int32_
 #pragma unroll
   for (int e = 0; e < FL_ROW; e++) fits = fits && kl[e] <= FL_U;
   if (!fits) {
-    factor_level_row_mem(f, r);
+    if (part)
+      factor_level_partial_mem(f, r);
+    else
+      factor_level_row_mem(f, r);
     return;
   }
   double drop = 0.0;
@@ -753,6 +818,23 @@ __global__ void __launch_bounds__(128) k_factor_level(FactLaunch f, const int32_
         }
       }
     }
+  }
+  if (part) {
+    const int64_t lb = f.Lrp[r], ro = f.Rrp[r - f.nfull];
+#pragma unroll
+    for (int e = 0; e < FL_ROW; e++) {
+      if (milu && c[e] == r) w[e] = w[e] + drop;
+      if (e < nl) {
+        f.Lc[lb + e] = c[e];
+        f.Lv[lb + e] = w[e];
+      } else if (e < len) {
+        f.Rc[ro + e - nl] = c[e];
+        f.Rv[ro + e - nl] = w[e];
+      }
+    }
+    f.Llen[r] = nl;
+    f.Rlen[r - f.nfull] = len - nl;
+    return;
   }
   double d = 0.0;
 #pragma unroll

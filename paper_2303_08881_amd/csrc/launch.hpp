@@ -91,8 +91,9 @@ int launch_gap_hist(const int64_t *rp, const int32_t *ci, int64_t n, bool upper,
 int launch_fact_caps(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nfull, int32_t method, int32_t lfil,
                      int64_t *Lcap, int64_t *Ucap, int64_t *Rcap, hipStream_t s);
 int launch_factor_rows(const FactLaunch &f, hipStream_t s);
-// ILU(0) / MILU(0) of the full rows rows[0 .. cnt) of one level of the lower
-// pattern (every earlier level already factored): the same factors as
+// ILU(0) / MILU(0) of rows rows[0 .. cnt) of one level of the lower pattern
+// over the interior columns (every earlier level already factored; partial
+// rows, r >= nfull, take interior pivots only): the same factors as
 // launch_factor_rows
 int launch_factor_level(const FactLaunch &f, const int32_t *rows, int64_t cnt, hipStream_t s);
 // *out = max(*out, longest of rows [0, n))
